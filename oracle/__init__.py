@@ -1,0 +1,282 @@
+"""Python access to the reference checker (``oracle.c``).
+
+TEST INFRASTRUCTURE ONLY. Only the test-suite, the smoke check and the
+benchmark's CPU-baseline leg import this package; the GPU library and its
+binding never do. See ``oracle.h`` for the precision policy and array layouts.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+MISS_TMAX, MISS_EXIT, HIT, HIT_EXHAUSTED, INSIDE = 0, 1, 2, 3, 4
+MAX_LEVELS = 4
+
+# -ffp-contract=off forbids fusing any multiply-add the source does not spell out;
+# fmaf() is the only fused operation, and it is correctly rounded in glibc.
+CFLAGS = ["-O2", "-fPIC", "-shared", "-pthread", "-std=c11", "-ffp-contract=off",
+          "-fno-fast-math", "-fexcess-precision=standard", "-Wall", "-Wextra"]
+
+
+def build(force: bool = True, extra_cflags: Sequence[str] = (), out: Optional[str] = None) -> str:
+    """Compile oracle.c with gcc into a shared library (returns its path)."""
+    path = out or _LIB_PATH
+    if force or not os.path.exists(path):
+        tmp = path + ".tmp"
+        cmd = ["gcc", *CFLAGS, *extra_cflags, os.path.join(_HERE, "oracle.c"), "-o", tmp, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, path)
+    return path
+
+
+class Level(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("origin", ctypes.c_double * 3),
+                ("spacing", ctypes.c_double), ("sdf", ctypes.c_void_p),
+                ("albedo", ctypes.c_void_p)]
+
+
+class Setup(ctypes.Structure):
+    _fields_ = [("num_levels", ctypes.c_int32), ("level", Level * MAX_LEVELS),
+                ("probe_n", ctypes.c_int32 * 3), ("probe_origin", ctypes.c_double * 3),
+                ("probe_spacing", ctypes.c_double * 3), ("rays", ctypes.c_int32),
+                ("max_steps", ctypes.c_int32), ("irr_res", ctypes.c_int32),
+                ("depth_res", ctypes.c_int32), ("hit_eps", ctypes.c_float),
+                ("t_max", ctypes.c_float), ("hysteresis", ctypes.c_float),
+                ("bounce_gain", ctypes.c_float), ("depth_sharpness", ctypes.c_float),
+                ("shadow_bias", ctypes.c_float), ("relax", ctypes.c_float),
+                ("sky", ctypes.c_float * 3), ("albedo", ctypes.c_float * 3)]
+
+
+class FrameDesc(ctypes.Structure):
+    _fields_ = [("dir_to_light", ctypes.c_float * 3), ("radiance", ctypes.c_float * 3),
+                ("rotation_seed", ctypes.c_uint64), ("reset_history", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=True)
+        L = ctypes.CDLL(_LIB_PATH)
+        L.orc_splitmix64.restype = ctypes.c_uint64
+        L.orc_splitmix64.argtypes = [ctypes.POINTER(ctypes.c_uint64)]
+        L.orc_sdf32.restype = ctypes.c_float
+        L.orc_level32.restype = ctypes.c_int32
+        L.orc_blend_probe.restype = ctypes.c_int32
+        L.orc_update_probes.restype = ctypes.c_int32
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+class Checker:
+    """A reference setup built from a workload (keeps its arrays alive)."""
+
+    def __init__(self, workload, **overrides):
+        w = workload
+        prm = w.params
+        vals = dict(rays=prm.rays_per_probe, max_steps=prm.max_steps, irr_res=prm.irr_res,
+                    depth_res=prm.depth_res, hit_eps=prm.hit_eps, t_max=prm.t_max,
+                    hysteresis=prm.hysteresis, bounce_gain=prm.bounce_gain,
+                    depth_sharpness=prm.depth_sharpness, shadow_bias=prm.shadow_bias,
+                    relax=prm.relax, sky=prm.sky_rgb, albedo=prm.albedo)
+        vals.update(overrides)
+        s = Setup()
+        self._keep = []
+        s.num_levels = len(w.levels)
+        for k, lv in enumerate(w.levels):
+            sdf = np.ascontiguousarray(lv.sdf, dtype=np.float32)
+            self._keep.append(sdf)
+            s.level[k].n[:] = list(lv.n)
+            s.level[k].origin[:] = list(lv.origin)
+            s.level[k].spacing = lv.spacing
+            s.level[k].sdf = sdf.ctypes.data
+            if lv.albedo is not None:
+                alb = np.ascontiguousarray(lv.albedo, dtype=np.float32)
+                self._keep.append(alb)
+                s.level[k].albedo = alb.ctypes.data
+            else:
+                s.level[k].albedo = None
+        s.probe_n[:] = list(w.probes.n)
+        s.probe_origin[:] = list(w.probes.origin)
+        s.probe_spacing[:] = list(w.probes.spacing)
+        for key in ("rays", "max_steps", "irr_res", "depth_res", "hit_eps", "t_max",
+                    "hysteresis", "bounce_gain", "depth_sharpness", "shadow_bias", "relax"):
+            setattr(s, key, vals[key])
+        s.sky[:] = list(vals["sky"])
+        s.albedo[:] = list(vals["albedo"])
+        self.s = s
+        self.workload = w
+        self.num_probes = int(np.prod(w.probes.n))
+        self.rays = int(vals["rays"])
+        self.irr_res = int(vals["irr_res"])
+        self.depth_res = int(vals["depth_res"])
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.s)
+
+    # -- geometry -------------------------------------------------------
+    def sdf32(self, level: int, x) -> float:
+        xa = (ctypes.c_float * 3)(*[float(v) for v in x])
+        return float(lib().orc_sdf32(self.ref, ctypes.c_int32(level), xa))
+
+    def level32(self, x) -> int:
+        xa = (ctypes.c_float * 3)(*[float(v) for v in x])
+        return int(lib().orc_level32(self.ref, xa))
+
+    def trace_ray32(self, origin, direction, dir_to_light=(0.0, 1.0, 0.0)) -> np.ndarray:
+        o = (ctypes.c_float * 3)(*[float(v) for v in origin])
+        d = (ctypes.c_float * 3)(*[float(v) for v in direction])
+        l = (ctypes.c_float * 3)(*[float(v) for v in dir_to_light])
+        rec = (ctypes.c_int32 * 8)()
+        lib().orc_trace_ray32(self.ref, o, d, l, rec)
+        return np.array(list(rec), dtype=np.int32)
+
+    def probe_position(self, p: int) -> np.ndarray:
+        out = (ctypes.c_double * 3)()
+        lib().orc_probe_position(self.ref, ctypes.c_int32(p), out)
+        return np.array(list(out))
+
+    # -- radiometry -----------------------------------------------------
+    def interp_irradiance(self, atlas: np.ndarray, x, n) -> np.ndarray:
+        atlas = np.ascontiguousarray(atlas, dtype=np.float64)
+        xa = (ctypes.c_double * 3)(*[float(v) for v in x])
+        na = (ctypes.c_double * 3)(*[float(v) for v in n])
+        out = (ctypes.c_double * 3)()
+        lib().orc_interp_irradiance(self.ref, _p(atlas), xa, na, out)
+        return np.array(list(out))
+
+    def blend_probe(self, seed: int, reset: bool, payload: np.ndarray,
+                    prev_irr_tile: Optional[np.ndarray], prev_depth_tile: Optional[np.ndarray]):
+        pl = np.ascontiguousarray(payload, dtype=np.float64)
+        ri, rd = self.irr_res + 2, self.depth_res + 2
+        irr = np.zeros((ri, ri, 3))
+        dep = np.zeros((rd, rd, 2))
+        pi = (np.ascontiguousarray(prev_irr_tile, dtype=np.float64)
+              if prev_irr_tile is not None else None)
+        pd = (np.ascontiguousarray(prev_depth_tile, dtype=np.float64)
+              if prev_depth_tile is not None else None)
+        rc = lib().orc_blend_probe(self.ref, ctypes.c_uint64(seed), ctypes.c_int32(int(reset)),
+                                   _p(pl), _p(pi) if pi is not None else None,
+                                   _p(pd) if pd is not None else None, _p(irr), _p(dep))
+        if rc != 0:
+            raise RuntimeError("orc_blend_probe failed")
+        return irr, dep
+
+    def update_probes(self, frame, reset: bool, prev_irr: Optional[np.ndarray],
+                      prev_depth: Optional[np.ndarray], probes: Optional[Sequence[int]] = None,
+                      threads: int = 0, want_payload: bool = False, want_records: bool = False):
+        """One frame for the listed probes (all by default) from the given previous atlas."""
+        if probes is None:
+            probes = np.arange(self.num_probes, dtype=np.int32)
+        probes = np.ascontiguousarray(probes, dtype=np.int32)
+        cnt = int(probes.shape[0])
+        ri, rd = self.irr_res + 2, self.depth_res + 2
+        irr = np.zeros((cnt, ri, ri, 3))
+        dep = np.zeros((cnt, rd, rd, 2))
+        pl = np.zeros((cnt, self.rays, 4)) if want_payload else None
+        rec = np.zeros((cnt, self.rays, 8), dtype=np.int32) if want_records else None
+        pi = np.ascontiguousarray(prev_irr, dtype=np.float64) if prev_irr is not None else None
+        pd = (np.ascontiguousarray(prev_depth, dtype=np.float64)
+              if prev_depth is not None else None)
+        fd = FrameDesc()
+        fd.dir_to_light[:] = [float(v) for v in frame.dir_to_light]
+        fd.radiance[:] = [float(v) for v in frame.radiance_rgb]
+        fd.rotation_seed = int(frame.rotation_seed)
+        fd.reset_history = int(reset)
+        if threads <= 0:
+            threads = min(16, os.cpu_count() or 1)
+        rc = lib().orc_update_probes(
+            self.ref, ctypes.byref(fd), _p(pi) if pi is not None else None,
+            _p(pd) if pd is not None else None, _p(probes), ctypes.c_int32(cnt), _p(irr),
+            _p(dep), _p(pl) if pl is not None else None, _p(rec) if rec is not None else None,
+            ctypes.c_int32(threads))
+        if rc != 0:
+            raise RuntimeError("orc_update_probes failed")
+        return irr, dep, pl, rec
+
+    def run_frames(self, frames, init: Optional[Tuple[np.ndarray, np.ndarray]] = None,
+                   reset_first: bool = True, threads: int = 0):
+        """Free-run the listed frames from ``init`` (zeros by default); returns every atlas."""
+        ri, rd = self.irr_res + 2, self.depth_res + 2
+        if init is None:
+            irr = np.zeros((self.num_probes, ri, ri, 3))
+            dep = np.zeros((self.num_probes, rd, rd, 2))
+        else:
+            irr = np.asarray(init[0], dtype=np.float64)
+            dep = np.asarray(init[1], dtype=np.float64)
+        out = []
+        for k, fr in enumerate(frames):
+            irr, dep, _, _ = self.update_probes(fr, reset_first and k == 0, irr, dep,
+                                                threads=threads)
+            out.append((irr, dep))
+        return out
+
+
+# -- free functions -------------------------------------------------------
+
+def splitmix64_sequence(seed: int, count: int) -> List[int]:
+    st = ctypes.c_uint64(seed)
+    return [int(lib().orc_splitmix64(ctypes.byref(st))) for _ in range(count)]
+
+
+def frame_rotation(seed: int) -> np.ndarray:
+    q = (ctypes.c_double * 9)()
+    lib().orc_frame_rotation(ctypes.c_uint64(seed), q)
+    return np.array(list(q)).reshape(3, 3)
+
+
+def ray_directions(seed: int, rays: int) -> np.ndarray:
+    out = np.zeros((rays, 3))
+    lib().orc_ray_directions(ctypes.c_uint64(seed), ctypes.c_int32(rays), _p(out))
+    return out
+
+
+def oct_encode(n) -> np.ndarray:
+    na = (ctypes.c_double * 3)(*[float(v) for v in n])
+    uv = (ctypes.c_double * 2)()
+    lib().orc_oct_encode(na, uv)
+    return np.array(list(uv))
+
+
+def oct_decode(uv) -> np.ndarray:
+    ua = (ctypes.c_double * 2)(*[float(v) for v in uv])
+    n = (ctypes.c_double * 3)()
+    lib().orc_oct_decode(ua, n)
+    return np.array(list(n))
+
+
+def texel_direction(res: int, i: int, j: int) -> np.ndarray:
+    n = (ctypes.c_double * 3)()
+    lib().orc_texel_direction(ctypes.c_int32(res), ctypes.c_int32(i), ctypes.c_int32(j), n)
+    return np.array(list(n))
+
+
+def border_source(res: int, a: int, b: int) -> Tuple[int, int]:
+    i = ctypes.c_int32()
+    j = ctypes.c_int32()
+    lib().orc_border_source(ctypes.c_int32(res), ctypes.c_int32(a), ctypes.c_int32(b),
+                            ctypes.byref(i), ctypes.byref(j))
+    return int(i.value), int(j.value)
+
+
+def record_fields(rec: np.ndarray):
+    """Split records [..., 8] into named fields (t and normal as float32)."""
+    rec = np.asarray(rec, dtype=np.int32)
+    return dict(kind=rec[..., 0] & 0xFF, level=(rec[..., 0] >> 8) & 0xFF, steps=rec[..., 1],
+                visibility=rec[..., 2], shadow_steps=rec[..., 3],
+                t=rec[..., 4].view(np.float32), normal=rec[..., 5:8].view(np.float32))

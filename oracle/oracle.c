@@ -1,0 +1,693 @@
+/*
+ * Reference checker for the SDFDDGI per-frame probe update.
+ * TEST INFRASTRUCTURE ONLY: see oracle.h for the precision policy and layouts.
+ * Only the test-suite, the smoke check and the benchmark's CPU-baseline leg use
+ * this file; it shares no code with the GPU library.
+ *
+ * What it computes, step by step (paper Sec. 3.3, Probe update):
+ *   1. per frame, one random rotation of a spherical-Fibonacci direction set
+ *      (the paper's random low-discrepancy ray directions);
+ *   2. per probe and ray, a sphere trace through the baked distance grid
+ *      (the paper's sphere tracing of probe rays);
+ *   3. at a hit, the radiance leaving the hit point: albedo/pi times the sum
+ *      of the direct sun term, seen through an SDF shadow ray, and the previous
+ *      frame's probe irradiance scaled by the multi-bounce coefficient (the
+ *      paper's hit shading and its reuse of last frame's probes for
+ *      multi-bounce);
+ *   4. per texel direction D of the octahedral map, Eq. 3's irradiance
+ *      E(D) = integral of max(0, cos(D, D')) L(D') dD' estimated from the ray
+ *      samples, plus the depth moments of the ray distances;
+ *   5. the temporal mix of new and old values (the paper's temporal mixing),
+ *      skipped when the probe's history is rejected (Alg. 1's
+ *      markRejectHistory);
+ *   6. the octahedral tile's one-texel border.
+ */
+#define _GNU_SOURCE
+#include "oracle.h"
+
+#include <math.h>
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+
+static const double kPi = 3.14159265358979323846;
+
+/* ======================================================================== */
+/* Per-frame constants                                                       */
+/* ======================================================================== */
+
+/* SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
+ * generators", OOPSLA 2014): a Weyl sequence with increment 0x9E3779B97F4A7C15
+ * followed by a 64-bit finaliser. */
+uint64_t orc_splitmix64(uint64_t *state)
+{
+    *state += 0x9E3779B97F4A7C15ull;
+    uint64_t z = *state;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+static double unit_double(uint64_t *state)
+{
+    return (double)(orc_splitmix64(state) >> 11) * 0x1.0p-53;
+}
+
+/* One uniformly random rotation per frame (Shoemake, "Uniform random
+ * rotations", Graphics Gems III, 1992): three uniforms u1,u2,u3 give the unit
+ * quaternion (x,y,z,w) = (sqrt(1-u1) sin 2pi u2, sqrt(1-u1) cos 2pi u2,
+ * sqrt(u1) sin 2pi u3, sqrt(u1) cos 2pi u3), turned into a row-major matrix. */
+void orc_frame_rotation(uint64_t seed, double q[9])
+{
+    uint64_t st = seed;
+    double u1 = unit_double(&st);
+    double u2 = unit_double(&st);
+    double u3 = unit_double(&st);
+    double two_pi = 2.0 * kPi;
+    double r1 = sqrt(1.0 - u1);
+    double r2 = sqrt(u1);
+    double t1 = two_pi * u2;
+    double t2 = two_pi * u3;
+    double x = r1 * sin(t1), y = r1 * cos(t1);
+    double z = r2 * sin(t2), w = r2 * cos(t2);
+    q[0] = 1.0 - 2.0 * (y * y + z * z);
+    q[1] = 2.0 * (x * y - z * w);
+    q[2] = 2.0 * (x * z + y * w);
+    q[3] = 2.0 * (x * y + z * w);
+    q[4] = 1.0 - 2.0 * (x * x + z * z);
+    q[5] = 2.0 * (y * z - x * w);
+    q[6] = 2.0 * (x * z - y * w);
+    q[7] = 2.0 * (y * z + x * w);
+    q[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+/* Ray i of R: the spherical-Fibonacci point z = 1 - (2i+1)/R,
+ * phi = 2 pi frac(i * gamma) with gamma = (sqrt 5 - 1)/2, rotated by the
+ * frame's rotation (Sec. 3.3: random low-discrepancy directions). */
+void orc_ray_directions(uint64_t seed, int32_t rays, double *dirs)
+{
+    double q[9];
+    orc_frame_rotation(seed, q);
+    double gamma = (sqrt(5.0) - 1.0) * 0.5;
+    double two_pi = 2.0 * kPi;
+    for (int32_t i = 0; i < rays; ++i) {
+        double z = 1.0 - (2.0 * (double)i + 1.0) / (double)rays;
+        double r = sqrt(1.0 - z * z);
+        double g = (double)i * gamma;
+        double phi = two_pi * (g - floor(g));
+        double s0 = r * cos(phi), s1 = r * sin(phi), s2 = z;
+        for (int a = 0; a < 3; ++a)
+            dirs[3 * i + a] = q[3 * a + 0] * s0 + q[3 * a + 1] * s1 + q[3 * a + 2] * s2;
+    }
+}
+
+/* Probe p = x + nx*(y + ny*z) sits on the uniform grid (Sec. 3.2). */
+void orc_probe_position(const orc_setup *s, int32_t p, double pos[3])
+{
+    int32_t idx[3];
+    idx[0] = p % s->probe_n[0];
+    idx[1] = (p / s->probe_n[0]) % s->probe_n[1];
+    idx[2] = p / (s->probe_n[0] * s->probe_n[1]);
+    for (int c = 0; c < 3; ++c)
+        pos[c] = s->probe_origin[c] + s->probe_spacing[c] * (double)idx[c];
+}
+
+/* ======================================================================== */
+/* Octahedral parameterisation (Sec. 3.3 stores each probe's directions in   */
+/* an octahedral map, after Cigolle et al. 2014).                            */
+/* ======================================================================== */
+
+static double sgn(double v) { return v >= 0.0 ? 1.0 : -1.0; }
+
+void orc_oct_encode(const double n[3], double uv[2])
+{
+    double l1 = fabs(n[0]) + fabs(n[1]) + fabs(n[2]);
+    double u = n[0] / l1, v = n[1] / l1;
+    if (n[2] < 0.0) {
+        double fu = (1.0 - fabs(v)) * sgn(u);
+        double fv = (1.0 - fabs(u)) * sgn(v);
+        u = fu;
+        v = fv;
+    }
+    uv[0] = u;
+    uv[1] = v;
+}
+
+void orc_oct_decode(const double uv[2], double n[3])
+{
+    double x = uv[0], y = uv[1];
+    double z = 1.0 - fabs(x) - fabs(y);
+    if (z < 0.0) {
+        double fx = (1.0 - fabs(y)) * sgn(x);
+        double fy = (1.0 - fabs(x)) * sgn(y);
+        x = fx;
+        y = fy;
+    }
+    double len = sqrt(x * x + y * y + z * z);
+    n[0] = x / len;
+    n[1] = y / len;
+    n[2] = z / len;
+}
+
+/* Interior texel (i = column along u, j = row along v) has its centre at
+ * ((i + 1/2)/res * 2 - 1, (j + 1/2)/res * 2 - 1). */
+void orc_texel_direction(int32_t res, int32_t i, int32_t j, double n[3])
+{
+    double uv[2];
+    uv[0] = ((double)i + 0.5) / (double)res * 2.0 - 1.0;
+    uv[1] = ((double)j + 0.5) / (double)res * 2.0 - 1.0;
+    orc_oct_decode(uv, n);
+}
+
+/* Padded texel (a = column, b = row, both 0..res+1) -> interior source
+ * (i, j). Crossing an edge of the octahedral square lands on the same edge
+ * reflected about its midpoint; the four corners all meet at the -z pole and
+ * take the diagonally opposite interior corner. */
+void orc_border_source(int32_t res, int32_t a, int32_t b, int32_t *i, int32_t *j)
+{
+    int32_t n = res;
+    int left = a == 0, right = a == n + 1, top = b == 0, bottom = b == n + 1;
+    if ((left || right) && (top || bottom)) {
+        *i = left ? n - 1 : 0;
+        *j = top ? n - 1 : 0;
+    } else if (top || bottom) {
+        *i = n - a;
+        *j = top ? 0 : n - 1;
+    } else if (left || right) {
+        *i = left ? 0 : n - 1;
+        *j = n - b;
+    } else {
+        *i = a - 1;
+        *j = b - 1;
+    }
+}
+
+/* ======================================================================== */
+/* Geometry in binary32: the integer decisions of the trace.                 */
+/* ======================================================================== */
+
+typedef struct {
+    float org[3];
+    float inv;   /* (float)(1 / spacing) */
+    float half;  /* (float)(spacing / 2): central-difference offset */
+} lvl32;
+
+static void level_constants(const orc_level *L, lvl32 *g)
+{
+    for (int c = 0; c < 3; ++c) g->org[c] = (float)L->origin[c];
+    g->inv = (float)(1.0 / L->spacing);
+    g->half = (float)(0.5 * L->spacing);
+}
+
+/* Trilinear interpolation at grid coordinate u of a vertex-centred grid; the
+ * cell is clamped to the grid and the fraction to [0,1]. */
+static float trilinear32(const float *grid, const int32_t n[3], const float u[3])
+{
+    int32_t i[3];
+    float f[3];
+    for (int c = 0; c < 3; ++c) {
+        float fl = floorf(u[c]);
+        fl = fminf(fmaxf(fl, 0.0f), (float)(n[c] - 2));
+        i[c] = (int32_t)fl;
+        f[c] = fminf(fmaxf(u[c] - fl, 0.0f), 1.0f);
+    }
+    size_t sx = 1, sy = (size_t)n[0], sz = (size_t)n[0] * (size_t)n[1];
+    const float *g = grid + (size_t)i[2] * sz + (size_t)i[1] * sy + (size_t)i[0];
+    float v000 = g[0], v100 = g[sx], v010 = g[sy], v110 = g[sy + sx];
+    float v001 = g[sz], v101 = g[sz + sx], v011 = g[sz + sy], v111 = g[sz + sy + sx];
+    float c00 = fmaf(f[0], v100 - v000, v000);
+    float c10 = fmaf(f[0], v110 - v010, v010);
+    float c01 = fmaf(f[0], v101 - v001, v001);
+    float c11 = fmaf(f[0], v111 - v011, v011);
+    float c0 = fmaf(f[1], c10 - c00, c00);
+    float c1 = fmaf(f[1], c11 - c01, c01);
+    return fmaf(f[2], c1 - c0, c0);
+}
+
+static void grid_coord32(const lvl32 *g, const float x[3], float u[3])
+{
+    for (int c = 0; c < 3; ++c) u[c] = (x[c] - g->org[c]) * g->inv;
+}
+
+float orc_sdf32(const orc_setup *s, int32_t level, const float x[3])
+{
+    lvl32 g;
+    level_constants(&s->level[level], &g);
+    float u[3];
+    grid_coord32(&g, x, u);
+    return trilinear32(s->level[level].sdf, s->level[level].n, u);
+}
+
+/* The finest level whose box, shrunk by one voxel, holds x; the coarsest level
+ * counts with its full box. -1 when x is outside the coarsest box. */
+int32_t orc_level32(const orc_setup *s, const float x[3])
+{
+    for (int32_t L = 0; L < s->num_levels; ++L) {
+        lvl32 g;
+        level_constants(&s->level[L], &g);
+        int inner = L < s->num_levels - 1;
+        int ok = 1;
+        for (int c = 0; c < 3; ++c) {
+            float u = (x[c] - g.org[c]) * g.inv;
+            float lo = inner ? 1.0f : 0.0f;
+            float hi = (float)(s->level[L].n[c] - (inner ? 2 : 1));
+            if (!(u >= lo && u <= hi)) ok = 0;
+        }
+        if (ok) return L;
+    }
+    return -1;
+}
+
+typedef struct {
+    int32_t kind, steps, level;
+    float t;
+    float x[3];
+} trace32_result;
+
+/* Sphere tracing (Hart 1996, as used in Sec. 3.3): step along the ray by the
+ * distance bound until it falls under the hit epsilon, the ray passes t_max or
+ * leaves the grid, or the step budget runs out (then: a hit at the last
+ * sample). A primary ray whose first sample is inside geometry reports
+ * "inside". */
+static trace32_result trace32(const orc_setup *s, const float o[3], const float w[3],
+                              int primary)
+{
+    trace32_result r = {ORC_HIT_EXHAUSTED, s->max_steps, -1, 0.0f, {0.0f, 0.0f, 0.0f}};
+    float t = 0.0f;
+    for (int32_t k = 0; k < s->max_steps; ++k) {
+        if (t > s->t_max) {
+            r.kind = ORC_MISS_TMAX;
+            r.steps = k;
+            return r;
+        }
+        float x[3];
+        for (int c = 0; c < 3; ++c) x[c] = fmaf(t, w[c], o[c]);
+        int32_t L = orc_level32(s, x);
+        if (L < 0) {
+            r.kind = ORC_MISS_EXIT;
+            r.steps = k;
+            return r;
+        }
+        float d = orc_sdf32(s, L, x);
+        r.t = t;
+        r.level = L;
+        memcpy(r.x, x, sizeof x);
+        if (primary && k == 0 && d < 0.0f) {
+            r.kind = ORC_INSIDE;
+            r.steps = 1;
+            return r;
+        }
+        if (d < s->hit_eps) {
+            r.kind = ORC_HIT;
+            r.steps = k + 1;
+            return r;
+        }
+        t = fmaf(s->relax, d, t);
+    }
+    return r; /* exhausted: hit at the last sample */
+}
+
+/* Surface normal from central differences of the grid the hit was found on,
+ * offset half a voxel; a vanishing gradient falls back to facing the ray. */
+static void normal32(const orc_setup *s, int32_t level, const float x[3], const float w[3],
+                     float n[3])
+{
+    lvl32 g;
+    level_constants(&s->level[level], &g);
+    float grad[3];
+    for (int c = 0; c < 3; ++c) {
+        float xp[3] = {x[0], x[1], x[2]}, xm[3] = {x[0], x[1], x[2]};
+        xp[c] = x[c] + g.half;
+        xm[c] = x[c] - g.half;
+        float up[3], um[3];
+        grid_coord32(&g, xp, up);
+        grid_coord32(&g, xm, um);
+        grad[c] = trilinear32(s->level[level].sdf, s->level[level].n, up) -
+                  trilinear32(s->level[level].sdf, s->level[level].n, um);
+    }
+    float len2 = fmaf(grad[2], grad[2], fmaf(grad[1], grad[1], grad[0] * grad[0]));
+    if (!(len2 >= 1e-24f)) {
+        for (int c = 0; c < 3; ++c) n[c] = -w[c];
+        return;
+    }
+    float inv = 1.0f / sqrtf(len2);
+    for (int c = 0; c < 3; ++c) n[c] = grad[c] * inv;
+}
+
+typedef struct {
+    trace32_result prim;
+    float n[3];
+    int32_t visibility;     /* 1 lit, 0 blocked, -1 not traced */
+    int32_t shadow_steps;
+} ray32;
+
+static int is_hit(int32_t kind) { return kind == ORC_HIT || kind == ORC_HIT_EXHAUSTED; }
+
+/* Primary trace, hit normal and the SDF shadow ray toward the light. The
+ * shadow ray starts at x + bias*n, is traced only where n.l > 0, and counts as
+ * blocked on a hit or on running out of steps. */
+static ray32 ray_geometry32(const orc_setup *s, const float o[3], const float w[3],
+                            const float l[3])
+{
+    ray32 g;
+    memset(&g, 0, sizeof g);
+    g.prim = trace32(s, o, w, 1);
+    g.visibility = -1;
+    if (!is_hit(g.prim.kind)) return g;
+    normal32(s, g.prim.level, g.prim.x, w, g.n);
+    float ndl = fmaf(g.n[2], l[2], fmaf(g.n[1], l[1], g.n[0] * l[0]));
+    if (ndl > 0.0f) {
+        float xs[3];
+        for (int c = 0; c < 3; ++c) xs[c] = fmaf(g.n[c], s->shadow_bias, g.prim.x[c]);
+        trace32_result sh = trace32(s, xs, l, 0);
+        g.visibility = is_hit(sh.kind) ? 0 : 1;
+        g.shadow_steps = sh.steps;
+    }
+    return g;
+}
+
+static int32_t bits_of(float v)
+{
+    int32_t b;
+    memcpy(&b, &v, sizeof b);
+    return b;
+}
+
+static void fill_record(const orc_setup *s, const ray32 *g, int32_t rec[8])
+{
+    float t = g->prim.t;
+    if (g->prim.kind == ORC_MISS_TMAX || g->prim.kind == ORC_MISS_EXIT) t = s->t_max;
+    if (g->prim.kind == ORC_INSIDE) t = 0.0f;
+    int32_t lev = is_hit(g->prim.kind) ? g->prim.level : 0;
+    rec[0] = g->prim.kind | (lev << 8);
+    rec[1] = g->prim.steps;
+    rec[2] = g->visibility;
+    rec[3] = g->shadow_steps;
+    rec[4] = bits_of(t);
+    rec[5] = bits_of(g->n[0]);
+    rec[6] = bits_of(g->n[1]);
+    rec[7] = bits_of(g->n[2]);
+}
+
+static void light_direction(const float in[3], double l64[3], float l32[3])
+{
+    double d0 = in[0], d1 = in[1], d2 = in[2];
+    double len = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    l64[0] = d0 / len;
+    l64[1] = d1 / len;
+    l64[2] = d2 / len;
+    for (int c = 0; c < 3; ++c) l32[c] = (float)l64[c];
+}
+
+void orc_trace_ray32(const orc_setup *s, const float origin[3], const float dir[3],
+                     const float dir_to_light[3], int32_t record[8])
+{
+    double l64[3];
+    float l32[3];
+    light_direction(dir_to_light, l64, l32);
+    ray32 g = ray_geometry32(s, origin, dir, l32);
+    fill_record(s, &g, record);
+}
+
+/* ======================================================================== */
+/* Radiometry in binary64                                                    */
+/* ======================================================================== */
+
+static double trilinear64(const float *grid, int32_t comps, int32_t comp, const int32_t n[3],
+                          const double u[3])
+{
+    int32_t i[3];
+    double f[3];
+    for (int c = 0; c < 3; ++c) {
+        double fl = floor(u[c]);
+        if (fl < 0.0) fl = 0.0;
+        if (fl > (double)(n[c] - 2)) fl = (double)(n[c] - 2);
+        i[c] = (int32_t)fl;
+        double fr = u[c] - fl;
+        f[c] = fr < 0.0 ? 0.0 : (fr > 1.0 ? 1.0 : fr);
+    }
+    double acc = 0.0;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                size_t v = ((size_t)(i[2] + dz) * n[1] + (size_t)(i[1] + dy)) * n[0] +
+                           (size_t)(i[0] + dx);
+                double w = (dx ? f[0] : 1.0 - f[0]) * (dy ? f[1] : 1.0 - f[1]) *
+                           (dz ? f[2] : 1.0 - f[2]);
+                acc += w * (double)grid[v * comps + comp];
+            }
+    return acc;
+}
+
+/* Irradiance at x for direction n from a probe atlas: trilinear over the 8
+ * probes of the cell around x, each read bilinearly from its padded
+ * octahedral tile (the probe interpolation of Sec. 3.4, without visibility). */
+void orc_interp_irradiance(const orc_setup *s, const double *atlas, const double x[3],
+                           const double n[3], double out[3])
+{
+    int32_t base[3];
+    double f[3];
+    for (int c = 0; c < 3; ++c) {
+        double g = (x[c] - s->probe_origin[c]) / s->probe_spacing[c];
+        double b = floor(g);
+        if (b < 0.0) b = 0.0;
+        if (b > (double)(s->probe_n[c] - 2)) b = (double)(s->probe_n[c] - 2);
+        base[c] = (int32_t)b;
+        double fr = g - b;
+        f[c] = fr < 0.0 ? 0.0 : (fr > 1.0 ? 1.0 : fr);
+    }
+    int32_t res = s->irr_res, side = res + 2;
+    double uv[2];
+    orc_oct_encode(n, uv);
+    int32_t a0[2];
+    double fa[2];
+    for (int k = 0; k < 2; ++k) {
+        double sc = ((double)res * (uv[k] + 1.0) + 1.0) * 0.5; /* padded texel units */
+        double fl = floor(sc);
+        if (fl < 0.0) fl = 0.0;
+        if (fl > (double)res) fl = (double)res;
+        a0[k] = (int32_t)fl;
+        double fr = sc - fl;
+        fa[k] = fr < 0.0 ? 0.0 : (fr > 1.0 ? 1.0 : fr);
+    }
+    out[0] = out[1] = out[2] = 0.0;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                double wp = (dx ? f[0] : 1.0 - f[0]) * (dy ? f[1] : 1.0 - f[1]) *
+                            (dz ? f[2] : 1.0 - f[2]);
+                int32_t p = (base[0] + dx) +
+                            s->probe_n[0] * ((base[1] + dy) + s->probe_n[1] * (base[2] + dz));
+                const double *tile = atlas + (size_t)p * side * side * 3;
+                for (int dv = 0; dv < 2; ++dv)
+                    for (int du = 0; du < 2; ++du) {
+                        double wt = (du ? fa[0] : 1.0 - fa[0]) * (dv ? fa[1] : 1.0 - fa[1]);
+                        const double *texel = tile + ((size_t)(a0[1] + dv) * side +
+                                                      (size_t)(a0[0] + du)) * 3;
+                        for (int c = 0; c < 3; ++c) out[c] += wp * wt * texel[c];
+                    }
+            }
+}
+
+/* Radiance carried back along one probe ray, and its distance (payload). */
+static void shade_ray(const orc_setup *s, const orc_frame *f, const double l64[3],
+                      const double *prev_irr, const ray32 *g, double out[4])
+{
+    int32_t kind = g->prim.kind;
+    if (kind == ORC_MISS_TMAX || kind == ORC_MISS_EXIT) {
+        for (int c = 0; c < 3; ++c) out[c] = (double)s->sky[c];
+        out[3] = (double)s->t_max;
+        return;
+    }
+    if (kind == ORC_INSIDE) {
+        out[0] = out[1] = out[2] = out[3] = 0.0;
+        return;
+    }
+    double x[3], n[3];
+    for (int c = 0; c < 3; ++c) {
+        x[c] = (double)g->prim.x[c];
+        n[c] = (double)g->n[c];
+    }
+    const orc_level *L = &s->level[g->prim.level];
+    double albedo[3];
+    if (L->albedo) {
+        double u[3];
+        for (int c = 0; c < 3; ++c) u[c] = (x[c] - L->origin[c]) / L->spacing;
+        for (int c = 0; c < 3; ++c) albedo[c] = trilinear64(L->albedo, 3, c, L->n, u);
+    } else {
+        for (int c = 0; c < 3; ++c) albedo[c] = (double)s->albedo[c];
+    }
+    double ndl = n[0] * l64[0] + n[1] * l64[1] + n[2] * l64[2];
+    double lit = (g->visibility == 1 && ndl > 0.0) ? ndl : 0.0;
+    double indirect[3] = {0.0, 0.0, 0.0};
+    if (s->bounce_gain != 0.0f && prev_irr) orc_interp_irradiance(s, prev_irr, x, n, indirect);
+    for (int c = 0; c < 3; ++c) {
+        double direct = (double)f->radiance[c] * lit;
+        out[c] = albedo[c] / kPi * (direct + (double)s->bounce_gain * indirect[c]);
+    }
+    out[3] = (double)g->prim.t;
+}
+
+/* Eq. 3 estimated from the probe's ray samples as a ratio of weighted sums,
+ * E(D) = pi * sum_i w_i L_i / sum_i w_i with w_i = max(0, D . omega_i), which
+ * returns pi*L exactly when every sample sees the same radiance L. Depth
+ * moments use w_i^s. The new value is mixed with the old one by the
+ * hysteresis unless the history is rejected; a texel whose weights all vanish
+ * keeps its old value. The border is then filled from the interior. */
+static void blend_tile(const orc_setup *s, const double *dirs, int32_t reset,
+                       const double *payload, const double *prev_irr, const double *prev_depth,
+                       double *irr, double *depth)
+{
+    double h = reset ? 0.0 : (double)s->hysteresis;
+    double sharp = (double)s->depth_sharpness;
+    for (int pass = 0; pass < 2; ++pass) {
+        int32_t res = pass == 0 ? s->irr_res : s->depth_res;
+        int32_t comps = pass == 0 ? 3 : 2;
+        int32_t side = res + 2;
+        const double *old = pass == 0 ? prev_irr : prev_depth;
+        double *out = pass == 0 ? irr : depth;
+        for (int32_t j = 0; j < res; ++j)
+            for (int32_t i = 0; i < res; ++i) {
+                double dn[3];
+                orc_texel_direction(res, i, j, dn);
+                double sw = 0.0, acc[3] = {0.0, 0.0, 0.0};
+                for (int32_t r = 0; r < s->rays; ++r) {
+                    const double *w3 = dirs + 3 * r;
+                    double c = dn[0] * w3[0] + dn[1] * w3[1] + dn[2] * w3[2];
+                    double w = c > 0.0 ? c : 0.0;
+                    const double *pl = payload + 4 * (size_t)r;
+                    if (pass == 0) {
+                        sw += w;
+                        for (int k = 0; k < 3; ++k) acc[k] += w * pl[k];
+                    } else {
+                        double wd = pow(w, sharp);
+                        sw += wd;
+                        acc[0] += wd * pl[3];
+                        acc[1] += wd * pl[3] * pl[3];
+                    }
+                }
+                size_t at = ((size_t)(j + 1) * side + (size_t)(i + 1)) * comps;
+                for (int k = 0; k < comps; ++k) {
+                    double prev = old ? old[at + k] : 0.0;
+                    double v;
+                    if (sw > 0.0) {
+                        double u = (pass == 0 ? kPi : 1.0) * acc[k] / sw;
+                        v = h * prev + (1.0 - h) * u;
+                    } else {
+                        v = prev;
+                    }
+                    out[at + k] = v;
+                }
+            }
+        for (int32_t b = 0; b < side; ++b)
+            for (int32_t a = 0; a < side; ++a) {
+                if (a >= 1 && a <= res && b >= 1 && b <= res) continue;
+                int32_t si, sj;
+                orc_border_source(res, a, b, &si, &sj);
+                size_t dst = ((size_t)b * side + a) * comps;
+                size_t src = ((size_t)(sj + 1) * side + (size_t)(si + 1)) * comps;
+                for (int k = 0; k < comps; ++k) out[dst + k] = out[src + k];
+            }
+    }
+}
+
+int32_t orc_blend_probe(const orc_setup *s, uint64_t rotation_seed, int32_t reset_history,
+                        const double *payload, const double *prev_irr_tile,
+                        const double *prev_depth_tile, double *irr_tile, double *depth_tile)
+{
+    if (s->rays <= 0) return -1;
+    double *dirs = (double *)malloc(sizeof(double) * 3 * (size_t)s->rays);
+    if (!dirs) return -1;
+    orc_ray_directions(rotation_seed, s->rays, dirs);
+    blend_tile(s, dirs, reset_history, payload, prev_irr_tile, prev_depth_tile, irr_tile,
+               depth_tile);
+    free(dirs);
+    return 0;
+}
+
+/* ======================================================================== */
+/* Whole-frame update of a list of probes (Jacobi: every probe reads only    */
+/* the previous frame's atlas).                                              */
+/* ======================================================================== */
+
+typedef struct {
+    const orc_setup *s;
+    const orc_frame *f;
+    const double *prev_irr, *prev_depth;
+    const int32_t *probes;
+    int32_t count, stride, first;
+    double *irr_tiles, *depth_tiles, *payload;
+    int32_t *records;
+    const double *dirs64;
+    const float *dirs32;
+    double l64[3];
+    float l32[3];
+} frame_job;
+
+static void *frame_worker(void *arg)
+{
+    const frame_job *J = (const frame_job *)arg;
+    const orc_setup *s = J->s;
+    int32_t R = s->rays;
+    size_t irr_tile = (size_t)(s->irr_res + 2) * (s->irr_res + 2) * 3;
+    size_t dep_tile = (size_t)(s->depth_res + 2) * (s->depth_res + 2) * 2;
+    double *pl = (double *)malloc(sizeof(double) * 4 * (size_t)R);
+    if (!pl) return (void *)1;
+    for (int32_t q = J->first; q < J->count; q += J->stride) {
+        int32_t p = J->probes[q];
+        double pos[3];
+        orc_probe_position(s, p, pos);
+        float o[3] = {(float)pos[0], (float)pos[1], (float)pos[2]};
+        for (int32_t r = 0; r < R; ++r) {
+            ray32 g = ray_geometry32(s, o, J->dirs32 + 3 * r, J->l32);
+            shade_ray(s, J->f, J->l64, J->prev_irr, &g, pl + 4 * r);
+            if (J->records) fill_record(s, &g, J->records + ((size_t)q * R + r) * 8);
+        }
+        if (J->payload) memcpy(J->payload + (size_t)q * R * 4, pl, sizeof(double) * 4 * R);
+        blend_tile(s, J->dirs64, J->f->reset_history, pl,
+                   J->prev_irr ? J->prev_irr + (size_t)p * irr_tile : NULL,
+                   J->prev_depth ? J->prev_depth + (size_t)p * dep_tile : NULL,
+                   J->irr_tiles + (size_t)q * irr_tile, J->depth_tiles + (size_t)q * dep_tile);
+    }
+    free(pl);
+    return NULL;
+}
+
+int32_t orc_update_probes(const orc_setup *s, const orc_frame *f, const double *prev_irr,
+                          const double *prev_depth, const int32_t *probes, int32_t count,
+                          double *irr_tiles, double *depth_tiles, double *payload,
+                          int32_t *records, int32_t threads)
+{
+    if (s->rays <= 0 || s->max_steps < 1 || count < 0) return -1;
+    int32_t P = s->probe_n[0] * s->probe_n[1] * s->probe_n[2];
+    for (int32_t q = 0; q < count; ++q)
+        if (probes[q] < 0 || probes[q] >= P) return -1;
+    double *d64 = (double *)malloc(sizeof(double) * 3 * (size_t)s->rays);
+    float *d32 = (float *)malloc(sizeof(float) * 3 * (size_t)s->rays);
+    if (!d64 || !d32) { free(d64); free(d32); return -1; }
+    orc_ray_directions(f->rotation_seed, s->rays, d64);
+    for (int32_t k = 0; k < 3 * s->rays; ++k) d32[k] = (float)d64[k];
+    if (threads < 1) threads = 1;
+    if (threads > 256) threads = 256;
+    frame_job jobs[256];
+    pthread_t th[256];
+    int32_t rc = 0;
+    for (int32_t t = 0; t < threads; ++t) {
+        frame_job *J = &jobs[t];
+        J->s = s; J->f = f; J->prev_irr = prev_irr; J->prev_depth = prev_depth;
+        J->probes = probes; J->count = count; J->stride = threads; J->first = t;
+        J->irr_tiles = irr_tiles; J->depth_tiles = depth_tiles; J->payload = payload;
+        J->records = records; J->dirs64 = d64; J->dirs32 = d32;
+        light_direction(f->dir_to_light, J->l64, J->l32);
+    }
+    for (int32_t t = 1; t < threads; ++t) pthread_create(&th[t], NULL, frame_worker, &jobs[t]);
+    if (frame_worker(&jobs[0])) rc = -1;
+    for (int32_t t = 1; t < threads; ++t) {
+        void *ret = NULL;
+        pthread_join(th[t], &ret);
+        if (ret) rc = -1;
+    }
+    free(d64);
+    free(d32);
+    return rc;
+}

@@ -1,0 +1,123 @@
+/*
+ * Reference checker for the SDFDDGI per-frame probe update (Hu et al.,
+ * "Signed Distance Fields Dynamic Diffuse Global Illumination", Sec. 3.3).
+ *
+ * TEST INFRASTRUCTURE ONLY. This is a plain, slow, serial-per-ray CPU
+ * implementation used by the test-suite, the smoke check and the benchmark's
+ * CPU-baseline leg to check the GPU library. The library never links, loads or
+ * calls it, and it shares no code with the library.
+ *
+ * Precision policy.
+ *   - Every quantity that decides an integer (which cascade level a point
+ *     falls in, when a sphere-traced ray stops and why, how many steps it
+ *     took, whether a shadow ray is traced and whether it is blocked) is
+ *     computed in IEEE binary32 following one fixed operation sequence, the
+ *     precision the GPU kernel takes these decisions in. fmaf() marks every
+ *     fused multiply-add of that sequence; everything else is a single
+ *     correctly rounded binary32 operation. Compile with -ffp-contract=off.
+ *   - Everything continuous (albedo, direct light, the multi-bounce lookup,
+ *     ray radiance, the Eq. 3 irradiance estimate, depth moments and the
+ *     temporal blend) is computed in binary64 from those binary32 results.
+ *
+ * Array layouts (all row-major, x fastest):
+ *   SDF level       float [n2][n1][n0], vertex (i,j,k) at origin + spacing*(i,j,k)
+ *   albedo level    float [n2][n1][n0][3]
+ *   irradiance tile [res+2 rows (v)][res+2 cols (u)][3], interior at 1..res
+ *   depth tile      [res+2][res+2][2]  (E[t], E[t^2])
+ *   atlas           tiles of all probes, probe p = x + nx*(y + ny*z)
+ */
+#ifndef SDFDDGI_ORACLE_H
+#define SDFDDGI_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_MAX_LEVELS 4
+
+/* Ray outcome codes (low byte of a record's first word; level in bits 8..15). */
+enum {
+    ORC_MISS_TMAX = 0,      /* travelled past t_max                       */
+    ORC_MISS_EXIT = 1,      /* left the outermost grid level              */
+    ORC_HIT = 2,            /* distance fell below the hit epsilon        */
+    ORC_HIT_EXHAUSTED = 3,  /* ran out of steps: hit at the last sample   */
+    ORC_INSIDE = 4          /* primary ray started inside geometry        */
+};
+
+typedef struct {
+    int32_t n[3];
+    double origin[3];
+    double spacing;
+    const float *sdf;
+    const float *albedo;  /* NULL: the constant albedo of the setup */
+} orc_level;
+
+typedef struct {
+    int32_t num_levels;           /* level 0 finest; levels are nested */
+    orc_level level[ORC_MAX_LEVELS];
+    int32_t probe_n[3];
+    double probe_origin[3];
+    double probe_spacing[3];
+    int32_t rays;
+    int32_t max_steps;
+    int32_t irr_res;
+    int32_t depth_res;
+    float hit_eps;
+    float t_max;
+    float hysteresis;
+    float bounce_gain;
+    float depth_sharpness;
+    float shadow_bias;
+    float relax;
+    float sky[3];
+    float albedo[3];
+} orc_setup;
+
+typedef struct {
+    float dir_to_light[3];
+    float radiance[3];
+    uint64_t rotation_seed;
+    int32_t reset_history;  /* 1: no temporal blending this frame (M = U) */
+} orc_frame;
+
+/* ---- per-frame constants ---------------------------------------------- */
+uint64_t orc_splitmix64(uint64_t *state);
+void orc_frame_rotation(uint64_t seed, double q[9]);
+void orc_ray_directions(uint64_t seed, int32_t rays, double *dirs /* [rays][3] */);
+void orc_probe_position(const orc_setup *s, int32_t probe, double pos[3]);
+
+/* ---- octahedral parameterisation --------------------------------------- */
+void orc_oct_encode(const double n[3], double uv[2]);
+void orc_oct_decode(const double uv[2], double n[3]);
+void orc_texel_direction(int32_t res, int32_t i, int32_t j, double n[3]);
+void orc_border_source(int32_t res, int32_t a, int32_t b, int32_t *i, int32_t *j);
+
+/* ---- binary32 geometry -------------------------------------------------- */
+float orc_sdf32(const orc_setup *s, int32_t level, const float x[3]);
+int32_t orc_level32(const orc_setup *s, const float x[3]);
+/* record: [kind|level<<8, steps, visibility(1 lit, 0 blocked, -1 not traced),
+ *          shadow steps, bits(t), bits(nx), bits(ny), bits(nz)] */
+void orc_trace_ray32(const orc_setup *s, const float origin[3], const float dir[3],
+                     const float dir_to_light[3], int32_t record[8]);
+
+/* ---- binary64 radiometry and blending ---------------------------------- */
+void orc_interp_irradiance(const orc_setup *s, const double *irr_atlas, const double x[3],
+                           const double n[3], double out[3]);
+int32_t orc_blend_probe(const orc_setup *s, uint64_t rotation_seed, int32_t reset_history,
+                        const double *payload /* [rays][4] */,
+                        const double *prev_irr_tile, const double *prev_depth_tile,
+                        double *irr_tile, double *depth_tile);
+int32_t orc_update_probes(const orc_setup *s, const orc_frame *f,
+                          const double *prev_irr, const double *prev_depth,
+                          const int32_t *probes, int32_t count,
+                          double *irr_tiles, double *depth_tiles,
+                          double *payload /* [count][rays][4] or NULL */,
+                          int32_t *records /* [count][rays][8] or NULL */,
+                          int32_t threads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
