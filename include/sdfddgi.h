@@ -1,0 +1,238 @@
+/*
+ * sdfddgi.h -- C ABI of the MI355X (gfx950) implementation of the per-frame
+ * probe update of "Signed Distance Fields Dynamic Diffuse Global Illumination"
+ * (Hu et al., arXiv 2007.14394), Sec. 3.3 "Probe update".
+ *
+ * One call to sdfddgi_update_frame performs, for every probe of a uniform
+ * grid (Sec. 3.2, Eq. 2: irradiance sampled at probe positions P over
+ * directions D):
+ *   1. rotate a spherical-Fibonacci ray set by one random rotation drawn from
+ *      the frame's seed (Sec. 3.3: random low-discrepancy directions);
+ *   2. sphere-trace every ray through the baked signed distance grid (Sec. 3.3);
+ *   3. shade each hit with the sun seen through an SDF shadow ray plus the
+ *      previous frame's probe irradiance times the multi-bounce coefficient
+ *      (Sec. 3.3, multi-bounce through last frame's probes);
+ *   4. estimate Eq. 3, E(D) = integral over the sphere of max(0, cos(D, D'))
+ *      L(D') dD', for every texel direction D of the probe's octahedral map, and
+ *      the first two moments of the ray distances for the depth map;
+ *   5. mix with the previous values (Sec. 3.3, temporal mixing; skipped for
+ *      probes whose history is rejected, Alg. 1 markRejectHistory) and fill
+ *      the octahedral one-texel border.
+ *
+ * Numerical contract (what the library computes, exactly):
+ *   - Ray directions: ray i of R is the spherical-Fibonacci point
+ *     z = 1 - (2i+1)/R, r = sqrt(1 - z^2), phi = 2 pi frac(i*g), g = (sqrt5-1)/2,
+ *     rotated by the matrix of Shoemake's uniform random quaternion built
+ *     from three SplitMix64 draws u = (x >> 11) * 2^-53 of the frame seed, all
+ *     in binary64 and rounded once to binary32 (sdfddgi_ray_directions).
+ *   - Geometry (the decisions): binary32 with one fixed operation order --
+ *     grid coordinate u = (x - (float)origin) * (float)(1/spacing); cell
+ *     clamp(floor(u), 0, n-2); fraction clamp(u - cell, 0, 1); trilinear as
+ *     three rounds of lerps a + f*(b - a) evaluated as fma(f, b - a, a)
+ *     (x, then y, then z); sample point x = fma(t, w, o); step t = fma(relax, d, t).
+ *     Cascade level = finest level whose box shrunk by one voxel holds x (the
+ *     coarsest level counts with its full box; outside it the ray escapes).
+ *     A ray stops on: t > t_max (miss), leaving the grid (miss), d < 0 at the
+ *     first sample of a probe ray (inside), d < hit_eps (hit), or after
+ *     max_steps samples (hit at the last sample). Normal = central differences
+ *     at +-spacing/2 on the hit's level, scaled by 1/sqrt(|g|^2) (falls back to
+ *     -w when |g|^2 < 1e-24). Shadow ray from fma(n, shadow_bias, x) toward the
+ *     light, traced only where n.l > 0; blocked on a hit or on running out of
+ *     steps.
+ *   - Radiometry: ray radiance = albedo/pi * (E_sun + bounce_gain * E_prev),
+ *     E_sun = radiance * max(0, n.l) * visible, E_prev = the previous atlas
+ *     interpolated at (x, n) like sdfddgi_sample_irradiance; a miss carries
+ *     sky_rgb at distance t_max, a probe inside geometry carries 0 at 0.
+ *   - Eq. 3 estimator: E_t = pi * sum_i w_ti L_i / sum_i w_ti with
+ *     w_ti = max(0, n_t . w_i); depth moments sum_i w_ti^s (t_i, t_i^2) /
+ *     sum_i w_ti^s with s = depth_sharpness. Blend M = h M_old + (1-h) E with
+ *     h = hysteresis, or M = E for a probe whose history is rejected.
+ *   - Accuracy: ray decisions (outcome, step counts, shadow result, distance
+ *     and normal bits) are bit-identical to a binary32 evaluation of the
+ *     sequence above; maps agree with a binary64 evaluation of the
+ *     radiometry to about 1e-5 relative.
+ *
+ * Layouts (row-major, x fastest):
+ *   SDF level    float [n2][n1][n0], vertex (i,j,k) at origin + spacing*(i,j,k)
+ *   albedo level float [n2][n1][n0][3]
+ *   probes       p = x + nx*(y + ny*z), position origin + spacing*(x,y,z)
+ *   irradiance   float [P][irr_res+2][irr_res+2][3]  (rows = v, columns = u of
+ *                the octahedral square; interior 1..irr_res, texel (i,j) centre
+ *                at u = (i+1/2)/res*2-1, v = (j+1/2)/res*2-1; z folds at |u|+|v|=1)
+ *   depth        float [P][depth_res+2][depth_res+2][2]  (E[t], E[t^2])
+ *   payload      float [P][R][4]  (R, G, B, t) per ray
+ *   ray records  int32 [P][R][8]  (outcome | level<<8, steps, visibility
+ *                (1 lit, 0 blocked, -1 not traced), shadow steps, bits of t,
+ *                bits of the normal's x, y, z)
+ *
+ * Conventions:
+ *   - Every array argument except those of sdfddgi_ray_directions is a DEVICE
+ *     pointer owned by the caller and only read/written during the call's
+ *     stream-ordered work; sdfddgi_create copies the grids into memory the
+ *     context owns, so the caller may free them once create returns.
+ *   - All GPU work goes on the stream given to sdfddgi_create, in order, and is
+ *     asynchronous: results are valid once the caller synchronises that stream.
+ *   - Status codes only; nothing is thrown across the ABI. A failed call leaves
+ *     the context's maps as they were. sdfddgi_last_error gives the message.
+ *   - A context is used by one host thread at a time (no internal locking).
+ *     Calls on different contexts are independent.
+ */
+#ifndef SDFDDGI_H
+#define SDFDDGI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sdfddgi_ctx sdfddgi_ctx;
+
+typedef enum {
+    SDFDDGI_OK = 0,
+    SDFDDGI_EINVAL = 1,   /* bad argument: sizes, non-finite values, NULL pointers */
+    SDFDDGI_ENOMEM = 2,   /* device or host allocation failed                      */
+    SDFDDGI_EDEVICE = 3,  /* no usable gfx950 device, or a HIP call/launch failed  */
+    SDFDDGI_ESTATE = 4    /* call not valid in the context's current state         */
+} sdfddgi_status;
+
+#define SDFDDGI_MAX_LEVELS 4
+#define SDFDDGI_MAX_RAYS 1024
+
+/* Context flags (sdfddgi_params.flags). */
+#define SDFDDGI_FLAG_RECORD_RAYS 1u  /* keep per-ray records (sdfddgi_get_ray_records) */
+#define SDFDDGI_FLAG_TIMING 2u       /* time each kernel with events (sdfddgi_get_kernel_times) */
+
+/* One level of the baked distance grid. Level 0 is the finest; each coarser
+ * level must contain the finer ones (a nested cascade). */
+typedef struct {
+    int32_t n[3];              /* vertices per axis, each >= 2                    */
+    double origin[3];          /* position of vertex (0,0,0)                     */
+    double spacing;            /* vertex spacing (cubic voxels), > 0             */
+    const float *sdf;          /* device [n2][n1][n0]                            */
+    const float *albedo_rgb;   /* device [n2][n1][n0][3], or NULL: params.albedo */
+} sdfddgi_sdf_level;
+
+typedef struct {
+    int32_t num_levels;                          /* 1..SDFDDGI_MAX_LEVELS */
+    sdfddgi_sdf_level level[SDFDDGI_MAX_LEVELS];
+} sdfddgi_sdf_grid;
+
+/* The uniform probe grid of Sec. 3.2 (relocation of Alg. 1 is not applied). */
+typedef struct {
+    int32_t n[3];              /* probes per axis, each >= 2 */
+    double origin[3];
+    double spacing[3];         /* each > 0 */
+} sdfddgi_probe_grid;
+
+typedef struct {
+    int32_t rays_per_probe;    /* R: multiple of 16, 16..SDFDDGI_MAX_RAYS          */
+    int32_t max_steps;         /* sphere-trace samples per ray, 1..4096            */
+    int32_t irr_res;           /* irradiance map side (interior), 2..32; 8 typical */
+    int32_t depth_res;         /* depth map side (interior), 2..32; 16 typical     */
+    float hit_eps;             /* hit when the distance falls below this, > 0      */
+    float t_max;               /* longest ray, > 0                                 */
+    float hysteresis;          /* weight of the old value, [0, 1)                  */
+    float bounce_gain;         /* multi-bounce coefficient, [0, 1]                 */
+    float depth_sharpness;     /* cosine power of the depth weights, >= 0          */
+    float shadow_bias;         /* shadow-ray origin offset along the normal, >= 0  */
+    float relax;               /* step = relax * distance, (0, 2]                  */
+    float sky_rgb[3];          /* radiance of escaping rays, finite, >= 0          */
+    float albedo[3];           /* albedo where a level has no albedo grid          */
+    uint32_t flags;            /* SDFDDGI_FLAG_*                                   */
+} sdfddgi_params;
+
+/* Directional light: direction toward the light (any non-zero length; it is
+ * normalised in binary64) and its radiance. */
+typedef struct {
+    float dir_to_light[3];
+    float radiance_rgb[3];
+} sdfddgi_light;
+
+/* Fill *p with the defaults used for the 8x8 / 16x16 maps: 144 rays, 64 steps,
+ * eps 1e-3, t_max 2*sqrt(3), h 0.97, gain 1, s 50, bias 4e-3, relax 1, black
+ * sky, albedo 0.5, no flags. Host only. */
+void sdfddgi_default_params(sdfddgi_params *p);
+
+/* Create a context on the current HIP device: validates the arguments, copies
+ * the grids (device to device) into context-owned memory, allocates both
+ * atlas pairs (zeroed; every probe's history starts rejected), and waits for
+ * the copies. hip_stream: the hipStream_t all later work runs on (NULL: the
+ * null stream). On failure *out is set to NULL. */
+sdfddgi_status sdfddgi_create(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_grid *probes,
+                              const sdfddgi_params *params, void *hip_stream,
+                              sdfddgi_ctx **out);
+
+/* One frame of the probe update of Sec. 3.3 for every probe (steps 1-5
+ * above). Reads the current maps as the previous frame, writes the other
+ * buffer pair, then makes it current. Clears every probe's reject flag. */
+sdfddgi_status sdfddgi_update_frame(sdfddgi_ctx *ctx, const sdfddgi_light *light,
+                                    uint64_t rotation_seed);
+
+/* Irradiance at points for normals from the current irradiance atlas: trilinear
+ * over the 8 probes of the cell holding each point (cell clamped to the grid),
+ * each probe read bilinearly from its padded octahedral tile at the normal's
+ * direction (the probe interpolation of Sec. 3.4, without visibility
+ * weighting). points, normals: device [n][3]; normals need not be unit length
+ * but must be non-zero; out_rgb: device [n][3]. n = 0 is a no-op. */
+sdfddgi_status sdfddgi_sample_irradiance(sdfddgi_ctx *ctx, const float *points,
+                                         const float *normals, int64_t n, float *out_rgb);
+
+/* Steps 4-5 alone on a caller-provided payload (device [P][R][4]: R, G, B, t),
+ * with the ray directions of rotation_seed; like update_frame it reads the
+ * current maps, writes the other pair, makes it current and clears the reject
+ * flags. Lets a caller with its own tracer use the blend. */
+sdfddgi_status sdfddgi_blend(sdfddgi_ctx *ctx, const float *payload, uint64_t rotation_seed);
+
+/* Copy the current maps out to device buffers (layouts above); either may be NULL. */
+sdfddgi_status sdfddgi_get_maps(sdfddgi_ctx *ctx, float *irr, float *depth);
+
+/* Install maps (e.g. a checkpoint) as the current ones and mark every probe's
+ * history valid. Both pointers are required. */
+sdfddgi_status sdfddgi_set_maps(sdfddgi_ctx *ctx, const float *irr, const float *depth);
+
+/* Reject every probe's history: the next frame writes its new estimate
+ * without mixing in the old maps (Alg. 1, markRejectHistory). */
+sdfddgi_status sdfddgi_reset_history(sdfddgi_ctx *ctx);
+
+/* Copy the last frame's per-ray payload (device [P][R][4]). ESTATE before the
+ * first frame. */
+sdfddgi_status sdfddgi_get_payload(sdfddgi_ctx *ctx, float *out);
+
+/* Copy the last frame's per-ray records (device int32 [P][R][8]). ESTATE if
+ * the context was created without SDFDDGI_FLAG_RECORD_RAYS or before the
+ * first frame. */
+sdfddgi_status sdfddgi_get_ray_records(sdfddgi_ctx *ctx, int32_t *out);
+
+/* Copy the last frame's binary32 ray directions (device [R][3]). */
+sdfddgi_status sdfddgi_get_ray_directions(sdfddgi_ctx *ctx, float *out);
+
+/* The binary32 ray directions of a frame seed, computed on the host (host
+ * pointer out [rays][3]); identical to what the GPU uses for that seed. */
+sdfddgi_status sdfddgi_ray_directions(uint64_t rotation_seed, int32_t rays, float *out);
+
+/* Mean per-kernel GPU times in milliseconds over the update_frame calls made
+ * since the previous call of this function (at most the last 256), measured
+ * with events recorded on the context's stream around each kernel:
+ * [0] ray-direction/weight tables, [1] trace and shade, [2] blend, [3] whole
+ * frame. Host pointer ms[count], count <= 4. Waits for the last timed frame.
+ * ESTATE without SDFDDGI_FLAG_TIMING or when no frame ran since the last call. */
+sdfddgi_status sdfddgi_get_kernel_times(sdfddgi_ctx *ctx, float *ms, int32_t count);
+
+/* Sizes of the context's problem: probes P, rays R, and the float counts of
+ * one irradiance and one depth atlas. Host pointers; any may be NULL. */
+sdfddgi_status sdfddgi_get_sizes(const sdfddgi_ctx *ctx, int64_t *probes, int32_t *rays,
+                                 int64_t *irr_floats, int64_t *depth_floats);
+
+/* Message of the context's last failure ("" if none). With ctx == NULL: the
+ * message of the last failed sdfddgi_create on this thread. */
+const char *sdfddgi_last_error(const sdfddgi_ctx *ctx);
+
+/* Wait for the context's stream, then free everything the context owns.
+ * NULL is a no-op. */
+sdfddgi_status sdfddgi_destroy(sdfddgi_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SDFDDGI_H */

@@ -1,0 +1,90 @@
+// Internal interface between the host runtime (runtime.hip) and the gfx950
+// kernels (kernels.hip). Plain structs passed by value as kernel arguments.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sdfddgi {
+
+constexpr int kMaxLevels = 4;
+constexpr int kMaxRays = 1024;
+constexpr int kMaxRes = 32;
+
+// One cascade level as the kernels see it. org/inv/half are the binary32
+// roundings of origin, 1/spacing and spacing/2 (computed once in binary64).
+struct DevLevel {
+    const float *sdf;   // [n2][n1][n0]
+    const float *alb;   // [n2][n1][n0][3] or nullptr
+    int n0, n1, n2;
+    float org0, org1, org2;
+    float inv;
+    float half;
+};
+
+struct ProbeGridDev {
+    int n0, n1, n2;
+    float org0, org1, org2;     // (float)origin
+    float inv0, inv1, inv2;     // (float)(1/spacing)
+};
+
+struct TraceArgs {
+    DevLevel lv[kMaxLevels];
+    int nl;
+    int P, R;
+    int max_steps;
+    int irr_res;
+    ProbeGridDev pg;
+    float eps, t_max, relax, bias, gain;
+    float l0, l1, l2;           // unit direction toward the light (binary32)
+    float rad0, rad1, rad2;
+    float sky0, sky1, sky2;
+    float alb0, alb1, alb2;
+    const float *probe_pos;     // [P][3]
+    const float *dirs;          // [R][3]
+    const float *prev_irr;      // previous irradiance atlas
+    float4 *payload;            // [P*R]
+    int *records;               // [P*R*8] or nullptr
+};
+
+struct TableArgs {
+    int R, Ti, Td;
+    double q[9];                // frame rotation, row-major
+    double sharp;               // depth cosine power
+    const double *base;         // [R][3] unrotated spherical-Fibonacci set
+    const double *texel_i;      // [Ti][3] irradiance texel directions
+    const double *texel_d;      // [Td][3] depth texel directions
+    float *dirs;                // [R][3]
+    float *wt_i;                // [R][Ti]  w_ti, transposed
+    float *wt_d;                // [R][Td]  w_ti^s, transposed
+    float *norm_i;              // [Ti]  pi / sum_i w_ti   (-1: all weights vanish)
+    float *norm_d;              // [Td]  1 / sum_i w_ti^s  (-1: all weights vanish)
+};
+
+struct BlendArgs {
+    int P, R, irr_res, depth_res;
+    float hysteresis;
+    const float4 *payload;
+    const float *wt_i, *wt_d, *norm_i, *norm_d;
+    const float *prev_irr, *prev_depth;
+    float *new_irr, *new_depth;
+    uint8_t *reject;
+};
+
+struct SampleArgs {
+    int64_t n;
+    int irr_res;
+    ProbeGridDev pg;
+    const float *atlas;
+    const float *points, *normals;
+    float *out;
+};
+
+// Launchers (kernels.hip). Each enqueues on `stream` and returns the launch status.
+hipError_t launch_tables(const TableArgs &a, hipStream_t stream);
+hipError_t launch_trace(const TraceArgs &a, hipStream_t stream);
+hipError_t launch_blend(const BlendArgs &a, hipStream_t stream);
+hipError_t launch_sample(const SampleArgs &a, hipStream_t stream);
+hipError_t launch_fill_u8(uint8_t *dst, uint8_t value, int64_t n, hipStream_t stream);
+
+}  // namespace sdfddgi

@@ -1,0 +1,376 @@
+"""Thin ctypes binding of libsdfddgi (include/sdfddgi.h), same names as the C ABI.
+
+Argument marshalling only: every step of the probe update runs in the gfx950
+kernels of the shared library. PyTorch supplies device memory (CUDA/HIP
+tensors) and the stream (torch's current stream at create time). Importing
+this module does not need a GPU; loading the library does need it to be built
+(``python -m paper_2007_14394_amd.build`` or ``__graft_entry__.build()``), and
+there is no fallback: a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+from .build import LIB_PATH
+
+SDFDDGI_OK, SDFDDGI_EINVAL, SDFDDGI_ENOMEM, SDFDDGI_EDEVICE, SDFDDGI_ESTATE = range(5)
+SDFDDGI_MAX_LEVELS = 4
+SDFDDGI_MAX_RAYS = 1024
+SDFDDGI_FLAG_RECORD_RAYS = 1
+SDFDDGI_FLAG_TIMING = 2
+
+STATUS_NAMES = {0: "SDFDDGI_OK", 1: "SDFDDGI_EINVAL", 2: "SDFDDGI_ENOMEM",
+                3: "SDFDDGI_EDEVICE", 4: "SDFDDGI_ESTATE"}
+
+EXPORTED = [
+    "sdfddgi_default_params", "sdfddgi_create", "sdfddgi_update_frame",
+    "sdfddgi_sample_irradiance", "sdfddgi_blend", "sdfddgi_get_maps", "sdfddgi_set_maps",
+    "sdfddgi_reset_history", "sdfddgi_get_payload", "sdfddgi_get_ray_records",
+    "sdfddgi_get_ray_directions", "sdfddgi_ray_directions", "sdfddgi_get_kernel_times",
+    "sdfddgi_get_sizes", "sdfddgi_last_error", "sdfddgi_destroy",
+]
+
+
+class sdfddgi_sdf_level(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("origin", ctypes.c_double * 3),
+                ("spacing", ctypes.c_double), ("sdf", ctypes.c_void_p),
+                ("albedo_rgb", ctypes.c_void_p)]
+
+
+class sdfddgi_sdf_grid(ctypes.Structure):
+    _fields_ = [("num_levels", ctypes.c_int32),
+                ("level", sdfddgi_sdf_level * SDFDDGI_MAX_LEVELS)]
+
+
+class sdfddgi_probe_grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("origin", ctypes.c_double * 3),
+                ("spacing", ctypes.c_double * 3)]
+
+
+class sdfddgi_params(ctypes.Structure):
+    _fields_ = [("rays_per_probe", ctypes.c_int32), ("max_steps", ctypes.c_int32),
+                ("irr_res", ctypes.c_int32), ("depth_res", ctypes.c_int32),
+                ("hit_eps", ctypes.c_float), ("t_max", ctypes.c_float),
+                ("hysteresis", ctypes.c_float), ("bounce_gain", ctypes.c_float),
+                ("depth_sharpness", ctypes.c_float), ("shadow_bias", ctypes.c_float),
+                ("relax", ctypes.c_float), ("sky_rgb", ctypes.c_float * 3),
+                ("albedo", ctypes.c_float * 3), ("flags", ctypes.c_uint32)]
+
+
+class sdfddgi_light(ctypes.Structure):
+    _fields_ = [("dir_to_light", ctypes.c_float * 3), ("radiance_rgb", ctypes.c_float * 3)]
+
+
+class SdfddgiError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return LIB_PATH
+
+
+def load_library() -> ctypes.CDLL:
+    """Load the built shared library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(there is no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+    L.sdfddgi_default_params.argtypes = [ctypes.POINTER(sdfddgi_params)]
+    L.sdfddgi_default_params.restype = None
+    L.sdfddgi_create.argtypes = [ctypes.POINTER(sdfddgi_sdf_grid),
+                                 ctypes.POINTER(sdfddgi_probe_grid),
+                                 ctypes.POINTER(sdfddgi_params), vp, ctypes.POINTER(vp)]
+    L.sdfddgi_update_frame.argtypes = [vp, ctypes.POINTER(sdfddgi_light), u64]
+    L.sdfddgi_sample_irradiance.argtypes = [vp, vp, vp, i64, vp]
+    L.sdfddgi_blend.argtypes = [vp, vp, u64]
+    L.sdfddgi_get_maps.argtypes = [vp, vp, vp]
+    L.sdfddgi_set_maps.argtypes = [vp, vp, vp]
+    L.sdfddgi_reset_history.argtypes = [vp]
+    L.sdfddgi_get_payload.argtypes = [vp, vp]
+    L.sdfddgi_get_ray_records.argtypes = [vp, vp]
+    L.sdfddgi_get_ray_directions.argtypes = [vp, vp]
+    L.sdfddgi_ray_directions.argtypes = [u64, i32, vp]
+    L.sdfddgi_get_kernel_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32]
+    L.sdfddgi_get_sizes.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i32),
+                                    ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.sdfddgi_last_error.argtypes = [vp]
+    L.sdfddgi_last_error.restype = ctypes.c_char_p
+    L.sdfddgi_destroy.argtypes = [vp]
+    for name in EXPORTED:
+        if name not in ("sdfddgi_default_params", "sdfddgi_last_error"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+class Context:
+    """An sdfddgi_ctx handle plus the sizes the binding needs to shape outputs."""
+
+    def __init__(self, handle: int, device, stream, probes: int, rays: int,
+                 irr_res: int, depth_res: int, flags: int):
+        self.handle = ctypes.c_void_p(handle)
+        self.device = device
+        self.stream = stream
+        self.probes = probes
+        self.rays = rays
+        self.irr_res = irr_res
+        self.depth_res = depth_res
+        self.flags = flags
+
+    @property
+    def irr_shape(self):
+        s = self.irr_res + 2
+        return (self.probes, s, s, 3)
+
+    @property
+    def depth_shape(self):
+        s = self.depth_res + 2
+        return (self.probes, s, s, 2)
+
+    def __del__(self):
+        try:
+            if self.handle and self.handle.value:
+                load_library().sdfddgi_destroy(self.handle)
+                self.handle = ctypes.c_void_p(0)
+        except Exception:
+            pass
+
+
+def _check(ctx: Optional[Context], status: int):
+    if status != SDFDDGI_OK:
+        msg = load_library().sdfddgi_last_error(ctx.handle if ctx is not None else None)
+        raise SdfddgiError(status, (msg or b"").decode())
+
+
+def _dev_ptr(t, dtype, name: str, device=None) -> int:
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, the context on {device}")
+    return t.data_ptr()
+
+
+def _stream_handle(stream) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+# -------------------------------------------------------------- C ABI names --
+
+def sdfddgi_default_params() -> sdfddgi_params:
+    p = sdfddgi_params()
+    load_library().sdfddgi_default_params(ctypes.byref(p))
+    return p
+
+
+def sdfddgi_create(levels: Sequence[dict], probe_n, probe_origin, probe_spacing,
+                   params: sdfddgi_params, stream=None) -> Context:
+    """levels: dicts with device tensors ``sdf`` [n2,n1,n0] and optional
+    ``albedo`` [n2,n1,n0,3], plus ``origin`` (3 floats) and ``spacing``;
+    finest first."""
+    import torch
+    L = load_library()
+    grid = sdfddgi_sdf_grid()
+    grid.num_levels = len(levels)
+    if not 1 <= len(levels) <= SDFDDGI_MAX_LEVELS:
+        raise ValueError("1..4 levels")
+    device = None
+    for k, lv in enumerate(levels):
+        sdf = lv["sdf"]
+        device = sdf.device if device is None else device
+        grid.level[k].sdf = _dev_ptr(sdf, torch.float32, f"levels[{k}].sdf", device)
+        n2, n1, n0 = sdf.shape
+        grid.level[k].n[:] = [n0, n1, n2]
+        grid.level[k].origin[:] = [float(v) for v in lv["origin"]]
+        grid.level[k].spacing = float(lv["spacing"])
+        alb = lv.get("albedo")
+        if alb is not None:
+            if tuple(alb.shape) != (n2, n1, n0, 3):
+                raise ValueError(f"levels[{k}].albedo must be [n2,n1,n0,3]")
+            grid.level[k].albedo_rgb = _dev_ptr(alb, torch.float32, f"levels[{k}].albedo", device)
+        else:
+            grid.level[k].albedo_rgb = None
+    pg = sdfddgi_probe_grid()
+    pg.n[:] = [int(v) for v in probe_n]
+    pg.origin[:] = [float(v) for v in probe_origin]
+    pg.spacing[:] = [float(v) for v in probe_spacing]
+    with torch.cuda.device(device):
+        sh = _stream_handle(stream)
+        out = ctypes.c_void_p()
+        _check(None, L.sdfddgi_create(ctypes.byref(grid), ctypes.byref(pg), ctypes.byref(params),
+                                      ctypes.c_void_p(sh), ctypes.byref(out)))
+    P = int(np.prod([int(v) for v in probe_n]))
+    return Context(out.value, device, stream, P, int(params.rays_per_probe),
+                   int(params.irr_res), int(params.depth_res), int(params.flags))
+
+
+def sdfddgi_update_frame(ctx: Context, dir_to_light, radiance_rgb, rotation_seed: int) -> None:
+    li = sdfddgi_light()
+    li.dir_to_light[:] = [float(v) for v in dir_to_light]
+    li.radiance_rgb[:] = [float(v) for v in radiance_rgb]
+    _check(ctx, load_library().sdfddgi_update_frame(ctx.handle, ctypes.byref(li),
+                                                     ctypes.c_uint64(int(rotation_seed))))
+
+
+def sdfddgi_sample_irradiance(ctx: Context, points, normals, out=None):
+    import torch
+    n = int(points.shape[0])
+    if tuple(points.shape) != (n, 3) or tuple(normals.shape) != (n, 3):
+        raise ValueError("points and normals must be [n,3]")
+    if out is None:
+        out = torch.empty((n, 3), dtype=torch.float32, device=ctx.device)
+    if n == 0:
+        return out
+    _check(ctx, load_library().sdfddgi_sample_irradiance(
+        ctx.handle, _dev_ptr(points, torch.float32, "points", ctx.device),
+        _dev_ptr(normals, torch.float32, "normals", ctx.device), ctypes.c_int64(n),
+        _dev_ptr(out, torch.float32, "out", ctx.device)))
+    return out
+
+
+def sdfddgi_blend(ctx: Context, payload, rotation_seed: int) -> None:
+    import torch
+    if tuple(payload.shape) != (ctx.probes, ctx.rays, 4):
+        raise ValueError("payload must be [P,R,4]")
+    _check(ctx, load_library().sdfddgi_blend(
+        ctx.handle, _dev_ptr(payload, torch.float32, "payload", ctx.device),
+        ctypes.c_uint64(int(rotation_seed))))
+
+
+def sdfddgi_get_maps(ctx: Context, irr=None, depth=None):
+    import torch
+    if irr is None:
+        irr = torch.empty(ctx.irr_shape, dtype=torch.float32, device=ctx.device)
+    if depth is None:
+        depth = torch.empty(ctx.depth_shape, dtype=torch.float32, device=ctx.device)
+    _check(ctx, load_library().sdfddgi_get_maps(
+        ctx.handle, _dev_ptr(irr, torch.float32, "irr", ctx.device),
+        _dev_ptr(depth, torch.float32, "depth", ctx.device)))
+    return irr, depth
+
+
+def sdfddgi_set_maps(ctx: Context, irr, depth) -> None:
+    import torch
+    if tuple(irr.shape) != ctx.irr_shape or tuple(depth.shape) != ctx.depth_shape:
+        raise ValueError("map shapes do not match the context")
+    _check(ctx, load_library().sdfddgi_set_maps(
+        ctx.handle, _dev_ptr(irr, torch.float32, "irr", ctx.device),
+        _dev_ptr(depth, torch.float32, "depth", ctx.device)))
+
+
+def sdfddgi_reset_history(ctx: Context) -> None:
+    _check(ctx, load_library().sdfddgi_reset_history(ctx.handle))
+
+
+def sdfddgi_get_payload(ctx: Context):
+    import torch
+    out = torch.empty((ctx.probes, ctx.rays, 4), dtype=torch.float32, device=ctx.device)
+    _check(ctx, load_library().sdfddgi_get_payload(ctx.handle, out.data_ptr()))
+    return out
+
+
+def sdfddgi_get_ray_records(ctx: Context):
+    import torch
+    out = torch.empty((ctx.probes, ctx.rays, 8), dtype=torch.int32, device=ctx.device)
+    _check(ctx, load_library().sdfddgi_get_ray_records(ctx.handle, out.data_ptr()))
+    return out
+
+
+def sdfddgi_get_ray_directions(ctx: Context):
+    import torch
+    out = torch.empty((ctx.rays, 3), dtype=torch.float32, device=ctx.device)
+    _check(ctx, load_library().sdfddgi_get_ray_directions(ctx.handle, out.data_ptr()))
+    return out
+
+
+def sdfddgi_ray_directions(rotation_seed: int, rays: int) -> np.ndarray:
+    """Host-side binary32 directions of a frame seed (no GPU needed)."""
+    out = np.zeros((max(int(rays), 0), 3), dtype=np.float32)
+    st = load_library().sdfddgi_ray_directions(ctypes.c_uint64(int(rotation_seed)),
+                                               ctypes.c_int32(rays),
+                                               ctypes.c_void_p(out.ctypes.data))
+    if st != SDFDDGI_OK:
+        raise SdfddgiError(st, "sdfddgi_ray_directions rejected its arguments")
+    return out
+
+
+def sdfddgi_get_kernel_times(ctx: Context):
+    ms = (ctypes.c_float * 4)()
+    _check(ctx, load_library().sdfddgi_get_kernel_times(ctx.handle, ms, 4))
+    return dict(tables=ms[0], trace=ms[1], blend=ms[2], frame=ms[3])
+
+
+def sdfddgi_get_sizes(ctx: Context):
+    p, i, d = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    r = ctypes.c_int32()
+    _check(ctx, load_library().sdfddgi_get_sizes(ctx.handle, ctypes.byref(p), ctypes.byref(r),
+                                                  ctypes.byref(i), ctypes.byref(d)))
+    return dict(probes=p.value, rays=r.value, irr_floats=i.value, depth_floats=d.value)
+
+
+def sdfddgi_last_error(ctx: Optional[Context]) -> str:
+    msg = load_library().sdfddgi_last_error(ctx.handle if ctx is not None else None)
+    return (msg or b"").decode()
+
+
+def sdfddgi_destroy(ctx: Context) -> None:
+    if ctx.handle and ctx.handle.value:
+        _check(None, load_library().sdfddgi_destroy(ctx.handle))
+        ctx.handle = ctypes.c_void_p(0)
+
+
+# -------------------------------------------------------------- conveniences --
+
+def params_from(p, flags: int = 0) -> sdfddgi_params:
+    """sdfddgi_params from any object with the same field names (e.g. a dataclass)."""
+    out = sdfddgi_default_params()
+    for name in ("rays_per_probe", "max_steps", "irr_res", "depth_res", "hit_eps", "t_max",
+                 "hysteresis", "bounce_gain", "depth_sharpness", "shadow_bias", "relax"):
+        setattr(out, name, getattr(p, name))
+    out.sky_rgb[:] = [float(v) for v in p.sky_rgb]
+    out.albedo[:] = [float(v) for v in p.albedo]
+    out.flags = flags
+    return out
+
+
+def context_from_workload(w, flags: int = 0, device="cuda:0", stream=None, **param_overrides):
+    """Upload a workload's grids (numpy) and create a context on ``device``.
+
+    ``w`` needs ``levels`` (n, origin, spacing, sdf, albedo), ``probes`` (n, origin,
+    spacing) and ``params``; the uploaded copies are released once create returns.
+    """
+    import torch
+    prm = params_from(w.params, flags)
+    for k, v in param_overrides.items():
+        if k in ("sky_rgb", "albedo"):
+            getattr(prm, k)[:] = [float(x) for x in v]
+        else:
+            setattr(prm, k, v)
+    dev = torch.device(device)
+    levels = []
+    for lv in w.levels:
+        d = dict(sdf=torch.from_numpy(np.ascontiguousarray(lv.sdf)).to(dev),
+                 origin=lv.origin, spacing=lv.spacing)
+        if lv.albedo is not None:
+            d["albedo"] = torch.from_numpy(np.ascontiguousarray(lv.albedo)).to(dev)
+        levels.append(d)
+    ctx = sdfddgi_create(levels, w.probes.n, w.probes.origin, w.probes.spacing, prm, stream)
+    del levels
+    return ctx

@@ -1,0 +1,132 @@
+"""Host-side checks of the C-ABI library (no GPU needed, no kernel launched)."""
+import ctypes
+import re
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2007_14394_amd import sdfddgi as S
+from tests.conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "sdfddgi.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sdfddgi_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = S.load_library()
+    names = declared_functions()
+    assert len(names) >= 16
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing
+    out = subprocess.run(["nm", "-D", "--defined-only", S.library_path()], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (sdfddgi_[a-z_]+)", out))
+    assert set(names) <= exported
+    assert set(S.EXPORTED) == set(names)
+
+
+def test_library_holds_gfx950_code():
+    # the offload bundle of the library built here names its only GPU target
+    blob = open(S.library_path(), "rb").read()
+    assert b"amdgcn-amd-amdhsa--gfx950" in blob
+    assert b"gfx942" not in blob and b"gfx90a" not in blob
+
+
+@pytest.mark.parametrize("seed", [0, 7, 2**40 + 3, 2**64 - 1])
+@pytest.mark.parametrize("rays", [16, 64, 144, 256, 512, 1024])
+def test_host_directions_bit_exact_with_checker(seed, rays):
+    got = S.sdfddgi_ray_directions(seed, rays)
+    ref = oracle.ray_directions(seed, rays).astype(np.float32)
+    assert np.array_equal(got.view(np.int32), ref.view(np.int32))
+
+
+def test_host_directions_reject_bad_sizes():
+    for rays in (0, -1, 1025):
+        with pytest.raises(S.SdfddgiError):
+            S.sdfddgi_ray_directions(1, rays)
+
+
+def test_default_params():
+    p = S.sdfddgi_default_params()
+    assert p.rays_per_probe == 144 and p.max_steps == 64
+    assert p.irr_res == 8 and p.depth_res == 16
+    assert p.hysteresis == np.float32(0.97) and p.depth_sharpness == 50.0
+    assert p.t_max == np.float32(2 * np.sqrt(3))
+
+
+def _grid_and_probes(n=(8, 8, 8), pn=(2, 2, 2)):
+    g = S.sdfddgi_sdf_grid()
+    g.num_levels = 1
+    g.level[0].n[:] = list(n)
+    g.level[0].origin[:] = [0.0, 0.0, 0.0]
+    g.level[0].spacing = 1.0
+    g.level[0].sdf = 0x1000  # never dereferenced: validation rejects first
+    pg = S.sdfddgi_probe_grid()
+    pg.n[:] = list(pn)
+    pg.origin[:] = [0.0, 0.0, 0.0]
+    pg.spacing[:] = [1.0, 1.0, 1.0]
+    return g, pg
+
+
+def _create_status(g, pg, p):
+    out = ctypes.c_void_p()
+    st = S.load_library().sdfddgi_create(ctypes.byref(g), ctypes.byref(pg), ctypes.byref(p),
+                                         None, ctypes.byref(out))
+    return st, out.value
+
+
+@pytest.mark.parametrize("mutate", [
+    lambda g, pg, p: setattr(p, "rays_per_probe", 100),       # not a multiple of 16
+    lambda g, pg, p: setattr(p, "rays_per_probe", 2048),
+    lambda g, pg, p: setattr(p, "max_steps", 0),
+    lambda g, pg, p: setattr(p, "hit_eps", float("nan")),
+    lambda g, pg, p: setattr(p, "t_max", -1.0),
+    lambda g, pg, p: setattr(p, "hysteresis", 1.0),
+    lambda g, pg, p: setattr(p, "bounce_gain", 1.5),
+    lambda g, pg, p: setattr(p, "relax", 0.0),
+    lambda g, pg, p: setattr(p, "irr_res", 64),
+    lambda g, pg, p: p.sky_rgb.__setitem__(0, float("inf")),
+    lambda g, pg, p: setattr(g, "num_levels", 0),
+    lambda g, pg, p: setattr(g, "num_levels", 5),
+    lambda g, pg, p: g.level[0].n.__setitem__(1, 1),
+    lambda g, pg, p: setattr(g.level[0], "spacing", 0.0),
+    lambda g, pg, p: setattr(g.level[0], "sdf", None),
+    lambda g, pg, p: pg.n.__setitem__(2, 1),
+    lambda g, pg, p: pg.spacing.__setitem__(0, -2.0),
+])
+def test_create_rejects_bad_arguments_before_touching_a_device(mutate):
+    g, pg = _grid_and_probes()
+    p = S.sdfddgi_default_params()
+    mutate(g, pg, p)
+    st, handle = _create_status(g, pg, p)
+    assert st == S.SDFDDGI_EINVAL
+    assert handle is None
+    assert S.sdfddgi_last_error(None) != ""
+
+
+def test_create_null_arguments():
+    out = ctypes.c_void_p()
+    lib = S.load_library()
+    assert lib.sdfddgi_create(None, None, None, None, ctypes.byref(out)) == S.SDFDDGI_EINVAL
+    g, pg = _grid_and_probes()
+    p = S.sdfddgi_default_params()
+    assert lib.sdfddgi_create(ctypes.byref(g), ctypes.byref(pg), ctypes.byref(p), None,
+                              None) == S.SDFDDGI_EINVAL
+
+
+def test_calls_on_null_context_are_rejected():
+    lib = S.load_library()
+    li = S.sdfddgi_light()
+    assert lib.sdfddgi_update_frame(None, ctypes.byref(li), 1) == S.SDFDDGI_EINVAL
+    assert lib.sdfddgi_get_maps(None, None, None) == S.SDFDDGI_EINVAL
+    assert lib.sdfddgi_reset_history(None) == S.SDFDDGI_EINVAL
+    assert lib.sdfddgi_destroy(None) == S.SDFDDGI_OK
+    assert lib.sdfddgi_get_sizes(None, None, None, None, None) == S.SDFDDGI_EINVAL

@@ -1,0 +1,302 @@
+"""GPU parity: the gfx950 library against the reference checker, through the C ABI.
+
+Bars: ray directions, probe positions and every ray decision (outcome, step
+counts, shadow result, distance and normal bits) bit-exact; payload, maps and
+interpolation within 1e-4 relative per element with a floor of 1e-3 of the
+mean magnitude (near-black texels), the tolerance the update is specified to.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-4
+
+
+def announce(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    from paper_2007_14394_amd import sdfddgi
+    assert torch.cuda.is_available(), "GPU tests need a visible gfx950 device"
+    sdfddgi.load_library()
+    return sdfddgi
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def to_dev(a):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def to_host(t):
+    _torch().cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def gpu_frame(S, ctx, fr):
+    S.sdfddgi_update_frame(ctx, fr.dir_to_light, fr.radiance_rgb, fr.rotation_seed)
+
+
+def assert_close(name, got, ref, rel=REL):
+    ok, worst = H.rel_close(got, ref, rel=rel)
+    assert ok, f"{name}: worst relative error {worst:.3e} > {rel:.0e}"
+    return worst
+
+
+def compare_records(gpu_rec, ref_rec, where):
+    if np.array_equal(gpu_rec, ref_rec):
+        return
+    bad = np.argwhere(np.any(gpu_rec != ref_rec, axis=-1))
+    k = tuple(bad[0])
+    raise AssertionError(f"{where}: {len(bad)} rays differ; first {k}: gpu {gpu_rec[k]} "
+                         f"ref {ref_rec[k]}")
+
+
+def single_frame_check(S, w, frame, reset, seed_atlas=1, probes=None, check_all=True, **over):
+    """One frame from a seeded previous atlas; compare records, payload and maps."""
+    announce(f"{w.name} P={w.num_probes} R={w.params.rays_per_probe} reset={reset} {over}")
+    ctx = S.context_from_workload(w, flags=S.SDFDDGI_FLAG_RECORD_RAYS, **over)
+    chk = oracle.Checker(w, **{k if k != "sky_rgb" else "sky": v for k, v in over.items()})
+    irr0, dep0 = scenegen.random_atlas(w.num_probes, w.params, seed=seed_atlas)
+    S.sdfddgi_set_maps(ctx, to_dev(irr0), to_dev(dep0))
+    if reset:
+        S.sdfddgi_reset_history(ctx)
+    gpu_frame(S, ctx, frame)
+    irr, dep = S.sdfddgi_get_maps(ctx)
+    rec = to_host(S.sdfddgi_get_ray_records(ctx))
+    pl = to_host(S.sdfddgi_get_payload(ctx))
+    irr, dep = to_host(irr), to_host(dep)
+    if probes is None:
+        probes = np.arange(w.num_probes)
+    probes = np.asarray(probes)
+    ri, rd, rp, rr = chk.update_probes(frame, reset, irr0, dep0, probes=probes,
+                                       want_payload=True, want_records=True)
+    compare_records(rec[probes], rr, w.name)
+    worst = dict(payload=assert_close("payload", pl[probes], rp),
+                 irr=assert_close("irradiance", irr[probes], ri),
+                 depth=assert_close("depth", dep[probes], rd))
+    S.sdfddgi_destroy(ctx)
+    return worst, oracle.record_fields(rr)
+
+
+# ------------------------------------------------------------------ tables ---
+
+def test_device_directions_and_tables_bit_exact(S):
+    w = scenegen.config1(0, "1b", frames=3)
+    ctx = S.context_from_workload(w)
+    for fr in w.frames:
+        gpu_frame(S, ctx, fr)
+        d = to_host(S.sdfddgi_get_ray_directions(ctx))
+        ref = oracle.ray_directions(fr.rotation_seed, w.params.rays_per_probe).astype(np.float32)
+        assert np.array_equal(d.view(np.int32), ref.view(np.int32))
+        host = S.sdfddgi_ray_directions(fr.rotation_seed, w.params.rays_per_probe)
+        assert np.array_equal(d.view(np.int32), host.view(np.int32))
+    S.sdfddgi_destroy(ctx)
+
+
+# ------------------------------------------------------------ interpolation ---
+
+@pytest.mark.parametrize("make", [lambda: scenegen.config1(0, "1b", frames=1),
+                                  lambda: scenegen.small_cascade(0)])
+def test_sample_irradiance_matches_checker(S, make):
+    w = make()
+    announce(f"sample_irradiance {w.name}")
+    ctx = S.context_from_workload(w)
+    chk = oracle.Checker(w)
+    irr0, dep0 = scenegen.random_atlas(w.num_probes, w.params, seed=3)
+    S.sdfddgi_set_maps(ctx, to_dev(irr0), to_dev(dep0))
+    lo = np.array(w.probes.origin) - 0.5 * np.array(w.probes.spacing)
+    hi = (np.array(w.probes.origin) + np.array(w.probes.spacing) *
+          (np.array(w.probes.n) - 1) + 0.5 * np.array(w.probes.spacing))
+    pts, nrm = scenegen.random_queries(3001, lo, hi, seed=4)  # ragged count, some outside
+    out = to_host(S.sdfddgi_sample_irradiance(ctx, to_dev(pts), to_dev(nrm)))
+    ref = np.array([chk.interp_irradiance(irr0, pts[k], nrm[k]) for k in range(len(pts))])
+    assert_close("sample_irradiance", out, ref, rel=1e-5)
+    # zero queries is a no-op
+    empty = _torch().zeros((0, 3), device="cuda:0")
+    assert S.sdfddgi_sample_irradiance(ctx, empty, empty).shape == (0, 3)
+    S.sdfddgi_destroy(ctx)
+
+
+# -------------------------------------------------------------------- blend ---
+
+@pytest.mark.parametrize("rays,reset", [(144, False), (256, True), (64, False)])
+def test_blend_alone_matches_checker(S, rays, reset):
+    w = scenegen.config1(2, "1b", frames=1, rays=rays)
+    announce(f"blend R={rays} reset={reset}")
+    ctx = S.context_from_workload(w)
+    chk = oracle.Checker(w)
+    irr0, dep0 = scenegen.random_atlas(w.num_probes, w.params, seed=5)
+    S.sdfddgi_set_maps(ctx, to_dev(irr0), to_dev(dep0))
+    if reset:
+        S.sdfddgi_reset_history(ctx)
+    pl = scenegen.random_payload(w.num_probes, rays, seed=6, t_max=w.params.t_max)
+    seed = 424242 + rays
+    S.sdfddgi_blend(ctx, to_dev(pl), seed)
+    irr, dep = S.sdfddgi_get_maps(ctx)
+    irr, dep = to_host(irr), to_host(dep)
+    for p in range(w.num_probes):
+        ri, rd = chk.blend_probe(seed, reset, pl[p], irr0[p], dep0[p])
+        assert_close(f"irr probe {p}", irr[p], ri, rel=2e-5)
+        assert_close(f"depth probe {p}", dep[p], rd, rel=2e-5)
+    S.sdfddgi_destroy(ctx)
+
+
+# --------------------------------------------------------------- one frame ---
+
+def test_frame_config1b_bit_exact_decisions(S):
+    w = scenegen.config1(0, "1b", frames=2)
+    worst, f = single_frame_check(S, w, w.frames[1], reset=False)
+    # the scene exercises every outcome the trace can take
+    kinds = set(np.unique(f["kind"]).tolist())
+    assert {oracle.HIT, oracle.MISS_EXIT, oracle.INSIDE} <= kinds
+    assert (f["visibility"] == 0).any() and (f["visibility"] == 1).any()
+    announce(f"worst {worst}")
+
+
+def test_frame_small_cascade_ragged(S):
+    w = scenegen.small_cascade(0)
+    worst, f = single_frame_check(S, w, w.frames[0], reset=True)
+    assert set(np.unique(f["level"][f["kind"] >= oracle.HIT]).tolist()) == {0, 1}
+    announce(f"worst {worst}")
+
+
+@pytest.mark.parametrize("over", [dict(bounce_gain=0.5, relax=1.3),
+                                  dict(max_steps=12, hit_eps=5e-3),
+                                  dict(depth_sharpness=8.0, hysteresis=0.5)])
+def test_frame_parameter_variants(S, over):
+    w = scenegen.small_cascade(1, probes=(5, 2, 4), rays=144)
+    single_frame_check(S, w, w.frames[1], reset=False, **over)
+
+
+def test_frame_without_albedo_grid(S):
+    w = scenegen.config1(3, "1b", frames=1)
+    w.levels[0].albedo = None
+    single_frame_check(S, w, w.frames[0], reset=True)
+
+
+# ---------------------------------------------------------------- free run ---
+
+def test_free_run_config1b_ten_frames(S):
+    w = scenegen.config1(0, "1b", frames=10)
+    announce("free run config1b 10 frames")
+    ctx = S.context_from_workload(w)
+    chk = oracle.Checker(w)
+    states = chk.run_frames(w.frames)
+    worst = 0.0
+    for k, fr in enumerate(w.frames):
+        gpu_frame(S, ctx, fr)
+        irr, dep = S.sdfddgi_get_maps(ctx)
+        irr, dep = to_host(irr), to_host(dep)
+        worst = max(worst, assert_close(f"frame {k} irr", irr, states[k][0]))
+        assert_close(f"frame {k} depth", dep, states[k][1])
+    announce(f"worst irradiance error over 10 frames {worst:.2e}")
+    S.sdfddgi_destroy(ctx)
+
+
+# ------------------------------------------------------------ closed forms ---
+
+def test_uniform_sky_gives_pi_L_on_gpu(S):
+    w = scenegen.empty_sky(sky=0.5, probes=(3, 2, 2), rays=128)
+    ctx = S.context_from_workload(w)
+    L = float(np.float32(0.5))
+    t_max = float(np.float32(w.params.t_max))
+    for fr in w.frames:
+        gpu_frame(S, ctx, fr)
+        irr, dep = S.sdfddgi_get_maps(ctx)
+        irr, dep = to_host(irr), to_host(dep)
+        assert np.abs(irr / (math.pi * L) - 1).max() < 2e-6
+        assert np.abs(dep[..., 0] / t_max - 1).max() < 2e-6
+        assert np.abs(dep[..., 1] / t_max ** 2 - 1).max() < 4e-6
+    S.sdfddgi_destroy(ctx)
+
+
+def test_dark_room_exactly_black_on_gpu(S):
+    w = scenegen.config1(0, "1a", frames=3)
+    ctx = S.context_from_workload(w)
+    for fr in w.frames:
+        gpu_frame(S, ctx, fr)
+        irr, _ = S.sdfddgi_get_maps(ctx)
+        assert np.all(to_host(irr) == 0.0)
+    S.sdfddgi_destroy(ctx)
+
+
+# ------------------------------------------------- full size, sampled probes ---
+
+@pytest.mark.parametrize("probes", [16384, 8192])
+def test_config2_full_size_sampled_probes(S, probes):
+    w = scenegen.config2(0, probes=probes, frames=2)
+    rng = np.random.default_rng(probes)
+    sample = np.sort(rng.choice(w.num_probes, 48, replace=False))
+    sample[0], sample[-1] = 0, w.num_probes - 1
+    for reset, fr in ((True, w.frames[0]), (False, w.frames[1])):
+        worst, f = single_frame_check(S, w, fr, reset=reset, probes=sample)
+        announce(f"config2 {probes} reset={reset} worst {worst}")
+    assert set(np.unique(f["level"][f["kind"] >= oracle.HIT]).tolist()) >= {2, 3}
+
+
+# -------------------------------------------------------------- behaviour ---
+
+def test_deterministic_across_contexts(S):
+    w = scenegen.small_cascade(2)
+    outs = []
+    for _ in range(2):
+        ctx = S.context_from_workload(w)
+        for fr in w.frames:
+            gpu_frame(S, ctx, fr)
+        irr, dep = S.sdfddgi_get_maps(ctx)
+        outs.append((to_host(irr), to_host(dep)))
+        S.sdfddgi_destroy(ctx)
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_error_paths_leave_state_untouched(S):
+    w = scenegen.config1(0, "1b", frames=1)
+    ctx = S.context_from_workload(w)
+    with pytest.raises(S.SdfddgiError) as e:
+        S.sdfddgi_get_payload(ctx)
+    assert e.value.status == S.SDFDDGI_ESTATE
+    with pytest.raises(S.SdfddgiError) as e:
+        S.sdfddgi_get_ray_records(ctx)
+    assert e.value.status == S.SDFDDGI_ESTATE
+    with pytest.raises(S.SdfddgiError) as e:
+        S.sdfddgi_get_kernel_times(ctx)
+    assert e.value.status == S.SDFDDGI_ESTATE
+    fr = w.frames[0]
+    gpu_frame(S, ctx, fr)
+    before = [to_host(t) for t in S.sdfddgi_get_maps(ctx)]
+    for light, rad in (((0.0, 0.0, 0.0), (1, 1, 1)), ((0, 1, 0), (float("nan"), 1, 1)),
+                       ((0, 1, 0), (-1.0, 1, 1))):
+        with pytest.raises(S.SdfddgiError) as e:
+            S.sdfddgi_update_frame(ctx, light, rad, 1)
+        assert e.value.status == S.SDFDDGI_EINVAL
+    after = [to_host(t) for t in S.sdfddgi_get_maps(ctx)]
+    assert all(np.array_equal(a, b) for a, b in zip(before, after))
+    S.sdfddgi_destroy(ctx)
+
+
+def test_kernel_timing_reports_positive_times(S):
+    w = scenegen.config1(0, "1b", frames=2)
+    ctx = S.context_from_workload(w, flags=S.SDFDDGI_FLAG_TIMING)
+    for fr in w.frames:
+        gpu_frame(S, ctx, fr)
+    t = S.sdfddgi_get_kernel_times(ctx)
+    assert all(v > 0 for v in t.values())
+    assert t["frame"] >= t["trace"]
+    S.sdfddgi_destroy(ctx)
