@@ -14,7 +14,7 @@ constexpr int kMaxRes = 32;
 // One cascade level as the kernels see it. org/inv/half are the binary32
 // roundings of origin, 1/spacing and spacing/2 (computed once in binary64).
 struct DevLevel {
-    const float *sdf;   // [n2][n1][n0]
+    const float4 *quad; // [n2-1][n1-1][n0] corner quads (see trilinear in kernels.hip)
     const float *alb;   // [n2][n1][n0][3] or nullptr
     int n0, n1, n2;
     float org0, org1, org2;
@@ -45,20 +45,23 @@ struct TraceArgs {
     const float *prev_irr;      // previous irradiance atlas
     float4 *payload;            // [P*R]
     int *records;               // [P*R*8] or nullptr
+    int *counter;               // next unclaimed ray (zeroed by tables_kernel)
 };
 
 struct TableArgs {
     int R, Ti, Td;
+    int Tpi, Tpd;               // row strides of the weight tables: T rounded up to 16
     double q[9];                // frame rotation, row-major
     double sharp;               // depth cosine power
     const double *base;         // [R][3] unrotated spherical-Fibonacci set
     const double *texel_i;      // [Ti][3] irradiance texel directions
     const double *texel_d;      // [Td][3] depth texel directions
     float *dirs;                // [R][3]
-    float *wt_i;                // [R][Ti]  w_ti, transposed
-    float *wt_d;                // [R][Td]  w_ti^s, transposed
+    float *wt_i;                // [R][Tpi] w_ti, transposed; rows t >= Ti stay zero
+    float *wt_d;                // [R][Tpd] w_ti^s, transposed; rows t >= Td stay zero
     float *norm_i;              // [Ti]  pi / sum_i w_ti   (-1: all weights vanish)
     float *norm_d;              // [Td]  1 / sum_i w_ti^s  (-1: all weights vanish)
+    int *counter;               // trace_kernel's ray counter, reset here (may be null)
 };
 
 struct BlendArgs {
@@ -82,9 +85,12 @@ struct SampleArgs {
 
 // Launchers (kernels.hip). Each enqueues on `stream` and returns the launch status.
 hipError_t launch_tables(const TableArgs &a, hipStream_t stream);
-hipError_t launch_trace(const TraceArgs &a, hipStream_t stream);
+int trace_grid_blocks(int device, int64_t rays);
+hipError_t launch_trace(const TraceArgs &a, int blocks, hipStream_t stream);
 hipError_t launch_blend(const BlendArgs &a, hipStream_t stream);
 hipError_t launch_sample(const SampleArgs &a, hipStream_t stream);
+hipError_t launch_pack_quads(const float *grid, int n0, int n1, int n2, float4 *quad,
+                             hipStream_t stream);
 hipError_t launch_fill_u8(uint8_t *dst, uint8_t value, int64_t n, hipStream_t stream);
 
 }  // namespace sdfddgi

@@ -26,14 +26,14 @@ __device__ __forceinline__ float clampf(float v, float lo, float hi) { return fm
 // ------------------------------------------------------------- geometry -----
 
 struct LevelView {
-    const float *sdf;
+    const float4 *quad;
     const float *alb;
     int n0, n1, n2;
     float org0, org1, org2, inv, half;
 };
 
 __device__ __forceinline__ void level_view(const DevLevel &d, LevelView &v) {
-    v.sdf = d.sdf; v.alb = d.alb; v.n0 = d.n0; v.n1 = d.n1; v.n2 = d.n2;
+    v.quad = d.quad; v.alb = d.alb; v.n0 = d.n0; v.n1 = d.n1; v.n2 = d.n2;
     v.org0 = d.org0; v.org1 = d.org1; v.org2 = d.org2; v.inv = d.inv; v.half = d.half;
 }
 
@@ -45,17 +45,21 @@ __device__ __forceinline__ void cell_of(float u, int n, int &i, float &f) {
 }
 
 // Trilinear sample at grid coordinates (u0,u1,u2): lerps along x, then y, then z.
-__device__ __forceinline__ float trilinear(const float *__restrict__ g, int n0, int n1, int n2,
+// The grid is stored as corner quads: quad (i,j,k) = the values at (i,j,k),
+// (i,j+1,k), (i,j,k+1), (i,j+1,k+1), so a cell's eight corners are the two
+// adjacent quads (i,j,k) and (i+1,j,k) -- usually one cache line.
+__device__ __forceinline__ float trilinear(const float4 *__restrict__ quad, int n0, int n1, int n2,
                                            float u0, float u1, float u2) {
     int i0, i1, i2;
     float f0, f1, f2;
     cell_of(u0, n0, i0, f0);
     cell_of(u1, n1, i1, f1);
     cell_of(u2, n2, i2, f2);
-    const uint32_t sy = (uint32_t)n0, sz = (uint32_t)n0 * (uint32_t)n1;
-    const float *p = g + ((uint32_t)i2 * sz + (uint32_t)i1 * sy + (uint32_t)i0);
-    float v000 = p[0], v100 = p[1], v010 = p[sy], v110 = p[sy + 1];
-    float v001 = p[sz], v101 = p[sz + 1], v011 = p[sz + sy], v111 = p[sz + sy + 1];
+    const uint32_t row = (uint32_t)n0, slice = (uint32_t)n0 * (uint32_t)(n1 - 1);
+    const float4 *q = quad + ((uint32_t)i2 * slice + (uint32_t)i1 * row + (uint32_t)i0);
+    const float4 a = q[0], b = q[1];
+    const float v000 = a.x, v010 = a.y, v001 = a.z, v011 = a.w;
+    const float v100 = b.x, v110 = b.y, v101 = b.z, v111 = b.w;
     float c00 = fmaf(f0, v100 - v000, v000);
     float c10 = fmaf(f0, v110 - v010, v010);
     float c01 = fmaf(f0, v101 - v001, v001);
@@ -92,38 +96,8 @@ __device__ __forceinline__ int select_level(const TraceArgs &a, float x0, float 
     return -1;
 }
 
-struct TraceHit {
-    int kind, steps, level;
-    float t, x0, x1, x2;
-};
-
-// Sphere tracing along o + t w (Hart 1996; paper Sec. 3.3).
-template <bool kPrimary>
-__device__ __forceinline__ TraceHit trace_ray(const TraceArgs &a, float o0, float o1, float o2,
-                                              float w0, float w1, float w2, LevelView &hit_lv) {
-    TraceHit r;
-    r.kind = kHitExhausted; r.steps = a.max_steps; r.level = -1;
-    r.t = 0.0f; r.x0 = r.x1 = r.x2 = 0.0f;
-    float t = 0.0f;
-    for (int k = 0; k < a.max_steps; ++k) {
-        if (t > a.t_max) { r.kind = kMissTmax; r.steps = k; return r; }
-        float x0 = fmaf(t, w0, o0), x1 = fmaf(t, w1, o1), x2 = fmaf(t, w2, o2);
-        LevelView lv;
-        float u0, u1, u2;
-        int L = select_level(a, x0, x1, x2, lv, u0, u1, u2);
-        if (L < 0) { r.kind = kMissExit; r.steps = k; return r; }
-        float d = trilinear(lv.sdf, lv.n0, lv.n1, lv.n2, u0, u1, u2);
-        r.t = t; r.level = L; r.x0 = x0; r.x1 = x1; r.x2 = x2;
-        if (kPrimary) hit_lv = lv;
-        if (kPrimary && k == 0 && d < 0.0f) { r.kind = kInside; r.steps = 1; return r; }
-        if (d < a.eps) { r.kind = kHit; r.steps = k + 1; return r; }
-        t = fmaf(a.relax, d, t);
-    }
-    return r;
-}
-
 __device__ __forceinline__ float sample_at(const LevelView &lv, float p0, float p1, float p2) {
-    return trilinear(lv.sdf, lv.n0, lv.n1, lv.n2, (p0 - lv.org0) * lv.inv,
+    return trilinear(lv.quad, lv.n0, lv.n1, lv.n2, (p0 - lv.org0) * lv.inv,
                      (p1 - lv.org1) * lv.inv, (p2 - lv.org2) * lv.inv);
 }
 
@@ -132,9 +106,15 @@ __device__ __forceinline__ void hit_normal(const LevelView &lv, float x0, float 
                                            float w0, float w1, float w2,
                                            float &n0, float &n1, float &n2) {
     const float h = lv.half;
-    float g0 = sample_at(lv, x0 + h, x1, x2) - sample_at(lv, x0 - h, x1, x2);
-    float g1 = sample_at(lv, x0, x1 + h, x2) - sample_at(lv, x0, x1 - h, x2);
-    float g2 = sample_at(lv, x0, x1, x2 + h) - sample_at(lv, x0, x1, x2 - h);
+    float g[3];
+#pragma unroll 1
+    for (int ax = 0; ax < 3; ++ax) {
+        const float p0 = x0 + (ax == 0 ? h : 0.0f), m0 = x0 - (ax == 0 ? h : 0.0f);
+        const float p1 = x1 + (ax == 1 ? h : 0.0f), m1 = x1 - (ax == 1 ? h : 0.0f);
+        const float p2 = x2 + (ax == 2 ? h : 0.0f), m2 = x2 - (ax == 2 ? h : 0.0f);
+        g[ax] = sample_at(lv, p0, p1, p2) - sample_at(lv, m0, m1, m2);
+    }
+    const float g0 = g[0], g1 = g[1], g2 = g[2];
     float len2 = fmaf(g2, g2, fmaf(g1, g1, g0 * g0));
     if (!(len2 >= 1e-24f)) { n0 = -w0; n1 = -w1; n2 = -w2; return; }
     float inv = 1.0f / sqrtf(len2);
@@ -170,27 +150,21 @@ __device__ __forceinline__ float3 interp_irradiance(const float *__restrict__ at
     const int side = res + 2;
     const int t00 = ((int)av * side + (int)au) * 3;
     const int tile = side * side * 3;
-    float w00 = (1.0f - fu) * (1.0f - fv), w10 = fu * (1.0f - fv);
-    float w01 = (1.0f - fu) * fv, w11 = fu * fv;
+    const float w00 = (1.0f - fu) * (1.0f - fv), w10 = fu * (1.0f - fv);
+    const float w01 = (1.0f - fu) * fv, w11 = fu * fv;
     float3 acc = make_float3(0.0f, 0.0f, 0.0f);
-#pragma unroll
-    for (int dz = 0; dz < 2; ++dz)
-#pragma unroll
-        for (int dy = 0; dy < 2; ++dy)
-#pragma unroll
-            for (int dx = 0; dx < 2; ++dx) {
-                float wp = (dx ? f0 : 1.0f - f0) * (dy ? f1 : 1.0f - f1) * (dz ? f2 : 1.0f - f2);
-                int p = (b0 + dx) + pg.n0 * ((b1 + dy) + pg.n1 * (b2 + dz));
-                const float *tx = atlas + (size_t)p * tile + t00;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    float s = w00 * tx[c] + w10 * tx[3 + c] + w01 * tx[side * 3 + c] +
-                              w11 * tx[side * 3 + 3 + c];
-                    if (c == 0) acc.x += wp * s;
-                    if (c == 1) acc.y += wp * s;
-                    if (c == 2) acc.z += wp * s;
-                }
-            }
+    // one probe per iteration keeps 12 loads in flight rather than 96
+#pragma unroll 1
+    for (int c8 = 0; c8 < 8; ++c8) {
+        const int dx = c8 & 1, dy = (c8 >> 1) & 1, dz = c8 >> 2;
+        const float wp = (dx ? f0 : 1.0f - f0) * (dy ? f1 : 1.0f - f1) * (dz ? f2 : 1.0f - f2);
+        const int p = (b0 + dx) + pg.n0 * ((b1 + dy) + pg.n1 * (b2 + dz));
+        const float *tx = atlas + (size_t)p * tile + t00;
+        const float *ty = tx + side * 3;
+        acc.x += wp * (w00 * tx[0] + w10 * tx[3] + w01 * ty[0] + w11 * ty[3]);
+        acc.y += wp * (w00 * tx[1] + w10 * tx[4] + w01 * ty[1] + w11 * ty[4]);
+        acc.z += wp * (w00 * tx[2] + w10 * tx[5] + w01 * ty[2] + w11 * ty[5]);
+    }
     return acc;
 }
 
@@ -220,54 +194,177 @@ __device__ __forceinline__ float3 albedo_at(const TraceArgs &a, const LevelView 
 
 // ------------------------------------------------------------- kernels ------
 
-__global__ __launch_bounds__(256) void trace_kernel(TraceArgs a) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t total = (int64_t)a.P * a.R;
-    if (gid >= total) return;
-    const int p = (int)(gid / a.R);
-    const int i = (int)(gid - (int64_t)p * a.R);
-    const float o0 = a.probe_pos[3 * p], o1 = a.probe_pos[3 * p + 1], o2 = a.probe_pos[3 * p + 2];
-    const float w0 = a.dirs[3 * i], w1 = a.dirs[3 * i + 1], w2 = a.dirs[3 * i + 2];
+// Level view of the hit point's level: select_level(x) again (the same x gives the
+// same level), which keeps the per-level kernel arguments in registers.
+__device__ __forceinline__ LevelView hit_level_view(const TraceArgs &a, float x0, float x1,
+                                                    float x2) {
+    LevelView v;
+    float u0, u1, u2;
+    (void)select_level(a, x0, x1, x2, v, u0, u1, u2);
+    return v;
+}
 
-    LevelView lv;
-    TraceHit h = trace_ray<true>(a, o0, o1, o2, w0, w1, w2, lv);
-    float n0 = 0.0f, n1 = 0.0f, n2 = 0.0f;
-    int vis = -1, shadow_steps = 0;
-    float4 out;
-    const bool hit = h.kind == kHit || h.kind == kHitExhausted;
-    if (hit) {
-        hit_normal(lv, h.x0, h.x1, h.x2, w0, w1, w2, n0, n1, n2);
-        float ndl = fmaf(n2, a.l2, fmaf(n1, a.l1, n0 * a.l0));
-        if (ndl > 0.0f) {
-            LevelView unused;
-            TraceHit s = trace_ray<false>(a, fmaf(n0, a.bias, h.x0), fmaf(n1, a.bias, h.x1),
-                                          fmaf(n2, a.bias, h.x2), a.l0, a.l1, a.l2, unused);
-            vis = (s.kind == kHit || s.kind == kHitExhausted) ? 0 : 1;
-            shadow_steps = s.steps;
-        }
-        float lit = vis == 1 ? ndl : 0.0f;
-        float3 alb = albedo_at(a, lv, h.x0, h.x1, h.x2);
-        float3 ind = make_float3(0.0f, 0.0f, 0.0f);
-        if (a.gain != 0.0f)
-            ind = interp_irradiance(a.prev_irr, a.irr_res, a.pg, h.x0, h.x1, h.x2, n0, n1, n2);
-        const float inv_pi = 0.318309886183790671538f;
-        out.x = alb.x * inv_pi * (a.rad0 * lit + a.gain * ind.x);
-        out.y = alb.y * inv_pi * (a.rad1 * lit + a.gain * ind.y);
-        out.z = alb.z * inv_pi * (a.rad2 * lit + a.gain * ind.z);
-        out.w = h.t;
-    } else if (h.kind == kInside) {
-        out = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    } else {
-        out = make_float4(a.sky0, a.sky1, a.sky2, a.t_max);
-    }
-    a.payload[gid] = out;
+__device__ __forceinline__ void write_ray(const TraceArgs &a, int ray, float4 out, int kind,
+                                          int level, int steps, int vis, int shadow_steps,
+                                          float n0, float n1, float n2) {
+    a.payload[ray] = out;
     if (a.records) {
-        int4 r0 = make_int4(h.kind | ((hit ? h.level : 0) << 8), h.steps, vis, shadow_steps);
-        int4 r1 = make_int4(__float_as_int(out.w), __float_as_int(n0), __float_as_int(n1),
-                            __float_as_int(n2));
-        int4 *rec = reinterpret_cast<int4 *>(a.records) + 2 * gid;
-        rec[0] = r0;
-        rec[1] = r1;
+        int4 *rec = reinterpret_cast<int4 *>(a.records) + 2 * (int64_t)ray;
+        rec[0] = make_int4(kind | (level << 8), steps, vis, shadow_steps);
+        rec[1] = make_int4(__float_as_int(out.w), __float_as_int(n0), __float_as_int(n1),
+                           __float_as_int(n2));
+    }
+}
+
+enum : int { kIdle = 0, kPrimary = 1, kShadow = 2, kPendNormal = 3, kPendShade = 4 };
+constexpr int kChunk = 64;        // rays taken from the global counter at a time
+constexpr int kRefillBelow = 48;  // run the batched phases when fewer lanes are stepping
+
+// Persistent, wave-compacted trace: every lane of a wave owns one ray at a time and
+// advances it one sphere-trace sample per iteration. When fewer than kRefillBelow
+// lanes are still stepping, the wave runs the divergent per-ray work in batches
+// (hit normal + shadow-ray set-up, then shading and payload write) and refills idle
+// lanes with new rays from a global counter (kChunk rays per atomic). Each ray's
+// arithmetic is the fixed sequence of trace_ray/hit_normal, so results do not depend
+// on which lane or wave processed it. Every wave exits once the counter has passed
+// the last ray and its lanes are idle; each ray takes at most 2*max_steps samples.
+__global__ __launch_bounds__(256) void trace_kernel(TraceArgs a) {
+    const int lane = (int)__lane_id();
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const int total = a.P * a.R;
+    int chunk_next = 0, chunk_end = 0;
+    bool exhausted = false;
+
+    int mode = kIdle, ray = 0;
+    float o0 = 0, o1 = 0, o2 = 0, w0 = 0, w1 = 0, w2 = 0, t = 0;
+    int k = 0;
+    // primary hit kept for shading
+    float hx0 = 0, hx1 = 0, hx2 = 0, ht = 0;
+    int hkind = 0, hsteps = 0, hlevel = 0;
+    float n0 = 0, n1 = 0, n2 = 0;
+    int vis = -1;
+
+    while (true) {
+        uint64_t stepping = __ballot(mode == kPrimary || mode == kShadow);
+        if (__popcll(stepping) < kRefillBelow) {
+            if (__ballot(mode == kPendNormal)) {
+                if (mode == kPendNormal) {
+                    const LevelView lv = hit_level_view(a, hx0, hx1, hx2);
+                    hit_normal(lv, hx0, hx1, hx2, w0, w1, w2, n0, n1, n2);
+                    const float ndl = fmaf(n2, a.l2, fmaf(n1, a.l1, n0 * a.l0));
+                    if (ndl > 0.0f) {
+                        o0 = fmaf(n0, a.bias, hx0);
+                        o1 = fmaf(n1, a.bias, hx1);
+                        o2 = fmaf(n2, a.bias, hx2);
+                        w0 = a.l0; w1 = a.l1; w2 = a.l2;
+                        t = 0.0f;
+                        k = 0;
+                        mode = kShadow;
+                    } else {
+                        vis = -1;
+                        k = 0;
+                        mode = kPendShade;
+                    }
+                }
+            }
+            if (__ballot(mode == kPendShade)) {
+                if (mode == kPendShade) {
+                    // k holds the shadow ray's step count here
+                    const LevelView lv = hit_level_view(a, hx0, hx1, hx2);
+                    const float ndl = fmaf(n2, a.l2, fmaf(n1, a.l1, n0 * a.l0));
+                    const float lit = vis == 1 ? ndl : 0.0f;
+                    const float3 alb = albedo_at(a, lv, hx0, hx1, hx2);
+                    float3 ind = make_float3(0.0f, 0.0f, 0.0f);
+                    if (a.gain != 0.0f)
+                        ind = interp_irradiance(a.prev_irr, a.irr_res, a.pg, hx0, hx1, hx2, n0,
+                                                n1, n2);
+                    const float inv_pi = 0.318309886183790671538f;
+                    float4 out;
+                    out.x = alb.x * inv_pi * (a.rad0 * lit + a.gain * ind.x);
+                    out.y = alb.y * inv_pi * (a.rad1 * lit + a.gain * ind.y);
+                    out.z = alb.z * inv_pi * (a.rad2 * lit + a.gain * ind.z);
+                    out.w = ht;
+                    write_ray(a, ray, out, hkind, hlevel, hsteps, vis, k, n0, n1, n2);
+                    mode = kIdle;
+                }
+            }
+            uint64_t idle = __ballot(mode == kIdle);
+            while (idle != 0 && !exhausted) {
+                if (chunk_next >= chunk_end) {
+                    int base = 0;
+                    if (lane == 0) base = atomicAdd(a.counter, kChunk);
+                    base = __builtin_amdgcn_readfirstlane(base);
+                    if (base >= total) {
+                        exhausted = true;
+                        break;
+                    }
+                    chunk_next = base;
+                    chunk_end = min(base + kChunk, total);
+                }
+                const int avail = chunk_end - chunk_next;
+                const int rank = __popcll(idle & below);
+                if (mode == kIdle && rank < avail) {
+                    ray = chunk_next + rank;
+                    const int p = ray / a.R;
+                    const int i = ray - p * a.R;
+                    o0 = a.probe_pos[3 * p]; o1 = a.probe_pos[3 * p + 1]; o2 = a.probe_pos[3 * p + 2];
+                    w0 = a.dirs[3 * i]; w1 = a.dirs[3 * i + 1]; w2 = a.dirs[3 * i + 2];
+                    t = 0.0f;
+                    k = 0;
+                    mode = kPrimary;
+                }
+                chunk_next += min(avail, (int)__popcll(idle));
+                idle = __ballot(mode == kIdle);
+            }
+            stepping = __ballot(mode == kPrimary || mode == kShadow);
+            if (stepping == 0) break;  // counter exhausted and every lane idle
+        }
+
+        if (mode == kPrimary || mode == kShadow) {
+            // one sample of the fixed sphere-trace sequence
+            int kind = -1, steps = 0, level = 0;
+            float tt = t, x0 = 0, x1 = 0, x2 = 0;
+            if (t > a.t_max) {
+                kind = kMissTmax; steps = k;
+            } else {
+                x0 = fmaf(t, w0, o0); x1 = fmaf(t, w1, o1); x2 = fmaf(t, w2, o2);
+                LevelView lv;
+                float u0, u1, u2;
+                level = select_level(a, x0, x1, x2, lv, u0, u1, u2);
+                if (level < 0) {
+                    kind = kMissExit; steps = k;
+                } else {
+                    const float d = trilinear(lv.quad, lv.n0, lv.n1, lv.n2, u0, u1, u2);
+                    if (mode == kPrimary && k == 0 && d < 0.0f) {
+                        kind = kInside; steps = 1;
+                    } else if (d < a.eps) {
+                        kind = kHit; steps = k + 1;
+                    } else {
+                        t = fmaf(a.relax, d, t);
+                        ++k;
+                        if (k == a.max_steps) { kind = kHitExhausted; steps = k; }
+                    }
+                }
+            }
+            if (kind >= 0) {
+                const bool is_hit = kind == kHit || kind == kHitExhausted;
+                if (mode == kShadow) {
+                    vis = is_hit ? 0 : 1;
+                    k = steps;
+                    mode = kPendShade;
+                } else if (is_hit) {
+                    hx0 = x0; hx1 = x1; hx2 = x2; ht = tt;
+                    hkind = kind; hsteps = steps; hlevel = level;
+                    mode = kPendNormal;
+                } else {
+                    const float4 out = kind == kInside
+                                           ? make_float4(0.0f, 0.0f, 0.0f, 0.0f)
+                                           : make_float4(a.sky0, a.sky1, a.sky2, a.t_max);
+                    write_ray(a, ray, out, kind, 0, steps, -1, 0, 0.0f, 0.0f, 0.0f);
+                    mode = kIdle;
+                }
+            }
+        }
     }
 }
 
@@ -301,13 +398,16 @@ __global__ __launch_bounds__(256) void tables_kernel(TableArgs a) {
         double w = c > 0.0 ? c : 0.0;
         if (is_depth) {
             w = pow(w, a.sharp);
-            a.wt_d[(size_t)i * a.Td + t] = (float)w;
+            a.wt_d[(size_t)i * a.Tpd + t] = (float)w;
         } else {
-            a.wt_i[(size_t)i * a.Ti + t] = (float)w;
+            a.wt_i[(size_t)i * a.Tpi + t] = (float)w;
         }
         part += w;
     }
-    if (is_dirs) return;
+    if (is_dirs) {
+        if (tid == 0 && a.counter) *a.counter = 0;  // trace_kernel's ray counter
+        return;
+    }
     red[tid] = part;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
@@ -322,85 +422,176 @@ __global__ __launch_bounds__(256) void tables_kernel(TableArgs a) {
     }
 }
 
-// Source interior texel of padded texel (col a, row b) of an n x n map.
-__device__ __forceinline__ void border_source(int n, int a, int b, int &i, int &j) {
-    const bool left = a == 0, right = a == n + 1, top = b == 0, bottom = b == n + 1;
-    if ((left || right) && (top || bottom)) { i = left ? n - 1 : 0; j = top ? n - 1 : 0; }
-    else if (top || bottom) { i = n - a; j = top ? 0 : n - 1; }
-    else if (left || right) { i = left ? 0 : n - 1; j = n - b; }
-    else { i = a - 1; j = b - 1; }
+// Write interior texel (i, j) of an n x n map with `comps` channels into its padded
+// tile, together with every border texel that copies it: crossing an edge of the
+// octahedral square lands on the same edge reflected about its midpoint, and the
+// four corners take the diagonally opposite interior corner.
+__device__ __forceinline__ void store_with_border(float *__restrict__ tile, int n, int comps,
+                                                  int i, int j, int c, float v) {
+    const int side = n + 2;
+    tile[((j + 1) * side + (i + 1)) * comps + c] = v;
+    if (j == 0) tile[(0 * side + (n - i)) * comps + c] = v;
+    if (j == n - 1) tile[((n + 1) * side + (n - i)) * comps + c] = v;
+    if (i == 0) tile[((n - j) * side + 0) * comps + c] = v;
+    if (i == n - 1) tile[((n - j) * side + (n + 1)) * comps + c] = v;
+    if (i == n - 1 && j == n - 1) tile[0 * comps + c] = v;
+    if (i == 0 && j == n - 1) tile[(n + 1) * comps + c] = v;
+    if (i == n - 1 && j == 0) tile[((n + 1) * side) * comps + c] = v;
+    if (i == 0 && j == 0) tile[((n + 1) * side + (n + 1)) * comps + c] = v;
 }
 
-// One block per probe: Eq. 3 for every texel from the probe's ray payload staged in
-// LDS, temporal mix with the previous interior, border fill from LDS.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kBlendProbes = 16;  // probes per workgroup: the N extent of a tile row
+constexpr int kBlendChunk = 64;   // rays staged in LDS at a time
+constexpr int kBlendPitch = kBlendChunk + 1;
+constexpr int kMSlots = 5;        // 16-texel M-tiles per wave per pass
+
+// Eq. 3 for 16 probes as a matrix product on MFMA (v_mfma_f32_16x16x4f32):
+//   irradiance  U_i[t][(q,c)] = sum_k w_tk   * L[q][k][c]      (M = texels, N = 16 x RGB)
+//   depth       U_d[t][(q,m)] = sum_k w_tk^s * t[q][k]^(m+1)   (M = texels, N = 16 x 2)
+// with K = rays. The weights (shared by every probe of the frame) are the A operand,
+// read from the transposed [R][T] tables; the probes' payload is the B operand,
+// staged in LDS 64 rays at a time. M-tiles are dealt round-robin to the 4 waves, up
+// to kMSlots per wave per pass (one pass covers 8x8 + 16x16 maps). The epilogue
+// normalises, mixes with the previous interior (hysteresis, or none for rejected
+// probes) and writes interior and border texels.
+// kStd: the 8x8 irradiance + 16x16 depth layout (4 + 16 M-tiles, one pass), where
+// slot 0 of every wave is an irradiance tile and slots 1..4 are depth tiles, known at
+// compile time; other resolutions take the general instantiation.
+template <bool kStd>
 __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a) {
-    __shared__ float4 pl[kMaxRays];
-    __shared__ float ti[kMaxRes * kMaxRes * 3];
-    __shared__ float td[kMaxRes * kMaxRes * 2];
-    const int p = blockIdx.x;
-    const int tid = threadIdx.x;
-    for (int i = tid; i < a.R; i += 256) pl[i] = a.payload[(size_t)p * a.R + i];
-    __syncthreads();
-    const float h = a.reject[p] ? 0.0f : a.hysteresis;
+    // payload of 16 probes x 4 channels x 64 rays, plus one zero row for absent probes
+    __shared__ float sx[(kBlendProbes * 4 + 1) * kBlendPitch];
+    __shared__ float s_h[kBlendProbes];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int row = lane & 15, krow = lane >> 4;
+    const int pb = blockIdx.x * kBlendProbes;
+    const int np = min(kBlendProbes, a.P - pb);
     const int ri = a.irr_res, rd = a.depth_res;
     const int Ti = ri * ri, Td = rd * rd;
+    const int mti = (Ti + 15) >> 4, mtd = (Td + 15) >> 4;
+    const int Tpi = mti * 16, Tpd = mtd * 16;   // padded rows of the weight tables
+    const int mtiles = mti + mtd;
     const int si = ri + 2, sd = rd + 2;
-    const float *old_i = a.prev_irr + (size_t)p * si * si * 3;
-    const float *old_d = a.prev_depth + (size_t)p * sd * sd * 2;
-    for (int t = tid; t < Ti; t += 256) {
-        float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
-        for (int i = 0; i < a.R; ++i) {
-            const float w = a.wt_i[(size_t)i * Ti + t];
-            const float4 v = pl[i];
-            s0 = fmaf(w, v.x, s0); s1 = fmaf(w, v.y, s1); s2 = fmaf(w, v.z, s2);
-        }
-        const float nrm = a.norm_i[t];
-        const int at = ((t / ri + 1) * si + (t % ri + 1)) * 3;
-        const float o0 = old_i[at], o1 = old_i[at + 1], o2 = old_i[at + 2];
-        if (nrm < 0.0f) {
-            ti[3 * t] = o0; ti[3 * t + 1] = o1; ti[3 * t + 2] = o2;
-        } else {
-            const float u0 = s0 * nrm, u1 = s1 * nrm, u2 = s2 * nrm;
-            ti[3 * t] = fmaf(h, o0 - u0, u0);
-            ti[3 * t + 1] = fmaf(h, o1 - u1, u1);
-            ti[3 * t + 2] = fmaf(h, o2 - u2, u2);
-        }
+    constexpr int kZeroRow = kBlendProbes * 4 * kBlendPitch;
+    if (tid < kBlendProbes) s_h[tid] = (tid < np && !a.reject[pb + tid]) ? a.hysteresis : 0.0f;
+    for (int e = tid; e < kBlendPitch; e += 256) sx[kZeroRow + e] = 0.0f;
+
+    // B-operand columns of this lane: irradiance (q, c) for 3 N-tiles, depth (q, m) for 2
+    int bi_off[3], bd_off[2];
+    bool bd_sq[2];
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+        const int col = n * 16 + row, q = col / 3, c = col - 3 * (col / 3);
+        bi_off[n] = q < np ? (q * 4 + c) * kBlendPitch : kZeroRow;
     }
-    for (int t = tid; t < Td; t += 256) {
-        float m1 = 0.0f, m2 = 0.0f;
-        for (int i = 0; i < a.R; ++i) {
-            const float w = a.wt_d[(size_t)i * Td + t];
-            const float d = pl[i].w;
-            m1 = fmaf(w, d, m1);
-            m2 = fmaf(w, d * d, m2);
+#pragma unroll
+    for (int n = 0; n < 2; ++n) {
+        const int col = n * 16 + row, q = col >> 1;
+        bd_off[n] = q < np ? (q * 4 + 3) * kBlendPitch : kZeroRow;
+        bd_sq[n] = (col & 1) != 0;
+    }
+
+    const int passes = kStd ? 1 : (mtiles + 4 * kMSlots - 1) / (4 * kMSlots);
+    for (int pass = 0; pass < passes; ++pass) {
+        floatx4 acc[kMSlots][3];
+        int mt[kMSlots];          // wave-uniform M-tile of each slot
+        const float *wcol[kMSlots];
+        int wstride[kMSlots];
+#pragma unroll
+        for (int s = 0; s < kMSlots; ++s) {
+            mt[s] = pass * 4 * kMSlots + s * 4 + wave;
+            const bool irr = kStd ? s == 0 : mt[s] < mti;
+            wcol[s] = irr ? a.wt_i + mt[s] * 16 + row : a.wt_d + (mt[s] - mti) * 16 + row;
+            wstride[s] = irr ? Tpi : Tpd;
+#pragma unroll
+            for (int n = 0; n < 3; ++n) acc[s][n] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
         }
-        const float nrm = a.norm_d[t];
-        const int at = ((t / rd + 1) * sd + (t % rd + 1)) * 2;
-        const float o0 = old_d[at], o1 = old_d[at + 1];
-        if (nrm < 0.0f) {
-            td[2 * t] = o0; td[2 * t + 1] = o1;
-        } else {
-            const float u0 = m1 * nrm, u1 = m2 * nrm;
-            td[2 * t] = fmaf(h, o0 - u0, u0);
-            td[2 * t + 1] = fmaf(h, o1 - u1, u1);
+        for (int k0 = 0; k0 < a.R; k0 += kBlendChunk) {
+            __syncthreads();
+            const int kc = min(kBlendChunk, a.R - k0);
+            for (int e = tid; e < kBlendProbes * kBlendChunk; e += 256) {
+                const int q = e / kBlendChunk, kk = e - q * kBlendChunk;
+                float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if (q < np && kk < kc) v = a.payload[(size_t)(pb + q) * a.R + k0 + kk];
+                float *d = sx + q * 4 * kBlendPitch + kk;
+                d[0] = v.x; d[kBlendPitch] = v.y; d[2 * kBlendPitch] = v.z; d[3 * kBlendPitch] = v.w;
+            }
+            __syncthreads();
+            float a_cur[kMSlots], a_nxt[kMSlots];
+#pragma unroll
+            for (int s = 0; s < kMSlots; ++s)
+                a_cur[s] = (kStd || mt[s] < mtiles) ? wcol[s][(size_t)(k0 + krow) * wstride[s]] : 0.0f;
+            for (int kk = 0; kk < kc; kk += 4) {
+                const int kl = kk + krow;
+                if (kk + 4 < kc) {
+#pragma unroll
+                    for (int s = 0; s < kMSlots; ++s)
+                        a_nxt[s] = (kStd || mt[s] < mtiles) ? wcol[s][(size_t)(k0 + kl + 4) * wstride[s]]
+                                                            : 0.0f;
+                }
+                float bi[3], bd[2];
+#pragma unroll
+                for (int n = 0; n < 3; ++n) bi[n] = sx[bi_off[n] + kl];
+#pragma unroll
+                for (int n = 0; n < 2; ++n) {
+                    const float tv = sx[bd_off[n] + kl];
+                    bd[n] = bd_sq[n] ? tv * tv : tv;
+                }
+#pragma unroll
+                for (int s = 0; s < kMSlots; ++s) {
+                    if (kStd ? s == 0 : mt[s] < mti) {
+#pragma unroll
+                        for (int n = 0; n < 3; ++n)
+                            acc[s][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_cur[s], bi[n], acc[s][n], 0, 0, 0);
+                    } else if (kStd || mt[s] < mtiles) {
+#pragma unroll
+                        for (int n = 0; n < 2; ++n)
+                            acc[s][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_cur[s], bd[n], acc[s][n], 0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int s = 0; s < kMSlots; ++s) a_cur[s] = a_nxt[s];
+            }
+        }
+        // epilogue: lane holds D[4*krow + r][row] of each tile
+#pragma unroll
+        for (int s = 0; s < kMSlots; ++s) {
+            if (!kStd && mt[s] >= mtiles) continue;
+            const bool irr = kStd ? s == 0 : mt[s] < mti;
+            const int res = irr ? ri : rd, T = irr ? Ti : Td, comps = irr ? 3 : 2;
+            const int side = irr ? si : sd;
+            const int m0 = (irr ? mt[s] : mt[s] - mti) * 16 + 4 * krow;
+            const float *norm = irr ? a.norm_i : a.norm_d;
+#pragma unroll
+            for (int n = 0; n < 3; ++n) {
+                if (!irr && n == 2) break;
+                const int col = n * 16 + row;
+                const int q = irr ? col / 3 : col >> 1;
+                const int c = irr ? col - 3 * q : col & 1;
+                if (q >= np) continue;
+                const size_t tile_floats = (size_t)side * side * comps;
+                const float *old_tile = (irr ? a.prev_irr : a.prev_depth) + (size_t)(pb + q) * tile_floats;
+                float *new_tile = (irr ? a.new_irr : a.new_depth) + (size_t)(pb + q) * tile_floats;
+                const float h = s_h[q];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int t = m0 + r;
+                    if (t >= T) continue;
+                    const int i = t % res, j = t / res;
+                    const float nrm = norm[t];
+                    const float old = old_tile[((j + 1) * side + (i + 1)) * comps + c];
+                    const float u = acc[s][n][r] * nrm;
+                    const float v = nrm < 0.0f ? old : fmaf(h, old - u, u);
+                    store_with_border(new_tile, res, comps, i, j, c, v);
+                }
+            }
         }
     }
     __syncthreads();
-    float *out_i = a.new_irr + (size_t)p * si * si * 3;
-    for (int k = tid; k < si * si; k += 256) {
-        int i, j;
-        border_source(ri, k % si, k / si, i, j);
-        const int src = (j * ri + i) * 3;
-        out_i[3 * k] = ti[src]; out_i[3 * k + 1] = ti[src + 1]; out_i[3 * k + 2] = ti[src + 2];
-    }
-    float *out_d = a.new_depth + (size_t)p * sd * sd * 2;
-    for (int k = tid; k < sd * sd; k += 256) {
-        int i, j;
-        border_source(rd, k % sd, k / sd, i, j);
-        const int src = (j * rd + i) * 2;
-        out_d[2 * k] = td[src]; out_d[2 * k + 1] = td[src + 1];
-    }
-    if (tid == 0) a.reject[p] = 0;
+    if (tid < np) a.reject[pb + tid] = 0;
 }
 
 __global__ __launch_bounds__(256) void sample_kernel(SampleArgs a) {
@@ -412,6 +603,20 @@ __global__ __launch_bounds__(256) void sample_kernel(SampleArgs a) {
     a.out[3 * q] = e.x;
     a.out[3 * q + 1] = e.y;
     a.out[3 * q + 2] = e.z;
+}
+
+// Corner-quad repacking of one grid level (see trilinear).
+__global__ __launch_bounds__(256) void pack_quads_kernel(const float *__restrict__ g, int n0, int n1,
+                                                         int n2, float4 *__restrict__ quad) {
+    const int64_t total = (int64_t)n0 * (n1 - 1) * (n2 - 1);
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= total) return;
+    const int i = (int)(q % n0);
+    const int j = (int)((q / n0) % (n1 - 1));
+    const int k = (int)(q / ((int64_t)n0 * (n1 - 1)));
+    const int64_t sy = n0, sz = (int64_t)n0 * n1;
+    const int64_t v = k * sz + j * sy + i;
+    quad[q] = make_float4(g[v], g[v + sy], g[v + sz], g[v + sz + sy]);
 }
 
 __global__ __launch_bounds__(256) void fill_u8_kernel(uint8_t *dst, uint8_t value, int64_t n) {
@@ -428,21 +633,44 @@ hipError_t launch_tables(const TableArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_trace(const TraceArgs &a, hipStream_t s) {
-    const int64_t total = (int64_t)a.P * a.R;
-    if (total == 0) return hipSuccess;
-    hipLaunchKernelGGL(trace_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, s, a);
+// Persistent grid: as many 256-thread blocks as fit on the device at once (fewer
+// when there are fewer rays).
+int trace_grid_blocks(int device, int64_t rays) {
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_kernel, 256, 0) != hipSuccess)
+        per_cu = 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+        cus = 1;
+    const int64_t resident = (int64_t)(per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+    const int64_t needed = blocks_for(rays, 256);
+    return (int)(needed < resident ? needed : resident);
+}
+
+hipError_t launch_trace(const TraceArgs &a, int blocks, hipStream_t s) {
+    if ((int64_t)a.P * a.R == 0 || blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(trace_kernel, dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_blend(const BlendArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(blend_kernel, dim3(a.P), dim3(256), 0, s, a);
+    const dim3 grid(blocks_for(a.P, kBlendProbes)), block(256);
+    if (a.irr_res == 8 && a.depth_res == 16)
+        hipLaunchKernelGGL(blend_kernel<true>, grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL(blend_kernel<false>, grid, block, 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_sample(const SampleArgs &a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
     hipLaunchKernelGGL(sample_kernel, dim3(blocks_for(a.n, 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_quads(const float *g, int n0, int n1, int n2, float4 *quad, hipStream_t s) {
+    const int64_t total = (int64_t)n0 * (n1 - 1) * (n2 - 1);
+    hipLaunchKernelGGL(pack_quads_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, s, g, n0, n1,
+                       n2, quad);
     return hipGetLastError();
 }
 

@@ -107,11 +107,11 @@ struct sdfddgi_ctx {
     int n[kMaxLevels][3]{};
     double origin[kMaxLevels][3]{};
     double spacing[kMaxLevels]{};
-    float *sdf[kMaxLevels]{};
+    float4 *quad[kMaxLevels]{};  // corner-quad repacking of each level's grid
     float *alb[kMaxLevels]{};
     sdfddgi_probe_grid pg{};
     int64_t P = 0;
-    int R = 0, Ti = 0, Td = 0;
+    int R = 0, Ti = 0, Td = 0, Tpi = 0, Tpd = 0;
     int64_t irr_floats = 0, depth_floats = 0;
     float *probe_pos = nullptr;
     double *base_dirs = nullptr, *texel_i = nullptr, *texel_d = nullptr;
@@ -119,6 +119,8 @@ struct sdfddgi_ctx {
     float *irr[2]{}, *depth[2]{};
     int cur = 0;
     uint8_t *reject = nullptr;
+    int *counter = nullptr;
+    int trace_blocks = 0;
     float4 *payload = nullptr;
     int *records = nullptr;
     bool have_frame = false, have_records = false;
@@ -159,12 +161,12 @@ hipError_t dev_alloc(T **p, size_t count) {
 
 void free_all(sdfddgi_ctx *c) {
     for (int L = 0; L < kMaxLevels; ++L) {
-        if (c->sdf[L]) (void)hipFree(c->sdf[L]);
+        if (c->quad[L]) (void)hipFree(c->quad[L]);
         if (c->alb[L]) (void)hipFree(c->alb[L]);
     }
     void *bufs[] = {c->probe_pos, c->base_dirs, c->texel_i, c->texel_d, c->dirs, c->wt_i,
                     c->wt_d, c->norm_i, c->norm_d, c->irr[0], c->irr[1], c->depth[0],
-                    c->depth[1], c->reject, c->payload, c->records};
+                    c->depth[1], c->reject, c->counter, c->payload, c->records};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (c->ev_ring) {
@@ -189,7 +191,7 @@ sdfddgi_status validate(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_grid *p
                 return fail(nullptr, SDFDDGI_EINVAL, "level %d: non-finite origin", L);
             cnt *= lv.n[c];
         }
-        if (cnt * 3 >= (int64_t)1 << 31)
+        if (cnt * 4 >= (int64_t)1 << 31)
             return fail(nullptr, SDFDDGI_EINVAL, "level %d: grid too large", L);
         if (!(lv.spacing > 0.0) || !std::isfinite(lv.spacing))
             return fail(nullptr, SDFDDGI_EINVAL, "level %d: spacing must be finite and > 0", L);
@@ -234,7 +236,7 @@ sdfddgi_status validate(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_grid *p
 
 DevLevel dev_level(const sdfddgi_ctx *c, int L) {
     DevLevel d{};
-    d.sdf = c->sdf[L];
+    d.quad = c->quad[L];
     d.alb = c->alb[L];
     d.n0 = c->n[L][0];
     d.n1 = c->n[L][1];
@@ -266,6 +268,8 @@ TableArgs table_args(const sdfddgi_ctx *c, uint64_t seed) {
     t.R = c->R;
     t.Ti = c->Ti;
     t.Td = c->Td;
+    t.Tpi = c->Tpi;
+    t.Tpd = c->Tpd;
     rotation_matrix(seed, t.q);
     t.sharp = (double)c->prm.depth_sharpness;
     t.base = c->base_dirs;
@@ -276,6 +280,7 @@ TableArgs table_args(const sdfddgi_ctx *c, uint64_t seed) {
     t.wt_d = c->wt_d;
     t.norm_i = c->norm_i;
     t.norm_d = c->norm_d;
+    t.counter = c->counter;
     return t;
 }
 
@@ -359,6 +364,8 @@ sdfddgi_status sdfddgi_create(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_g
     c->R = params->rays_per_probe;
     c->Ti = params->irr_res * params->irr_res;
     c->Td = params->depth_res * params->depth_res;
+    c->Tpi = (c->Ti + 15) / 16 * 16;
+    c->Tpd = (c->Td + 15) / 16 * 16;
     c->irr_floats = c->P * (params->irr_res + 2) * (params->irr_res + 2) * 3;
     c->depth_floats = c->P * (params->depth_res + 2) * (params->depth_res + 2) * 2;
 
@@ -382,9 +389,10 @@ sdfddgi_status sdfddgi_create(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_g
             c->origin[L][k] = lv.origin[k];
         }
         c->spacing[L] = lv.spacing;
-        SDF_TRY(dev_alloc(&c->sdf[L], cnt), "allocating sdf level");
-        SDF_TRY(hipMemcpyAsync(c->sdf[L], lv.sdf, cnt * sizeof(float), hipMemcpyDeviceToDevice,
-                               c->stream), "copying sdf level");
+        const size_t nquad = (size_t)lv.n[0] * (lv.n[1] - 1) * (lv.n[2] - 1);
+        SDF_TRY(dev_alloc(&c->quad[L], nquad), "allocating sdf level");
+        SDF_TRY(launch_pack_quads(lv.sdf, lv.n[0], lv.n[1], lv.n[2], c->quad[L], c->stream),
+                "packing sdf level");
         if (lv.albedo_rgb) {
             SDF_TRY(dev_alloc(&c->alb[L], 3 * cnt), "allocating albedo level");
             SDF_TRY(hipMemcpyAsync(c->alb[L], lv.albedo_rgb, 3 * cnt * sizeof(float),
@@ -432,8 +440,12 @@ sdfddgi_status sdfddgi_create(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_g
     SDF_TRY(ce, "uploading constants");
 
     SDF_TRY(dev_alloc(&c->dirs, 3 * c->R), "allocating tables");
-    SDF_TRY(dev_alloc(&c->wt_i, (size_t)c->R * c->Ti), "allocating tables");
-    SDF_TRY(dev_alloc(&c->wt_d, (size_t)c->R * c->Td), "allocating tables");
+    SDF_TRY(dev_alloc(&c->wt_i, (size_t)c->R * c->Tpi), "allocating tables");
+    SDF_TRY(dev_alloc(&c->wt_d, (size_t)c->R * c->Tpd), "allocating tables");
+    SDF_TRY(hipMemsetAsync(c->wt_i, 0, (size_t)c->R * c->Tpi * sizeof(float), c->stream),
+            "clearing tables");
+    SDF_TRY(hipMemsetAsync(c->wt_d, 0, (size_t)c->R * c->Tpd * sizeof(float), c->stream),
+            "clearing tables");
     SDF_TRY(dev_alloc(&c->norm_i, c->Ti), "allocating tables");
     SDF_TRY(dev_alloc(&c->norm_d, c->Td), "allocating tables");
     for (int k = 0; k < 2; ++k) {
@@ -446,7 +458,9 @@ sdfddgi_status sdfddgi_create(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_g
     }
     SDF_TRY(dev_alloc(&c->reject, P), "allocating reject flags");
     SDF_TRY(launch_fill_u8(c->reject, 1, P, c->stream), "launching fill");
+    SDF_TRY(dev_alloc(&c->counter, 1), "allocating ray counter");
     SDF_TRY(dev_alloc(&c->payload, (size_t)P * c->R), "allocating payload");
+    c->trace_blocks = trace_grid_blocks(dev, P * c->R);
     if (params->flags & SDFDDGI_FLAG_RECORD_RAYS)
         SDF_TRY(dev_alloc(&c->records, (size_t)P * c->R * 8), "allocating ray records");
     if (params->flags & SDFDDGI_FLAG_TIMING) {
@@ -505,6 +519,7 @@ sdfddgi_status sdfddgi_update_frame(sdfddgi_ctx *c, const sdfddgi_light *light,
     t.prev_irr = c->irr[c->cur];
     t.payload = c->payload;
     t.records = c->records;
+    t.counter = c->counter;
 
     hipEvent_t *ev = c->ev_ring ? c->ev_ring + 4 * c->ring_head : nullptr;
     hipError_t e;
@@ -514,7 +529,7 @@ sdfddgi_status sdfddgi_update_frame(sdfddgi_ctx *c, const sdfddgi_light *light,
         return hip_fail(c, e, "launching tables_kernel");
     if (ev && (e = hipEventRecord(ev[1], c->stream)) != hipSuccess)
         return hip_fail(c, e, "event");
-    if ((e = launch_trace(t, c->stream)) != hipSuccess)
+    if ((e = launch_trace(t, c->trace_blocks, c->stream)) != hipSuccess)
         return hip_fail(c, e, "launching trace_kernel");
     if (ev && (e = hipEventRecord(ev[2], c->stream)) != hipSuccess)
         return hip_fail(c, e, "event");

@@ -68,11 +68,12 @@ def compare_records(gpu_rec, ref_rec, where):
                          f"ref {ref_rec[k]}")
 
 
-def single_frame_check(S, w, frame, reset, seed_atlas=1, probes=None, check_all=True, **over):
+def single_frame_check(S, w, frame, reset, seed_atlas=1, probes=None, **over):
     """One frame from a seeded previous atlas; compare records, payload and maps."""
     announce(f"{w.name} P={w.num_probes} R={w.params.rays_per_probe} reset={reset} {over}")
-    ctx = S.context_from_workload(w, flags=S.SDFDDGI_FLAG_RECORD_RAYS, **over)
-    chk = oracle.Checker(w, **{k if k != "sky_rgb" else "sky": v for k, v in over.items()})
+    w = scenegen.with_params(w, **over)
+    ctx = S.context_from_workload(w, flags=S.SDFDDGI_FLAG_RECORD_RAYS)
+    chk = oracle.Checker(w)
     irr0, dep0 = scenegen.random_atlas(w.num_probes, w.params, seed=seed_atlas)
     S.sdfddgi_set_maps(ctx, to_dev(irr0), to_dev(dep0))
     if reset:
@@ -179,7 +180,9 @@ def test_frame_small_cascade_ragged(S):
 
 @pytest.mark.parametrize("over", [dict(bounce_gain=0.5, relax=1.3),
                                   dict(max_steps=12, hit_eps=5e-3),
-                                  dict(depth_sharpness=8.0, hysteresis=0.5)])
+                                  dict(depth_sharpness=8.0, hysteresis=0.5),
+                                  dict(irr_res=6, depth_res=12),     # partial MFMA tiles
+                                  dict(irr_res=10, depth_res=20)])   # several blend passes
 def test_frame_parameter_variants(S, over):
     w = scenegen.small_cascade(1, probes=(5, 2, 4), rays=144)
     single_frame_check(S, w, w.frames[1], reset=False, **over)
