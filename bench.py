@@ -22,7 +22,7 @@ if ROOT not in sys.path:
 
 METRIC = "probe-rays/s + ms/frame (16k probes); learned vs plain at equal irradiance err"
 HBM_PEAK_GBS = 8000.0
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "trace_kernel_hbm_counters.json")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "hbm_counters_open_scene_16384x256.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2007_14394_amd", "csrc", "kernels.hip")
 
 # Algorithmic bytes of the trace kernel (what the method reads/writes per ray):
@@ -42,7 +42,22 @@ def parse():
                     help="probes in the CPU-baseline sample (0 disables it)")
     ap.add_argument("--no-stats", action="store_true",
                     help="skip the ray-statistics pass (for profiler runs)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB five times "
+                         "(reference reading for the HBM byte counters) and exit")
     return ap.parse_args()
+
+
+def copy_calibration(mib: int) -> None:
+    import torch
+    n = mib * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_per_dispatch": n * 4, "dispatches": 5}), flush=True)
 
 
 def kernel_source_hash() -> str:
@@ -50,16 +65,21 @@ def kernel_source_hash() -> str:
 
 
 def load_traffic(launch_rays: int):
-    """HBM bytes per trace launch from committed rocprofv3 counters, if current."""
+    """HBM bytes per trace launch from the committed rocprofv3 counter summary, or None
+    when the summary is missing, for another problem size, or older than kernels.hip."""
+    data = {}
     try:
-        data = json.load(open(COUNTERS_FILE))
-    except (OSError, ValueError):
+        for line in open(COUNTERS_FILE):
+            if " = " in line:
+                k, v = line.split(" = ", 1)
+                data[k.strip()] = v.strip()
+    except OSError:
         return None
     if data.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    if data.get("rays_per_launch") != launch_rays:
+    if data.get("rays_per_launch") != str(launch_rays):
         return None
-    return float(data["hbm_bytes_per_launch"])
+    return float(data["trace_hbm_bytes_per_launch"])
 
 
 def ray_statistics(S, w, frames):
@@ -121,6 +141,9 @@ def main():
     from paper_2007_14394_amd import sdfddgi as S
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     total_frames = args.warmup + args.steps
     w = scenegen.config2(args.seed, probes=args.probes, frames=max(total_frames, 1))
     P, R = w.num_probes, w.params.rays_per_probe
@@ -134,7 +157,8 @@ def main():
     for k in range(args.warmup):
         frame(k)
     torch.cuda.synchronize()
-    S.sdfddgi_get_kernel_times(ctx) if args.warmup else None  # drop warmup timings
+    if args.warmup:
+        S.sdfddgi_get_kernel_times(ctx)  # discard the warmup frames' timings
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     start.record(stream)
