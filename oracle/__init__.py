@@ -60,6 +60,37 @@ class FrameDesc(ctypes.Structure):
 
 
 _lib = None
+_lib_path = _LIB_PATH
+
+
+def _load(path: str):
+    L = ctypes.CDLL(path)
+    L.orc_splitmix64.restype = ctypes.c_uint64
+    L.orc_splitmix64.argtypes = [ctypes.POINTER(ctypes.c_uint64)]
+    L.orc_sdf32.restype = ctypes.c_float
+    L.orc_level32.restype = ctypes.c_int32
+    L.orc_blend_probe.restype = ctypes.c_int32
+    L.orc_update_probes.restype = ctypes.c_int32
+    return L
+
+
+class use_library:
+    """Temporarily route every checker call to another build of oracle.c (the
+    mutation tests load copies with one planted mistake each)."""
+
+    def __init__(self, path: str):
+        self.path = path
+
+    def __enter__(self):
+        global _lib, _lib_path
+        self._saved = (_lib, _lib_path)
+        _lib, _lib_path = _load(self.path), self.path
+        return self
+
+    def __exit__(self, *exc):
+        global _lib, _lib_path
+        _lib, _lib_path = self._saved
+        return False
 
 
 def lib():
@@ -67,14 +98,7 @@ def lib():
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
             build(force=True)
-        L = ctypes.CDLL(_LIB_PATH)
-        L.orc_splitmix64.restype = ctypes.c_uint64
-        L.orc_splitmix64.argtypes = [ctypes.POINTER(ctypes.c_uint64)]
-        L.orc_sdf32.restype = ctypes.c_float
-        L.orc_level32.restype = ctypes.c_int32
-        L.orc_blend_probe.restype = ctypes.c_int32
-        L.orc_update_probes.restype = ctypes.c_int32
-        _lib = L
+        _lib = _load(_LIB_PATH)
     return _lib
 
 

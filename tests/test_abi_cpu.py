@@ -130,3 +130,11 @@ def test_calls_on_null_context_are_rejected():
     assert lib.sdfddgi_reset_history(None) == S.SDFDDGI_EINVAL
     assert lib.sdfddgi_destroy(None) == S.SDFDDGI_OK
     assert lib.sdfddgi_get_sizes(None, None, None, None, None) == S.SDFDDGI_EINVAL
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path, monkeypatch):
+    # there is no CPU fallback: a missing shared library is an error, not a silent path
+    monkeypatch.setattr(S, "LIB_PATH", str(tmp_path / "missing" / "libsdfddgi.so"))
+    monkeypatch.setattr(S, "_lib", None)
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        S.load_library()

@@ -1,0 +1,87 @@
+"""Sensitivity of the checker's pins: each case compiles a copy of oracle.c with one
+plausible mistake planted (on the CPU) and shows that a pin fails on it.
+
+The planted copies live in a temporary directory; the real checker is untouched.
+"""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from tests import test_oracle_pins as pins
+from tests.conftest import ROOT
+
+SRC = os.path.join(ROOT, "oracle", "oracle.c")
+
+# (name, exact text in oracle.c, replacement, pins expected to catch it)
+MUTANTS = [
+    ("rotation_sign", "q[1] = 2.0 * (x * y - z * w);", "q[1] = 2.0 * (x * y + z * w);",
+     [lambda: pins.test_rotation_is_proper_orthonormal(0)]),
+    ("fibonacci_offset", "double z = 1.0 - (2.0 * (double)i + 1.0) / (double)rays;",
+     "double z = 1.0 - (2.0 * (double)i) / (double)rays;",
+     [lambda: pins.test_spherical_fibonacci_set(144)]),
+    ("golden_angle", "double gamma = (sqrt(5.0) - 1.0) * 0.5;", "double gamma = (sqrt(5.0) - 1.0) * 0.45;",
+     [lambda: pins.test_spherical_fibonacci_set(256)]),
+    ("oct_fold", "double fu = (1.0 - fabs(v)) * sgn(u);\n        double fv = (1.0 - fabs(u)) * sgn(v);\n        u = fu;",
+     "double fu = (1.0 - fabs(u)) * sgn(u);\n        double fv = (1.0 - fabs(v)) * sgn(v);\n        u = fu;",
+     [pins.test_octahedral_round_trip]),
+    ("border_reflection", "        *i = n - a;\n        *j = top ? 0 : n - 1;", "        *i = a - 1;\n        *j = top ? 0 : n - 1;",
+     [lambda: pins.test_border_makes_lookup_continuous_across_every_seam(8)]),
+    ("trilinear_axis", "float c0 = fmaf(f[1], c10 - c00, c00);", "float c0 = fmaf(f[0], c10 - c00, c00);",
+     [pins.test_sampler_exact_at_vertices_and_on_linear_fields,
+      pins.test_sampler_within_trilinear_error_bound_of_sphere]),
+    ("trace_step", "t = fmaf(s->relax, d, t);", "t = fmaf(s->relax, d * 0.5f, t);",
+     [pins.test_plane_trace_closed_form]),
+    ("shadow_bias_sign", "xs[c] = fmaf(g.n[c], s->shadow_bias, g.prim.x[c]);",
+     "xs[c] = fmaf(g.n[c], -s->shadow_bias, g.prim.x[c]);",
+     [pins.test_direct_term_is_lambert_on_open_plane]),
+    ("bounce_gain_dropped", "out[c] = albedo[c] / kPi * (direct + (double)s->bounce_gain * indirect[c]);",
+     "out[c] = albedo[c] / kPi * (direct + indirect[c]);",
+     [pins.test_indirect_term_from_constant_atlas]),
+    ("cosine_sign", "double w = c > 0.0 ? c : 0.0;", "double w = c < 0.0 ? -c : 0.0;",
+     [pins.test_eq3_quadrature_of_linear_radiance]),
+    ("depth_second_moment", "acc[1] += wd * pl[3] * pl[3];", "acc[1] += wd * pl[3];",
+     [lambda: pins.test_uniform_radiance_gives_pi_L_and_constant_depth(144)]),
+    ("hysteresis_swapped", "v = h * prev + (1.0 - h) * u;", "v = (1.0 - h) * prev + h * u;",
+     [pins.test_hysteresis_sequence]),
+    ("interp_weight", "double wp = (dx ? f[0] : 1.0 - f[0]) * (dy ? f[1] : 1.0 - f[1]) *\n                            (dz ? f[2] : 1.0 - f[2]);",
+     "double wp = (dx ? f[0] : 1.0 - f[0]) * (dy ? f[1] : 1.0 - f[1]) *\n                            (dz ? f[1] : 1.0 - f[1]);",
+     [pins.test_interp_reproduces_fields_linear_in_position]),
+    ("inside_ignored", "if (primary && k == 0 && d < 0.0f) {", "if (primary && k == 0 && d < -1e30f) {",
+     [pins.test_miss_inside_and_exhaustion_outcomes]),
+]
+
+
+def build_mutant(tmp_path, name, old, new):
+    text = open(SRC).read()
+    assert text.count(old) == 1, f"{name}: planted text not found exactly once"
+    src = tmp_path / f"oracle_{name}.c"
+    src.write_text(text.replace(old, new))
+    # the header sits beside the real source
+    out = tmp_path / f"liboracle_{name}.so"
+    subprocess.check_call(["gcc", *oracle.CFLAGS, f"-I{os.path.dirname(SRC)}", str(src),
+                           "-o", str(out), "-lm"])
+    return str(out)
+
+
+@pytest.mark.parametrize("name,old,new,catchers", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_planted_mistake_fails_a_pin(tmp_path, name, old, new, catchers):
+    path = build_mutant(tmp_path, name, old, new)
+    with oracle.use_library(path):
+        failed = 0
+        for pin in catchers:
+            try:
+                pin()
+            except AssertionError:
+                failed += 1
+        assert failed == len(catchers), f"{name}: {len(catchers) - failed} pin(s) did not notice"
+
+
+def test_unmodified_copy_passes_the_same_pins(tmp_path):
+    path = build_mutant(tmp_path, "identity", "static const double kPi", "static const double kPi")
+    with oracle.use_library(path):
+        for _, _, _, catchers in MUTANTS:
+            for pin in catchers:
+                pin()
