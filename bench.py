@@ -22,13 +22,15 @@ if ROOT not in sys.path:
 
 METRIC = "probe-rays/s + ms/frame (16k probes); learned vs plain at equal irradiance err"
 HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK_TFLOPS = 157.3
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "hbm_counters_open_scene_16384x256.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2007_14394_amd", "csrc", "kernels.hip")
 
-# Algorithmic bytes of the trace kernel (what the method reads/writes per ray):
+# Algorithmic bytes of the two trace kernels (what the method reads/writes per ray):
 SAMPLE_BYTES = 8 * 4          # one trilinear SDF sample: 8 binary32 corners
 HIT_BYTES = 6 * SAMPLE_BYTES + 8 * 3 * 4 + 8 * 4 * 3 * 4  # normal, albedo, 8 probes x 4 texels RGB
 PAYLOAD_BYTES = 16            # (R, G, B, t) written per ray
+HITREC_BYTES = 8              # primary hit record written per ray, read back by the hit kernel
 
 
 def parse():
@@ -64,9 +66,9 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
 
 
-def load_traffic(launch_rays: int):
-    """HBM bytes per trace launch from the committed rocprofv3 counter summary, or None
-    when the summary is missing, for another problem size, or older than kernels.hip."""
+def load_traffic(launch_rays: int, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or
+    None when the summary is missing, for another problem size, or older than kernels.hip."""
     data = {}
     try:
         for line in open(COUNTERS_FILE):
@@ -79,14 +81,15 @@ def load_traffic(launch_rays: int):
         return None
     if data.get("rays_per_launch") != str(launch_rays):
         return None
-    return float(data["trace_hbm_bytes_per_launch"])
+    key = f"{kernel}_hbm_bytes_per_launch"
+    return float(data[key]) if key in data else None
 
 
 def ray_statistics(S, w, frames):
-    """Mean algorithmic bytes per trace launch, from the GPU's own ray records."""
+    """Mean algorithmic bytes per launch of each trace kernel, from the GPU's ray records."""
     import torch
     ctx = S.context_from_workload(w, flags=S.SDFDDGI_FLAG_RECORD_RAYS)
-    tot = dict(bytes=0.0, prim=0.0, shadow=0.0, hits=0.0)
+    tot = dict(primary_bytes=0.0, hits_bytes=0.0, prim=0.0, shadow=0.0, hits=0.0)
     for fr in frames:
         S.sdfddgi_update_frame(ctx, fr.dir_to_light, fr.radiance_rgb, fr.rotation_seed)
         rec = S.sdfddgi_get_ray_records(ctx).view(-1, 8)
@@ -94,8 +97,10 @@ def ray_statistics(S, w, frames):
         hit = ((kind == 2) | (kind == 3)).double()
         prim = rec[:, 1].double()
         shadow = rec[:, 3].double()
-        nbytes = (SAMPLE_BYTES * (prim + shadow) + HIT_BYTES * hit + PAYLOAD_BYTES).sum()
-        tot["bytes"] += float(nbytes)
+        primary = (SAMPLE_BYTES * prim + HITREC_BYTES + PAYLOAD_BYTES * (1.0 - hit)).sum()
+        hits = (HITREC_BYTES + hit * (SAMPLE_BYTES * shadow + HIT_BYTES + PAYLOAD_BYTES)).sum()
+        tot["primary_bytes"] += float(primary)
+        tot["hits_bytes"] += float(hits)
         tot["prim"] += float(prim.mean())
         tot["shadow"] += float(shadow.mean())
         tot["hits"] += float(hit.mean())
@@ -199,17 +204,31 @@ def main():
         stats_frames = [w.frames[(args.warmup + k) % len(w.frames)]
                         for k in range(0, args.steps, max(1, args.steps // 10))]
         st = ray_statistics(S, w, stats_frames)
-        achieved = st["bytes"] / (kt["trace"] * 1e-3) / 1e9
-        traffic = load_traffic(P * R)
-        out["roofline"] = {"kernel": "trace_kernel", "bound": "hbm", "achieved": achieved,
-                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+        flops = 2.0 * P * R * (w.params.irr_res ** 2 * 3 + w.params.depth_res ** 2 * 2)
+        kernels = {
+            "primary_kernel": {"ms": kt["primary"], "bound": "hbm", "unit": "GB/s",
+                               "peak": HBM_PEAK_GBS, "work": st["primary_bytes"],
+                               "achieved": st["primary_bytes"] / (kt["primary"] * 1e-3) / 1e9},
+            "hits_kernel": {"ms": kt["hits"], "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                            "work": st["hits_bytes"],
+                            "achieved": st["hits_bytes"] / (kt["hits"] * 1e-3) / 1e9},
+            "blend_kernel": {"ms": kt["blend"], "bound": "mfma", "unit": "TFLOP/s",
+                             "peak": FP32_MFMA_PEAK_TFLOPS, "work": flops,
+                             "achieved": flops / (kt["blend"] * 1e-3) / 1e12},
+        }
+        for v in kernels.values():
+            v["frac"] = v["achieved"] / v["peak"]
+        name = max(kernels, key=lambda n: kernels[n]["ms"])
+        dom = kernels[name]
+        traffic = load_traffic(P * R, name)
+        out["roofline"] = {"kernel": name, "bound": dom["bound"], "achieved": dom["achieved"],
+                           "peak": dom["peak"], "unit": dom["unit"], "frac": dom["frac"],
                            "traffic": traffic,
-                           "algorithmic_bytes_per_launch": st["bytes"]}
+                           ("algorithmic_bytes_per_launch" if dom["unit"] == "GB/s"
+                            else "flops_per_launch"): dom["work"]}
+        out["kernels"] = kernels
         out["ray_stats"] = {"primary_steps": st["prim"], "shadow_steps": st["shadow"],
                             "hit_fraction": st["hits"]}
-        flops = 2.0 * P * R * (w.params.irr_res ** 2 * 3 + w.params.depth_res ** 2 * 2)
-        out["blend"] = {"flops_per_launch": flops,
-                        "tflops": flops / (kt["blend"] * 1e-3) / 1e12}
     if args.cpu_probes > 0:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_probes)
     print(json.dumps(out), flush=True)

@@ -214,8 +214,9 @@ sdfddgi_status sdfddgi_ray_directions(uint64_t rotation_seed, int32_t rays, floa
 /* Mean per-kernel GPU times in milliseconds over the update_frame calls made
  * since the previous call of this function (at most the last 256), measured
  * with events recorded on the context's stream around each kernel:
- * [0] ray-direction/weight tables, [1] trace and shade, [2] blend, [3] whole
- * frame. Host pointer ms[count], count <= 4. Waits for the last timed frame.
+ * [0] ray-direction/weight tables, [1] primary sphere trace, [2] hit
+ * shading (normal, shadow ray, lookups), [3] blend, [4] whole frame.
+ * Host pointer ms[count], count <= 5. Waits for the last timed frame.
  * ESTATE without SDFDDGI_FLAG_TIMING or when no frame ran since the last call. */
 sdfddgi_status sdfddgi_get_kernel_times(sdfddgi_ctx *ctx, float *ms, int32_t count);
 

@@ -20,6 +20,10 @@ struct DevLevel {
     float org0, org1, org2;
     float inv;
     float half;
+    // Exact binary32 bounds on x of the level's box test: for every float x,
+    // lo <= (x - org) * inv  <=>  x >= xlo, and (x - org) * inv <= hi  <=>  x <= xhi,
+    // with [lo, hi] = [1, n-2] (inner levels) or [0, n-1] (coarsest level).
+    float xlo0, xlo1, xlo2, xhi0, xhi1, xhi2;
 };
 
 struct ProbeGridDev {
@@ -45,7 +49,13 @@ struct TraceArgs {
     const float *prev_irr;      // previous irradiance atlas
     float4 *payload;            // [P*R]
     int *records;               // [P*R*8] or nullptr
-    int *counter;               // next unclaimed ray (zeroed by tables_kernel)
+    int4 *hitq;                 // [P*R] queue of primary hits: (ray, bits of t, outcome|level<<4|steps<<8, 0)
+    int *counter;               // [3] rays claimed by primary_kernel, queue entries claimed by
+                                //     hits_kernel, queue length (all zeroed by tables_kernel)
+};
+
+struct TraceGrid {
+    int primary_blocks = 0, hits_blocks = 0;
 };
 
 struct TableArgs {
@@ -61,7 +71,7 @@ struct TableArgs {
     float *wt_d;                // [R][Tpd] w_ti^s, transposed; rows t >= Td stay zero
     float *norm_i;              // [Ti]  pi / sum_i w_ti   (-1: all weights vanish)
     float *norm_d;              // [Td]  1 / sum_i w_ti^s  (-1: all weights vanish)
-    int *counter;               // trace_kernel's ray counter, reset here (may be null)
+    int *counter;               // [3] the trace kernels' counters, reset here (may be null)
 };
 
 struct BlendArgs {
@@ -85,8 +95,9 @@ struct SampleArgs {
 
 // Launchers (kernels.hip). Each enqueues on `stream` and returns the launch status.
 hipError_t launch_tables(const TableArgs &a, hipStream_t stream);
-int trace_grid_blocks(int device, int64_t rays);
-hipError_t launch_trace(const TraceArgs &a, int blocks, hipStream_t stream);
+TraceGrid trace_grid(int device, int64_t rays);
+hipError_t launch_primary(const TraceArgs &a, const TraceGrid &grid, hipStream_t stream);
+hipError_t launch_hits(const TraceArgs &a, const TraceGrid &grid, hipStream_t stream);
 hipError_t launch_blend(const BlendArgs &a, hipStream_t stream);
 hipError_t launch_sample(const SampleArgs &a, hipStream_t stream);
 hipError_t launch_pack_quads(const float *grid, int n0, int n1, int n2, float4 *quad,

@@ -4,8 +4,9 @@
 //                   spherical-Fibonacci set, rounded once) and the Eq. 3 texel-by-
 //                   ray weight matrices w_ti = max(0, n_t . w_i) and w_ti^s with
 //                   their reciprocal row sums
-//   trace_kernel    per ray: sphere trace, hit normal, SDF shadow ray, albedo,
-//                   multi-bounce lookup into the previous atlas, payload (R,G,B,t)
+//   primary_kernel  per ray: primary sphere trace; payload of misses, hit records
+//   hits_kernel     per hit: normal, SDF shadow ray, albedo, multi-bounce lookup into
+//                   the previous atlas, payload (R,G,B,t)
 //   blend_kernel    per probe: Eq. 3 ratio estimate for every texel, depth
 //                   moments, temporal mix, octahedral border
 //   sample_kernel   probe interpolation at arbitrary points and normals
@@ -25,21 +26,39 @@ __device__ __forceinline__ float clampf(float v, float lo, float hi) { return fm
 
 // ------------------------------------------------------------- geometry -----
 
-struct LevelView {
-    const float4 *quad;
-    const float *alb;
-    int n0, n1, n2;
-    float org0, org1, org2, inv, half;
+// A cascade level as the trace loops read it, copied to LDS once per block. The
+// binary32 constants were computed once in binary64 on the host.
+struct LevelLds {
+    const float4 *quad;            // corner quads [n2-1][n1-1][n0]
+    const float *alb;              // albedo [n2][n1][n0][3] or nullptr
+    float org0, org1, org2, inv;   // (float)origin, (float)(1/spacing)
+    float cmax0, cmax1, cmax2;     // (float)(n-2): last cell index per axis
+    float half;                    // (float)(spacing/2)
+    uint32_t row, slice;           // quad strides: n0, n0*(n1-1)
+    uint32_t arow, aslice;         // albedo strides: n0, n0*n1
 };
 
-__device__ __forceinline__ void level_view(const DevLevel &d, LevelView &v) {
-    v.quad = d.quad; v.alb = d.alb; v.n0 = d.n0; v.n1 = d.n1; v.n2 = d.n2;
-    v.org0 = d.org0; v.org1 = d.org1; v.org2 = d.org2; v.inv = d.inv; v.half = d.half;
+__device__ __forceinline__ void load_levels(const TraceArgs &a, LevelLds *s_lv) {
+    if (threadIdx.x < kMaxLevels && (int)threadIdx.x < a.nl) {
+        const DevLevel &d = a.lv[threadIdx.x];
+        LevelLds v;
+        v.quad = d.quad; v.alb = d.alb;
+        v.org0 = d.org0; v.org1 = d.org1; v.org2 = d.org2; v.inv = d.inv;
+        v.cmax0 = (float)(d.n0 - 2); v.cmax1 = (float)(d.n1 - 2); v.cmax2 = (float)(d.n2 - 2);
+        v.half = d.half;
+        v.row = (uint32_t)d.n0; v.slice = (uint32_t)d.n0 * (uint32_t)(d.n1 - 1);
+        v.arow = (uint32_t)d.n0; v.aslice = (uint32_t)d.n0 * (uint32_t)d.n1;
+        s_lv[threadIdx.x] = v;
+    }
+    __syncthreads();
 }
 
-// Cell and fraction of grid coordinate u along one axis with n vertices.
-__device__ __forceinline__ void cell_of(float u, int n, int &i, float &f) {
-    float fl = clampf(floorf(u), 0.0f, (float)(n - 2));
+// Cell and fraction of grid coordinate u along one axis (cell clamped to [0, cmax],
+// cmax = vertices - 2). The int overload is deleted so a vertex count cannot be
+// passed by mistake.
+__device__ void cell_of(float u, int cmax, int &i, float &f) = delete;
+__device__ __forceinline__ void cell_of(float u, float cmax, int &i, float &f) {
+    const float fl = clampf(floorf(u), 0.0f, cmax);
     i = (int)fl;
     f = clampf(u - fl, 0.0f, 1.0f);
 }
@@ -48,77 +67,88 @@ __device__ __forceinline__ void cell_of(float u, int n, int &i, float &f) {
 // The grid is stored as corner quads: quad (i,j,k) = the values at (i,j,k),
 // (i,j+1,k), (i,j,k+1), (i,j+1,k+1), so a cell's eight corners are the two
 // adjacent quads (i,j,k) and (i+1,j,k) -- usually one cache line.
-__device__ __forceinline__ float trilinear(const float4 *__restrict__ quad, int n0, int n1, int n2,
-                                           float u0, float u1, float u2) {
+__device__ __forceinline__ float trilinear(const LevelLds &d, float u0, float u1, float u2) {
     int i0, i1, i2;
     float f0, f1, f2;
-    cell_of(u0, n0, i0, f0);
-    cell_of(u1, n1, i1, f1);
-    cell_of(u2, n2, i2, f2);
-    const uint32_t row = (uint32_t)n0, slice = (uint32_t)n0 * (uint32_t)(n1 - 1);
-    const float4 *q = quad + ((uint32_t)i2 * slice + (uint32_t)i1 * row + (uint32_t)i0);
+    cell_of(u0, d.cmax0, i0, f0);
+    cell_of(u1, d.cmax1, i1, f1);
+    cell_of(u2, d.cmax2, i2, f2);
+    const float4 *q = d.quad + ((uint32_t)i2 * d.slice + (uint32_t)i1 * d.row + (uint32_t)i0);
     const float4 a = q[0], b = q[1];
     const float v000 = a.x, v010 = a.y, v001 = a.z, v011 = a.w;
     const float v100 = b.x, v110 = b.y, v101 = b.z, v111 = b.w;
-    float c00 = fmaf(f0, v100 - v000, v000);
-    float c10 = fmaf(f0, v110 - v010, v010);
-    float c01 = fmaf(f0, v101 - v001, v001);
-    float c11 = fmaf(f0, v111 - v011, v011);
-    float c0 = fmaf(f1, c10 - c00, c00);
-    float c1 = fmaf(f1, c11 - c01, c01);
+    const float c00 = fmaf(f0, v100 - v000, v000);
+    const float c10 = fmaf(f0, v110 - v010, v010);
+    const float c01 = fmaf(f0, v101 - v001, v001);
+    const float c11 = fmaf(f0, v111 - v011, v011);
+    const float c0 = fmaf(f1, c10 - c00, c00);
+    const float c1 = fmaf(f1, c11 - c01, c01);
     return fmaf(f2, c1 - c0, c0);
 }
 
-// Finest level whose box shrunk by one voxel holds x (the coarsest level with its
-// full box); returns -1 outside the coarsest box. Fills the level and x's grid
-// coordinates on it.
-__device__ __forceinline__ int select_level(const TraceArgs &a, float x0, float x1, float x2,
-                                            LevelView &lv, float &u0, float &u1, float &u2) {
-#pragma unroll
-    for (int L = 0; L < kMaxLevels; ++L) {
-        if (L < a.nl) {
-            const DevLevel &d = a.lv[L];
-            const bool inner = L < a.nl - 1;
-            const float lo = inner ? 1.0f : 0.0f;
-            const int shrink = inner ? 2 : 1;
-            float v0 = (x0 - d.org0) * d.inv;
-            float v1 = (x1 - d.org1) * d.inv;
-            float v2 = (x2 - d.org2) * d.inv;
-            bool in = v0 >= lo && v0 <= (float)(d.n0 - shrink) && v1 >= lo &&
-                      v1 <= (float)(d.n1 - shrink) && v2 >= lo && v2 <= (float)(d.n2 - shrink);
-            if (in) {
-                level_view(d, lv);
-                u0 = v0; u1 = v1; u2 = v2;
-                return L;
-            }
-        }
-    }
-    return -1;
+__device__ __forceinline__ float sample_at(const LevelLds &d, float p0, float p1, float p2) {
+    return trilinear(d, (p0 - d.org0) * d.inv, (p1 - d.org1) * d.inv, (p2 - d.org2) * d.inv);
 }
 
-__device__ __forceinline__ float sample_at(const LevelView &lv, float p0, float p1, float p2) {
-    return trilinear(lv.quad, lv.n0, lv.n1, lv.n2, (p0 - lv.org0) * lv.inv,
-                     (p1 - lv.org1) * lv.inv, (p2 - lv.org2) * lv.inv);
+// Finest level whose box, shrunk by one voxel (the coarsest level: its full box),
+// holds x; -1 outside the coarsest box. The test "grid coordinate within [lo, hi]"
+// is made on x itself against per-level bounds: u = (x - org) * inv is monotone in x,
+// so the host finds the exact binary32 thresholds once and the result is the same.
+__device__ __forceinline__ int select_level(const TraceArgs &a, float x0, float x1, float x2) {
+    int L = -1;
+#pragma unroll
+    for (int l = kMaxLevels - 1; l >= 0; --l) {
+        if (l < a.nl) {
+            const DevLevel &d = a.lv[l];
+            const bool in = (x0 >= d.xlo0) & (x0 <= d.xhi0) & (x1 >= d.xlo1) & (x1 <= d.xhi1) &
+                            (x2 >= d.xlo2) & (x2 <= d.xhi2);
+            L = in ? l : L;
+        }
+    }
+    return L;
 }
 
 // Central differences at +-spacing/2 on the hit's level, normalised.
-__device__ __forceinline__ void hit_normal(const LevelView &lv, float x0, float x1, float x2,
+__device__ __forceinline__ void hit_normal(const LevelLds &d, float x0, float x1, float x2,
                                            float w0, float w1, float w2,
                                            float &n0, float &n1, float &n2) {
-    const float h = lv.half;
+    const float h = d.half;
     float g[3];
-#pragma unroll 1
+#pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
         const float p0 = x0 + (ax == 0 ? h : 0.0f), m0 = x0 - (ax == 0 ? h : 0.0f);
         const float p1 = x1 + (ax == 1 ? h : 0.0f), m1 = x1 - (ax == 1 ? h : 0.0f);
         const float p2 = x2 + (ax == 2 ? h : 0.0f), m2 = x2 - (ax == 2 ? h : 0.0f);
-        g[ax] = sample_at(lv, p0, p1, p2) - sample_at(lv, m0, m1, m2);
+        g[ax] = sample_at(d, p0, p1, p2) - sample_at(d, m0, m1, m2);
     }
     const float g0 = g[0], g1 = g[1], g2 = g[2];
-    float len2 = fmaf(g2, g2, fmaf(g1, g1, g0 * g0));
+    const float len2 = fmaf(g2, g2, fmaf(g1, g1, g0 * g0));
     if (!(len2 >= 1e-24f)) { n0 = -w0; n1 = -w1; n2 = -w2; return; }
-    float inv = 1.0f / sqrtf(len2);
+    const float inv = 1.0f / sqrtf(len2);
     n0 = g0 * inv; n1 = g1 * inv; n2 = g2 * inv;
+}
+
+// One sample of the fixed sphere-trace sequence for a ray o + t w at sample k.
+// Returns the outcome code when the ray stops here (steps in *steps), -1 otherwise
+// (t and k are then advanced). x and the level of the sample are returned too.
+template <bool kPrimary>
+__device__ __forceinline__ int trace_step(const TraceArgs &a, const LevelLds *s_lv, float o0,
+                                          float o1, float o2, float w0, float w1, float w2,
+                                          float &t, int &k, float &x0, float &x1, float &x2,
+                                          int &level, int &steps) {
+    if (t > a.t_max) { steps = k; return kMissTmax; }
+    x0 = fmaf(t, w0, o0); x1 = fmaf(t, w1, o1); x2 = fmaf(t, w2, o2);
+    level = select_level(a, x0, x1, x2);
+    if (level < 0) { steps = k; return kMissExit; }
+    const LevelLds &d = s_lv[level];
+    const float dist = trilinear(d, (x0 - d.org0) * d.inv, (x1 - d.org1) * d.inv,
+                                 (x2 - d.org2) * d.inv);
+    if (kPrimary && k == 0 && dist < 0.0f) { steps = 1; return kInside; }
+    if (dist < a.eps) { steps = k + 1; return kHit; }
+    t = fmaf(a.relax, dist, t);
+    ++k;
+    if (k == a.max_steps) { steps = k; return kHitExhausted; }
+    return -1;
 }
 
 // ----------------------------------------------------------- radiometry -----
@@ -132,9 +162,9 @@ __device__ __forceinline__ float3 interp_irradiance(const float *__restrict__ at
                                                    float x2, float n0, float n1, float n2) {
     int b0, b1, b2;
     float f0, f1, f2;
-    cell_of((x0 - pg.org0) * pg.inv0, pg.n0, b0, f0);
-    cell_of((x1 - pg.org1) * pg.inv1, pg.n1, b1, f1);
-    cell_of((x2 - pg.org2) * pg.inv2, pg.n2, b2, f2);
+    cell_of((x0 - pg.org0) * pg.inv0, (float)(pg.n0 - 2), b0, f0);
+    cell_of((x1 - pg.org1) * pg.inv1, (float)(pg.n1 - 2), b1, f1);
+    cell_of((x2 - pg.org2) * pg.inv2, (float)(pg.n2 - 2), b2, f2);
     float l1 = fabsf(n0) + fabsf(n1) + fabsf(n2);
     float u = n0 / l1, v = n1 / l1;
     if (n2 < 0.0f) {
@@ -153,8 +183,9 @@ __device__ __forceinline__ float3 interp_irradiance(const float *__restrict__ at
     const float w00 = (1.0f - fu) * (1.0f - fv), w10 = fu * (1.0f - fv);
     const float w01 = (1.0f - fu) * fv, w11 = fu * fv;
     float3 acc = make_float3(0.0f, 0.0f, 0.0f);
-    // one probe per iteration keeps 12 loads in flight rather than 96
-#pragma unroll 1
+    // four probes per iteration: 48 loads in flight, a quarter of the registers of a
+    // full unroll
+#pragma unroll 4
     for (int c8 = 0; c8 < 8; ++c8) {
         const int dx = c8 & 1, dy = (c8 >> 1) & 1, dz = c8 >> 2;
         const float wp = (dx ? f0 : 1.0f - f0) * (dy ? f1 : 1.0f - f1) * (dz ? f2 : 1.0f - f2);
@@ -168,41 +199,31 @@ __device__ __forceinline__ float3 interp_irradiance(const float *__restrict__ at
     return acc;
 }
 
-__device__ __forceinline__ float3 albedo_at(const TraceArgs &a, const LevelView &lv, float x0,
+__device__ __forceinline__ float3 albedo_at(const TraceArgs &a, const LevelLds &d, float x0,
                                             float x1, float x2) {
-    if (!lv.alb) return make_float3(a.alb0, a.alb1, a.alb2);
+    if (!d.alb) return make_float3(a.alb0, a.alb1, a.alb2);
     int i0, i1, i2;
     float f0, f1, f2;
-    cell_of((x0 - lv.org0) * lv.inv, lv.n0, i0, f0);
-    cell_of((x1 - lv.org1) * lv.inv, lv.n1, i1, f1);
-    cell_of((x2 - lv.org2) * lv.inv, lv.n2, i2, f2);
-    const uint32_t sy = (uint32_t)lv.n0, sz = (uint32_t)lv.n0 * (uint32_t)lv.n1;
-    const float *p = lv.alb + 3u * ((uint32_t)i2 * sz + (uint32_t)i1 * sy + (uint32_t)i0);
+    cell_of((x0 - d.org0) * d.inv, d.cmax0, i0, f0);
+    cell_of((x1 - d.org1) * d.inv, d.cmax1, i1, f1);
+    cell_of((x2 - d.org2) * d.inv, d.cmax2, i2, f2);
+    const uint32_t sy = d.arow, sz = d.aslice;
+    const float *p = d.alb + 3u * ((uint32_t)i2 * sz + (uint32_t)i1 * sy + (uint32_t)i0);
     float out[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        float v000 = p[c], v100 = p[3 + c], v010 = p[3 * sy + c], v110 = p[3 * (sy + 1) + c];
-        float v001 = p[3 * sz + c], v101 = p[3 * (sz + 1) + c];
-        float v011 = p[3 * (sz + sy) + c], v111 = p[3 * (sz + sy + 1) + c];
-        float c00 = fmaf(f0, v100 - v000, v000), c10 = fmaf(f0, v110 - v010, v010);
-        float c01 = fmaf(f0, v101 - v001, v001), c11 = fmaf(f0, v111 - v011, v011);
-        float c0 = fmaf(f1, c10 - c00, c00), c1 = fmaf(f1, c11 - c01, c01);
+        const float v000 = p[c], v100 = p[3 + c], v010 = p[3 * sy + c], v110 = p[3 * (sy + 1) + c];
+        const float v001 = p[3 * sz + c], v101 = p[3 * (sz + 1) + c];
+        const float v011 = p[3 * (sz + sy) + c], v111 = p[3 * (sz + sy + 1) + c];
+        const float c00 = fmaf(f0, v100 - v000, v000), c10 = fmaf(f0, v110 - v010, v010);
+        const float c01 = fmaf(f0, v101 - v001, v001), c11 = fmaf(f0, v111 - v011, v011);
+        const float c0 = fmaf(f1, c10 - c00, c00), c1 = fmaf(f1, c11 - c01, c01);
         out[c] = fmaf(f2, c1 - c0, c0);
     }
     return make_float3(out[0], out[1], out[2]);
 }
 
 // ------------------------------------------------------------- kernels ------
-
-// Level view of the hit point's level: select_level(x) again (the same x gives the
-// same level), which keeps the per-level kernel arguments in registers.
-__device__ __forceinline__ LevelView hit_level_view(const TraceArgs &a, float x0, float x1,
-                                                    float x2) {
-    LevelView v;
-    float u0, u1, u2;
-    (void)select_level(a, x0, x1, x2, v, u0, u1, u2);
-    return v;
-}
 
 __device__ __forceinline__ void write_ray(const TraceArgs &a, int ray, float4 out, int kind,
                                           int level, int steps, int vis, int shadow_steps,
@@ -216,153 +237,233 @@ __device__ __forceinline__ void write_ray(const TraceArgs &a, int ray, float4 ou
     }
 }
 
-enum : int { kIdle = 0, kPrimary = 1, kShadow = 2, kPendNormal = 3, kPendShade = 4 };
-constexpr int kChunk = 64;        // rays taken from the global counter at a time
-constexpr int kRefillBelow = 48;  // run the batched phases when fewer lanes are stepping
+// Primary-ray hit record packing: outcome | level << 4 | steps << 8.
+__device__ __forceinline__ int pack_hit(int kind, int level, int steps) {
+    return kind | (level << 4) | (steps << 8);
+}
 
-// Persistent, wave-compacted trace: every lane of a wave owns one ray at a time and
-// advances it one sphere-trace sample per iteration. When fewer than kRefillBelow
-// lanes are still stepping, the wave runs the divergent per-ray work in batches
-// (hit normal + shadow-ray set-up, then shading and payload write) and refills idle
-// lanes with new rays from a global counter (kChunk rays per atomic). Each ray's
-// arithmetic is the fixed sequence of trace_ray/hit_normal, so results do not depend
-// on which lane or wave processed it. Every wave exits once the counter has passed
-// the last ray and its lanes are idle; each ray takes at most 2*max_steps samples.
-__global__ __launch_bounds__(256) void trace_kernel(TraceArgs a) {
+// Per-wave staging of hit-queue entries (ray, bits of t, packed info, 0) in LDS;
+// flushed to the global queue 64 at a time with one atomic.
+__device__ __forceinline__ void flush_hits(const TraceArgs &a, int4 *buf, int count) {
+    if (count == 0) return;
+    int base = 0;
+    if (__lane_id() == 0) base = atomicAdd(a.counter + 2, count);
+    base = __builtin_amdgcn_readfirstlane(base);
     const int lane = (int)__lane_id();
+    if (lane < count) a.hitq[base + lane] = buf[lane];
+    __builtin_amdgcn_wave_barrier();
+}
+
+constexpr int kChunk = 256;       // primary rays claimed from the global counter at a time
+constexpr int kHitChunk = 64;     // queued hits claimed at a time (spreads them over all waves)
+constexpr int kRefillBelow = 40;  // refill / run batched work when fewer lanes are stepping
+
+// Wave-level work feeder: claims `chunk` consecutive items per atomic and hands them
+// to idle lanes in order. All members are wave-uniform.
+template <int kChunkSize>
+struct Feeder {
+    int next = 0, end = 0;
+    bool exhausted = false;
+    // Returns the number of items given out; the rank-th idle lane takes first + rank.
+    __device__ __forceinline__ int claim(int *counter, int total, int want, int &first) {
+        if (next >= end) {
+            int base = 0;
+            if (__lane_id() == 0) base = atomicAdd(counter, kChunkSize);
+            base = __builtin_amdgcn_readfirstlane(base);
+            if (base >= total) { exhausted = true; return 0; }
+            next = base;
+            end = min(base + kChunkSize, total);
+        }
+        const int n = min(want, end - next);
+        first = next;
+        next += n;
+        return n;
+    }
+};
+
+// Primary sphere trace, persistent and wave-compacted: each lane owns one ray and
+// takes one sample per iteration; when fewer than kRefillBelow lanes are stepping,
+// idle lanes take the next rays (kChunk per global atomic, consecutive rays of the
+// same probes). Misses and probes inside geometry write their payload here; hits are
+// appended to a compact queue (ray, t, outcome, level, steps) for hits_kernel, staged
+// per wave in LDS. Each ray's arithmetic is the fixed sequence of trace_step,
+// whatever lane or wave runs it. Every wave exits once the counter has passed the
+// last ray and its lanes are idle, after flushing its staged hits.
+__global__ __launch_bounds__(256) void primary_kernel(TraceArgs a) {
+    __shared__ LevelLds s_lv[kMaxLevels];
+    __shared__ int4 s_hits[4][64];
+    load_levels(a, s_lv);
+    const int lane = (int)__lane_id();
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    int staged = 0;  // wave-uniform count of entries in s_hits[wave]
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const int total = a.P * a.R;
-    int chunk_next = 0, chunk_end = 0;
-    bool exhausted = false;
-
-    int mode = kIdle, ray = 0;
+    Feeder<kChunk> feed;
+    bool active = false;
+    int ray = 0, k = 0;
     float o0 = 0, o1 = 0, o2 = 0, w0 = 0, w1 = 0, w2 = 0, t = 0;
-    int k = 0;
-    // primary hit kept for shading
-    float hx0 = 0, hx1 = 0, hx2 = 0, ht = 0;
-    int hkind = 0, hsteps = 0, hlevel = 0;
-    float n0 = 0, n1 = 0, n2 = 0;
-    int vis = -1;
-
     while (true) {
-        uint64_t stepping = __ballot(mode == kPrimary || mode == kShadow);
+        uint64_t stepping = __ballot(active);
         if (__popcll(stepping) < kRefillBelow) {
-            if (__ballot(mode == kPendNormal)) {
-                if (mode == kPendNormal) {
-                    const LevelView lv = hit_level_view(a, hx0, hx1, hx2);
-                    hit_normal(lv, hx0, hx1, hx2, w0, w1, w2, n0, n1, n2);
-                    const float ndl = fmaf(n2, a.l2, fmaf(n1, a.l1, n0 * a.l0));
-                    if (ndl > 0.0f) {
-                        o0 = fmaf(n0, a.bias, hx0);
-                        o1 = fmaf(n1, a.bias, hx1);
-                        o2 = fmaf(n2, a.bias, hx2);
-                        w0 = a.l0; w1 = a.l1; w2 = a.l2;
-                        t = 0.0f;
-                        k = 0;
-                        mode = kShadow;
-                    } else {
-                        vis = -1;
-                        k = 0;
-                        mode = kPendShade;
-                    }
-                }
-            }
-            if (__ballot(mode == kPendShade)) {
-                if (mode == kPendShade) {
-                    // k holds the shadow ray's step count here
-                    const LevelView lv = hit_level_view(a, hx0, hx1, hx2);
-                    const float ndl = fmaf(n2, a.l2, fmaf(n1, a.l1, n0 * a.l0));
-                    const float lit = vis == 1 ? ndl : 0.0f;
-                    const float3 alb = albedo_at(a, lv, hx0, hx1, hx2);
-                    float3 ind = make_float3(0.0f, 0.0f, 0.0f);
-                    if (a.gain != 0.0f)
-                        ind = interp_irradiance(a.prev_irr, a.irr_res, a.pg, hx0, hx1, hx2, n0,
-                                                n1, n2);
-                    const float inv_pi = 0.318309886183790671538f;
-                    float4 out;
-                    out.x = alb.x * inv_pi * (a.rad0 * lit + a.gain * ind.x);
-                    out.y = alb.y * inv_pi * (a.rad1 * lit + a.gain * ind.y);
-                    out.z = alb.z * inv_pi * (a.rad2 * lit + a.gain * ind.z);
-                    out.w = ht;
-                    write_ray(a, ray, out, hkind, hlevel, hsteps, vis, k, n0, n1, n2);
-                    mode = kIdle;
-                }
-            }
-            uint64_t idle = __ballot(mode == kIdle);
-            while (idle != 0 && !exhausted) {
-                if (chunk_next >= chunk_end) {
-                    int base = 0;
-                    if (lane == 0) base = atomicAdd(a.counter, kChunk);
-                    base = __builtin_amdgcn_readfirstlane(base);
-                    if (base >= total) {
-                        exhausted = true;
-                        break;
-                    }
-                    chunk_next = base;
-                    chunk_end = min(base + kChunk, total);
-                }
-                const int avail = chunk_end - chunk_next;
+            uint64_t idle = ~stepping;
+            while (idle != 0 && !feed.exhausted) {
+                int first = 0;
+                const int n = feed.claim(a.counter, total, __popcll(idle), first);
                 const int rank = __popcll(idle & below);
-                if (mode == kIdle && rank < avail) {
-                    ray = chunk_next + rank;
-                    const int p = ray / a.R;
-                    const int i = ray - p * a.R;
+                if (!active && rank < n) {
+                    ray = first + rank;
+                    const int p = ray / a.R, i = ray - (ray / a.R) * a.R;
                     o0 = a.probe_pos[3 * p]; o1 = a.probe_pos[3 * p + 1]; o2 = a.probe_pos[3 * p + 2];
                     w0 = a.dirs[3 * i]; w1 = a.dirs[3 * i + 1]; w2 = a.dirs[3 * i + 2];
                     t = 0.0f;
                     k = 0;
-                    mode = kPrimary;
+                    active = true;
                 }
-                chunk_next += min(avail, (int)__popcll(idle));
-                idle = __ballot(mode == kIdle);
+                idle = __ballot(!active);
             }
-            stepping = __ballot(mode == kPrimary || mode == kShadow);
-            if (stepping == 0) break;  // counter exhausted and every lane idle
+            stepping = __ballot(active);
+            if (stepping == 0) {  // counter exhausted and every lane idle
+                flush_hits(a, s_hits[wave], staged);
+                break;
+            }
         }
-
-        if (mode == kPrimary || mode == kShadow) {
-            // one sample of the fixed sphere-trace sequence
-            int kind = -1, steps = 0, level = 0;
-            float tt = t, x0 = 0, x1 = 0, x2 = 0;
-            if (t > a.t_max) {
-                kind = kMissTmax; steps = k;
-            } else {
-                x0 = fmaf(t, w0, o0); x1 = fmaf(t, w1, o1); x2 = fmaf(t, w2, o2);
-                LevelView lv;
-                float u0, u1, u2;
-                level = select_level(a, x0, x1, x2, lv, u0, u1, u2);
-                if (level < 0) {
-                    kind = kMissExit; steps = k;
+        bool hit_now = false;
+        int4 entry = make_int4(0, 0, 0, 0);
+        if (active) {
+            const float tt = t;
+            float x0, x1, x2;
+            int level = 0, steps = 0;
+            const int kind = trace_step<true>(a, s_lv, o0, o1, o2, w0, w1, w2, t, k, x0, x1, x2,
+                                              level, steps);
+            if (kind >= 0) {
+                if (kind == kHit || kind == kHitExhausted) {
+                    hit_now = true;
+                    entry = make_int4(ray, __float_as_int(tt), pack_hit(kind, level, steps), 0);
                 } else {
-                    const float d = trilinear(lv.quad, lv.n0, lv.n1, lv.n2, u0, u1, u2);
-                    if (mode == kPrimary && k == 0 && d < 0.0f) {
-                        kind = kInside; steps = 1;
-                    } else if (d < a.eps) {
-                        kind = kHit; steps = k + 1;
-                    } else {
-                        t = fmaf(a.relax, d, t);
-                        ++k;
-                        if (k == a.max_steps) { kind = kHitExhausted; steps = k; }
+                    const float4 out = kind == kInside ? make_float4(0.0f, 0.0f, 0.0f, 0.0f)
+                                                       : make_float4(a.sky0, a.sky1, a.sky2, a.t_max);
+                    write_ray(a, ray, out, kind, 0, steps, -1, 0, 0.0f, 0.0f, 0.0f);
+                }
+                active = false;
+            }
+        }
+        const uint64_t hm = __ballot(hit_now);
+        if (hm) {
+            const int n = __popcll(hm);
+            if (staged + n > 64) {
+                flush_hits(a, s_hits[wave], staged);
+                staged = 0;
+            }
+            if (hit_now) s_hits[wave][staged + __popcll(hm & below)] = entry;
+            __builtin_amdgcn_wave_barrier();
+            staged += n;
+            if (staged == 64) {
+                flush_hits(a, s_hits[wave], staged);
+                staged = 0;
+            }
+        }
+    }
+}
+
+enum : int { kIdle = 0, kShadow = 1, kNew = 2, kPendShade = 3 };
+constexpr int kShadeBatch = 16;   // shade when this many lanes wait (or stepping runs low)
+
+// Hit rays from the queue the primary trace built: idle lanes take the next entries
+// (kHitChunk per global atomic), then per lane: hit point and normal (batched for all
+// newly assigned lanes), the SDF shadow ray toward the light (wave-compacted like the
+// primary trace), and shading -- albedo, sun, multi-bounce lookup -- batched when
+// kShadeBatch lanes wait or stepping runs low.
+__global__ __launch_bounds__(256) void hits_kernel(TraceArgs a) {
+    __shared__ LevelLds s_lv[kMaxLevels];
+    load_levels(a, s_lv);
+    const int lane = (int)__lane_id();
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const int total = a.counter[2];  // queue length, final once primary_kernel has finished
+    Feeder<kHitChunk> feed;
+
+    int mode = kIdle, ray = 0, info = 0, k = 0, vis = -1;
+    float ht = 0, hx0 = 0, hx1 = 0, hx2 = 0, n0 = 0, n1 = 0, n2 = 0;
+    float o0 = 0, o1 = 0, o2 = 0, t = 0;
+    while (true) {
+        uint64_t stepping = __ballot(mode == kShadow);
+        const int waiting = __popcll(__ballot(mode == kPendShade));
+        if (__popcll(stepping) < kRefillBelow || waiting >= kShadeBatch) {
+            for (int round = 0; round < 2; ++round) {
+                if (__ballot(mode == kPendShade)) {
+                    if (mode == kPendShade) {
+                        // k holds the shadow ray's step count here
+                        const LevelLds &d = s_lv[(info >> 4) & 15];
+                        const float ndl = fmaf(n2, a.l2, fmaf(n1, a.l1, n0 * a.l0));
+                        const float lit = vis == 1 ? ndl : 0.0f;
+                        const float3 alb = albedo_at(a, d, hx0, hx1, hx2);
+                        float3 ind = make_float3(0.0f, 0.0f, 0.0f);
+                        if (a.gain != 0.0f)
+                            ind = interp_irradiance(a.prev_irr, a.irr_res, a.pg, hx0, hx1, hx2, n0,
+                                                    n1, n2);
+                        const float inv_pi = 0.318309886183790671538f;
+                        float4 out;
+                        out.x = alb.x * inv_pi * (a.rad0 * lit + a.gain * ind.x);
+                        out.y = alb.y * inv_pi * (a.rad1 * lit + a.gain * ind.y);
+                        out.z = alb.z * inv_pi * (a.rad2 * lit + a.gain * ind.z);
+                        out.w = ht;
+                        write_ray(a, ray, out, info & 15, (info >> 4) & 15, info >> 8, vis, k, n0,
+                                  n1, n2);
+                        mode = kIdle;
+                    }
+                }
+                if (round == 1) break;
+                // refill idle lanes with entries of the hit queue
+                uint64_t idle = __ballot(mode == kIdle);
+                while (idle != 0 && !feed.exhausted) {
+                    int first = 0;
+                    const int n = feed.claim(a.counter + 1, total, __popcll(idle), first);
+                    const int rank = __popcll(idle & below);
+                    if (mode == kIdle && rank < n) {
+                        const int4 e = a.hitq[first + rank];
+                        ray = e.x;
+                        ht = __int_as_float(e.y);
+                        info = e.z;
+                        mode = kNew;
+                    }
+                    idle = __ballot(mode == kIdle);
+                }
+                // newly assigned hits: hit point, normal, shadow ray set-up
+                if (__ballot(mode == kNew)) {
+                    if (mode == kNew) {
+                        const int p = ray / a.R, i = ray - (ray / a.R) * a.R;
+                        const float po0 = a.probe_pos[3 * p], po1 = a.probe_pos[3 * p + 1],
+                                    po2 = a.probe_pos[3 * p + 2];
+                        const float w0 = a.dirs[3 * i], w1 = a.dirs[3 * i + 1], w2 = a.dirs[3 * i + 2];
+                        hx0 = fmaf(ht, w0, po0); hx1 = fmaf(ht, w1, po1); hx2 = fmaf(ht, w2, po2);
+                        hit_normal(s_lv[(info >> 4) & 15], hx0, hx1, hx2, w0, w1, w2, n0, n1, n2);
+                        const float ndl = fmaf(n2, a.l2, fmaf(n1, a.l1, n0 * a.l0));
+                        if (ndl > 0.0f) {
+                            o0 = fmaf(n0, a.bias, hx0);
+                            o1 = fmaf(n1, a.bias, hx1);
+                            o2 = fmaf(n2, a.bias, hx2);
+                            t = 0.0f;
+                            k = 0;
+                            mode = kShadow;
+                        } else {
+                            vis = -1;
+                            k = 0;
+                            mode = kPendShade;
+                        }
                     }
                 }
             }
+            stepping = __ballot(mode == kShadow);
+            if (stepping == 0 && feed.exhausted) break;
+        }
+        if (mode == kShadow) {
+            float x0, x1, x2;
+            int level = 0, steps = 0;
+            const int kind = trace_step<false>(a, s_lv, o0, o1, o2, a.l0, a.l1, a.l2, t, k, x0,
+                                               x1, x2, level, steps);
             if (kind >= 0) {
-                const bool is_hit = kind == kHit || kind == kHitExhausted;
-                if (mode == kShadow) {
-                    vis = is_hit ? 0 : 1;
-                    k = steps;
-                    mode = kPendShade;
-                } else if (is_hit) {
-                    hx0 = x0; hx1 = x1; hx2 = x2; ht = tt;
-                    hkind = kind; hsteps = steps; hlevel = level;
-                    mode = kPendNormal;
-                } else {
-                    const float4 out = kind == kInside
-                                           ? make_float4(0.0f, 0.0f, 0.0f, 0.0f)
-                                           : make_float4(a.sky0, a.sky1, a.sky2, a.t_max);
-                    write_ray(a, ray, out, kind, 0, steps, -1, 0, 0.0f, 0.0f, 0.0f);
-                    mode = kIdle;
-                }
+                vis = (kind == kHit || kind == kHitExhausted) ? 0 : 1;
+                k = steps;
+                mode = kPendShade;
             }
         }
     }
@@ -405,7 +506,7 @@ __global__ __launch_bounds__(256) void tables_kernel(TableArgs a) {
         part += w;
     }
     if (is_dirs) {
-        if (tid == 0 && a.counter) *a.counter = 0;  // trace_kernel's ray counter
+        if (tid < 3 && a.counter) a.counter[tid] = 0;  // the trace kernels' counters
         return;
     }
     red[tid] = part;
@@ -635,9 +736,11 @@ hipError_t launch_tables(const TableArgs &a, hipStream_t s) {
 
 // Persistent grid: as many 256-thread blocks as fit on the device at once (fewer
 // when there are fewer rays).
-int trace_grid_blocks(int device, int64_t rays) {
+// Persistent grids: as many 256-thread blocks as fit on the device at once (fewer
+// when there are fewer rays).
+static int persistent_blocks(const void *kernel, int device, int64_t rays) {
     int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_kernel, 256, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess)
         per_cu = 1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
         cus = 1;
@@ -646,9 +749,22 @@ int trace_grid_blocks(int device, int64_t rays) {
     return (int)(needed < resident ? needed : resident);
 }
 
-hipError_t launch_trace(const TraceArgs &a, int blocks, hipStream_t s) {
-    if ((int64_t)a.P * a.R == 0 || blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(trace_kernel, dim3(blocks), dim3(256), 0, s, a);
+TraceGrid trace_grid(int device, int64_t rays) {
+    TraceGrid g;
+    g.primary_blocks = persistent_blocks((const void *)primary_kernel, device, rays);
+    g.hits_blocks = persistent_blocks((const void *)hits_kernel, device, rays);
+    return g;
+}
+
+hipError_t launch_primary(const TraceArgs &a, const TraceGrid &g, hipStream_t s) {
+    if ((int64_t)a.P * a.R == 0) return hipSuccess;
+    hipLaunchKernelGGL(primary_kernel, dim3(g.primary_blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_hits(const TraceArgs &a, const TraceGrid &g, hipStream_t s) {
+    if ((int64_t)a.P * a.R == 0) return hipSuccess;
+    hipLaunchKernelGGL(hits_kernel, dim3(g.hits_blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -7,6 +7,7 @@
 #include "sdfddgi.h"
 #include "internal.h"
 
+#include <cfloat>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -22,6 +23,7 @@ thread_local std::string g_create_error;
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kTimingRing = 256;
+constexpr int kEvents = 5;
 
 // ---------------------------------------------------------- frame constants --
 
@@ -120,13 +122,14 @@ struct sdfddgi_ctx {
     int cur = 0;
     uint8_t *reject = nullptr;
     int *counter = nullptr;
-    int trace_blocks = 0;
+    int4 *hitq = nullptr;
+    TraceGrid grid;
     float4 *payload = nullptr;
     int *records = nullptr;
     bool have_frame = false, have_records = false;
-    // Timing: four events per frame (before tables, after tables, after trace,
-    // after blend) in a ring; sdfddgi_get_kernel_times averages the frames
-    // recorded since its previous call.
+    // Timing: kEvents events per frame (before tables, after tables, after the
+    // primary trace, after the hit kernel, after the blend) in a ring;
+    // sdfddgi_get_kernel_times averages the frames recorded since its previous call.
     hipEvent_t *ev_ring = nullptr;
     int ring_head = 0;
     int64_t timed_frames = 0;
@@ -166,11 +169,11 @@ void free_all(sdfddgi_ctx *c) {
     }
     void *bufs[] = {c->probe_pos, c->base_dirs, c->texel_i, c->texel_d, c->dirs, c->wt_i,
                     c->wt_d, c->norm_i, c->norm_d, c->irr[0], c->irr[1], c->depth[0],
-                    c->depth[1], c->reject, c->counter, c->payload, c->records};
+                    c->depth[1], c->reject, c->counter, c->hitq, c->payload, c->records};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (c->ev_ring) {
-        for (int k = 0; k < 4 * kTimingRing; ++k)
+        for (int k = 0; k < kEvents * kTimingRing; ++k)
             if (c->ev_ring[k]) (void)hipEventDestroy(c->ev_ring[k]);
         delete[] c->ev_ring;
     }
@@ -234,6 +237,53 @@ sdfddgi_status validate(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_grid *p
     return SDFDDGI_OK;
 }
 
+// Monotone integer key of a binary32 value (orders all finite floats).
+int32_t float_key(float f) {
+    int32_t b;
+    std::memcpy(&b, &f, 4);
+    return b >= 0 ? b : -(b & 0x7fffffff);
+}
+
+float key_float(int32_t k) {
+    int32_t b = k >= 0 ? k : (int32_t)(0x80000000u | (uint32_t)(-k));
+    float f;
+    std::memcpy(&f, &b, 4);
+    return f;
+}
+
+// Grid coordinate of x exactly as the kernels compute it.
+float grid_coord(float x, float org, float inv) {
+    volatile float d = x - org;  // one binary32 subtraction, then one multiplication
+    return d * inv;
+}
+
+// Smallest float x with grid_coord(x) >= lo (the map is monotone in x); -inf / +inf
+// when every / no finite float qualifies.
+float lower_bound_x(float org, float inv, float lo) {
+    int64_t a = float_key(-FLT_MAX), b = float_key(FLT_MAX);
+    if (grid_coord(key_float((int32_t)a), org, inv) >= lo) return -INFINITY;
+    if (!(grid_coord(key_float((int32_t)b), org, inv) >= lo)) return INFINITY;
+    while (b - a > 1) {
+        const int32_t m = (int32_t)(a + (b - a) / 2);
+        if (grid_coord(key_float(m), org, inv) >= lo) b = m;
+        else a = m;
+    }
+    return key_float((int32_t)b);
+}
+
+// Largest float x with grid_coord(x) <= hi.
+float upper_bound_x(float org, float inv, float hi) {
+    int64_t a = float_key(-FLT_MAX), b = float_key(FLT_MAX);
+    if (grid_coord(key_float((int32_t)b), org, inv) <= hi) return INFINITY;
+    if (!(grid_coord(key_float((int32_t)a), org, inv) <= hi)) return -INFINITY;
+    while (b - a > 1) {
+        const int32_t m = (int32_t)(a + (b - a) / 2);
+        if (grid_coord(key_float(m), org, inv) <= hi) a = m;
+        else b = m;
+    }
+    return key_float((int32_t)a);
+}
+
 DevLevel dev_level(const sdfddgi_ctx *c, int L) {
     DevLevel d{};
     d.quad = c->quad[L];
@@ -246,6 +296,17 @@ DevLevel dev_level(const sdfddgi_ctx *c, int L) {
     d.org2 = (float)c->origin[L][2];
     d.inv = (float)(1.0 / c->spacing[L]);
     d.half = (float)(0.5 * c->spacing[L]);
+    const bool inner = L < c->nl - 1;
+    const float org[3] = {d.org0, d.org1, d.org2};
+    float lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) {
+        const float ulo = inner ? 1.0f : 0.0f;
+        const float uhi = (float)(c->n[L][k] - (inner ? 2 : 1));
+        lo[k] = lower_bound_x(org[k], d.inv, ulo);
+        hi[k] = upper_bound_x(org[k], d.inv, uhi);
+    }
+    d.xlo0 = lo[0]; d.xlo1 = lo[1]; d.xlo2 = lo[2];
+    d.xhi0 = hi[0]; d.xhi1 = hi[1]; d.xhi2 = hi[2];
     return d;
 }
 
@@ -458,15 +519,16 @@ sdfddgi_status sdfddgi_create(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_g
     }
     SDF_TRY(dev_alloc(&c->reject, P), "allocating reject flags");
     SDF_TRY(launch_fill_u8(c->reject, 1, P, c->stream), "launching fill");
-    SDF_TRY(dev_alloc(&c->counter, 1), "allocating ray counter");
+    SDF_TRY(dev_alloc(&c->counter, 3), "allocating ray counters");
+    SDF_TRY(dev_alloc(&c->hitq, (size_t)P * c->R), "allocating the hit queue");
     SDF_TRY(dev_alloc(&c->payload, (size_t)P * c->R), "allocating payload");
-    c->trace_blocks = trace_grid_blocks(dev, P * c->R);
+    c->grid = trace_grid(dev, P * c->R);
     if (params->flags & SDFDDGI_FLAG_RECORD_RAYS)
         SDF_TRY(dev_alloc(&c->records, (size_t)P * c->R * 8), "allocating ray records");
     if (params->flags & SDFDDGI_FLAG_TIMING) {
-        c->ev_ring = new (std::nothrow) hipEvent_t[4 * kTimingRing]();
+        c->ev_ring = new (std::nothrow) hipEvent_t[kEvents * kTimingRing]();
         if (!c->ev_ring) return bail(fail(nullptr, SDFDDGI_ENOMEM, "host allocation failed"));
-        for (int k = 0; k < 4 * kTimingRing; ++k)
+        for (int k = 0; k < kEvents * kTimingRing; ++k)
             SDF_TRY(hipEventCreate(&c->ev_ring[k]), "creating events");
     }
     SDF_TRY(hipStreamSynchronize(c->stream), "waiting for create");
@@ -520,8 +582,9 @@ sdfddgi_status sdfddgi_update_frame(sdfddgi_ctx *c, const sdfddgi_light *light,
     t.payload = c->payload;
     t.records = c->records;
     t.counter = c->counter;
+    t.hitq = c->hitq;
 
-    hipEvent_t *ev = c->ev_ring ? c->ev_ring + 4 * c->ring_head : nullptr;
+    hipEvent_t *ev = c->ev_ring ? c->ev_ring + kEvents * c->ring_head : nullptr;
     hipError_t e;
     if (ev && (e = hipEventRecord(ev[0], c->stream)) != hipSuccess)
         return hip_fail(c, e, "event");
@@ -529,13 +592,17 @@ sdfddgi_status sdfddgi_update_frame(sdfddgi_ctx *c, const sdfddgi_light *light,
         return hip_fail(c, e, "launching tables_kernel");
     if (ev && (e = hipEventRecord(ev[1], c->stream)) != hipSuccess)
         return hip_fail(c, e, "event");
-    if ((e = launch_trace(t, c->trace_blocks, c->stream)) != hipSuccess)
-        return hip_fail(c, e, "launching trace_kernel");
+    if ((e = launch_primary(t, c->grid, c->stream)) != hipSuccess)
+        return hip_fail(c, e, "launching primary_kernel");
     if (ev && (e = hipEventRecord(ev[2], c->stream)) != hipSuccess)
+        return hip_fail(c, e, "event");
+    if ((e = launch_hits(t, c->grid, c->stream)) != hipSuccess)
+        return hip_fail(c, e, "launching hits_kernel");
+    if (ev && (e = hipEventRecord(ev[3], c->stream)) != hipSuccess)
         return hip_fail(c, e, "event");
     if ((e = launch_blend(blend_args(c, c->payload), c->stream)) != hipSuccess)
         return hip_fail(c, e, "launching blend_kernel");
-    if (ev && (e = hipEventRecord(ev[3], c->stream)) != hipSuccess)
+    if (ev && (e = hipEventRecord(ev[4], c->stream)) != hipSuccess)
         return hip_fail(c, e, "event");
     if (ev) {
         c->ring_head = (c->ring_head + 1) % kTimingRing;
@@ -666,18 +733,18 @@ sdfddgi_status sdfddgi_ray_directions(uint64_t rotation_seed, int32_t rays, floa
 sdfddgi_status sdfddgi_get_kernel_times(sdfddgi_ctx *c, float *ms, int32_t count) {
     sdfddgi_status st = check_ctx(c);
     if (st != SDFDDGI_OK) return st;
-    if (!ms || count < 0 || count > 4) return fail(c, SDFDDGI_EINVAL, "bad output array");
+    if (!ms || count < 0 || count > kEvents) return fail(c, SDFDDGI_EINVAL, "bad output array");
     if (!c->ev_ring) return fail(c, SDFDDGI_ESTATE, "created without SDFDDGI_FLAG_TIMING");
     if (c->timed_frames == 0) return fail(c, SDFDDGI_ESTATE, "no timed frame since the last call");
     const int frames = (int)(c->timed_frames < kTimingRing ? c->timed_frames : kTimingRing);
     const int last = (c->ring_head + kTimingRing - 1) % kTimingRing;
-    hipError_t e = hipEventSynchronize(c->ev_ring[4 * last + 3]);
+    hipError_t e = hipEventSynchronize(c->ev_ring[kEvents * last + kEvents - 1]);
     if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
-    const int pairs[4][2] = {{0, 1}, {1, 2}, {2, 3}, {0, 3}};
-    double sum[4] = {0, 0, 0, 0};
+    const int pairs[kEvents][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {0, 4}};
+    double sum[kEvents] = {0, 0, 0, 0, 0};
     for (int f = 0; f < frames; ++f) {
-        const hipEvent_t *ev = c->ev_ring + 4 * ((last - f + kTimingRing) % kTimingRing);
-        for (int k = 0; k < 4; ++k) {
+        const hipEvent_t *ev = c->ev_ring + kEvents * ((last - f + kTimingRing) % kTimingRing);
+        for (int k = 0; k < kEvents; ++k) {
             float v = 0.0f;
             e = hipEventElapsedTime(&v, ev[pairs[k][0]], ev[pairs[k][1]]);
             if (e != hipSuccess) return hip_fail(c, e, "hipEventElapsedTime");

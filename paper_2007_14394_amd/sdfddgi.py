@@ -312,9 +312,9 @@ def sdfddgi_ray_directions(rotation_seed: int, rays: int) -> np.ndarray:
 
 
 def sdfddgi_get_kernel_times(ctx: Context):
-    ms = (ctypes.c_float * 4)()
-    _check(ctx, load_library().sdfddgi_get_kernel_times(ctx.handle, ms, 4))
-    return dict(tables=ms[0], trace=ms[1], blend=ms[2], frame=ms[3])
+    ms = (ctypes.c_float * 5)()
+    _check(ctx, load_library().sdfddgi_get_kernel_times(ctx.handle, ms, 5))
+    return dict(tables=ms[0], primary=ms[1], hits=ms[2], blend=ms[3], frame=ms[4])
 
 
 def sdfddgi_get_sizes(ctx: Context):
