@@ -45,6 +45,7 @@ struct TraceArgs {
     float sky0, sky1, sky2;
     float alb0, alb1, alb2;
     const float *probe_pos;     // [P][3]
+    const int *probe_order;     // [P] probes in Morton order of (x, y, z): the tracing order
     const float *dirs;          // [R][3]
     const float *prev_irr;      // previous irradiance atlas
     float4 *payload;            // [P*R]

@@ -283,8 +283,8 @@ struct Feeder {
 
 // Primary sphere trace, persistent and wave-compacted: each lane owns one ray and
 // takes one sample per iteration; when fewer than kRefillBelow lanes are stepping,
-// idle lanes take the next rays (kChunk per global atomic, consecutive rays of the
-// same probes). Misses and probes inside geometry write their payload here; hits are
+// idle lanes take the next rays (kChunk per global atomic: the rays of one probe,
+// probes visited in Morton order of their grid cell). Misses and probes inside geometry write their payload here; hits are
 // appended to a compact queue (ray, t, outcome, level, steps) for hits_kernel, staged
 // per wave in LDS. Each ray's arithmetic is the fixed sequence of trace_step,
 // whatever lane or wave runs it. Every wave exits once the counter has passed the
@@ -311,8 +311,12 @@ __global__ __launch_bounds__(256) void primary_kernel(TraceArgs a) {
                 const int n = feed.claim(a.counter, total, __popcll(idle), first);
                 const int rank = __popcll(idle & below);
                 if (!active && rank < n) {
-                    ray = first + rank;
-                    const int p = ray / a.R, i = ray - (ray / a.R) * a.R;
+                    // slot -> (probe in Morton order, ray): neighbouring slots trace
+                    // neighbouring probes, so the rays in flight share cache lines
+                    const int slot = first + rank;
+                    const int q = slot / a.R, i = slot - (slot / a.R) * a.R;
+                    const int p = a.probe_order[q];
+                    ray = p * a.R + i;
                     o0 = a.probe_pos[3 * p]; o1 = a.probe_pos[3 * p + 1]; o2 = a.probe_pos[3 * p + 2];
                     w0 = a.dirs[3 * i]; w1 = a.dirs[3 * i + 1]; w2 = a.dirs[3 * i + 2];
                     t = 0.0f;

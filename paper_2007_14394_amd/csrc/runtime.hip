@@ -7,6 +7,7 @@
 #include "sdfddgi.h"
 #include "internal.h"
 
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
 #include <cstdarg>
@@ -14,6 +15,8 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
+#include <vector>
 
 using namespace sdfddgi;
 
@@ -116,6 +119,7 @@ struct sdfddgi_ctx {
     int R = 0, Ti = 0, Td = 0, Tpi = 0, Tpd = 0;
     int64_t irr_floats = 0, depth_floats = 0;
     float *probe_pos = nullptr;
+    int *probe_order = nullptr;
     double *base_dirs = nullptr, *texel_i = nullptr, *texel_d = nullptr;
     float *dirs = nullptr, *wt_i = nullptr, *wt_d = nullptr, *norm_i = nullptr, *norm_d = nullptr;
     float *irr[2]{}, *depth[2]{};
@@ -167,7 +171,7 @@ void free_all(sdfddgi_ctx *c) {
         if (c->quad[L]) (void)hipFree(c->quad[L]);
         if (c->alb[L]) (void)hipFree(c->alb[L]);
     }
-    void *bufs[] = {c->probe_pos, c->base_dirs, c->texel_i, c->texel_d, c->dirs, c->wt_i,
+    void *bufs[] = {c->probe_pos, c->probe_order, c->base_dirs, c->texel_i, c->texel_d, c->dirs, c->wt_i,
                     c->wt_d, c->norm_i, c->norm_d, c->irr[0], c->irr[1], c->depth[0],
                     c->depth[1], c->reject, c->counter, c->hitq, c->payload, c->records};
     for (void *b : bufs)
@@ -479,6 +483,20 @@ sdfddgi_status sdfddgi_create(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_g
             h_pos[3 * p + k] = (float)(probes->origin[k] + probes->spacing[k] * (double)idx[k]);
     }
     for (int i = 0; i < c->R; ++i) fibonacci_point(i, c->R, h_base + 3 * i);
+    // tracing order of the probes: Morton order of their (x, y, z) grid index
+    std::vector<std::pair<uint64_t, int32_t>> morton((size_t)P);
+    for (int64_t p = 0; p < P; ++p) {
+        const uint64_t x = (uint64_t)(p % nx), y = (uint64_t)((p / nx) % ny);
+        const uint64_t z = (uint64_t)(p / ((int64_t)nx * ny));
+        uint64_t m = 0;
+        for (int b = 0; b < 21; ++b)
+            m |= (((x >> b) & 1) << (3 * b)) | (((y >> b) & 1) << (3 * b + 1)) |
+                 (((z >> b) & 1) << (3 * b + 2));
+        morton[(size_t)p] = {m, (int32_t)p};
+    }
+    std::sort(morton.begin(), morton.end());
+    std::vector<int32_t> h_order((size_t)P);
+    for (int64_t j = 0; j < P; ++j) h_order[(size_t)j] = morton[(size_t)j].second;
     for (int t = 0; t < c->Ti; ++t)
         texel_direction(params->irr_res, t % params->irr_res, t / params->irr_res, h_ti + 3 * t);
     for (int t = 0; t < c->Td; ++t)
@@ -488,11 +506,13 @@ sdfddgi_status sdfddgi_create(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_g
     hipError_t ce = hipSuccess;
     auto chk = [&](hipError_t x) { if (ce == hipSuccess) ce = x; };
     chk(dev_alloc(&c->probe_pos, 3 * P));
+    chk(dev_alloc(&c->probe_order, P));
     chk(dev_alloc(&c->base_dirs, 3 * c->R));
     chk(dev_alloc(&c->texel_i, 3 * c->Ti));
     chk(dev_alloc(&c->texel_d, 3 * c->Td));
     if (ce == hipSuccess) {
         chk(hipMemcpy(c->probe_pos, h_pos, 3 * P * sizeof(float), hipMemcpyHostToDevice));
+        chk(hipMemcpy(c->probe_order, h_order.data(), P * sizeof(int32_t), hipMemcpyHostToDevice));
         chk(hipMemcpy(c->base_dirs, h_base, 3 * c->R * sizeof(double), hipMemcpyHostToDevice));
         chk(hipMemcpy(c->texel_i, h_ti, 3 * c->Ti * sizeof(double), hipMemcpyHostToDevice));
         chk(hipMemcpy(c->texel_d, h_td, 3 * c->Td * sizeof(double), hipMemcpyHostToDevice));
@@ -577,6 +597,7 @@ sdfddgi_status sdfddgi_update_frame(sdfddgi_ctx *c, const sdfddgi_light *light,
     t.alb1 = c->prm.albedo[1];
     t.alb2 = c->prm.albedo[2];
     t.probe_pos = c->probe_pos;
+    t.probe_order = c->probe_order;
     t.dirs = c->dirs;
     t.prev_irr = c->irr[c->cur];
     t.payload = c->payload;
