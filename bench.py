@@ -186,6 +186,25 @@ def main():
     per_ms = np.array([a.elapsed_time(b) for a, b in per])
     S.sdfddgi_destroy(ctx)
 
+    # the precision form (binary16 SDF, FP16/BF16 MFMA blend) over the same frames
+    ctx16 = S.context_from_workload(w, flags=S.SDFDDGI_FLAG_TIMING | S.SDFDDGI_FLAG_FP16)
+    for k in range(args.warmup):
+        fr = w.frames[k % len(w.frames)]
+        S.sdfddgi_update_frame(ctx16, fr.dir_to_light, fr.radiance_rgb, fr.rotation_seed)
+    torch.cuda.synchronize()
+    if args.warmup:
+        S.sdfddgi_get_kernel_times(ctx16)
+    a16, b16 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a16.record(stream)
+    for k in range(args.steps):
+        fr = w.frames[(args.warmup + k) % len(w.frames)]
+        S.sdfddgi_update_frame(ctx16, fr.dir_to_light, fr.radiance_rgb, fr.rotation_seed)
+    b16.record(stream)
+    torch.cuda.synchronize()
+    ms16 = a16.elapsed_time(b16) / args.steps
+    kt16 = S.sdfddgi_get_kernel_times(ctx16)
+    S.sdfddgi_destroy(ctx16)
+
     out = {
         "metric": METRIC, "value": P * R / (ms_per_step * 1e-3), "unit": "probe-rays/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -199,6 +218,10 @@ def main():
         "ms_per_frame_p50": float(np.percentile(per_ms, 50)),
         "ms_per_frame_p99": float(np.percentile(per_ms, 99)),
         "kernel_ms": {k: float(v) for k, v in kt.items()},
+        "precision_form": {"dtype": "SDF f16, blend f16/bf16 MFMA with f32 accumulation, "
+                                    "f32 stepping and hysteresis",
+                           "ms_per_step": ms16, "value": P * R / (ms16 * 1e-3),
+                           "kernel_ms": {k: float(v) for k, v in kt16.items()}},
     }
     if not args.no_stats:
         stats_frames = [w.frames[(args.warmup + k) % len(w.frames)]

@@ -102,6 +102,12 @@ typedef enum {
 /* Context flags (sdfddgi_params.flags). */
 #define SDFDDGI_FLAG_RECORD_RAYS 1u  /* keep per-ray records (sdfddgi_get_ray_records) */
 #define SDFDDGI_FLAG_TIMING 2u       /* time each kernel with events (sdfddgi_get_kernel_times) */
+/* Precision form: the SDF is stored in binary16 (each value clamped to +-65504 and
+ * rounded to nearest even at create; stepping still runs in binary32 on the
+ * widened values, so ray decisions are those of the binary32 sequence on that
+ * rounded grid), and the Eq. 3 contraction runs on FP16 (irradiance) and BF16
+ * (depth moments) MFMA with FP32 accumulation; hysteresis stays binary32. */
+#define SDFDDGI_FLAG_FP16 4u
 
 /* One level of the baked distance grid. Level 0 is the finest; each coarser
  * level must contain the finer ones (a nested cascade). */

@@ -14,7 +14,8 @@ constexpr int kMaxRes = 32;
 // One cascade level as the kernels see it. org/inv/half are the binary32
 // roundings of origin, 1/spacing and spacing/2 (computed once in binary64).
 struct DevLevel {
-    const float4 *quad; // [n2-1][n1-1][n0] corner quads (see trilinear in kernels.hip)
+    const void *quad;   // [n2-1][n1-1][n0] corner quads (see trilinear in kernels.hip):
+                        // float4, or 4 x binary16 in the precision form
     const float *alb;   // [n2][n1][n0][3] or nullptr
     int n0, n1, n2;
     float org0, org1, org2;
@@ -35,6 +36,7 @@ struct ProbeGridDev {
 struct TraceArgs {
     DevLevel lv[kMaxLevels];
     int nl;
+    int half_sdf;               // 1: the quads hold binary16 values
     int P, R;
     int max_steps;
     int irr_res;
@@ -73,6 +75,9 @@ struct TableArgs {
     float *norm_i;              // [Ti]  pi / sum_i w_ti   (-1: all weights vanish)
     float *norm_d;              // [Td]  1 / sum_i w_ti^s  (-1: all weights vanish)
     int *counter;               // [3] the trace kernels' counters, reset here (may be null)
+    int Rpad;                   // row length of the 16-bit tables: R rounded up to 64
+    _Float16 *w16_i;            // precision form: [Tpi][Rpad] FP16 w_ti (else null)
+    __bf16 *w16_d;              // precision form: [Tpd][Rpad] BF16 w_ti^s (else null)
 };
 
 struct BlendArgs {
@@ -80,6 +85,9 @@ struct BlendArgs {
     float hysteresis;
     const float4 *payload;
     const float *wt_i, *wt_d, *norm_i, *norm_d;
+    int Rpad;
+    const _Float16 *w16_i;      // precision form (see TableArgs); null: FP32 blend
+    const __bf16 *w16_d;
     const float *prev_irr, *prev_depth;
     float *new_irr, *new_depth;
     uint8_t *reject;
@@ -96,12 +104,12 @@ struct SampleArgs {
 
 // Launchers (kernels.hip). Each enqueues on `stream` and returns the launch status.
 hipError_t launch_tables(const TableArgs &a, hipStream_t stream);
-TraceGrid trace_grid(int device, int64_t rays);
+TraceGrid trace_grid(int device, int64_t rays, bool half);
 hipError_t launch_primary(const TraceArgs &a, const TraceGrid &grid, hipStream_t stream);
 hipError_t launch_hits(const TraceArgs &a, const TraceGrid &grid, hipStream_t stream);
 hipError_t launch_blend(const BlendArgs &a, hipStream_t stream);
 hipError_t launch_sample(const SampleArgs &a, hipStream_t stream);
-hipError_t launch_pack_quads(const float *grid, int n0, int n1, int n2, float4 *quad,
+hipError_t launch_pack_quads(const float *grid, int n0, int n1, int n2, bool half, void *quad,
                              hipStream_t stream);
 hipError_t launch_fill_u8(uint8_t *dst, uint8_t value, int64_t n, hipStream_t stream);
 

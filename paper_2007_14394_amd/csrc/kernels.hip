@@ -29,7 +29,7 @@ __device__ __forceinline__ float clampf(float v, float lo, float hi) { return fm
 // A cascade level as the trace loops read it, copied to LDS once per block. The
 // binary32 constants were computed once in binary64 on the host.
 struct LevelLds {
-    const float4 *quad;            // corner quads [n2-1][n1-1][n0]
+    const void *quad;              // corner quads [n2-1][n1-1][n0], float4 or half4
     const float *alb;              // albedo [n2][n1][n0][3] or nullptr
     float org0, org1, org2, inv;   // (float)origin, (float)(1/spacing)
     float cmax0, cmax1, cmax2;     // (float)(n-2): last cell index per axis
@@ -67,14 +67,33 @@ __device__ __forceinline__ void cell_of(float u, float cmax, int &i, float &f) {
 // The grid is stored as corner quads: quad (i,j,k) = the values at (i,j,k),
 // (i,j+1,k), (i,j,k+1), (i,j+1,k+1), so a cell's eight corners are the two
 // adjacent quads (i,j,k) and (i+1,j,k) -- usually one cache line.
+// With kHalf the quads hold binary16 values (the precision form); they are widened
+// exactly to binary32 and the arithmetic is unchanged.
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+
+template <bool kHalf>
+__device__ __forceinline__ void load_quads(const void *base, uint32_t idx, float4 &a, float4 &b) {
+    if (kHalf) {
+        const half4_t *q = static_cast<const half4_t *>(base) + idx;
+        const half4_t ha = q[0], hb = q[1];
+        a = make_float4((float)ha.x, (float)ha.y, (float)ha.z, (float)ha.w);
+        b = make_float4((float)hb.x, (float)hb.y, (float)hb.z, (float)hb.w);
+    } else {
+        const float4 *q = static_cast<const float4 *>(base) + idx;
+        a = q[0];
+        b = q[1];
+    }
+}
+
+template <bool kHalf>
 __device__ __forceinline__ float trilinear(const LevelLds &d, float u0, float u1, float u2) {
     int i0, i1, i2;
     float f0, f1, f2;
     cell_of(u0, d.cmax0, i0, f0);
     cell_of(u1, d.cmax1, i1, f1);
     cell_of(u2, d.cmax2, i2, f2);
-    const float4 *q = d.quad + ((uint32_t)i2 * d.slice + (uint32_t)i1 * d.row + (uint32_t)i0);
-    const float4 a = q[0], b = q[1];
+    float4 a, b;
+    load_quads<kHalf>(d.quad, (uint32_t)i2 * d.slice + (uint32_t)i1 * d.row + (uint32_t)i0, a, b);
     const float v000 = a.x, v010 = a.y, v001 = a.z, v011 = a.w;
     const float v100 = b.x, v110 = b.y, v101 = b.z, v111 = b.w;
     const float c00 = fmaf(f0, v100 - v000, v000);
@@ -86,8 +105,9 @@ __device__ __forceinline__ float trilinear(const LevelLds &d, float u0, float u1
     return fmaf(f2, c1 - c0, c0);
 }
 
+template <bool kHalf>
 __device__ __forceinline__ float sample_at(const LevelLds &d, float p0, float p1, float p2) {
-    return trilinear(d, (p0 - d.org0) * d.inv, (p1 - d.org1) * d.inv, (p2 - d.org2) * d.inv);
+    return trilinear<kHalf>(d, (p0 - d.org0) * d.inv, (p1 - d.org1) * d.inv, (p2 - d.org2) * d.inv);
 }
 
 // Finest level whose box, shrunk by one voxel (the coarsest level: its full box),
@@ -109,6 +129,7 @@ __device__ __forceinline__ int select_level(const TraceArgs &a, float x0, float 
 }
 
 // Central differences at +-spacing/2 on the hit's level, normalised.
+template <bool kHalf>
 __device__ __forceinline__ void hit_normal(const LevelLds &d, float x0, float x1, float x2,
                                            float w0, float w1, float w2,
                                            float &n0, float &n1, float &n2) {
@@ -119,7 +140,7 @@ __device__ __forceinline__ void hit_normal(const LevelLds &d, float x0, float x1
         const float p0 = x0 + (ax == 0 ? h : 0.0f), m0 = x0 - (ax == 0 ? h : 0.0f);
         const float p1 = x1 + (ax == 1 ? h : 0.0f), m1 = x1 - (ax == 1 ? h : 0.0f);
         const float p2 = x2 + (ax == 2 ? h : 0.0f), m2 = x2 - (ax == 2 ? h : 0.0f);
-        g[ax] = sample_at(d, p0, p1, p2) - sample_at(d, m0, m1, m2);
+        g[ax] = sample_at<kHalf>(d, p0, p1, p2) - sample_at<kHalf>(d, m0, m1, m2);
     }
     const float g0 = g[0], g1 = g[1], g2 = g[2];
     const float len2 = fmaf(g2, g2, fmaf(g1, g1, g0 * g0));
@@ -131,7 +152,7 @@ __device__ __forceinline__ void hit_normal(const LevelLds &d, float x0, float x1
 // One sample of the fixed sphere-trace sequence for a ray o + t w at sample k.
 // Returns the outcome code when the ray stops here (steps in *steps), -1 otherwise
 // (t and k are then advanced). x and the level of the sample are returned too.
-template <bool kPrimary>
+template <bool kPrimary, bool kHalf>
 __device__ __forceinline__ int trace_step(const TraceArgs &a, const LevelLds *s_lv, float o0,
                                           float o1, float o2, float w0, float w1, float w2,
                                           float &t, int &k, float &x0, float &x1, float &x2,
@@ -141,8 +162,8 @@ __device__ __forceinline__ int trace_step(const TraceArgs &a, const LevelLds *s_
     level = select_level(a, x0, x1, x2);
     if (level < 0) { steps = k; return kMissExit; }
     const LevelLds &d = s_lv[level];
-    const float dist = trilinear(d, (x0 - d.org0) * d.inv, (x1 - d.org1) * d.inv,
-                                 (x2 - d.org2) * d.inv);
+    const float dist = trilinear<kHalf>(d, (x0 - d.org0) * d.inv, (x1 - d.org1) * d.inv,
+                                        (x2 - d.org2) * d.inv);
     if (kPrimary && k == 0 && dist < 0.0f) { steps = 1; return kInside; }
     if (dist < a.eps) { steps = k + 1; return kHit; }
     t = fmaf(a.relax, dist, t);
@@ -289,6 +310,7 @@ struct Feeder {
 // per wave in LDS. Each ray's arithmetic is the fixed sequence of trace_step,
 // whatever lane or wave runs it. Every wave exits once the counter has passed the
 // last ray and its lanes are idle, after flushing its staged hits.
+template <bool kHalf>
 __global__ __launch_bounds__(256) void primary_kernel(TraceArgs a) {
     __shared__ LevelLds s_lv[kMaxLevels];
     __shared__ int4 s_hits[4][64];
@@ -337,8 +359,8 @@ __global__ __launch_bounds__(256) void primary_kernel(TraceArgs a) {
             const float tt = t;
             float x0, x1, x2;
             int level = 0, steps = 0;
-            const int kind = trace_step<true>(a, s_lv, o0, o1, o2, w0, w1, w2, t, k, x0, x1, x2,
-                                              level, steps);
+            const int kind = trace_step<true, kHalf>(a, s_lv, o0, o1, o2, w0, w1, w2, t, k, x0,
+                                                     x1, x2, level, steps);
             if (kind >= 0) {
                 if (kind == kHit || kind == kHitExhausted) {
                     hit_now = true;
@@ -377,6 +399,7 @@ constexpr int kShadeBatch = 16;   // shade when this many lanes wait (or steppin
 // newly assigned lanes), the SDF shadow ray toward the light (wave-compacted like the
 // primary trace), and shading -- albedo, sun, multi-bounce lookup -- batched when
 // kShadeBatch lanes wait or stepping runs low.
+template <bool kHalf>
 __global__ __launch_bounds__(256) void hits_kernel(TraceArgs a) {
     __shared__ LevelLds s_lv[kMaxLevels];
     load_levels(a, s_lv);
@@ -439,7 +462,8 @@ __global__ __launch_bounds__(256) void hits_kernel(TraceArgs a) {
                                     po2 = a.probe_pos[3 * p + 2];
                         const float w0 = a.dirs[3 * i], w1 = a.dirs[3 * i + 1], w2 = a.dirs[3 * i + 2];
                         hx0 = fmaf(ht, w0, po0); hx1 = fmaf(ht, w1, po1); hx2 = fmaf(ht, w2, po2);
-                        hit_normal(s_lv[(info >> 4) & 15], hx0, hx1, hx2, w0, w1, w2, n0, n1, n2);
+                        hit_normal<kHalf>(s_lv[(info >> 4) & 15], hx0, hx1, hx2, w0, w1, w2, n0, n1,
+                                          n2);
                         const float ndl = fmaf(n2, a.l2, fmaf(n1, a.l1, n0 * a.l0));
                         if (ndl > 0.0f) {
                             o0 = fmaf(n0, a.bias, hx0);
@@ -462,8 +486,8 @@ __global__ __launch_bounds__(256) void hits_kernel(TraceArgs a) {
         if (mode == kShadow) {
             float x0, x1, x2;
             int level = 0, steps = 0;
-            const int kind = trace_step<false>(a, s_lv, o0, o1, o2, a.l0, a.l1, a.l2, t, k, x0,
-                                               x1, x2, level, steps);
+            const int kind = trace_step<false, kHalf>(a, s_lv, o0, o1, o2, a.l0, a.l1, a.l2, t,
+                                                      k, x0, x1, x2, level, steps);
             if (kind >= 0) {
                 vis = (kind == kHit || kind == kHitExhausted) ? 0 : 1;
                 k = steps;
@@ -503,9 +527,21 @@ __global__ __launch_bounds__(256) void tables_kernel(TableArgs a) {
         double w = c > 0.0 ? c : 0.0;
         if (is_depth) {
             w = pow(w, a.sharp);
-            a.wt_d[(size_t)i * a.Tpd + t] = (float)w;
+            if (a.w16_d) {  // precision form: BF16 depth weights, sums of the rounded values
+                const __bf16 b = (__bf16)(float)w;
+                a.w16_d[(size_t)t * a.Rpad + i] = b;
+                w = (double)(float)b;
+            } else {
+                a.wt_d[(size_t)i * a.Tpd + t] = (float)w;
+            }
         } else {
-            a.wt_i[(size_t)i * a.Tpi + t] = (float)w;
+            if (a.w16_i) {  // precision form: FP16 irradiance weights
+                const _Float16 h = (_Float16)w;
+                a.w16_i[(size_t)t * a.Rpad + i] = h;
+                w = (double)(float)h;
+            } else {
+                a.wt_i[(size_t)i * a.Tpi + t] = (float)w;
+            }
         }
         part += w;
     }
@@ -561,6 +597,146 @@ constexpr int kMSlots = 5;        // 16-texel M-tiles per wave per pass
 // to kMSlots per wave per pass (one pass covers 8x8 + 16x16 maps). The epilogue
 // normalises, mixes with the previous interior (hysteresis, or none for rejected
 // probes) and writes interior and border texels.
+// Epilogue of both blend kernels for one 16x16 accumulator tile: lane holds
+// D[4*krow + r][row]. Normalises, mixes with the previous interior (hysteresis, or
+// none for rejected probes) and writes interior and border texels.
+__device__ __forceinline__ void blend_epilogue(const BlendArgs &a, const float *s_h, int pb, int np,
+                                               bool irr, int mtile, int n, int row, int krow,
+                                               floatx4 acc) {
+    const int res = irr ? a.irr_res : a.depth_res;
+    const int T = res * res, comps = irr ? 3 : 2, side = res + 2;
+    const int m0 = mtile * 16 + 4 * krow;
+    const float *norm = irr ? a.norm_i : a.norm_d;
+    const int col = n * 16 + row;
+    const int q = irr ? col / 3 : col >> 1;
+    const int c = irr ? col - 3 * q : col & 1;
+    if (q >= np) return;
+    const size_t tile_floats = (size_t)side * side * comps;
+    const float *old_tile = (irr ? a.prev_irr : a.prev_depth) + (size_t)(pb + q) * tile_floats;
+    float *new_tile = (irr ? a.new_irr : a.new_depth) + (size_t)(pb + q) * tile_floats;
+    const float h = s_h[q];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int t = m0 + r;
+        if (t >= T) continue;
+        const int i = t % res, j = t / res;
+        const float nrm = norm[t];
+        const float old = old_tile[((j + 1) * side + (i + 1)) * comps + c];
+        const float u = acc[r] * nrm;
+        const float v = nrm < 0.0f ? old : fmaf(h, old - u, u);
+        store_with_border(new_tile, res, comps, i, j, c, v);
+    }
+}
+
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+constexpr int kPitch16 = kBlendChunk + 8;  // halves per LDS column (+8 spreads the banks)
+
+// Precision form of the blend: the same tiling as blend_kernel, with the weights as
+// FP16 (irradiance) / BF16 (depth) rows [T][Rpad] and the payload staged in LDS as
+// FP16 radiance and BF16 (t, t^2) columns, contracted 32 rays at a time on
+// v_mfma_f32_16x16x32_{f16,bf16} with FP32 accumulation.
+template <bool kStd>
+__global__ __launch_bounds__(256) void blend16_kernel(BlendArgs a) {
+    __shared__ __attribute__((aligned(16))) _Float16 si[(kBlendProbes * 3 + 1) * kPitch16];
+    __shared__ __attribute__((aligned(16))) __bf16 sd[(kBlendProbes * 2 + 1) * kPitch16];
+    __shared__ float s_h[kBlendProbes];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int row = lane & 15, kgrp = lane >> 4;
+    const int pb = blockIdx.x * kBlendProbes;
+    const int np = min(kBlendProbes, a.P - pb);
+    const int Ti = a.irr_res * a.irr_res, Td = a.depth_res * a.depth_res;
+    const int mti = (Ti + 15) >> 4, mtd = (Td + 15) >> 4;
+    const int mtiles = mti + mtd;
+    if (tid < kBlendProbes) s_h[tid] = (tid < np && !a.reject[pb + tid]) ? a.hysteresis : 0.0f;
+    for (int e = tid; e < kPitch16; e += 256) {
+        si[kBlendProbes * 3 * kPitch16 + e] = (_Float16)0.0f;
+        sd[kBlendProbes * 2 * kPitch16 + e] = (__bf16)0.0f;
+    }
+    int bi_off[3], bd_off[2];
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+        const int col = n * 16 + row;
+        bi_off[n] = (col / 3 < np ? col : kBlendProbes * 3) * kPitch16;
+    }
+#pragma unroll
+    for (int n = 0; n < 2; ++n) {
+        const int col = n * 16 + row;
+        bd_off[n] = ((col >> 1) < np ? col : kBlendProbes * 2) * kPitch16;
+    }
+    const int passes = kStd ? 1 : (mtiles + 4 * kMSlots - 1) / (4 * kMSlots);
+    for (int pass = 0; pass < passes; ++pass) {
+        floatx4 acc[kMSlots][3];
+        int mt[kMSlots];
+        const _Float16 *wi[kMSlots];
+        const __bf16 *wd[kMSlots];
+#pragma unroll
+        for (int s = 0; s < kMSlots; ++s) {
+            mt[s] = pass * 4 * kMSlots + s * 4 + wave;
+            const bool irr = kStd ? s == 0 : mt[s] < mti;
+            wi[s] = a.w16_i + (size_t)(mt[s] * 16 + row) * a.Rpad;
+            wd[s] = a.w16_d + (size_t)((irr ? 0 : mt[s] - mti) * 16 + row) * a.Rpad;
+#pragma unroll
+            for (int n = 0; n < 3; ++n) acc[s][n] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+        for (int k0 = 0; k0 < a.Rpad; k0 += kBlendChunk) {
+            __syncthreads();
+            const int kc = min(kBlendChunk, a.R - k0);  // rays present in this chunk
+            for (int e = tid; e < kBlendProbes * kBlendChunk; e += 256) {
+                const int q = e / kBlendChunk, kk = e - q * kBlendChunk;
+                float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if (q < np && kk < kc) v = a.payload[(size_t)(pb + q) * a.R + k0 + kk];
+                si[(q * 3 + 0) * kPitch16 + kk] = (_Float16)v.x;
+                si[(q * 3 + 1) * kPitch16 + kk] = (_Float16)v.y;
+                si[(q * 3 + 2) * kPitch16 + kk] = (_Float16)v.z;
+                sd[(q * 2 + 0) * kPitch16 + kk] = (__bf16)v.w;
+                sd[(q * 2 + 1) * kPitch16 + kk] = (__bf16)(v.w * v.w);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int kk = 0; kk < kBlendChunk; kk += 32) {
+                const int kl = kk + 8 * kgrp;  // this lane's 8 rays within the chunk
+                half8_t bi[3];
+                bf16x8_t bd[2];
+#pragma unroll
+                for (int n = 0; n < 3; ++n)
+                    bi[n] = *reinterpret_cast<const half8_t *>(&si[bi_off[n] + kl]);
+#pragma unroll
+                for (int n = 0; n < 2; ++n)
+                    bd[n] = *reinterpret_cast<const bf16x8_t *>(&sd[bd_off[n] + kl]);
+#pragma unroll
+                for (int s = 0; s < kMSlots; ++s) {
+                    if (kStd ? s == 0 : mt[s] < mti) {
+                        const half8_t av = *reinterpret_cast<const half8_t *>(wi[s] + k0 + kl);
+#pragma unroll
+                        for (int n = 0; n < 3; ++n)
+                            acc[s][n] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bi[n], acc[s][n], 0, 0, 0);
+                    } else if (kStd || mt[s] < mtiles) {
+                        const bf16x8_t av = *reinterpret_cast<const bf16x8_t *>(wd[s] + k0 + kl);
+#pragma unroll
+                        for (int n = 0; n < 2; ++n)
+                            acc[s][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bd[n], acc[s][n], 0, 0, 0);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < kMSlots; ++s) {
+            if (!kStd && mt[s] >= mtiles) continue;
+            const bool irr = kStd ? s == 0 : mt[s] < mti;
+#pragma unroll
+            for (int n = 0; n < 3; ++n) {
+                if (!irr && n == 2) break;
+                blend_epilogue(a, s_h, pb, np, irr, irr ? mt[s] : mt[s] - mti, n, row, kgrp,
+                               acc[s][n]);
+            }
+        }
+    }
+    __syncthreads();
+    if (tid < np) a.reject[pb + tid] = 0;
+}
+
 // kStd: the 8x8 irradiance + 16x16 depth layout (4 + 16 M-tiles, one pass), where
 // slot 0 of every wave is an irradiance tile and slots 1..4 are depth tiles, known at
 // compile time; other resolutions take the general instantiation.
@@ -710,7 +886,28 @@ __global__ __launch_bounds__(256) void sample_kernel(SampleArgs a) {
     a.out[3 * q + 2] = e.z;
 }
 
-// Corner-quad repacking of one grid level (see trilinear).
+// Corner-quad repacking of one grid level (see trilinear). The binary16 form clamps
+// each value to +-65504 and rounds it to nearest even.
+__device__ __forceinline__ _Float16 to_half(float v) {
+    return (_Float16)fminf(fmaxf(v, -65504.0f), 65504.0f);
+}
+
+__global__ __launch_bounds__(256) void pack_quads_half_kernel(const float *__restrict__ g, int n0,
+                                                              int n1, int n2,
+                                                              half4_t *__restrict__ quad) {
+    const int64_t total = (int64_t)n0 * (n1 - 1) * (n2 - 1);
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= total) return;
+    const int i = (int)(q % n0);
+    const int j = (int)((q / n0) % (n1 - 1));
+    const int k = (int)(q / ((int64_t)n0 * (n1 - 1)));
+    const int64_t sy = n0, sz = (int64_t)n0 * n1;
+    const int64_t v = k * sz + j * sy + i;
+    half4_t h;
+    h.x = to_half(g[v]); h.y = to_half(g[v + sy]); h.z = to_half(g[v + sz]); h.w = to_half(g[v + sz + sy]);
+    quad[q] = h;
+}
+
 __global__ __launch_bounds__(256) void pack_quads_kernel(const float *__restrict__ g, int n0, int n1,
                                                          int n2, float4 *__restrict__ quad) {
     const int64_t total = (int64_t)n0 * (n1 - 1) * (n2 - 1);
@@ -753,27 +950,44 @@ static int persistent_blocks(const void *kernel, int device, int64_t rays) {
     return (int)(needed < resident ? needed : resident);
 }
 
-TraceGrid trace_grid(int device, int64_t rays) {
+TraceGrid trace_grid(int device, int64_t rays, bool half) {
     TraceGrid g;
-    g.primary_blocks = persistent_blocks((const void *)primary_kernel, device, rays);
-    g.hits_blocks = persistent_blocks((const void *)hits_kernel, device, rays);
+    g.primary_blocks = persistent_blocks(half ? (const void *)primary_kernel<true>
+                                              : (const void *)primary_kernel<false>,
+                                         device, rays);
+    g.hits_blocks = persistent_blocks(half ? (const void *)hits_kernel<true>
+                                           : (const void *)hits_kernel<false>,
+                                      device, rays);
     return g;
 }
 
 hipError_t launch_primary(const TraceArgs &a, const TraceGrid &g, hipStream_t s) {
     if ((int64_t)a.P * a.R == 0) return hipSuccess;
-    hipLaunchKernelGGL(primary_kernel, dim3(g.primary_blocks), dim3(256), 0, s, a);
+    if (a.half_sdf)
+        hipLaunchKernelGGL(primary_kernel<true>, dim3(g.primary_blocks), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(primary_kernel<false>, dim3(g.primary_blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_hits(const TraceArgs &a, const TraceGrid &g, hipStream_t s) {
     if ((int64_t)a.P * a.R == 0) return hipSuccess;
-    hipLaunchKernelGGL(hits_kernel, dim3(g.hits_blocks), dim3(256), 0, s, a);
+    if (a.half_sdf)
+        hipLaunchKernelGGL(hits_kernel<true>, dim3(g.hits_blocks), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(hits_kernel<false>, dim3(g.hits_blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_blend(const BlendArgs &a, hipStream_t s) {
     const dim3 grid(blocks_for(a.P, kBlendProbes)), block(256);
+    if (a.w16_i) {
+        if (a.irr_res == 8 && a.depth_res == 16)
+            hipLaunchKernelGGL(blend16_kernel<true>, grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL(blend16_kernel<false>, grid, block, 0, s, a);
+        return hipGetLastError();
+    }
     if (a.irr_res == 8 && a.depth_res == 16)
         hipLaunchKernelGGL(blend_kernel<true>, grid, block, 0, s, a);
     else
@@ -787,10 +1001,15 @@ hipError_t launch_sample(const SampleArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_pack_quads(const float *g, int n0, int n1, int n2, float4 *quad, hipStream_t s) {
+hipError_t launch_pack_quads(const float *g, int n0, int n1, int n2, bool half, void *quad,
+                             hipStream_t s) {
     const int64_t total = (int64_t)n0 * (n1 - 1) * (n2 - 1);
-    hipLaunchKernelGGL(pack_quads_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, s, g, n0, n1,
-                       n2, quad);
+    if (half)
+        hipLaunchKernelGGL(pack_quads_half_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, s, g,
+                           n0, n1, n2, static_cast<half4_t *>(quad));
+    else
+        hipLaunchKernelGGL(pack_quads_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, s, g, n0,
+                           n1, n2, static_cast<float4 *>(quad));
     return hipGetLastError();
 }
 

@@ -112,7 +112,8 @@ struct sdfddgi_ctx {
     int n[kMaxLevels][3]{};
     double origin[kMaxLevels][3]{};
     double spacing[kMaxLevels]{};
-    float4 *quad[kMaxLevels]{};  // corner-quad repacking of each level's grid
+    void *quad[kMaxLevels]{};    // corner-quad repacking of each level's grid
+    bool half = false;           // precision form: quads in binary16
     float *alb[kMaxLevels]{};
     sdfddgi_probe_grid pg{};
     int64_t P = 0;
@@ -122,6 +123,9 @@ struct sdfddgi_ctx {
     int *probe_order = nullptr;
     double *base_dirs = nullptr, *texel_i = nullptr, *texel_d = nullptr;
     float *dirs = nullptr, *wt_i = nullptr, *wt_d = nullptr, *norm_i = nullptr, *norm_d = nullptr;
+    _Float16 *w16_i = nullptr;   // precision-form weight tables [T][Rpad]
+    __bf16 *w16_d = nullptr;
+    int Rpad = 0;
     float *irr[2]{}, *depth[2]{};
     int cur = 0;
     uint8_t *reject = nullptr;
@@ -172,7 +176,7 @@ void free_all(sdfddgi_ctx *c) {
         if (c->alb[L]) (void)hipFree(c->alb[L]);
     }
     void *bufs[] = {c->probe_pos, c->probe_order, c->base_dirs, c->texel_i, c->texel_d, c->dirs, c->wt_i,
-                    c->wt_d, c->norm_i, c->norm_d, c->irr[0], c->irr[1], c->depth[0],
+                    c->wt_d, c->norm_i, c->norm_d, c->w16_i, c->w16_d, c->irr[0], c->irr[1], c->depth[0],
                     c->depth[1], c->reject, c->counter, c->hitq, c->payload, c->records};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -346,6 +350,9 @@ TableArgs table_args(const sdfddgi_ctx *c, uint64_t seed) {
     t.norm_i = c->norm_i;
     t.norm_d = c->norm_d;
     t.counter = c->counter;
+    t.Rpad = c->Rpad;
+    t.w16_i = c->w16_i;
+    t.w16_d = c->w16_d;
     return t;
 }
 
@@ -361,6 +368,9 @@ BlendArgs blend_args(const sdfddgi_ctx *c, const float4 *payload) {
     b.wt_d = c->wt_d;
     b.norm_i = c->norm_i;
     b.norm_d = c->norm_d;
+    b.Rpad = c->Rpad;
+    b.w16_i = c->w16_i;
+    b.w16_d = c->w16_d;
     b.prev_irr = c->irr[c->cur];
     b.prev_depth = c->depth[c->cur];
     b.new_irr = c->irr[1 - c->cur];
@@ -423,6 +433,7 @@ sdfddgi_status sdfddgi_create(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_g
     c->device = dev;
     c->stream = (hipStream_t)hip_stream;
     c->prm = *params;
+    c->half = (params->flags & SDFDDGI_FLAG_FP16) != 0;
     c->nl = sdf->num_levels;
     c->pg = *probes;
     c->P = (int64_t)probes->n[0] * probes->n[1] * probes->n[2];
@@ -455,8 +466,9 @@ sdfddgi_status sdfddgi_create(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_g
         }
         c->spacing[L] = lv.spacing;
         const size_t nquad = (size_t)lv.n[0] * (lv.n[1] - 1) * (lv.n[2] - 1);
-        SDF_TRY(dev_alloc(&c->quad[L], nquad), "allocating sdf level");
-        SDF_TRY(launch_pack_quads(lv.sdf, lv.n[0], lv.n[1], lv.n[2], c->quad[L], c->stream),
+        SDF_TRY(hipMalloc(&c->quad[L], nquad * (c->half ? 8 : 16)), "allocating sdf level");
+        SDF_TRY(launch_pack_quads(lv.sdf, lv.n[0], lv.n[1], lv.n[2], c->half, c->quad[L],
+                                  c->stream),
                 "packing sdf level");
         if (lv.albedo_rgb) {
             SDF_TRY(dev_alloc(&c->alb[L], 3 * cnt), "allocating albedo level");
@@ -527,6 +539,15 @@ sdfddgi_status sdfddgi_create(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_g
             "clearing tables");
     SDF_TRY(hipMemsetAsync(c->wt_d, 0, (size_t)c->R * c->Tpd * sizeof(float), c->stream),
             "clearing tables");
+    if (c->half) {
+        c->Rpad = (c->R + 63) / 64 * 64;
+        SDF_TRY(dev_alloc(&c->w16_i, (size_t)c->Tpi * c->Rpad), "allocating tables");
+        SDF_TRY(dev_alloc(&c->w16_d, (size_t)c->Tpd * c->Rpad), "allocating tables");
+        SDF_TRY(hipMemsetAsync(c->w16_i, 0, (size_t)c->Tpi * c->Rpad * 2, c->stream),
+                "clearing tables");
+        SDF_TRY(hipMemsetAsync(c->w16_d, 0, (size_t)c->Tpd * c->Rpad * 2, c->stream),
+                "clearing tables");
+    }
     SDF_TRY(dev_alloc(&c->norm_i, c->Ti), "allocating tables");
     SDF_TRY(dev_alloc(&c->norm_d, c->Td), "allocating tables");
     for (int k = 0; k < 2; ++k) {
@@ -542,7 +563,7 @@ sdfddgi_status sdfddgi_create(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_g
     SDF_TRY(dev_alloc(&c->counter, 3), "allocating ray counters");
     SDF_TRY(dev_alloc(&c->hitq, (size_t)P * c->R), "allocating the hit queue");
     SDF_TRY(dev_alloc(&c->payload, (size_t)P * c->R), "allocating payload");
-    c->grid = trace_grid(dev, P * c->R);
+    c->grid = trace_grid(dev, P * c->R, c->half);
     if (params->flags & SDFDDGI_FLAG_RECORD_RAYS)
         SDF_TRY(dev_alloc(&c->records, (size_t)P * c->R * 8), "allocating ray records");
     if (params->flags & SDFDDGI_FLAG_TIMING) {
@@ -574,6 +595,7 @@ sdfddgi_status sdfddgi_update_frame(sdfddgi_ctx *c, const sdfddgi_light *light,
     TraceArgs t{};
     for (int L = 0; L < c->nl; ++L) t.lv[L] = dev_level(c, L);
     t.nl = c->nl;
+    t.half_sdf = c->half ? 1 : 0;
     t.P = (int)c->P;
     t.R = c->R;
     t.max_steps = c->prm.max_steps;

@@ -22,6 +22,7 @@ SDFDDGI_MAX_LEVELS = 4
 SDFDDGI_MAX_RAYS = 1024
 SDFDDGI_FLAG_RECORD_RAYS = 1
 SDFDDGI_FLAG_TIMING = 2
+SDFDDGI_FLAG_FP16 = 4
 
 STATUS_NAMES = {0: "SDFDDGI_OK", 1: "SDFDDGI_EINVAL", 2: "SDFDDGI_ENOMEM",
                 3: "SDFDDGI_EDEVICE", 4: "SDFDDGI_ESTATE"}
