@@ -25,12 +25,18 @@ CFLAGS = ["-O2", "-fPIC", "-shared", "-pthread", "-std=c11", "-ffp-contract=off"
           "-fno-fast-math", "-fexcess-precision=standard", "-Wall", "-Wextra"]
 
 
-def build(force: bool = True, extra_cflags: Sequence[str] = (), out: Optional[str] = None) -> str:
-    """Compile oracle.c with gcc into a shared library (returns its path)."""
+SOURCES = ("oracle.c", "learned.c")
+
+
+def build(force: bool = True, extra_cflags: Sequence[str] = (), out: Optional[str] = None,
+          sources: Optional[Sequence[str]] = None) -> str:
+    """Compile oracle.c and learned.c with gcc into a shared library (returns its path)."""
     path = out or _LIB_PATH
+    if sources is None:
+        sources = [os.path.join(_HERE, f) for f in SOURCES]
     if force or not os.path.exists(path):
         tmp = path + ".tmp"
-        cmd = ["gcc", *CFLAGS, *extra_cflags, os.path.join(_HERE, "oracle.c"), "-o", tmp, "-lm"]
+        cmd = ["gcc", *CFLAGS, *extra_cflags, *sources, "-o", tmp, "-lm"]
         subprocess.check_call(cmd)
         os.replace(tmp, path)
     return path
@@ -71,6 +77,12 @@ def _load(path: str):
     L.orc_level32.restype = ctypes.c_int32
     L.orc_blend_probe.restype = ctypes.c_int32
     L.orc_update_probes.restype = ctypes.c_int32
+    L.orc_round_bf16.restype = ctypes.c_double
+    L.orc_round_bf16.argtypes = [ctypes.c_double]
+    L.orc_mlp_loss_grad.restype = ctypes.c_double
+    L.orc_batch_index.restype = ctypes.c_int64
+    L.orc_batch_index.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64]
+    L.orc_probe_sdf.restype = ctypes.c_double
     return L
 
 
@@ -148,6 +160,8 @@ class Checker:
         self.rays = int(vals["rays"])
         self.irr_res = int(vals["irr_res"])
         self.depth_res = int(vals["depth_res"])
+        self.hysteresis = float(s.hysteresis)  # the binary32 value the C checker uses
+        self._overrides = dict(overrides)
 
     @property
     def ref(self):
@@ -233,6 +247,69 @@ class Checker:
             raise RuntimeError("orc_update_probes failed")
         return irr, dep, pl, rec
 
+    # -- learned form ---------------------------------------------------
+    def probe_sdf(self, p: int) -> float:
+        return float(lib().orc_probe_sdf(self.ref, ctypes.c_int32(p)))
+
+    def learned_features(self, u_irr, prev_irr, prev_depth, S: float, D: float,
+                         probes: Optional[Sequence[int]] = None) -> np.ndarray:
+        """Features [count, Ti, 16] of every interior irradiance texel of the probes."""
+        if probes is None:
+            probes = np.arange(self.num_probes, dtype=np.int32)
+        probes = np.ascontiguousarray(probes, dtype=np.int32)
+        u = np.ascontiguousarray(u_irr, dtype=np.float64)
+        pi = np.ascontiguousarray(prev_irr, dtype=np.float64)
+        pd = np.ascontiguousarray(prev_depth, dtype=np.float64)
+        out = np.zeros((probes.shape[0], self.irr_res ** 2, FEATURES))
+        lib().orc_learned_features_all(self.ref, _p(u), _p(pi), _p(pd), _p(probes),
+                                       ctypes.c_int32(probes.shape[0]), ctypes.c_double(S),
+                                       ctypes.c_double(D), _p(out))
+        return out
+
+    def learned_frame(self, frame, reset: bool, prev_irr, prev_depth, theta, S: float, D: float,
+                      tau: float, learned_rays: int, fallback=None, threads: int = 0,
+                      mirror: bool = True):
+        """One frame of the learned form for every probe.
+
+        Low-ray Eq. 3 update (no hysteresis), features, network (mirror mode unless
+        ``mirror`` is false),
+        per-probe decision: a probe takes the plain update when the history is
+        reset or the mean of exp(o_3) over its texels exceeds tau. ``fallback``
+        (a boolean per probe) overrides the decision, for checking another
+        implementation's choice where the two precisions may legitimately differ.
+        Returns dict(irr, depth, fallback, mean_error, o, features, u_irr, u_depth).
+        """
+        P, T = self.num_probes, self.irr_res ** 2
+        low = Checker(self.workload, **{**self._overrides, "rays": learned_rays,
+                                        "hysteresis": 0.0})
+        u_irr, u_dep, _, _ = low.update_probes(frame, True, prev_irr, prev_depth,
+                                               threads=threads)
+        feats = self.learned_features(u_irr, prev_irr, prev_depth, S, D)
+        o = mlp_forward(theta, feats.reshape(-1, FEATURES), mirror=mirror).reshape(P, T, 4)
+        mean_err = np.exp(o[..., 3]).mean(axis=1)
+        decided = np.full(P, True) if reset else mean_err > tau
+        fb = decided if fallback is None else np.asarray(fallback, dtype=bool)
+        h = self.hysteresis
+        prev_irr = np.asarray(prev_irr, dtype=np.float64)
+        prev_depth = np.asarray(prev_depth, dtype=np.float64)
+        irr = np.zeros_like(prev_irr)
+        dep = np.zeros_like(prev_depth)
+        ri = self.irr_res
+        interior = prev_irr[:, 1:ri + 1, 1:ri + 1, :].reshape(P, T, 3)
+        u_hat = np.maximum(0.0, interior + S * o[..., :3])
+        mixed = (h * interior + (1.0 - h) * u_hat).reshape(P, ri, ri, 3)
+        irr[:, 1:ri + 1, 1:ri + 1, :] = mixed
+        _fill_borders(irr, ri)
+        dep[:] = h * prev_depth + (1.0 - h) * u_dep
+        idx = np.nonzero(fb)[0].astype(np.int32)
+        if idx.size:
+            fi, fd, _, _ = self.update_probes(frame, reset, prev_irr, prev_depth, probes=idx,
+                                              threads=threads)
+            irr[idx] = fi
+            dep[idx] = fd
+        return dict(irr=irr, depth=dep, fallback=fb, decided=decided, mean_error=mean_err, o=o,
+                    features=feats, u_irr=u_irr, u_depth=u_dep)
+
     def run_frames(self, frames, init: Optional[Tuple[np.ndarray, np.ndarray]] = None,
                    reset_first: bool = True, threads: int = 0):
         """Free-run the listed frames from ``init`` (zeros by default); returns every atlas."""
@@ -252,6 +329,82 @@ class Checker:
 
 
 # -- free functions -------------------------------------------------------
+
+FEATURES, HIDDEN, OUTPUTS = 16, 64, 4
+OFF_W1 = 0
+OFF_W2 = OFF_W1 + HIDDEN * FEATURES
+OFF_B2 = OFF_W2 + HIDDEN * HIDDEN
+OFF_W3 = OFF_B2 + HIDDEN
+OFF_B3 = OFF_W3 + HIDDEN * HIDDEN
+OFF_W4 = OFF_B3 + HIDDEN
+OFF_B4 = OFF_W4 + OUTPUTS * HIDDEN
+MLP_PARAMS = OFF_B4 + OUTPUTS
+
+
+class LossConfig(ctypes.Structure):
+    _fields_ = [("head_weight", ctypes.c_double), ("min_error", ctypes.c_double)]
+
+
+def round_bf16(v: float) -> float:
+    return float(lib().orc_round_bf16(float(v)))
+
+
+def mlp_forward(theta, x, mirror: bool = True) -> np.ndarray:
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    xs = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(-1, FEATURES))
+    out = np.zeros((xs.shape[0], OUTPUTS))
+    lib().orc_mlp_forward_batch(_p(th), _p(xs), ctypes.c_int64(xs.shape[0]),
+                                ctypes.c_int32(int(mirror)), _p(out))
+    return out
+
+
+def mlp_activations(theta, x, mirror: bool = True) -> Tuple[np.ndarray, np.ndarray]:
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    xa = (ctypes.c_double * FEATURES)(*[float(v) for v in np.asarray(x).ravel()])
+    o = (ctypes.c_double * OUTPUTS)()
+    act = np.zeros((3, HIDDEN))
+    lib().orc_mlp_forward(_p(th), xa, ctypes.c_int32(int(mirror)), o, _p(act))
+    return np.array(list(o)), act
+
+
+def mlp_loss_grad(theta, x, targets, head_weight: float, min_error: float,
+                  mirror: bool = True, want_grad: bool = True):
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    xs = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(-1, FEATURES))
+    tg = np.ascontiguousarray(np.asarray(targets, dtype=np.float64).reshape(-1, 4))
+    g = np.zeros(MLP_PARAMS) if want_grad else None
+    cfg = LossConfig(head_weight, min_error)
+    loss = lib().orc_mlp_loss_grad(_p(th), _p(xs), _p(tg), ctypes.c_int32(xs.shape[0]),
+                                   ctypes.byref(cfg), ctypes.c_int32(int(mirror)),
+                                   _p(g) if g is not None else None)
+    return float(loss), g
+
+
+def adam_step(theta, m, v, g, t: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+              eps: float = 1e-8) -> None:
+    """In place on float64 arrays theta, m, v."""
+    for a in (theta, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    gg = np.ascontiguousarray(g, dtype=np.float64)
+    lib().orc_adam_step(_p(theta), _p(m), _p(v), _p(gg), ctypes.c_int32(theta.size),
+                        ctypes.c_int32(t), ctypes.c_double(lr), ctypes.c_double(beta1),
+                        ctypes.c_double(beta2), ctypes.c_double(eps))
+
+
+def batch_index(seed: int, i: int, count: int) -> int:
+    return int(lib().orc_batch_index(seed, i, count))
+
+
+def _fill_borders(tiles: np.ndarray, res: int) -> None:
+    """Copy interior texels into the border of padded tiles [P, res+2, res+2, C]."""
+    side = res + 2
+    for b in range(side):
+        for a in range(side):
+            if 1 <= a <= res and 1 <= b <= res:
+                continue
+            i, j = border_source(res, a, b)
+            tiles[:, b, a, :] = tiles[:, j + 1, i + 1, :]
+
 
 def splitmix64_sequence(seed: int, count: int) -> List[int]:
     st = ctypes.c_uint64(seed)

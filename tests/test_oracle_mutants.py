@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests import test_learned_pins as lp
 from tests import test_oracle_pins as pins
 from tests.conftest import ROOT
 
@@ -54,14 +55,44 @@ MUTANTS = [
 ]
 
 
-def build_mutant(tmp_path, name, old, new):
-    text = open(SRC).read()
+LEARNED = os.path.join(ROOT, "oracle", "learned.c")
+
+# the learned form's checker (learned.c): same scheme
+LEARNED_MUTANTS = [
+    ("relu_dropped_layer2", "st->h[1][k] = rnd(st->a[1][k] > 0 ? st->a[1][k] : 0, mirror);",
+     "st->h[1][k] = rnd(st->a[1][k], mirror);",
+     [lambda: lp.test_gradient_matches_central_differences(0)]),
+    ("output_gradient_sign", "go[c] = rnd(2.0 * inv_n * (st.o[c] - z[c]), mirror);",
+     "go[c] = rnd(2.0 * inv_n * (z[c] - st.o[c]), mirror);",
+     [lambda: lp.test_gradient_matches_central_differences(1)]),
+    ("hidden_bias_skipped", "affine(theta + ORC_OFF_W2, theta + ORC_OFF_B2,",
+     "affine(theta + ORC_OFF_W2, NULL,", [lp.test_biases_of_hidden_layers_enter_after_the_product]),
+    ("adam_no_bias_correction", "const double mh = m[k] / c1, vh = v[k] / c2;",
+     "const double mh = m[k] + 0 * c1, vh = v[k] + 0 * c2;",
+     [lp.test_adam_first_step_moves_by_lr_in_sign_direction]),
+    ("bf16_ties_up", "else r = fmod(fl, 2.0) == 0.0 ? fl : fl + 1.0;", "else r = fl + 1.0;",
+     [lp.test_bf16_ties_go_to_even, lambda: lp.test_bf16_matches_library_conversion(0)]),
+    ("depth_block_transposed",
+     "const size_t d = ((size_t)(k * j + b + 1) * sd + (size_t)(k * i + a + 1)) * 2;",
+     "const size_t d = ((size_t)(k * i + b + 1) * sd + (size_t)(k * j + a + 1)) * 2;",
+     [lp.test_depth_feature_averages_the_covering_block]),
+    ("batch_index_offset", "uint64_t st = seed + (uint64_t)i;", "uint64_t st = seed + (uint64_t)i + 1;",
+     [lp.test_batch_index_is_splitmix64]),
+    ("input_not_rounded", "for (int k = 0; k < ORC_FEATURES; ++k) st->x[k] = rnd(x[k], mirror);",
+     "for (int k = 0; k < ORC_FEATURES; ++k) st->x[k] = x[k];",
+     [lp.test_mirror_mode_rounds_the_input]),
+]
+
+
+def build_mutant(tmp_path, name, old, new, target=SRC):
+    text = open(target).read()
     assert text.count(old) == 1, f"{name}: planted text not found exactly once"
-    src = tmp_path / f"oracle_{name}.c"
+    src = tmp_path / f"mutant_{name}.c"
     src.write_text(text.replace(old, new))
-    # the header sits beside the real source
+    sources = [str(src), LEARNED] if target == SRC else [SRC, str(src)]
+    # the headers sit beside the real sources
     out = tmp_path / f"liboracle_{name}.so"
-    subprocess.check_call(["gcc", *oracle.CFLAGS, f"-I{os.path.dirname(SRC)}", str(src),
+    subprocess.check_call(["gcc", *oracle.CFLAGS, f"-I{os.path.dirname(SRC)}", *sources,
                            "-o", str(out), "-lm"])
     return str(out)
 
@@ -77,6 +108,29 @@ def test_planted_mistake_fails_a_pin(tmp_path, name, old, new, catchers):
             except AssertionError:
                 failed += 1
         assert failed == len(catchers), f"{name}: {len(catchers) - failed} pin(s) did not notice"
+
+
+@pytest.mark.parametrize("name,old,new,catchers", LEARNED_MUTANTS,
+                         ids=[m[0] for m in LEARNED_MUTANTS])
+def test_planted_mistake_in_learned_form_fails_a_pin(tmp_path, name, old, new, catchers):
+    path = build_mutant(tmp_path, name, old, new, target=LEARNED)
+    with oracle.use_library(path):
+        failed = 0
+        for pin in catchers:
+            try:
+                pin()
+            except AssertionError:
+                failed += 1
+        assert failed == len(catchers), f"{name}: {len(catchers) - failed} pin(s) did not notice"
+
+
+def test_unmodified_learned_copy_passes_the_same_pins(tmp_path):
+    path = build_mutant(tmp_path, "identity_learned", "#include <math.h>", "#include <math.h>",
+                        target=LEARNED)
+    with oracle.use_library(path):
+        for _, _, _, catchers in LEARNED_MUTANTS:
+            for pin in catchers:
+                pin()
 
 
 def test_unmodified_copy_passes_the_same_pins(tmp_path):
