@@ -146,6 +146,11 @@ typedef struct {
     float sky_rgb[3];          /* radiance of escaping rays, finite, >= 0          */
     float albedo[3];           /* albedo where a level has no albedo grid          */
     uint32_t flags;            /* SDFDDGI_FLAG_*                                   */
+    /* Learned form (sdfddgi_update_frame_learned); 0 rays: not available. */
+    int32_t learned_rays;      /* low ray count: 0, or a multiple of 16 in 16..R   */
+    float fallback_error;      /* tau: mean predicted relative error above which a
+                                  probe takes the plain update, >= 0 (+inf: only
+                                  probes without history do)                       */
 } sdfddgi_params;
 
 /* Directional light: direction toward the light (any non-zero length; it is
@@ -157,7 +162,7 @@ typedef struct {
 
 /* Fill *p with the defaults used for the 8x8 / 16x16 maps: 144 rays, 64 steps,
  * eps 1e-3, t_max 2*sqrt(3), h 0.97, gain 1, s 50, bias 4e-3, relax 1, black
- * sky, albedo 0.5, no flags. Host only. */
+ * sky, albedo 0.5, no flags, no learned form (0 rays, tau 0.02). Host only. */
 void sdfddgi_default_params(sdfddgi_params *p);
 
 /* Create a context on the current HIP device: validates the arguments, copies
@@ -217,12 +222,14 @@ sdfddgi_status sdfddgi_get_ray_directions(sdfddgi_ctx *ctx, float *out);
  * pointer out [rays][3]); identical to what the GPU uses for that seed. */
 sdfddgi_status sdfddgi_ray_directions(uint64_t rotation_seed, int32_t rays, float *out);
 
-/* Mean per-kernel GPU times in milliseconds over the update_frame calls made
- * since the previous call of this function (at most the last 256), measured
- * with events recorded on the context's stream around each kernel:
- * [0] ray-direction/weight tables, [1] primary sphere trace, [2] hit
- * shading (normal, shadow ray, lookups), [3] blend, [4] whole frame.
- * Host pointer ms[count], count <= 5. Waits for the last timed frame.
+/* Mean per-kernel GPU times in milliseconds over the update_frame calls (plain
+ * or learned) made since the previous call of this function (at most the last
+ * 256), measured with events recorded on the context's stream around each
+ * kernel: [0] ray-direction/weight tables, [1] primary sphere trace, [2] hit
+ * shading (normal, shadow ray, lookups), [3] blend, [4] whole frame,
+ * [5] denoiser, [6] fallback trace (primary + hits), [7] fallback blend. In a
+ * learned frame [1]-[3] are the low-ray pass; [5]-[7] are 0 in a plain frame.
+ * Host pointer ms[count], count <= 8. Waits for the last timed frame.
  * ESTATE without SDFDDGI_FLAG_TIMING or when no frame ran since the last call. */
 sdfddgi_status sdfddgi_get_kernel_times(sdfddgi_ctx *ctx, float *ms, int32_t count);
 
@@ -238,6 +245,117 @@ const char *sdfddgi_last_error(const sdfddgi_ctx *ctx);
 /* Wait for the context's stream, then free everything the context owns.
  * NULL is a no-op. */
 sdfddgi_status sdfddgi_destroy(sdfddgi_ctx *ctx);
+
+/* ------------------------------------------------------------ learned form --
+ * An extension beyond the paper: each frame traces learned_rays rays per probe,
+ * forms the Eq. 3 estimate U_low from them (no hysteresis), and a per-texel
+ * network maps it, with the probe's history, to the estimate a many-ray set
+ * would give. Per interior irradiance texel t the network reads
+ *   x = (U_low/S [3], E_prev/S [3], mean E[d]/D, sqrt(mean E[d^2])/D over the
+ *        k x k depth texels covering t (k = depth_res/irr_res), texel direction
+ *        [3], clamp(probe signed distance / D, -4, 4), 1, 0, 0, 0)
+ * and computes h1 = relu(W1 x), h2 = relu(W2 h1 + b2), h3 = relu(W3 h2 + b3),
+ * o = W4 h3 + b4 (16 -> 64 -> 64 -> 64 -> 4) with bfloat16 weights, inputs and
+ * activations (round to nearest even) and FP32 accumulation on MFMA. The
+ * texel's update is U_hat = max(0, E_prev + S o[0..2]) and its predicted
+ * relative error exp(o[3]). A probe whose history is rejected, or whose mean
+ * predicted error over its texels exceeds fallback_error, takes the plain
+ * update with rays_per_probe rays; every other probe mixes U_hat into its
+ * irradiance (hysteresis, then borders) and the low-ray depth moments into its
+ * depth map. Requires learned_rays > 0 and depth_res a multiple of irr_res,
+ * irr_res <= 16.
+ *
+ * Parameter vector (binary32, SDFDDGI_DENOISER_PARAMS values, row-major):
+ *   W1 [64][16] | W2 [64][64] | b2 [64] | W3 [64][64] | b3 [64] | W4 [4][64] | b4 [4] */
+#define SDFDDGI_DENOISER_PARAMS 9604
+#define SDFDDGI_FEATURES 16
+
+typedef struct sdfddgi_denoiser sdfddgi_denoiser;
+
+/* Upload a network (host params[count], count == SDFDDGI_DENOISER_PARAMS, all
+ * finite) with its feature scales S = irr_scale and D = depth_scale (both > 0)
+ * to the current device and pack its bfloat16 MFMA operands. hip_stream as in
+ * sdfddgi_create. */
+sdfddgi_status sdfddgi_denoiser_create(const float *params, int32_t count, float irr_scale,
+                                       float depth_scale, void *hip_stream,
+                                       sdfddgi_denoiser **out);
+
+/* The network on n feature vectors: device features[n][16] -> device out[n][4]
+ * (o[0..3] above). n = 0 is a no-op. */
+sdfddgi_status sdfddgi_denoiser_infer(sdfddgi_denoiser *den, const float *features, int64_t n,
+                                      float *out);
+
+sdfddgi_status sdfddgi_denoiser_destroy(sdfddgi_denoiser *den);
+
+/* One learned frame (see above) on the context's stream; like update_frame it
+ * reads the current maps, writes the other pair, makes it current and clears
+ * the reject flags of the probes it updated plainly. ESTATE if the context was
+ * created with learned_rays == 0; EINVAL if den is on another device. */
+sdfddgi_status sdfddgi_update_frame_learned(sdfddgi_ctx *ctx, const sdfddgi_denoiser *den,
+                                            const sdfddgi_light *light, uint64_t rotation_seed);
+
+/* The last learned frame's fallback: *count (host) = number of probes that took
+ * the plain update; probes (device [P], may be NULL) receives their indices in
+ * no particular order, mean_error (device [P], may be NULL) every probe's mean
+ * predicted relative error. Waits for the stream. ESTATE before a learned frame. */
+sdfddgi_status sdfddgi_get_fallback(sdfddgi_ctx *ctx, int32_t *count, int32_t *probes,
+                                    float *mean_error);
+
+/* Training pairs for the network from the current maps, without changing them:
+ * traces learned_rays and target_rays (16..SDFDDGI_MAX_RAYS, multiple of 16) per
+ * probe for the frame, forms both Eq. 3 estimates without hysteresis, and writes
+ * for every probe p and interior irradiance texel t (row p*Ti + t):
+ *   features[.][16] = x above (the denoiser's S and D),
+ *   targets[.][4]   = ((U* - E_prev)/S [3], |U*|_1 / S + rel_floor)
+ * with U* the target-ray estimate. Device pointers; the context's stream. */
+sdfddgi_status sdfddgi_learned_examples(sdfddgi_ctx *ctx, const sdfddgi_denoiser *den,
+                                        const sdfddgi_light *light, uint64_t rotation_seed,
+                                        int32_t target_rays, float rel_floor, float *features,
+                                        float *targets);
+
+/* ---------------------------------------------------------------- training --
+ * Loss per sample (o = network output, (z, q) = targets row):
+ *   sum_c (o_c - z_c)^2 + head_weight * (o_3 - ln max(r, min_error))^2,
+ *   r = sum_c |o_c - z_c| / q, held constant in the gradient;
+ * the step's loss is the mean over its samples. Forward and backward run with
+ * the bfloat16 roundings of the forward pass above plus the output gradient and
+ * each hidden gradient (after its ReLU mask) rounded to bfloat16, FP32
+ * accumulation; Adam (Kingma and Ba 2015) updates binary32 masters. */
+typedef struct {
+    float head_weight;   /* weight of the error-head term, >= 0 */
+    float min_error;     /* floor of r in the log target, > 0   */
+    float beta1, beta2;  /* Adam moment decays, [0, 1)          */
+    float eps;           /* Adam denominator offset, >= 0       */
+} sdfddgi_train_config;
+
+typedef struct sdfddgi_trainer sdfddgi_trainer;
+
+sdfddgi_status sdfddgi_trainer_create(const float *init_params, int32_t count,
+                                      const sdfddgi_train_config *cfg, void *hip_stream,
+                                      sdfddgi_trainer **out);
+
+/* Mean loss and gradient over samples 0..n-1 of device features[n][16],
+ * targets[n][4], in order; grad (host [SDFDDGI_DENOISER_PARAMS]) and loss (host)
+ * may be NULL. Waits for the stream. Parameters are not changed. */
+sdfddgi_status sdfddgi_trainer_gradient(sdfddgi_trainer *tr, const float *features,
+                                        const float *targets, int32_t n, float *grad,
+                                        float *loss);
+
+/* One Adam step with learning rate lr on a minibatch of `batch` samples: sample
+ * i of the step is row (first SplitMix64 output of the state seed + i) mod count
+ * of the device arrays. loss (host, may be NULL) receives the minibatch loss
+ * before the update (and waits for the stream). */
+sdfddgi_status sdfddgi_trainer_step(sdfddgi_trainer *tr, const float *features,
+                                    const float *targets, int64_t count, int32_t batch,
+                                    uint64_t seed, float lr, float *loss);
+
+/* Copy the binary32 master parameters to host params[SDFDDGI_DENOISER_PARAMS]. */
+sdfddgi_status sdfddgi_trainer_get_params(sdfddgi_trainer *tr, float *params);
+
+sdfddgi_status sdfddgi_trainer_destroy(sdfddgi_trainer *tr);
+
+/* Message of the last failure of a denoiser or trainer call on this thread. */
+const char *sdfddgi_learned_last_error(void);
 
 #ifdef __cplusplus
 }

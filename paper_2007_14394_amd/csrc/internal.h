@@ -47,7 +47,10 @@ struct TraceArgs {
     float sky0, sky1, sky2;
     float alb0, alb1, alb2;
     const float *probe_pos;     // [P][3]
-    const int *probe_order;     // [P] probes in Morton order of (x, y, z): the tracing order
+    const int *probe_order;     // [P] probes in Morton order of (x, y, z): the tracing order,
+                                //     or the list of probes to trace
+    const int *probe_count;     // null: trace all P probes; else the device-side length of
+                                //     probe_order (the learned form's fallback list)
     const float *dirs;          // [R][3]
     const float *prev_irr;      // previous irradiance atlas
     float4 *payload;            // [P*R]
@@ -74,7 +77,8 @@ struct TableArgs {
     float *wt_d;                // [R][Tpd] w_ti^s, transposed; rows t >= Td stay zero
     float *norm_i;              // [Ti]  pi / sum_i w_ti   (-1: all weights vanish)
     float *norm_d;              // [Td]  1 / sum_i w_ti^s  (-1: all weights vanish)
-    int *counter;               // [3] the trace kernels' counters, reset here (may be null)
+    int *counter;               // [ncounter] counters reset here (may be null): the trace
+    int ncounter;               //     kernels' and, in the learned form, the fallback pass's
     int Rpad;                   // row length of the 16-bit tables: R rounded up to 64
     _Float16 *w16_i;            // precision form: [Tpi][Rpad] FP16 w_ti (else null)
     __bf16 *w16_d;              // precision form: [Tpd][Rpad] BF16 w_ti^s (else null)
@@ -90,7 +94,9 @@ struct BlendArgs {
     const __bf16 *w16_d;
     const float *prev_irr, *prev_depth;
     float *new_irr, *new_depth;
-    uint8_t *reject;
+    uint8_t *reject;            // per-probe history flags (read, then cleared); null: none
+    const int *probe_list;      // null: probes 0..P-1; else blend only these probes
+    const int *probe_count;     //     (device-side count; P bounds it)
 };
 
 struct SampleArgs {
@@ -112,5 +118,102 @@ hipError_t launch_sample(const SampleArgs &a, hipStream_t stream);
 hipError_t launch_pack_quads(const float *grid, int n0, int n1, int n2, bool half, void *quad,
                              hipStream_t stream);
 hipError_t launch_fill_u8(uint8_t *dst, uint8_t value, int64_t n, hipStream_t stream);
+
+}  // namespace sdfddgi
+
+// ------------------------------------------------------------ learned form --
+// A per-texel network (16 -> 64 -> 64 -> 64 -> 4, bfloat16 weights, FP32
+// accumulation on MFMA) maps a low-ray Eq. 3 update to the many-ray one. Parameter
+// vector (binary32 masters, row-major): W1[64][16] | W2[64][64] | b2[64] |
+// W3[64][64] | b3[64] | W4[4][64] | b4[4].
+namespace sdfddgi {
+
+constexpr int kFeatures = 16, kHidden = 64, kOutputs = 4;
+constexpr int kOffW1 = 0;
+constexpr int kOffW2 = kOffW1 + kHidden * kFeatures;
+constexpr int kOffB2 = kOffW2 + kHidden * kHidden;
+constexpr int kOffW3 = kOffB2 + kHidden;
+constexpr int kOffB3 = kOffW3 + kHidden * kHidden;
+constexpr int kOffW4 = kOffB3 + kHidden;
+constexpr int kOffB4 = kOffW4 + kOutputs * kHidden;
+constexpr int kMlpParams = kOffB4 + kOutputs;
+// Per-lane MFMA operand packs (16 bytes = 8 bfloat16 per lane and entry):
+// forward A operands of the four layers, backward A operands (transposed W4, W3, W2)
+constexpr int kFwdEntries = 22, kBwdEntries = 20;
+constexpr int kBiasFloats = 2 * kHidden + 16;   // b2 | b3 | b4 padded to 16
+constexpr int kMaxLearnedRes = 16;               // irradiance maps up to 16 x 16
+
+struct MlpPack {
+    const uint4 *fwd;     // [kFwdEntries][64]
+    const uint4 *bwd;     // [kBwdEntries][64]
+    const float *bias;    // [kBiasFloats]
+};
+
+// Inputs of the per-texel feature vector (see feature_group in learned.hip).
+struct FeatureArgs {
+    int irr_res, depth_res;
+    float inv_s, inv_d;           // 1/S and 1/D in binary32
+    const float *u_irr;           // low-ray Eq. 3 irradiance atlas (no hysteresis)
+    const float *prev_irr, *prev_depth;
+    const float *probe_sdf;       // [P] signed distance at each probe
+    const float *texel_dir;       // [Ti][3] texel centre directions (binary32)
+};
+
+struct DenoiseArgs {
+    FeatureArgs f;
+    int P;
+    float hysteresis, s, tau;
+    const uint8_t *reject;
+    const float *u_depth;         // low-ray depth moments atlas (no hysteresis)
+    float *new_irr, *new_depth;
+    MlpPack mlp;
+    int *fallback_list;           // [P] probes that take the plain update
+    int *fallback_count;          // zeroed before the launch
+    float *mean_error;            // [P] mean predicted relative error (may be null)
+};
+
+struct ExampleArgs {
+    FeatureArgs f;
+    int P;
+    const float *target_irr;      // many-ray Eq. 3 irradiance atlas (no hysteresis)
+    float rel_floor;              // added to |U*|_1 / S in the relative-error scale
+    float *features;              // [P*Ti][16]
+    float *targets;               // [P*Ti][4]: (U* - E_prev) / S, |U*|_1 / S + floor
+};
+
+struct InferArgs {
+    int64_t n;
+    const float *features;        // [n][16]
+    float *out;                   // [n][4]
+    MlpPack mlp;
+};
+
+struct TrainArgs {
+    const float *features, *targets;
+    int64_t count;                // samples available
+    int batch;                    // samples of this step
+    uint64_t seed;
+    int sequential;               // 1: samples 0..batch-1 in order; 0: SplitMix64 draws
+    MlpPack mlp;
+    float inv_n, head_weight, min_error;
+    float *grad;                  // [kMlpParams], accumulated (zero before the launch)
+    float *loss;                  // [1], accumulated
+};
+
+struct AdamArgs {
+    float *theta, *m, *v, *grad;  // grad is consumed and zeroed
+    int n;
+    float lr, beta1, beta2, eps, c1, c2;   // c1 = 1/(1-beta1^t), c2 = 1/(1-beta2^t)
+};
+
+hipError_t launch_probe_sdf(const TraceArgs &a, float *out, hipStream_t stream);
+hipError_t launch_pack_mlp(const float *theta, uint4 *fwd, uint4 *bwd, float *bias,
+                           hipStream_t stream);
+hipError_t launch_denoise(const DenoiseArgs &a, hipStream_t stream);
+hipError_t launch_examples(const ExampleArgs &a, hipStream_t stream);
+hipError_t launch_infer(const InferArgs &a, hipStream_t stream);
+hipError_t launch_train(const TrainArgs &a, hipStream_t stream);
+hipError_t launch_adam(const AdamArgs &a, hipStream_t stream);
+hipError_t launch_zero_f32(float *dst, int64_t n, hipStream_t stream);
 
 }  // namespace sdfddgi

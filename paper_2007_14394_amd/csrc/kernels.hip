@@ -15,6 +15,7 @@
 // one fixed binary32 operation sequence, spelled out with fmaf; contraction of
 // any other multiply-add is disabled for this file.
 #include "internal.h"
+#include "octahedral.h"
 
 #pragma clang fp contract(off)
 
@@ -319,7 +320,7 @@ __global__ __launch_bounds__(256) void primary_kernel(TraceArgs a) {
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     int staged = 0;  // wave-uniform count of entries in s_hits[wave]
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    const int total = a.P * a.R;
+    const int total = (a.probe_count ? *a.probe_count : a.P) * a.R;
     Feeder<kChunk> feed;
     bool active = false;
     int ray = 0, k = 0;
@@ -546,7 +547,7 @@ __global__ __launch_bounds__(256) void tables_kernel(TableArgs a) {
         part += w;
     }
     if (is_dirs) {
-        if (tid < 3 && a.counter) a.counter[tid] = 0;  // the trace kernels' counters
+        if (tid < a.ncounter && a.counter) a.counter[tid] = 0;  // trace (and fallback) counters
         return;
     }
     red[tid] = part;
@@ -563,27 +564,22 @@ __global__ __launch_bounds__(256) void tables_kernel(TableArgs a) {
     }
 }
 
-// Write interior texel (i, j) of an n x n map with `comps` channels into its padded
-// tile, together with every border texel that copies it: crossing an edge of the
-// octahedral square lands on the same edge reflected about its midpoint, and the
-// four corners take the diagonally opposite interior corner.
-__device__ __forceinline__ void store_with_border(float *__restrict__ tile, int n, int comps,
-                                                  int i, int j, int c, float v) {
-    const int side = n + 2;
-    tile[((j + 1) * side + (i + 1)) * comps + c] = v;
-    if (j == 0) tile[(0 * side + (n - i)) * comps + c] = v;
-    if (j == n - 1) tile[((n + 1) * side + (n - i)) * comps + c] = v;
-    if (i == 0) tile[((n - j) * side + 0) * comps + c] = v;
-    if (i == n - 1) tile[((n - j) * side + (n + 1)) * comps + c] = v;
-    if (i == n - 1 && j == n - 1) tile[0 * comps + c] = v;
-    if (i == 0 && j == n - 1) tile[(n + 1) * comps + c] = v;
-    if (i == n - 1 && j == 0) tile[((n + 1) * side) * comps + c] = v;
-    if (i == 0 && j == 0) tile[((n + 1) * side + (n + 1)) * comps + c] = v;
-}
-
+constexpr int kBlendProbes = 16;  // probes per workgroup: the N extent of a tile row
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-constexpr int kBlendProbes = 16;  // probes per workgroup: the N extent of a tile row
+// The probes of one blend workgroup (slots pb .. pb+np-1 of the probe list, or of
+// 0..P-1) and their hysteresis: none where the history is rejected. The first
+// __syncthreads of the caller's ray loop publishes them.
+__device__ __forceinline__ void load_blend_probes(const BlendArgs &a, int pb, int np, int *s_pid,
+                                                  float *s_h) {
+    const int tid = threadIdx.x;
+    if (tid < kBlendProbes) {
+        const int pid = tid < np ? (a.probe_list ? a.probe_list[pb + tid] : pb + tid) : 0;
+        s_pid[tid] = pid;
+        s_h[tid] = (tid < np && !(a.reject && a.reject[pid])) ? a.hysteresis : 0.0f;
+    }
+}
+
 constexpr int kBlendChunk = 64;   // rays staged in LDS at a time
 constexpr int kBlendPitch = kBlendChunk + 1;
 constexpr int kMSlots = 5;        // 16-texel M-tiles per wave per pass
@@ -600,7 +596,7 @@ constexpr int kMSlots = 5;        // 16-texel M-tiles per wave per pass
 // Epilogue of both blend kernels for one 16x16 accumulator tile: lane holds
 // D[4*krow + r][row]. Normalises, mixes with the previous interior (hysteresis, or
 // none for rejected probes) and writes interior and border texels.
-__device__ __forceinline__ void blend_epilogue(const BlendArgs &a, const float *s_h, int pb, int np,
+__device__ __forceinline__ void blend_epilogue(const BlendArgs &a, const float *s_h, const int *s_pid, int np,
                                                bool irr, int mtile, int n, int row, int krow,
                                                floatx4 acc) {
     const int res = irr ? a.irr_res : a.depth_res;
@@ -612,8 +608,8 @@ __device__ __forceinline__ void blend_epilogue(const BlendArgs &a, const float *
     const int c = irr ? col - 3 * q : col & 1;
     if (q >= np) return;
     const size_t tile_floats = (size_t)side * side * comps;
-    const float *old_tile = (irr ? a.prev_irr : a.prev_depth) + (size_t)(pb + q) * tile_floats;
-    float *new_tile = (irr ? a.new_irr : a.new_depth) + (size_t)(pb + q) * tile_floats;
+    const float *old_tile = (irr ? a.prev_irr : a.prev_depth) + (size_t)s_pid[q] * tile_floats;
+    float *new_tile = (irr ? a.new_irr : a.new_depth) + (size_t)s_pid[q] * tile_floats;
     const float h = s_h[q];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -641,15 +637,18 @@ __global__ __launch_bounds__(256) void blend16_kernel(BlendArgs a) {
     __shared__ __attribute__((aligned(16))) _Float16 si[(kBlendProbes * 3 + 1) * kPitch16];
     __shared__ __attribute__((aligned(16))) __bf16 sd[(kBlendProbes * 2 + 1) * kPitch16];
     __shared__ float s_h[kBlendProbes];
+    __shared__ int s_pid[kBlendProbes];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int row = lane & 15, kgrp = lane >> 4;
     const int pb = blockIdx.x * kBlendProbes;
-    const int np = min(kBlendProbes, a.P - pb);
+    const int count = a.probe_list ? min(*a.probe_count, a.P) : a.P;
+    if (pb >= count) return;
+    const int np = min(kBlendProbes, count - pb);
     const int Ti = a.irr_res * a.irr_res, Td = a.depth_res * a.depth_res;
     const int mti = (Ti + 15) >> 4, mtd = (Td + 15) >> 4;
     const int mtiles = mti + mtd;
-    if (tid < kBlendProbes) s_h[tid] = (tid < np && !a.reject[pb + tid]) ? a.hysteresis : 0.0f;
+    load_blend_probes(a, pb, np, s_pid, s_h);
     for (int e = tid; e < kPitch16; e += 256) {
         si[kBlendProbes * 3 * kPitch16 + e] = (_Float16)0.0f;
         sd[kBlendProbes * 2 * kPitch16 + e] = (__bf16)0.0f;
@@ -686,7 +685,7 @@ __global__ __launch_bounds__(256) void blend16_kernel(BlendArgs a) {
             for (int e = tid; e < kBlendProbes * kBlendChunk; e += 256) {
                 const int q = e / kBlendChunk, kk = e - q * kBlendChunk;
                 float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                if (q < np && kk < kc) v = a.payload[(size_t)(pb + q) * a.R + k0 + kk];
+                if (q < np && kk < kc) v = a.payload[(size_t)s_pid[q] * a.R + k0 + kk];
                 si[(q * 3 + 0) * kPitch16 + kk] = (_Float16)v.x;
                 si[(q * 3 + 1) * kPitch16 + kk] = (_Float16)v.y;
                 si[(q * 3 + 2) * kPitch16 + kk] = (_Float16)v.z;
@@ -728,13 +727,13 @@ __global__ __launch_bounds__(256) void blend16_kernel(BlendArgs a) {
 #pragma unroll
             for (int n = 0; n < 3; ++n) {
                 if (!irr && n == 2) break;
-                blend_epilogue(a, s_h, pb, np, irr, irr ? mt[s] : mt[s] - mti, n, row, kgrp,
+                blend_epilogue(a, s_h, s_pid, np, irr, irr ? mt[s] : mt[s] - mti, n, row, kgrp,
                                acc[s][n]);
             }
         }
     }
     __syncthreads();
-    if (tid < np) a.reject[pb + tid] = 0;
+    if (tid < np && a.reject) a.reject[s_pid[tid]] = 0;
 }
 
 // kStd: the 8x8 irradiance + 16x16 depth layout (4 + 16 M-tiles, one pass), where
@@ -745,11 +744,14 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a) {
     // payload of 16 probes x 4 channels x 64 rays, plus one zero row for absent probes
     __shared__ float sx[(kBlendProbes * 4 + 1) * kBlendPitch];
     __shared__ float s_h[kBlendProbes];
+    __shared__ int s_pid[kBlendProbes];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int row = lane & 15, krow = lane >> 4;
     const int pb = blockIdx.x * kBlendProbes;
-    const int np = min(kBlendProbes, a.P - pb);
+    const int count = a.probe_list ? min(*a.probe_count, a.P) : a.P;
+    if (pb >= count) return;
+    const int np = min(kBlendProbes, count - pb);
     const int ri = a.irr_res, rd = a.depth_res;
     const int Ti = ri * ri, Td = rd * rd;
     const int mti = (Ti + 15) >> 4, mtd = (Td + 15) >> 4;
@@ -757,7 +759,7 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a) {
     const int mtiles = mti + mtd;
     const int si = ri + 2, sd = rd + 2;
     constexpr int kZeroRow = kBlendProbes * 4 * kBlendPitch;
-    if (tid < kBlendProbes) s_h[tid] = (tid < np && !a.reject[pb + tid]) ? a.hysteresis : 0.0f;
+    load_blend_probes(a, pb, np, s_pid, s_h);
     for (int e = tid; e < kBlendPitch; e += 256) sx[kZeroRow + e] = 0.0f;
 
     // B-operand columns of this lane: irradiance (q, c) for 3 N-tiles, depth (q, m) for 2
@@ -796,7 +798,7 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a) {
             for (int e = tid; e < kBlendProbes * kBlendChunk; e += 256) {
                 const int q = e / kBlendChunk, kk = e - q * kBlendChunk;
                 float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                if (q < np && kk < kc) v = a.payload[(size_t)(pb + q) * a.R + k0 + kk];
+                if (q < np && kk < kc) v = a.payload[(size_t)s_pid[q] * a.R + k0 + kk];
                 float *d = sx + q * 4 * kBlendPitch + kk;
                 d[0] = v.x; d[kBlendPitch] = v.y; d[2 * kBlendPitch] = v.z; d[3 * kBlendPitch] = v.w;
             }
@@ -854,8 +856,8 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a) {
                 const int c = irr ? col - 3 * q : col & 1;
                 if (q >= np) continue;
                 const size_t tile_floats = (size_t)side * side * comps;
-                const float *old_tile = (irr ? a.prev_irr : a.prev_depth) + (size_t)(pb + q) * tile_floats;
-                float *new_tile = (irr ? a.new_irr : a.new_depth) + (size_t)(pb + q) * tile_floats;
+                const float *old_tile = (irr ? a.prev_irr : a.prev_depth) + (size_t)s_pid[q] * tile_floats;
+                float *new_tile = (irr ? a.new_irr : a.new_depth) + (size_t)s_pid[q] * tile_floats;
                 const float h = s_h[q];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
@@ -872,7 +874,19 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a) {
         }
     }
     __syncthreads();
-    if (tid < np) a.reject[pb + tid] = 0;
+    if (tid < np && a.reject) a.reject[s_pid[tid]] = 0;
+}
+
+// Signed distance at each probe position: the trace's own level choice and sampler.
+template <bool kHalf>
+__global__ __launch_bounds__(256) void probe_sdf_kernel(TraceArgs a, float *out) {
+    __shared__ LevelLds s_lv[kMaxLevels];
+    load_levels(a, s_lv);
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.P) return;
+    const float x0 = a.probe_pos[3 * p], x1 = a.probe_pos[3 * p + 1], x2 = a.probe_pos[3 * p + 2];
+    const int L = select_level(a, x0, x1, x2);
+    out[p] = L < 0 ? 1e30f : sample_at<kHalf>(s_lv[L], x0, x1, x2);
 }
 
 __global__ __launch_bounds__(256) void sample_kernel(SampleArgs a) {
@@ -992,6 +1006,14 @@ hipError_t launch_blend(const BlendArgs &a, hipStream_t s) {
         hipLaunchKernelGGL(blend_kernel<true>, grid, block, 0, s, a);
     else
         hipLaunchKernelGGL(blend_kernel<false>, grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_sdf(const TraceArgs &a, float *out, hipStream_t s) {
+    if (a.half_sdf)
+        hipLaunchKernelGGL(probe_sdf_kernel<true>, dim3(blocks_for(a.P, 256)), dim3(256), 0, s, a, out);
+    else
+        hipLaunchKernelGGL(probe_sdf_kernel<false>, dim3(blocks_for(a.P, 256)), dim3(256), 0, s, a, out);
     return hipGetLastError();
 }
 

@@ -1,0 +1,599 @@
+// gfx950 kernels of the learned form of the probe update (an extension beyond
+// the paper): a small per-texel network maps the Eq. 3 update of a low ray count,
+// with the probe's history, to the update of a many-ray set, and predicts its own
+// relative error; probes whose mean predicted error is too high take the plain
+// update instead.
+//
+//   pack_mlp_kernel   binary32 parameters -> per-lane bfloat16 MFMA operand packs
+//   denoise_kernel    per probe: features, network, decision, hysteresis and
+//                     border writes of accepted probes, fallback list of the rest
+//   examples_kernel   training pairs: features and many-ray targets per texel
+//   infer_kernel      the network on a feature array
+//   train_kernel      loss gradient over a minibatch (forward, backward, weight
+//                     gradients; all contractions on bfloat16 MFMA)
+//   adam_kernel       Adam update of the binary32 masters
+//
+// MFMA layout (v_mfma_f32_16x16x32_bf16, wave64): lane l = n + 16 g holds the A
+// operand A[n][8g .. 8g+7], the B operand B[8g .. 8g+7][n], and the result
+// D[4g + r][n] in register r. A layer's outputs (rows = units, columns = 16
+// texels) therefore sit as units 16 mt + 4 g + r of m-tile mt in lane (n, g). The
+// next layer contracts over those units in an order of its own choosing: k-step
+// ks, slot s of lane group g stands for unit 16 (2 ks + s/4) + 4 g + s%4, which
+// is exactly what the lane holds -- activations never leave registers. The
+// weight packs are written in that unit order.
+#include "internal.h"
+#include "octahedral.h"
+
+#include <algorithm>
+
+#pragma clang fp contract(off)
+
+namespace sdfddgi {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+
+// Unit of layer input slot s of k-step ks in lane group g (see above).
+__host__ __device__ __forceinline__ int unit_of(int ks, int g, int s) {
+    return 16 * (2 * ks + (s >> 2)) + 4 * g + (s & 3);
+}
+
+__device__ __forceinline__ bf16x8_t as_bf16x8(uint4 u) { return __builtin_bit_cast(bf16x8_t, u); }
+
+__device__ __forceinline__ floatx4 mfma(bf16x8_t a, bf16x8_t b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// ReLU, round to bfloat16 and regroup a layer's four m-tiles into the two B
+// operands (k-steps) of the next layer.
+__device__ __forceinline__ void relu_pack(const floatx4 d[4], bf16x8_t h[2]) {
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int s = 0; s < 8; ++s) h[ks][s] = (__bf16)fmaxf(d[2 * ks + (s >> 2)][s & 3], 0.0f);
+}
+
+__device__ __forceinline__ floatx4 bias4(const float *s_bias, int off) {
+    return floatx4{s_bias[off], s_bias[off + 1], s_bias[off + 2], s_bias[off + 3]};
+}
+
+// Forward pass of 16 texels (one per n); lanes g < 2 supply the input slots in xb.
+// d1..d3 keep the pre-activations, h1..h3 the bfloat16 activations as B operands.
+// Returns D of the output layer: lanes with g == 0 hold o[0..3] of texel n.
+__device__ __forceinline__ floatx4 mlp_forward(const bf16x8_t *wf, const float *s_bias, int g,
+                                               bf16x8_t xb, floatx4 d1[4], floatx4 d2[4],
+                                               floatx4 d3[4], bf16x8_t h1[2], bf16x8_t h2[2],
+                                               bf16x8_t h3[2]) {
+    const floatx4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) d1[mt] = mfma(wf[mt], xb, zero);
+    relu_pack(d1, h1);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        floatx4 acc = bias4(s_bias, 16 * mt + 4 * g);
+        acc = mfma(wf[4 + 2 * mt], h1[0], acc);
+        d2[mt] = mfma(wf[5 + 2 * mt], h1[1], acc);
+    }
+    relu_pack(d2, h2);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        floatx4 acc = bias4(s_bias, kHidden + 16 * mt + 4 * g);
+        acc = mfma(wf[12 + 2 * mt], h2[0], acc);
+        d3[mt] = mfma(wf[13 + 2 * mt], h2[1], acc);
+    }
+    relu_pack(d3, h3);
+    floatx4 o = bias4(s_bias, 2 * kHidden + 4 * g);
+    o = mfma(wf[20], h3[0], o);
+    return mfma(wf[21], h3[1], o);
+}
+
+__device__ __forceinline__ void load_pack(const MlpPack &m, bf16x8_t *wf, float *s_bias) {
+    const int lane = (int)__lane_id();
+#pragma unroll
+    for (int e = 0; e < kFwdEntries; ++e) wf[e] = as_bf16x8(m.fwd[e * 64 + lane]);
+    for (int e = threadIdx.x; e < kBiasFloats; e += blockDim.x) s_bias[e] = m.bias[e];
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// ------------------------------------------------------------------ packing --
+
+// One thread per (entry, lane) of the forward and backward packs, plus the biases.
+__global__ __launch_bounds__(256) void pack_mlp_kernel(const float *__restrict__ th,
+                                                       uint4 *__restrict__ fwd,
+                                                       uint4 *__restrict__ bwd,
+                                                       float *__restrict__ bias) {
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    const int total = (kFwdEntries + kBwdEntries) * 64;
+    if (id < kBiasFloats) {
+        float b = 0.0f;
+        if (id < kHidden) b = th[kOffB2 + id];
+        else if (id < 2 * kHidden) b = th[kOffB3 + id - kHidden];
+        else if (id - 2 * kHidden < kOutputs) b = th[kOffB4 + id - 2 * kHidden];
+        bias[id] = b;
+    }
+    if (id >= total) return;
+    const bool is_fwd = id < kFwdEntries * 64;
+    const int e = is_fwd ? id >> 6 : (id >> 6) - kFwdEntries;
+    const int lane = id & 63, m = lane & 15, g = lane >> 4;
+    bf16x8_t v;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        float w = 0.0f;
+        if (is_fwd) {
+            if (e < 4) {                       // layer 1, m-tile e: natural feature order
+                const int k = 8 * g + s;
+                if (k < kFeatures) w = th[kOffW1 + (16 * e + m) * kFeatures + k];
+            } else if (e < 20) {               // layers 2, 3: (m-tile, k-step)
+                const int q = e < 12 ? e - 4 : e - 12, mt = q >> 1, ks = q & 1;
+                const int off = e < 12 ? kOffW2 : kOffW3;
+                w = th[off + (16 * mt + m) * kHidden + unit_of(ks, g, s)];
+            } else {                           // layer 4, k-step e - 20, rows >= 4 are zero
+                if (m < kOutputs) w = th[kOffW4 + m * kHidden + unit_of(e - 20, g, s)];
+            }
+        } else {
+            if (e < 4) {                       // W4^T: rows = hidden units, k = outputs
+                const int k = 8 * g + s;
+                if (k < kOutputs) w = th[kOffW4 + k * kHidden + 16 * e + m];
+            } else {                           // W3^T (e < 12), W2^T: (m-tile, k-step)
+                const int q = e < 12 ? e - 4 : e - 12, mt = q >> 1, ks = q & 1;
+                const int off = e < 12 ? kOffW3 : kOffW2;
+                w = th[off + unit_of(ks, g, s) * kHidden + 16 * mt + m];
+            }
+        }
+        v[s] = (__bf16)w;
+    }
+    const uint4 u = __builtin_bit_cast(uint4, v);
+    if (is_fwd) fwd[id] = u;
+    else bwd[id - kFwdEntries * 64] = u;
+}
+
+// ----------------------------------------------------------------- features --
+
+// Slots 8g .. 8g+7 of the feature vector of interior irradiance texel t of probe p:
+//   g = 0:  U_low / S (3), E_prev / S (3), mean E[t] / D, sqrt(mean E[t^2]) / D over
+//           the k x k depth texels covering the texel (k = depth_res / irr_res)
+//   g = 1:  texel direction (3), clamp(probe distance / D, -4, 4), 1, 0, 0, 0
+__device__ __forceinline__ void feature_group(const FeatureArgs &f, int p, int t, int g,
+                                              float v[8]) {
+    const int ri = f.irr_res, rd = f.depth_res;
+    const int i = t % ri, j = t / ri;
+    if (g == 0) {
+        const int si = ri + 2, sd = rd + 2;
+        const size_t ti = (size_t)p * si * si * 3 + ((size_t)(j + 1) * si + (i + 1)) * 3;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            v[c] = f.u_irr[ti + c] * f.inv_s;
+            v[3 + c] = f.prev_irr[ti + c] * f.inv_s;
+        }
+        const int k = rd / ri;
+        const float *dt = f.prev_depth + (size_t)p * sd * sd * 2;
+        float m1 = 0.0f, m2 = 0.0f;
+        for (int b = 0; b < k; ++b)
+            for (int a = 0; a < k; ++a) {
+                const float *d = dt + ((size_t)(k * j + b + 1) * sd + (k * i + a + 1)) * 2;
+                m1 += d[0];
+                m2 += d[1];
+            }
+        const float inv_kk = 1.0f / (float)(k * k);
+        v[6] = m1 * inv_kk * f.inv_d;
+        v[7] = sqrtf(fmaxf(m2 * inv_kk, 0.0f)) * f.inv_d;
+    } else {
+        v[0] = f.texel_dir[3 * t];
+        v[1] = f.texel_dir[3 * t + 1];
+        v[2] = f.texel_dir[3 * t + 2];
+        v[3] = fminf(fmaxf(f.probe_sdf[p] * f.inv_d, -4.0f), 4.0f);
+        v[4] = 1.0f;
+        v[5] = v[6] = v[7] = 0.0f;
+    }
+}
+
+__device__ __forceinline__ bf16x8_t to_bf16x8(const float v[8]) {
+    bf16x8_t b;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) b[s] = (__bf16)v[s];
+    return b;
+}
+
+// ------------------------------------------------------------------ denoise --
+
+constexpr int kWaves = 4;
+
+// One wave per probe (waves stride over probes). Per 16-texel tile: features, the
+// network, U_hat = max(0, E_prev + S o[0..2]) staged in LDS, and exp(o[3]) summed.
+// The probe falls back (appended to the list, nothing written) when its history is
+// rejected or its mean predicted error exceeds tau; otherwise its irradiance
+// interior and borders take the hysteresis mix with U_hat and its depth moments the
+// mix with the low-ray update.
+__global__ __launch_bounds__(256) void denoise_kernel(DenoiseArgs a) {
+    __shared__ float s_bias[kBiasFloats];
+    __shared__ float s_u[kWaves][kMaxLearnedRes * kMaxLearnedRes * 3];
+    bf16x8_t wf[kFwdEntries];
+    load_pack(a.mlp, wf, s_bias);
+    __syncthreads();
+    const int lane = (int)__lane_id(), n = lane & 15, g = lane >> 4;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int ri = a.f.irr_res, Ti = ri * ri, tiles = (Ti + 15) >> 4;
+    const int si = ri + 2, sd = a.f.depth_res + 2;
+    const size_t tile_i = (size_t)si * si * 3, tile_d = (size_t)sd * sd * 2;
+    float *su = s_u[wave];
+    for (int p = blockIdx.x * kWaves + wave; p < a.P; p += gridDim.x * kWaves) {
+        float esum = 0.0f;
+        for (int tile = 0; tile < tiles; ++tile) {
+            const int t = tile * 16 + n;
+            float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (g < 2 && t < Ti) feature_group(a.f, p, t, g, v);
+            floatx4 d1[4], d2[4], d3[4];
+            bf16x8_t h1[2], h2[2], h3[2];
+            const floatx4 o = mlp_forward(wf, s_bias, g, to_bf16x8(v), d1, d2, d3, h1, h2, h3);
+            if (g == 0 && t < Ti) {
+                const float *prev = a.f.prev_irr + (size_t)p * tile_i +
+                                    ((size_t)(t / ri + 1) * si + (t % ri + 1)) * 3;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) su[3 * t + c] = fmaxf(0.0f, fmaf(a.s, o[c], prev[c]));
+                esum += expf(o[3]);
+            }
+        }
+        const float mean = wave_sum(esum) / (float)Ti;
+        if (a.mean_error && lane == 0) a.mean_error[p] = mean;
+        if (a.reject[p] != 0 || mean > a.tau) {
+            if (lane == 0) a.fallback_list[atomicAdd(a.fallback_count, 1)] = p;
+            continue;
+        }
+        __builtin_amdgcn_wave_barrier();
+        const float h = a.hysteresis;
+        const float *old_i = a.f.prev_irr + (size_t)p * tile_i;
+        float *new_i = a.new_irr + (size_t)p * tile_i;
+        for (int e = lane; e < Ti * 3; e += 64) {
+            const int t = e / 3, c = e - 3 * (e / 3);
+            const int i = t % ri, j = t / ri;
+            const float u = su[e];
+            const float old = old_i[((j + 1) * si + (i + 1)) * 3 + c];
+            store_with_border(new_i, ri, 3, i, j, c, fmaf(h, old - u, u));
+        }
+        const float *old_d = a.f.prev_depth + (size_t)p * tile_d;
+        const float *ud = a.u_depth + (size_t)p * tile_d;
+        float *new_d = a.new_depth + (size_t)p * tile_d;
+        for (int e = lane; e < (int)tile_d; e += 64) {
+            const float u = ud[e];
+            new_d[e] = fmaf(h, old_d[e] - u, u);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// ---------------------------------------------------------------- examples ---
+
+// One thread per (probe, texel): the 16 features and the target pair.
+__global__ __launch_bounds__(256) void examples_kernel(ExampleArgs a) {
+    const int Ti = a.f.irr_res * a.f.irr_res;
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (int64_t)a.P * Ti) return;
+    const int p = (int)(id / Ti), t = (int)(id - (int64_t)p * Ti);
+    float v[8];
+    float *x = a.features + id * kFeatures;
+    feature_group(a.f, p, t, 0, v);
+#pragma unroll
+    for (int s = 0; s < 8; ++s) x[s] = v[s];
+    feature_group(a.f, p, t, 1, v);
+#pragma unroll
+    for (int s = 0; s < 8; ++s) x[8 + s] = v[s];
+    const int ri = a.f.irr_res, si = ri + 2;
+    const size_t at = (size_t)p * si * si * 3 + ((size_t)(t / ri + 1) * si + (t % ri + 1)) * 3;
+    float *z = a.targets + id * 4;
+    float l1 = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float u = a.target_irr[at + c];
+        z[c] = (u - a.f.prev_irr[at + c]) * a.f.inv_s;
+        l1 += fabsf(u);
+    }
+    z[3] = l1 * a.f.inv_s + a.rel_floor;
+}
+
+// ------------------------------------------------------------------- infer ---
+
+__global__ __launch_bounds__(256) void infer_kernel(InferArgs a) {
+    __shared__ float s_bias[kBiasFloats];
+    bf16x8_t wf[kFwdEntries];
+    load_pack(a.mlp, wf, s_bias);
+    __syncthreads();
+    const int lane = (int)__lane_id(), n = lane & 15, g = lane >> 4;
+    const int64_t tiles = (a.n + 15) >> 4;
+    for (int64_t tile = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); tile < tiles;
+         tile += (int64_t)gridDim.x * kWaves) {
+        const int64_t q = tile * 16 + n;
+        float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (g < 2 && q < a.n) {
+            const float *x = a.features + q * kFeatures + 8 * g;
+#pragma unroll
+            for (int s = 0; s < 8; ++s) v[s] = x[s];
+        }
+        floatx4 d1[4], d2[4], d3[4];
+        bf16x8_t h1[2], h2[2], h3[2];
+        const floatx4 o = mlp_forward(wf, s_bias, g, to_bf16x8(v), d1, d2, d3, h1, h2, h3);
+        if (g == 0 && q < a.n) {
+            float *out = a.out + q * kOutputs;
+            out[0] = o[0]; out[1] = o[1]; out[2] = o[2]; out[3] = o[3];
+        }
+    }
+}
+
+// ------------------------------------------------------------------- train ---
+
+constexpr int kTrainBlock = 128;             // samples per workgroup iteration
+constexpr int kRowPitch = kTrainBlock + 8;   // bfloat16 per LDS row (+8 spreads banks)
+// LDS rows: inputs, activations of the three hidden layers, output gradients
+// (rows >= 4 stay zero), hidden gradients after their ReLU masks
+constexpr int kRowX = 0, kRowH1 = 16, kRowH2 = 80, kRowH3 = 144, kRowDO = 208;
+constexpr int kRowG1 = 224, kRowG2 = 288, kRowG3 = 352, kRows = 416;
+
+__device__ __forceinline__ uint64_t splitmix_first(uint64_t state) {
+    uint64_t z = state + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Store a layer's D-layout values (unit 16 mt + 4 g + r of sample column) as
+// bfloat16 rows of the LDS matrix starting at `row0`.
+__device__ __forceinline__ void store_units(__bf16 *lds, int row0, int g, int col,
+                                            const floatx4 d[4], bool relu) {
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const float v = relu ? fmaxf(d[mt][r], 0.0f) : d[mt][r];
+            lds[(row0 + 16 * mt + 4 * g + r) * kRowPitch + col] = (__bf16)v;
+        }
+}
+
+// Hidden gradient of one layer from the next layer's gradient B operands:
+// D = W^T g_next (per m-tile, two k-steps), masked where the pre-activation is <= 0.
+__device__ __forceinline__ void back_layer(const bf16x8_t *wb, const bf16x8_t gn[2],
+                                           const floatx4 pre[4], floatx4 out[4]) {
+    const floatx4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        floatx4 acc = mfma(wb[2 * mt], gn[0], zero);
+        acc = mfma(wb[2 * mt + 1], gn[1], acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) out[mt][r] = pre[mt][r] > 0.0f ? acc[r] : 0.0f;
+    }
+}
+
+// Gradient of the mean loss over the step's samples (see the checker's loss). Each
+// workgroup iteration takes 128 samples: every wave runs 2 x 16 of them forward and
+// backward in registers and writes inputs, activations and gradients as bfloat16
+// rows to LDS; then the 40 weight-gradient tiles (dW1 4, dW2 16, dW3 16, dW4 4) are
+// contracted over the samples on MFMA, 10 per wave, accumulating in registers across
+// iterations, and the bias gradients are summed from the same rows. One atomic add
+// per gradient element and workgroup at the end.
+__global__ __launch_bounds__(256) void train_kernel(TrainArgs a) {
+    __shared__ float s_bias[kBiasFloats];
+    __shared__ __attribute__((aligned(16))) __bf16 s_m[kRows * kRowPitch];
+    __shared__ float s_loss[kWaves];
+    bf16x8_t wf[kFwdEntries], wb[kBwdEntries];
+    load_pack(a.mlp, wf, s_bias);
+    const int lane = (int)__lane_id(), n = lane & 15, g = lane >> 4;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+#pragma unroll
+    for (int e = 0; e < kBwdEntries; ++e) wb[e] = as_bf16x8(a.mlp.bwd[e * 64 + lane]);
+    for (int e = threadIdx.x; e < 16 * kRowPitch; e += blockDim.x)
+        s_m[kRowDO * kRowPitch + e] = (__bf16)0.0f;
+    __syncthreads();
+
+    floatx4 acc[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) acc[k] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    float bsum = 0.0f;     // bias gradient of row threadIdx.x (< 132)
+    float lsum = 0.0f;
+    const floatx4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+
+    const int blocks = (a.batch + kTrainBlock - 1) / kTrainBlock;
+    for (int blk = blockIdx.x; blk < blocks; blk += gridDim.x) {
+        // ---- forward and backward, 2 x 16 samples per wave
+        for (int half = 0; half < 2; ++half) {
+            const int col = wave * 32 + half * 16 + n;       // sample column in LDS
+            const int pos = blk * kTrainBlock + col;         // position in the batch
+            const bool valid = pos < a.batch;
+            int64_t idx = 0;
+            if (valid) idx = a.sequential ? pos : (int64_t)(splitmix_first(a.seed + (uint64_t)pos) %
+                                                            (uint64_t)a.count);
+            float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (g < 2 && valid) {
+                const float *x = a.features + idx * kFeatures + 8 * g;
+#pragma unroll
+                for (int s = 0; s < 8; ++s) v[s] = x[s];
+            }
+            const bf16x8_t xb = to_bf16x8(v);
+            floatx4 d1[4], d2[4], d3[4];
+            bf16x8_t h1[2], h2[2], h3[2];
+            const floatx4 o = mlp_forward(wf, s_bias, g, xb, d1, d2, d3, h1, h2, h3);
+            // output gradient (lanes g == 0 own the sample's four outputs)
+            float go[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            if (g == 0 && valid) {
+                const float *z = a.targets + idx * 4;
+                float err = 0.0f, sq = 0.0f;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float dlt = o[c] - z[c];
+                    sq += dlt * dlt;
+                    err += fabsf(dlt);
+                    go[c] = 2.0f * a.inv_n * dlt;
+                }
+                const float r = err / z[3];
+                const float dh = o[3] - logf(fmaxf(r, a.min_error));
+                go[3] = 2.0f * a.head_weight * a.inv_n * dh;
+                lsum += (sq + a.head_weight * dh * dh) * a.inv_n;
+            }
+            bf16x8_t gb[2];
+            gb[0] = bf16x8_t{(__bf16)go[0], (__bf16)go[1], (__bf16)go[2], (__bf16)go[3],
+                             (__bf16)0.0f, (__bf16)0.0f, (__bf16)0.0f, (__bf16)0.0f};
+            // hidden gradients: W4^T (k = outputs, one k-step), then W3^T, W2^T
+            floatx4 g3[4], g2[4], g1[4];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                const floatx4 t = mfma(wb[mt], gb[0], zero);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) g3[mt][r] = d3[mt][r] > 0.0f ? t[r] : 0.0f;
+            }
+            bf16x8_t g3b[2], g2b[2];
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+                for (int s = 0; s < 8; ++s) g3b[ks][s] = (__bf16)g3[2 * ks + (s >> 2)][s & 3];
+            back_layer(wb + 4, g3b, d2, g2);
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+                for (int s = 0; s < 8; ++s) g2b[ks][s] = (__bf16)g2[2 * ks + (s >> 2)][s & 3];
+            back_layer(wb + 12, g2b, d1, g1);
+            // rows for the weight-gradient contractions
+            if (g < 2)
+#pragma unroll
+                for (int s = 0; s < 8; ++s) s_m[(kRowX + 8 * g + s) * kRowPitch + col] = xb[s];
+            store_units(s_m, kRowH1, g, col, d1, true);
+            store_units(s_m, kRowH2, g, col, d2, true);
+            store_units(s_m, kRowH3, g, col, d3, true);
+            store_units(s_m, kRowG1, g, col, g1, false);
+            store_units(s_m, kRowG2, g, col, g2, false);
+            store_units(s_m, kRowG3, g, col, g3, false);
+            if (g == 0)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) s_m[(kRowDO + c) * kRowPitch + col] = gb[0][c];
+        }
+        __syncthreads();
+        // ---- weight gradients: tile k of this wave is tile id wave + 4 k
+#pragma unroll
+        for (int k = 0; k < 10; ++k) {
+            const int id = wave + 4 * k;
+            int arow, brow;
+            if (id < 4) { arow = kRowG1 + 16 * id; brow = kRowX; }
+            else if (id < 20) { arow = kRowG2 + 16 * ((id - 4) >> 2); brow = kRowH1 + 16 * ((id - 4) & 3); }
+            else if (id < 36) { arow = kRowG3 + 16 * ((id - 20) >> 2); brow = kRowH2 + 16 * ((id - 20) & 3); }
+            else { arow = kRowDO; brow = kRowH3 + 16 * (id - 36); }
+#pragma unroll
+            for (int k0 = 0; k0 < kTrainBlock; k0 += 32) {
+                const bf16x8_t av = *reinterpret_cast<const bf16x8_t *>(
+                    &s_m[(arow + n) * kRowPitch + k0 + 8 * g]);
+                const bf16x8_t bv = *reinterpret_cast<const bf16x8_t *>(
+                    &s_m[(brow + n) * kRowPitch + k0 + 8 * g]);
+                acc[k] = mfma(av, bv, acc[k]);
+            }
+        }
+        // bias gradients: rows G2 (b2), G3 (b3), DO 0..3 (b4)
+        if (threadIdx.x < 2 * kHidden + kOutputs) {
+            const int row = threadIdx.x < kHidden ? kRowG2 + threadIdx.x
+                          : threadIdx.x < 2 * kHidden ? kRowG3 + threadIdx.x - kHidden
+                                                      : kRowDO + threadIdx.x - 2 * kHidden;
+            float sum = 0.0f;
+            for (int c = 0; c < kTrainBlock; ++c) sum += (float)s_m[row * kRowPitch + c];
+            bsum += sum;
+        }
+        __syncthreads();
+    }
+    // ---- accumulate into the global gradient: D[4g + r][n] of tile (out mt, in nt)
+#pragma unroll
+    for (int k = 0; k < 10; ++k) {
+        const int id = wave + 4 * k;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 4 * g + r;
+            int dst;
+            if (id < 4) dst = kOffW1 + (16 * id + row) * kFeatures + n;
+            else if (id < 20) dst = kOffW2 + (16 * ((id - 4) >> 2) + row) * kHidden + 16 * ((id - 4) & 3) + n;
+            else if (id < 36) dst = kOffW3 + (16 * ((id - 20) >> 2) + row) * kHidden + 16 * ((id - 20) & 3) + n;
+            else dst = row < kOutputs ? kOffW4 + row * kHidden + 16 * (id - 36) + n : -1;
+            if (dst >= 0) atomicAdd(a.grad + dst, acc[k][r]);
+        }
+    }
+    if (threadIdx.x < 2 * kHidden + kOutputs) {
+        const int dst = threadIdx.x < kHidden ? kOffB2 + threadIdx.x
+                      : threadIdx.x < 2 * kHidden ? kOffB3 + threadIdx.x - kHidden
+                                                  : kOffB4 + threadIdx.x - 2 * kHidden;
+        atomicAdd(a.grad + dst, bsum);
+    }
+    const float wl = wave_sum(lsum);
+    if (lane == 0) s_loss[wave] = wl;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(a.loss, s_loss[0] + s_loss[1] + s_loss[2] + s_loss[3]);
+}
+
+__global__ __launch_bounds__(256) void adam_kernel(AdamArgs a) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.n) return;
+    const float g = a.grad[k];
+    const float m = a.beta1 * a.m[k] + (1.0f - a.beta1) * g;
+    const float v = a.beta2 * a.v[k] + (1.0f - a.beta2) * g * g;
+    a.m[k] = m;
+    a.v[k] = v;
+    a.theta[k] -= a.lr * (m * a.c1) / (sqrtf(v * a.c2) + a.eps);
+    a.grad[k] = 0.0f;
+}
+
+__global__ __launch_bounds__(256) void zero_f32_kernel(float *dst, int64_t n) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) dst[k] = 0.0f;
+}
+
+// ---------------------------------------------------------------- launchers --
+
+static unsigned grid_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+static int device_cus() {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    return cus > 0 ? cus : 256;
+}
+
+hipError_t launch_pack_mlp(const float *theta, uint4 *fwd, uint4 *bwd, float *bias,
+                           hipStream_t s) {
+    const int total = (kFwdEntries + kBwdEntries) * 64;
+    hipLaunchKernelGGL(pack_mlp_kernel, dim3(grid_for(total, 256)), dim3(256), 0, s, theta, fwd,
+                       bwd, bias);
+    return hipGetLastError();
+}
+
+hipError_t launch_denoise(const DenoiseArgs &a, hipStream_t s) {
+    const int blocks = (int)std::min<int64_t>(grid_for(a.P, kWaves), 8 * device_cus());
+    hipLaunchKernelGGL(denoise_kernel, dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_examples(const ExampleArgs &a, hipStream_t s) {
+    const int64_t n = (int64_t)a.P * a.f.irr_res * a.f.irr_res;
+    hipLaunchKernelGGL(examples_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_infer(const InferArgs &a, hipStream_t s) {
+    const int64_t tiles = (a.n + 15) / 16;
+    const int blocks = (int)std::min<int64_t>(grid_for(tiles, kWaves), 8 * device_cus());
+    hipLaunchKernelGGL(infer_kernel, dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_train(const TrainArgs &a, hipStream_t s) {
+    const int blocks = (int)std::min<int64_t>(grid_for(a.batch, kTrainBlock), device_cus());
+    hipLaunchKernelGGL(train_kernel, dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(const AdamArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(adam_kernel, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_f32(float *dst, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_f32_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, dst, n);
+    return hipGetLastError();
+}
+
+}  // namespace sdfddgi

@@ -26,7 +26,7 @@ thread_local std::string g_create_error;
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kTimingRing = 256;
-constexpr int kEvents = 5;
+constexpr int kEvents = 8;
 
 // ---------------------------------------------------------- frame constants --
 
@@ -104,6 +104,25 @@ bool finite_all(const float *v, int n) {
 
 }  // namespace
 
+// One set of ray directions with its tables and per-ray buffers: the frame's
+// rays (rays_per_probe), the learned form's low ray count, and the target set of
+// the training pairs.
+struct RaySet {
+    int R = 0, Rpad = 0;
+    double *base = nullptr;          // [R][3] unrotated spherical-Fibonacci set
+    float *dirs = nullptr, *wt_i = nullptr, *wt_d = nullptr, *norm_i = nullptr, *norm_d = nullptr;
+    _Float16 *w16_i = nullptr;       // precision-form weight tables [T][Rpad]
+    __bf16 *w16_d = nullptr;
+    float4 *payload = nullptr;       // [P][R]
+    int4 *hitq = nullptr;            // [P][R]
+    TraceGrid grid;
+};
+
+// Counters of one frame: [0..2] the trace pass over all probes (rays claimed,
+// queue entries claimed, queue length), [3..5] the second trace pass (the learned
+// form's fallback probes, or the target rays of training pairs), [6] fallback count.
+constexpr int kCounters = 8;
+
 struct sdfddgi_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -117,26 +136,26 @@ struct sdfddgi_ctx {
     float *alb[kMaxLevels]{};
     sdfddgi_probe_grid pg{};
     int64_t P = 0;
-    int R = 0, Ti = 0, Td = 0, Tpi = 0, Tpd = 0;
+    int Ti = 0, Td = 0, Tpi = 0, Tpd = 0;
     int64_t irr_floats = 0, depth_floats = 0;
     float *probe_pos = nullptr;
     int *probe_order = nullptr;
-    double *base_dirs = nullptr, *texel_i = nullptr, *texel_d = nullptr;
-    float *dirs = nullptr, *wt_i = nullptr, *wt_d = nullptr, *norm_i = nullptr, *norm_d = nullptr;
-    _Float16 *w16_i = nullptr;   // precision-form weight tables [T][Rpad]
-    __bf16 *w16_d = nullptr;
-    int Rpad = 0;
+    double *texel_i = nullptr, *texel_d = nullptr;
+    RaySet main, low, target;
     float *irr[2]{}, *depth[2]{};
     int cur = 0;
     uint8_t *reject = nullptr;
-    int *counter = nullptr;
-    int4 *hitq = nullptr;
-    TraceGrid grid;
-    float4 *payload = nullptr;
+    int *counter = nullptr;      // [kCounters]
     int *records = nullptr;
-    bool have_frame = false, have_records = false;
-    // Timing: kEvents events per frame (before tables, after tables, after the
-    // primary trace, after the hit kernel, after the blend) in a ring;
+    bool have_frame = false, have_records = false, have_learned = false;
+    // learned form
+    float *u_irr = nullptr, *u_depth = nullptr;      // low-ray estimates (no hysteresis)
+    float *t_irr = nullptr, *t_depth = nullptr;      // target-ray estimates
+    float *probe_sdf = nullptr;                      // [P]
+    float *texel_dir = nullptr;                      // [Ti][3] binary32
+    int *fallback = nullptr;                         // [P]
+    float *mean_error = nullptr;                     // [P]
+    // Timing: kEvents events per frame in a ring (see sdfddgi_get_kernel_times);
     // sdfddgi_get_kernel_times averages the frames recorded since its previous call.
     hipEvent_t *ev_ring = nullptr;
     int ring_head = 0;
@@ -144,7 +163,28 @@ struct sdfddgi_ctx {
     std::string err;
 };
 
+struct sdfddgi_denoiser {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    float S = 1.0f, D = 1.0f;
+    float *theta = nullptr;
+    uint4 *fwd = nullptr, *bwd = nullptr;
+    float *bias = nullptr;
+};
+
+struct sdfddgi_trainer {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    sdfddgi_train_config cfg{};
+    int64_t step = 0;
+    float *theta = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr, *loss = nullptr;
+    uint4 *fwd = nullptr, *bwd = nullptr;
+    float *bias = nullptr;
+};
+
 namespace {
+
+thread_local std::string g_learned_error;
 
 sdfddgi_status fail(sdfddgi_ctx *c, sdfddgi_status s, const char *fmt, ...) {
     char buf[512];
@@ -163,6 +203,21 @@ sdfddgi_status hip_fail(sdfddgi_ctx *c, hipError_t e, const char *what) {
     return fail(c, SDFDDGI_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
+sdfddgi_status lfail(sdfddgi_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_learned_error = buf;
+    return s;
+}
+
+sdfddgi_status lhip_fail(hipError_t e, const char *what) {
+    if (e == hipErrorOutOfMemory) return lfail(SDFDDGI_ENOMEM, "%s: out of device memory", what);
+    return lfail(SDFDDGI_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
 template <typename T>
 hipError_t dev_alloc(T **p, size_t count) {
     *p = nullptr;
@@ -170,22 +225,40 @@ hipError_t dev_alloc(T **p, size_t count) {
     return hipMalloc((void **)p, count * sizeof(T));
 }
 
+template <typename T>
+void dev_free(T *&p) {
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+void free_set(RaySet &r) {
+    dev_free(r.base); dev_free(r.dirs); dev_free(r.wt_i); dev_free(r.wt_d);
+    dev_free(r.norm_i); dev_free(r.norm_d); dev_free(r.w16_i); dev_free(r.w16_d);
+    dev_free(r.payload); dev_free(r.hitq);
+    r.R = r.Rpad = 0;
+}
+
 void free_all(sdfddgi_ctx *c) {
     for (int L = 0; L < kMaxLevels; ++L) {
-        if (c->quad[L]) (void)hipFree(c->quad[L]);
-        if (c->alb[L]) (void)hipFree(c->alb[L]);
+        dev_free(c->quad[L]);
+        dev_free(c->alb[L]);
     }
-    void *bufs[] = {c->probe_pos, c->probe_order, c->base_dirs, c->texel_i, c->texel_d, c->dirs, c->wt_i,
-                    c->wt_d, c->norm_i, c->norm_d, c->w16_i, c->w16_d, c->irr[0], c->irr[1], c->depth[0],
-                    c->depth[1], c->reject, c->counter, c->hitq, c->payload, c->records};
-    for (void *b : bufs)
-        if (b) (void)hipFree(b);
+    free_set(c->main);
+    free_set(c->low);
+    free_set(c->target);
+    dev_free(c->probe_pos); dev_free(c->probe_order); dev_free(c->texel_i); dev_free(c->texel_d);
+    dev_free(c->irr[0]); dev_free(c->irr[1]); dev_free(c->depth[0]); dev_free(c->depth[1]);
+    dev_free(c->reject); dev_free(c->counter); dev_free(c->records);
+    dev_free(c->u_irr); dev_free(c->u_depth); dev_free(c->t_irr); dev_free(c->t_depth);
+    dev_free(c->probe_sdf); dev_free(c->texel_dir); dev_free(c->fallback); dev_free(c->mean_error);
     if (c->ev_ring) {
         for (int k = 0; k < kEvents * kTimingRing; ++k)
             if (c->ev_ring[k]) (void)hipEventDestroy(c->ev_ring[k]);
         delete[] c->ev_ring;
     }
 }
+
+bool valid_rays(int R) { return R >= 16 && R <= kMaxRays && R % 16 == 0; }
 
 sdfddgi_status validate(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_grid *pg,
                         const sdfddgi_params *p) {
@@ -217,7 +290,7 @@ sdfddgi_status validate(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_grid *p
         P *= pg->n[c];
     }
     const int R = p->rays_per_probe;
-    if (R < 16 || R > kMaxRays || R % 16)
+    if (!valid_rays(R))
         return fail(nullptr, SDFDDGI_EINVAL, "rays_per_probe %d: need a multiple of 16 in 16..%d",
                     R, kMaxRays);
     if (P * R >= (int64_t)1 << 31) return fail(nullptr, SDFDDGI_EINVAL, "probes x rays too large");
@@ -229,6 +302,8 @@ sdfddgi_status validate(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_grid *p
                              p->depth_sharpness, p->shadow_bias, p->relax};
     if (!finite_all(scalars, 7) || !finite_all(p->sky_rgb, 3) || !finite_all(p->albedo, 3))
         return fail(nullptr, SDFDDGI_EINVAL, "non-finite parameter");
+    if (!(p->fallback_error >= 0))  // +inf allowed: no probe falls back on its prediction
+        return fail(nullptr, SDFDDGI_EINVAL, "fallback_error must be >= 0");
     if (!(p->hit_eps > 0) || !(p->t_max > 0))
         return fail(nullptr, SDFDDGI_EINVAL, "hit_eps and t_max must be > 0");
     if (!(p->hysteresis >= 0 && p->hysteresis < 1))
@@ -242,6 +317,16 @@ sdfddgi_status validate(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_grid *p
     for (int c = 0; c < 3; ++c)
         if (p->sky_rgb[c] < 0 || p->albedo[c] < 0)
             return fail(nullptr, SDFDDGI_EINVAL, "sky and albedo must be >= 0");
+    if (p->learned_rays != 0) {
+        if (!valid_rays(p->learned_rays) || p->learned_rays > R)
+            return fail(nullptr, SDFDDGI_EINVAL,
+                        "learned_rays %d: need 0 or a multiple of 16 in 16..rays_per_probe",
+                        p->learned_rays);
+        if (p->irr_res > kMaxLearnedRes || p->depth_res % p->irr_res != 0)
+            return fail(nullptr, SDFDDGI_EINVAL,
+                        "learned form needs irr_res <= %d and depth_res a multiple of irr_res",
+                        kMaxLearnedRes);
+    }
     return SDFDDGI_OK;
 }
 
@@ -332,60 +417,195 @@ ProbeGridDev dev_probes(const sdfddgi_ctx *c) {
     return g;
 }
 
-TableArgs table_args(const sdfddgi_ctx *c, uint64_t seed) {
+
+// Allocate a ray set of R rays: the fixed spherical-Fibonacci set (binary64,
+// uploaded), zeroed weight tables and the per-ray buffers.
+hipError_t alloc_set(sdfddgi_ctx *c, RaySet &r, int R) {
+    free_set(r);
+    r.R = R;
+    std::vector<double> h_base(3 * (size_t)R);
+    for (int i = 0; i < R; ++i) fibonacci_point(i, R, h_base.data() + 3 * i);
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+    chk(dev_alloc(&r.base, 3 * (size_t)R));
+    chk(dev_alloc(&r.dirs, 3 * (size_t)R));
+    chk(dev_alloc(&r.wt_i, (size_t)R * c->Tpi));
+    chk(dev_alloc(&r.wt_d, (size_t)R * c->Tpd));
+    chk(dev_alloc(&r.norm_i, c->Ti));
+    chk(dev_alloc(&r.norm_d, c->Td));
+    chk(dev_alloc(&r.payload, (size_t)c->P * R));
+    chk(dev_alloc(&r.hitq, (size_t)c->P * R));
+    if (e != hipSuccess) return e;
+    chk(hipMemcpy(r.base, h_base.data(), 3 * (size_t)R * sizeof(double), hipMemcpyHostToDevice));
+    chk(hipMemsetAsync(r.wt_i, 0, (size_t)R * c->Tpi * sizeof(float), c->stream));
+    chk(hipMemsetAsync(r.wt_d, 0, (size_t)R * c->Tpd * sizeof(float), c->stream));
+    if (c->half) {
+        r.Rpad = (R + 63) / 64 * 64;
+        chk(dev_alloc(&r.w16_i, (size_t)c->Tpi * r.Rpad));
+        chk(dev_alloc(&r.w16_d, (size_t)c->Tpd * r.Rpad));
+        if (e != hipSuccess) return e;
+        chk(hipMemsetAsync(r.w16_i, 0, (size_t)c->Tpi * r.Rpad * 2, c->stream));
+        chk(hipMemsetAsync(r.w16_d, 0, (size_t)c->Tpd * r.Rpad * 2, c->stream));
+    }
+    r.grid = trace_grid(c->device, c->P * R, c->half);
+    return e;
+}
+
+TableArgs table_args(const sdfddgi_ctx *c, const RaySet &r, uint64_t seed, int ncounter) {
     TableArgs t{};
-    t.R = c->R;
+    t.R = r.R;
     t.Ti = c->Ti;
     t.Td = c->Td;
     t.Tpi = c->Tpi;
     t.Tpd = c->Tpd;
     rotation_matrix(seed, t.q);
     t.sharp = (double)c->prm.depth_sharpness;
-    t.base = c->base_dirs;
+    t.base = r.base;
     t.texel_i = c->texel_i;
     t.texel_d = c->texel_d;
-    t.dirs = c->dirs;
-    t.wt_i = c->wt_i;
-    t.wt_d = c->wt_d;
-    t.norm_i = c->norm_i;
-    t.norm_d = c->norm_d;
-    t.counter = c->counter;
-    t.Rpad = c->Rpad;
-    t.w16_i = c->w16_i;
-    t.w16_d = c->w16_d;
+    t.dirs = r.dirs;
+    t.wt_i = r.wt_i;
+    t.wt_d = r.wt_d;
+    t.norm_i = r.norm_i;
+    t.norm_d = r.norm_d;
+    t.counter = ncounter > 0 ? c->counter : nullptr;
+    t.ncounter = ncounter;
+    t.Rpad = r.Rpad;
+    t.w16_i = r.w16_i;
+    t.w16_d = r.w16_d;
     return t;
 }
 
-BlendArgs blend_args(const sdfddgi_ctx *c, const float4 *payload) {
+// Blend of ray set r's payload: reads prev maps, writes new ones (hysteresis h,
+// none where reject is set; reject may be null), optionally for a probe list.
+BlendArgs blend_args(const sdfddgi_ctx *c, const RaySet &r, const float4 *payload, float h,
+                     const float *prev_irr, const float *prev_depth, float *new_irr,
+                     float *new_depth, uint8_t *reject, const int *list, const int *count) {
     BlendArgs b{};
     b.P = (int)c->P;
-    b.R = c->R;
+    b.R = r.R;
     b.irr_res = c->prm.irr_res;
     b.depth_res = c->prm.depth_res;
-    b.hysteresis = c->prm.hysteresis;
+    b.hysteresis = h;
     b.payload = payload;
-    b.wt_i = c->wt_i;
-    b.wt_d = c->wt_d;
-    b.norm_i = c->norm_i;
-    b.norm_d = c->norm_d;
-    b.Rpad = c->Rpad;
-    b.w16_i = c->w16_i;
-    b.w16_d = c->w16_d;
-    b.prev_irr = c->irr[c->cur];
-    b.prev_depth = c->depth[c->cur];
-    b.new_irr = c->irr[1 - c->cur];
-    b.new_depth = c->depth[1 - c->cur];
-    b.reject = c->reject;
+    b.wt_i = r.wt_i;
+    b.wt_d = r.wt_d;
+    b.norm_i = r.norm_i;
+    b.norm_d = r.norm_d;
+    b.Rpad = r.Rpad;
+    b.w16_i = r.w16_i;
+    b.w16_d = r.w16_d;
+    b.prev_irr = prev_irr;
+    b.prev_depth = prev_depth;
+    b.new_irr = new_irr;
+    b.new_depth = new_depth;
+    b.reject = reject;
+    b.probe_list = list;
+    b.probe_count = count;
     return b;
+}
+
+// Trace arguments shared by every pass of a frame (levels, probes, light, params).
+TraceArgs trace_base(const sdfddgi_ctx *c, const float l[3], const float rad[3]) {
+    TraceArgs t{};
+    for (int L = 0; L < c->nl; ++L) t.lv[L] = dev_level(c, L);
+    t.nl = c->nl;
+    t.half_sdf = c->half ? 1 : 0;
+    t.P = (int)c->P;
+    t.max_steps = c->prm.max_steps;
+    t.irr_res = c->prm.irr_res;
+    t.pg = dev_probes(c);
+    t.eps = c->prm.hit_eps;
+    t.t_max = c->prm.t_max;
+    t.relax = c->prm.relax;
+    t.bias = c->prm.shadow_bias;
+    t.gain = c->prm.bounce_gain;
+    t.l0 = l[0]; t.l1 = l[1]; t.l2 = l[2];
+    t.rad0 = rad[0]; t.rad1 = rad[1]; t.rad2 = rad[2];
+    t.sky0 = c->prm.sky_rgb[0];
+    t.sky1 = c->prm.sky_rgb[1];
+    t.sky2 = c->prm.sky_rgb[2];
+    t.alb0 = c->prm.albedo[0];
+    t.alb1 = c->prm.albedo[1];
+    t.alb2 = c->prm.albedo[2];
+    t.probe_pos = c->probe_pos;
+    t.probe_order = c->probe_order;
+    t.prev_irr = c->irr[c->cur];
+    return t;
+}
+
+// The pass of ray set r: all probes (list == null) or the device-side list.
+TraceArgs trace_pass(const TraceArgs &base, const RaySet &r, int *counters, const int *list,
+                     const int *count, int *records) {
+    TraceArgs t = base;
+    t.R = r.R;
+    t.dirs = r.dirs;
+    t.payload = r.payload;
+    t.hitq = r.hitq;
+    t.counter = counters;
+    t.records = records;
+    if (list) {
+        t.probe_order = list;
+        t.probe_count = count;
+    }
+    return t;
 }
 
 sdfddgi_status check_ctx(sdfddgi_ctx *c) {
     if (!c) return SDFDDGI_EINVAL;
     c->err.clear();
+    // launch status is read with hipGetLastError: drop a failure some other code left
+    (void)hipGetLastError();
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
     return SDFDDGI_OK;
 }
+
+// Light direction normalised in binary64 and rounded once; EINVAL on bad input.
+sdfddgi_status light_of(sdfddgi_ctx *c, const sdfddgi_light *light, float l[3], float rad[3]) {
+    if (!light) return fail(c, SDFDDGI_EINVAL, "light is NULL");
+    if (!finite_all(light->dir_to_light, 3) || !finite_all(light->radiance_rgb, 3))
+        return fail(c, SDFDDGI_EINVAL, "non-finite light");
+    const double d0 = light->dir_to_light[0], d1 = light->dir_to_light[1],
+                 d2 = light->dir_to_light[2];
+    const double len = std::sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    if (!(len > 0.0)) return fail(c, SDFDDGI_EINVAL, "light direction has zero length");
+    for (int k = 0; k < 3; ++k)
+        if (light->radiance_rgb[k] < 0) return fail(c, SDFDDGI_EINVAL, "negative radiance");
+    l[0] = (float)(d0 / len);
+    l[1] = (float)(d1 / len);
+    l[2] = (float)(d2 / len);
+    for (int k = 0; k < 3; ++k) rad[k] = light->radiance_rgb[k];
+    return SDFDDGI_OK;
+}
+
+// Timing events of one frame: [0] start, [1] tables, [2] primary, [3] hits,
+// [4] blend, [5] denoiser, [6] fallback trace, [7] fallback blend.
+struct FrameEvents {
+    hipEvent_t *ev = nullptr;
+    hipStream_t s = nullptr;
+    hipError_t mark(int k) { return ev ? hipEventRecord(ev[k], s) : hipSuccess; }
+};
+
+FrameEvents frame_events(sdfddgi_ctx *c) {
+    FrameEvents f;
+    f.ev = c->ev_ring ? c->ev_ring + kEvents * c->ring_head : nullptr;
+    f.s = c->stream;
+    return f;
+}
+
+void frame_done(sdfddgi_ctx *c) {
+    if (c->ev_ring) {
+        c->ring_head = (c->ring_head + 1) % kTimingRing;
+        ++c->timed_frames;
+    }
+}
+
+#define TRY_HIP(c, expr, what)                                                  \
+    do {                                                                        \
+        hipError_t e_ = (expr);                                                 \
+        if (e_ != hipSuccess) return hip_fail((c), e_, (what));                 \
+    } while (0)
 
 }  // namespace
 
@@ -406,6 +626,8 @@ void sdfddgi_default_params(sdfddgi_params *p) {
     p->shadow_bias = 4e-3f;
     p->relax = 1.0f;
     for (int c = 0; c < 3; ++c) p->albedo[c] = 0.5f;
+    p->learned_rays = 0;
+    p->fallback_error = 0.02f;
 }
 
 sdfddgi_status sdfddgi_create(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_grid *probes,
@@ -437,7 +659,6 @@ sdfddgi_status sdfddgi_create(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_g
     c->nl = sdf->num_levels;
     c->pg = *probes;
     c->P = (int64_t)probes->n[0] * probes->n[1] * probes->n[2];
-    c->R = params->rays_per_probe;
     c->Ti = params->irr_res * params->irr_res;
     c->Td = params->depth_res * params->depth_res;
     c->Tpi = (c->Ti + 15) / 16 * 16;
@@ -477,24 +698,18 @@ sdfddgi_status sdfddgi_create(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_g
         }
     }
 
-    // Host constants in binary64: probe positions (rounded once), the fixed
-    // spherical-Fibonacci set and the texel directions of both maps.
+    // Host constants in binary64: probe positions (rounded once), the probes'
+    // tracing order and the texel directions of both maps.
     const int64_t P = c->P;
-    float *h_pos = new (std::nothrow) float[3 * P];
-    double *h_base = new (std::nothrow) double[3 * c->R];
-    double *h_ti = new (std::nothrow) double[3 * c->Ti];
-    double *h_td = new (std::nothrow) double[3 * c->Td];
-    if (!h_pos || !h_base || !h_ti || !h_td) {
-        delete[] h_pos; delete[] h_base; delete[] h_ti; delete[] h_td;
-        return bail(fail(nullptr, SDFDDGI_ENOMEM, "host allocation failed"));
-    }
+    std::vector<float> h_pos(3 * (size_t)P);
+    std::vector<double> h_ti(3 * (size_t)c->Ti), h_td(3 * (size_t)c->Td);
+    std::vector<float> h_tif(3 * (size_t)c->Ti);
     const int nx = probes->n[0], ny = probes->n[1];
     for (int64_t p = 0; p < P; ++p) {
         const int64_t idx[3] = {p % nx, (p / nx) % ny, p / ((int64_t)nx * ny)};
         for (int k = 0; k < 3; ++k)
             h_pos[3 * p + k] = (float)(probes->origin[k] + probes->spacing[k] * (double)idx[k]);
     }
-    for (int i = 0; i < c->R; ++i) fibonacci_point(i, c->R, h_base + 3 * i);
     // tracing order of the probes: Morton order of their (x, y, z) grid index
     std::vector<std::pair<uint64_t, int32_t>> morton((size_t)P);
     for (int64_t p = 0; p < P; ++p) {
@@ -509,47 +724,29 @@ sdfddgi_status sdfddgi_create(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_g
     std::sort(morton.begin(), morton.end());
     std::vector<int32_t> h_order((size_t)P);
     for (int64_t j = 0; j < P; ++j) h_order[(size_t)j] = morton[(size_t)j].second;
-    for (int t = 0; t < c->Ti; ++t)
-        texel_direction(params->irr_res, t % params->irr_res, t / params->irr_res, h_ti + 3 * t);
+    for (int t = 0; t < c->Ti; ++t) {
+        texel_direction(params->irr_res, t % params->irr_res, t / params->irr_res, &h_ti[3 * t]);
+        for (int k = 0; k < 3; ++k) h_tif[3 * t + k] = (float)h_ti[3 * t + k];
+    }
     for (int t = 0; t < c->Td; ++t)
         texel_direction(params->depth_res, t % params->depth_res, t / params->depth_res,
-                        h_td + 3 * t);
+                        &h_td[3 * t]);
 
     hipError_t ce = hipSuccess;
     auto chk = [&](hipError_t x) { if (ce == hipSuccess) ce = x; };
     chk(dev_alloc(&c->probe_pos, 3 * P));
     chk(dev_alloc(&c->probe_order, P));
-    chk(dev_alloc(&c->base_dirs, 3 * c->R));
     chk(dev_alloc(&c->texel_i, 3 * c->Ti));
     chk(dev_alloc(&c->texel_d, 3 * c->Td));
     if (ce == hipSuccess) {
-        chk(hipMemcpy(c->probe_pos, h_pos, 3 * P * sizeof(float), hipMemcpyHostToDevice));
+        chk(hipMemcpy(c->probe_pos, h_pos.data(), 3 * P * sizeof(float), hipMemcpyHostToDevice));
         chk(hipMemcpy(c->probe_order, h_order.data(), P * sizeof(int32_t), hipMemcpyHostToDevice));
-        chk(hipMemcpy(c->base_dirs, h_base, 3 * c->R * sizeof(double), hipMemcpyHostToDevice));
-        chk(hipMemcpy(c->texel_i, h_ti, 3 * c->Ti * sizeof(double), hipMemcpyHostToDevice));
-        chk(hipMemcpy(c->texel_d, h_td, 3 * c->Td * sizeof(double), hipMemcpyHostToDevice));
+        chk(hipMemcpy(c->texel_i, h_ti.data(), 3 * c->Ti * sizeof(double), hipMemcpyHostToDevice));
+        chk(hipMemcpy(c->texel_d, h_td.data(), 3 * c->Td * sizeof(double), hipMemcpyHostToDevice));
     }
-    delete[] h_pos; delete[] h_base; delete[] h_ti; delete[] h_td;
     SDF_TRY(ce, "uploading constants");
 
-    SDF_TRY(dev_alloc(&c->dirs, 3 * c->R), "allocating tables");
-    SDF_TRY(dev_alloc(&c->wt_i, (size_t)c->R * c->Tpi), "allocating tables");
-    SDF_TRY(dev_alloc(&c->wt_d, (size_t)c->R * c->Tpd), "allocating tables");
-    SDF_TRY(hipMemsetAsync(c->wt_i, 0, (size_t)c->R * c->Tpi * sizeof(float), c->stream),
-            "clearing tables");
-    SDF_TRY(hipMemsetAsync(c->wt_d, 0, (size_t)c->R * c->Tpd * sizeof(float), c->stream),
-            "clearing tables");
-    if (c->half) {
-        c->Rpad = (c->R + 63) / 64 * 64;
-        SDF_TRY(dev_alloc(&c->w16_i, (size_t)c->Tpi * c->Rpad), "allocating tables");
-        SDF_TRY(dev_alloc(&c->w16_d, (size_t)c->Tpd * c->Rpad), "allocating tables");
-        SDF_TRY(hipMemsetAsync(c->w16_i, 0, (size_t)c->Tpi * c->Rpad * 2, c->stream),
-                "clearing tables");
-        SDF_TRY(hipMemsetAsync(c->w16_d, 0, (size_t)c->Tpd * c->Rpad * 2, c->stream),
-                "clearing tables");
-    }
-    SDF_TRY(dev_alloc(&c->norm_i, c->Ti), "allocating tables");
-    SDF_TRY(dev_alloc(&c->norm_d, c->Td), "allocating tables");
+    SDF_TRY(alloc_set(c, c->main, params->rays_per_probe), "allocating the ray set");
     for (int k = 0; k < 2; ++k) {
         SDF_TRY(dev_alloc(&c->irr[k], c->irr_floats), "allocating irradiance atlas");
         SDF_TRY(dev_alloc(&c->depth[k], c->depth_floats), "allocating depth atlas");
@@ -560,12 +757,26 @@ sdfddgi_status sdfddgi_create(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_g
     }
     SDF_TRY(dev_alloc(&c->reject, P), "allocating reject flags");
     SDF_TRY(launch_fill_u8(c->reject, 1, P, c->stream), "launching fill");
-    SDF_TRY(dev_alloc(&c->counter, 3), "allocating ray counters");
-    SDF_TRY(dev_alloc(&c->hitq, (size_t)P * c->R), "allocating the hit queue");
-    SDF_TRY(dev_alloc(&c->payload, (size_t)P * c->R), "allocating payload");
-    c->grid = trace_grid(dev, P * c->R, c->half);
+    SDF_TRY(dev_alloc(&c->counter, kCounters), "allocating ray counters");
+    SDF_TRY(hipMemsetAsync(c->counter, 0, kCounters * sizeof(int), c->stream),
+            "clearing counters");
     if (params->flags & SDFDDGI_FLAG_RECORD_RAYS)
-        SDF_TRY(dev_alloc(&c->records, (size_t)P * c->R * 8), "allocating ray records");
+        SDF_TRY(dev_alloc(&c->records, (size_t)P * c->main.R * 8), "allocating ray records");
+    if (params->learned_rays > 0) {
+        SDF_TRY(alloc_set(c, c->low, params->learned_rays), "allocating the learned ray set");
+        SDF_TRY(dev_alloc(&c->u_irr, c->irr_floats), "allocating learned buffers");
+        SDF_TRY(dev_alloc(&c->u_depth, c->depth_floats), "allocating learned buffers");
+        SDF_TRY(dev_alloc(&c->probe_sdf, P), "allocating learned buffers");
+        SDF_TRY(dev_alloc(&c->texel_dir, 3 * c->Ti), "allocating learned buffers");
+        SDF_TRY(dev_alloc(&c->fallback, P), "allocating learned buffers");
+        SDF_TRY(dev_alloc(&c->mean_error, P), "allocating learned buffers");
+        SDF_TRY(hipMemcpy(c->texel_dir, h_tif.data(), 3 * c->Ti * sizeof(float),
+                          hipMemcpyHostToDevice),
+                "uploading texel directions");
+        const float l[3] = {0.0f, 1.0f, 0.0f}, rad[3] = {0.0f, 0.0f, 0.0f};
+        SDF_TRY(launch_probe_sdf(trace_base(c, l, rad), c->probe_sdf, c->stream),
+                "launching probe_sdf_kernel");
+    }
     if (params->flags & SDFDDGI_FLAG_TIMING) {
         c->ev_ring = new (std::nothrow) hipEvent_t[kEvents * kTimingRing]();
         if (!c->ev_ring) return bail(fail(nullptr, SDFDDGI_ENOMEM, "host allocation failed"));
@@ -582,76 +793,28 @@ sdfddgi_status sdfddgi_update_frame(sdfddgi_ctx *c, const sdfddgi_light *light,
                                     uint64_t rotation_seed) {
     sdfddgi_status st = check_ctx(c);
     if (st != SDFDDGI_OK) return st;
-    if (!light) return fail(c, SDFDDGI_EINVAL, "light is NULL");
-    if (!finite_all(light->dir_to_light, 3) || !finite_all(light->radiance_rgb, 3))
-        return fail(c, SDFDDGI_EINVAL, "non-finite light");
-    const double d0 = light->dir_to_light[0], d1 = light->dir_to_light[1],
-                 d2 = light->dir_to_light[2];
-    const double len = std::sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-    if (!(len > 0.0)) return fail(c, SDFDDGI_EINVAL, "light direction has zero length");
-    for (int k = 0; k < 3; ++k)
-        if (light->radiance_rgb[k] < 0) return fail(c, SDFDDGI_EINVAL, "negative radiance");
-
-    TraceArgs t{};
-    for (int L = 0; L < c->nl; ++L) t.lv[L] = dev_level(c, L);
-    t.nl = c->nl;
-    t.half_sdf = c->half ? 1 : 0;
-    t.P = (int)c->P;
-    t.R = c->R;
-    t.max_steps = c->prm.max_steps;
-    t.irr_res = c->prm.irr_res;
-    t.pg = dev_probes(c);
-    t.eps = c->prm.hit_eps;
-    t.t_max = c->prm.t_max;
-    t.relax = c->prm.relax;
-    t.bias = c->prm.shadow_bias;
-    t.gain = c->prm.bounce_gain;
-    t.l0 = (float)(d0 / len);
-    t.l1 = (float)(d1 / len);
-    t.l2 = (float)(d2 / len);
-    t.rad0 = light->radiance_rgb[0];
-    t.rad1 = light->radiance_rgb[1];
-    t.rad2 = light->radiance_rgb[2];
-    t.sky0 = c->prm.sky_rgb[0];
-    t.sky1 = c->prm.sky_rgb[1];
-    t.sky2 = c->prm.sky_rgb[2];
-    t.alb0 = c->prm.albedo[0];
-    t.alb1 = c->prm.albedo[1];
-    t.alb2 = c->prm.albedo[2];
-    t.probe_pos = c->probe_pos;
-    t.probe_order = c->probe_order;
-    t.dirs = c->dirs;
-    t.prev_irr = c->irr[c->cur];
-    t.payload = c->payload;
-    t.records = c->records;
-    t.counter = c->counter;
-    t.hitq = c->hitq;
-
-    hipEvent_t *ev = c->ev_ring ? c->ev_ring + kEvents * c->ring_head : nullptr;
-    hipError_t e;
-    if (ev && (e = hipEventRecord(ev[0], c->stream)) != hipSuccess)
-        return hip_fail(c, e, "event");
-    if ((e = launch_tables(table_args(c, rotation_seed), c->stream)) != hipSuccess)
-        return hip_fail(c, e, "launching tables_kernel");
-    if (ev && (e = hipEventRecord(ev[1], c->stream)) != hipSuccess)
-        return hip_fail(c, e, "event");
-    if ((e = launch_primary(t, c->grid, c->stream)) != hipSuccess)
-        return hip_fail(c, e, "launching primary_kernel");
-    if (ev && (e = hipEventRecord(ev[2], c->stream)) != hipSuccess)
-        return hip_fail(c, e, "event");
-    if ((e = launch_hits(t, c->grid, c->stream)) != hipSuccess)
-        return hip_fail(c, e, "launching hits_kernel");
-    if (ev && (e = hipEventRecord(ev[3], c->stream)) != hipSuccess)
-        return hip_fail(c, e, "event");
-    if ((e = launch_blend(blend_args(c, c->payload), c->stream)) != hipSuccess)
-        return hip_fail(c, e, "launching blend_kernel");
-    if (ev && (e = hipEventRecord(ev[4], c->stream)) != hipSuccess)
-        return hip_fail(c, e, "event");
-    if (ev) {
-        c->ring_head = (c->ring_head + 1) % kTimingRing;
-        ++c->timed_frames;
-    }
-    c->cur = 1 - c->cur;
+    float l[3], rad[3];
+    if ((st = light_of(c, light, l, rad)) != SDFDDGI_OK) return st;
+    const TraceArgs t = trace_pass(trace_base(c, l, rad), c->main, c->counter, nullptr, nullptr,
+                                   c->records);
+    FrameEvents ev = frame_events(c);
+    const int nxt = 1 - c->cur;
+    TRY_HIP(c, ev.mark(0), "event");
+    TRY_HIP(c, launch_tables(table_args(c, c->main, rotation_seed, 3), c->stream),
+            "launching tables_kernel");
+    TRY_HIP(c, ev.mark(1), "event");
+    TRY_HIP(c, launch_primary(t, c->main.grid, c->stream), "launching primary_kernel");
+    TRY_HIP(c, ev.mark(2), "event");
+    TRY_HIP(c, launch_hits(t, c->main.grid, c->stream), "launching hits_kernel");
+    TRY_HIP(c, ev.mark(3), "event");
+    TRY_HIP(c, launch_blend(blend_args(c, c->main, c->main.payload, c->prm.hysteresis,
+                                       c->irr[c->cur], c->depth[c->cur], c->irr[nxt],
+                                       c->depth[nxt], c->reject, nullptr, nullptr),
+                            c->stream),
+            "launching blend_kernel");
+    for (int k = 4; k < kEvents; ++k) TRY_HIP(c, ev.mark(k), "event");
+    frame_done(c);
+    c->cur = nxt;
     c->have_frame = true;
     c->have_records = c->records != nullptr;
     return SDFDDGI_OK;
@@ -661,12 +824,15 @@ sdfddgi_status sdfddgi_blend(sdfddgi_ctx *c, const float *payload, uint64_t rota
     sdfddgi_status st = check_ctx(c);
     if (st != SDFDDGI_OK) return st;
     if (!payload) return fail(c, SDFDDGI_EINVAL, "payload is NULL");
-    hipError_t e;
-    if ((e = launch_tables(table_args(c, rotation_seed), c->stream)) != hipSuccess)
-        return hip_fail(c, e, "launching tables_kernel");
-    if ((e = launch_blend(blend_args(c, (const float4 *)payload), c->stream)) != hipSuccess)
-        return hip_fail(c, e, "launching blend_kernel");
-    c->cur = 1 - c->cur;
+    const int nxt = 1 - c->cur;
+    TRY_HIP(c, launch_tables(table_args(c, c->main, rotation_seed, 0), c->stream),
+            "launching tables_kernel");
+    TRY_HIP(c, launch_blend(blend_args(c, c->main, (const float4 *)payload, c->prm.hysteresis,
+                                       c->irr[c->cur], c->depth[c->cur], c->irr[nxt],
+                                       c->depth[nxt], c->reject, nullptr, nullptr),
+                            c->stream),
+            "launching blend_kernel");
+    c->cur = nxt;
     return SDFDDGI_OK;
 }
 
@@ -685,21 +851,21 @@ sdfddgi_status sdfddgi_sample_irradiance(sdfddgi_ctx *c, const float *points,
     a.points = points;
     a.normals = normals;
     a.out = out_rgb;
-    hipError_t e = launch_sample(a, c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "launching sample_kernel");
+    TRY_HIP(c, launch_sample(a, c->stream), "launching sample_kernel");
     return SDFDDGI_OK;
 }
 
 sdfddgi_status sdfddgi_get_maps(sdfddgi_ctx *c, float *irr, float *depth) {
     sdfddgi_status st = check_ctx(c);
     if (st != SDFDDGI_OK) return st;
-    hipError_t e;
-    if (irr && (e = hipMemcpyAsync(irr, c->irr[c->cur], c->irr_floats * sizeof(float),
-                                   hipMemcpyDeviceToDevice, c->stream)) != hipSuccess)
-        return hip_fail(c, e, "copying irradiance atlas");
-    if (depth && (e = hipMemcpyAsync(depth, c->depth[c->cur], c->depth_floats * sizeof(float),
-                                     hipMemcpyDeviceToDevice, c->stream)) != hipSuccess)
-        return hip_fail(c, e, "copying depth atlas");
+    if (irr)
+        TRY_HIP(c, hipMemcpyAsync(irr, c->irr[c->cur], c->irr_floats * sizeof(float),
+                                  hipMemcpyDeviceToDevice, c->stream),
+                "copying irradiance atlas");
+    if (depth)
+        TRY_HIP(c, hipMemcpyAsync(depth, c->depth[c->cur], c->depth_floats * sizeof(float),
+                                  hipMemcpyDeviceToDevice, c->stream),
+                "copying depth atlas");
     return SDFDDGI_OK;
 }
 
@@ -707,23 +873,20 @@ sdfddgi_status sdfddgi_set_maps(sdfddgi_ctx *c, const float *irr, const float *d
     sdfddgi_status st = check_ctx(c);
     if (st != SDFDDGI_OK) return st;
     if (!irr || !depth) return fail(c, SDFDDGI_EINVAL, "both maps are required");
-    hipError_t e;
-    if ((e = hipMemcpyAsync(c->irr[c->cur], irr, c->irr_floats * sizeof(float),
-                            hipMemcpyDeviceToDevice, c->stream)) != hipSuccess)
-        return hip_fail(c, e, "copying irradiance atlas");
-    if ((e = hipMemcpyAsync(c->depth[c->cur], depth, c->depth_floats * sizeof(float),
-                            hipMemcpyDeviceToDevice, c->stream)) != hipSuccess)
-        return hip_fail(c, e, "copying depth atlas");
-    if ((e = launch_fill_u8(c->reject, 0, c->P, c->stream)) != hipSuccess)
-        return hip_fail(c, e, "launching fill");
+    TRY_HIP(c, hipMemcpyAsync(c->irr[c->cur], irr, c->irr_floats * sizeof(float),
+                              hipMemcpyDeviceToDevice, c->stream),
+            "copying irradiance atlas");
+    TRY_HIP(c, hipMemcpyAsync(c->depth[c->cur], depth, c->depth_floats * sizeof(float),
+                              hipMemcpyDeviceToDevice, c->stream),
+            "copying depth atlas");
+    TRY_HIP(c, launch_fill_u8(c->reject, 0, c->P, c->stream), "launching fill");
     return SDFDDGI_OK;
 }
 
 sdfddgi_status sdfddgi_reset_history(sdfddgi_ctx *c) {
     sdfddgi_status st = check_ctx(c);
     if (st != SDFDDGI_OK) return st;
-    hipError_t e = launch_fill_u8(c->reject, 1, c->P, c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "launching fill");
+    TRY_HIP(c, launch_fill_u8(c->reject, 1, c->P, c->stream), "launching fill");
     return SDFDDGI_OK;
 }
 
@@ -732,9 +895,9 @@ sdfddgi_status sdfddgi_get_payload(sdfddgi_ctx *c, float *out) {
     if (st != SDFDDGI_OK) return st;
     if (!out) return fail(c, SDFDDGI_EINVAL, "out is NULL");
     if (!c->have_frame) return fail(c, SDFDDGI_ESTATE, "no frame has been traced yet");
-    hipError_t e = hipMemcpyAsync(out, c->payload, (size_t)c->P * c->R * sizeof(float4),
-                                  hipMemcpyDeviceToDevice, c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "copying payload");
+    TRY_HIP(c, hipMemcpyAsync(out, c->main.payload, (size_t)c->P * c->main.R * sizeof(float4),
+                              hipMemcpyDeviceToDevice, c->stream),
+            "copying payload");
     return SDFDDGI_OK;
 }
 
@@ -744,9 +907,9 @@ sdfddgi_status sdfddgi_get_ray_records(sdfddgi_ctx *c, int32_t *out) {
     if (!out) return fail(c, SDFDDGI_EINVAL, "out is NULL");
     if (!c->records) return fail(c, SDFDDGI_ESTATE, "created without SDFDDGI_FLAG_RECORD_RAYS");
     if (!c->have_records) return fail(c, SDFDDGI_ESTATE, "no frame has been traced yet");
-    hipError_t e = hipMemcpyAsync(out, c->records, (size_t)c->P * c->R * 8 * sizeof(int32_t),
-                                  hipMemcpyDeviceToDevice, c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "copying records");
+    TRY_HIP(c, hipMemcpyAsync(out, c->records, (size_t)c->P * c->main.R * 8 * sizeof(int32_t),
+                              hipMemcpyDeviceToDevice, c->stream),
+            "copying records");
     return SDFDDGI_OK;
 }
 
@@ -754,9 +917,9 @@ sdfddgi_status sdfddgi_get_ray_directions(sdfddgi_ctx *c, float *out) {
     sdfddgi_status st = check_ctx(c);
     if (st != SDFDDGI_OK) return st;
     if (!out) return fail(c, SDFDDGI_EINVAL, "out is NULL");
-    hipError_t e = hipMemcpyAsync(out, c->dirs, (size_t)c->R * 3 * sizeof(float),
-                                  hipMemcpyDeviceToDevice, c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "copying directions");
+    TRY_HIP(c, hipMemcpyAsync(out, c->main.dirs, (size_t)c->main.R * 3 * sizeof(float),
+                              hipMemcpyDeviceToDevice, c->stream),
+            "copying directions");
     return SDFDDGI_OK;
 }
 
@@ -781,16 +944,17 @@ sdfddgi_status sdfddgi_get_kernel_times(sdfddgi_ctx *c, float *ms, int32_t count
     if (c->timed_frames == 0) return fail(c, SDFDDGI_ESTATE, "no timed frame since the last call");
     const int frames = (int)(c->timed_frames < kTimingRing ? c->timed_frames : kTimingRing);
     const int last = (c->ring_head + kTimingRing - 1) % kTimingRing;
-    hipError_t e = hipEventSynchronize(c->ev_ring[kEvents * last + kEvents - 1]);
-    if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
-    const int pairs[kEvents][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {0, 4}};
-    double sum[kEvents] = {0, 0, 0, 0, 0};
+    TRY_HIP(c, hipEventSynchronize(c->ev_ring[kEvents * last + kEvents - 1]),
+            "hipEventSynchronize");
+    // tables, primary, hits, blend, frame, denoiser, fallback trace, fallback blend
+    const int pairs[kEvents][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {0, 7}, {4, 5}, {5, 6}, {6, 7}};
+    double sum[kEvents] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int f = 0; f < frames; ++f) {
         const hipEvent_t *ev = c->ev_ring + kEvents * ((last - f + kTimingRing) % kTimingRing);
         for (int k = 0; k < kEvents; ++k) {
             float v = 0.0f;
-            e = hipEventElapsedTime(&v, ev[pairs[k][0]], ev[pairs[k][1]]);
-            if (e != hipSuccess) return hip_fail(c, e, "hipEventElapsedTime");
+            TRY_HIP(c, hipEventElapsedTime(&v, ev[pairs[k][0]], ev[pairs[k][1]]),
+                    "hipEventElapsedTime");
             sum[k] += v;
         }
     }
@@ -803,7 +967,7 @@ sdfddgi_status sdfddgi_get_sizes(const sdfddgi_ctx *c, int64_t *probes, int32_t 
                                  int64_t *irr_floats, int64_t *depth_floats) {
     if (!c) return SDFDDGI_EINVAL;
     if (probes) *probes = c->P;
-    if (rays) *rays = c->R;
+    if (rays) *rays = c->main.R;
     if (irr_floats) *irr_floats = c->irr_floats;
     if (depth_floats) *depth_floats = c->depth_floats;
     return SDFDDGI_OK;
@@ -821,5 +985,381 @@ sdfddgi_status sdfddgi_destroy(sdfddgi_ctx *c) {
     delete c;
     return SDFDDGI_OK;
 }
+
+// ------------------------------------------------------------ learned form --
+
+sdfddgi_status sdfddgi_denoiser_create(const float *params, int32_t count, float irr_scale,
+                                       float depth_scale, void *hip_stream,
+                                       sdfddgi_denoiser **out) {
+    g_learned_error.clear();
+    if (!out) return lfail(SDFDDGI_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!params || count != kMlpParams)
+        return lfail(SDFDDGI_EINVAL, "need %d parameters, got %d", kMlpParams, count);
+    if (!finite_all(params, kMlpParams)) return lfail(SDFDDGI_EINVAL, "non-finite parameter");
+    (void)hipGetLastError();
+    if (!(irr_scale > 0) || !(depth_scale > 0) || !std::isfinite(irr_scale) ||
+        !std::isfinite(depth_scale))
+        return lfail(SDFDDGI_EINVAL, "feature scales must be finite and > 0");
+    sdfddgi_denoiser *d = new (std::nothrow) sdfddgi_denoiser();
+    if (!d) return lfail(SDFDDGI_ENOMEM, "host allocation failed");
+    hipError_t e = hipGetDevice(&d->device);
+    d->stream = (hipStream_t)hip_stream;
+    d->S = irr_scale;
+    d->D = depth_scale;
+    auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+    chk(dev_alloc(&d->theta, kMlpParams));
+    chk(dev_alloc(&d->fwd, kFwdEntries * 64));
+    chk(dev_alloc(&d->bwd, kBwdEntries * 64));
+    chk(dev_alloc(&d->bias, kBiasFloats));
+    if (e == hipSuccess)
+        chk(hipMemcpy(d->theta, params, kMlpParams * sizeof(float), hipMemcpyHostToDevice));
+    if (e == hipSuccess) chk(launch_pack_mlp(d->theta, d->fwd, d->bwd, d->bias, d->stream));
+    if (e == hipSuccess) chk(hipStreamSynchronize(d->stream));
+    if (e != hipSuccess) {
+        sdfddgi_denoiser_destroy(d);
+        return lhip_fail(e, "creating the denoiser");
+    }
+    *out = d;
+    return SDFDDGI_OK;
+}
+
+sdfddgi_status sdfddgi_denoiser_infer(sdfddgi_denoiser *d, const float *features, int64_t n,
+                                      float *out) {
+    g_learned_error.clear();
+    if (!d) return lfail(SDFDDGI_EINVAL, "denoiser is NULL");
+    if (n < 0) return lfail(SDFDDGI_EINVAL, "negative count");
+    if (n == 0) return SDFDDGI_OK;
+    if (!features || !out) return lfail(SDFDDGI_EINVAL, "null array");
+    (void)hipGetLastError();
+    hipError_t e = hipSetDevice(d->device);
+    if (e != hipSuccess) return lhip_fail(e, "hipSetDevice");
+    InferArgs a{};
+    a.n = n;
+    a.features = features;
+    a.out = out;
+    a.mlp = MlpPack{d->fwd, d->bwd, d->bias};
+    if ((e = launch_infer(a, d->stream)) != hipSuccess) return lhip_fail(e, "launching infer_kernel");
+    return SDFDDGI_OK;
+}
+
+sdfddgi_status sdfddgi_denoiser_destroy(sdfddgi_denoiser *d) {
+    if (!d) return SDFDDGI_OK;
+    (void)hipSetDevice(d->device);
+    (void)hipStreamSynchronize(d->stream);
+    dev_free(d->theta); dev_free(d->fwd); dev_free(d->bwd); dev_free(d->bias);
+    delete d;
+    return SDFDDGI_OK;
+}
+
+static FeatureArgs feature_args(const sdfddgi_ctx *c, const sdfddgi_denoiser *d) {
+    FeatureArgs f{};
+    f.irr_res = c->prm.irr_res;
+    f.depth_res = c->prm.depth_res;
+    f.inv_s = (float)(1.0 / (double)d->S);
+    f.inv_d = (float)(1.0 / (double)d->D);
+    f.u_irr = c->u_irr;
+    f.prev_irr = c->irr[c->cur];
+    f.prev_depth = c->depth[c->cur];
+    f.probe_sdf = c->probe_sdf;
+    f.texel_dir = c->texel_dir;
+    return f;
+}
+
+static sdfddgi_status check_learned(sdfddgi_ctx *c, const sdfddgi_denoiser *d) {
+    if (!c->low.R) return fail(c, SDFDDGI_ESTATE, "context created with learned_rays == 0");
+    if (!d) return fail(c, SDFDDGI_EINVAL, "denoiser is NULL");
+    if (d->device != c->device) return fail(c, SDFDDGI_EINVAL, "denoiser is on another device");
+    return SDFDDGI_OK;
+}
+
+sdfddgi_status sdfddgi_update_frame_learned(sdfddgi_ctx *c, const sdfddgi_denoiser *d,
+                                            const sdfddgi_light *light, uint64_t rotation_seed) {
+    sdfddgi_status st = check_ctx(c);
+    if (st != SDFDDGI_OK) return st;
+    if ((st = check_learned(c, d)) != SDFDDGI_OK) return st;
+    float l[3], rad[3];
+    if ((st = light_of(c, light, l, rad)) != SDFDDGI_OK) return st;
+    const TraceArgs base = trace_base(c, l, rad);
+    const int nxt = 1 - c->cur;
+    int *fb_count = c->counter + 6;
+    FrameEvents ev = frame_events(c);
+    TRY_HIP(c, ev.mark(0), "event");
+    // tables of both sets; the first one zeroes every counter of the frame
+    TRY_HIP(c, launch_tables(table_args(c, c->low, rotation_seed, 7), c->stream),
+            "launching tables_kernel");
+    TRY_HIP(c, launch_tables(table_args(c, c->main, rotation_seed, 0), c->stream),
+            "launching tables_kernel");
+    TRY_HIP(c, ev.mark(1), "event");
+    // low-ray pass over every probe, Eq. 3 without hysteresis
+    const TraceArgs tl = trace_pass(base, c->low, c->counter, nullptr, nullptr, nullptr);
+    TRY_HIP(c, launch_primary(tl, c->low.grid, c->stream), "launching primary_kernel");
+    TRY_HIP(c, ev.mark(2), "event");
+    TRY_HIP(c, launch_hits(tl, c->low.grid, c->stream), "launching hits_kernel");
+    TRY_HIP(c, ev.mark(3), "event");
+    TRY_HIP(c, launch_blend(blend_args(c, c->low, c->low.payload, 0.0f, c->irr[c->cur],
+                                       c->depth[c->cur], c->u_irr, c->u_depth, nullptr, nullptr,
+                                       nullptr),
+                            c->stream),
+            "launching blend_kernel");
+    TRY_HIP(c, ev.mark(4), "event");
+    // network, decision, accepted probes' maps, fallback list
+    DenoiseArgs da{};
+    da.f = feature_args(c, d);
+    da.P = (int)c->P;
+    da.hysteresis = c->prm.hysteresis;
+    da.s = d->S;
+    da.tau = c->prm.fallback_error;
+    da.reject = c->reject;
+    da.u_depth = c->u_depth;
+    da.new_irr = c->irr[nxt];
+    da.new_depth = c->depth[nxt];
+    da.mlp = MlpPack{d->fwd, d->bwd, d->bias};
+    da.fallback_list = c->fallback;
+    da.fallback_count = fb_count;
+    da.mean_error = c->mean_error;
+    TRY_HIP(c, launch_denoise(da, c->stream), "launching denoise_kernel");
+    TRY_HIP(c, ev.mark(5), "event");
+    // plain update of the fallback probes
+    const TraceArgs tf = trace_pass(base, c->main, c->counter + 3, c->fallback, fb_count, nullptr);
+    TRY_HIP(c, launch_primary(tf, c->main.grid, c->stream), "launching primary_kernel");
+    TRY_HIP(c, launch_hits(tf, c->main.grid, c->stream), "launching hits_kernel");
+    TRY_HIP(c, ev.mark(6), "event");
+    TRY_HIP(c, launch_blend(blend_args(c, c->main, c->main.payload, c->prm.hysteresis,
+                                       c->irr[c->cur], c->depth[c->cur], c->irr[nxt],
+                                       c->depth[nxt], c->reject, c->fallback, fb_count),
+                            c->stream),
+            "launching blend_kernel");
+    TRY_HIP(c, ev.mark(7), "event");
+    frame_done(c);
+    c->cur = nxt;
+    c->have_learned = true;
+    return SDFDDGI_OK;
+}
+
+sdfddgi_status sdfddgi_get_fallback(sdfddgi_ctx *c, int32_t *count, int32_t *probes,
+                                    float *mean_error) {
+    sdfddgi_status st = check_ctx(c);
+    if (st != SDFDDGI_OK) return st;
+    if (!count) return fail(c, SDFDDGI_EINVAL, "count is NULL");
+    if (!c->have_learned) return fail(c, SDFDDGI_ESTATE, "no learned frame yet");
+    TRY_HIP(c, hipMemcpyAsync(count, c->counter + 6, sizeof(int32_t), hipMemcpyDeviceToHost,
+                              c->stream),
+            "copying the fallback count");
+    if (probes)
+        TRY_HIP(c, hipMemcpyAsync(probes, c->fallback, c->P * sizeof(int32_t),
+                                  hipMemcpyDeviceToDevice, c->stream),
+                "copying the fallback list");
+    if (mean_error)
+        TRY_HIP(c, hipMemcpyAsync(mean_error, c->mean_error, c->P * sizeof(float),
+                                  hipMemcpyDeviceToDevice, c->stream),
+                "copying the mean errors");
+    TRY_HIP(c, hipStreamSynchronize(c->stream), "waiting for the stream");
+    return SDFDDGI_OK;
+}
+
+sdfddgi_status sdfddgi_learned_examples(sdfddgi_ctx *c, const sdfddgi_denoiser *d,
+                                        const sdfddgi_light *light, uint64_t rotation_seed,
+                                        int32_t target_rays, float rel_floor, float *features,
+                                        float *targets) {
+    sdfddgi_status st = check_ctx(c);
+    if (st != SDFDDGI_OK) return st;
+    if ((st = check_learned(c, d)) != SDFDDGI_OK) return st;
+    if (!valid_rays(target_rays))
+        return fail(c, SDFDDGI_EINVAL, "target_rays %d: need a multiple of 16 in 16..%d",
+                    target_rays, kMaxRays);
+    if (c->P * target_rays >= (int64_t)1 << 31)
+        return fail(c, SDFDDGI_EINVAL, "probes x target rays too large");
+    if (!features || !targets) return fail(c, SDFDDGI_EINVAL, "null array");
+    if (!(rel_floor >= 0) || !std::isfinite(rel_floor))
+        return fail(c, SDFDDGI_EINVAL, "rel_floor must be finite and >= 0");
+    float l[3], rad[3];
+    if ((st = light_of(c, light, l, rad)) != SDFDDGI_OK) return st;
+    if (c->target.R != target_rays) {
+        TRY_HIP(c, hipStreamSynchronize(c->stream), "waiting for the stream");
+        TRY_HIP(c, alloc_set(c, c->target, target_rays), "allocating the target ray set");
+        if (!c->t_irr) {
+            TRY_HIP(c, dev_alloc(&c->t_irr, c->irr_floats), "allocating target maps");
+            TRY_HIP(c, dev_alloc(&c->t_depth, c->depth_floats), "allocating target maps");
+        }
+    }
+    const TraceArgs base = trace_base(c, l, rad);
+    TRY_HIP(c, launch_tables(table_args(c, c->low, rotation_seed, 7), c->stream),
+            "launching tables_kernel");
+    TRY_HIP(c, launch_tables(table_args(c, c->target, rotation_seed, 0), c->stream),
+            "launching tables_kernel");
+    const TraceArgs tl = trace_pass(base, c->low, c->counter, nullptr, nullptr, nullptr);
+    TRY_HIP(c, launch_primary(tl, c->low.grid, c->stream), "launching primary_kernel");
+    TRY_HIP(c, launch_hits(tl, c->low.grid, c->stream), "launching hits_kernel");
+    TRY_HIP(c, launch_blend(blend_args(c, c->low, c->low.payload, 0.0f, c->irr[c->cur],
+                                       c->depth[c->cur], c->u_irr, c->u_depth, nullptr, nullptr,
+                                       nullptr),
+                            c->stream),
+            "launching blend_kernel");
+    const TraceArgs tt = trace_pass(base, c->target, c->counter + 3, nullptr, nullptr, nullptr);
+    TRY_HIP(c, launch_primary(tt, c->target.grid, c->stream), "launching primary_kernel");
+    TRY_HIP(c, launch_hits(tt, c->target.grid, c->stream), "launching hits_kernel");
+    TRY_HIP(c, launch_blend(blend_args(c, c->target, c->target.payload, 0.0f, c->irr[c->cur],
+                                       c->depth[c->cur], c->t_irr, c->t_depth, nullptr, nullptr,
+                                       nullptr),
+                            c->stream),
+            "launching blend_kernel");
+    ExampleArgs ea{};
+    ea.f = feature_args(c, d);
+    ea.P = (int)c->P;
+    ea.target_irr = c->t_irr;
+    ea.rel_floor = rel_floor;
+    ea.features = features;
+    ea.targets = targets;
+    TRY_HIP(c, launch_examples(ea, c->stream), "launching examples_kernel");
+    return SDFDDGI_OK;
+}
+
+// ---------------------------------------------------------------- training --
+
+sdfddgi_status sdfddgi_trainer_destroy(sdfddgi_trainer *t) {
+    if (!t) return SDFDDGI_OK;
+    (void)hipSetDevice(t->device);
+    (void)hipStreamSynchronize(t->stream);
+    t->loss = nullptr;  // the last element of the grad allocation, not an allocation
+    dev_free(t->theta); dev_free(t->m); dev_free(t->v); dev_free(t->grad);
+    dev_free(t->fwd); dev_free(t->bwd); dev_free(t->bias);
+    delete t;
+    return SDFDDGI_OK;
+}
+
+sdfddgi_status sdfddgi_trainer_create(const float *init, int32_t count,
+                                      const sdfddgi_train_config *cfg, void *hip_stream,
+                                      sdfddgi_trainer **out) {
+    g_learned_error.clear();
+    if (!out) return lfail(SDFDDGI_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!init || count != kMlpParams)
+        return lfail(SDFDDGI_EINVAL, "need %d parameters, got %d", kMlpParams, count);
+    if (!cfg) return lfail(SDFDDGI_EINVAL, "cfg is NULL");
+    if (!finite_all(init, kMlpParams)) return lfail(SDFDDGI_EINVAL, "non-finite parameter");
+    const float v[5] = {cfg->head_weight, cfg->min_error, cfg->beta1, cfg->beta2, cfg->eps};
+    if (!finite_all(v, 5) || !(cfg->head_weight >= 0) || !(cfg->min_error > 0) ||
+        !(cfg->beta1 >= 0 && cfg->beta1 < 1) || !(cfg->beta2 >= 0 && cfg->beta2 < 1) ||
+        !(cfg->eps >= 0))
+        return lfail(SDFDDGI_EINVAL, "bad training configuration");
+    (void)hipGetLastError();
+    sdfddgi_trainer *t = new (std::nothrow) sdfddgi_trainer();
+    if (!t) return lfail(SDFDDGI_ENOMEM, "host allocation failed");
+    hipError_t e = hipGetDevice(&t->device);
+    t->stream = (hipStream_t)hip_stream;
+    t->cfg = *cfg;
+    auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+    chk(dev_alloc(&t->theta, kMlpParams));
+    chk(dev_alloc(&t->m, kMlpParams));
+    chk(dev_alloc(&t->v, kMlpParams));
+    chk(dev_alloc(&t->grad, kMlpParams + 1));
+    chk(dev_alloc(&t->fwd, kFwdEntries * 64));
+    chk(dev_alloc(&t->bwd, kBwdEntries * 64));
+    chk(dev_alloc(&t->bias, kBiasFloats));
+    if (e == hipSuccess) {
+        t->loss = t->grad + kMlpParams;
+        chk(hipMemcpy(t->theta, init, kMlpParams * sizeof(float), hipMemcpyHostToDevice));
+        chk(launch_zero_f32(t->m, kMlpParams, t->stream));
+        chk(launch_zero_f32(t->v, kMlpParams, t->stream));
+        chk(launch_pack_mlp(t->theta, t->fwd, t->bwd, t->bias, t->stream));
+        chk(hipStreamSynchronize(t->stream));
+    }
+    if (e != hipSuccess) {
+        t->loss = nullptr;
+        sdfddgi_trainer_destroy(t);
+        return lhip_fail(e, "creating the trainer");
+    }
+    *out = t;
+    return SDFDDGI_OK;
+}
+
+static hipError_t run_train(sdfddgi_trainer *t, const float *features, const float *targets,
+                            int64_t count, int32_t batch, uint64_t seed, int sequential) {
+    (void)hipGetLastError();
+    hipError_t e = launch_zero_f32(t->grad, kMlpParams + 1, t->stream);
+    if (e != hipSuccess) return e;
+    TrainArgs a{};
+    a.features = features;
+    a.targets = targets;
+    a.count = count;
+    a.batch = batch;
+    a.seed = seed;
+    a.sequential = sequential;
+    a.mlp = MlpPack{t->fwd, t->bwd, t->bias};
+    a.inv_n = (float)(1.0 / (double)batch);
+    a.head_weight = t->cfg.head_weight;
+    a.min_error = t->cfg.min_error;
+    a.grad = t->grad;
+    a.loss = t->loss;
+    return launch_train(a, t->stream);
+}
+
+sdfddgi_status sdfddgi_trainer_gradient(sdfddgi_trainer *t, const float *features,
+                                        const float *targets, int32_t n, float *grad,
+                                        float *loss) {
+    g_learned_error.clear();
+    if (!t) return lfail(SDFDDGI_EINVAL, "trainer is NULL");
+    if (n < 1 || !features || !targets) return lfail(SDFDDGI_EINVAL, "need n >= 1 samples");
+    hipError_t e = hipSetDevice(t->device);
+    if (e == hipSuccess) e = run_train(t, features, targets, n, n, 0, 1);
+    if (e == hipSuccess && grad)
+        e = hipMemcpyAsync(grad, t->grad, kMlpParams * sizeof(float), hipMemcpyDeviceToHost,
+                           t->stream);
+    if (e == hipSuccess && loss)
+        e = hipMemcpyAsync(loss, t->loss, sizeof(float), hipMemcpyDeviceToHost, t->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(t->stream);
+    if (e != hipSuccess) return lhip_fail(e, "computing the gradient");
+    return SDFDDGI_OK;
+}
+
+sdfddgi_status sdfddgi_trainer_step(sdfddgi_trainer *t, const float *features,
+                                    const float *targets, int64_t count, int32_t batch,
+                                    uint64_t seed, float lr, float *loss) {
+    g_learned_error.clear();
+    if (!t) return lfail(SDFDDGI_EINVAL, "trainer is NULL");
+    if (count < 1 || batch < 1 || !features || !targets)
+        return lfail(SDFDDGI_EINVAL, "need count >= 1, batch >= 1 and both arrays");
+    if (!(lr >= 0) || !std::isfinite(lr)) return lfail(SDFDDGI_EINVAL, "bad learning rate");
+    hipError_t e = hipSetDevice(t->device);
+    if (e == hipSuccess) e = run_train(t, features, targets, count, batch, seed, 0);
+    if (e == hipSuccess) {
+        ++t->step;
+        AdamArgs a{};
+        a.theta = t->theta;
+        a.m = t->m;
+        a.v = t->v;
+        a.grad = t->grad;
+        a.n = kMlpParams;
+        a.lr = lr;
+        a.beta1 = t->cfg.beta1;
+        a.beta2 = t->cfg.beta2;
+        a.eps = t->cfg.eps;
+        a.c1 = (float)(1.0 / (1.0 - std::pow((double)t->cfg.beta1, (double)t->step)));
+        a.c2 = (float)(1.0 / (1.0 - std::pow((double)t->cfg.beta2, (double)t->step)));
+        e = launch_adam(a, t->stream);
+    }
+    if (e == hipSuccess) e = launch_pack_mlp(t->theta, t->fwd, t->bwd, t->bias, t->stream);
+    if (e == hipSuccess && loss) {
+        e = hipMemcpyAsync(loss, t->loss, sizeof(float), hipMemcpyDeviceToHost, t->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(t->stream);
+    }
+    if (e != hipSuccess) return lhip_fail(e, "training step");
+    return SDFDDGI_OK;
+}
+
+sdfddgi_status sdfddgi_trainer_get_params(sdfddgi_trainer *t, float *params) {
+    g_learned_error.clear();
+    if (!t || !params) return lfail(SDFDDGI_EINVAL, "null argument");
+    hipError_t e = hipSetDevice(t->device);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(params, t->theta, kMlpParams * sizeof(float), hipMemcpyDeviceToHost,
+                           t->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(t->stream);
+    if (e != hipSuccess) return lhip_fail(e, "copying parameters");
+    return SDFDDGI_OK;
+}
+
+const char *sdfddgi_learned_last_error(void) { return g_learned_error.c_str(); }
 
 }  // extern "C"

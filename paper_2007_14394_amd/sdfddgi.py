@@ -33,7 +33,15 @@ EXPORTED = [
     "sdfddgi_reset_history", "sdfddgi_get_payload", "sdfddgi_get_ray_records",
     "sdfddgi_get_ray_directions", "sdfddgi_ray_directions", "sdfddgi_get_kernel_times",
     "sdfddgi_get_sizes", "sdfddgi_last_error", "sdfddgi_destroy",
+    "sdfddgi_denoiser_create", "sdfddgi_denoiser_infer", "sdfddgi_denoiser_destroy",
+    "sdfddgi_update_frame_learned", "sdfddgi_get_fallback", "sdfddgi_learned_examples",
+    "sdfddgi_trainer_create", "sdfddgi_trainer_gradient", "sdfddgi_trainer_step",
+    "sdfddgi_trainer_get_params", "sdfddgi_trainer_destroy", "sdfddgi_learned_last_error",
 ]
+SDFDDGI_DENOISER_PARAMS = 9604
+SDFDDGI_FEATURES = 16
+KERNEL_TIMES = ("tables", "primary", "hits", "blend", "frame", "denoise", "fallback_trace",
+                "fallback_blend")
 
 
 class sdfddgi_sdf_level(ctypes.Structure):
@@ -59,7 +67,13 @@ class sdfddgi_params(ctypes.Structure):
                 ("hysteresis", ctypes.c_float), ("bounce_gain", ctypes.c_float),
                 ("depth_sharpness", ctypes.c_float), ("shadow_bias", ctypes.c_float),
                 ("relax", ctypes.c_float), ("sky_rgb", ctypes.c_float * 3),
-                ("albedo", ctypes.c_float * 3), ("flags", ctypes.c_uint32)]
+                ("albedo", ctypes.c_float * 3), ("flags", ctypes.c_uint32),
+                ("learned_rays", ctypes.c_int32), ("fallback_error", ctypes.c_float)]
+
+
+class sdfddgi_train_config(ctypes.Structure):
+    _fields_ = [("head_weight", ctypes.c_float), ("min_error", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
 
 
 class sdfddgi_light(ctypes.Structure):
@@ -110,8 +124,25 @@ def load_library() -> ctypes.CDLL:
     L.sdfddgi_last_error.argtypes = [vp]
     L.sdfddgi_last_error.restype = ctypes.c_char_p
     L.sdfddgi_destroy.argtypes = [vp]
+    f32 = ctypes.c_float
+    L.sdfddgi_denoiser_create.argtypes = [vp, i32, f32, f32, vp, ctypes.POINTER(vp)]
+    L.sdfddgi_denoiser_infer.argtypes = [vp, vp, i64, vp]
+    L.sdfddgi_denoiser_destroy.argtypes = [vp]
+    L.sdfddgi_update_frame_learned.argtypes = [vp, vp, ctypes.POINTER(sdfddgi_light), u64]
+    L.sdfddgi_get_fallback.argtypes = [vp, ctypes.POINTER(i32), vp, vp]
+    L.sdfddgi_learned_examples.argtypes = [vp, vp, ctypes.POINTER(sdfddgi_light), u64, i32, f32,
+                                           vp, vp]
+    L.sdfddgi_trainer_create.argtypes = [vp, i32, ctypes.POINTER(sdfddgi_train_config), vp,
+                                         ctypes.POINTER(vp)]
+    L.sdfddgi_trainer_gradient.argtypes = [vp, vp, vp, i32, vp, vp]
+    L.sdfddgi_trainer_step.argtypes = [vp, vp, vp, i64, i32, u64, f32, vp]
+    L.sdfddgi_trainer_get_params.argtypes = [vp, vp]
+    L.sdfddgi_trainer_destroy.argtypes = [vp]
+    L.sdfddgi_learned_last_error.argtypes = []
+    L.sdfddgi_learned_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
-        if name not in ("sdfddgi_default_params", "sdfddgi_last_error"):
+        if name not in ("sdfddgi_default_params", "sdfddgi_last_error",
+                        "sdfddgi_learned_last_error"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -313,9 +344,10 @@ def sdfddgi_ray_directions(rotation_seed: int, rays: int) -> np.ndarray:
 
 
 def sdfddgi_get_kernel_times(ctx: Context):
-    ms = (ctypes.c_float * 5)()
-    _check(ctx, load_library().sdfddgi_get_kernel_times(ctx.handle, ms, 5))
-    return dict(tables=ms[0], primary=ms[1], hits=ms[2], blend=ms[3], frame=ms[4])
+    n = len(KERNEL_TIMES)
+    ms = (ctypes.c_float * n)()
+    _check(ctx, load_library().sdfddgi_get_kernel_times(ctx.handle, ms, n))
+    return {k: ms[i] for i, k in enumerate(KERNEL_TIMES)}
 
 
 def sdfddgi_get_sizes(ctx: Context):
@@ -335,6 +367,194 @@ def sdfddgi_destroy(ctx: Context) -> None:
     if ctx.handle and ctx.handle.value:
         _check(None, load_library().sdfddgi_destroy(ctx.handle))
         ctx.handle = ctypes.c_void_p(0)
+
+
+# ------------------------------------------------------------ learned form --
+
+class Denoiser:
+    def __init__(self, handle: int, device, irr_scale: float, depth_scale: float):
+        self.handle = ctypes.c_void_p(handle)
+        self.device = device
+        self.irr_scale = irr_scale
+        self.depth_scale = depth_scale
+
+    def __del__(self):
+        try:
+            if self.handle and self.handle.value:
+                load_library().sdfddgi_denoiser_destroy(self.handle)
+                self.handle = ctypes.c_void_p(0)
+        except Exception:
+            pass
+
+
+class Trainer:
+    def __init__(self, handle: int, device):
+        self.handle = ctypes.c_void_p(handle)
+        self.device = device
+
+    def __del__(self):
+        try:
+            if self.handle and self.handle.value:
+                load_library().sdfddgi_trainer_destroy(self.handle)
+                self.handle = ctypes.c_void_p(0)
+        except Exception:
+            pass
+
+
+def _lcheck(status: int):
+    if status != SDFDDGI_OK:
+        msg = load_library().sdfddgi_learned_last_error()
+        raise SdfddgiError(status, (msg or b"").decode())
+
+
+def _host_params(params) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(params, dtype=np.float32).ravel())
+    if a.size != SDFDDGI_DENOISER_PARAMS:
+        raise ValueError(f"need {SDFDDGI_DENOISER_PARAMS} parameters, got {a.size}")
+    return a
+
+
+def sdfddgi_denoiser_create(params, irr_scale: float, depth_scale: float, device="cuda:0",
+                            stream=None) -> Denoiser:
+    import torch
+    a = _host_params(params)
+    dev = torch.device(device)
+    with torch.cuda.device(dev):
+        out = ctypes.c_void_p()
+        _lcheck(load_library().sdfddgi_denoiser_create(
+            ctypes.c_void_p(a.ctypes.data), ctypes.c_int32(a.size), ctypes.c_float(irr_scale),
+            ctypes.c_float(depth_scale), ctypes.c_void_p(_stream_handle(stream)),
+            ctypes.byref(out)))
+    return Denoiser(out.value, dev, float(irr_scale), float(depth_scale))
+
+
+def sdfddgi_denoiser_infer(den: Denoiser, features, out=None):
+    import torch
+    n = int(features.shape[0])
+    if tuple(features.shape) != (n, SDFDDGI_FEATURES):
+        raise ValueError("features must be [n,16]")
+    if out is None:
+        out = torch.empty((n, 4), dtype=torch.float32, device=den.device)
+    if n == 0:
+        return out
+    _lcheck(load_library().sdfddgi_denoiser_infer(
+        den.handle, _dev_ptr(features, torch.float32, "features", den.device), ctypes.c_int64(n),
+        _dev_ptr(out, torch.float32, "out", den.device)))
+    return out
+
+
+def sdfddgi_denoiser_destroy(den: Denoiser) -> None:
+    if den.handle and den.handle.value:
+        _lcheck(load_library().sdfddgi_denoiser_destroy(den.handle))
+        den.handle = ctypes.c_void_p(0)
+
+
+def sdfddgi_update_frame_learned(ctx: Context, den: Denoiser, dir_to_light, radiance_rgb,
+                                 rotation_seed: int) -> None:
+    li = sdfddgi_light()
+    li.dir_to_light[:] = [float(v) for v in dir_to_light]
+    li.radiance_rgb[:] = [float(v) for v in radiance_rgb]
+    _check(ctx, load_library().sdfddgi_update_frame_learned(
+        ctx.handle, den.handle, ctypes.byref(li), ctypes.c_uint64(int(rotation_seed))))
+
+
+def sdfddgi_get_fallback(ctx: Context, want_lists: bool = True):
+    """(count, fallback probe indices [count] or None, mean predicted errors [P] or None)."""
+    import torch
+    cnt = ctypes.c_int32()
+    probes = errs = None
+    if want_lists:
+        probes = torch.empty(ctx.probes, dtype=torch.int32, device=ctx.device)
+        errs = torch.empty(ctx.probes, dtype=torch.float32, device=ctx.device)
+    _check(ctx, load_library().sdfddgi_get_fallback(
+        ctx.handle, ctypes.byref(cnt), probes.data_ptr() if probes is not None else None,
+        errs.data_ptr() if errs is not None else None))
+    if probes is not None:
+        probes = probes[:cnt.value]
+    return cnt.value, probes, errs
+
+
+def sdfddgi_learned_examples(ctx: Context, den: Denoiser, dir_to_light, radiance_rgb,
+                             rotation_seed: int, target_rays: int, rel_floor: float,
+                             features=None, targets=None):
+    import torch
+    n = ctx.probes * ctx.irr_res * ctx.irr_res
+    if features is None:
+        features = torch.empty((n, SDFDDGI_FEATURES), dtype=torch.float32, device=ctx.device)
+    if targets is None:
+        targets = torch.empty((n, 4), dtype=torch.float32, device=ctx.device)
+    if tuple(features.shape) != (n, SDFDDGI_FEATURES) or tuple(targets.shape) != (n, 4):
+        raise ValueError("features must be [P*Ti,16] and targets [P*Ti,4]")
+    li = sdfddgi_light()
+    li.dir_to_light[:] = [float(v) for v in dir_to_light]
+    li.radiance_rgb[:] = [float(v) for v in radiance_rgb]
+    _check(ctx, load_library().sdfddgi_learned_examples(
+        ctx.handle, den.handle, ctypes.byref(li), ctypes.c_uint64(int(rotation_seed)),
+        ctypes.c_int32(int(target_rays)), ctypes.c_float(rel_floor),
+        _dev_ptr(features, torch.float32, "features", ctx.device),
+        _dev_ptr(targets, torch.float32, "targets", ctx.device)))
+    return features, targets
+
+
+def sdfddgi_trainer_create(init_params, head_weight: float = 0.1, min_error: float = 1e-4,
+                           beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
+                           device="cuda:0", stream=None) -> Trainer:
+    import torch
+    a = _host_params(init_params)
+    cfg = sdfddgi_train_config(head_weight, min_error, beta1, beta2, eps)
+    dev = torch.device(device)
+    with torch.cuda.device(dev):
+        out = ctypes.c_void_p()
+        _lcheck(load_library().sdfddgi_trainer_create(
+            ctypes.c_void_p(a.ctypes.data), ctypes.c_int32(a.size), ctypes.byref(cfg),
+            ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(out)))
+    return Trainer(out.value, dev)
+
+
+def sdfddgi_trainer_gradient(tr: Trainer, features, targets):
+    """(mean loss, gradient float32 [SDFDDGI_DENOISER_PARAMS]) over all rows in order."""
+    import torch
+    n = int(features.shape[0])
+    if tuple(features.shape) != (n, SDFDDGI_FEATURES) or tuple(targets.shape) != (n, 4):
+        raise ValueError("features must be [n,16] and targets [n,4]")
+    g = np.zeros(SDFDDGI_DENOISER_PARAMS, dtype=np.float32)
+    loss = ctypes.c_float()
+    _lcheck(load_library().sdfddgi_trainer_gradient(
+        tr.handle, _dev_ptr(features, torch.float32, "features", tr.device),
+        _dev_ptr(targets, torch.float32, "targets", tr.device), ctypes.c_int32(n),
+        ctypes.c_void_p(g.ctypes.data), ctypes.byref(loss)))
+    return float(loss.value), g
+
+
+def sdfddgi_trainer_step(tr: Trainer, features, targets, batch: int, seed: int, lr: float,
+                         want_loss: bool = False, count: Optional[int] = None):
+    import torch
+    n = int(features.shape[0]) if count is None else int(count)
+    if features.shape[0] < n or targets.shape[0] < n:
+        raise ValueError("count exceeds the arrays")
+    loss = ctypes.c_float()
+    _lcheck(load_library().sdfddgi_trainer_step(
+        tr.handle, _dev_ptr(features, torch.float32, "features", tr.device),
+        _dev_ptr(targets, torch.float32, "targets", tr.device), ctypes.c_int64(n),
+        ctypes.c_int32(int(batch)), ctypes.c_uint64(int(seed)), ctypes.c_float(lr),
+        ctypes.byref(loss) if want_loss else None))
+    return float(loss.value) if want_loss else None
+
+
+def sdfddgi_trainer_get_params(tr: Trainer) -> np.ndarray:
+    out = np.zeros(SDFDDGI_DENOISER_PARAMS, dtype=np.float32)
+    _lcheck(load_library().sdfddgi_trainer_get_params(tr.handle, ctypes.c_void_p(out.ctypes.data)))
+    return out
+
+
+def sdfddgi_trainer_destroy(tr: Trainer) -> None:
+    if tr.handle and tr.handle.value:
+        _lcheck(load_library().sdfddgi_trainer_destroy(tr.handle))
+        tr.handle = ctypes.c_void_p(0)
+
+
+def sdfddgi_learned_last_error() -> str:
+    return (load_library().sdfddgi_learned_last_error() or b"").decode()
 
 
 # -------------------------------------------------------------- conveniences --

@@ -56,6 +56,7 @@ def test_host_directions_reject_bad_sizes():
 
 def test_default_params():
     p = S.sdfddgi_default_params()
+    assert p.learned_rays == 0 and p.fallback_error == np.float32(0.02)
     assert p.rays_per_probe == 144 and p.max_steps == 64
     assert p.irr_res == 8 and p.depth_res == 16
     assert p.hysteresis == np.float32(0.97) and p.depth_sharpness == 50.0
@@ -101,6 +102,13 @@ def _create_status(g, pg, p):
     lambda g, pg, p: setattr(g.level[0], "sdf", None),
     lambda g, pg, p: pg.n.__setitem__(2, 1),
     lambda g, pg, p: pg.spacing.__setitem__(0, -2.0),
+    lambda g, pg, p: setattr(p, "learned_rays", 40),          # not a multiple of 16
+    lambda g, pg, p: setattr(p, "learned_rays", 160),         # more than rays_per_probe
+    lambda g, pg, p: (setattr(p, "learned_rays", 32), setattr(p, "depth_res", 12)),
+    lambda g, pg, p: (setattr(p, "learned_rays", 32), setattr(p, "irr_res", 32),
+                      setattr(p, "depth_res", 32)),
+    lambda g, pg, p: (setattr(p, "learned_rays", 32), setattr(p, "fallback_error", -1.0)),
+    lambda g, pg, p: setattr(p, "fallback_error", float("nan")),
 ])
 def test_create_rejects_bad_arguments_before_touching_a_device(mutate):
     g, pg = _grid_and_probes()
@@ -138,3 +146,36 @@ def test_binding_fails_loudly_without_the_library(tmp_path, monkeypatch):
     monkeypatch.setattr(S, "_lib", None)
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         S.load_library()
+
+
+def test_learned_entry_points_reject_bad_arguments_before_touching_a_device():
+    lib = S.load_library()
+    out = ctypes.c_void_p()
+    good = np.zeros(S.SDFDDGI_DENOISER_PARAMS, dtype=np.float32)
+    gp = ctypes.c_void_p(good.ctypes.data)
+    n = S.SDFDDGI_DENOISER_PARAMS
+    assert lib.sdfddgi_denoiser_create(gp, n - 1, 1.0, 1.0, None, ctypes.byref(out)) == S.SDFDDGI_EINVAL
+    assert lib.sdfddgi_denoiser_create(gp, n, 0.0, 1.0, None, ctypes.byref(out)) == S.SDFDDGI_EINVAL
+    assert lib.sdfddgi_denoiser_create(gp, n, 1.0, float("inf"), None, ctypes.byref(out)) == S.SDFDDGI_EINVAL
+    bad = good.copy()
+    bad[17] = np.nan
+    assert lib.sdfddgi_denoiser_create(ctypes.c_void_p(bad.ctypes.data), n, 1.0, 1.0, None,
+                                       ctypes.byref(out)) == S.SDFDDGI_EINVAL
+    assert "non-finite" in S.sdfddgi_learned_last_error()
+    assert out.value is None
+    cfg = S.sdfddgi_train_config(0.1, 1e-4, 0.9, 0.999, 1e-8)
+    for field, value in [("min_error", 0.0), ("beta1", 1.0), ("beta2", -0.1), ("eps", -1.0),
+                         ("head_weight", float("nan"))]:
+        c = S.sdfddgi_train_config(0.1, 1e-4, 0.9, 0.999, 1e-8)
+        setattr(c, field, value)
+        assert lib.sdfddgi_trainer_create(gp, n, ctypes.byref(c), None,
+                                          ctypes.byref(out)) == S.SDFDDGI_EINVAL
+    assert lib.sdfddgi_trainer_create(gp, n, None, None, ctypes.byref(out)) == S.SDFDDGI_EINVAL
+    assert lib.sdfddgi_trainer_create(gp, 5, ctypes.byref(cfg), None,
+                                      ctypes.byref(out)) == S.SDFDDGI_EINVAL
+    li = S.sdfddgi_light()
+    assert lib.sdfddgi_update_frame_learned(None, None, ctypes.byref(li), 1) == S.SDFDDGI_EINVAL
+    assert lib.sdfddgi_denoiser_infer(None, None, 4, None) == S.SDFDDGI_EINVAL
+    assert lib.sdfddgi_trainer_step(None, None, None, 1, 1, 0, 0.1, None) == S.SDFDDGI_EINVAL
+    assert lib.sdfddgi_denoiser_destroy(None) == S.SDFDDGI_OK
+    assert lib.sdfddgi_trainer_destroy(None) == S.SDFDDGI_OK

@@ -1,0 +1,350 @@
+"""GPU parity of the learned form: the denoiser, training and learned-frame kernels
+against the checker's learned form (mirror mode: the same bfloat16 rounding points),
+through the C ABI.
+
+Tolerance of the network's outputs. Both sides round the same values to bfloat16
+at the same places, but the kernel accumulates in binary32 (MFMA order) and the
+checker in binary64, so an activation that lies within an accumulation error of
+a rounding boundary can round the other way: one bfloat16 unit (2^-8 relative)
+on that activation. Each of the at most five rounding stages (input, three
+hidden layers, and in the backward pass the output gradient) therefore moves an
+output by at most 2^-8 of its magnitude bound M = |W4| (|W3| (|W2| (|W1| |x|) +
+|b2|) + |b3|) + |b4|, giving |o_gpu - o_ref| <= 5 * 2^-8 M < 2^-5.6 M; the tests
+use 2^-5 M. Flips are rare, so most outputs agree far more closely, which the
+tests check as well.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+F = oracle.FEATURES
+OUT_BOUND = 2.0 ** -5
+
+
+def announce(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    from paper_2007_14394_amd import sdfddgi
+    assert torch.cuda.is_available(), "GPU tests need a visible gfx950 device"
+    sdfddgi.load_library()
+    return sdfddgi
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to("cuda:0")
+
+
+def to_host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def random_theta(seed, scale=1.0):
+    """He-style initial parameters (the same recipe the trainer starts from)."""
+    rng = np.random.default_rng(seed)
+    th = np.zeros(oracle.MLP_PARAMS)
+    shapes = [(oracle.OFF_W1, 64, 16), (oracle.OFF_W2, 64, 64), (oracle.OFF_W3, 64, 64),
+              (oracle.OFF_W4, 4, 64)]
+    for off, r, c in shapes:
+        th[off:off + r * c] = rng.normal(0, scale * math.sqrt(2.0 / c), r * c)
+    for off in (oracle.OFF_B2, oracle.OFF_B3):
+        th[off:off + 64] = rng.normal(0, 0.05 * scale, 64)
+    th[oracle.OFF_B4:oracle.OFF_B4 + 4] = rng.normal(0, 0.05 * scale, 4)
+    return th.astype(np.float32).astype(np.float64)
+
+
+def magnitude(theta, x):
+    """M of the module docstring, per row of x and output: the network evaluated
+    exactly with |theta| and |x| (its ReLUs then pass everything)."""
+    a = np.abs(np.asarray(theta, dtype=np.float64))
+    return oracle.mlp_forward(a, np.abs(np.asarray(x, dtype=np.float64)), mirror=False)
+
+
+def random_features(n, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.normal(0, 1, (n, F)).astype(np.float32)
+    x[:, 12] = 1.0
+    x[:, 13:] = 0.0
+    return x
+
+
+# ------------------------------------------------------------------ network --
+
+@pytest.mark.parametrize("n", [1, 16, 1037])
+def test_inference_matches_checker(S, n):
+    announce(f"denoiser_infer n={n}")
+    th = random_theta(1)
+    x = random_features(n, 2)
+    den = S.sdfddgi_denoiser_create(th.astype(np.float32), 2.0, 1.5)
+    out = to_host(S.sdfddgi_denoiser_infer(den, to_dev(x)))
+    ref = oracle.mlp_forward(th, x.astype(np.float64), mirror=True)
+    M = magnitude(th, x.astype(np.float64))
+    err = np.abs(out - ref)
+    assert np.all(err <= OUT_BOUND * M + 1e-7), float((err / M).max())
+    # rounding flips are rare: nearly every output agrees to accumulation precision
+    assert np.mean(err <= 1e-5 * M + 1e-7) > 0.95
+
+
+def test_passthrough_network_is_exact(S):
+    # o_c = x_c - x_{3+c} on bfloat16-representable inputs: exact on both sides
+    from tests.test_learned_pins import passthrough_theta
+    th = passthrough_theta(scale=0.5)
+    rng = np.random.default_rng(3)
+    x = (rng.integers(-64, 64, (200, F)) / 16.0).astype(np.float32)
+    den = S.sdfddgi_denoiser_create(th.astype(np.float32), 1.0, 1.0)
+    out = to_host(S.sdfddgi_denoiser_infer(den, to_dev(x)))
+    np.testing.assert_array_equal(out[:, :3], 0.5 * (x[:, :3] - x[:, 3:6]))
+    np.testing.assert_array_equal(out[:, 3], -2.0)
+
+
+def training_problem(n, seed):
+    th = random_theta(seed)
+    x = random_features(n, seed + 10)
+    rng = np.random.default_rng(seed + 20)
+    tg = np.column_stack([rng.normal(0, 0.3, (n, 3)), rng.uniform(0.3, 2.0, n)]).astype(np.float32)
+    return th, x, tg
+
+
+@pytest.mark.parametrize("n", [16, 300])
+def test_training_gradient_matches_checker(S, n):
+    announce(f"trainer_gradient n={n}")
+    th, x, tg = training_problem(n, 4)
+    tr = S.sdfddgi_trainer_create(th.astype(np.float32), head_weight=0.3, min_error=1e-4)
+    loss, g = S.sdfddgi_trainer_gradient(tr, to_dev(x), to_dev(tg))
+    rl, rg = oracle.mlp_loss_grad(th, x.astype(np.float64), tg.astype(np.float64), 0.3, 1e-4,
+                                  mirror=True)
+    assert abs(loss - rl) <= 1e-3 * abs(rl)
+    blocks = [("W1", oracle.OFF_W1, oracle.OFF_W2), ("W2", oracle.OFF_W2, oracle.OFF_B2),
+              ("b2", oracle.OFF_B2, oracle.OFF_W3), ("W3", oracle.OFF_W3, oracle.OFF_B3),
+              ("b3", oracle.OFF_B3, oracle.OFF_W4), ("W4", oracle.OFF_W4, oracle.OFF_B4),
+              ("b4", oracle.OFF_B4, oracle.MLP_PARAMS)]
+    for name, a, b in blocks:
+        rel = np.linalg.norm(g[a:b] - rg[a:b]) / np.linalg.norm(rg[a:b])
+        assert rel <= OUT_BOUND, f"{name}: relative gradient error {rel:.2e}"
+
+
+def test_adam_steps_match_checker(S):
+    announce("trainer_step x2")
+    count, batch, lr = 700, 256, 1e-3
+    th, x, tg = training_problem(count, 6)
+    tr = S.sdfddgi_trainer_create(th.astype(np.float32), head_weight=0.3, min_error=1e-4)
+    xd, td = to_dev(x), to_dev(tg)
+    ref = th.copy()
+    m, v = np.zeros_like(ref), np.zeros_like(ref)
+    prev_gpu = th.astype(np.float32).astype(np.float64)
+    for step, seed in enumerate((11, 12), start=1):
+        S.sdfddgi_trainer_step(tr, xd, td, batch, seed, lr)
+        got = S.sdfddgi_trainer_get_params(tr).astype(np.float64)
+        idx = [oracle.batch_index(seed, i, count) for i in range(batch)]
+        _, g = oracle.mlp_loss_grad(ref, x[idx].astype(np.float64), tg[idx].astype(np.float64),
+                                    0.3, 1e-4, mirror=True)
+        before = ref.copy()
+        oracle.adam_step(ref, m, v, g, step, lr)
+        d_ref, d_gpu = ref - before, got - prev_gpu
+        # Adam's steps are ~lr * sign(g): compare where the gradient is well above
+        # the kernel/checker gradient noise, bound the step everywhere
+        strong = np.abs(g) > 0.05 * np.abs(g).max()
+        assert strong.sum() > 100
+        assert np.all(np.abs(d_gpu - d_ref)[strong] <= 0.05 * lr)
+        assert np.all(np.abs(d_gpu) <= lr * 1.02)
+        # keep both on the GPU's trajectory for the next step
+        ref = got.copy() if step == 1 else ref
+        prev_gpu = got
+
+
+# ------------------------------------------------------------ learned frame --
+
+S_IRR, D_DEPTH = 2.0, 1.5
+
+
+def learned_workload():
+    w = scenegen.small_cascade(0, rays=64, frames=4)
+    return w
+
+
+def make_ctx(S, w, tau, flags=0, learned_rays=32):
+    return S.context_from_workload(w, flags=flags, learned_rays=learned_rays, fallback_error=tau)
+
+
+def warm(S, ctx, w, frames=2):
+    for fr in w.frames[:frames]:
+        S.sdfddgi_update_frame(ctx, fr.dir_to_light, fr.radiance_rgb, fr.rotation_seed)
+    irr, dep = S.sdfddgi_get_maps(ctx)
+    return to_host(irr).astype(np.float64), to_host(dep).astype(np.float64)
+
+
+def test_examples_match_checker(S):
+    announce("learned_examples small_cascade")
+    w = learned_workload()
+    ctx = make_ctx(S, w, 0.02)
+    den = S.sdfddgi_denoiser_create(random_theta(0).astype(np.float32), S_IRR, D_DEPTH)
+    irr, dep = warm(S, ctx, w)
+    fr = w.frames[2]
+    feats, targ = S.sdfddgi_learned_examples(ctx, den, fr.dir_to_light, fr.radiance_rgb,
+                                             fr.rotation_seed, 128, 0.05)
+    feats, targ = to_host(feats), to_host(targ)
+    # maps untouched
+    irr2, dep2 = S.sdfddgi_get_maps(ctx)
+    assert np.array_equal(to_host(irr2), irr.astype(np.float32))
+    ck = oracle.Checker(w)
+    low = oracle.Checker(w, rays=32, hysteresis=0.0)
+    ui, _, _, _ = low.update_probes(fr, True, irr, dep)
+    ref_f = ck.learned_features(ui, irr, dep, S_IRR, D_DEPTH).reshape(-1, F)
+    tgt = oracle.Checker(w, rays=128, hysteresis=0.0)
+    ti, _, _, _ = tgt.update_probes(fr, True, irr, dep)
+    ri = w.params.irr_res
+    t_in = ti[:, 1:ri + 1, 1:ri + 1, :].reshape(-1, 3)
+    p_in = irr[:, 1:ri + 1, 1:ri + 1, :].reshape(-1, 3)
+    ref_z = (t_in - p_in) / S_IRR
+    ref_q = np.abs(t_in).sum(axis=1) / S_IRR + 0.05
+    scale = np.abs(ref_f).max(axis=0) + 1e-3
+    assert np.all(np.abs(feats - ref_f) <= 2e-4 * scale + 1e-6), \
+        float((np.abs(feats - ref_f) / scale).max())
+    zs = np.abs(t_in).max() / S_IRR
+    assert np.all(np.abs(targ[:, :3] - ref_z) <= 2e-4 * zs)
+    np.testing.assert_allclose(targ[:, 3], ref_q, rtol=2e-4)
+
+
+def run_learned(S, w, theta, tau, frames, flags=0):
+    ctx = make_ctx(S, w, tau, flags=flags)
+    den = S.sdfddgi_denoiser_create(np.asarray(theta, dtype=np.float32), S_IRR, D_DEPTH)
+    irr, dep = warm(S, ctx, w)
+    out = []
+    for fr in frames:
+        S.sdfddgi_update_frame_learned(ctx, den, fr.dir_to_light, fr.radiance_rgb,
+                                       fr.rotation_seed)
+        cnt, lst, errs = S.sdfddgi_get_fallback(ctx)
+        ni, nd = S.sdfddgi_get_maps(ctx)
+        out.append(dict(count=cnt, fallback=np.sort(to_host(lst)), mean_error=to_host(errs),
+                        irr=to_host(ni).astype(np.float64), depth=to_host(nd).astype(np.float64)))
+    return (irr, dep), out
+
+
+def test_learned_frame_matches_checker(S):
+    announce("learned frame small_cascade")
+    w = learned_workload()
+    th = random_theta(7, scale=0.5)
+    th[oracle.OFF_B4 + 3] = -3.0          # predicted errors around exp(-3)
+    ck = oracle.Checker(w)
+    P = ck.num_probes
+    # tau at the median of the checker's mean predicted errors: both decisions occur
+    ctx = make_ctx(S, w, 0.0)
+    irr0, dep0 = warm(S, ctx, w)
+    probe = ck.learned_frame(w.frames[2], False, irr0, dep0, th, S_IRR, D_DEPTH, math.inf, 32)
+    tau = float(np.median(probe["mean_error"]))
+    (irr, dep), res = run_learned(S, w, th, tau, [w.frames[2], w.frames[3]])
+    prev = (irr, dep)
+    for k, r in enumerate(res):
+        fr = w.frames[2 + k]
+        ref = ck.learned_frame(fr, False, prev[0], prev[1], th, S_IRR, D_DEPTH, tau, 32)
+        # mean predicted error: exp(o3) moves by at most the output bound of o3
+        M3 = magnitude(th, ref["features"].reshape(-1, F))[:, 3].reshape(P, -1)
+        slack = np.exp(OUT_BOUND * M3.max(axis=1)) - 1.0
+        rel = np.abs(r["mean_error"] / ref["mean_error"] - 1.0)
+        assert np.all(rel <= slack + 1e-5), float((rel - slack).max())
+        assert np.median(rel) <= 1e-4
+        # decisions agree wherever the checker's mean is clearly on one side of tau
+        gpu_fb = np.zeros(P, bool)
+        gpu_fb[r["fallback"]] = True
+        assert r["count"] == gpu_fb.sum() and len(np.unique(r["fallback"])) == r["count"]
+        clear = np.abs(ref["mean_error"] / tau - 1.0) > 2 * slack + 1e-4
+        assert np.array_equal(gpu_fb[clear], ref["decided"][clear])
+        assert 0 < gpu_fb.sum() < P
+        # maps, given the GPU's decisions
+        ref2 = ck.learned_frame(fr, False, prev[0], prev[1], th, S_IRR, D_DEPTH, tau, 32,
+                                fallback=gpu_fb)
+        ok, worst = H.rel_close(r["depth"], ref2["depth"], rel=1e-4)
+        assert ok, worst
+        ok, worst = H.rel_close(r["irr"][gpu_fb], ref2["irr"][gpu_fb], rel=1e-4)
+        assert ok, worst
+        # accepted texels: U_hat = max(0, E_prev + S o) enters with weight (1 - h)
+        h = ck.hysteresis
+        Mo = magnitude(th, ref2["features"].reshape(-1, F))[:, :3]
+        ri = w.params.irr_res
+        bound = np.zeros_like(ref2["irr"])
+        bound[:, 1:ri + 1, 1:ri + 1, :] = ((1 - h) * S_IRR * OUT_BOUND * Mo).reshape(P, ri, ri, 3)
+        oracle._fill_borders(bound, ri)   # border texels copy interior ones
+        acc = ~gpu_fb
+        got, want = r["irr"][acc], ref2["irr"][acc]
+        assert np.all(np.abs(got - want) <= bound[acc] + 1e-4 * np.abs(want) + 1e-6)
+        # and typically far closer than the bound
+        assert np.median(np.abs(got - want) / (np.abs(want) + 1e-3)) <= 1e-4
+        prev = (r["irr"], r["depth"])
+
+
+def test_all_fallback_is_the_plain_frame_bit_for_bit(S):
+    announce("learned frame tau=0 vs plain")
+    w = learned_workload()
+    th = random_theta(3)
+    (irr, dep), res = run_learned(S, w, th, 0.0, [w.frames[2]])
+    ctx = S.context_from_workload(w)
+    warm(S, ctx, w)
+    fr = w.frames[2]
+    S.sdfddgi_update_frame(ctx, fr.dir_to_light, fr.radiance_rgb, fr.rotation_seed)
+    pi, pd = S.sdfddgi_get_maps(ctx)
+    assert res[0]["count"] == w.num_probes
+    assert np.array_equal(res[0]["irr"].astype(np.float32), to_host(pi))
+    assert np.array_equal(res[0]["depth"].astype(np.float32), to_host(pd))
+
+
+def test_reset_history_falls_back_everywhere(S):
+    announce("learned frame after reset")
+    w = learned_workload()
+    ctx = make_ctx(S, w, math.inf)
+    den = S.sdfddgi_denoiser_create(random_theta(5).astype(np.float32), S_IRR, D_DEPTH)
+    warm(S, ctx, w)
+    S.sdfddgi_reset_history(ctx)
+    fr = w.frames[2]
+    S.sdfddgi_update_frame_learned(ctx, den, fr.dir_to_light, fr.radiance_rgb, fr.rotation_seed)
+    cnt, _, _ = S.sdfddgi_get_fallback(ctx)
+    assert cnt == w.num_probes
+    # the flags are cleared by that update: the next learned frame accepts every probe
+    S.sdfddgi_update_frame_learned(ctx, den, fr.dir_to_light, fr.radiance_rgb, fr.rotation_seed)
+    cnt, _, _ = S.sdfddgi_get_fallback(ctx)
+    assert cnt == 0
+
+
+def test_precision_form_all_fallback_is_its_plain_frame(S):
+    announce("learned frame fp16 tau=0 vs plain fp16")
+    w = learned_workload()
+    (irr, dep), res = run_learned(S, w, random_theta(3), 0.0, [w.frames[2]],
+                                  flags=S.SDFDDGI_FLAG_FP16)
+    ctx = S.context_from_workload(w, flags=S.SDFDDGI_FLAG_FP16)
+    warm(S, ctx, w)
+    fr = w.frames[2]
+    S.sdfddgi_update_frame(ctx, fr.dir_to_light, fr.radiance_rgb, fr.rotation_seed)
+    pi, pd = S.sdfddgi_get_maps(ctx)
+    assert np.array_equal(res[0]["irr"].astype(np.float32), to_host(pi))
+    assert np.array_equal(res[0]["depth"].astype(np.float32), to_host(pd))
+
+
+def test_learned_errors_are_rejected(S):
+    w = learned_workload()
+    ctx = S.context_from_workload(w)            # no learned ray set
+    den = S.sdfddgi_denoiser_create(random_theta(0).astype(np.float32), 1.0, 1.0)
+    fr = w.frames[0]
+    with pytest.raises(S.SdfddgiError) as e:
+        S.sdfddgi_update_frame_learned(ctx, den, fr.dir_to_light, fr.radiance_rgb, 1)
+    assert e.value.status == S.SDFDDGI_ESTATE
+    with pytest.raises(S.SdfddgiError) as e:
+        S.sdfddgi_get_fallback(ctx)
+    assert e.value.status == S.SDFDDGI_ESTATE
+    ctx2 = make_ctx(S, w, 0.02)
+    with pytest.raises(S.SdfddgiError) as e:
+        S.sdfddgi_learned_examples(ctx2, den, fr.dir_to_light, fr.radiance_rgb, 1, 100, 0.05)
+    assert e.value.status == S.SDFDDGI_EINVAL
