@@ -44,6 +44,10 @@ def parse():
                     help="probes in the CPU-baseline sample (0 disables it)")
     ap.add_argument("--no-stats", action="store_true",
                     help="skip the ray-statistics pass (for profiler runs)")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-vs-plain comparison at equal irradiance error")
+    ap.add_argument("--learned-frames", type=int, default=60,
+                    help="frames of each run in the learned-vs-plain comparison")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times "
                          "(reference reading for the HBM byte counters) and exit")
@@ -128,6 +132,93 @@ def cpu_baseline(w, probes: int):
             "sample": f"{len(sample)} of {w.num_probes} probes (every {step}th) x "
                       f"{w.params.rays_per_probe} rays, one frame, binary32 geometry + "
                       f"binary64 radiometry, {threads} threads, {dt:.2f} s wall"}
+
+
+def learned_comparison(S, w, n_frames: int, torch):
+    """Irradiance error of each form against the plain 1024-ray update over the same
+    frames, and its ms/frame; the learned forms' speed-up over the plain FP32 form
+    at equal irradiance error.
+
+    Every form runs the same n_frames frames from a rejected history (the sun turns
+    one degree per frame). Error of a form at frame f: sqrt(sum (E - E_ref)^2 /
+    sum E_ref^2) over every interior irradiance texel and channel, against the
+    1024-ray plain run at the same frame; the reported error is its mean over frames
+    20, 25, ... (after the history has built up). ms/frame is the mean frame time
+    from the context's own events (map snapshots excluded).
+    """
+    import numpy as np
+    from paper_2007_14394_amd import denoiser_weights
+    if not denoiser_weights.available():
+        return None
+    wts = denoiser_weights.load()
+    frames = [w.frames[k % len(w.frames)] for k in range(n_frames)]
+    evals = list(range(min(20, n_frames - 1), n_frames, 5))
+    ri = w.params.irr_res
+    den = S.sdfddgi_denoiser_create(wts["params"], wts["irr_scale"], wts["depth_scale"])
+
+    def run(rays, flags=0, learned=False):
+        over = dict(rays_per_probe=rays)
+        if learned:
+            over.update(learned_rays=wts["learned_rays"], fallback_error=wts["tau"])
+        ctx = S.context_from_workload(w, flags=flags | S.SDFDDGI_FLAG_TIMING, **over)
+        snaps, fb, kts = [], [], []
+        for k, fr in enumerate(frames):
+            if learned:
+                S.sdfddgi_update_frame_learned(ctx, den, fr.dir_to_light, fr.radiance_rgb,
+                                               fr.rotation_seed)
+            else:
+                S.sdfddgi_update_frame(ctx, fr.dir_to_light, fr.radiance_rgb, fr.rotation_seed)
+            if k == evals[0] - 1:
+                S.sdfddgi_get_kernel_times(ctx)        # drop the frames before the first snapshot
+            if k in evals:
+                kts.append(S.sdfddgi_get_kernel_times(ctx))
+                irr, _ = S.sdfddgi_get_maps(ctx)
+                snaps.append(irr[:, 1:ri + 1, 1:ri + 1, :].clone())
+                if learned:
+                    fb.append(S.sdfddgi_get_fallback(ctx, want_lists=False)[0] / w.num_probes)
+        S.sdfddgi_destroy(ctx)
+        kt = {key: float(np.mean([t[key] for t in kts])) for key in kts[0]}
+        return snaps, kt, (float(np.mean(fb)) if fb else None)
+
+    ref, ref_kt, _ = run(1024)
+
+    def err(snaps):
+        e = [float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+             for a, b in zip(snaps, ref)]
+        return float(np.mean(e))
+
+    def entry(rays, kt, snaps, **extra):
+        return dict(rays=rays, ms_per_frame=kt["frame"], irr_rel_rms_error=err(snaps),
+                    kernel_ms=kt, **extra)
+
+    forms = {"plain_f32_1024": entry(1024, ref_kt, ref)}
+    for rays in (64, 128, 256):
+        sn, kt, _ = run(rays)
+        forms[f"plain_f32_{rays}"] = entry(rays, kt, sn)
+    sn, kt, _ = run(256, S.SDFDDGI_FLAG_FP16)
+    forms["plain_f16_256"] = entry(256, kt, sn)
+    for name, flags in (("learned_f32", 0), ("learned_f16", S.SDFDDGI_FLAG_FP16)):
+        sn, kt, fb = run(256, flags, learned=True)
+        forms[name] = entry(wts["learned_rays"], kt, sn, fallback_rays=256, fallback_fraction=fb)
+
+    # plain FP32 at equal error: log-log interpolation of error and time in the ray count
+    lr = np.log([64.0, 128.0, 256.0])
+    le = np.log([forms[f"plain_f32_{r}"]["irr_rel_rms_error"] for r in (64, 128, 256)])
+    lm = np.log([forms[f"plain_f32_{r}"]["ms_per_frame"] for r in (64, 128, 256)])
+    out = {}
+    for name in ("learned_f32", "learned_f16"):
+        e = forms[name]["irr_rel_rms_error"]
+        if e <= float(np.exp(le[-1])):
+            # at least as accurate as the plain 256-ray form: compare with that form
+            rays_eq, ms_eq, bound = 256.0, forms["plain_f32_256"]["ms_per_frame"], "lower_error"
+        else:
+            x = float(np.interp(-np.log(e), -le, lr))   # error falls as rays grow
+            rays_eq, ms_eq, bound = float(np.exp(x)), float(np.exp(np.interp(x, lr, lm))), "equal"
+        out[name] = dict(plain_rays_at_equal_error=rays_eq, plain_ms_at_equal_error=ms_eq,
+                         speedup=ms_eq / forms[name]["ms_per_frame"], comparison=bound)
+    return dict(reference="plain FP32 update with 1024 rays per probe, same frames",
+                frames=n_frames, eval_frames=evals, weights=wts["meta"].get("command"),
+                tau=wts["tau"], forms=forms, at_equal_error=out)
 
 
 def main():
@@ -252,6 +343,9 @@ def main():
         out["kernels"] = kernels
         out["ray_stats"] = {"primary_steps": st["prim"], "shadow_steps": st["shadow"],
                             "hit_fraction": st["hits"]}
+    if not args.no_learned:
+        lw = scenegen.config2(args.seed, probes=args.probes, frames=args.learned_frames)
+        out["learned_form"] = learned_comparison(S, lw, args.learned_frames, torch)
     if args.cpu_probes > 0:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_probes)
     print(json.dumps(out), flush=True)

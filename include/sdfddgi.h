@@ -249,8 +249,8 @@ sdfddgi_status sdfddgi_destroy(sdfddgi_ctx *ctx);
 /* ------------------------------------------------------------ learned form --
  * An extension beyond the paper: each frame traces learned_rays rays per probe,
  * forms the Eq. 3 estimate U_low from them (no hysteresis), and a per-texel
- * network maps it, with the probe's history, to the estimate a many-ray set
- * would give. Per interior irradiance texel t the network reads
+ * network maps it, with the probe's history, to the estimate of the frame's
+ * update with many rays. Per interior irradiance texel t the network reads
  *   x = (U_low/S [3], E_prev/S [3], mean E[d]/D, sqrt(mean E[d^2])/D over the
  *        k x k depth texels covering t (k = depth_res/irr_res), texel direction
  *        [3], clamp(probe signed distance / D, -4, 4), 1, 0, 0, 0)
@@ -260,10 +260,10 @@ sdfddgi_status sdfddgi_destroy(sdfddgi_ctx *ctx);
  * texel's update is U_hat = max(0, E_prev + S o[0..2]) and its predicted
  * relative error exp(o[3]). A probe whose history is rejected, or whose mean
  * predicted error over its texels exceeds fallback_error, takes the plain
- * update with rays_per_probe rays; every other probe mixes U_hat into its
- * irradiance (hysteresis, then borders) and the low-ray depth moments into its
- * depth map. Requires learned_rays > 0 and depth_res a multiple of irr_res,
- * irr_res <= 16.
+ * update with rays_per_probe rays instead; every other probe mixes U_hat into
+ * its irradiance (hysteresis, then borders) and the low-ray depth moments into
+ * its depth map. Requires learned_rays > 0, depth_res an even multiple of
+ * irr_res and irr_res <= 16.
  *
  * Parameter vector (binary32, SDFDDGI_DENOISER_PARAMS values, row-major):
  *   W1 [64][16] | W2 [64][64] | b2 [64] | W3 [64][64] | b3 [64] | W4 [4][64] | b4 [4] */
@@ -302,16 +302,17 @@ sdfddgi_status sdfddgi_get_fallback(sdfddgi_ctx *ctx, int32_t *count, int32_t *p
                                     float *mean_error);
 
 /* Training pairs for the network from the current maps, without changing them:
- * traces learned_rays and target_rays (16..SDFDDGI_MAX_RAYS, multiple of 16) per
- * probe for the frame, forms both Eq. 3 estimates without hysteresis, and writes
- * for every probe p and interior irradiance texel t (row p*Ti + t):
+ * traces learned_rays per probe for the frame, forms U_low, and writes for every
+ * probe p and interior irradiance texel t (row p*Ti + t):
  *   features[.][16] = x above (the denoiser's S and D),
- *   targets[.][4]   = ((U* - E_prev)/S [3], |U*|_1 / S + rel_floor)
- * with U* the target-ray estimate. Device pointers; the context's stream. */
+ *   targets[.][4]   = ((T - E_prev)/S [3], |T|_1 / S + rel_floor)
+ * with T the texel of target_irr, an irradiance atlas of the context's layout
+ * (e.g. the many-ray plain update of the same frame from the same maps, without
+ * hysteresis). Device pointers; the context's stream. */
 sdfddgi_status sdfddgi_learned_examples(sdfddgi_ctx *ctx, const sdfddgi_denoiser *den,
                                         const sdfddgi_light *light, uint64_t rotation_seed,
-                                        int32_t target_rays, float rel_floor, float *features,
-                                        float *targets);
+                                        const float *target_irr, float rel_floor,
+                                        float *features, float *targets);
 
 /* ---------------------------------------------------------------- training --
  * Loss per sample (o = network output, (z, q) = targets row):
@@ -354,7 +355,22 @@ sdfddgi_status sdfddgi_trainer_get_params(sdfddgi_trainer *tr, float *params);
 
 sdfddgi_status sdfddgi_trainer_destroy(sdfddgi_trainer *tr);
 
-/* Message of the last failure of a denoiser or trainer call on this thread. */
+/* ------------------------------------------------------------ scene baking --
+ * Input preparation on the device (training scenes in bulk): the exact signed
+ * distance of a union of primitives at every vertex (i,j,k) of a grid, vertex at
+ * origin + spacing*(i,j,k), evaluated in binary64 and rounded once; albedo_out
+ * receives the albedo of the nearest primitive (ties: lower index), 0 and
+ * empty_value where there are no primitives. Primitive arrays are host arrays:
+ * kind[nprims] (0 sphere with radius half[.][0], 1 axis-aligned box with half
+ * extents half[.][0..2]), center/half/albedo [nprims][3]. sdf (device
+ * [n2][n1][n0]) and albedo_out (device [n2][n1][n0][3], may be NULL). Waits for
+ * the stream before returning. */
+sdfddgi_status sdfddgi_bake_sdf(int32_t nprims, const int32_t *kind, const double *center,
+                                const double *half, const double *albedo, const int32_t n[3],
+                                const double origin[3], double spacing, float empty_value,
+                                float *sdf, float *albedo_out, void *hip_stream);
+
+/* Message of the last failure of a denoiser, trainer or baking call on this thread. */
 const char *sdfddgi_learned_last_error(void);
 
 #ifdef __cplusplus

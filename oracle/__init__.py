@@ -272,7 +272,9 @@ class Checker:
         """One frame of the learned form for every probe.
 
         Low-ray Eq. 3 update (no hysteresis), features, network (mirror mode unless
-        ``mirror`` is false),
+        ``mirror`` is false); an accepted probe mixes the network's
+        U_hat = max(0, E_prev + S o) into its irradiance and the low-ray depth
+        moments into its depth map with the hysteresis;
         per-probe decision: a probe takes the plain update when the history is
         reset or the mean of exp(o_3) over its texels exceeds tau. ``fallback``
         (a boolean per probe) overrides the decision, for checking another

@@ -8,7 +8,7 @@
  * The learned form is an extension beyond the paper. Each frame it traces a
  * small ray set per probe, forms the Eq. 3 estimate from it, and lets a small
  * per-texel network map that noisy estimate (with the probe's history) to the
- * estimate a many-ray set would give. A second output of the network predicts
+ * update a many-ray set would give for the frame. A second output of the network predicts
  * its own relative error; probes whose mean predicted error exceeds a threshold
  * (and probes without history) take the plain update instead.
  *
@@ -26,7 +26,8 @@
  * gradient and each hidden gradient after its ReLU mask. Biases stay binary32
  * values; everything else here is binary64. Exact mode rounds nothing.
  *
- * Output mapping: irradiance U = max(0, E_prev + S * o[0..2]) per channel,
+ * Output mapping: the update U = max(0, E_prev + S * o[0..2]) per channel,
+ * mixed into the irradiance with the hysteresis like the plain update;
  * predicted relative error r = exp(o[3]).
  */
 #ifndef SDFDDGI_ORACLE_LEARNED_H

@@ -175,7 +175,7 @@ struct DenoiseArgs {
 struct ExampleArgs {
     FeatureArgs f;
     int P;
-    const float *target_irr;      // many-ray Eq. 3 irradiance atlas (no hysteresis)
+    const float *target_irr;      // target irradiance atlas (e.g. a many-ray run's maps)
     float rel_floor;              // added to |U*|_1 / S in the relative-error scale
     float *features;              // [P*Ti][16]
     float *targets;               // [P*Ti][4]: (U* - E_prev) / S, |U*|_1 / S + floor
@@ -215,5 +215,20 @@ hipError_t launch_infer(const InferArgs &a, hipStream_t stream);
 hipError_t launch_train(const TrainArgs &a, hipStream_t stream);
 hipError_t launch_adam(const AdamArgs &a, hipStream_t stream);
 hipError_t launch_zero_f32(float *dst, int64_t n, hipStream_t stream);
+
+// Scene baking (scene.hip). Primitive arrays are device copies; kind 0 sphere
+// (radius in half[0]), 1 axis-aligned box.
+struct BakeArgs {
+    int nprims;
+    const int *kind;
+    const double *center, *half, *albedo;   // [nprims][3]
+    int n0, n1, n2;
+    double org0, org1, org2, spacing;
+    float empty_value;
+    float *sdf;                             // [n2][n1][n0]
+    float *alb;                             // [n2][n1][n0][3] or null
+};
+
+hipError_t launch_bake(const BakeArgs &a, hipStream_t stream);
 
 }  // namespace sdfddgi

@@ -7,7 +7,7 @@
 //   pack_mlp_kernel   binary32 parameters -> per-lane bfloat16 MFMA operand packs
 //   denoise_kernel    per probe: features, network, decision, hysteresis and
 //                     border writes of accepted probes, fallback list of the rest
-//   examples_kernel   training pairs: features and many-ray targets per texel
+//   examples_kernel   training pairs: features and targets (a converged atlas) per texel
 //   infer_kernel      the network on a feature array
 //   train_kernel      loss gradient over a minibatch (forward, backward, weight
 //                     gradients; all contractions on bfloat16 MFMA)
@@ -202,13 +202,15 @@ __device__ __forceinline__ bf16x8_t to_bf16x8(const float v[8]) {
 // ------------------------------------------------------------------ denoise --
 
 constexpr int kWaves = 4;
+constexpr int kTileBatch = 4;    // texel tiles whose features are gathered together
+constexpr int kMaxDepthF4 = (2 * kMaxLearnedRes + 2) * (2 * kMaxLearnedRes + 2) * 2 / 4;
 
 // One wave per probe (waves stride over probes). Per 16-texel tile: features, the
 // network, U_hat = max(0, E_prev + S o[0..2]) staged in LDS, and exp(o[3]) summed.
 // The probe falls back (appended to the list, nothing written) when its history is
-// rejected or its mean predicted error exceeds tau; otherwise its irradiance
-// interior and borders take the hysteresis mix with U_hat and its depth moments the
-// mix with the low-ray update.
+// rejected or its mean predicted error exceeds tau; otherwise U_hat takes the place
+// of the plain update in the hysteresis mix of its irradiance (interior and borders),
+// and its depth moments take the hysteresis mix with the low-ray update.
 __global__ __launch_bounds__(256) void denoise_kernel(DenoiseArgs a) {
     __shared__ float s_bias[kBiasFloats];
     __shared__ float s_u[kWaves][kMaxLearnedRes * kMaxLearnedRes * 3];
@@ -223,19 +225,31 @@ __global__ __launch_bounds__(256) void denoise_kernel(DenoiseArgs a) {
     float *su = s_u[wave];
     for (int p = blockIdx.x * kWaves + wave; p < a.P; p += gridDim.x * kWaves) {
         float esum = 0.0f;
-        for (int tile = 0; tile < tiles; ++tile) {
-            const int t = tile * 16 + n;
-            float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            if (g < 2 && t < Ti) feature_group(a.f, p, t, g, v);
-            floatx4 d1[4], d2[4], d3[4];
-            bf16x8_t h1[2], h2[2], h3[2];
-            const floatx4 o = mlp_forward(wf, s_bias, g, to_bf16x8(v), d1, d2, d3, h1, h2, h3);
-            if (g == 0 && t < Ti) {
-                const float *prev = a.f.prev_irr + (size_t)p * tile_i +
-                                    ((size_t)(t / ri + 1) * si + (t % ri + 1)) * 3;
+        for (int tb = 0; tb < tiles; tb += kTileBatch) {
+            // gather the features of kTileBatch tiles first, so their loads overlap
+            bf16x8_t xb[kTileBatch];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) su[3 * t + c] = fmaxf(0.0f, fmaf(a.s, o[c], prev[c]));
-                esum += expf(o[3]);
+            for (int q = 0; q < kTileBatch; ++q) {
+                const int t = (tb + q) * 16 + n;
+                float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                if (g < 2 && t < Ti) feature_group(a.f, p, t, g, v);
+                xb[q] = to_bf16x8(v);
+            }
+#pragma unroll
+            for (int q = 0; q < kTileBatch; ++q) {
+                if (tb + q >= tiles) break;
+                const int t = (tb + q) * 16 + n;
+                floatx4 d1[4], d2[4], d3[4];
+                bf16x8_t h1[2], h2[2], h3[2];
+                const floatx4 o = mlp_forward(wf, s_bias, g, xb[q], d1, d2, d3, h1, h2, h3);
+                if (g == 0 && t < Ti) {
+                    const float *prev = a.f.prev_irr + (size_t)p * tile_i +
+                                        ((size_t)(t / ri + 1) * si + (t % ri + 1)) * 3;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        su[3 * t + c] = fmaxf(0.0f, fmaf(a.s, o[c], prev[c]));
+                    esum += expf(o[3]);
+                }
             }
         }
         const float mean = wave_sum(esum) / (float)Ti;
@@ -246,21 +260,31 @@ __global__ __launch_bounds__(256) void denoise_kernel(DenoiseArgs a) {
         }
         __builtin_amdgcn_wave_barrier();
         const float h = a.hysteresis;
-        const float *old_i = a.f.prev_irr + (size_t)p * tile_i;
         float *new_i = a.new_irr + (size_t)p * tile_i;
-        for (int e = lane; e < Ti * 3; e += 64) {
+        // unrolled so that every lane's loads are in flight together
+        const float *old_i = a.f.prev_irr + (size_t)p * tile_i;
+#pragma unroll
+        for (int k = 0; k < kMaxLearnedRes * kMaxLearnedRes * 3 / 64; ++k) {
+            const int e = lane + 64 * k;
+            if (e >= Ti * 3) break;
             const int t = e / 3, c = e - 3 * (e / 3);
             const int i = t % ri, j = t / ri;
             const float u = su[e];
             const float old = old_i[((j + 1) * si + (i + 1)) * 3 + c];
             store_with_border(new_i, ri, 3, i, j, c, fmaf(h, old - u, u));
         }
-        const float *old_d = a.f.prev_depth + (size_t)p * tile_d;
-        const float *ud = a.u_depth + (size_t)p * tile_d;
-        float *new_d = a.new_depth + (size_t)p * tile_d;
-        for (int e = lane; e < (int)tile_d; e += 64) {
-            const float u = ud[e];
-            new_d[e] = fmaf(h, old_d[e] - u, u);
+        // depth tiles are whole float4s: (res+2)^2 * 2 floats with res even
+        const float4 *old_d = reinterpret_cast<const float4 *>(a.f.prev_depth + (size_t)p * tile_d);
+        const float4 *ud = reinterpret_cast<const float4 *>(a.u_depth + (size_t)p * tile_d);
+        float4 *new_d = reinterpret_cast<float4 *>(a.new_depth + (size_t)p * tile_d);
+        const int nd4 = (int)(tile_d / 4);
+#pragma unroll
+        for (int k = 0; k < kMaxDepthF4 / 64 + 1; ++k) {
+            const int e = lane + 64 * k;
+            if (e >= nd4) break;
+            const float4 u = ud[e], o = old_d[e];
+            new_d[e] = make_float4(fmaf(h, o.x - u.x, u.x), fmaf(h, o.y - u.y, u.y),
+                                   fmaf(h, o.z - u.z, u.z), fmaf(h, o.w - u.w, u.w));
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -561,6 +585,8 @@ hipError_t launch_pack_mlp(const float *theta, uint4 *fwd, uint4 *bwd, float *bi
 }
 
 hipError_t launch_denoise(const DenoiseArgs &a, hipStream_t s) {
+    // more waves than fit at once: the kernel is bound by load latency, and the
+    // workgroups that start later hide the tails of the first ones
     const int blocks = (int)std::min<int64_t>(grid_for(a.P, kWaves), 8 * device_cus());
     hipLaunchKernelGGL(denoise_kernel, dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();

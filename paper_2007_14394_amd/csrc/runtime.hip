@@ -105,8 +105,7 @@ bool finite_all(const float *v, int n) {
 }  // namespace
 
 // One set of ray directions with its tables and per-ray buffers: the frame's
-// rays (rays_per_probe), the learned form's low ray count, and the target set of
-// the training pairs.
+// rays (rays_per_probe) and the learned form's low ray count.
 struct RaySet {
     int R = 0, Rpad = 0;
     double *base = nullptr;          // [R][3] unrotated spherical-Fibonacci set
@@ -119,8 +118,8 @@ struct RaySet {
 };
 
 // Counters of one frame: [0..2] the trace pass over all probes (rays claimed,
-// queue entries claimed, queue length), [3..5] the second trace pass (the learned
-// form's fallback probes, or the target rays of training pairs), [6] fallback count.
+// queue entries claimed, queue length), [3..5] the learned form's second pass (its
+// fallback probes), [6] fallback count.
 constexpr int kCounters = 8;
 
 struct sdfddgi_ctx {
@@ -141,7 +140,7 @@ struct sdfddgi_ctx {
     float *probe_pos = nullptr;
     int *probe_order = nullptr;
     double *texel_i = nullptr, *texel_d = nullptr;
-    RaySet main, low, target;
+    RaySet main, low;
     float *irr[2]{}, *depth[2]{};
     int cur = 0;
     uint8_t *reject = nullptr;
@@ -150,7 +149,6 @@ struct sdfddgi_ctx {
     bool have_frame = false, have_records = false, have_learned = false;
     // learned form
     float *u_irr = nullptr, *u_depth = nullptr;      // low-ray estimates (no hysteresis)
-    float *t_irr = nullptr, *t_depth = nullptr;      // target-ray estimates
     float *probe_sdf = nullptr;                      // [P]
     float *texel_dir = nullptr;                      // [Ti][3] binary32
     int *fallback = nullptr;                         // [P]
@@ -245,11 +243,10 @@ void free_all(sdfddgi_ctx *c) {
     }
     free_set(c->main);
     free_set(c->low);
-    free_set(c->target);
     dev_free(c->probe_pos); dev_free(c->probe_order); dev_free(c->texel_i); dev_free(c->texel_d);
     dev_free(c->irr[0]); dev_free(c->irr[1]); dev_free(c->depth[0]); dev_free(c->depth[1]);
     dev_free(c->reject); dev_free(c->counter); dev_free(c->records);
-    dev_free(c->u_irr); dev_free(c->u_depth); dev_free(c->t_irr); dev_free(c->t_depth);
+    dev_free(c->u_irr); dev_free(c->u_depth);
     dev_free(c->probe_sdf); dev_free(c->texel_dir); dev_free(c->fallback); dev_free(c->mean_error);
     if (c->ev_ring) {
         for (int k = 0; k < kEvents * kTimingRing; ++k)
@@ -322,10 +319,10 @@ sdfddgi_status validate(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_grid *p
             return fail(nullptr, SDFDDGI_EINVAL,
                         "learned_rays %d: need 0 or a multiple of 16 in 16..rays_per_probe",
                         p->learned_rays);
-        if (p->irr_res > kMaxLearnedRes || p->depth_res % p->irr_res != 0)
+        if (p->irr_res > kMaxLearnedRes || p->depth_res % p->irr_res != 0 || p->depth_res % 2)
             return fail(nullptr, SDFDDGI_EINVAL,
-                        "learned form needs irr_res <= %d and depth_res a multiple of irr_res",
-                        kMaxLearnedRes);
+                        "learned form needs irr_res <= %d and depth_res an even multiple of "
+                        "irr_res", kMaxLearnedRes);
     }
     return SDFDDGI_OK;
 }
@@ -1160,33 +1157,18 @@ sdfddgi_status sdfddgi_get_fallback(sdfddgi_ctx *c, int32_t *count, int32_t *pro
 
 sdfddgi_status sdfddgi_learned_examples(sdfddgi_ctx *c, const sdfddgi_denoiser *d,
                                         const sdfddgi_light *light, uint64_t rotation_seed,
-                                        int32_t target_rays, float rel_floor, float *features,
-                                        float *targets) {
+                                        const float *target_irr, float rel_floor,
+                                        float *features, float *targets) {
     sdfddgi_status st = check_ctx(c);
     if (st != SDFDDGI_OK) return st;
     if ((st = check_learned(c, d)) != SDFDDGI_OK) return st;
-    if (!valid_rays(target_rays))
-        return fail(c, SDFDDGI_EINVAL, "target_rays %d: need a multiple of 16 in 16..%d",
-                    target_rays, kMaxRays);
-    if (c->P * target_rays >= (int64_t)1 << 31)
-        return fail(c, SDFDDGI_EINVAL, "probes x target rays too large");
-    if (!features || !targets) return fail(c, SDFDDGI_EINVAL, "null array");
+    if (!target_irr || !features || !targets) return fail(c, SDFDDGI_EINVAL, "null array");
     if (!(rel_floor >= 0) || !std::isfinite(rel_floor))
         return fail(c, SDFDDGI_EINVAL, "rel_floor must be finite and >= 0");
     float l[3], rad[3];
     if ((st = light_of(c, light, l, rad)) != SDFDDGI_OK) return st;
-    if (c->target.R != target_rays) {
-        TRY_HIP(c, hipStreamSynchronize(c->stream), "waiting for the stream");
-        TRY_HIP(c, alloc_set(c, c->target, target_rays), "allocating the target ray set");
-        if (!c->t_irr) {
-            TRY_HIP(c, dev_alloc(&c->t_irr, c->irr_floats), "allocating target maps");
-            TRY_HIP(c, dev_alloc(&c->t_depth, c->depth_floats), "allocating target maps");
-        }
-    }
     const TraceArgs base = trace_base(c, l, rad);
     TRY_HIP(c, launch_tables(table_args(c, c->low, rotation_seed, 7), c->stream),
-            "launching tables_kernel");
-    TRY_HIP(c, launch_tables(table_args(c, c->target, rotation_seed, 0), c->stream),
             "launching tables_kernel");
     const TraceArgs tl = trace_pass(base, c->low, c->counter, nullptr, nullptr, nullptr);
     TRY_HIP(c, launch_primary(tl, c->low.grid, c->stream), "launching primary_kernel");
@@ -1196,18 +1178,10 @@ sdfddgi_status sdfddgi_learned_examples(sdfddgi_ctx *c, const sdfddgi_denoiser *
                                        nullptr),
                             c->stream),
             "launching blend_kernel");
-    const TraceArgs tt = trace_pass(base, c->target, c->counter + 3, nullptr, nullptr, nullptr);
-    TRY_HIP(c, launch_primary(tt, c->target.grid, c->stream), "launching primary_kernel");
-    TRY_HIP(c, launch_hits(tt, c->target.grid, c->stream), "launching hits_kernel");
-    TRY_HIP(c, launch_blend(blend_args(c, c->target, c->target.payload, 0.0f, c->irr[c->cur],
-                                       c->depth[c->cur], c->t_irr, c->t_depth, nullptr, nullptr,
-                                       nullptr),
-                            c->stream),
-            "launching blend_kernel");
     ExampleArgs ea{};
     ea.f = feature_args(c, d);
     ea.P = (int)c->P;
-    ea.target_irr = c->t_irr;
+    ea.target_irr = target_irr;
     ea.rel_floor = rel_floor;
     ea.features = features;
     ea.targets = targets;
@@ -1357,6 +1331,58 @@ sdfddgi_status sdfddgi_trainer_get_params(sdfddgi_trainer *t, float *params) {
                            t->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(t->stream);
     if (e != hipSuccess) return lhip_fail(e, "copying parameters");
+    return SDFDDGI_OK;
+}
+
+sdfddgi_status sdfddgi_bake_sdf(int32_t nprims, const int32_t *kind, const double *center,
+                                const double *half, const double *albedo, const int32_t n[3],
+                                const double origin[3], double spacing, float empty_value,
+                                float *sdf, float *albedo_out, void *hip_stream) {
+    g_learned_error.clear();
+    if (nprims < 0 || !n || !origin || !sdf) return lfail(SDFDDGI_EINVAL, "null or negative argument");
+    if (nprims > 0 && (!kind || !center || !half || !albedo))
+        return lfail(SDFDDGI_EINVAL, "primitive arrays are NULL");
+    if (n[0] < 2 || n[1] < 2 || n[2] < 2 || (int64_t)n[0] * n[1] * n[2] >= (int64_t)1 << 31)
+        return lfail(SDFDDGI_EINVAL, "grid size out of range");
+    if (!(spacing > 0) || !std::isfinite(spacing) || !std::isfinite(origin[0]) ||
+        !std::isfinite(origin[1]) || !std::isfinite(origin[2]))
+        return lfail(SDFDDGI_EINVAL, "spacing and origin must be finite, spacing > 0");
+    for (int32_t m = 0; m < nprims; ++m)
+        if (kind[m] != 0 && kind[m] != 1) return lfail(SDFDDGI_EINVAL, "primitive kind %d", kind[m]);
+    (void)hipGetLastError();
+    hipStream_t st = (hipStream_t)hip_stream;
+    int *d_kind = nullptr;
+    double *d_prm = nullptr;   // center | half | albedo
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+    const size_t np = (size_t)(nprims > 0 ? nprims : 1);
+    chk(dev_alloc(&d_kind, np));
+    chk(dev_alloc(&d_prm, 9 * np));
+    if (e == hipSuccess && nprims > 0) {
+        chk(hipMemcpy(d_kind, kind, nprims * sizeof(int), hipMemcpyHostToDevice));
+        chk(hipMemcpy(d_prm, center, 3 * nprims * sizeof(double), hipMemcpyHostToDevice));
+        chk(hipMemcpy(d_prm + 3 * np, half, 3 * nprims * sizeof(double), hipMemcpyHostToDevice));
+        chk(hipMemcpy(d_prm + 6 * np, albedo, 3 * nprims * sizeof(double), hipMemcpyHostToDevice));
+    }
+    if (e == hipSuccess) {
+        BakeArgs a{};
+        a.nprims = nprims;
+        a.kind = d_kind;
+        a.center = d_prm;
+        a.half = d_prm + 3 * np;
+        a.albedo = d_prm + 6 * np;
+        a.n0 = n[0]; a.n1 = n[1]; a.n2 = n[2];
+        a.org0 = origin[0]; a.org1 = origin[1]; a.org2 = origin[2];
+        a.spacing = spacing;
+        a.empty_value = empty_value;
+        a.sdf = sdf;
+        a.alb = albedo_out;
+        chk(launch_bake(a, st));
+        chk(hipStreamSynchronize(st));
+    }
+    dev_free(d_kind);
+    dev_free(d_prm);
+    if (e != hipSuccess) return lhip_fail(e, "baking");
     return SDFDDGI_OK;
 }
 

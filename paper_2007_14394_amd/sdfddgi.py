@@ -37,6 +37,7 @@ EXPORTED = [
     "sdfddgi_update_frame_learned", "sdfddgi_get_fallback", "sdfddgi_learned_examples",
     "sdfddgi_trainer_create", "sdfddgi_trainer_gradient", "sdfddgi_trainer_step",
     "sdfddgi_trainer_get_params", "sdfddgi_trainer_destroy", "sdfddgi_learned_last_error",
+    "sdfddgi_bake_sdf",
 ]
 SDFDDGI_DENOISER_PARAMS = 9604
 SDFDDGI_FEATURES = 16
@@ -130,7 +131,7 @@ def load_library() -> ctypes.CDLL:
     L.sdfddgi_denoiser_destroy.argtypes = [vp]
     L.sdfddgi_update_frame_learned.argtypes = [vp, vp, ctypes.POINTER(sdfddgi_light), u64]
     L.sdfddgi_get_fallback.argtypes = [vp, ctypes.POINTER(i32), vp, vp]
-    L.sdfddgi_learned_examples.argtypes = [vp, vp, ctypes.POINTER(sdfddgi_light), u64, i32, f32,
+    L.sdfddgi_learned_examples.argtypes = [vp, vp, ctypes.POINTER(sdfddgi_light), u64, vp, f32,
                                            vp, vp]
     L.sdfddgi_trainer_create.argtypes = [vp, i32, ctypes.POINTER(sdfddgi_train_config), vp,
                                          ctypes.POINTER(vp)]
@@ -138,6 +139,9 @@ def load_library() -> ctypes.CDLL:
     L.sdfddgi_trainer_step.argtypes = [vp, vp, vp, i64, i32, u64, f32, vp]
     L.sdfddgi_trainer_get_params.argtypes = [vp, vp]
     L.sdfddgi_trainer_destroy.argtypes = [vp]
+    L.sdfddgi_bake_sdf.argtypes = [i32, vp, vp, vp, vp, ctypes.POINTER(i32),
+                                   ctypes.POINTER(ctypes.c_double), ctypes.c_double, f32, vp,
+                                   vp, vp]
     L.sdfddgi_learned_last_error.argtypes = []
     L.sdfddgi_learned_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -475,10 +479,13 @@ def sdfddgi_get_fallback(ctx: Context, want_lists: bool = True):
 
 
 def sdfddgi_learned_examples(ctx: Context, den: Denoiser, dir_to_light, radiance_rgb,
-                             rotation_seed: int, target_rays: int, rel_floor: float,
+                             rotation_seed: int, target_irr, rel_floor: float,
                              features=None, targets=None):
+    """Training pairs against a target irradiance atlas (device, the context's layout)."""
     import torch
     n = ctx.probes * ctx.irr_res * ctx.irr_res
+    if tuple(target_irr.shape) != ctx.irr_shape:
+        raise ValueError("target_irr must have the context's irradiance atlas shape")
     if features is None:
         features = torch.empty((n, SDFDDGI_FEATURES), dtype=torch.float32, device=ctx.device)
     if targets is None:
@@ -490,7 +497,7 @@ def sdfddgi_learned_examples(ctx: Context, den: Denoiser, dir_to_light, radiance
     li.radiance_rgb[:] = [float(v) for v in radiance_rgb]
     _check(ctx, load_library().sdfddgi_learned_examples(
         ctx.handle, den.handle, ctypes.byref(li), ctypes.c_uint64(int(rotation_seed)),
-        ctypes.c_int32(int(target_rays)), ctypes.c_float(rel_floor),
+        _dev_ptr(target_irr, torch.float32, "target_irr", ctx.device), ctypes.c_float(rel_floor),
         _dev_ptr(features, torch.float32, "features", ctx.device),
         _dev_ptr(targets, torch.float32, "targets", ctx.device)))
     return features, targets
@@ -551,6 +558,32 @@ def sdfddgi_trainer_destroy(tr: Trainer) -> None:
     if tr.handle and tr.handle.value:
         _lcheck(load_library().sdfddgi_trainer_destroy(tr.handle))
         tr.handle = ctypes.c_void_p(0)
+
+
+def sdfddgi_bake_sdf(kind, center, half, albedo, n, origin, spacing: float,
+                     empty_value: float = 1e30, with_albedo: bool = True, device="cuda:0",
+                     stream=None):
+    """Bake one grid level on the device; returns (sdf [n2,n1,n0], albedo [.,3] or None)."""
+    import torch
+    kind = np.ascontiguousarray(kind, dtype=np.int32).reshape(-1)
+    m = kind.shape[0]
+    cen = np.ascontiguousarray(center, dtype=np.float64).reshape(m, 3)
+    hal = np.ascontiguousarray(half, dtype=np.float64).reshape(m, 3)
+    alb = np.ascontiguousarray(albedo, dtype=np.float64).reshape(m, 3)
+    n = [int(v) for v in n]
+    dev = torch.device(device)
+    sdf = torch.empty((n[2], n[1], n[0]), dtype=torch.float32, device=dev)
+    out_alb = (torch.empty((n[2], n[1], n[0], 3), dtype=torch.float32, device=dev)
+               if with_albedo else None)
+    P = ctypes.c_void_p
+    with torch.cuda.device(dev):
+        _lcheck(load_library().sdfddgi_bake_sdf(
+            ctypes.c_int32(m), P(kind.ctypes.data), P(cen.ctypes.data), P(hal.ctypes.data),
+            P(alb.ctypes.data), (ctypes.c_int32 * 3)(*n), (ctypes.c_double * 3)(*origin),
+            ctypes.c_double(spacing), ctypes.c_float(empty_value), P(sdf.data_ptr()),
+            P(out_alb.data_ptr()) if out_alb is not None else None,
+            P(_stream_handle(stream))))
+    return sdf, out_alb
 
 
 def sdfddgi_learned_last_error() -> str:

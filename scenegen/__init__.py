@@ -264,6 +264,43 @@ def config2(seed: int = 0, probes: int = 16384, frames: int = 60, rays: int = 25
     return Workload(f"config2_{probes}", prims, levels, pg, params, fr)
 
 
+@dataclass
+class SceneSpec:
+    """A scene described without its baked grids (baked elsewhere, e.g. on a GPU)."""
+    name: str
+    prims: Primitives
+    levels: List[Tuple[Tuple[int, int, int], Tuple[float, float, float], float]]  # n, origin, spacing
+    probes: ProbeGrid
+    params: Params
+    frames: List[Frame]
+
+
+def training_scene(seed: int, probes=(16, 16, 16), frames: int = 61, rays: int = 256,
+                   grid: int = 128, num_prims: int = 400) -> SceneSpec:
+    """An open scene of the 64x16x64 m kind (400 seeded spheres and boxes, 4-level
+    cascade of 128^3 grids) with a 16x16x16 probe block at the open scene's probe
+    spacing (2, 1, 2) m around the cascade centre, and a sun of random elevation in
+    [25, 65] degrees and random azimuth turning 1 degree per frame."""
+    rng = np.random.default_rng(7_000_000 + seed)
+    prims = open_scene_primitives(rng, num_prims, (-32.0, 0.0, -32.0), (32.0, 16.0, 32.0))
+    levels = []
+    for side in (8.0, 16.0, 32.0, 64.0):
+        origin = (-side / 2, 8.0 - side / 2, -side / 2)
+        levels.append(((grid,) * 3, origin, side / (grid - 1)))
+    n = tuple(int(v) for v in probes)
+    spacing = (2.0, 1.0, 2.0)
+    origin = tuple(-0.5 * spacing[a] * (n[a] - 1) for a in range(3))
+    origin = (origin[0], 0.5, origin[2])
+    pg = ProbeGrid(n, origin, spacing)
+    params = Params(rays_per_probe=rays, t_max=64.0 * math.sqrt(3.0), sky_rgb=(0.5, 0.5, 0.5))
+    elev = float(rng.uniform(25.0, 65.0))
+    az0 = float(rng.uniform(0.0, 360.0))
+    seeds = _rotation_seeds(rng, frames)
+    fr = [Frame(sun_direction(elev, az0 + float(f)), (3.0, 3.0, 3.0), seeds[f])
+          for f in range(frames)]
+    return SceneSpec(f"training_{seed}", prims, levels, pg, params, fr)
+
+
 def small_cascade(seed: int = 0, probes=(6, 3, 5), rays: int = 64, grid: int = 40,
                   num_prims: int = 24, frames: int = 4) -> Workload:
     """A reduced open scene: 2-level cascade, ragged probe count, for quick parity."""

@@ -108,6 +108,8 @@ def _create_status(g, pg, p):
     lambda g, pg, p: (setattr(p, "learned_rays", 32), setattr(p, "irr_res", 32),
                       setattr(p, "depth_res", 32)),
     lambda g, pg, p: (setattr(p, "learned_rays", 32), setattr(p, "fallback_error", -1.0)),
+    lambda g, pg, p: (setattr(p, "learned_rays", 32), setattr(p, "irr_res", 3),
+                      setattr(p, "depth_res", 9)),                  # odd depth map
     lambda g, pg, p: setattr(p, "fallback_error", float("nan")),
 ])
 def test_create_rejects_bad_arguments_before_touching_a_device(mutate):

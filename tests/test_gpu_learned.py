@@ -194,30 +194,28 @@ def test_examples_match_checker(S):
     ctx = make_ctx(S, w, 0.02)
     den = S.sdfddgi_denoiser_create(random_theta(0).astype(np.float32), S_IRR, D_DEPTH)
     irr, dep = warm(S, ctx, w)
+    target, _ = scenegen.random_atlas(w.num_probes, w.params, seed=9)
     fr = w.frames[2]
     feats, targ = S.sdfddgi_learned_examples(ctx, den, fr.dir_to_light, fr.radiance_rgb,
-                                             fr.rotation_seed, 128, 0.05)
+                                             fr.rotation_seed, to_dev(target), 0.05)
     feats, targ = to_host(feats), to_host(targ)
     # maps untouched
-    irr2, dep2 = S.sdfddgi_get_maps(ctx)
+    irr2, _ = S.sdfddgi_get_maps(ctx)
     assert np.array_equal(to_host(irr2), irr.astype(np.float32))
     ck = oracle.Checker(w)
     low = oracle.Checker(w, rays=32, hysteresis=0.0)
     ui, _, _, _ = low.update_probes(fr, True, irr, dep)
     ref_f = ck.learned_features(ui, irr, dep, S_IRR, D_DEPTH).reshape(-1, F)
-    tgt = oracle.Checker(w, rays=128, hysteresis=0.0)
-    ti, _, _, _ = tgt.update_probes(fr, True, irr, dep)
     ri = w.params.irr_res
-    t_in = ti[:, 1:ri + 1, 1:ri + 1, :].reshape(-1, 3)
+    t_in = target[:, 1:ri + 1, 1:ri + 1, :].reshape(-1, 3).astype(np.float64)
     p_in = irr[:, 1:ri + 1, 1:ri + 1, :].reshape(-1, 3)
     ref_z = (t_in - p_in) / S_IRR
     ref_q = np.abs(t_in).sum(axis=1) / S_IRR + 0.05
     scale = np.abs(ref_f).max(axis=0) + 1e-3
     assert np.all(np.abs(feats - ref_f) <= 2e-4 * scale + 1e-6), \
         float((np.abs(feats - ref_f) / scale).max())
-    zs = np.abs(t_in).max() / S_IRR
-    assert np.all(np.abs(targ[:, :3] - ref_z) <= 2e-4 * zs)
-    np.testing.assert_allclose(targ[:, 3], ref_q, rtol=2e-4)
+    np.testing.assert_allclose(targ[:, :3], ref_z, rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(targ[:, 3], ref_q, rtol=1e-5)
 
 
 def run_learned(S, w, theta, tau, frames, flags=0):
@@ -345,6 +343,26 @@ def test_learned_errors_are_rejected(S):
         S.sdfddgi_get_fallback(ctx)
     assert e.value.status == S.SDFDDGI_ESTATE
     ctx2 = make_ctx(S, w, 0.02)
+    irr, _ = S.sdfddgi_get_maps(ctx2)
     with pytest.raises(S.SdfddgiError) as e:
-        S.sdfddgi_learned_examples(ctx2, den, fr.dir_to_light, fr.radiance_rgb, 1, 100, 0.05)
+        S.sdfddgi_learned_examples(ctx2, den, fr.dir_to_light, fr.radiance_rgb, 1, irr, -1.0)
     assert e.value.status == S.SDFDDGI_EINVAL
+
+
+# ------------------------------------------------------------- scene baking --
+
+def test_device_bake_matches_host_baker(S):
+    announce("bake_sdf vs host baker")
+    rng = np.random.default_rng(12)
+    prims = scenegen.open_scene_primitives(rng, 300, (-8.0, 0.0, -8.0), (8.0, 4.0, 8.0))
+    n, origin, spacing = (37, 21, 30), (-9.0, -1.0, -7.5), 0.43
+    host = scenegen.bake(prims, n, origin, spacing)
+    sdf, alb = S.sdfddgi_bake_sdf(prims.kind, prims.center, prims.half, prims.albedo, n, origin,
+                                  spacing)
+    assert np.array_equal(to_host(sdf).view(np.int32), host.sdf.view(np.int32))
+    assert np.array_equal(to_host(alb).view(np.int32), host.albedo.view(np.int32))
+    empty = scenegen.Primitives(np.zeros(0, np.int32), np.zeros((0, 3)), np.zeros((0, 3)),
+                                np.zeros((0, 3)))
+    sdf, alb = S.sdfddgi_bake_sdf(empty.kind, empty.center, empty.half, empty.albedo,
+                                  (4, 5, 6), (0.0, 0.0, 0.0), 1.0, empty_value=1e30)
+    assert np.all(to_host(sdf) == np.float32(1e30)) and not to_host(alb).any()

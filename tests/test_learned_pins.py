@@ -348,8 +348,7 @@ def test_passthrough_network_gives_the_low_ray_plain_update():
     S = 2.0
     out = ck.learned_frame(w.frames[2], False, irr, dep, passthrough_theta(), S, 1.0, math.inf,
                            learned_rays=32, mirror=False)
-    low = oracle.Checker(w, rays=32)
-    li, ld, _, _ = low.update_probes(w.frames[2], False, irr, dep)
+    li, ld, _, _ = oracle.Checker(w, rays=32).update_probes(w.frames[2], False, irr, dep)
     assert not out["fallback"].any()
     np.testing.assert_allclose(out["irr"], li, rtol=1e-12, atol=1e-12)
     np.testing.assert_allclose(out["depth"], ld, rtol=1e-12, atol=1e-12)
