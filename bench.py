@@ -48,6 +48,9 @@ def parse():
                     help="skip the learned-vs-plain comparison at equal irradiance error")
     ap.add_argument("--learned-frames", type=int, default=60,
                     help="frames of each run in the learned-vs-plain comparison")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched form (64 uneven scenes per graph replay)")
+    ap.add_argument("--batch-frames", type=int, default=30)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times "
                          "(reference reading for the HBM byte counters) and exit")
@@ -221,6 +224,70 @@ def learned_comparison(S, w, n_frames: int, torch):
                 tau=wts["tau"], forms=forms, at_equal_error=out)
 
 
+def batch_form(S, scenegen, n_frames: int, torch):
+    """The batched form: 64 seeded scenes of uneven size (SDF 32^3-192^3 in binary16,
+    probe grids 4^3-24x12x24, 64-512 rays per probe) updated by one graph replay per
+    frame after autotuning; against the same scenes as 64 single-scene contexts
+    (precision form) updated one after another."""
+    import numpy as np
+    warm = 5
+    specs, seeds = scenegen.batch_scene_specs(0, 64, frames=warm + n_frames + 1)
+
+    def lights(f):
+        return [(sp.frames[f].dir_to_light, sp.frames[f].radiance_rgb) for sp in specs]
+
+    b = S.batch_from_specs(specs)
+    probes, rays = S.sdfddgi_batch_sizes(b)
+    tuning, tried = S.sdfddgi_batch_autotune(b, lights(0), seeds[0], 2)
+    for f in range(warm):
+        S.sdfddgi_batch_update_frame(b, lights(f), seeds[f])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for f in range(warm, warm + n_frames):
+        S.sdfddgi_batch_update_frame(b, lights(f), seeds[f])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / n_frames
+    lat = []
+    for f in range(warm, warm + n_frames):
+        S.sdfddgi_batch_update_frame(b, lights(f), seeds[f])
+        lat.append(S.sdfddgi_batch_scene_latency(b)[0])
+    lat = np.concatenate(lat)
+    S.sdfddgi_batch_destroy(b)
+    # the same scenes as separate contexts, one after another
+    ctxs = []
+    for sp in specs:
+        (n, origin, spacing), = sp.levels
+        sdf, alb = S.sdfddgi_bake_sdf(sp.prims.kind, sp.prims.center, sp.prims.half,
+                                      sp.prims.albedo, n, origin, spacing)
+        ctxs.append(S.sdfddgi_create([dict(sdf=sdf, albedo=alb, origin=origin, spacing=spacing)],
+                                     sp.probes.n, sp.probes.origin, sp.probes.spacing,
+                                     S.params_from(sp.params, S.SDFDDGI_FLAG_FP16)))
+
+    def seq_frame(f):
+        for sp, c in zip(specs, ctxs):
+            fr = sp.frames[f]
+            S.sdfddgi_update_frame(c, fr.dir_to_light, fr.radiance_rgb, seeds[f])
+
+    for f in range(warm):
+        seq_frame(f)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for f in range(warm, warm + n_frames):
+        seq_frame(f)
+    torch.cuda.synchronize()
+    ms_seq = (time.perf_counter() - t0) * 1e3 / n_frames
+    for c in ctxs:
+        S.sdfddgi_destroy(c)
+    return dict(scenes=len(specs), probes=probes, rays_per_frame=rays,
+                sdf_sizes=[sp.levels[0][0][0] for sp in specs],
+                rays_per_probe=[sp.params.rays_per_probe for sp in specs],
+                tuning=tuning, tuning_candidates=tried, frames=n_frames,
+                ms_per_frame=ms, probe_rays_per_s=rays / (ms * 1e-3),
+                scene_latency_ms_p50=float(np.percentile(lat, 50)),
+                scene_latency_ms_p99=float(np.percentile(lat, 99)),
+                sequential_contexts_ms_per_frame=ms_seq, speedup_vs_sequential=ms_seq / ms)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -346,6 +413,8 @@ def main():
     if not args.no_learned:
         lw = scenegen.config2(args.seed, probes=args.probes, frames=args.learned_frames)
         out["learned_form"] = learned_comparison(S, lw, args.learned_frames, torch)
+    if not args.no_batch:
+        out["batch_form"] = batch_form(S, scenegen, args.batch_frames, torch)
     if args.cpu_probes > 0:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_probes)
     print(json.dumps(out), flush=True)

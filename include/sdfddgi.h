@@ -370,7 +370,79 @@ sdfddgi_status sdfddgi_bake_sdf(int32_t nprims, const int32_t *kind, const doubl
                                 const double origin[3], double spacing, float empty_value,
                                 float *sdf, float *albedo_out, void *hip_stream);
 
-/* Message of the last failure of a denoiser, trainer or baking call on this thread. */
+/* ------------------------------------------------------------ batched form --
+ * Many independent scenes of uneven size updated together: each frame is one
+ * replay of a captured HIP graph whose launches cover every scene -- the ray
+ * tables of each distinct ray count, one persistent primary trace over the
+ * concatenated rays of all scenes, one hit-shading pass over all their hits and
+ * one blend over all their probes. Every scene runs the precision form (its grid
+ * stored in binary16, FP16/BF16 MFMA blend) of the update above, so each scene's
+ * maps are bit-identical to a single-scene context created with
+ * SDFDDGI_FLAG_FP16 and run over the same frames. Scenes share the frame's
+ * rotation seed; each has its own light. */
+#define SDFDDGI_MAX_BATCH_SCENES 64
+
+typedef struct sdfddgi_batch sdfddgi_batch;
+
+typedef struct {
+    sdfddgi_sdf_level level;      /* one grid level (device arrays, as in create)       */
+    sdfddgi_probe_grid probes;
+    sdfddgi_params params;        /* rays_per_probe a multiple of 64; irr_res 8 and
+                                     depth_res 16; flags and learned fields ignored    */
+} sdfddgi_batch_scene;
+
+/* Launch configuration of the batch's trace kernels, chosen by
+ * sdfddgi_batch_autotune (or the defaults at create). */
+typedef struct {
+    int32_t primary_chunk;        /* rays claimed per atomic: 64, 128, 256 or 512        */
+    int32_t primary_blocks;       /* persistent workgroups of the primary trace          */
+    int32_t hits_chunk;           /* hits claimed per atomic: 16, 32, 64 or 128          */
+    int32_t hits_blocks;          /* persistent workgroups of the hit shading            */
+    int32_t refill;               /* refill idle lanes when fewer than this many of a
+                                     wave's 64 lanes are stepping: 1..64                 */
+} sdfddgi_batch_tuning;
+
+/* Validate and upload count (1..SDFDDGI_MAX_BATCH_SCENES) scenes, allocate their
+ * maps (every history rejected), capture the frame graphs with the default
+ * tuning, and wait. hip_stream as in sdfddgi_create (NULL: the library creates a
+ * stream of its own; graphs cannot be captured on the null stream). */
+sdfddgi_status sdfddgi_batch_create(const sdfddgi_batch_scene *scenes, int32_t count,
+                                    void *hip_stream, sdfddgi_batch **out);
+
+/* One frame for every scene: lights (host [count]) and the shared rotation seed.
+ * Enqueues one graph replay on the batch's stream. */
+sdfddgi_status sdfddgi_batch_update_frame(sdfddgi_batch *b, const sdfddgi_light *lights,
+                                          uint64_t rotation_seed);
+
+/* Try launch configurations of the trace kernels on real frames of the batch
+ * (each candidate timed over frames_per_candidate frames with events), keep the
+ * fastest primary and hit configurations, re-capture the graphs, and restore the
+ * maps and history flags to what they were before (tuning changes no result:
+ * every configuration computes the same bits). *chosen (may be NULL) receives
+ * the result; *tried the number of candidates timed. */
+sdfddgi_status sdfddgi_batch_autotune(sdfddgi_batch *b, const sdfddgi_light *lights,
+                                      uint64_t rotation_seed, int32_t frames_per_candidate,
+                                      sdfddgi_batch_tuning *chosen, int32_t *tried);
+
+/* Use this configuration (validated) and re-capture the graphs. */
+sdfddgi_status sdfddgi_batch_set_tuning(sdfddgi_batch *b, const sdfddgi_batch_tuning *t);
+
+/* Copy scene s's current maps to device buffers (layouts as sdfddgi_get_maps). */
+sdfddgi_status sdfddgi_batch_get_maps(sdfddgi_batch *b, int32_t scene, float *irr,
+                                      float *depth);
+
+/* Per-scene latency of the last frame, from the device clock: ms[s] (host
+ * [count]) = time from the frame's first kernel to the end of scene s's last
+ * blend workgroup; *frame_ms (may be NULL) = the largest. Waits for the frame. */
+sdfddgi_status sdfddgi_batch_scene_latency(sdfddgi_batch *b, float *ms, float *frame_ms);
+
+/* Total probes and probe-rays of one frame of the batch (host pointers, may be NULL). */
+sdfddgi_status sdfddgi_batch_sizes(const sdfddgi_batch *b, int64_t *probes, int64_t *rays);
+
+sdfddgi_status sdfddgi_batch_destroy(sdfddgi_batch *b);
+
+/* Message of the last failure of a denoiser, trainer, baking or batch call on this
+ * thread. */
 const char *sdfddgi_learned_last_error(void);
 
 #ifdef __cplusplus

@@ -1,0 +1,183 @@
+// The Eq. 3 blend of one workgroup's probes, shared by the single-scene kernels
+// (kernels.hip) and the batched ones (batch.hip).
+#pragma once
+
+#include "internal.h"
+#include "octahedral.h"
+
+namespace sdfddgi {
+
+constexpr int kBlendProbes = 16;  // probes per workgroup: the N extent of a tile row
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// The probes of one blend workgroup (slots pb .. pb+np-1 of the probe list, or of
+// 0..P-1) and their hysteresis: none where the history is rejected. The first
+// __syncthreads of the caller's ray loop publishes them.
+__device__ __forceinline__ void load_blend_probes(const BlendArgs &a, int pb, int np, int *s_pid,
+                                                  float *s_h) {
+    const int tid = threadIdx.x;
+    if (tid < kBlendProbes) {
+        const int pid = tid < np ? (a.probe_list ? a.probe_list[pb + tid] : pb + tid) : 0;
+        s_pid[tid] = pid;
+        s_h[tid] = (tid < np && !(a.reject && a.reject[pid])) ? a.hysteresis : 0.0f;
+    }
+}
+
+constexpr int kBlendChunk = 64;   // rays staged in LDS at a time
+constexpr int kBlendPitch = kBlendChunk + 1;
+constexpr int kMSlots = 5;        // 16-texel M-tiles per wave per pass
+
+// Eq. 3 for 16 probes as a matrix product on MFMA (v_mfma_f32_16x16x4f32):
+//   irradiance  U_i[t][(q,c)] = sum_k w_tk   * L[q][k][c]      (M = texels, N = 16 x RGB)
+//   depth       U_d[t][(q,m)] = sum_k w_tk^s * t[q][k]^(m+1)   (M = texels, N = 16 x 2)
+// with K = rays. The weights (shared by every probe of the frame) are the A operand,
+// read from the transposed [R][T] tables; the probes' payload is the B operand,
+// staged in LDS 64 rays at a time. M-tiles are dealt round-robin to the 4 waves, up
+// to kMSlots per wave per pass (one pass covers 8x8 + 16x16 maps). The epilogue
+// normalises, mixes with the previous interior (hysteresis, or none for rejected
+// probes) and writes interior and border texels.
+// Epilogue of both blend kernels for one 16x16 accumulator tile: lane holds
+// D[4*krow + r][row]. Normalises, mixes with the previous interior (hysteresis, or
+// none for rejected probes) and writes interior and border texels.
+__device__ __forceinline__ void blend_epilogue(const BlendArgs &a, const float *s_h, const int *s_pid, int np,
+                                               bool irr, int mtile, int n, int row, int krow,
+                                               floatx4 acc) {
+    const int res = irr ? a.irr_res : a.depth_res;
+    const int T = res * res, comps = irr ? 3 : 2, side = res + 2;
+    const int m0 = mtile * 16 + 4 * krow;
+    const float *norm = irr ? a.norm_i : a.norm_d;
+    const int col = n * 16 + row;
+    const int q = irr ? col / 3 : col >> 1;
+    const int c = irr ? col - 3 * q : col & 1;
+    if (q >= np) return;
+    const size_t tile_floats = (size_t)side * side * comps;
+    const float *old_tile = (irr ? a.prev_irr : a.prev_depth) + (size_t)s_pid[q] * tile_floats;
+    float *new_tile = (irr ? a.new_irr : a.new_depth) + (size_t)s_pid[q] * tile_floats;
+    const float h = s_h[q];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int t = m0 + r;
+        if (t >= T) continue;
+        const int i = t % res, j = t / res;
+        const float nrm = norm[t];
+        const float old = old_tile[((j + 1) * side + (i + 1)) * comps + c];
+        const float u = acc[r] * nrm;
+        const float v = nrm < 0.0f ? old : fmaf(h, old - u, u);
+        store_with_border(new_tile, res, comps, i, j, c, v);
+    }
+}
+
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+constexpr int kPitch16 = kBlendChunk + 8;  // halves per LDS column (+8 spreads the banks)
+
+// Precision form of the blend: the same tiling as blend_kernel, with the weights as
+// FP16 (irradiance) / BF16 (depth) rows [T][Rpad] and the payload staged in LDS as
+// FP16 radiance and BF16 (t, t^2) columns, contracted 32 rays at a time on
+// v_mfma_f32_16x16x32_{f16,bf16} with FP32 accumulation.
+// One workgroup's share (probe slots pb .. pb+15) of the precision-form blend; also
+// the body of the batched blend, which passes each scene's arguments.
+template <bool kStd>
+__device__ __forceinline__ void blend16_block(const BlendArgs &a, int pb) {
+    __shared__ __attribute__((aligned(16))) _Float16 si[(kBlendProbes * 3 + 1) * kPitch16];
+    __shared__ __attribute__((aligned(16))) __bf16 sd[(kBlendProbes * 2 + 1) * kPitch16];
+    __shared__ float s_h[kBlendProbes];
+    __shared__ int s_pid[kBlendProbes];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int row = lane & 15, kgrp = lane >> 4;
+    const int count = a.probe_list ? min(*a.probe_count, a.P) : a.P;
+    if (pb >= count) return;
+    const int np = min(kBlendProbes, count - pb);
+    const int Ti = a.irr_res * a.irr_res, Td = a.depth_res * a.depth_res;
+    const int mti = (Ti + 15) >> 4, mtd = (Td + 15) >> 4;
+    const int mtiles = mti + mtd;
+    load_blend_probes(a, pb, np, s_pid, s_h);
+    for (int e = tid; e < kPitch16; e += 256) {
+        si[kBlendProbes * 3 * kPitch16 + e] = (_Float16)0.0f;
+        sd[kBlendProbes * 2 * kPitch16 + e] = (__bf16)0.0f;
+    }
+    int bi_off[3], bd_off[2];
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+        const int col = n * 16 + row;
+        bi_off[n] = (col / 3 < np ? col : kBlendProbes * 3) * kPitch16;
+    }
+#pragma unroll
+    for (int n = 0; n < 2; ++n) {
+        const int col = n * 16 + row;
+        bd_off[n] = ((col >> 1) < np ? col : kBlendProbes * 2) * kPitch16;
+    }
+    const int passes = kStd ? 1 : (mtiles + 4 * kMSlots - 1) / (4 * kMSlots);
+    for (int pass = 0; pass < passes; ++pass) {
+        floatx4 acc[kMSlots][3];
+        int mt[kMSlots];
+        const _Float16 *wi[kMSlots];
+        const __bf16 *wd[kMSlots];
+#pragma unroll
+        for (int s = 0; s < kMSlots; ++s) {
+            mt[s] = pass * 4 * kMSlots + s * 4 + wave;
+            const bool irr = kStd ? s == 0 : mt[s] < mti;
+            wi[s] = a.w16_i + (size_t)(mt[s] * 16 + row) * a.Rpad;
+            wd[s] = a.w16_d + (size_t)((irr ? 0 : mt[s] - mti) * 16 + row) * a.Rpad;
+#pragma unroll
+            for (int n = 0; n < 3; ++n) acc[s][n] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+        for (int k0 = 0; k0 < a.Rpad; k0 += kBlendChunk) {
+            __syncthreads();
+            const int kc = min(kBlendChunk, a.R - k0);  // rays present in this chunk
+            for (int e = tid; e < kBlendProbes * kBlendChunk; e += 256) {
+                const int q = e / kBlendChunk, kk = e - q * kBlendChunk;
+                float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if (q < np && kk < kc) v = a.payload[(size_t)s_pid[q] * a.R + k0 + kk];
+                si[(q * 3 + 0) * kPitch16 + kk] = (_Float16)v.x;
+                si[(q * 3 + 1) * kPitch16 + kk] = (_Float16)v.y;
+                si[(q * 3 + 2) * kPitch16 + kk] = (_Float16)v.z;
+                sd[(q * 2 + 0) * kPitch16 + kk] = (__bf16)v.w;
+                sd[(q * 2 + 1) * kPitch16 + kk] = (__bf16)(v.w * v.w);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int kk = 0; kk < kBlendChunk; kk += 32) {
+                const int kl = kk + 8 * kgrp;  // this lane's 8 rays within the chunk
+                half8_t bi[3];
+                bf16x8_t bd[2];
+#pragma unroll
+                for (int n = 0; n < 3; ++n)
+                    bi[n] = *reinterpret_cast<const half8_t *>(&si[bi_off[n] + kl]);
+#pragma unroll
+                for (int n = 0; n < 2; ++n)
+                    bd[n] = *reinterpret_cast<const bf16x8_t *>(&sd[bd_off[n] + kl]);
+#pragma unroll
+                for (int s = 0; s < kMSlots; ++s) {
+                    if (kStd ? s == 0 : mt[s] < mti) {
+                        const half8_t av = *reinterpret_cast<const half8_t *>(wi[s] + k0 + kl);
+#pragma unroll
+                        for (int n = 0; n < 3; ++n)
+                            acc[s][n] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bi[n], acc[s][n], 0, 0, 0);
+                    } else if (kStd || mt[s] < mtiles) {
+                        const bf16x8_t av = *reinterpret_cast<const bf16x8_t *>(wd[s] + k0 + kl);
+#pragma unroll
+                        for (int n = 0; n < 2; ++n)
+                            acc[s][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bd[n], acc[s][n], 0, 0, 0);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < kMSlots; ++s) {
+            if (!kStd && mt[s] >= mtiles) continue;
+            const bool irr = kStd ? s == 0 : mt[s] < mti;
+#pragma unroll
+            for (int n = 0; n < 3; ++n) {
+                if (!irr && n == 2) break;
+                blend_epilogue(a, s_h, s_pid, np, irr, irr ? mt[s] : mt[s] - mti, n, row, kgrp,
+                               acc[s][n]);
+            }
+        }
+    }
+    __syncthreads();
+    if (tid < np && a.reject) a.reject[s_pid[tid]] = 0;
+}
+
+}  // namespace sdfddgi

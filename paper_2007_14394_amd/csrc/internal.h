@@ -27,6 +27,18 @@ struct DevLevel {
     float xlo0, xlo1, xlo2, xhi0, xhi1, xhi2;
 };
 
+// A cascade level as the trace loops read it, copied to LDS once per block. The
+// binary32 constants were computed once in binary64 on the host.
+struct LevelLds {
+    const void *quad;              // corner quads [n2-1][n1-1][n0], float4 or half4
+    const float *alb;              // albedo [n2][n1][n0][3] or nullptr
+    float org0, org1, org2, inv;   // (float)origin, (float)(1/spacing)
+    float cmax0, cmax1, cmax2;     // (float)(n-2): last cell index per axis
+    float half;                    // (float)(spacing/2)
+    uint32_t row, slice;           // quad strides: n0, n0*(n1-1)
+    uint32_t arow, aslice;         // albedo strides: n0, n0*n1
+};
+
 struct ProbeGridDev {
     int n0, n1, n2;
     float org0, org1, org2;     // (float)origin
@@ -68,6 +80,8 @@ struct TableArgs {
     int R, Ti, Td;
     int Tpi, Tpd;               // row strides of the weight tables: T rounded up to 16
     double q[9];                // frame rotation, row-major
+    const double *q_dev;        // null: q above; else the rotation read from device memory
+                                //     (a captured graph replays with per-frame values)
     double sharp;               // depth cosine power
     const double *base;         // [R][3] unrotated spherical-Fibonacci set
     const double *texel_i;      // [Ti][3] irradiance texel directions
@@ -230,5 +244,64 @@ struct BakeArgs {
 };
 
 hipError_t launch_bake(const BakeArgs &a, hipStream_t stream);
+
+// ------------------------------------------------------------ batched form --
+// Many scenes of uneven size (one binary16 grid level each, 8x8 irradiance and
+// 16x16 depth maps, their own probe grids and ray counts) updated by one set of
+// launches per frame (batch.hip). Scenes are concatenated: scene s owns probes
+// probe_base .. probe_base+P-1 of the batch's probe arrays and atlases, and rays
+// ray_base .. ray_base+P*R-1 of its payload.
+constexpr int kMaxBatchScenes = 64;
+
+struct BatchScene {
+    LevelLds lv;                          // its grid level (binary16 quads)
+    float xlo0, xlo1, xlo2, xhi0, xhi1, xhi2;   // exact x bounds of the grid box
+    ProbeGridDev pg;
+    int P, R, ray_base, probe_base, dir_base, max_steps;
+    float eps, t_max, relax, bias, gain, hysteresis;
+    float sky0, sky1, sky2, alb0, alb1, alb2;
+    const _Float16 *w16_i;                // its ray set's tables
+    const __bf16 *w16_d;
+    const float *norm_i, *norm_d;
+};
+
+struct BatchArgs {
+    int nscenes;
+    const BatchScene *scenes;             // [nscenes]
+    const float *lights;                  // [nscenes][6]: unit direction to the light, radiance
+    int total_rays;
+    const float *probe_pos;               // [GP][3]
+    const int *probe_order;               // [GP]: each scene's probes in Morton order (local ids)
+    const float *dirs;                    // ray sets' directions, concatenated [.][3]
+    const float *prev_irr;                // [GP] irradiance tiles of the previous frame
+    float4 *payload;                      // [total_rays]
+    int4 *hitq;                           // [total_rays]: (ray, bits of t, info, scene)
+    int *counter;                         // [3]
+    int refill;                           // refill idle lanes below this many stepping lanes
+};
+
+struct BatchBlendArgs {
+    int nscenes;
+    const BatchScene *scenes;
+    const int2 *blocks;                   // [nblocks]: (scene, first probe) of each workgroup
+    const float4 *payload;
+    const float *prev_irr, *prev_depth;
+    float *new_irr, *new_depth;
+    uint8_t *reject;                      // [GP]
+    unsigned long long *done;             // [nscenes] device clock when the scene's last
+                                          //     blend workgroup finished (atomic max)
+};
+
+struct BatchTuning {
+    int primary_chunk, primary_blocks, hits_chunk, hits_blocks, refill;
+};
+
+hipError_t launch_batch_begin(int *counter, unsigned long long *stamps, int nscenes,
+                              hipStream_t stream);
+hipError_t launch_batch_primary(const BatchArgs &a, const BatchTuning &t, hipStream_t stream);
+hipError_t launch_batch_hits(const BatchArgs &a, const BatchTuning &t, hipStream_t stream);
+hipError_t launch_batch_blend(const BatchBlendArgs &a, int nblocks, hipStream_t stream);
+int batch_max_blocks(int device, bool hits);
+bool batch_chunk_supported(int chunk, bool hits);
 
 }  // namespace sdfddgi

@@ -16,28 +16,14 @@
 // any other multiply-add is disabled for this file.
 #include "internal.h"
 #include "octahedral.h"
+#include "trace_common.h"
+#include "blend_common.h"
 
 #pragma clang fp contract(off)
 
 namespace sdfddgi {
 
-enum : int { kMissTmax = 0, kMissExit = 1, kHit = 2, kHitExhausted = 3, kInside = 4 };
-
-__device__ __forceinline__ float clampf(float v, float lo, float hi) { return fminf(fmaxf(v, lo), hi); }
-
 // ------------------------------------------------------------- geometry -----
-
-// A cascade level as the trace loops read it, copied to LDS once per block. The
-// binary32 constants were computed once in binary64 on the host.
-struct LevelLds {
-    const void *quad;              // corner quads [n2-1][n1-1][n0], float4 or half4
-    const float *alb;              // albedo [n2][n1][n0][3] or nullptr
-    float org0, org1, org2, inv;   // (float)origin, (float)(1/spacing)
-    float cmax0, cmax1, cmax2;     // (float)(n-2): last cell index per axis
-    float half;                    // (float)(spacing/2)
-    uint32_t row, slice;           // quad strides: n0, n0*(n1-1)
-    uint32_t arow, aslice;         // albedo strides: n0, n0*n1
-};
 
 __device__ __forceinline__ void load_levels(const TraceArgs &a, LevelLds *s_lv) {
     if (threadIdx.x < kMaxLevels && (int)threadIdx.x < a.nl) {
@@ -52,63 +38,6 @@ __device__ __forceinline__ void load_levels(const TraceArgs &a, LevelLds *s_lv) 
         s_lv[threadIdx.x] = v;
     }
     __syncthreads();
-}
-
-// Cell and fraction of grid coordinate u along one axis (cell clamped to [0, cmax],
-// cmax = vertices - 2). The int overload is deleted so a vertex count cannot be
-// passed by mistake.
-__device__ void cell_of(float u, int cmax, int &i, float &f) = delete;
-__device__ __forceinline__ void cell_of(float u, float cmax, int &i, float &f) {
-    const float fl = clampf(floorf(u), 0.0f, cmax);
-    i = (int)fl;
-    f = clampf(u - fl, 0.0f, 1.0f);
-}
-
-// Trilinear sample at grid coordinates (u0,u1,u2): lerps along x, then y, then z.
-// The grid is stored as corner quads: quad (i,j,k) = the values at (i,j,k),
-// (i,j+1,k), (i,j,k+1), (i,j+1,k+1), so a cell's eight corners are the two
-// adjacent quads (i,j,k) and (i+1,j,k) -- usually one cache line.
-// With kHalf the quads hold binary16 values (the precision form); they are widened
-// exactly to binary32 and the arithmetic is unchanged.
-typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
-
-template <bool kHalf>
-__device__ __forceinline__ void load_quads(const void *base, uint32_t idx, float4 &a, float4 &b) {
-    if (kHalf) {
-        const half4_t *q = static_cast<const half4_t *>(base) + idx;
-        const half4_t ha = q[0], hb = q[1];
-        a = make_float4((float)ha.x, (float)ha.y, (float)ha.z, (float)ha.w);
-        b = make_float4((float)hb.x, (float)hb.y, (float)hb.z, (float)hb.w);
-    } else {
-        const float4 *q = static_cast<const float4 *>(base) + idx;
-        a = q[0];
-        b = q[1];
-    }
-}
-
-template <bool kHalf>
-__device__ __forceinline__ float trilinear(const LevelLds &d, float u0, float u1, float u2) {
-    int i0, i1, i2;
-    float f0, f1, f2;
-    cell_of(u0, d.cmax0, i0, f0);
-    cell_of(u1, d.cmax1, i1, f1);
-    cell_of(u2, d.cmax2, i2, f2);
-    float4 a, b;
-    load_quads<kHalf>(d.quad, (uint32_t)i2 * d.slice + (uint32_t)i1 * d.row + (uint32_t)i0, a, b);
-    const float v000 = a.x, v010 = a.y, v001 = a.z, v011 = a.w;
-    const float v100 = b.x, v110 = b.y, v101 = b.z, v111 = b.w;
-    const float c00 = fmaf(f0, v100 - v000, v000);
-    const float c10 = fmaf(f0, v110 - v010, v010);
-    const float c01 = fmaf(f0, v101 - v001, v001);
-    const float c11 = fmaf(f0, v111 - v011, v011);
-    const float c0 = fmaf(f1, c10 - c00, c00);
-    const float c1 = fmaf(f1, c11 - c01, c01);
-    return fmaf(f2, c1 - c0, c0);
-}
-
-template <bool kHalf>
-__device__ __forceinline__ float sample_at(const LevelLds &d, float p0, float p1, float p2) {
-    return trilinear<kHalf>(d, (p0 - d.org0) * d.inv, (p1 - d.org1) * d.inv, (p2 - d.org2) * d.inv);
 }
 
 // Finest level whose box, shrunk by one voxel (the coarsest level: its full box),
@@ -127,27 +56,6 @@ __device__ __forceinline__ int select_level(const TraceArgs &a, float x0, float 
         }
     }
     return L;
-}
-
-// Central differences at +-spacing/2 on the hit's level, normalised.
-template <bool kHalf>
-__device__ __forceinline__ void hit_normal(const LevelLds &d, float x0, float x1, float x2,
-                                           float w0, float w1, float w2,
-                                           float &n0, float &n1, float &n2) {
-    const float h = d.half;
-    float g[3];
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        const float p0 = x0 + (ax == 0 ? h : 0.0f), m0 = x0 - (ax == 0 ? h : 0.0f);
-        const float p1 = x1 + (ax == 1 ? h : 0.0f), m1 = x1 - (ax == 1 ? h : 0.0f);
-        const float p2 = x2 + (ax == 2 ? h : 0.0f), m2 = x2 - (ax == 2 ? h : 0.0f);
-        g[ax] = sample_at<kHalf>(d, p0, p1, p2) - sample_at<kHalf>(d, m0, m1, m2);
-    }
-    const float g0 = g[0], g1 = g[1], g2 = g[2];
-    const float len2 = fmaf(g2, g2, fmaf(g1, g1, g0 * g0));
-    if (!(len2 >= 1e-24f)) { n0 = -w0; n1 = -w1; n2 = -w2; return; }
-    const float inv = 1.0f / sqrtf(len2);
-    n0 = g0 * inv; n1 = g1 * inv; n2 = g2 * inv;
 }
 
 // One sample of the fixed sphere-trace sequence for a ray o + t w at sample k.
@@ -174,52 +82,6 @@ __device__ __forceinline__ int trace_step(const TraceArgs &a, const LevelLds *s_
 }
 
 // ----------------------------------------------------------- radiometry -----
-
-__device__ __forceinline__ float sgnf(float v) { return v >= 0.0f ? 1.0f : -1.0f; }
-
-// Probe interpolation: trilinear over the 8 probes of x's cell, bilinear in each
-// probe's padded octahedral tile at direction n.
-__device__ __forceinline__ float3 interp_irradiance(const float *__restrict__ atlas, int res,
-                                                   const ProbeGridDev &pg, float x0, float x1,
-                                                   float x2, float n0, float n1, float n2) {
-    int b0, b1, b2;
-    float f0, f1, f2;
-    cell_of((x0 - pg.org0) * pg.inv0, (float)(pg.n0 - 2), b0, f0);
-    cell_of((x1 - pg.org1) * pg.inv1, (float)(pg.n1 - 2), b1, f1);
-    cell_of((x2 - pg.org2) * pg.inv2, (float)(pg.n2 - 2), b2, f2);
-    float l1 = fabsf(n0) + fabsf(n1) + fabsf(n2);
-    float u = n0 / l1, v = n1 / l1;
-    if (n2 < 0.0f) {
-        float fu = (1.0f - fabsf(v)) * sgnf(u);
-        float fv = (1.0f - fabsf(u)) * sgnf(v);
-        u = fu; v = fv;
-    }
-    const float fres = (float)res;
-    float su = (fres * (u + 1.0f) + 1.0f) * 0.5f;
-    float sv = (fres * (v + 1.0f) + 1.0f) * 0.5f;
-    float au = clampf(floorf(su), 0.0f, fres), av = clampf(floorf(sv), 0.0f, fres);
-    float fu = clampf(su - au, 0.0f, 1.0f), fv = clampf(sv - av, 0.0f, 1.0f);
-    const int side = res + 2;
-    const int t00 = ((int)av * side + (int)au) * 3;
-    const int tile = side * side * 3;
-    const float w00 = (1.0f - fu) * (1.0f - fv), w10 = fu * (1.0f - fv);
-    const float w01 = (1.0f - fu) * fv, w11 = fu * fv;
-    float3 acc = make_float3(0.0f, 0.0f, 0.0f);
-    // four probes per iteration: 48 loads in flight, a quarter of the registers of a
-    // full unroll
-#pragma unroll 4
-    for (int c8 = 0; c8 < 8; ++c8) {
-        const int dx = c8 & 1, dy = (c8 >> 1) & 1, dz = c8 >> 2;
-        const float wp = (dx ? f0 : 1.0f - f0) * (dy ? f1 : 1.0f - f1) * (dz ? f2 : 1.0f - f2);
-        const int p = (b0 + dx) + pg.n0 * ((b1 + dy) + pg.n1 * (b2 + dz));
-        const float *tx = atlas + (size_t)p * tile + t00;
-        const float *ty = tx + side * 3;
-        acc.x += wp * (w00 * tx[0] + w10 * tx[3] + w01 * ty[0] + w11 * ty[3]);
-        acc.y += wp * (w00 * tx[1] + w10 * tx[4] + w01 * ty[1] + w11 * ty[4]);
-        acc.z += wp * (w00 * tx[2] + w10 * tx[5] + w01 * ty[2] + w11 * ty[5]);
-    }
-    return acc;
-}
 
 __device__ __forceinline__ float3 albedo_at(const TraceArgs &a, const LevelLds &d, float x0,
                                             float x1, float x2) {
@@ -259,11 +121,6 @@ __device__ __forceinline__ void write_ray(const TraceArgs &a, int ray, float4 ou
     }
 }
 
-// Primary-ray hit record packing: outcome | level << 4 | steps << 8.
-__device__ __forceinline__ int pack_hit(int kind, int level, int steps) {
-    return kind | (level << 4) | (steps << 8);
-}
-
 // Per-wave staging of hit-queue entries (ray, bits of t, packed info, 0) in LDS;
 // flushed to the global queue 64 at a time with one atomic.
 __device__ __forceinline__ void flush_hits(const TraceArgs &a, int4 *buf, int count) {
@@ -279,29 +136,6 @@ __device__ __forceinline__ void flush_hits(const TraceArgs &a, int4 *buf, int co
 constexpr int kChunk = 256;       // primary rays claimed from the global counter at a time
 constexpr int kHitChunk = 64;     // queued hits claimed at a time (spreads them over all waves)
 constexpr int kRefillBelow = 40;  // refill / run batched work when fewer lanes are stepping
-
-// Wave-level work feeder: claims `chunk` consecutive items per atomic and hands them
-// to idle lanes in order. All members are wave-uniform.
-template <int kChunkSize>
-struct Feeder {
-    int next = 0, end = 0;
-    bool exhausted = false;
-    // Returns the number of items given out; the rank-th idle lane takes first + rank.
-    __device__ __forceinline__ int claim(int *counter, int total, int want, int &first) {
-        if (next >= end) {
-            int base = 0;
-            if (__lane_id() == 0) base = atomicAdd(counter, kChunkSize);
-            base = __builtin_amdgcn_readfirstlane(base);
-            if (base >= total) { exhausted = true; return 0; }
-            next = base;
-            end = min(base + kChunkSize, total);
-        }
-        const int n = min(want, end - next);
-        first = next;
-        next += n;
-        return n;
-    }
-};
 
 // Primary sphere trace, persistent and wave-compacted: each lane owns one ray and
 // takes one sample per iteration; when fewer than kRefillBelow lanes are stepping,
@@ -507,6 +341,9 @@ __global__ __launch_bounds__(256) void tables_kernel(TableArgs a) {
     const bool is_dirs = row == a.Ti + a.Td;
     const bool is_depth = row >= a.Ti && !is_dirs;
     const int t = is_depth ? row - a.Ti : row;
+    double q[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) q[k] = a.q_dev ? a.q_dev[k] : a.q[k];
     double nt0 = 0, nt1 = 0, nt2 = 0;
     if (!is_dirs) {
         const double *nt = is_depth ? a.texel_d + 3 * t : a.texel_i + 3 * t;
@@ -515,9 +352,9 @@ __global__ __launch_bounds__(256) void tables_kernel(TableArgs a) {
     double part = 0.0;
     for (int i = tid; i < a.R; i += 256) {
         const double s0 = a.base[3 * i], s1 = a.base[3 * i + 1], s2 = a.base[3 * i + 2];
-        const double w0 = a.q[0] * s0 + a.q[1] * s1 + a.q[2] * s2;
-        const double w1 = a.q[3] * s0 + a.q[4] * s1 + a.q[5] * s2;
-        const double w2 = a.q[6] * s0 + a.q[7] * s1 + a.q[8] * s2;
+        const double w0 = q[0] * s0 + q[1] * s1 + q[2] * s2;
+        const double w1 = q[3] * s0 + q[4] * s1 + q[5] * s2;
+        const double w2 = q[6] * s0 + q[7] * s1 + q[8] * s2;
         if (is_dirs) {
             a.dirs[3 * i] = (float)w0;
             a.dirs[3 * i + 1] = (float)w1;
@@ -564,176 +401,9 @@ __global__ __launch_bounds__(256) void tables_kernel(TableArgs a) {
     }
 }
 
-constexpr int kBlendProbes = 16;  // probes per workgroup: the N extent of a tile row
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-
-// The probes of one blend workgroup (slots pb .. pb+np-1 of the probe list, or of
-// 0..P-1) and their hysteresis: none where the history is rejected. The first
-// __syncthreads of the caller's ray loop publishes them.
-__device__ __forceinline__ void load_blend_probes(const BlendArgs &a, int pb, int np, int *s_pid,
-                                                  float *s_h) {
-    const int tid = threadIdx.x;
-    if (tid < kBlendProbes) {
-        const int pid = tid < np ? (a.probe_list ? a.probe_list[pb + tid] : pb + tid) : 0;
-        s_pid[tid] = pid;
-        s_h[tid] = (tid < np && !(a.reject && a.reject[pid])) ? a.hysteresis : 0.0f;
-    }
-}
-
-constexpr int kBlendChunk = 64;   // rays staged in LDS at a time
-constexpr int kBlendPitch = kBlendChunk + 1;
-constexpr int kMSlots = 5;        // 16-texel M-tiles per wave per pass
-
-// Eq. 3 for 16 probes as a matrix product on MFMA (v_mfma_f32_16x16x4f32):
-//   irradiance  U_i[t][(q,c)] = sum_k w_tk   * L[q][k][c]      (M = texels, N = 16 x RGB)
-//   depth       U_d[t][(q,m)] = sum_k w_tk^s * t[q][k]^(m+1)   (M = texels, N = 16 x 2)
-// with K = rays. The weights (shared by every probe of the frame) are the A operand,
-// read from the transposed [R][T] tables; the probes' payload is the B operand,
-// staged in LDS 64 rays at a time. M-tiles are dealt round-robin to the 4 waves, up
-// to kMSlots per wave per pass (one pass covers 8x8 + 16x16 maps). The epilogue
-// normalises, mixes with the previous interior (hysteresis, or none for rejected
-// probes) and writes interior and border texels.
-// Epilogue of both blend kernels for one 16x16 accumulator tile: lane holds
-// D[4*krow + r][row]. Normalises, mixes with the previous interior (hysteresis, or
-// none for rejected probes) and writes interior and border texels.
-__device__ __forceinline__ void blend_epilogue(const BlendArgs &a, const float *s_h, const int *s_pid, int np,
-                                               bool irr, int mtile, int n, int row, int krow,
-                                               floatx4 acc) {
-    const int res = irr ? a.irr_res : a.depth_res;
-    const int T = res * res, comps = irr ? 3 : 2, side = res + 2;
-    const int m0 = mtile * 16 + 4 * krow;
-    const float *norm = irr ? a.norm_i : a.norm_d;
-    const int col = n * 16 + row;
-    const int q = irr ? col / 3 : col >> 1;
-    const int c = irr ? col - 3 * q : col & 1;
-    if (q >= np) return;
-    const size_t tile_floats = (size_t)side * side * comps;
-    const float *old_tile = (irr ? a.prev_irr : a.prev_depth) + (size_t)s_pid[q] * tile_floats;
-    float *new_tile = (irr ? a.new_irr : a.new_depth) + (size_t)s_pid[q] * tile_floats;
-    const float h = s_h[q];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int t = m0 + r;
-        if (t >= T) continue;
-        const int i = t % res, j = t / res;
-        const float nrm = norm[t];
-        const float old = old_tile[((j + 1) * side + (i + 1)) * comps + c];
-        const float u = acc[r] * nrm;
-        const float v = nrm < 0.0f ? old : fmaf(h, old - u, u);
-        store_with_border(new_tile, res, comps, i, j, c, v);
-    }
-}
-
-typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
-constexpr int kPitch16 = kBlendChunk + 8;  // halves per LDS column (+8 spreads the banks)
-
-// Precision form of the blend: the same tiling as blend_kernel, with the weights as
-// FP16 (irradiance) / BF16 (depth) rows [T][Rpad] and the payload staged in LDS as
-// FP16 radiance and BF16 (t, t^2) columns, contracted 32 rays at a time on
-// v_mfma_f32_16x16x32_{f16,bf16} with FP32 accumulation.
 template <bool kStd>
 __global__ __launch_bounds__(256) void blend16_kernel(BlendArgs a) {
-    __shared__ __attribute__((aligned(16))) _Float16 si[(kBlendProbes * 3 + 1) * kPitch16];
-    __shared__ __attribute__((aligned(16))) __bf16 sd[(kBlendProbes * 2 + 1) * kPitch16];
-    __shared__ float s_h[kBlendProbes];
-    __shared__ int s_pid[kBlendProbes];
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int row = lane & 15, kgrp = lane >> 4;
-    const int pb = blockIdx.x * kBlendProbes;
-    const int count = a.probe_list ? min(*a.probe_count, a.P) : a.P;
-    if (pb >= count) return;
-    const int np = min(kBlendProbes, count - pb);
-    const int Ti = a.irr_res * a.irr_res, Td = a.depth_res * a.depth_res;
-    const int mti = (Ti + 15) >> 4, mtd = (Td + 15) >> 4;
-    const int mtiles = mti + mtd;
-    load_blend_probes(a, pb, np, s_pid, s_h);
-    for (int e = tid; e < kPitch16; e += 256) {
-        si[kBlendProbes * 3 * kPitch16 + e] = (_Float16)0.0f;
-        sd[kBlendProbes * 2 * kPitch16 + e] = (__bf16)0.0f;
-    }
-    int bi_off[3], bd_off[2];
-#pragma unroll
-    for (int n = 0; n < 3; ++n) {
-        const int col = n * 16 + row;
-        bi_off[n] = (col / 3 < np ? col : kBlendProbes * 3) * kPitch16;
-    }
-#pragma unroll
-    for (int n = 0; n < 2; ++n) {
-        const int col = n * 16 + row;
-        bd_off[n] = ((col >> 1) < np ? col : kBlendProbes * 2) * kPitch16;
-    }
-    const int passes = kStd ? 1 : (mtiles + 4 * kMSlots - 1) / (4 * kMSlots);
-    for (int pass = 0; pass < passes; ++pass) {
-        floatx4 acc[kMSlots][3];
-        int mt[kMSlots];
-        const _Float16 *wi[kMSlots];
-        const __bf16 *wd[kMSlots];
-#pragma unroll
-        for (int s = 0; s < kMSlots; ++s) {
-            mt[s] = pass * 4 * kMSlots + s * 4 + wave;
-            const bool irr = kStd ? s == 0 : mt[s] < mti;
-            wi[s] = a.w16_i + (size_t)(mt[s] * 16 + row) * a.Rpad;
-            wd[s] = a.w16_d + (size_t)((irr ? 0 : mt[s] - mti) * 16 + row) * a.Rpad;
-#pragma unroll
-            for (int n = 0; n < 3; ++n) acc[s][n] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-        }
-        for (int k0 = 0; k0 < a.Rpad; k0 += kBlendChunk) {
-            __syncthreads();
-            const int kc = min(kBlendChunk, a.R - k0);  // rays present in this chunk
-            for (int e = tid; e < kBlendProbes * kBlendChunk; e += 256) {
-                const int q = e / kBlendChunk, kk = e - q * kBlendChunk;
-                float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                if (q < np && kk < kc) v = a.payload[(size_t)s_pid[q] * a.R + k0 + kk];
-                si[(q * 3 + 0) * kPitch16 + kk] = (_Float16)v.x;
-                si[(q * 3 + 1) * kPitch16 + kk] = (_Float16)v.y;
-                si[(q * 3 + 2) * kPitch16 + kk] = (_Float16)v.z;
-                sd[(q * 2 + 0) * kPitch16 + kk] = (__bf16)v.w;
-                sd[(q * 2 + 1) * kPitch16 + kk] = (__bf16)(v.w * v.w);
-            }
-            __syncthreads();
-#pragma unroll
-            for (int kk = 0; kk < kBlendChunk; kk += 32) {
-                const int kl = kk + 8 * kgrp;  // this lane's 8 rays within the chunk
-                half8_t bi[3];
-                bf16x8_t bd[2];
-#pragma unroll
-                for (int n = 0; n < 3; ++n)
-                    bi[n] = *reinterpret_cast<const half8_t *>(&si[bi_off[n] + kl]);
-#pragma unroll
-                for (int n = 0; n < 2; ++n)
-                    bd[n] = *reinterpret_cast<const bf16x8_t *>(&sd[bd_off[n] + kl]);
-#pragma unroll
-                for (int s = 0; s < kMSlots; ++s) {
-                    if (kStd ? s == 0 : mt[s] < mti) {
-                        const half8_t av = *reinterpret_cast<const half8_t *>(wi[s] + k0 + kl);
-#pragma unroll
-                        for (int n = 0; n < 3; ++n)
-                            acc[s][n] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bi[n], acc[s][n], 0, 0, 0);
-                    } else if (kStd || mt[s] < mtiles) {
-                        const bf16x8_t av = *reinterpret_cast<const bf16x8_t *>(wd[s] + k0 + kl);
-#pragma unroll
-                        for (int n = 0; n < 2; ++n)
-                            acc[s][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bd[n], acc[s][n], 0, 0, 0);
-                    }
-                }
-            }
-        }
-#pragma unroll
-        for (int s = 0; s < kMSlots; ++s) {
-            if (!kStd && mt[s] >= mtiles) continue;
-            const bool irr = kStd ? s == 0 : mt[s] < mti;
-#pragma unroll
-            for (int n = 0; n < 3; ++n) {
-                if (!irr && n == 2) break;
-                blend_epilogue(a, s_h, s_pid, np, irr, irr ? mt[s] : mt[s] - mti, n, row, kgrp,
-                               acc[s][n]);
-            }
-        }
-    }
-    __syncthreads();
-    if (tid < np && a.reject) a.reject[s_pid[tid]] = 0;
+    blend16_block<kStd>(a, blockIdx.x * kBlendProbes);
 }
 
 // kStd: the 8x8 irradiance + 16x16 depth layout (4 + 16 M-tiles, one pass), where

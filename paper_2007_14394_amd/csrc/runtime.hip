@@ -1389,3 +1389,625 @@ sdfddgi_status sdfddgi_bake_sdf(int32_t nprims, const int32_t *kind, const doubl
 const char *sdfddgi_learned_last_error(void) { return g_learned_error.c_str(); }
 
 }  // extern "C"
+
+// ------------------------------------------------------------ batched form --
+
+namespace {
+
+constexpr int kFrameSlots = 8;   // pinned staging slots of the per-frame constants
+
+struct BatchSet {
+    int R = 0, dir_base = 0;
+    double *base = nullptr;
+    _Float16 *w16_i = nullptr;
+    __bf16 *w16_d = nullptr;
+    float *norm_i = nullptr, *norm_d = nullptr;
+};
+
+}  // namespace
+
+struct sdfddgi_batch {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int S = 0;
+    int64_t GP = 0, total_rays = 0;
+    double sharp = 50.0;
+    std::vector<sdfddgi_batch_scene> scenes;
+    std::vector<BatchScene> host_scenes;
+    std::vector<BatchSet> sets;
+    void *quad[kMaxBatchScenes]{};
+    float *alb[kMaxBatchScenes]{};
+    BatchScene *dev_scenes = nullptr;
+    float *probe_pos = nullptr, *dirs = nullptr;
+    int *probe_order = nullptr;
+    double *texel_i = nullptr, *texel_d = nullptr;
+    float *irr[2]{}, *depth[2]{};
+    int cur = 0;
+    uint8_t *reject = nullptr;
+    float4 *payload = nullptr;
+    int4 *hitq = nullptr;
+    int *counter = nullptr;
+    unsigned long long *stamps = nullptr;    // [1 + S]
+    int2 *blocks = nullptr;
+    int nblocks = 0;
+    // per-frame constants on the device: rotation (9 doubles) then lights [S][6]
+    char *frame_dev = nullptr;
+    char *frame_host[kFrameSlots]{};          // pinned
+    hipEvent_t frame_ev[kFrameSlots]{};
+    bool frame_used[kFrameSlots]{};
+    int slot = 0;
+    size_t frame_bytes = 0;
+    BatchTuning tuning{};
+    hipGraph_t graph[2]{};
+    hipGraphExec_t exec[2]{};
+    bool have_frame = false;
+};
+
+namespace {
+
+void batch_free(sdfddgi_batch *b) {
+    for (int k = 0; k < 2; ++k) {
+        if (b->exec[k]) (void)hipGraphExecDestroy(b->exec[k]);
+        if (b->graph[k]) (void)hipGraphDestroy(b->graph[k]);
+        b->exec[k] = nullptr;
+        b->graph[k] = nullptr;
+    }
+    for (int s = 0; s < kMaxBatchScenes; ++s) {
+        dev_free(b->quad[s]);
+        dev_free(b->alb[s]);
+    }
+    for (BatchSet &r : b->sets) {
+        dev_free(r.base); dev_free(r.w16_i); dev_free(r.w16_d); dev_free(r.norm_i);
+        dev_free(r.norm_d);
+    }
+    dev_free(b->dev_scenes); dev_free(b->probe_pos); dev_free(b->dirs); dev_free(b->probe_order);
+    dev_free(b->texel_i); dev_free(b->texel_d);
+    dev_free(b->irr[0]); dev_free(b->irr[1]); dev_free(b->depth[0]); dev_free(b->depth[1]);
+    dev_free(b->reject); dev_free(b->payload); dev_free(b->hitq); dev_free(b->counter);
+    dev_free(b->stamps); dev_free(b->blocks); dev_free(b->frame_dev);
+    for (int k = 0; k < kFrameSlots; ++k) {
+        if (b->frame_host[k]) (void)hipHostFree(b->frame_host[k]);
+        if (b->frame_ev[k]) (void)hipEventDestroy(b->frame_ev[k]);
+    }
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+}
+
+BatchArgs batch_args(const sdfddgi_batch *b, int cur) {
+    BatchArgs a{};
+    a.nscenes = b->S;
+    a.scenes = b->dev_scenes;
+    a.lights = reinterpret_cast<const float *>(b->frame_dev + 9 * sizeof(double));
+    a.total_rays = (int)b->total_rays;
+    a.probe_pos = b->probe_pos;
+    a.probe_order = b->probe_order;
+    a.dirs = b->dirs;
+    a.prev_irr = b->irr[cur];
+    a.payload = b->payload;
+    a.hitq = b->hitq;
+    a.counter = b->counter;
+    a.refill = b->tuning.refill;
+    return a;
+}
+
+// The launches of one frame reading map pair `cur` and writing the other; `ev`
+// (may be null) receives events around the primary and hit kernels.
+hipError_t batch_enqueue(sdfddgi_batch *b, int cur, const BatchTuning &t, hipEvent_t *ev) {
+    hipError_t e = launch_batch_begin(b->counter, b->stamps, b->S, b->stream);
+    for (const BatchSet &r : b->sets) {
+        if (e != hipSuccess) return e;
+        TableArgs ta{};
+        ta.R = r.R;
+        ta.Ti = 64;
+        ta.Td = 256;
+        ta.Tpi = 64;
+        ta.Tpd = 256;
+        ta.q_dev = reinterpret_cast<const double *>(b->frame_dev);
+        ta.sharp = b->sharp;
+        ta.base = r.base;
+        ta.texel_i = b->texel_i;
+        ta.texel_d = b->texel_d;
+        ta.dirs = b->dirs + 3 * (size_t)r.dir_base;
+        ta.norm_i = r.norm_i;
+        ta.norm_d = r.norm_d;
+        ta.Rpad = r.R;
+        ta.w16_i = r.w16_i;
+        ta.w16_d = r.w16_d;
+        e = launch_tables(ta, b->stream);
+    }
+    if (e != hipSuccess) return e;
+    BatchArgs a = batch_args(b, cur);
+    a.refill = t.refill;
+    if (ev && (e = hipEventRecord(ev[0], b->stream)) != hipSuccess) return e;
+    if ((e = launch_batch_primary(a, t, b->stream)) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[1], b->stream)) != hipSuccess) return e;
+    if ((e = launch_batch_hits(a, t, b->stream)) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[2], b->stream)) != hipSuccess) return e;
+    BatchBlendArgs bb{};
+    bb.nscenes = b->S;
+    bb.scenes = b->dev_scenes;
+    bb.blocks = b->blocks;
+    bb.payload = b->payload;
+    bb.prev_irr = b->irr[cur];
+    bb.prev_depth = b->depth[cur];
+    bb.new_irr = b->irr[1 - cur];
+    bb.new_depth = b->depth[1 - cur];
+    bb.reject = b->reject;
+    bb.done = b->stamps + 1;
+    return launch_batch_blend(bb, b->nblocks, b->stream);
+}
+
+hipError_t batch_capture(sdfddgi_batch *b) {
+    for (int k = 0; k < 2; ++k) {
+        if (b->exec[k]) (void)hipGraphExecDestroy(b->exec[k]);
+        if (b->graph[k]) (void)hipGraphDestroy(b->graph[k]);
+        b->exec[k] = nullptr;
+        b->graph[k] = nullptr;
+    }
+    for (int k = 0; k < 2; ++k) {
+        hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return e;
+        const hipError_t le = batch_enqueue(b, k, b->tuning, nullptr);
+        e = hipStreamEndCapture(b->stream, &b->graph[k]);
+        if (le != hipSuccess) return le;
+        if (e != hipSuccess) return e;
+        if ((e = hipGraphInstantiate(&b->exec[k], b->graph[k], nullptr, nullptr, 0)) != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+// Stage the frame's rotation and lights through a pinned slot.
+sdfddgi_status batch_stage_frame(sdfddgi_batch *b, const sdfddgi_light *lights, uint64_t seed) {
+    if (!lights) return lfail(SDFDDGI_EINVAL, "lights is NULL");
+    const int k = b->slot;
+    hipError_t e = hipSuccess;
+    if (b->frame_used[k] && (e = hipEventSynchronize(b->frame_ev[k])) != hipSuccess)
+        return lhip_fail(e, "waiting for a staging slot");
+    double *q = reinterpret_cast<double *>(b->frame_host[k]);
+    rotation_matrix(seed, q);
+    float *lt = reinterpret_cast<float *>(b->frame_host[k] + 9 * sizeof(double));
+    for (int s = 0; s < b->S; ++s) {
+        const sdfddgi_light &li = lights[s];
+        if (!finite_all(li.dir_to_light, 3) || !finite_all(li.radiance_rgb, 3))
+            return lfail(SDFDDGI_EINVAL, "scene %d: non-finite light", s);
+        const double d0 = li.dir_to_light[0], d1 = li.dir_to_light[1], d2 = li.dir_to_light[2];
+        const double len = std::sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        if (!(len > 0.0)) return lfail(SDFDDGI_EINVAL, "scene %d: zero light direction", s);
+        for (int c = 0; c < 3; ++c)
+            if (li.radiance_rgb[c] < 0) return lfail(SDFDDGI_EINVAL, "scene %d: negative radiance", s);
+        lt[6 * s + 0] = (float)(d0 / len);
+        lt[6 * s + 1] = (float)(d1 / len);
+        lt[6 * s + 2] = (float)(d2 / len);
+        for (int c = 0; c < 3; ++c) lt[6 * s + 3 + c] = li.radiance_rgb[c];
+    }
+    if ((e = hipMemcpyAsync(b->frame_dev, b->frame_host[k], b->frame_bytes, hipMemcpyHostToDevice,
+                            b->stream)) != hipSuccess ||
+        (e = hipEventRecord(b->frame_ev[k], b->stream)) != hipSuccess)
+        return lhip_fail(e, "staging the frame");
+    b->frame_used[k] = true;
+    b->slot = (k + 1) % kFrameSlots;
+    return SDFDDGI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sdfddgi_status sdfddgi_batch_destroy(sdfddgi_batch *b) {
+    if (!b) return SDFDDGI_OK;
+    (void)hipSetDevice(b->device);
+    (void)hipStreamSynchronize(b->stream);
+    batch_free(b);
+    delete b;
+    return SDFDDGI_OK;
+}
+
+sdfddgi_status sdfddgi_batch_create(const sdfddgi_batch_scene *scenes, int32_t count,
+                                    void *hip_stream, sdfddgi_batch **out) {
+    g_learned_error.clear();
+    if (!out) return lfail(SDFDDGI_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!scenes || count < 1 || count > kMaxBatchScenes)
+        return lfail(SDFDDGI_EINVAL, "need 1..%d scenes", kMaxBatchScenes);
+    int64_t GP = 0, rays = 0;
+    for (int s = 0; s < count; ++s) {
+        const sdfddgi_batch_scene &sc = scenes[s];
+        sdfddgi_sdf_grid g{};
+        g.num_levels = 1;
+        g.level[0] = sc.level;
+        sdfddgi_params p = sc.params;
+        p.learned_rays = 0;
+        p.flags = 0;
+        if (validate(&g, &sc.probes, &p) != SDFDDGI_OK)
+            return lfail(SDFDDGI_EINVAL, "scene %d: %s", s, g_create_error.c_str());
+        if (p.rays_per_probe % 64 || p.irr_res != 8 || p.depth_res != 16)
+            return lfail(SDFDDGI_EINVAL,
+                         "scene %d: batched scenes need rays a multiple of 64, 8x8 and 16x16 maps", s);
+        if (p.depth_sharpness != scenes[0].params.depth_sharpness)
+            return lfail(SDFDDGI_EINVAL, "scene %d: every scene needs the same depth_sharpness", s);
+        const int64_t P = (int64_t)sc.probes.n[0] * sc.probes.n[1] * sc.probes.n[2];
+        GP += P;
+        rays += P * p.rays_per_probe;
+    }
+    if (rays >= (int64_t)1 << 31) return lfail(SDFDDGI_EINVAL, "too many rays in the batch");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return lhip_fail(e, "hipGetDevice");
+    (void)hipGetLastError();
+    sdfddgi_batch *b = new (std::nothrow) sdfddgi_batch();
+    if (!b) return lfail(SDFDDGI_ENOMEM, "host allocation failed");
+    b->device = dev;
+    b->S = count;
+    b->GP = GP;
+    b->total_rays = rays;
+    b->sharp = scenes[0].params.depth_sharpness;
+    b->scenes.assign(scenes, scenes + count);
+    auto bail = [&](sdfddgi_status st) {
+        (void)hipStreamSynchronize(b->stream);
+        batch_free(b);
+        delete b;
+        return st;
+    };
+#define B_TRY(expr, what)                                                       \
+    do {                                                                        \
+        hipError_t e_ = (expr);                                                 \
+        if (e_ != hipSuccess) return bail(lhip_fail(e_, what));                 \
+    } while (0)
+    if (hip_stream) {
+        b->stream = (hipStream_t)hip_stream;
+    } else {
+        B_TRY(hipStreamCreate(&b->stream), "creating a stream");
+        b->own_stream = true;
+    }
+    // ray sets: one per distinct ray count, directions concatenated
+    std::vector<int> set_of(count);
+    int dir_total = 0;
+    for (int s = 0; s < count; ++s) {
+        const int R = scenes[s].params.rays_per_probe;
+        int k = 0;
+        while (k < (int)b->sets.size() && b->sets[k].R != R) ++k;
+        if (k == (int)b->sets.size()) {
+            BatchSet r;
+            r.R = R;
+            r.dir_base = dir_total;
+            dir_total += R;
+            b->sets.push_back(r);
+        }
+        set_of[s] = k;
+    }
+    for (BatchSet &r : b->sets) {
+        std::vector<double> h(3 * (size_t)r.R);
+        for (int i = 0; i < r.R; ++i) fibonacci_point(i, r.R, &h[3 * i]);
+        B_TRY(dev_alloc(&r.base, h.size()), "allocating ray sets");
+        B_TRY(hipMemcpy(r.base, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice),
+              "uploading ray sets");
+        B_TRY(dev_alloc(&r.w16_i, (size_t)64 * r.R), "allocating tables");
+        B_TRY(dev_alloc(&r.w16_d, (size_t)256 * r.R), "allocating tables");
+        B_TRY(dev_alloc(&r.norm_i, 64), "allocating tables");
+        B_TRY(dev_alloc(&r.norm_d, 256), "allocating tables");
+    }
+    B_TRY(dev_alloc(&b->dirs, 3 * (size_t)dir_total), "allocating directions");
+    {
+        std::vector<double> ti(3 * 64), td(3 * 256);
+        for (int t = 0; t < 64; ++t) texel_direction(8, t % 8, t / 8, &ti[3 * t]);
+        for (int t = 0; t < 256; ++t) texel_direction(16, t % 16, t / 16, &td[3 * t]);
+        B_TRY(dev_alloc(&b->texel_i, ti.size()), "allocating texel directions");
+        B_TRY(dev_alloc(&b->texel_d, td.size()), "allocating texel directions");
+        B_TRY(hipMemcpy(b->texel_i, ti.data(), ti.size() * sizeof(double), hipMemcpyHostToDevice),
+              "uploading texel directions");
+        B_TRY(hipMemcpy(b->texel_d, td.data(), td.size() * sizeof(double), hipMemcpyHostToDevice),
+              "uploading texel directions");
+    }
+    // scenes: binary16 grids, descriptors, probe positions and tracing orders
+    std::vector<float> h_pos(3 * (size_t)GP);
+    std::vector<int32_t> h_order((size_t)GP);
+    std::vector<int2> h_blocks;
+    b->host_scenes.resize(count);
+    int64_t pbase = 0, rbase = 0;
+    for (int s = 0; s < count; ++s) {
+        const sdfddgi_batch_scene &sc = scenes[s];
+        const sdfddgi_sdf_level &lv = sc.level;
+        const size_t nquad = (size_t)lv.n[0] * (lv.n[1] - 1) * (lv.n[2] - 1);
+        B_TRY(hipMalloc(&b->quad[s], nquad * 8), "allocating a grid");
+        B_TRY(launch_pack_quads(lv.sdf, lv.n[0], lv.n[1], lv.n[2], true, b->quad[s], b->stream),
+              "packing a grid");
+        const size_t cnt = (size_t)lv.n[0] * lv.n[1] * lv.n[2];
+        if (lv.albedo_rgb) {
+            B_TRY(dev_alloc(&b->alb[s], 3 * cnt), "allocating albedo");
+            B_TRY(hipMemcpyAsync(b->alb[s], lv.albedo_rgb, 3 * cnt * sizeof(float),
+                                 hipMemcpyDeviceToDevice, b->stream),
+                  "copying albedo");
+        }
+        BatchScene &d = b->host_scenes[s];
+        d = BatchScene{};
+        d.lv.quad = b->quad[s];
+        d.lv.alb = b->alb[s];
+        d.lv.org0 = (float)lv.origin[0];
+        d.lv.org1 = (float)lv.origin[1];
+        d.lv.org2 = (float)lv.origin[2];
+        d.lv.inv = (float)(1.0 / lv.spacing);
+        d.lv.cmax0 = (float)(lv.n[0] - 2);
+        d.lv.cmax1 = (float)(lv.n[1] - 2);
+        d.lv.cmax2 = (float)(lv.n[2] - 2);
+        d.lv.half = (float)(0.5 * lv.spacing);
+        d.lv.row = (uint32_t)lv.n[0];
+        d.lv.slice = (uint32_t)lv.n[0] * (uint32_t)(lv.n[1] - 1);
+        d.lv.arow = (uint32_t)lv.n[0];
+        d.lv.aslice = (uint32_t)lv.n[0] * (uint32_t)lv.n[1];
+        const float org[3] = {d.lv.org0, d.lv.org1, d.lv.org2};
+        float lo[3], hi[3];
+        for (int k = 0; k < 3; ++k) {   // one level: the whole grid box, [0, n-1]
+            lo[k] = lower_bound_x(org[k], d.lv.inv, 0.0f);
+            hi[k] = upper_bound_x(org[k], d.lv.inv, (float)(lv.n[k] - 1));
+        }
+        d.xlo0 = lo[0]; d.xlo1 = lo[1]; d.xlo2 = lo[2];
+        d.xhi0 = hi[0]; d.xhi1 = hi[1]; d.xhi2 = hi[2];
+        const sdfddgi_probe_grid &pg = sc.probes;
+        d.pg.n0 = pg.n[0]; d.pg.n1 = pg.n[1]; d.pg.n2 = pg.n[2];
+        d.pg.org0 = (float)pg.origin[0];
+        d.pg.org1 = (float)pg.origin[1];
+        d.pg.org2 = (float)pg.origin[2];
+        d.pg.inv0 = (float)(1.0 / pg.spacing[0]);
+        d.pg.inv1 = (float)(1.0 / pg.spacing[1]);
+        d.pg.inv2 = (float)(1.0 / pg.spacing[2]);
+        const int64_t P = (int64_t)pg.n[0] * pg.n[1] * pg.n[2];
+        const sdfddgi_params &p = sc.params;
+        d.P = (int)P;
+        d.R = p.rays_per_probe;
+        d.ray_base = (int)rbase;
+        d.probe_base = (int)pbase;
+        const BatchSet &r = b->sets[set_of[s]];
+        d.dir_base = r.dir_base;
+        d.max_steps = p.max_steps;
+        d.eps = p.hit_eps;
+        d.t_max = p.t_max;
+        d.relax = p.relax;
+        d.bias = p.shadow_bias;
+        d.gain = p.bounce_gain;
+        d.hysteresis = p.hysteresis;
+        d.sky0 = p.sky_rgb[0]; d.sky1 = p.sky_rgb[1]; d.sky2 = p.sky_rgb[2];
+        d.alb0 = p.albedo[0]; d.alb1 = p.albedo[1]; d.alb2 = p.albedo[2];
+        d.w16_i = r.w16_i;
+        d.w16_d = r.w16_d;
+        d.norm_i = r.norm_i;
+        d.norm_d = r.norm_d;
+        // positions (binary64, rounded once) and the Morton tracing order
+        const int nx = pg.n[0], ny = pg.n[1];
+        std::vector<std::pair<uint64_t, int32_t>> morton((size_t)P);
+        for (int64_t q = 0; q < P; ++q) {
+            const int64_t idx[3] = {q % nx, (q / nx) % ny, q / ((int64_t)nx * ny)};
+            for (int k = 0; k < 3; ++k)
+                h_pos[3 * (pbase + q) + k] =
+                    (float)(pg.origin[k] + pg.spacing[k] * (double)idx[k]);
+            uint64_t m = 0;
+            for (int bit = 0; bit < 21; ++bit)
+                m |= ((((uint64_t)idx[0] >> bit) & 1) << (3 * bit)) |
+                     ((((uint64_t)idx[1] >> bit) & 1) << (3 * bit + 1)) |
+                     ((((uint64_t)idx[2] >> bit) & 1) << (3 * bit + 2));
+            morton[(size_t)q] = {m, (int32_t)q};
+        }
+        std::sort(morton.begin(), morton.end());
+        for (int64_t q = 0; q < P; ++q) h_order[(size_t)(pbase + q)] = morton[(size_t)q].second;
+        for (int pb = 0; pb < (int)P; pb += 16) h_blocks.push_back(make_int2(s, pb));
+        pbase += P;
+        rbase += P * p.rays_per_probe;
+    }
+    b->nblocks = (int)h_blocks.size();
+    B_TRY(dev_alloc(&b->dev_scenes, count), "allocating scene descriptors");
+    B_TRY(hipMemcpy(b->dev_scenes, b->host_scenes.data(), count * sizeof(BatchScene),
+                    hipMemcpyHostToDevice),
+          "uploading scene descriptors");
+    B_TRY(dev_alloc(&b->probe_pos, h_pos.size()), "allocating probes");
+    B_TRY(dev_alloc(&b->probe_order, h_order.size()), "allocating probes");
+    B_TRY(dev_alloc(&b->blocks, h_blocks.size()), "allocating the blend table");
+    B_TRY(hipMemcpy(b->probe_pos, h_pos.data(), h_pos.size() * sizeof(float), hipMemcpyHostToDevice),
+          "uploading probes");
+    B_TRY(hipMemcpy(b->probe_order, h_order.data(), h_order.size() * sizeof(int32_t),
+                    hipMemcpyHostToDevice),
+          "uploading probes");
+    B_TRY(hipMemcpy(b->blocks, h_blocks.data(), h_blocks.size() * sizeof(int2),
+                    hipMemcpyHostToDevice),
+          "uploading the blend table");
+    const size_t irr_f = (size_t)GP * 10 * 10 * 3, dep_f = (size_t)GP * 18 * 18 * 2;
+    for (int k = 0; k < 2; ++k) {
+        B_TRY(dev_alloc(&b->irr[k], irr_f), "allocating maps");
+        B_TRY(dev_alloc(&b->depth[k], dep_f), "allocating maps");
+        B_TRY(hipMemsetAsync(b->irr[k], 0, irr_f * sizeof(float), b->stream), "clearing maps");
+        B_TRY(hipMemsetAsync(b->depth[k], 0, dep_f * sizeof(float), b->stream), "clearing maps");
+    }
+    B_TRY(dev_alloc(&b->reject, (size_t)GP), "allocating history flags");
+    B_TRY(launch_fill_u8(b->reject, 1, GP, b->stream), "launching fill");
+    B_TRY(dev_alloc(&b->payload, (size_t)rays), "allocating payload");
+    B_TRY(dev_alloc(&b->hitq, (size_t)rays), "allocating the hit queue");
+    B_TRY(dev_alloc(&b->counter, 3), "allocating counters");
+    B_TRY(dev_alloc(&b->stamps, 1 + (size_t)count), "allocating stamps");
+    b->frame_bytes = 9 * sizeof(double) + 6 * sizeof(float) * (size_t)count;
+    B_TRY(dev_alloc(&b->frame_dev, b->frame_bytes), "allocating frame constants");
+    for (int k = 0; k < kFrameSlots; ++k) {
+        B_TRY(hipHostMalloc((void **)&b->frame_host[k], b->frame_bytes, hipHostMallocDefault),
+              "allocating pinned staging");
+        B_TRY(hipEventCreateWithFlags(&b->frame_ev[k], hipEventDisableTiming), "creating events");
+    }
+    b->tuning.primary_chunk = 256;
+    b->tuning.primary_blocks = batch_max_blocks(dev, false);
+    b->tuning.hits_chunk = 64;
+    b->tuning.hits_blocks = batch_max_blocks(dev, true);
+    b->tuning.refill = 40;
+    B_TRY(hipStreamSynchronize(b->stream), "waiting for the uploads");
+    B_TRY(batch_capture(b), "capturing the frame graphs");
+#undef B_TRY
+    *out = b;
+    return SDFDDGI_OK;
+}
+
+sdfddgi_status sdfddgi_batch_update_frame(sdfddgi_batch *b, const sdfddgi_light *lights,
+                                          uint64_t rotation_seed) {
+    g_learned_error.clear();
+    if (!b) return lfail(SDFDDGI_EINVAL, "batch is NULL");
+    (void)hipGetLastError();
+    hipError_t e = hipSetDevice(b->device);
+    if (e != hipSuccess) return lhip_fail(e, "hipSetDevice");
+    sdfddgi_status st = batch_stage_frame(b, lights, rotation_seed);
+    if (st != SDFDDGI_OK) return st;
+    if ((e = hipGraphLaunch(b->exec[b->cur], b->stream)) != hipSuccess)
+        return lhip_fail(e, "launching the frame graph");
+    b->cur = 1 - b->cur;
+    b->have_frame = true;
+    return SDFDDGI_OK;
+}
+
+static bool tuning_valid(int device, const sdfddgi_batch_tuning *t) {
+    return t && batch_chunk_supported(t->primary_chunk, false) &&
+           batch_chunk_supported(t->hits_chunk, true) && t->primary_blocks >= 1 &&
+           t->primary_blocks <= batch_max_blocks(device, false) && t->hits_blocks >= 1 &&
+           t->hits_blocks <= batch_max_blocks(device, true) && t->refill >= 1 && t->refill <= 64;
+}
+
+sdfddgi_status sdfddgi_batch_set_tuning(sdfddgi_batch *b, const sdfddgi_batch_tuning *t) {
+    g_learned_error.clear();
+    if (!b) return lfail(SDFDDGI_EINVAL, "batch is NULL");
+    (void)hipGetLastError();
+    if (!tuning_valid(b->device, t)) return lfail(SDFDDGI_EINVAL, "tuning out of range");
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return lhip_fail(e, "waiting for the stream");
+    b->tuning = BatchTuning{t->primary_chunk, t->primary_blocks, t->hits_chunk, t->hits_blocks,
+                            t->refill};
+    if ((e = batch_capture(b)) != hipSuccess) return lhip_fail(e, "capturing the frame graphs");
+    return SDFDDGI_OK;
+}
+
+sdfddgi_status sdfddgi_batch_autotune(sdfddgi_batch *b, const sdfddgi_light *lights,
+                                      uint64_t rotation_seed, int32_t frames,
+                                      sdfddgi_batch_tuning *chosen, int32_t *tried) {
+    g_learned_error.clear();
+    if (!b) return lfail(SDFDDGI_EINVAL, "batch is NULL");
+    if (frames < 1 || frames > 64) return lfail(SDFDDGI_EINVAL, "frames_per_candidate in 1..64");
+    (void)hipGetLastError();
+    hipError_t e = hipSetDevice(b->device);
+    if (e != hipSuccess) return lhip_fail(e, "hipSetDevice");
+    sdfddgi_status st = batch_stage_frame(b, lights, rotation_seed);
+    if (st != SDFDDGI_OK) return st;
+    // candidate frames read the current maps and write the other pair (the state
+    // does not advance); the history flags, which a blend clears, are restored
+    uint8_t *saved = nullptr;
+    if ((e = dev_alloc(&saved, (size_t)b->GP)) != hipSuccess) return lhip_fail(e, "allocating");
+    e = hipMemcpyAsync(saved, b->reject, (size_t)b->GP, hipMemcpyDeviceToDevice, b->stream);
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipEventCreate(&ev[k]);
+    const int pmax = batch_max_blocks(b->device, false), hmax = batch_max_blocks(b->device, true);
+    int count = 0;
+    // time one configuration: mean primary and hit kernel times over `frames`
+    auto measure = [&](const BatchTuning &t, float &prim, float &hits) -> hipError_t {
+        prim = hits = 0.0f;
+        for (int f = 0; f < frames; ++f) {
+            hipError_t x = batch_enqueue(b, b->cur, t, ev);
+            if (x != hipSuccess) return x;
+            if ((x = hipEventSynchronize(ev[2])) != hipSuccess) return x;
+            float a = 0.0f, c = 0.0f;
+            if ((x = hipEventElapsedTime(&a, ev[0], ev[1])) != hipSuccess) return x;
+            if ((x = hipEventElapsedTime(&c, ev[1], ev[2])) != hipSuccess) return x;
+            prim += a / frames;
+            hits += c / frames;
+        }
+        ++count;
+        return hipSuccess;
+    };
+    BatchTuning best = b->tuning;
+    float best_p = 1e30f, best_h = 1e30f, p = 0, h = 0;
+    // the primary trace: chunk x refill x grid; then the hit shading: chunk x grid
+    const int pchunks[4] = {64, 128, 256, 512}, refills[4] = {24, 32, 40, 48};
+    const int pgrids[2] = {pmax, std::max(1, pmax / 2)};
+    for (int ci = 0; ci < 4 && e == hipSuccess; ++ci)
+        for (int ri = 0; ri < 4 && e == hipSuccess; ++ri)
+            for (int gi = 0; gi < 2 && e == hipSuccess; ++gi) {
+                BatchTuning t = best;
+                t.primary_chunk = pchunks[ci];
+                t.refill = refills[ri];
+                t.primary_blocks = pgrids[gi];
+                if ((e = measure(t, p, h)) == hipSuccess && p < best_p) {
+                    best_p = p;
+                    best.primary_chunk = t.primary_chunk;
+                    best.refill = t.refill;
+                    best.primary_blocks = t.primary_blocks;
+                }
+            }
+    const int hchunks[4] = {16, 32, 64, 128};
+    const int hgrids[2] = {hmax, std::max(1, hmax / 2)};
+    for (int ci = 0; ci < 4 && e == hipSuccess; ++ci)
+        for (int gi = 0; gi < 2 && e == hipSuccess; ++gi) {
+            BatchTuning t = best;
+            t.hits_chunk = hchunks[ci];
+            t.hits_blocks = hgrids[gi];
+            if ((e = measure(t, p, h)) == hipSuccess && h < best_h) {
+                best_h = h;
+                best.hits_chunk = t.hits_chunk;
+                best.hits_blocks = t.hits_blocks;
+            }
+        }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->reject, saved, (size_t)b->GP, hipMemcpyDeviceToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    for (int k = 0; k < 3; ++k)
+        if (ev[k]) (void)hipEventDestroy(ev[k]);
+    dev_free(saved);
+    if (e != hipSuccess) return lhip_fail(e, "autotuning");
+    b->tuning = best;
+    if ((e = batch_capture(b)) != hipSuccess) return lhip_fail(e, "capturing the frame graphs");
+    if (chosen)
+        *chosen = sdfddgi_batch_tuning{best.primary_chunk, best.primary_blocks, best.hits_chunk,
+                                       best.hits_blocks, best.refill};
+    if (tried) *tried = count;
+    return SDFDDGI_OK;
+}
+
+sdfddgi_status sdfddgi_batch_get_maps(sdfddgi_batch *b, int32_t scene, float *irr, float *depth) {
+    g_learned_error.clear();
+    if (!b) return lfail(SDFDDGI_EINVAL, "batch is NULL");
+    if (scene < 0 || scene >= b->S) return lfail(SDFDDGI_EINVAL, "scene %d out of range", scene);
+    (void)hipGetLastError();
+    const BatchScene &d = b->host_scenes[scene];
+    const size_t ti = 10 * 10 * 3, td = 18 * 18 * 2;
+    hipError_t e = hipSuccess;
+    if (irr)
+        e = hipMemcpyAsync(irr, b->irr[b->cur] + (size_t)d.probe_base * ti,
+                           (size_t)d.P * ti * sizeof(float), hipMemcpyDeviceToDevice, b->stream);
+    if (e == hipSuccess && depth)
+        e = hipMemcpyAsync(depth, b->depth[b->cur] + (size_t)d.probe_base * td,
+                           (size_t)d.P * td * sizeof(float), hipMemcpyDeviceToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return lhip_fail(e, "copying maps");
+    return SDFDDGI_OK;
+}
+
+sdfddgi_status sdfddgi_batch_scene_latency(sdfddgi_batch *b, float *ms, float *frame_ms) {
+    g_learned_error.clear();
+    if (!b || !ms) return lfail(SDFDDGI_EINVAL, "null argument");
+    if (!b->have_frame) return lfail(SDFDDGI_ESTATE, "no frame yet");
+    (void)hipGetLastError();
+    std::vector<unsigned long long> st(1 + (size_t)b->S);
+    int rate_khz = 0;
+    hipError_t e = hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, b->device);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(st.data(), b->stamps, st.size() * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return lhip_fail(e, "reading the stamps");
+    if (rate_khz <= 0) return lfail(SDFDDGI_EDEVICE, "no device clock rate");
+    float worst = 0.0f;
+    for (int s = 0; s < b->S; ++s) {
+        ms[s] = (float)((double)(st[1 + s] - st[0]) / (double)rate_khz);
+        worst = std::max(worst, ms[s]);
+    }
+    if (frame_ms) *frame_ms = worst;
+    return SDFDDGI_OK;
+}
+
+sdfddgi_status sdfddgi_batch_sizes(const sdfddgi_batch *b, int64_t *probes, int64_t *rays) {
+    if (!b) return SDFDDGI_EINVAL;
+    if (probes) *probes = b->GP;
+    if (rays) *rays = b->total_rays;
+    return SDFDDGI_OK;
+}
+
+}  // extern "C"

@@ -37,8 +37,11 @@ EXPORTED = [
     "sdfddgi_update_frame_learned", "sdfddgi_get_fallback", "sdfddgi_learned_examples",
     "sdfddgi_trainer_create", "sdfddgi_trainer_gradient", "sdfddgi_trainer_step",
     "sdfddgi_trainer_get_params", "sdfddgi_trainer_destroy", "sdfddgi_learned_last_error",
-    "sdfddgi_bake_sdf",
+    "sdfddgi_bake_sdf", "sdfddgi_batch_create", "sdfddgi_batch_update_frame",
+    "sdfddgi_batch_autotune", "sdfddgi_batch_set_tuning", "sdfddgi_batch_get_maps",
+    "sdfddgi_batch_scene_latency", "sdfddgi_batch_sizes", "sdfddgi_batch_destroy",
 ]
+SDFDDGI_MAX_BATCH_SCENES = 64
 SDFDDGI_DENOISER_PARAMS = 9604
 SDFDDGI_FEATURES = 16
 KERNEL_TIMES = ("tables", "primary", "hits", "blend", "frame", "denoise", "fallback_trace",
@@ -75,6 +78,12 @@ class sdfddgi_params(ctypes.Structure):
 class sdfddgi_train_config(ctypes.Structure):
     _fields_ = [("head_weight", ctypes.c_float), ("min_error", ctypes.c_float),
                 ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+
+
+class sdfddgi_batch_tuning(ctypes.Structure):
+    _fields_ = [("primary_chunk", ctypes.c_int32), ("primary_blocks", ctypes.c_int32),
+                ("hits_chunk", ctypes.c_int32), ("hits_blocks", ctypes.c_int32),
+                ("refill", ctypes.c_int32)]
 
 
 class sdfddgi_light(ctypes.Structure):
@@ -142,6 +151,15 @@ def load_library() -> ctypes.CDLL:
     L.sdfddgi_bake_sdf.argtypes = [i32, vp, vp, vp, vp, ctypes.POINTER(i32),
                                    ctypes.POINTER(ctypes.c_double), ctypes.c_double, f32, vp,
                                    vp, vp]
+    L.sdfddgi_batch_create.argtypes = [vp, i32, vp, ctypes.POINTER(vp)]
+    L.sdfddgi_batch_update_frame.argtypes = [vp, vp, u64]
+    L.sdfddgi_batch_autotune.argtypes = [vp, vp, u64, i32, ctypes.POINTER(sdfddgi_batch_tuning),
+                                         ctypes.POINTER(i32)]
+    L.sdfddgi_batch_set_tuning.argtypes = [vp, ctypes.POINTER(sdfddgi_batch_tuning)]
+    L.sdfddgi_batch_get_maps.argtypes = [vp, i32, vp, vp]
+    L.sdfddgi_batch_scene_latency.argtypes = [vp, vp, vp]
+    L.sdfddgi_batch_sizes.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.sdfddgi_batch_destroy.argtypes = [vp]
     L.sdfddgi_learned_last_error.argtypes = []
     L.sdfddgi_learned_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -584,6 +602,142 @@ def sdfddgi_bake_sdf(kind, center, half, albedo, n, origin, spacing: float,
             P(out_alb.data_ptr()) if out_alb is not None else None,
             P(_stream_handle(stream))))
     return sdf, out_alb
+
+
+class sdfddgi_batch_scene(ctypes.Structure):
+    _fields_ = [("level", sdfddgi_sdf_level), ("probes", sdfddgi_probe_grid),
+                ("params", sdfddgi_params)]
+
+
+class Batch:
+    def __init__(self, handle: int, device, count: int, probes: Sequence[int]):
+        self.handle = ctypes.c_void_p(handle)
+        self.device = device
+        self.count = count
+        self.probes = list(probes)
+
+    def __del__(self):
+        try:
+            if self.handle and self.handle.value:
+                load_library().sdfddgi_batch_destroy(self.handle)
+                self.handle = ctypes.c_void_p(0)
+        except Exception:
+            pass
+
+
+def _lights(lights):
+    arr = (sdfddgi_light * len(lights))()
+    for k, (d, r) in enumerate(lights):
+        arr[k].dir_to_light[:] = [float(v) for v in d]
+        arr[k].radiance_rgb[:] = [float(v) for v in r]
+    return arr
+
+
+def sdfddgi_batch_create(scenes: Sequence[dict], stream=None) -> Batch:
+    """scenes: dicts with ``sdf`` [n2,n1,n0] and optional ``albedo`` device tensors,
+    ``origin``, ``spacing``, ``probe_n``, ``probe_origin``, ``probe_spacing`` and
+    ``params`` (an sdfddgi_params)."""
+    import torch
+    arr = (sdfddgi_batch_scene * len(scenes))()
+    device = None
+    keep = []
+    for k, sc in enumerate(scenes):
+        sdf = sc["sdf"]
+        device = sdf.device if device is None else device
+        lv = arr[k].level
+        lv.sdf = _dev_ptr(sdf, torch.float32, f"scenes[{k}].sdf", device)
+        n2, n1, n0 = sdf.shape
+        lv.n[:] = [n0, n1, n2]
+        lv.origin[:] = [float(v) for v in sc["origin"]]
+        lv.spacing = float(sc["spacing"])
+        alb = sc.get("albedo")
+        lv.albedo_rgb = (_dev_ptr(alb, torch.float32, f"scenes[{k}].albedo", device)
+                         if alb is not None else None)
+        arr[k].probes.n[:] = [int(v) for v in sc["probe_n"]]
+        arr[k].probes.origin[:] = [float(v) for v in sc["probe_origin"]]
+        arr[k].probes.spacing[:] = [float(v) for v in sc["probe_spacing"]]
+        arr[k].params = sc["params"]
+        keep.append(sc)
+    out = ctypes.c_void_p()
+    with torch.cuda.device(device):
+        st = ctypes.c_void_p(_stream_handle(stream)) if stream is not None else None
+        _lcheck(load_library().sdfddgi_batch_create(arr, ctypes.c_int32(len(scenes)), st,
+                                                    ctypes.byref(out)))
+    probes = [int(np.prod(list(sc["probe_n"]))) for sc in scenes]
+    return Batch(out.value, device, len(scenes), probes)
+
+
+def sdfddgi_batch_update_frame(b: Batch, lights, rotation_seed: int) -> None:
+    """lights: one (dir_to_light, radiance_rgb) pair per scene."""
+    if len(lights) != b.count:
+        raise ValueError("one light per scene")
+    _lcheck(load_library().sdfddgi_batch_update_frame(b.handle, _lights(lights),
+                                                      ctypes.c_uint64(int(rotation_seed))))
+
+
+def sdfddgi_batch_autotune(b: Batch, lights, rotation_seed: int, frames_per_candidate: int = 2):
+    t = sdfddgi_batch_tuning()
+    n = ctypes.c_int32()
+    _lcheck(load_library().sdfddgi_batch_autotune(
+        b.handle, _lights(lights), ctypes.c_uint64(int(rotation_seed)),
+        ctypes.c_int32(frames_per_candidate), ctypes.byref(t), ctypes.byref(n)))
+    return {f: getattr(t, f) for f, _ in sdfddgi_batch_tuning._fields_}, n.value
+
+
+def sdfddgi_batch_set_tuning(b: Batch, **fields) -> None:
+    t = sdfddgi_batch_tuning(**fields)
+    _lcheck(load_library().sdfddgi_batch_set_tuning(b.handle, ctypes.byref(t)))
+
+
+def sdfddgi_batch_get_maps(b: Batch, scene: int):
+    import torch
+    P = b.probes[scene]
+    irr = torch.empty((P, 10, 10, 3), dtype=torch.float32, device=b.device)
+    dep = torch.empty((P, 18, 18, 2), dtype=torch.float32, device=b.device)
+    _lcheck(load_library().sdfddgi_batch_get_maps(b.handle, ctypes.c_int32(scene),
+                                                  irr.data_ptr(), dep.data_ptr()))
+    return irr, dep
+
+
+def sdfddgi_batch_scene_latency(b: Batch):
+    ms = np.zeros(b.count, dtype=np.float32)
+    worst = ctypes.c_float()
+    _lcheck(load_library().sdfddgi_batch_scene_latency(b.handle, ctypes.c_void_p(ms.ctypes.data),
+                                                       ctypes.byref(worst)))
+    return ms, float(worst.value)
+
+
+def sdfddgi_batch_sizes(b: Batch):
+    p, r = ctypes.c_int64(), ctypes.c_int64()
+    _lcheck(load_library().sdfddgi_batch_sizes(b.handle, ctypes.byref(p), ctypes.byref(r)))
+    return p.value, r.value
+
+
+def sdfddgi_batch_destroy(b: Batch) -> None:
+    if b.handle and b.handle.value:
+        _lcheck(load_library().sdfddgi_batch_destroy(b.handle))
+        b.handle = ctypes.c_void_p(0)
+
+
+def batch_from_specs(specs, baked=None, stream=None, device="cuda:0") -> Batch:
+    """A batch from scenegen scene specs: grids baked on the device unless ``baked``
+    holds host SDFLevels (one per spec)."""
+    import torch
+    dev = torch.device(device)
+    scenes = []
+    for k, sp in enumerate(specs):
+        (n, origin, spacing), = sp.levels
+        if baked is None:
+            sdf, alb = sdfddgi_bake_sdf(sp.prims.kind, sp.prims.center, sp.prims.half,
+                                        sp.prims.albedo, n, origin, spacing, device=device)
+        else:
+            lv = baked[k]
+            sdf = torch.from_numpy(np.ascontiguousarray(lv.sdf)).to(dev)
+            alb = torch.from_numpy(np.ascontiguousarray(lv.albedo)).to(dev)
+        scenes.append(dict(sdf=sdf, albedo=alb, origin=origin, spacing=spacing,
+                           probe_n=sp.probes.n, probe_origin=sp.probes.origin,
+                           probe_spacing=sp.probes.spacing, params=params_from(sp.params)))
+    return sdfddgi_batch_create(scenes, stream)
 
 
 def sdfddgi_learned_last_error() -> str:

@@ -301,6 +301,55 @@ def training_scene(seed: int, probes=(16, 16, 16), frames: int = 61, rays: int =
     return SceneSpec(f"training_{seed}", prims, levels, pg, params, fr)
 
 
+def batch_scene_specs(seed: int, count: int = 64, frames: int = 40,
+                      sdf_range=(32, 192), probes_xz=(4, 24), probes_y=(4, 12),
+                      rays=(64, 128, 256, 512)) -> Tuple[List[SceneSpec], List[int]]:
+    """Scenes of uneven size for the batched form, and the frames' rotation seeds.
+
+    Scene s: probe grid nx x ny x nz (nx, nz log-uniform in probes_xz, ny in
+    probes_y) at 1 m spacing from (1, 1, 1); one cubic SDF grid of n^3 vertices (n
+    log-uniform in sdf_range) over [0, L]^3, L = max(nx, ny, nz) + 1; a ground
+    slab under y = 0 and 10 + volume/8 (at most 150) spheres and boxes (sizes
+    log-uniform in [0.2, 1.5] m, albedo U[0.2, 0.8]^3) inside the box; rays per
+    probe drawn from ``rays``; sky 0.5; a sun of random elevation (25-65 degrees)
+    and azimuth turning 1 degree per frame."""
+    rng = np.random.default_rng(8_000_000 + seed)
+    def logu(lo, hi):
+        return int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+    specs = []
+    for s in range(count):
+        nx, ny, nz = logu(*probes_xz), logu(*probes_y), logu(*probes_xz)
+        n = logu(*sdf_range)
+        L = float(max(nx, ny, nz) + 1)
+        rows = [(PRIM_BOX, [L / 2, -1.0, L / 2], [L, 1.0, L], rng.uniform(0.2, 0.8, 3))]
+        vol = (nx + 1) * (ny + 1) * (nz + 1)
+        for _ in range(min(150, 10 + vol // 8)):
+            c = [rng.uniform(0, nx + 1), rng.uniform(0, ny + 1), rng.uniform(0, nz + 1)]
+            if rng.uniform() < 0.5:
+                h = 0.5 * np.exp(rng.uniform(math.log(0.2), math.log(1.5), 3))
+                rows.append((PRIM_BOX, c, h, rng.uniform(0.2, 0.8, 3)))
+            else:
+                r = 0.5 * math.exp(rng.uniform(math.log(0.2), math.log(1.5)))
+                rows.append((PRIM_SPHERE, c, [r, r, r], rng.uniform(0.2, 0.8, 3)))
+        R = int(rng.choice(rays))
+        params = Params(rays_per_probe=R, t_max=L * math.sqrt(3.0), sky_rgb=(0.5, 0.5, 0.5))
+        elev, az0 = float(rng.uniform(25.0, 65.0)), float(rng.uniform(0.0, 360.0))
+        fr = [Frame(sun_direction(elev, az0 + float(f)), (3.0, 3.0, 3.0), 0)
+              for f in range(frames)]
+        specs.append(SceneSpec(f"batch_{seed}_{s}", _prims(rows),
+                               [((n, n, n), (0.0, 0.0, 0.0), L / (n - 1))],
+                               ProbeGrid((nx, ny, nz), (1.0, 1.0, 1.0), (1.0, 1.0, 1.0)),
+                               params, fr))
+    seeds = _rotation_seeds(rng, frames)
+    return specs, seeds
+
+
+def spec_workload(spec: SceneSpec) -> Workload:
+    """Bake a scene spec on the host (for tests at small sizes)."""
+    levels = [bake(spec.prims, n, origin, spacing) for n, origin, spacing in spec.levels]
+    return Workload(spec.name, spec.prims, levels, spec.probes, spec.params, list(spec.frames))
+
+
 def small_cascade(seed: int = 0, probes=(6, 3, 5), rays: int = 64, grid: int = 40,
                   num_prims: int = 24, frames: int = 4) -> Workload:
     """A reduced open scene: 2-level cascade, ragged probe count, for quick parity."""

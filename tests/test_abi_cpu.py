@@ -181,3 +181,36 @@ def test_learned_entry_points_reject_bad_arguments_before_touching_a_device():
     assert lib.sdfddgi_trainer_step(None, None, None, 1, 1, 0, 0.1, None) == S.SDFDDGI_EINVAL
     assert lib.sdfddgi_denoiser_destroy(None) == S.SDFDDGI_OK
     assert lib.sdfddgi_trainer_destroy(None) == S.SDFDDGI_OK
+
+
+def test_batch_create_rejects_bad_arguments_before_touching_a_device():
+    lib = S.load_library()
+    out = ctypes.c_void_p()
+    assert lib.sdfddgi_batch_create(None, 1, None, ctypes.byref(out)) == S.SDFDDGI_EINVAL
+
+    def scenes(k=2, mutate=None):
+        arr = (S.sdfddgi_batch_scene * k)()
+        for i in range(k):
+            g, pg = _grid_and_probes()
+            arr[i].level = g.level[0]
+            arr[i].probes = pg
+            p = S.sdfddgi_default_params()
+            p.rays_per_probe = 128
+            arr[i].params = p
+        if mutate:
+            mutate(arr)
+        return arr
+
+    assert lib.sdfddgi_batch_create(scenes(), 0, None, ctypes.byref(out)) == S.SDFDDGI_EINVAL
+    assert lib.sdfddgi_batch_create(scenes(), 65, None, ctypes.byref(out)) == S.SDFDDGI_EINVAL
+    for mutate in [lambda a: setattr(a[1].params, "rays_per_probe", 80),    # not a multiple of 64
+                   lambda a: setattr(a[0].params, "irr_res", 6),
+                   lambda a: setattr(a[1].params, "depth_sharpness", 20.0),
+                   lambda a: setattr(a[0].level, "sdf", None),
+                   lambda a: a[1].probes.n.__setitem__(0, 1)]:
+        st = lib.sdfddgi_batch_create(scenes(mutate=mutate), 2, None, ctypes.byref(out))
+        assert st == S.SDFDDGI_EINVAL, S.sdfddgi_learned_last_error()
+        assert out.value is None
+    li = (S.sdfddgi_light * 1)()
+    assert lib.sdfddgi_batch_update_frame(None, li, 1) == S.SDFDDGI_EINVAL
+    assert lib.sdfddgi_batch_destroy(None) == S.SDFDDGI_OK

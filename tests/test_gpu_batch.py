@@ -1,0 +1,122 @@
+"""GPU tests of the batched form: a batch of uneven scenes, updated by one graph
+replay per frame, gives every scene the maps of its own single-scene context in
+the precision form, bit for bit (those are checked against the reference checker
+by the precision-form tests); autotuning changes no result; per-scene latencies
+come from the device clock."""
+import sys
+
+import numpy as np
+import pytest
+
+import scenegen
+
+pytestmark = pytest.mark.gpu
+
+
+def announce(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    from paper_2007_14394_amd import sdfddgi
+    assert torch.cuda.is_available(), "GPU tests need a visible gfx950 device"
+    sdfddgi.load_library()
+    return sdfddgi
+
+
+def to_host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def small_batch(count=6, seed=1, frames=4):
+    specs, seeds = scenegen.batch_scene_specs(seed, count, frames=frames, sdf_range=(20, 44),
+                                              probes_xz=(2, 6), probes_y=(2, 4), rays=(64, 128))
+    return specs, seeds, [scenegen.spec_workload(sp) for sp in specs]
+
+
+def lights_of(specs, f):
+    return [(sp.frames[f].dir_to_light, sp.frames[f].radiance_rgb) for sp in specs]
+
+
+def single_maps(S, w, spec, seeds, frames):
+    ctx = S.context_from_workload(w, flags=S.SDFDDGI_FLAG_FP16)
+    for f in range(frames):
+        fr = spec.frames[f]
+        S.sdfddgi_update_frame(ctx, fr.dir_to_light, fr.radiance_rgb, seeds[f])
+    irr, dep = S.sdfddgi_get_maps(ctx)
+    return to_host(irr), to_host(dep)
+
+
+def test_batch_matches_single_contexts_bit_for_bit(S):
+    specs, seeds, works = small_batch()
+    announce(f"batch of {len(specs)}: probes {[sp.probes.n for sp in specs]} "
+             f"rays {[sp.params.rays_per_probe for sp in specs]}")
+    b = S.batch_from_specs(specs, baked=[w.levels[0] for w in works])
+    frames = 3
+    for f in range(frames):
+        S.sdfddgi_batch_update_frame(b, lights_of(specs, f), seeds[f])
+    for s, (sp, w) in enumerate(zip(specs, works)):
+        bi, bd = S.sdfddgi_batch_get_maps(b, s)
+        si, sd = single_maps(S, w, sp, seeds, frames)
+        assert np.array_equal(to_host(bi).view(np.int32), si.view(np.int32)), f"scene {s} irradiance"
+        assert np.array_equal(to_host(bd).view(np.int32), sd.view(np.int32)), f"scene {s} depth"
+
+
+def test_autotune_changes_no_result(S):
+    specs, seeds, works = small_batch(count=4, seed=2)
+    baked = [w.levels[0] for w in works]
+    a = S.batch_from_specs(specs, baked=baked)
+    t = S.batch_from_specs(specs, baked=baked)
+    S.sdfddgi_batch_update_frame(a, lights_of(specs, 0), seeds[0])
+    S.sdfddgi_batch_update_frame(t, lights_of(specs, 0), seeds[0])
+    before = [to_host(S.sdfddgi_batch_get_maps(t, s)[0]) for s in range(len(specs))]
+    tuning, tried = S.sdfddgi_batch_autotune(t, lights_of(specs, 1), seeds[1], 1)
+    announce(f"autotune tried {tried}: {tuning}")
+    assert tried == 40
+    assert tuning["primary_chunk"] in (64, 128, 256, 512) and tuning["hits_chunk"] in (16, 32, 64, 128)
+    for s in range(len(specs)):   # the tuning frames leave the state as it was
+        assert np.array_equal(to_host(S.sdfddgi_batch_get_maps(t, s)[0]), before[s])
+    for f in (1, 2):
+        S.sdfddgi_batch_update_frame(a, lights_of(specs, f), seeds[f])
+        S.sdfddgi_batch_update_frame(t, lights_of(specs, f), seeds[f])
+    for s in range(len(specs)):
+        for k in range(2):
+            x, y = S.sdfddgi_batch_get_maps(a, s)[k], S.sdfddgi_batch_get_maps(t, s)[k]
+            assert np.array_equal(to_host(x), to_host(y))
+
+
+def test_explicit_tuning_and_its_validation(S):
+    specs, seeds, works = small_batch(count=3, seed=3)
+    b = S.batch_from_specs(specs, baked=[w.levels[0] for w in works])
+    S.sdfddgi_batch_set_tuning(b, primary_chunk=64, primary_blocks=64, hits_chunk=16,
+                               hits_blocks=32, refill=24)
+    S.sdfddgi_batch_update_frame(b, lights_of(specs, 0), seeds[0])
+    with pytest.raises(S.SdfddgiError):
+        S.sdfddgi_batch_set_tuning(b, primary_chunk=100, primary_blocks=64, hits_chunk=16,
+                                   hits_blocks=32, refill=24)
+    with pytest.raises(S.SdfddgiError):
+        S.sdfddgi_batch_set_tuning(b, primary_chunk=64, primary_blocks=64, hits_chunk=16,
+                                   hits_blocks=32, refill=0)
+
+
+def test_scene_latencies_from_the_device_clock(S):
+    import time
+    import torch
+    specs, seeds, works = small_batch(count=5, seed=4)
+    b = S.batch_from_specs(specs, baked=[w.levels[0] for w in works])
+    with pytest.raises(S.SdfddgiError):
+        S.sdfddgi_batch_scene_latency(b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.sdfddgi_batch_update_frame(b, lights_of(specs, 0), seeds[0])
+    ms, worst = S.sdfddgi_batch_scene_latency(b)
+    wall = (time.perf_counter() - t0) * 1e3
+    assert np.all(ms > 0) and worst == ms.max() and worst <= wall
+    probes, rays = S.sdfddgi_batch_sizes(b)
+    assert probes == sum(int(np.prod(sp.probes.n)) for sp in specs)
+    assert rays == sum(int(np.prod(sp.probes.n)) * sp.params.rays_per_probe for sp in specs)
