@@ -124,7 +124,7 @@ typedef struct {
     sdfddgi_sdf_level level[SDFDDGI_MAX_LEVELS];
 } sdfddgi_sdf_grid;
 
-/* The uniform probe grid of Sec. 3.2 (relocation of Alg. 1 is not applied). */
+/* The uniform probe grid of Sec. 3.2 (sdfddgi_relocate_probes applies Alg. 1). */
 typedef struct {
     int32_t n[3];              /* probes per axis, each >= 2 */
     double origin[3];
@@ -232,6 +232,23 @@ sdfddgi_status sdfddgi_ray_directions(uint64_t rotation_seed, int32_t rays, floa
  * Host pointer ms[count], count <= 8. Waits for the last timed frame.
  * ESTATE without SDFDDGI_FLAG_TIMING or when no frame ran since the last call. */
 sdfddgi_status sdfddgi_get_kernel_times(sdfddgi_ctx *ctx, float *ms, int32_t count);
+
+/* Alg. 1 (UpdateProbePos) for every probe, on the context's stream: from its grid
+ * position x, while the SDF at x is below threshold1 (at most `iterations`
+ * times), step along the normalised SDF gradient (the hit-normal rule; +y where
+ * it vanishes) by threshold1 - SDF(x), a Newton step on the distance field;
+ * each coordinate stays within max_offset * spacing of the grid position, and a
+ * probe outside every level stays where it is. All binary32:
+ *   x_c = min(max(fma(threshold1 - d, n_c, x_c), g_c - o_c), g_c + o_c).
+ * A probe whose new position is more than threshold2 from its position before
+ * this call has its history rejected (markRejectHistory). Rays start from the
+ * new positions from the next frame on; the probe interpolation keeps using the
+ * grid cells. The paper gives no threshold values; they are arguments here. */
+sdfddgi_status sdfddgi_relocate_probes(sdfddgi_ctx *ctx, float threshold1, float threshold2,
+                                       int32_t iterations, float max_offset);
+
+/* Copy the current probe positions (device [P][3], binary32). */
+sdfddgi_status sdfddgi_get_probe_positions(sdfddgi_ctx *ctx, float *out);
 
 /* Sizes of the context's problem: probes P, rays R, and the float counts of
  * one irradiance and one depth atlas. Host pointers; any may be NULL. */

@@ -57,7 +57,8 @@ class Setup(ctypes.Structure):
                 ("t_max", ctypes.c_float), ("hysteresis", ctypes.c_float),
                 ("bounce_gain", ctypes.c_float), ("depth_sharpness", ctypes.c_float),
                 ("shadow_bias", ctypes.c_float), ("relax", ctypes.c_float),
-                ("sky", ctypes.c_float * 3), ("albedo", ctypes.c_float * 3)]
+                ("sky", ctypes.c_float * 3), ("albedo", ctypes.c_float * 3),
+                ("probe_pos", ctypes.c_void_p)]
 
 
 class FrameDesc(ctypes.Structure):
@@ -183,6 +184,40 @@ class Checker:
         rec = (ctypes.c_int32 * 8)()
         lib().orc_trace_ray32(self.ref, o, d, l, rec)
         return np.array(list(rec), dtype=np.int32)
+
+    def set_probe_positions(self, pos: Optional[np.ndarray]) -> None:
+        """Trace from these binary32 positions [P][3] (relocated probes); None: the grid."""
+        if pos is None:
+            self.s.probe_pos = None
+            self._pos = None
+            return
+        self._pos = np.ascontiguousarray(pos, dtype=np.float32).reshape(self.num_probes, 3)
+        self.s.probe_pos = self._pos.ctypes.data
+
+    def relocate_probes(self, last, threshold1: float, threshold2: float, iterations: int,
+                        max_offset: float):
+        """Alg. 1 for every probe: (positions [P][3] binary32, reject flags [P])."""
+        last = np.ascontiguousarray(last, dtype=np.float32).reshape(self.num_probes, 3)
+        out = np.zeros((self.num_probes, 3), dtype=np.float32)
+        rej = np.zeros(self.num_probes, dtype=np.int32)
+        for p in range(self.num_probes):
+            o = (ctypes.c_float * 3)()
+            r = ctypes.c_int32()
+            lib().orc_relocate_probe(self.ref, ctypes.c_int32(p), _p(last[p]),
+                                     ctypes.c_float(threshold1), ctypes.c_float(threshold2),
+                                     ctypes.c_int32(iterations), ctypes.c_float(max_offset), o,
+                                     ctypes.byref(r))
+            out[p] = list(o)
+            rej[p] = r.value
+        return out, rej
+
+    def grid_positions(self) -> np.ndarray:
+        """The grid positions rounded once to binary32 [P][3]."""
+        saved = self.s.probe_pos
+        self.s.probe_pos = None
+        pos = np.array([self.probe_position(p) for p in range(self.num_probes)]).astype(np.float32)
+        self.s.probe_pos = saved
+        return pos
 
     def probe_position(self, p: int) -> np.ndarray:
         out = (ctypes.c_double * 3)()

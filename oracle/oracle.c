@@ -104,6 +104,10 @@ void orc_ray_directions(uint64_t seed, int32_t rays, double *dirs)
 /* Probe p = x + nx*(y + ny*z) sits on the uniform grid (Sec. 3.2). */
 void orc_probe_position(const orc_setup *s, int32_t p, double pos[3])
 {
+    if (s->probe_pos) {
+        for (int c = 0; c < 3; ++c) pos[c] = (double)s->probe_pos[3 * p + c];
+        return;
+    }
     int32_t idx[3];
     idx[0] = p % s->probe_n[0];
     idx[1] = (p / s->probe_n[0]) % s->probe_n[1];
@@ -332,6 +336,43 @@ static void normal32(const orc_setup *s, int32_t level, const float x[3], const 
     }
     float inv = 1.0f / sqrtf(len2);
     for (int c = 0; c < 3; ++c) n[c] = grad[c] * inv;
+}
+
+/* Alg. 1: move a probe that is too close to (or inside) geometry out along the
+ * distance field's gradient; reject its history if it moved too far. */
+void orc_relocate_probe(const orc_setup *s, int32_t p, const float last[3], float threshold1,
+                        float threshold2, int32_t iterations, float max_offset, float out[3],
+                        int32_t *reject)
+{
+    int32_t idx[3];
+    idx[0] = p % s->probe_n[0];
+    idx[1] = (p / s->probe_n[0]) % s->probe_n[1];
+    idx[2] = p / (s->probe_n[0] * s->probe_n[1]);
+    float g[3], o[3], x[3];
+    for (int c = 0; c < 3; ++c) {
+        g[c] = (float)(s->probe_origin[c] + s->probe_spacing[c] * (double)idx[c]);
+        o[c] = (float)((double)max_offset * s->probe_spacing[c]);
+        x[c] = g[c];
+    }
+    const float down[3] = {0.0f, -1.0f, 0.0f};   /* normal fallback -down = +y */
+    for (int32_t it = 0; it < iterations; ++it) {
+        int32_t L = orc_level32(s, x);
+        if (L < 0) break;
+        float d = orc_sdf32(s, L, x);
+        if (!(d < threshold1)) break;
+        float n[3];
+        normal32(s, L, x, down, n);
+        float step = threshold1 - d;
+        for (int c = 0; c < 3; ++c) {
+            float v = fmaf(step, n[c], x[c]);
+            float lo = g[c] - o[c], hi = g[c] + o[c];
+            x[c] = v < lo ? lo : (v > hi ? hi : v);
+        }
+    }
+    float dx = x[0] - last[0], dy = x[1] - last[1], dz = x[2] - last[2];
+    float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    *reject = d2 > threshold2 * threshold2 ? 1 : 0;
+    for (int c = 0; c < 3; ++c) out[c] = x[c];
 }
 
 typedef struct {

@@ -73,6 +73,7 @@ typedef struct {
     float relax;
     float sky[3];
     float albedo[3];
+    const float *probe_pos;       /* [P][3] relocated positions, or NULL: the grid */
 } orc_setup;
 
 typedef struct {
@@ -87,6 +88,19 @@ uint64_t orc_splitmix64(uint64_t *state);
 void orc_frame_rotation(uint64_t seed, double q[9]);
 void orc_ray_directions(uint64_t seed, int32_t rays, double *dirs /* [rays][3] */);
 void orc_probe_position(const orc_setup *s, int32_t probe, double pos[3]);
+
+/* Alg. 1 (UpdateProbePos) for probe p: from its grid position x, while the SDF
+ * at x is below threshold1 (at most `iterations` times) step along the
+ * normalised SDF gradient by threshold1 - SDF(x) (a Newton step on the distance
+ * field), keeping each coordinate within max_offset * spacing of the grid
+ * position; outside every level x is left as it is. All in binary32:
+ *   x_c = min(max(fma(threshold1 - d, n_c, x_c), g_c - o_c), g_c + o_c)
+ * with n the normal rule of the hit points (fallback +y when the gradient
+ * vanishes) and o_c = (float)(max_offset * spacing_c). *reject = 1 when
+ * |x - last|^2 = fma(dz, dz, fma(dy, dy, dx*dx)) > threshold2^2 (binary32). */
+void orc_relocate_probe(const orc_setup *s, int32_t p, const float last[3], float threshold1,
+                        float threshold2, int32_t iterations, float max_offset, float out[3],
+                        int32_t *reject);
 
 /* ---- octahedral parameterisation --------------------------------------- */
 void orc_oct_encode(const double n[3], double uv[2]);

@@ -221,6 +221,18 @@ struct AdamArgs {
 };
 
 hipError_t launch_probe_sdf(const TraceArgs &a, float *out, hipStream_t stream);
+
+// Alg. 1 (UpdateProbePos) for every probe: new positions from the grid positions,
+// history rejected where a probe moved more than threshold2 since the last call.
+struct RelocateArgs {
+    const float *grid_pos;      // [P][3] the grid positions (binary32)
+    float *pos;                 // [P][3] current positions: read as the last, then written
+    uint8_t *reject;            // [P] set to 1 where the probe moved too far
+    float t1, t2;               // threshold1 (distance), threshold2 (displacement)
+    int iterations;
+    float off0, off1, off2;     // (float)(max_offset * spacing) per axis
+};
+hipError_t launch_relocate(const TraceArgs &a, const RelocateArgs &r, hipStream_t stream);
 hipError_t launch_pack_mlp(const float *theta, uint4 *fwd, uint4 *bwd, float *bias,
                            hipStream_t stream);
 hipError_t launch_denoise(const DenoiseArgs &a, hipStream_t stream);

@@ -547,6 +547,41 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a) {
     if (tid < np && a.reject) a.reject[s_pid[tid]] = 0;
 }
 
+// Alg. 1 per probe: from the grid position, while the distance is below t1 (at most
+// `iterations` times) take a Newton step t1 - d along the normalised distance
+// gradient (the hit-normal rule; +y where it vanishes), each coordinate kept within
+// the offset of the grid position; stop outside every level. Then compare with the
+// last position and reject the history of a probe that moved more than t2.
+template <bool kHalf>
+__global__ __launch_bounds__(256) void relocate_kernel(TraceArgs a, RelocateArgs r) {
+    __shared__ LevelLds s_lv[kMaxLevels];
+    load_levels(a, s_lv);
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.P) return;
+    const float g0 = r.grid_pos[3 * p], g1 = r.grid_pos[3 * p + 1], g2 = r.grid_pos[3 * p + 2];
+    const float lo0 = g0 - r.off0, lo1 = g1 - r.off1, lo2 = g2 - r.off2;
+    const float hi0 = g0 + r.off0, hi1 = g1 + r.off1, hi2 = g2 + r.off2;
+    float x0 = g0, x1 = g1, x2 = g2;
+    for (int it = 0; it < r.iterations; ++it) {
+        const int L = select_level(a, x0, x1, x2);
+        if (L < 0) break;
+        const float d = sample_at<kHalf>(s_lv[L], x0, x1, x2);
+        if (!(d < r.t1)) break;
+        float n0, n1, n2;
+        hit_normal<kHalf>(s_lv[L], x0, x1, x2, 0.0f, -1.0f, 0.0f, n0, n1, n2);
+        const float step = r.t1 - d;
+        x0 = fminf(fmaxf(fmaf(step, n0, x0), lo0), hi0);
+        x1 = fminf(fmaxf(fmaf(step, n1, x1), lo1), hi1);
+        x2 = fminf(fmaxf(fmaf(step, n2, x2), lo2), hi2);
+    }
+    const float dx = x0 - r.pos[3 * p], dy = x1 - r.pos[3 * p + 1], dz = x2 - r.pos[3 * p + 2];
+    const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    if (d2 > r.t2 * r.t2) r.reject[p] = 1;
+    r.pos[3 * p] = x0;
+    r.pos[3 * p + 1] = x1;
+    r.pos[3 * p + 2] = x2;
+}
+
 // Signed distance at each probe position: the trace's own level choice and sampler.
 template <bool kHalf>
 __global__ __launch_bounds__(256) void probe_sdf_kernel(TraceArgs a, float *out) {
@@ -676,6 +711,14 @@ hipError_t launch_blend(const BlendArgs &a, hipStream_t s) {
         hipLaunchKernelGGL(blend_kernel<true>, grid, block, 0, s, a);
     else
         hipLaunchKernelGGL(blend_kernel<false>, grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_relocate(const TraceArgs &a, const RelocateArgs &r, hipStream_t s) {
+    if (a.half_sdf)
+        hipLaunchKernelGGL(relocate_kernel<true>, dim3(blocks_for(a.P, 256)), dim3(256), 0, s, a, r);
+    else
+        hipLaunchKernelGGL(relocate_kernel<false>, dim3(blocks_for(a.P, 256)), dim3(256), 0, s, a, r);
     return hipGetLastError();
 }
 

@@ -138,6 +138,7 @@ struct sdfddgi_ctx {
     int Ti = 0, Td = 0, Tpi = 0, Tpd = 0;
     int64_t irr_floats = 0, depth_floats = 0;
     float *probe_pos = nullptr;
+    float *grid_pos = nullptr;   // the grid positions (probe_pos differs after relocation)
     int *probe_order = nullptr;
     double *texel_i = nullptr, *texel_d = nullptr;
     RaySet main, low;
@@ -243,7 +244,7 @@ void free_all(sdfddgi_ctx *c) {
     }
     free_set(c->main);
     free_set(c->low);
-    dev_free(c->probe_pos); dev_free(c->probe_order); dev_free(c->texel_i); dev_free(c->texel_d);
+    dev_free(c->probe_pos); dev_free(c->grid_pos); dev_free(c->probe_order); dev_free(c->texel_i); dev_free(c->texel_d);
     dev_free(c->irr[0]); dev_free(c->irr[1]); dev_free(c->depth[0]); dev_free(c->depth[1]);
     dev_free(c->reject); dev_free(c->counter); dev_free(c->records);
     dev_free(c->u_irr); dev_free(c->u_depth);
@@ -732,11 +733,13 @@ sdfddgi_status sdfddgi_create(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_g
     hipError_t ce = hipSuccess;
     auto chk = [&](hipError_t x) { if (ce == hipSuccess) ce = x; };
     chk(dev_alloc(&c->probe_pos, 3 * P));
+    chk(dev_alloc(&c->grid_pos, 3 * P));
     chk(dev_alloc(&c->probe_order, P));
     chk(dev_alloc(&c->texel_i, 3 * c->Ti));
     chk(dev_alloc(&c->texel_d, 3 * c->Td));
     if (ce == hipSuccess) {
         chk(hipMemcpy(c->probe_pos, h_pos.data(), 3 * P * sizeof(float), hipMemcpyHostToDevice));
+        chk(hipMemcpy(c->grid_pos, h_pos.data(), 3 * P * sizeof(float), hipMemcpyHostToDevice));
         chk(hipMemcpy(c->probe_order, h_order.data(), P * sizeof(int32_t), hipMemcpyHostToDevice));
         chk(hipMemcpy(c->texel_i, h_ti.data(), 3 * c->Ti * sizeof(double), hipMemcpyHostToDevice));
         chk(hipMemcpy(c->texel_d, h_td.data(), 3 * c->Td * sizeof(double), hipMemcpyHostToDevice));
@@ -957,6 +960,42 @@ sdfddgi_status sdfddgi_get_kernel_times(sdfddgi_ctx *c, float *ms, int32_t count
     }
     for (int k = 0; k < count; ++k) ms[k] = (float)(sum[k] / frames);
     c->timed_frames = 0;
+    return SDFDDGI_OK;
+}
+
+sdfddgi_status sdfddgi_relocate_probes(sdfddgi_ctx *c, float threshold1, float threshold2,
+                                       int32_t iterations, float max_offset) {
+    sdfddgi_status st = check_ctx(c);
+    if (st != SDFDDGI_OK) return st;
+    const float v[3] = {threshold1, threshold2, max_offset};
+    if (!finite_all(v, 3) || !(threshold2 >= 0) || !(max_offset >= 0) || iterations < 0 ||
+        iterations > 1024)
+        return fail(c, SDFDDGI_EINVAL, "relocation parameters out of range");
+    RelocateArgs r{};
+    r.grid_pos = c->grid_pos;
+    r.pos = c->probe_pos;
+    r.reject = c->reject;
+    r.t1 = threshold1;
+    r.t2 = threshold2;
+    r.iterations = iterations;
+    r.off0 = (float)((double)max_offset * c->pg.spacing[0]);
+    r.off1 = (float)((double)max_offset * c->pg.spacing[1]);
+    r.off2 = (float)((double)max_offset * c->pg.spacing[2]);
+    const float l[3] = {0.0f, 1.0f, 0.0f}, rad[3] = {0.0f, 0.0f, 0.0f};
+    const TraceArgs t = trace_base(c, l, rad);
+    TRY_HIP(c, launch_relocate(t, r, c->stream), "launching relocate_kernel");
+    if (c->probe_sdf)   // the learned form's feature follows the probe
+        TRY_HIP(c, launch_probe_sdf(t, c->probe_sdf, c->stream), "launching probe_sdf_kernel");
+    return SDFDDGI_OK;
+}
+
+sdfddgi_status sdfddgi_get_probe_positions(sdfddgi_ctx *c, float *out) {
+    sdfddgi_status st = check_ctx(c);
+    if (st != SDFDDGI_OK) return st;
+    if (!out) return fail(c, SDFDDGI_EINVAL, "out is NULL");
+    TRY_HIP(c, hipMemcpyAsync(out, c->probe_pos, (size_t)c->P * 3 * sizeof(float),
+                              hipMemcpyDeviceToDevice, c->stream),
+            "copying probe positions");
     return SDFDDGI_OK;
 }
 

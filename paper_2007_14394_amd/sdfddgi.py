@@ -33,6 +33,7 @@ EXPORTED = [
     "sdfddgi_reset_history", "sdfddgi_get_payload", "sdfddgi_get_ray_records",
     "sdfddgi_get_ray_directions", "sdfddgi_ray_directions", "sdfddgi_get_kernel_times",
     "sdfddgi_get_sizes", "sdfddgi_last_error", "sdfddgi_destroy",
+    "sdfddgi_relocate_probes", "sdfddgi_get_probe_positions",
     "sdfddgi_denoiser_create", "sdfddgi_denoiser_infer", "sdfddgi_denoiser_destroy",
     "sdfddgi_update_frame_learned", "sdfddgi_get_fallback", "sdfddgi_learned_examples",
     "sdfddgi_trainer_create", "sdfddgi_trainer_gradient", "sdfddgi_trainer_step",
@@ -135,6 +136,8 @@ def load_library() -> ctypes.CDLL:
     L.sdfddgi_last_error.restype = ctypes.c_char_p
     L.sdfddgi_destroy.argtypes = [vp]
     f32 = ctypes.c_float
+    L.sdfddgi_relocate_probes.argtypes = [vp, f32, f32, i32, f32]
+    L.sdfddgi_get_probe_positions.argtypes = [vp, vp]
     L.sdfddgi_denoiser_create.argtypes = [vp, i32, f32, f32, vp, ctypes.POINTER(vp)]
     L.sdfddgi_denoiser_infer.argtypes = [vp, vp, i64, vp]
     L.sdfddgi_denoiser_destroy.argtypes = [vp]
@@ -370,6 +373,20 @@ def sdfddgi_get_kernel_times(ctx: Context):
     ms = (ctypes.c_float * n)()
     _check(ctx, load_library().sdfddgi_get_kernel_times(ctx.handle, ms, n))
     return {k: ms[i] for i, k in enumerate(KERNEL_TIMES)}
+
+
+def sdfddgi_relocate_probes(ctx: Context, threshold1: float, threshold2: float,
+                            iterations: int = 8, max_offset: float = 0.45) -> None:
+    _check(ctx, load_library().sdfddgi_relocate_probes(
+        ctx.handle, ctypes.c_float(threshold1), ctypes.c_float(threshold2),
+        ctypes.c_int32(int(iterations)), ctypes.c_float(max_offset)))
+
+
+def sdfddgi_get_probe_positions(ctx: Context):
+    import torch
+    out = torch.empty((ctx.probes, 3), dtype=torch.float32, device=ctx.device)
+    _check(ctx, load_library().sdfddgi_get_probe_positions(ctx.handle, out.data_ptr()))
+    return out
 
 
 def sdfddgi_get_sizes(ctx: Context):

@@ -1,0 +1,74 @@
+"""GPU parity of probe relocation (Alg. 1): positions and reject decisions bit-exact
+with the checker, and the next frame traced from the relocated probes, with the
+rejected histories, matching the checker."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    from paper_2007_14394_amd import sdfddgi
+    assert torch.cuda.is_available(), "GPU tests need a visible gfx950 device"
+    sdfddgi.load_library()
+    return sdfddgi
+
+
+def to_host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+@pytest.mark.parametrize("flags", [0, 4])
+def test_relocation_and_next_frame_match_checker(S, flags):
+    print(f"[gpu] relocation small_cascade flags={flags}", flush=True)
+    w = scenegen.small_cascade(0, probes=(9, 4, 8), rays=64)
+    t1, t2, iters, off = 0.6, 0.25, 8, 0.45
+    if flags:   # precision form: the checker runs on the binary16-rounded grid
+        from tests.test_gpu_parity import fp16_grid
+        w = fp16_grid(w)
+    ctx = S.context_from_workload(w, flags=flags | S.SDFDDGI_FLAG_RECORD_RAYS)
+    ck = oracle.Checker(w)
+    irr0, dep0 = scenegen.random_atlas(w.num_probes, w.params, seed=3)
+    S.sdfddgi_set_maps(ctx, to_dev(irr0), to_dev(dep0))
+    grid = ck.grid_positions()
+    S.sdfddgi_relocate_probes(ctx, t1, t2, iters, off)
+    got = to_host(S.sdfddgi_get_probe_positions(ctx))
+    pos, rej = ck.relocate_probes(grid, t1, t2, iters, off)
+    assert np.array_equal(got.view(np.int32), pos.view(np.int32))
+    moved = np.any(pos != grid, axis=1)
+    print(f"[gpu] moved {moved.sum()} of {w.num_probes}, rejected {rej.sum()}", flush=True)
+    assert moved.any() and rej.any() and not rej.all()
+    # a second call from the relocated positions moves and rejects nothing
+    S.sdfddgi_relocate_probes(ctx, t1, t2, iters, off)
+    assert np.array_equal(to_host(S.sdfddgi_get_probe_positions(ctx)).view(np.int32),
+                          pos.view(np.int32))
+    fr = w.frames[1]
+    S.sdfddgi_update_frame(ctx, fr.dir_to_light, fr.radiance_rgb, fr.rotation_seed)
+    gi, gd = S.sdfddgi_get_maps(ctx)
+    gi, gd = to_host(gi), to_host(gd)
+    rec = to_host(S.sdfddgi_get_ray_records(ctx))
+    ck.set_probe_positions(pos)
+    for reset, sel in ((True, np.nonzero(rej)[0]), (False, np.nonzero(rej == 0)[0])):
+        ri, rd, _, rr = ck.update_probes(fr, reset, irr0, dep0, probes=sel, want_records=True)
+        assert np.array_equal(rec[sel], rr)
+        if flags:
+            continue   # the precision form's maps have their own bounds (test_gpu_parity)
+        ok, worst = H.rel_close(gi[sel], ri, rel=1e-4)
+        assert ok, worst
+        ok, worst = H.rel_close(gd[sel], rd, rel=1e-4)
+        assert ok, worst

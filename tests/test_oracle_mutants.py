@@ -11,6 +11,7 @@ import pytest
 
 import oracle
 from tests import test_learned_pins as lp
+from tests import test_relocation_pins as rp
 from tests import test_oracle_pins as pins
 from tests.conftest import ROOT
 
@@ -50,6 +51,8 @@ MUTANTS = [
     ("interp_weight", "double wp = (dx ? f[0] : 1.0 - f[0]) * (dy ? f[1] : 1.0 - f[1]) *\n                            (dz ? f[2] : 1.0 - f[2]);",
      "double wp = (dx ? f[0] : 1.0 - f[0]) * (dy ? f[1] : 1.0 - f[1]) *\n                            (dz ? f[1] : 1.0 - f[1]);",
      [pins.test_interp_reproduces_fields_linear_in_position]),
+    ("relocation_step_sign", "float step = threshold1 - d;", "float step = d - threshold1;",
+     [rp.test_plane_probes_rise_to_the_threshold]),
     ("inside_ignored", "if (primary && k == 0 && d < 0.0f) {", "if (primary && k == 0 && d < -1e30f) {",
      [pins.test_miss_inside_and_exhaustion_outcomes]),
 ]
