@@ -25,7 +25,7 @@ CFLAGS = ["-O2", "-fPIC", "-shared", "-pthread", "-std=c11", "-ffp-contract=off"
           "-fno-fast-math", "-fexcess-precision=standard", "-Wall", "-Wextra"]
 
 
-SOURCES = ("oracle.c", "learned.c")
+SOURCES = ("oracle.c", "learned.c", "cluster.c")
 
 
 def build(force: bool = True, extra_cflags: Sequence[str] = (), out: Optional[str] = None,
@@ -84,6 +84,8 @@ def _load(path: str):
     L.orc_batch_index.restype = ctypes.c_int64
     L.orc_batch_index.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64]
     L.orc_probe_sdf.restype = ctypes.c_double
+    L.orc_prim_distance32.restype = ctypes.c_float
+    L.orc_brute_sdf32.restype = ctypes.c_float
     return L
 
 
@@ -430,6 +432,51 @@ def adam_step(theta, m, v, g, t: int, lr: float, beta1: float = 0.9, beta2: floa
 
 def batch_index(seed: int, i: int, count: int) -> int:
     return int(lib().orc_batch_index(seed, i, count))
+
+
+class Prims32(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("kind", ctypes.c_void_p), ("center", ctypes.c_void_p),
+                ("half", ctypes.c_void_p)]
+
+
+class AnalyticScene:
+    """Primitives rounded once to binary32, for the analytic-SDF checks."""
+
+    def __init__(self, prims):
+        self.kind = np.ascontiguousarray(prims.kind, dtype=np.int32)
+        self.center = np.ascontiguousarray(prims.center, dtype=np.float32)
+        self.half = np.ascontiguousarray(prims.half, dtype=np.float32)
+        self.s = Prims32(int(self.kind.shape[0]), self.kind.ctypes.data, self.center.ctypes.data,
+                         self.half.ctypes.data)
+
+    def prim_distance(self, m: int, x) -> float:
+        xa = (ctypes.c_float * 3)(*[float(v) for v in x])
+        return float(lib().orc_prim_distance32(ctypes.c_int32(int(self.kind[m])),
+                                               _p(self.center[m]), _p(self.half[m]), xa))
+
+    def sdf(self, points) -> np.ndarray:
+        pts = np.ascontiguousarray(points, dtype=np.float32).reshape(-1, 3)
+        out = np.zeros(pts.shape[0], dtype=np.float32)
+        for k in range(pts.shape[0]):
+            out[k] = lib().orc_brute_sdf32(ctypes.byref(self.s), _p(pts[k]), None)
+        return out
+
+    def trace(self, origins, dirs, t_max, eps, relax, max_steps):
+        """(t, steps, kind) per ray."""
+        o = np.ascontiguousarray(origins, dtype=np.float32).reshape(-1, 3)
+        w = np.ascontiguousarray(dirs, dtype=np.float32).reshape(-1, 3)
+        n = o.shape[0]
+        t = np.zeros(n, dtype=np.float32)
+        st = np.zeros(n, dtype=np.int32)
+        kd = np.zeros(n, dtype=np.int32)
+        for k in range(n):
+            tv, sv, kv = ctypes.c_float(), ctypes.c_int32(), ctypes.c_int32()
+            lib().orc_analytic_trace32(ctypes.byref(self.s), _p(o[k]), _p(w[k]),
+                                       ctypes.c_float(t_max), ctypes.c_float(eps),
+                                       ctypes.c_float(relax), ctypes.c_int32(max_steps),
+                                       ctypes.byref(tv), ctypes.byref(sv), ctypes.byref(kv))
+            t[k], st[k], kd[k] = tv.value, sv.value, kv.value
+        return t, st, kd
 
 
 def _fill_borders(tiles: np.ndarray, res: int) -> None:

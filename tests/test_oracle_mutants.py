@@ -11,6 +11,7 @@ import pytest
 
 import oracle
 from tests import test_learned_pins as lp
+from tests import test_cluster_pins as cp
 from tests import test_relocation_pins as rp
 from tests import test_oracle_pins as pins
 from tests.conftest import ROOT
@@ -61,6 +62,20 @@ MUTANTS = [
 LEARNED = os.path.join(ROOT, "oracle", "learned.c")
 
 # the learned form's checker (learned.c): same scheme
+CLUSTER = os.path.join(ROOT, "oracle", "cluster.c")
+
+# the analytic-primitive checker (cluster.c)
+CLUSTER_MUTANTS = [
+    ("box_inside_dropped", "float inside = fminf(fmaxf(qx, fmaxf(qy, qz)), 0.0f);",
+     "float inside = 0.0f * fminf(fmaxf(qx, fmaxf(qy, qz)), 0.0f);",
+     [cp.test_box_inside_distance_is_minus_the_nearest_face]),
+    ("sphere_radius_sign", "return sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx))) - h[0];",
+     "return sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx))) + h[0];",
+     [cp.test_distances_agree_with_the_binary64_baker, cp.test_trace_closed_forms]),
+    ("inside_rule_dropped", "if (k == 0 && d < 0.0f) { *kind = 4;", "if (k == 0 && d < -1e30f) { *kind = 4;",
+     [cp.test_trace_inside_and_exhaustion]),
+]
+
 LEARNED_MUTANTS = [
     ("relu_dropped_layer2", "st->h[1][k] = rnd(st->a[1][k] > 0 ? st->a[1][k] : 0, mirror);",
      "st->h[1][k] = rnd(st->a[1][k], mirror);",
@@ -92,7 +107,8 @@ def build_mutant(tmp_path, name, old, new, target=SRC):
     assert text.count(old) == 1, f"{name}: planted text not found exactly once"
     src = tmp_path / f"mutant_{name}.c"
     src.write_text(text.replace(old, new))
-    sources = [str(src), LEARNED] if target == SRC else [SRC, str(src)]
+    sources = [SRC, LEARNED, CLUSTER]
+    sources[[SRC, LEARNED, CLUSTER].index(target)] = str(src)
     # the headers sit beside the real sources
     out = tmp_path / f"liboracle_{name}.so"
     subprocess.check_call(["gcc", *oracle.CFLAGS, f"-I{os.path.dirname(SRC)}", *sources,
@@ -117,6 +133,20 @@ def test_planted_mistake_fails_a_pin(tmp_path, name, old, new, catchers):
                          ids=[m[0] for m in LEARNED_MUTANTS])
 def test_planted_mistake_in_learned_form_fails_a_pin(tmp_path, name, old, new, catchers):
     path = build_mutant(tmp_path, name, old, new, target=LEARNED)
+    with oracle.use_library(path):
+        failed = 0
+        for pin in catchers:
+            try:
+                pin()
+            except AssertionError:
+                failed += 1
+        assert failed == len(catchers), f"{name}: {len(catchers) - failed} pin(s) did not notice"
+
+
+@pytest.mark.parametrize("name,old,new,catchers", CLUSTER_MUTANTS,
+                         ids=[m[0] for m in CLUSTER_MUTANTS])
+def test_planted_mistake_in_analytic_checker_fails_a_pin(tmp_path, name, old, new, catchers):
+    path = build_mutant(tmp_path, name, old, new, target=CLUSTER)
     with oracle.use_library(path):
         failed = 0
         for pin in catchers:
