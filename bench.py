@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched form (64 uneven scenes per graph replay)")
     ap.add_argument("--batch-frames", type=int, default=30)
+    ap.add_argument("--no-analytic", action="store_true",
+                    help="skip the analytic-primitive SDF query comparison")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times "
                          "(reference reading for the HBM byte counters) and exit")
@@ -288,6 +290,48 @@ def batch_form(S, scenegen, n_frames: int, torch):
                 sequential_contexts_ms_per_frame=ms_seq, speedup_vs_sequential=ms_seq / ms)
 
 
+def analytic_sdf(S, scenegen, torch):
+    """The analytic-primitive SDF query of Sec. 3.3 on the open scene's 400
+    primitives: 64 rays from each of the 16384 probes sphere-traced with every
+    primitive evaluated (mode 0), with cluster culling (1), and with culling from
+    the previous sample's bound (2), for several cluster sizes; all give the same
+    bits (tested), so only time and primitive evaluations differ."""
+    import numpy as np
+    w = scenegen.config2(0, probes=16384, frames=1)
+    prims = w.prims
+    pg = w.probes
+    idx = np.arange(16384)
+    grid = np.stack([idx % pg.n[0], (idx // pg.n[0]) % pg.n[1], idx // (pg.n[0] * pg.n[1])], 1)
+    pos = (np.asarray(pg.origin) + np.asarray(pg.spacing) * grid).astype(np.float32)
+    R = 64
+    dirs = S.sdfddgi_ray_directions(w.frames[0].rotation_seed, R)
+    o = torch.from_numpy(np.repeat(pos, R, axis=0)).to("cuda:0")
+    d = torch.from_numpy(np.tile(dirs, (16384, 1))).to("cuda:0")
+    t_max = float(w.params.t_max)
+    out = {}
+    for cs in (4, 8, 16, 32):
+        an = S.sdfddgi_analytic_create(prims.kind, prims.center, prims.half, cs)
+        for mode in ((0, 1, 2) if cs == 8 else (1, 2)):
+            _, st, _, ev = S.sdfddgi_analytic_trace(an, o, d, t_max, mode=mode)
+            samples = int(st.sum())
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(3):
+                S.sdfddgi_analytic_trace(an, o, d, t_max, mode=mode, want_evals=False)
+            b.record()
+            torch.cuda.synchronize()
+            out[f"mode{mode}_cluster{cs}"] = dict(
+                ms=a.elapsed_time(b) / 3, prim_evals_per_sample=ev / samples,
+                clusters=an.clusters)
+        S.sdfddgi_analytic_destroy(an)
+    base = out["mode0_cluster8"]["ms"]
+    best = min((k for k in out if k.startswith("mode2")), key=lambda k: out[k]["ms"])
+    return dict(workload=f"open scene 400 primitives, 16384 probes x {R} rays, 64 steps",
+                rays=16384 * R, results=out, best=best,
+                speedup_best_vs_all_primitives=base / out[best]["ms"],
+                speedup_bound_vs_plain_culling=out["mode1_cluster8"]["ms"] / out["mode2_cluster8"]["ms"])
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -415,6 +459,8 @@ def main():
         out["learned_form"] = learned_comparison(S, lw, args.learned_frames, torch)
     if not args.no_batch:
         out["batch_form"] = batch_form(S, scenegen, args.batch_frames, torch)
+    if not args.no_analytic:
+        out["analytic_sdf"] = analytic_sdf(S, scenegen, torch)
     if args.cpu_probes > 0:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_probes)
     print(json.dumps(out), flush=True)

@@ -458,8 +458,51 @@ sdfddgi_status sdfddgi_batch_sizes(const sdfddgi_batch *b, int64_t *probes, int6
 
 sdfddgi_status sdfddgi_batch_destroy(sdfddgi_batch *b);
 
-/* Message of the last failure of a denoiser, trainer, baking or batch call on this
- * thread. */
+/* --------------------------------------------------- analytic SDF query --
+ * The SDF query of Sec. 3.3 on analytic primitives: near primitives are packed
+ * into clusters (here: primitives sorted by the Morton code of their centres,
+ * cluster_size at a time); a query visits a cluster's primitives only when the
+ * signed distance to the cluster's bounding box is below the best distance so
+ * far, starting from +inf -- or, along a sphere-traced ray, from the bound the
+ * previous sample gives: the scene distance is 1-Lipschitz, so after a step of
+ * relax*d it is at most (1 + relax)*d (the paper's 2 lastSDF), widened here by
+ * 2^-10 relative and 1e-4 to stay a bound under rounding. Bounding boxes are
+ * widened by 1e-4 (1 + the scene's largest coordinate) for the same reason.
+ * Distances are binary32 (sphere: |x - c| - r; box: outside length plus the
+ * negative largest excess inside) and the culled result equals the minimum over
+ * every primitive bit for bit. Modes: 0 every primitive, 1 clusters from +inf,
+ * 2 clusters from the previous sample's bound. */
+typedef struct sdfddgi_analytic sdfddgi_analytic;
+
+/* Primitives as host arrays (kind 0 sphere with radius half[.][0], 1 box with
+ * half extents), rounded once to binary32; 1..1024 primitives, cluster_size
+ * 1..64 (at most 256 clusters). */
+sdfddgi_status sdfddgi_analytic_create(int32_t nprims, const int32_t *kind, const double *center,
+                                       const double *half, int32_t cluster_size,
+                                       void *hip_stream, sdfddgi_analytic **out);
+
+/* Distances at n points (device [n][3] -> device [n]); *evals (host, may be NULL)
+ * = primitive distances evaluated. Waits for the stream when evals is given. */
+sdfddgi_status sdfddgi_analytic_query(sdfddgi_analytic *an, const float *points, int32_t n,
+                                      int32_t mode, float *out, int64_t *evals);
+
+/* Sphere-trace n rays (device origins and unit directions [n][3]) with the
+ * stopping rules of the probe trace without a grid box: t > t_max -> 0 (miss),
+ * d < 0 at the first sample -> 4 (inside), d < eps -> 2 (hit), max_steps samples
+ * -> 3 (hit, exhausted); step t = fma(relax, d, t). Device outputs t[n],
+ * steps[n], kind[n]; *evals as above. */
+sdfddgi_status sdfddgi_analytic_trace(sdfddgi_analytic *an, const float *origins,
+                                      const float *dirs, int32_t n, float t_max, float eps,
+                                      float relax, int32_t max_steps, int32_t mode, float *t,
+                                      int32_t *steps, int32_t *kind, int64_t *evals);
+
+/* Number of clusters (host). */
+sdfddgi_status sdfddgi_analytic_clusters(const sdfddgi_analytic *an, int32_t *count);
+
+sdfddgi_status sdfddgi_analytic_destroy(sdfddgi_analytic *an);
+
+/* Message of the last failure of a denoiser, trainer, baking, batch or analytic call
+ * on this thread. */
 const char *sdfddgi_learned_last_error(void);
 
 #ifdef __cplusplus

@@ -314,6 +314,33 @@ hipError_t launch_batch_primary(const BatchArgs &a, const BatchTuning &t, hipStr
 hipError_t launch_batch_hits(const BatchArgs &a, const BatchTuning &t, hipStream_t stream);
 hipError_t launch_batch_blend(const BatchBlendArgs &a, int nblocks, hipStream_t stream);
 int batch_max_blocks(int device, bool hits);
+
+// -------------------------------------------------- analytic SDF (cluster.hip) --
+constexpr int kMaxAnalyticPrims = 1024;
+constexpr int kMaxClusters = 256;
+
+struct AnalyticArgs {
+    int nprims, nclusters;
+    const int *kind;                 // [nprims], primitives ordered by cluster
+    const float *center, *half;      // [nprims][3] binary32
+    const float *lo, *hi;            // [nclusters][3] widened bounding boxes
+    const int *first;                // [nclusters + 1] first primitive of each cluster
+};
+
+struct AnalyticTrace {
+    int n;
+    const float *o, *w;              // [n][3] ray origins and unit directions
+    float t_max, eps, relax;
+    int max_steps, mode;             // mode 0 every primitive, 1 clusters, 2 clusters + bound
+    float *t_out;
+    int *steps_out, *kind_out;
+    unsigned long long *evals;       // primitive distance evaluations (may be null)
+};
+
+hipError_t launch_cluster_query(const AnalyticArgs &a, const float *pts, int n, int mode,
+                                float *out, unsigned long long *evals, hipStream_t stream);
+hipError_t launch_cluster_trace(const AnalyticArgs &a, const AnalyticTrace &r,
+                                hipStream_t stream);
 bool batch_chunk_supported(int chunk, bool hits);
 
 }  // namespace sdfddgi

@@ -2050,3 +2050,199 @@ sdfddgi_status sdfddgi_batch_sizes(const sdfddgi_batch *b, int64_t *probes, int6
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------ analytic SDF --
+
+struct sdfddgi_analytic {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int nprims = 0, nclusters = 0;
+    int *kind = nullptr, *first = nullptr;
+    float *center = nullptr, *half = nullptr, *lo = nullptr, *hi = nullptr;
+    unsigned long long *evals = nullptr;
+};
+
+extern "C" {
+
+sdfddgi_status sdfddgi_analytic_destroy(sdfddgi_analytic *an) {
+    if (!an) return SDFDDGI_OK;
+    (void)hipSetDevice(an->device);
+    (void)hipStreamSynchronize(an->stream);
+    dev_free(an->kind); dev_free(an->first); dev_free(an->center); dev_free(an->half);
+    dev_free(an->lo); dev_free(an->hi); dev_free(an->evals);
+    delete an;
+    return SDFDDGI_OK;
+}
+
+sdfddgi_status sdfddgi_analytic_create(int32_t nprims, const int32_t *kind, const double *center,
+                                       const double *half, int32_t cluster_size,
+                                       void *hip_stream, sdfddgi_analytic **out) {
+    g_learned_error.clear();
+    if (!out) return lfail(SDFDDGI_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (nprims < 1 || nprims > kMaxAnalyticPrims || !kind || !center || !half)
+        return lfail(SDFDDGI_EINVAL, "need 1..%d primitives", kMaxAnalyticPrims);
+    if (cluster_size < 1 || cluster_size > 64)
+        return lfail(SDFDDGI_EINVAL, "cluster_size must be in 1..64");
+    const int nclusters = (nprims + cluster_size - 1) / cluster_size;
+    if (nclusters > kMaxClusters)
+        return lfail(SDFDDGI_EINVAL, "more than %d clusters", kMaxClusters);
+    double lo_s[3] = {INFINITY, INFINITY, INFINITY}, hi_s[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double reach = 0.0;
+    for (int m = 0; m < nprims; ++m) {
+        if (kind[m] != 0 && kind[m] != 1) return lfail(SDFDDGI_EINVAL, "primitive kind %d", kind[m]);
+        for (int c = 0; c < 3; ++c) {
+            const double h = kind[m] == 0 ? half[3 * m] : half[3 * m + c];
+            if (!std::isfinite(center[3 * m + c]) || !std::isfinite(h) || h < 0)
+                return lfail(SDFDDGI_EINVAL, "primitive %d: bad centre or size", m);
+            lo_s[c] = std::min(lo_s[c], center[3 * m + c]);
+            hi_s[c] = std::max(hi_s[c], center[3 * m + c]);
+            reach = std::max(reach, std::fabs(center[3 * m + c]) + h);
+        }
+    }
+    (void)hipGetLastError();
+    // clusters: primitives in Morton order of their centres, cluster_size at a time
+    std::vector<std::pair<uint64_t, int>> order((size_t)nprims);
+    for (int m = 0; m < nprims; ++m) {
+        uint64_t code = 0;
+        for (int c = 0; c < 3; ++c) {
+            const double ext = hi_s[c] - lo_s[c];
+            const double u = ext > 0 ? (center[3 * m + c] - lo_s[c]) / ext : 0.0;
+            const uint64_t q = (uint64_t)std::min(1023.0, std::max(0.0, std::floor(u * 1024.0)));
+            for (int bit = 0; bit < 10; ++bit) code |= ((q >> bit) & 1ull) << (3 * bit + c);
+        }
+        order[(size_t)m] = {code, m};
+    }
+    std::sort(order.begin(), order.end());
+    std::vector<int> h_kind(nprims), h_first(nclusters + 1);
+    std::vector<float> h_cen(3 * (size_t)nprims), h_half(3 * (size_t)nprims);
+    std::vector<float> h_lo(3 * (size_t)nclusters), h_hi(3 * (size_t)nclusters);
+    const double widen = 1e-4 * (1.0 + reach);
+    for (int k = 0; k < nclusters; ++k) {
+        h_first[k] = k * cluster_size;
+        double blo[3] = {INFINITY, INFINITY, INFINITY}, bhi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int j = k * cluster_size; j < std::min(nprims, (k + 1) * cluster_size); ++j) {
+            const int m = order[(size_t)j].second;
+            h_kind[j] = kind[m];
+            for (int c = 0; c < 3; ++c) {
+                const double h = kind[m] == 0 ? half[3 * m] : half[3 * m + c];
+                h_cen[3 * j + c] = (float)center[3 * m + c];
+                h_half[3 * j + c] = (float)half[3 * m + c];
+                blo[c] = std::min(blo[c], center[3 * m + c] - h);
+                bhi[c] = std::max(bhi[c], center[3 * m + c] + h);
+            }
+        }
+        for (int c = 0; c < 3; ++c) {   // widened, then rounded outward
+            h_lo[3 * k + c] = std::nextafter((float)(blo[c] - widen), -INFINITY);
+            h_hi[3 * k + c] = std::nextafter((float)(bhi[c] + widen), INFINITY);
+        }
+    }
+    h_first[nclusters] = nprims;
+    sdfddgi_analytic *an = new (std::nothrow) sdfddgi_analytic();
+    if (!an) return lfail(SDFDDGI_ENOMEM, "host allocation failed");
+    hipError_t e = hipGetDevice(&an->device);
+    an->stream = (hipStream_t)hip_stream;
+    an->nprims = nprims;
+    an->nclusters = nclusters;
+    auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+    chk(dev_alloc(&an->kind, nprims));
+    chk(dev_alloc(&an->first, nclusters + 1));
+    chk(dev_alloc(&an->center, 3 * (size_t)nprims));
+    chk(dev_alloc(&an->half, 3 * (size_t)nprims));
+    chk(dev_alloc(&an->lo, 3 * (size_t)nclusters));
+    chk(dev_alloc(&an->hi, 3 * (size_t)nclusters));
+    chk(dev_alloc(&an->evals, 1));
+    if (e == hipSuccess) {
+        chk(hipMemcpy(an->kind, h_kind.data(), nprims * sizeof(int), hipMemcpyHostToDevice));
+        chk(hipMemcpy(an->first, h_first.data(), (nclusters + 1) * sizeof(int), hipMemcpyHostToDevice));
+        chk(hipMemcpy(an->center, h_cen.data(), h_cen.size() * sizeof(float), hipMemcpyHostToDevice));
+        chk(hipMemcpy(an->half, h_half.data(), h_half.size() * sizeof(float), hipMemcpyHostToDevice));
+        chk(hipMemcpy(an->lo, h_lo.data(), h_lo.size() * sizeof(float), hipMemcpyHostToDevice));
+        chk(hipMemcpy(an->hi, h_hi.data(), h_hi.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+    if (e != hipSuccess) {
+        sdfddgi_analytic_destroy(an);
+        return lhip_fail(e, "creating the analytic scene");
+    }
+    *out = an;
+    return SDFDDGI_OK;
+}
+
+static AnalyticArgs analytic_args(const sdfddgi_analytic *an) {
+    AnalyticArgs a{};
+    a.nprims = an->nprims;
+    a.nclusters = an->nclusters;
+    a.kind = an->kind;
+    a.center = an->center;
+    a.half = an->half;
+    a.lo = an->lo;
+    a.hi = an->hi;
+    a.first = an->first;
+    return a;
+}
+
+static hipError_t read_evals(sdfddgi_analytic *an, int64_t *evals) {
+    unsigned long long v = 0;
+    hipError_t e = hipMemcpyAsync(&v, an->evals, sizeof v, hipMemcpyDeviceToHost, an->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(an->stream);
+    *evals = (int64_t)v;
+    return e;
+}
+
+sdfddgi_status sdfddgi_analytic_query(sdfddgi_analytic *an, const float *points, int32_t n,
+                                      int32_t mode, float *out, int64_t *evals) {
+    g_learned_error.clear();
+    if (!an || n < 0 || mode < 0 || mode > 1 || (n > 0 && (!points || !out)))
+        return lfail(SDFDDGI_EINVAL, "bad argument (query modes are 0 and 1)");
+    (void)hipGetLastError();
+    hipError_t e = hipSetDevice(an->device);
+    // two binary32 zeros clear the 64-bit evaluation counter
+    if (e == hipSuccess && evals) e = launch_zero_f32(reinterpret_cast<float *>(an->evals), 2, an->stream);
+    if (e == hipSuccess)
+        e = launch_cluster_query(analytic_args(an), points, n, mode, out, evals ? an->evals : nullptr,
+                                 an->stream);
+    if (e == hipSuccess && evals) e = read_evals(an, evals);
+    if (e != hipSuccess) return lhip_fail(e, "analytic query");
+    return SDFDDGI_OK;
+}
+
+sdfddgi_status sdfddgi_analytic_trace(sdfddgi_analytic *an, const float *origins,
+                                      const float *dirs, int32_t n, float t_max, float eps,
+                                      float relax, int32_t max_steps, int32_t mode, float *t,
+                                      int32_t *steps, int32_t *kind, int64_t *evals) {
+    g_learned_error.clear();
+    if (!an || n < 0 || mode < 0 || mode > 2 || (n > 0 && (!origins || !dirs || !t || !steps || !kind)))
+        return lfail(SDFDDGI_EINVAL, "bad argument");
+    const float v[3] = {t_max, eps, relax};
+    if (!finite_all(v, 3) || !(t_max > 0) || !(eps > 0) || !(relax > 0 && relax <= 2) ||
+        max_steps < 1 || max_steps > 4096)
+        return lfail(SDFDDGI_EINVAL, "trace parameters out of range");
+    (void)hipGetLastError();
+    hipError_t e = hipSetDevice(an->device);
+    if (e == hipSuccess && evals) e = launch_zero_f32(reinterpret_cast<float *>(an->evals), 2, an->stream);
+    AnalyticTrace r{};
+    r.n = n;
+    r.o = origins;
+    r.w = dirs;
+    r.t_max = t_max;
+    r.eps = eps;
+    r.relax = relax;
+    r.max_steps = max_steps;
+    r.mode = mode;
+    r.t_out = t;
+    r.steps_out = steps;
+    r.kind_out = kind;
+    r.evals = evals ? an->evals : nullptr;
+    if (e == hipSuccess) e = launch_cluster_trace(analytic_args(an), r, an->stream);
+    if (e == hipSuccess && evals) e = read_evals(an, evals);
+    if (e != hipSuccess) return lhip_fail(e, "analytic trace");
+    return SDFDDGI_OK;
+}
+
+sdfddgi_status sdfddgi_analytic_clusters(const sdfddgi_analytic *an, int32_t *count) {
+    if (!an || !count) return SDFDDGI_EINVAL;
+    *count = an->nclusters;
+    return SDFDDGI_OK;
+}
+
+}  // extern "C"

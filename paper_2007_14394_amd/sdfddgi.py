@@ -41,6 +41,8 @@ EXPORTED = [
     "sdfddgi_bake_sdf", "sdfddgi_batch_create", "sdfddgi_batch_update_frame",
     "sdfddgi_batch_autotune", "sdfddgi_batch_set_tuning", "sdfddgi_batch_get_maps",
     "sdfddgi_batch_scene_latency", "sdfddgi_batch_sizes", "sdfddgi_batch_destroy",
+    "sdfddgi_analytic_create", "sdfddgi_analytic_query", "sdfddgi_analytic_trace",
+    "sdfddgi_analytic_clusters", "sdfddgi_analytic_destroy",
 ]
 SDFDDGI_MAX_BATCH_SCENES = 64
 SDFDDGI_DENOISER_PARAMS = 9604
@@ -163,6 +165,12 @@ def load_library() -> ctypes.CDLL:
     L.sdfddgi_batch_scene_latency.argtypes = [vp, vp, vp]
     L.sdfddgi_batch_sizes.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.sdfddgi_batch_destroy.argtypes = [vp]
+    L.sdfddgi_analytic_create.argtypes = [i32, vp, vp, vp, i32, vp, ctypes.POINTER(vp)]
+    L.sdfddgi_analytic_query.argtypes = [vp, vp, i32, i32, vp, ctypes.POINTER(i64)]
+    L.sdfddgi_analytic_trace.argtypes = [vp, vp, vp, i32, f32, f32, f32, i32, i32, vp, vp, vp,
+                                         ctypes.POINTER(i64)]
+    L.sdfddgi_analytic_clusters.argtypes = [vp, ctypes.POINTER(i32)]
+    L.sdfddgi_analytic_destroy.argtypes = [vp]
     L.sdfddgi_learned_last_error.argtypes = []
     L.sdfddgi_learned_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -755,6 +763,76 @@ def batch_from_specs(specs, baked=None, stream=None, device="cuda:0") -> Batch:
                            probe_n=sp.probes.n, probe_origin=sp.probes.origin,
                            probe_spacing=sp.probes.spacing, params=params_from(sp.params)))
     return sdfddgi_batch_create(scenes, stream)
+
+
+class Analytic:
+    def __init__(self, handle: int, device, clusters: int):
+        self.handle = ctypes.c_void_p(handle)
+        self.device = device
+        self.clusters = clusters
+
+    def __del__(self):
+        try:
+            if self.handle and self.handle.value:
+                load_library().sdfddgi_analytic_destroy(self.handle)
+                self.handle = ctypes.c_void_p(0)
+        except Exception:
+            pass
+
+
+def sdfddgi_analytic_create(kind, center, half, cluster_size: int = 8, device="cuda:0",
+                            stream=None) -> Analytic:
+    import torch
+    kind = np.ascontiguousarray(kind, dtype=np.int32).reshape(-1)
+    m = kind.shape[0]
+    cen = np.ascontiguousarray(center, dtype=np.float64).reshape(m, 3)
+    hal = np.ascontiguousarray(half, dtype=np.float64).reshape(m, 3)
+    dev = torch.device(device)
+    out = ctypes.c_void_p()
+    P = ctypes.c_void_p
+    with torch.cuda.device(dev):
+        _lcheck(load_library().sdfddgi_analytic_create(
+            ctypes.c_int32(m), P(kind.ctypes.data), P(cen.ctypes.data), P(hal.ctypes.data),
+            ctypes.c_int32(cluster_size), P(_stream_handle(stream)), ctypes.byref(out)))
+    n = ctypes.c_int32()
+    load_library().sdfddgi_analytic_clusters(out, ctypes.byref(n))
+    return Analytic(out.value, dev, n.value)
+
+
+def sdfddgi_analytic_query(an: Analytic, points, mode: int = 1):
+    """(distances [n], primitive evaluations)."""
+    import torch
+    n = int(points.shape[0])
+    out = torch.empty(n, dtype=torch.float32, device=an.device)
+    ev = ctypes.c_int64()
+    _lcheck(load_library().sdfddgi_analytic_query(
+        an.handle, _dev_ptr(points, torch.float32, "points", an.device) if n else None,
+        ctypes.c_int32(n), ctypes.c_int32(mode), out.data_ptr() if n else None, ctypes.byref(ev)))
+    return out, ev.value
+
+
+def sdfddgi_analytic_trace(an: Analytic, origins, dirs, t_max: float, eps: float = 1e-3,
+                           relax: float = 1.0, max_steps: int = 64, mode: int = 2,
+                           want_evals: bool = True):
+    """(t [n], steps [n], kind [n], primitive evaluations or None)."""
+    import torch
+    n = int(origins.shape[0])
+    t = torch.empty(n, dtype=torch.float32, device=an.device)
+    st = torch.empty(n, dtype=torch.int32, device=an.device)
+    kd = torch.empty(n, dtype=torch.int32, device=an.device)
+    ev = ctypes.c_int64()
+    _lcheck(load_library().sdfddgi_analytic_trace(
+        an.handle, _dev_ptr(origins, torch.float32, "origins", an.device),
+        _dev_ptr(dirs, torch.float32, "dirs", an.device), ctypes.c_int32(n), ctypes.c_float(t_max),
+        ctypes.c_float(eps), ctypes.c_float(relax), ctypes.c_int32(max_steps), ctypes.c_int32(mode),
+        t.data_ptr(), st.data_ptr(), kd.data_ptr(), ctypes.byref(ev) if want_evals else None))
+    return t, st, kd, (ev.value if want_evals else None)
+
+
+def sdfddgi_analytic_destroy(an: Analytic) -> None:
+    if an.handle and an.handle.value:
+        _lcheck(load_library().sdfddgi_analytic_destroy(an.handle))
+        an.handle = ctypes.c_void_p(0)
 
 
 def sdfddgi_learned_last_error() -> str:
