@@ -70,8 +70,13 @@
  *     pointer owned by the caller and only read/written during the call's
  *     stream-ordered work; sdfddgi_create copies the grids into memory the
  *     context owns, so the caller may free them once create returns.
- *   - All GPU work goes on the stream given to sdfddgi_create, in order, and is
+ *   - GPU work goes on the stream given to sdfddgi_create, in order, and is
  *     asynchronous: results are valid once the caller synchronises that stream.
+ *     The one exception is internal: back-to-back sdfddgi_update_frame calls
+ *     run each frame's tables and primary trace on a side stream of the context
+ *     (default priority), overlapping the previous frame's hit shading and
+ *     blend, and join it back into the caller's stream before the frame's hit
+ *     shading -- so the rule above still holds for every result.
  *   - Status codes only; nothing is thrown across the ABI. A failed call leaves
  *     the context's maps as they were. sdfddgi_last_error gives the message.
  *   - A context is used by one host thread at a time (no internal locking).
@@ -176,7 +181,10 @@ sdfddgi_status sdfddgi_create(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_g
 
 /* One frame of the probe update of Sec. 3.3 for every probe (steps 1-5
  * above). Reads the current maps as the previous frame, writes the other
- * buffer pair, then makes it current. Clears every probe's reject flag. */
+ * buffer pair, then makes it current. Clears every probe's reject flag.
+ * Consecutive calls with no other call on the context in between overlap (see
+ * the stream convention above); the results are the same as one at a time.
+ * A context created with SDFDDGI_FLAG_RECORD_RAYS never overlaps frames. */
 sdfddgi_status sdfddgi_update_frame(sdfddgi_ctx *ctx, const sdfddgi_light *light,
                                     uint64_t rotation_seed);
 

@@ -26,7 +26,7 @@ thread_local std::string g_create_error;
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kTimingRing = 256;
-constexpr int kEvents = 8;
+constexpr int kEvents = 9;
 
 // ---------------------------------------------------------- frame constants --
 
@@ -114,6 +114,7 @@ struct RaySet {
     __bf16 *w16_d = nullptr;
     float4 *payload = nullptr;       // [P][R]
     int4 *hitq = nullptr;            // [P][R]
+    int *counter = nullptr;          // [3] counters of a plain frame's trace (see TraceArgs)
     TraceGrid grid;
 };
 
@@ -141,7 +142,19 @@ struct sdfddgi_ctx {
     float *grid_pos = nullptr;   // the grid positions (probe_pos differs after relocation)
     int *probe_order = nullptr;
     double *texel_i = nullptr, *texel_d = nullptr;
-    RaySet main, low;
+    // main: the ray set of the last plain frame; spare: the one the next plain frame
+    // traces into while the last one's hit shading and blend may still run
+    RaySet main, spare, low;
+    // Plain frames are pipelined: the tables and primary trace of frame f run on the
+    // side stream and may overlap frame f-1's hit shading and blend on the caller's
+    // stream (the primary trace reads neither the atlas nor anything frame f-1
+    // writes). ev_gate, recorded on the caller's stream just before a frame's hit
+    // shading, is what the next frame's side work waits for; ev_primary joins the
+    // side stream back. Any other call in between makes the next frame wait for
+    // everything before it (serialize_next).
+    hipStream_t side = nullptr;
+    hipEvent_t ev_gate = nullptr, ev_primary = nullptr, ev_tail = nullptr;
+    bool serialize_next = true;
     float *irr[2]{}, *depth[2]{};
     int cur = 0;
     uint8_t *reject = nullptr;
@@ -233,7 +246,7 @@ void dev_free(T *&p) {
 void free_set(RaySet &r) {
     dev_free(r.base); dev_free(r.dirs); dev_free(r.wt_i); dev_free(r.wt_d);
     dev_free(r.norm_i); dev_free(r.norm_d); dev_free(r.w16_i); dev_free(r.w16_d);
-    dev_free(r.payload); dev_free(r.hitq);
+    dev_free(r.payload); dev_free(r.hitq); dev_free(r.counter);
     r.R = r.Rpad = 0;
 }
 
@@ -243,7 +256,12 @@ void free_all(sdfddgi_ctx *c) {
         dev_free(c->alb[L]);
     }
     free_set(c->main);
+    free_set(c->spare);
     free_set(c->low);
+    if (c->ev_gate) (void)hipEventDestroy(c->ev_gate);
+    if (c->ev_primary) (void)hipEventDestroy(c->ev_primary);
+    if (c->ev_tail) (void)hipEventDestroy(c->ev_tail);
+    if (c->side) (void)hipStreamDestroy(c->side);
     dev_free(c->probe_pos); dev_free(c->grid_pos); dev_free(c->probe_order); dev_free(c->texel_i); dev_free(c->texel_d);
     dev_free(c->irr[0]); dev_free(c->irr[1]); dev_free(c->depth[0]); dev_free(c->depth[1]);
     dev_free(c->reject); dev_free(c->counter); dev_free(c->records);
@@ -433,6 +451,7 @@ hipError_t alloc_set(sdfddgi_ctx *c, RaySet &r, int R) {
     chk(dev_alloc(&r.norm_d, c->Td));
     chk(dev_alloc(&r.payload, (size_t)c->P * R));
     chk(dev_alloc(&r.hitq, (size_t)c->P * R));
+    chk(dev_alloc(&r.counter, 3));
     if (e != hipSuccess) return e;
     chk(hipMemcpy(r.base, h_base.data(), 3 * (size_t)R * sizeof(double), hipMemcpyHostToDevice));
     chk(hipMemsetAsync(r.wt_i, 0, (size_t)R * c->Tpi * sizeof(float), c->stream));
@@ -449,7 +468,8 @@ hipError_t alloc_set(sdfddgi_ctx *c, RaySet &r, int R) {
     return e;
 }
 
-TableArgs table_args(const sdfddgi_ctx *c, const RaySet &r, uint64_t seed, int ncounter) {
+TableArgs table_args(const sdfddgi_ctx *c, const RaySet &r, uint64_t seed, int ncounter,
+                     int *counter = nullptr) {
     TableArgs t{};
     t.R = r.R;
     t.Ti = c->Ti;
@@ -466,7 +486,7 @@ TableArgs table_args(const sdfddgi_ctx *c, const RaySet &r, uint64_t seed, int n
     t.wt_d = r.wt_d;
     t.norm_i = r.norm_i;
     t.norm_d = r.norm_d;
-    t.counter = ncounter > 0 ? c->counter : nullptr;
+    t.counter = ncounter > 0 ? (counter ? counter : c->counter) : nullptr;
     t.ncounter = ncounter;
     t.Rpad = r.Rpad;
     t.w16_i = r.w16_i;
@@ -554,6 +574,8 @@ sdfddgi_status check_ctx(sdfddgi_ctx *c) {
     c->err.clear();
     // launch status is read with hipGetLastError: drop a failure some other code left
     (void)hipGetLastError();
+    // the next plain frame waits for whatever this call enqueues
+    c->serialize_next = true;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
     return SDFDDGI_OK;
@@ -577,12 +599,16 @@ sdfddgi_status light_of(sdfddgi_ctx *c, const sdfddgi_light *light, float l[3], 
     return SDFDDGI_OK;
 }
 
-// Timing events of one frame: [0] start, [1] tables, [2] primary, [3] hits,
-// [4] blend, [5] denoiser, [6] fallback trace, [7] fallback blend.
+// Timing events of one frame, each recorded when its step is done: [0] start,
+// [1] tables, [2] primary trace, [3] hit shading may start, [4] hit shading,
+// [5] blend, [6] denoiser, [7] fallback trace, [8] fallback blend.
 struct FrameEvents {
     hipEvent_t *ev = nullptr;
     hipStream_t s = nullptr;
-    hipError_t mark(int k) { return ev ? hipEventRecord(ev[k], s) : hipSuccess; }
+    hipError_t mark(int k) { return mark_on(k, s); }
+    hipError_t mark_on(int k, hipStream_t on) {
+        return ev ? hipEventRecord(ev[k], on) : hipSuccess;
+    }
 };
 
 FrameEvents frame_events(sdfddgi_ctx *c) {
@@ -747,6 +773,11 @@ sdfddgi_status sdfddgi_create(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_g
     SDF_TRY(ce, "uploading constants");
 
     SDF_TRY(alloc_set(c, c->main, params->rays_per_probe), "allocating the ray set");
+    SDF_TRY(alloc_set(c, c->spare, params->rays_per_probe), "allocating the ray set");
+    SDF_TRY(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking), "creating a stream");
+    SDF_TRY(hipEventCreateWithFlags(&c->ev_gate, hipEventDisableTiming), "creating events");
+    SDF_TRY(hipEventCreateWithFlags(&c->ev_primary, hipEventDisableTiming), "creating events");
+    SDF_TRY(hipEventCreateWithFlags(&c->ev_tail, hipEventDisableTiming), "creating events");
     for (int k = 0; k < 2; ++k) {
         SDF_TRY(dev_alloc(&c->irr[k], c->irr_floats), "allocating irradiance atlas");
         SDF_TRY(dev_alloc(&c->depth[k], c->depth_floats), "allocating depth atlas");
@@ -791,32 +822,54 @@ sdfddgi_status sdfddgi_create(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_g
 
 sdfddgi_status sdfddgi_update_frame(sdfddgi_ctx *c, const sdfddgi_light *light,
                                     uint64_t rotation_seed) {
+    // overlap with the previous frame only when nothing else came in between and no
+    // per-ray records are kept (they are one buffer for both frames)
+    const bool serial = !c || c->serialize_next || c->records;
     sdfddgi_status st = check_ctx(c);
     if (st != SDFDDGI_OK) return st;
     float l[3], rad[3];
     if ((st = light_of(c, light, l, rad)) != SDFDDGI_OK) return st;
-    const TraceArgs t = trace_pass(trace_base(c, l, rad), c->main, c->counter, nullptr, nullptr,
+    RaySet &r = c->spare;  // becomes main once every launch has gone in
+    const TraceArgs t = trace_pass(trace_base(c, l, rad), r, r.counter, nullptr, nullptr,
                                    c->records);
     FrameEvents ev = frame_events(c);
     const int nxt = 1 - c->cur;
-    TRY_HIP(c, ev.mark(0), "event");
-    TRY_HIP(c, launch_tables(table_args(c, c->main, rotation_seed, 3), c->stream),
+    // side stream: tables and primary trace. This set was last used by the frame
+    // before the previous one, whose hit shading and blend ran on the caller's stream
+    // before the previous frame's gate; so wait for that gate, or, when serial, for
+    // everything enqueued so far
+    if (serial) {
+        TRY_HIP(c, hipEventRecord(c->ev_tail, c->stream), "event");
+        TRY_HIP(c, hipStreamWaitEvent(c->side, c->ev_tail, 0), "stream wait");
+    } else {
+        TRY_HIP(c, hipStreamWaitEvent(c->side, c->ev_gate, 0), "stream wait");
+    }
+    TRY_HIP(c, ev.mark_on(0, c->side), "event");
+    TRY_HIP(c, launch_tables(table_args(c, r, rotation_seed, 3, r.counter), c->side),
             "launching tables_kernel");
-    TRY_HIP(c, ev.mark(1), "event");
-    TRY_HIP(c, launch_primary(t, c->main.grid, c->stream), "launching primary_kernel");
-    TRY_HIP(c, ev.mark(2), "event");
-    TRY_HIP(c, launch_hits(t, c->main.grid, c->stream), "launching hits_kernel");
+    TRY_HIP(c, ev.mark_on(1, c->side), "event");
+    TRY_HIP(c, launch_primary(t, r.grid, c->side), "launching primary_kernel");
+    TRY_HIP(c, ev.mark_on(2, c->side), "event");
+    TRY_HIP(c, hipEventRecord(c->ev_primary, c->side), "event");
+    // caller's stream: hit shading (reads the previous atlas, so after the previous
+    // frame's blend) and blend
+    TRY_HIP(c, hipStreamWaitEvent(c->stream, c->ev_primary, 0), "stream wait");
+    TRY_HIP(c, hipEventRecord(c->ev_gate, c->stream), "event");
     TRY_HIP(c, ev.mark(3), "event");
-    TRY_HIP(c, launch_blend(blend_args(c, c->main, c->main.payload, c->prm.hysteresis,
-                                       c->irr[c->cur], c->depth[c->cur], c->irr[nxt],
-                                       c->depth[nxt], c->reject, nullptr, nullptr),
+    TRY_HIP(c, launch_hits(t, r.grid, c->stream), "launching hits_kernel");
+    TRY_HIP(c, ev.mark(4), "event");
+    TRY_HIP(c, launch_blend(blend_args(c, r, r.payload, c->prm.hysteresis, c->irr[c->cur],
+                                       c->depth[c->cur], c->irr[nxt], c->depth[nxt], c->reject,
+                                       nullptr, nullptr),
                             c->stream),
             "launching blend_kernel");
-    for (int k = 4; k < kEvents; ++k) TRY_HIP(c, ev.mark(k), "event");
+    for (int k = 5; k < kEvents; ++k) TRY_HIP(c, ev.mark(k), "event");
     frame_done(c);
+    std::swap(c->main, c->spare);
     c->cur = nxt;
     c->have_frame = true;
     c->have_records = c->records != nullptr;
+    c->serialize_next = false;
     return SDFDDGI_OK;
 }
 
@@ -939,7 +992,7 @@ sdfddgi_status sdfddgi_ray_directions(uint64_t rotation_seed, int32_t rays, floa
 sdfddgi_status sdfddgi_get_kernel_times(sdfddgi_ctx *c, float *ms, int32_t count) {
     sdfddgi_status st = check_ctx(c);
     if (st != SDFDDGI_OK) return st;
-    if (!ms || count < 0 || count > kEvents) return fail(c, SDFDDGI_EINVAL, "bad output array");
+    if (!ms || count < 0 || count > 8) return fail(c, SDFDDGI_EINVAL, "bad output array");
     if (!c->ev_ring) return fail(c, SDFDDGI_ESTATE, "created without SDFDDGI_FLAG_TIMING");
     if (c->timed_frames == 0) return fail(c, SDFDDGI_ESTATE, "no timed frame since the last call");
     const int frames = (int)(c->timed_frames < kTimingRing ? c->timed_frames : kTimingRing);
@@ -947,11 +1000,12 @@ sdfddgi_status sdfddgi_get_kernel_times(sdfddgi_ctx *c, float *ms, int32_t count
     TRY_HIP(c, hipEventSynchronize(c->ev_ring[kEvents * last + kEvents - 1]),
             "hipEventSynchronize");
     // tables, primary, hits, blend, frame, denoiser, fallback trace, fallback blend
-    const int pairs[kEvents][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {0, 7}, {4, 5}, {5, 6}, {6, 7}};
-    double sum[kEvents] = {0, 0, 0, 0, 0, 0, 0, 0};
+    constexpr int kTimes = 8;
+    const int pairs[kTimes][2] = {{0, 1}, {1, 2}, {3, 4}, {4, 5}, {0, 8}, {5, 6}, {6, 7}, {7, 8}};
+    double sum[kTimes] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int f = 0; f < frames; ++f) {
         const hipEvent_t *ev = c->ev_ring + kEvents * ((last - f + kTimingRing) % kTimingRing);
-        for (int k = 0; k < kEvents; ++k) {
+        for (int k = 0; k < kTimes; ++k) {
             float v = 0.0f;
             TRY_HIP(c, hipEventElapsedTime(&v, ev[pairs[k][0]], ev[pairs[k][1]]),
                     "hipEventElapsedTime");
@@ -1017,6 +1071,7 @@ sdfddgi_status sdfddgi_destroy(sdfddgi_ctx *c) {
     if (!c) return SDFDDGI_OK;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
+    if (c->side) (void)hipStreamSynchronize(c->side);
     free_all(c);
     delete c;
     return SDFDDGI_OK;
@@ -1131,14 +1186,15 @@ sdfddgi_status sdfddgi_update_frame_learned(sdfddgi_ctx *c, const sdfddgi_denois
     const TraceArgs tl = trace_pass(base, c->low, c->counter, nullptr, nullptr, nullptr);
     TRY_HIP(c, launch_primary(tl, c->low.grid, c->stream), "launching primary_kernel");
     TRY_HIP(c, ev.mark(2), "event");
-    TRY_HIP(c, launch_hits(tl, c->low.grid, c->stream), "launching hits_kernel");
     TRY_HIP(c, ev.mark(3), "event");
+    TRY_HIP(c, launch_hits(tl, c->low.grid, c->stream), "launching hits_kernel");
+    TRY_HIP(c, ev.mark(4), "event");
     TRY_HIP(c, launch_blend(blend_args(c, c->low, c->low.payload, 0.0f, c->irr[c->cur],
                                        c->depth[c->cur], c->u_irr, c->u_depth, nullptr, nullptr,
                                        nullptr),
                             c->stream),
             "launching blend_kernel");
-    TRY_HIP(c, ev.mark(4), "event");
+    TRY_HIP(c, ev.mark(5), "event");
     // network, decision, accepted probes' maps, fallback list
     DenoiseArgs da{};
     da.f = feature_args(c, d);
@@ -1155,18 +1211,18 @@ sdfddgi_status sdfddgi_update_frame_learned(sdfddgi_ctx *c, const sdfddgi_denois
     da.fallback_count = fb_count;
     da.mean_error = c->mean_error;
     TRY_HIP(c, launch_denoise(da, c->stream), "launching denoise_kernel");
-    TRY_HIP(c, ev.mark(5), "event");
+    TRY_HIP(c, ev.mark(6), "event");
     // plain update of the fallback probes
     const TraceArgs tf = trace_pass(base, c->main, c->counter + 3, c->fallback, fb_count, nullptr);
     TRY_HIP(c, launch_primary(tf, c->main.grid, c->stream), "launching primary_kernel");
     TRY_HIP(c, launch_hits(tf, c->main.grid, c->stream), "launching hits_kernel");
-    TRY_HIP(c, ev.mark(6), "event");
+    TRY_HIP(c, ev.mark(7), "event");
     TRY_HIP(c, launch_blend(blend_args(c, c->main, c->main.payload, c->prm.hysteresis,
                                        c->irr[c->cur], c->depth[c->cur], c->irr[nxt],
                                        c->depth[nxt], c->reject, c->fallback, fb_count),
                             c->stream),
             "launching blend_kernel");
-    TRY_HIP(c, ev.mark(7), "event");
+    TRY_HIP(c, ev.mark(8), "event");
     frame_done(c);
     c->cur = nxt;
     c->have_learned = true;

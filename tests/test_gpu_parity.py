@@ -294,6 +294,32 @@ def test_error_paths_leave_state_untouched(S):
     S.sdfddgi_destroy(ctx)
 
 
+def test_pipelined_frames_match_frames_run_one_at_a_time(S):
+    """Back-to-back plain frames overlap: the tables and primary trace of frame f run on
+    a side stream while frame f-1's hit shading and blend finish. A context that keeps
+    per-ray records never overlaps frames; both must give bit-identical maps and payload,
+    frame after frame, and so must a context whose frames are separated by other calls."""
+    import torch
+    w = scenegen.config2(0, probes=8192, frames=6)
+    a = S.context_from_workload(w)
+    b = S.context_from_workload(w, flags=S.SDFDDGI_FLAG_RECORD_RAYS)
+    c = S.context_from_workload(w)
+    for k, fr in enumerate(w.frames):
+        gpu_frame(S, a, fr)
+        gpu_frame(S, b, fr)
+        gpu_frame(S, c, fr)
+        if k % 2:
+            S.sdfddgi_get_maps(c)  # an unrelated call between frames
+    ia, da = S.sdfddgi_get_maps(a)
+    ib, db = S.sdfddgi_get_maps(b)
+    ic, dc = S.sdfddgi_get_maps(c)
+    assert torch.equal(ia, ib) and torch.equal(da, db)
+    assert torch.equal(ia, ic) and torch.equal(da, dc)
+    assert torch.equal(S.sdfddgi_get_payload(a), S.sdfddgi_get_payload(b))
+    for ctx in (a, b, c):
+        S.sdfddgi_destroy(ctx)
+
+
 def test_kernel_timing_reports_positive_times(S):
     w = scenegen.config1(0, "1b", frames=2)
     ctx = S.context_from_workload(w, flags=S.SDFDDGI_FLAG_TIMING)
