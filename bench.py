@@ -133,10 +133,22 @@ def cpu_baseline(w, probes: int):
     chk.update_probes(fr, False, irr0, dep0, probes=sample, threads=threads)
     dt = time.perf_counter() - t0
     rays = len(sample) * w.params.rays_per_probe
+    # one thread on every 16th probe of that sample
+    one = sample[::16]
+    t1 = time.perf_counter()
+    chk.update_probes(fr, False, irr0, dep0, probes=one, threads=1)
+    d1 = time.perf_counter() - t1
+    rays1 = len(one) * w.params.rays_per_probe
+    full = w.num_probes * w.params.rays_per_probe
     return {"value": rays / dt, "unit": "probe-rays/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(sample)} of {w.num_probes} probes (every {step}th) x "
                       f"{w.params.rays_per_probe} rays, one frame, binary32 geometry + "
-                      f"binary64 radiometry, {threads} threads, {dt:.2f} s wall"}
+                      f"binary64 radiometry, {threads} threads, {dt:.2f} s wall",
+            "ms_per_frame": full / (rays / dt) * 1e3,
+            "single_thread": {"value": rays1 / d1, "unit": "probe-rays/s",
+                              "ms_per_frame": full / (rays1 / d1) * 1e3,
+                              "sample": f"{len(one)} probes (every {16 * step}th), 1 thread, "
+                                        f"{d1:.2f} s wall"}}
 
 
 def learned_comparison(S, w, n_frames: int, torch):

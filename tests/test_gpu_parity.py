@@ -294,16 +294,20 @@ def test_error_paths_leave_state_untouched(S):
     S.sdfddgi_destroy(ctx)
 
 
-def test_pipelined_frames_match_frames_run_one_at_a_time(S):
+@pytest.mark.parametrize("probes,half", [(16384, False), (16384, True), (8192, False)])
+def test_pipelined_frames_match_frames_run_one_at_a_time(S, probes, half):
     """Back-to-back plain frames overlap: the tables and primary trace of frame f run on
     a side stream while frame f-1's hit shading and blend finish. A context that keeps
     per-ray records never overlaps frames; both must give bit-identical maps and payload,
-    frame after frame, and so must a context whose frames are separated by other calls."""
+    frame after frame, and so must a context whose frames are separated by other calls.
+    At the benchmarked size, in both precisions."""
     import torch
-    w = scenegen.config2(0, probes=8192, frames=6)
-    a = S.context_from_workload(w)
-    b = S.context_from_workload(w, flags=S.SDFDDGI_FLAG_RECORD_RAYS)
-    c = S.context_from_workload(w)
+    announce(f"pipelined vs one-at-a-time frames, {probes} x 256, half={half}")
+    w = scenegen.config2(0, probes=probes, frames=6)
+    fl = S.SDFDDGI_FLAG_FP16 if half else 0
+    a = S.context_from_workload(w, flags=fl)
+    b = S.context_from_workload(w, flags=fl | S.SDFDDGI_FLAG_RECORD_RAYS)
+    c = S.context_from_workload(w, flags=fl)
     for k, fr in enumerate(w.frames):
         gpu_frame(S, a, fr)
         gpu_frame(S, b, fr)
