@@ -10,6 +10,7 @@ namespace sdfddgi {
 constexpr int kMaxLevels = 4;
 constexpr int kMaxRays = 1024;
 constexpr int kMaxRes = 32;
+constexpr int kXcds = 8;  // accelerator complex dies of the chip, one L2 each
 
 // One cascade level as the kernels see it. org/inv/half are the binary32
 // roundings of origin, 1/spacing and spacing/2 (computed once in binary64).
@@ -70,6 +71,7 @@ struct TraceArgs {
     int4 *hitq;                 // [P*R] queue of primary hits: (ray, bits of t, outcome|level<<4|steps<<8, 0)
     int *counter;               // [3] rays claimed by primary_kernel, queue entries claimed by
                                 //     hits_kernel, queue length (all zeroed by tables_kernel)
+    int *parts;                 // [kXcds * 32] primary chunks claimed per XCD (zeroed likewise)
 };
 
 struct TraceGrid {

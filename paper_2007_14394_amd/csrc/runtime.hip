@@ -120,8 +120,11 @@ struct RaySet {
 
 // Counters of one frame: [0..2] the trace pass over all probes (rays claimed,
 // queue entries claimed, queue length), [3..5] the learned form's second pass (its
-// fallback probes), [6] fallback count.
-constexpr int kCounters = 8;
+// fallback probes), [6] fallback count; from [32] the two passes' per-XCD chunk
+// counters, kXcds * 32 ints each.
+constexpr int kCounters = 32 + 2 * kXcds * 32;
+// A ray set's own counters (plain frames): [0..2] as above, per-XCD ones from [32].
+constexpr int kSetCounters = 32 + kXcds * 32;
 
 struct sdfddgi_ctx {
     int device = 0;
@@ -451,7 +454,7 @@ hipError_t alloc_set(sdfddgi_ctx *c, RaySet &r, int R) {
     chk(dev_alloc(&r.norm_d, c->Td));
     chk(dev_alloc(&r.payload, (size_t)c->P * R));
     chk(dev_alloc(&r.hitq, (size_t)c->P * R));
-    chk(dev_alloc(&r.counter, 3));
+    chk(dev_alloc(&r.counter, kSetCounters));
     if (e != hipSuccess) return e;
     chk(hipMemcpy(r.base, h_base.data(), 3 * (size_t)R * sizeof(double), hipMemcpyHostToDevice));
     chk(hipMemsetAsync(r.wt_i, 0, (size_t)R * c->Tpi * sizeof(float), c->stream));
@@ -553,9 +556,10 @@ TraceArgs trace_base(const sdfddgi_ctx *c, const float l[3], const float rad[3])
 }
 
 // The pass of ray set r: all probes (list == null) or the device-side list.
-TraceArgs trace_pass(const TraceArgs &base, const RaySet &r, int *counters, const int *list,
-                     const int *count, int *records) {
+TraceArgs trace_pass(const TraceArgs &base, const RaySet &r, int *counters, int *parts,
+                     const int *list, const int *count, int *records) {
     TraceArgs t = base;
+    t.parts = parts;
     t.R = r.R;
     t.dirs = r.dirs;
     t.payload = r.payload;
@@ -830,8 +834,8 @@ sdfddgi_status sdfddgi_update_frame(sdfddgi_ctx *c, const sdfddgi_light *light,
     float l[3], rad[3];
     if ((st = light_of(c, light, l, rad)) != SDFDDGI_OK) return st;
     RaySet &r = c->spare;  // becomes main once every launch has gone in
-    const TraceArgs t = trace_pass(trace_base(c, l, rad), r, r.counter, nullptr, nullptr,
-                                   c->records);
+    const TraceArgs t = trace_pass(trace_base(c, l, rad), r, r.counter, r.counter + 32, nullptr,
+                                   nullptr, c->records);
     FrameEvents ev = frame_events(c);
     const int nxt = 1 - c->cur;
     // side stream: tables and primary trace. This set was last used by the frame
@@ -845,7 +849,7 @@ sdfddgi_status sdfddgi_update_frame(sdfddgi_ctx *c, const sdfddgi_light *light,
         TRY_HIP(c, hipStreamWaitEvent(c->side, c->ev_gate, 0), "stream wait");
     }
     TRY_HIP(c, ev.mark_on(0, c->side), "event");
-    TRY_HIP(c, launch_tables(table_args(c, r, rotation_seed, 3, r.counter), c->side),
+    TRY_HIP(c, launch_tables(table_args(c, r, rotation_seed, kSetCounters, r.counter), c->side),
             "launching tables_kernel");
     TRY_HIP(c, ev.mark_on(1, c->side), "event");
     TRY_HIP(c, launch_primary(t, r.grid, c->side), "launching primary_kernel");
@@ -1177,13 +1181,13 @@ sdfddgi_status sdfddgi_update_frame_learned(sdfddgi_ctx *c, const sdfddgi_denois
     FrameEvents ev = frame_events(c);
     TRY_HIP(c, ev.mark(0), "event");
     // tables of both sets; the first one zeroes every counter of the frame
-    TRY_HIP(c, launch_tables(table_args(c, c->low, rotation_seed, 7), c->stream),
+    TRY_HIP(c, launch_tables(table_args(c, c->low, rotation_seed, kCounters), c->stream),
             "launching tables_kernel");
     TRY_HIP(c, launch_tables(table_args(c, c->main, rotation_seed, 0), c->stream),
             "launching tables_kernel");
     TRY_HIP(c, ev.mark(1), "event");
     // low-ray pass over every probe, Eq. 3 without hysteresis
-    const TraceArgs tl = trace_pass(base, c->low, c->counter, nullptr, nullptr, nullptr);
+    const TraceArgs tl = trace_pass(base, c->low, c->counter, c->counter + 32, nullptr, nullptr, nullptr);
     TRY_HIP(c, launch_primary(tl, c->low.grid, c->stream), "launching primary_kernel");
     TRY_HIP(c, ev.mark(2), "event");
     TRY_HIP(c, ev.mark(3), "event");
@@ -1213,7 +1217,8 @@ sdfddgi_status sdfddgi_update_frame_learned(sdfddgi_ctx *c, const sdfddgi_denois
     TRY_HIP(c, launch_denoise(da, c->stream), "launching denoise_kernel");
     TRY_HIP(c, ev.mark(6), "event");
     // plain update of the fallback probes
-    const TraceArgs tf = trace_pass(base, c->main, c->counter + 3, c->fallback, fb_count, nullptr);
+    const TraceArgs tf = trace_pass(base, c->main, c->counter + 3, c->counter + 32 + kXcds * 32, c->fallback,
+                                    fb_count, nullptr);
     TRY_HIP(c, launch_primary(tf, c->main.grid, c->stream), "launching primary_kernel");
     TRY_HIP(c, launch_hits(tf, c->main.grid, c->stream), "launching hits_kernel");
     TRY_HIP(c, ev.mark(7), "event");
@@ -1263,9 +1268,9 @@ sdfddgi_status sdfddgi_learned_examples(sdfddgi_ctx *c, const sdfddgi_denoiser *
     float l[3], rad[3];
     if ((st = light_of(c, light, l, rad)) != SDFDDGI_OK) return st;
     const TraceArgs base = trace_base(c, l, rad);
-    TRY_HIP(c, launch_tables(table_args(c, c->low, rotation_seed, 7), c->stream),
+    TRY_HIP(c, launch_tables(table_args(c, c->low, rotation_seed, kCounters), c->stream),
             "launching tables_kernel");
-    const TraceArgs tl = trace_pass(base, c->low, c->counter, nullptr, nullptr, nullptr);
+    const TraceArgs tl = trace_pass(base, c->low, c->counter, c->counter + 32, nullptr, nullptr, nullptr);
     TRY_HIP(c, launch_primary(tl, c->low.grid, c->stream), "launching primary_kernel");
     TRY_HIP(c, launch_hits(tl, c->low.grid, c->stream), "launching hits_kernel");
     TRY_HIP(c, launch_blend(blend_args(c, c->low, c->low.payload, 0.0f, c->irr[c->cur],

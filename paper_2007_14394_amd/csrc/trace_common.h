@@ -164,4 +164,49 @@ struct Feeder {
     }
 };
 
+// The XCD (accelerator complex die) the calling wave runs on, from the hardware
+// register that holds it; each XCD has its own L2.
+__device__ __forceinline__ int xcd_id() {
+    return __builtin_amdgcn_s_getreg((3 << 11) | 20) & (kXcds - 1);  // HW_REG_XCC_ID, 4 bits
+}
+
+// Work handed out so that every XCD walks the same region of the item order at the
+// same time (the order is coherent in space, so the device-wide working set stays
+// small) while each XCD's L2 sees runs of neighbouring items: the order is cut into
+// blocks of kBlock chunks of kChunkSize items, block b belongs to XCD b mod kXcds,
+// and each XCD claims the chunks of its blocks in order from a counter of its own
+// (parts[x * kPartStride]). A wave starts on its XCD's counter and moves on to the
+// next XCD's once that one is used up; a counter, once used up, stays so, so a wave
+// that has found kXcds used up in a row has seen them all and reports exhausted.
+constexpr int kPartStride = 32;  // ints between the per-XCD counters: one 128-B line each
+
+template <int kChunkSize, int kBlock>
+struct BlockFeeder {
+    int next = 0, end = 0, part = 0, misses = 0;
+    bool exhausted = false;
+    __device__ __forceinline__ void start() { part = xcd_id(); }
+    // Returns the number of items given out; the rank-th idle lane takes first + rank.
+    __device__ __forceinline__ int claim(int *parts, int total, int want, int &first) {
+        while (next >= end) {
+            if (misses == kXcds) { exhausted = true; return 0; }
+            int s = 0;
+            if (__lane_id() == 0) s = atomicAdd(parts + part * kPartStride, 1);
+            s = __builtin_amdgcn_readfirstlane(s);
+            const int64_t chunk = ((int64_t)(s / kBlock) * kXcds + part) * kBlock + s % kBlock;
+            const int64_t base = chunk * kChunkSize;
+            if (base >= total) {
+                part = part + 1 == kXcds ? 0 : part + 1;
+                ++misses;
+                continue;
+            }
+            next = (int)base;
+            end = (int)min(base + kChunkSize, (int64_t)total);
+        }
+        const int n = min(want, end - next);
+        first = next;
+        next += n;
+        return n;
+    }
+};
+
 }  // namespace sdfddgi
