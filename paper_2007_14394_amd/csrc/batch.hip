@@ -86,7 +86,7 @@ __global__ __launch_bounds__(64) void batch_begin_kernel(int *counter,
                                                          unsigned long long *stamps, int n) {
     // stamps[0]: frame start; stamps[1 + s]: end of scene s's blend
     for (int e = threadIdx.x; e <= n; e += blockDim.x) stamps[e] = 0ull;
-    if (threadIdx.x < 3) counter[threadIdx.x] = 0;
+    for (int e = threadIdx.x; e < kBatchCounters; e += blockDim.x) counter[e] = 0;
     __syncthreads();
     if (threadIdx.x == 0) stamps[0] = wall_clock64();
 }
@@ -112,7 +112,9 @@ __global__ __launch_bounds__(256) void batch_primary_kernel(BatchArgs a) {
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     int staged = 0;
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    Feeder<kChunkSize> feed;
+    // blocks of the concatenated rays dealt to the XCDs in turn (see BlockFeeder)
+    BlockFeeder<kChunkSize, kBatchBlockRays / kChunkSize> feed;
+    feed.start();
     bool active = false;
     int ray = 0, k = 0, sc = 0;
     float o0 = 0, o1 = 0, o2 = 0, w0 = 0, w1 = 0, w2 = 0, t = 0;
@@ -123,7 +125,7 @@ __global__ __launch_bounds__(256) void batch_primary_kernel(BatchArgs a) {
             uint64_t idle = ~stepping;
             while (idle != 0 && !feed.exhausted) {
                 int first = 0;
-                const int n = feed.claim(a.counter, a.total_rays, __popcll(idle), first);
+                const int n = feed.claim(a.counter + kPartStride, a.total_rays, __popcll(idle), first);
                 const int rank = __popcll(idle & below);
                 if (!active && rank < n) {
                     const int slot = first + rank;

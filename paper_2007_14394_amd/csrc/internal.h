@@ -11,6 +11,7 @@ constexpr int kMaxLevels = 4;
 constexpr int kMaxRays = 1024;
 constexpr int kMaxRes = 32;
 constexpr int kXcds = 8;  // accelerator complex dies of the chip, one L2 each
+constexpr int kPartStride = 32;  // ints between per-XCD work counters: one 128-B line each
 
 // One cascade level as the kernels see it. org/inv/half are the binary32
 // roundings of origin, 1/spacing and spacing/2 (computed once in binary64).
@@ -266,6 +267,10 @@ hipError_t launch_bake(const BakeArgs &a, hipStream_t stream);
 // probe_base .. probe_base+P-1 of the batch's probe arrays and atlases, and rays
 // ray_base .. ray_base+P*R-1 of its payload.
 constexpr int kMaxBatchScenes = 64;
+// batch counters: [0..2] primary rays claimed, hits claimed, hit-queue length; from
+// [kPartStride] the primary trace's per-XCD counters
+constexpr int kBatchCounters = kPartStride + kXcds * kPartStride;
+constexpr int kBatchBlockRays = 65536;  // rays per block of the XCD interleave
 
 struct BatchScene {
     LevelLds lv;                          // its grid level (binary16 quads)

@@ -121,10 +121,10 @@ struct RaySet {
 // Counters of one frame: [0..2] the trace pass over all probes (rays claimed,
 // queue entries claimed, queue length), [3..5] the learned form's second pass (its
 // fallback probes), [6] fallback count; from [32] the two passes' per-XCD chunk
-// counters, kXcds * 32 ints each.
-constexpr int kCounters = 32 + 2 * kXcds * 32;
+// counters, kXcds * kPartStride ints each.
+constexpr int kCounters = kPartStride + 2 * kXcds * kPartStride;
 // A ray set's own counters (plain frames): [0..2] as above, per-XCD ones from [32].
-constexpr int kSetCounters = 32 + kXcds * 32;
+constexpr int kSetCounters = kPartStride + kXcds * kPartStride;
 
 struct sdfddgi_ctx {
     int device = 0;
@@ -834,8 +834,8 @@ sdfddgi_status sdfddgi_update_frame(sdfddgi_ctx *c, const sdfddgi_light *light,
     float l[3], rad[3];
     if ((st = light_of(c, light, l, rad)) != SDFDDGI_OK) return st;
     RaySet &r = c->spare;  // becomes main once every launch has gone in
-    const TraceArgs t = trace_pass(trace_base(c, l, rad), r, r.counter, r.counter + 32, nullptr,
-                                   nullptr, c->records);
+    const TraceArgs t = trace_pass(trace_base(c, l, rad), r, r.counter, r.counter + kPartStride,
+                                   nullptr, nullptr, c->records);
     FrameEvents ev = frame_events(c);
     const int nxt = 1 - c->cur;
     // side stream: tables and primary trace. This set was last used by the frame
@@ -1187,7 +1187,8 @@ sdfddgi_status sdfddgi_update_frame_learned(sdfddgi_ctx *c, const sdfddgi_denois
             "launching tables_kernel");
     TRY_HIP(c, ev.mark(1), "event");
     // low-ray pass over every probe, Eq. 3 without hysteresis
-    const TraceArgs tl = trace_pass(base, c->low, c->counter, c->counter + 32, nullptr, nullptr, nullptr);
+    const TraceArgs tl = trace_pass(base, c->low, c->counter, c->counter + kPartStride, nullptr,
+                                    nullptr, nullptr);
     TRY_HIP(c, launch_primary(tl, c->low.grid, c->stream), "launching primary_kernel");
     TRY_HIP(c, ev.mark(2), "event");
     TRY_HIP(c, ev.mark(3), "event");
@@ -1217,8 +1218,9 @@ sdfddgi_status sdfddgi_update_frame_learned(sdfddgi_ctx *c, const sdfddgi_denois
     TRY_HIP(c, launch_denoise(da, c->stream), "launching denoise_kernel");
     TRY_HIP(c, ev.mark(6), "event");
     // plain update of the fallback probes
-    const TraceArgs tf = trace_pass(base, c->main, c->counter + 3, c->counter + 32 + kXcds * 32, c->fallback,
-                                    fb_count, nullptr);
+    int *fb_parts = c->counter + kPartStride + kXcds * kPartStride;
+    const TraceArgs tf =
+        trace_pass(base, c->main, c->counter + 3, fb_parts, c->fallback, fb_count, nullptr);
     TRY_HIP(c, launch_primary(tf, c->main.grid, c->stream), "launching primary_kernel");
     TRY_HIP(c, launch_hits(tf, c->main.grid, c->stream), "launching hits_kernel");
     TRY_HIP(c, ev.mark(7), "event");
@@ -1270,7 +1272,8 @@ sdfddgi_status sdfddgi_learned_examples(sdfddgi_ctx *c, const sdfddgi_denoiser *
     const TraceArgs base = trace_base(c, l, rad);
     TRY_HIP(c, launch_tables(table_args(c, c->low, rotation_seed, kCounters), c->stream),
             "launching tables_kernel");
-    const TraceArgs tl = trace_pass(base, c->low, c->counter, c->counter + 32, nullptr, nullptr, nullptr);
+    const TraceArgs tl = trace_pass(base, c->low, c->counter, c->counter + kPartStride, nullptr,
+                                    nullptr, nullptr);
     TRY_HIP(c, launch_primary(tl, c->low.grid, c->stream), "launching primary_kernel");
     TRY_HIP(c, launch_hits(tl, c->low.grid, c->stream), "launching hits_kernel");
     TRY_HIP(c, launch_blend(blend_args(c, c->low, c->low.payload, 0.0f, c->irr[c->cur],
@@ -1920,7 +1923,7 @@ sdfddgi_status sdfddgi_batch_create(const sdfddgi_batch_scene *scenes, int32_t c
     B_TRY(launch_fill_u8(b->reject, 1, GP, b->stream), "launching fill");
     B_TRY(dev_alloc(&b->payload, (size_t)rays), "allocating payload");
     B_TRY(dev_alloc(&b->hitq, (size_t)rays), "allocating the hit queue");
-    B_TRY(dev_alloc(&b->counter, 3), "allocating counters");
+    B_TRY(dev_alloc(&b->counter, kBatchCounters), "allocating counters");
     B_TRY(dev_alloc(&b->stamps, 1 + (size_t)count), "allocating stamps");
     b->frame_bytes = 9 * sizeof(double) + 6 * sizeof(float) * (size_t)count;
     B_TRY(dev_alloc(&b->frame_dev, b->frame_bytes), "allocating frame constants");

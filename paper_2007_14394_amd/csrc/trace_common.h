@@ -178,7 +178,6 @@ __device__ __forceinline__ int xcd_id() {
 // (parts[x * kPartStride]). A wave starts on its XCD's counter and moves on to the
 // next XCD's once that one is used up; a counter, once used up, stays so, so a wave
 // that has found kXcds used up in a row has seen them all and reports exhausted.
-constexpr int kPartStride = 32;  // ints between the per-XCD counters: one 128-B line each
 
 template <int kChunkSize, int kBlock>
 struct BlockFeeder {
