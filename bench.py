@@ -24,7 +24,10 @@ METRIC = "probe-rays/s + ms/frame (16k probes); learned vs plain at equal irradi
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "hbm_counters_open_scene_16384x256.md")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2007_14394_amd", "csrc", "kernels.hip")
+# the sources the single-scene kernels are compiled from (their hash dates the counters)
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2007_14394_amd", "csrc", f)
+                  for f in ("kernels.hip", "trace_common.h", "blend_common.h", "octahedral.h",
+                            "internal.h")]
 
 # Algorithmic bytes of the two trace kernels (what the method reads/writes per ray):
 SAMPLE_BYTES = 8 * 4          # one trilinear SDF sample: 8 binary32 corners
@@ -72,12 +75,12 @@ def copy_calibration(mib: int) -> None:
 
 
 def kernel_source_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+    return hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SOURCES)).hexdigest()[:16]
 
 
 def load_traffic(launch_rays: int, kernel: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or
-    None when the summary is missing, for another problem size, or older than kernels.hip."""
+    None when the summary is missing, for another problem size, or older than the kernel sources."""
     data = {}
     try:
         for line in open(COUNTERS_FILE):
