@@ -77,6 +77,7 @@ struct TraceArgs {
 
 struct TraceGrid {
     int primary_blocks = 0, hits_blocks = 0;
+    int hits_blocks_overlapped = 0;  // hit shading beside the next frame's primary trace
 };
 
 struct TableArgs {

@@ -687,18 +687,20 @@ static int persistent_blocks(const void *kernel, int device, int64_t rays, int m
 // found in the L2 (each XCD's 4 MB serves its own CUs): more resident waves hide more
 // latency but evict each other's lines. Measured on the open scene at 16384 x 256
 // rays, in both precisions, the primary trace is fastest with 4 waves per SIMD (of
-// the 8 its registers allow) and the hit shading with 2 (of 4).
+// the 8 its registers allow) and the hit shading with 2 (of 4) when it runs alone,
+// 1 when it runs beside the next frame's primary trace.
 constexpr int kPrimaryBlocksPerCu = 4;
 constexpr int kHitsBlocksPerCu = 2;
+constexpr int kHitsBlocksPerCuOverlapped = 1;
 
 TraceGrid trace_grid(int device, int64_t rays, bool half) {
     TraceGrid g;
     g.primary_blocks = persistent_blocks(half ? (const void *)primary_kernel<true>
                                               : (const void *)primary_kernel<false>,
                                          device, rays, kPrimaryBlocksPerCu);
-    g.hits_blocks = persistent_blocks(half ? (const void *)hits_kernel<true>
-                                           : (const void *)hits_kernel<false>,
-                                      device, rays, kHitsBlocksPerCu);
+    const void *hk = half ? (const void *)hits_kernel<true> : (const void *)hits_kernel<false>;
+    g.hits_blocks = persistent_blocks(hk, device, rays, kHitsBlocksPerCu);
+    g.hits_blocks_overlapped = persistent_blocks(hk, device, rays, kHitsBlocksPerCuOverlapped);
     return g;
 }
 

@@ -860,7 +860,9 @@ sdfddgi_status sdfddgi_update_frame(sdfddgi_ctx *c, const sdfddgi_light *light,
     TRY_HIP(c, hipStreamWaitEvent(c->stream, c->ev_primary, 0), "stream wait");
     TRY_HIP(c, hipEventRecord(c->ev_gate, c->stream), "event");
     TRY_HIP(c, ev.mark(3), "event");
-    TRY_HIP(c, launch_hits(t, r.grid, c->stream), "launching hits_kernel");
+    TraceGrid hg = r.grid;
+    if (!serial) hg.hits_blocks = r.grid.hits_blocks_overlapped;
+    TRY_HIP(c, launch_hits(t, hg, c->stream), "launching hits_kernel");
     TRY_HIP(c, ev.mark(4), "event");
     TRY_HIP(c, launch_blend(blend_args(c, r, r.payload, c->prm.hysteresis, c->irr[c->cur],
                                        c->depth[c->cur], c->irr[nxt], c->depth[nxt], c->reject,
