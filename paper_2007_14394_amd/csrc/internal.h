@@ -70,9 +70,10 @@ struct TraceArgs {
     float4 *payload;            // [P*R]
     int *records;               // [P*R*8] or nullptr
     int4 *hitq;                 // [P*R] queue of primary hits: (ray, bits of t, outcome|level<<4|steps<<8, 0)
-    int *counter;               // [3] rays claimed by primary_kernel, queue entries claimed by
-                                //     hits_kernel, queue length (all zeroed by tables_kernel)
-    int *parts;                 // [kXcds * 32] primary chunks claimed per XCD (zeroed likewise)
+    int *counter;               // [3] (unused), queue entries claimed by hits_kernel, queue
+                                //     length (all zeroed by tables_kernel)
+    int *parts;                 // [kXcds * kPartStride] primary chunks claimed per XCD, one
+                                //     counter per 128-B line (zeroed likewise)
 };
 
 struct TraceGrid {

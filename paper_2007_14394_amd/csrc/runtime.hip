@@ -118,12 +118,13 @@ struct RaySet {
     TraceGrid grid;
 };
 
-// Counters of one frame: [0..2] the trace pass over all probes (rays claimed,
-// queue entries claimed, queue length), [3..5] the learned form's second pass (its
-// fallback probes), [6] fallback count; from [32] the two passes' per-XCD chunk
+// Counters of one learned frame: [0..2] the trace pass over all probes (unused,
+// queue entries claimed, queue length), [3..5] the second pass (its fallback
+// probes), [6] fallback count; from [kPartStride] the two passes' per-XCD chunk
 // counters, kXcds * kPartStride ints each.
 constexpr int kCounters = kPartStride + 2 * kXcds * kPartStride;
-// A ray set's own counters (plain frames): [0..2] as above, per-XCD ones from [32].
+// A ray set's own counters (plain frames): [0..2] as above, per-XCD ones from
+// [kPartStride].
 constexpr int kSetCounters = kPartStride + kXcds * kPartStride;
 
 struct sdfddgi_ctx {
