@@ -178,6 +178,7 @@ def learned_comparison(S, w, n_frames: int, torch):
     den = S.sdfddgi_denoiser_create(wts["params"], wts["irr_scale"], wts["depth_scale"])
 
     def run(rays, flags=0, learned=False):
+        stage(f"learned form: {'learned' if learned else 'plain'} {rays} rays, flags {flags}")
         over = dict(rays_per_probe=rays)
         if learned:
             over.update(learned_rays=wts["learned_rays"], fallback_error=wts["tau"])
@@ -366,6 +367,11 @@ def analytic_sdf(S, scenegen, torch):
                 speedup_bound_vs_plain_culling=out["mode1_cluster8"]["ms"] / out["mode2_cluster8"]["ms"])
 
 
+def stage(msg: str) -> None:
+    """Progress line on stderr (stdout carries only the JSON result)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -423,6 +429,7 @@ def main():
     S.sdfddgi_destroy(ctx)
 
     # the precision form (binary16 SDF, FP16/BF16 MFMA blend) over the same frames
+    stage("precision form")
     ctx16 = S.context_from_workload(w, flags=S.SDFDDGI_FLAG_TIMING | S.SDFDDGI_FLAG_FP16)
     for k in range(args.warmup):
         fr = w.frames[k % len(w.frames)]
@@ -466,6 +473,7 @@ def main():
     if not args.no_stats:
         stats_frames = [w.frames[(args.warmup + k) % len(w.frames)]
                         for k in range(0, args.steps, max(1, args.steps // 10))]
+        stage("ray statistics")
         st = ray_statistics(S, w, stats_frames)
         flops = 2.0 * P * R * (w.params.irr_res ** 2 * 3 + w.params.depth_res ** 2 * 2)
         kernels = {
@@ -494,12 +502,16 @@ def main():
                             "hit_fraction": st["hits"]}
     if not args.no_learned:
         lw = scenegen.config2(args.seed, probes=args.probes, frames=args.learned_frames)
+        stage("learned form")
         out["learned_form"] = learned_comparison(S, lw, args.learned_frames, torch)
     if not args.no_batch:
+        stage("batched form")
         out["batch_form"] = batch_form(S, scenegen, args.batch_frames, torch)
     if not args.no_analytic:
+        stage("analytic SDF")
         out["analytic_sdf"] = analytic_sdf(S, scenegen, torch)
     if args.cpu_probes > 0:
+        stage("CPU baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_probes)
     print(json.dumps(out), flush=True)
 
