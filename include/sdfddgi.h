@@ -435,16 +435,22 @@ sdfddgi_status sdfddgi_batch_create(const sdfddgi_batch_scene *scenes, int32_t c
                                     void *hip_stream, sdfddgi_batch **out);
 
 /* One frame for every scene: lights (host [count]) and the shared rotation seed.
- * Enqueues one graph replay on the batch's stream. */
+ * Enqueues two graph replays: the tables and primary trace on a side stream of
+ * the batch (default priority) and the hit shading and blend on the batch's
+ * stream, joined by an event. Consecutive calls overlap (a frame's side part runs
+ * beside the previous frame's hit shading and blend); any other call on the batch
+ * in between makes the next frame wait for everything before it. Results are
+ * valid once the caller synchronises the batch's stream. */
 sdfddgi_status sdfddgi_batch_update_frame(sdfddgi_batch *b, const sdfddgi_light *lights,
                                           uint64_t rotation_seed);
 
 /* Try launch configurations of the trace kernels on real frames of the batch
  * (each candidate timed over frames_per_candidate frames with events), keep the
- * fastest primary and hit configurations, re-capture the graphs, and restore the
- * maps and history flags to what they were before (tuning changes no result:
- * every configuration computes the same bits). *chosen (may be NULL) receives
- * the result; *tried the number of candidates timed. */
+ * fastest primary and hit configurations -- chunks and refill from each kernel
+ * alone, then the two grids from overlapped frames -- re-capture the graphs, and
+ * restore the maps and history flags to what they were before (tuning changes no
+ * result: every configuration computes the same bits). *chosen (may be NULL)
+ * receives the result; *tried the number of candidates timed. */
 sdfddgi_status sdfddgi_batch_autotune(sdfddgi_batch *b, const sdfddgi_light *lights,
                                       uint64_t rotation_seed, int32_t frames_per_candidate,
                                       sdfddgi_batch_tuning *chosen, int32_t *tried);

@@ -1502,12 +1502,13 @@ namespace {
 
 constexpr int kFrameSlots = 8;   // pinned staging slots of the per-frame constants
 
+// One ray count's direction set and, per lane (see sdfddgi_batch), its tables.
 struct BatchSet {
     int R = 0, dir_base = 0;
     double *base = nullptr;
-    _Float16 *w16_i = nullptr;
-    __bf16 *w16_d = nullptr;
-    float *norm_i = nullptr, *norm_d = nullptr;
+    _Float16 *w16_i[2]{};
+    __bf16 *w16_d[2]{};
+    float *norm_i[2]{}, *norm_d[2]{};
 };
 
 }  // namespace
@@ -1524,82 +1525,113 @@ struct sdfddgi_batch {
     std::vector<BatchSet> sets;
     void *quad[kMaxBatchScenes]{};
     float *alb[kMaxBatchScenes]{};
-    BatchScene *dev_scenes = nullptr;
-    float *probe_pos = nullptr, *dirs = nullptr;
+    // Frames are pipelined like the single-scene ones: the tables and primary trace
+    // of frame f (the front graph, on the side stream) run beside frame f-1's hit
+    // shading and blend (the back graph, on the caller's stream). Everything a
+    // frame writes before its blend comes in two lanes; frame f uses lane f mod 2,
+    // the same parity as the map pair it reads (cur).
+    BatchScene *dev_scenes[2]{};              // per lane: the lane's table pointers
+    float *probe_pos = nullptr, *dirs[2]{};
     int *probe_order = nullptr;
     double *texel_i = nullptr, *texel_d = nullptr;
     float *irr[2]{}, *depth[2]{};
     int cur = 0;
     uint8_t *reject = nullptr;
-    float4 *payload = nullptr;
-    int4 *hitq = nullptr;
-    int *counter = nullptr;
-    unsigned long long *stamps = nullptr;    // [1 + S]
+    float4 *payload[2]{};
+    int4 *hitq[2]{};
+    int *counter[2]{};
+    unsigned long long *stamps[2]{};         // [1 + S] per lane
+    int last_lane = 0;                       // lane of the last frame
     int2 *blocks = nullptr;
     int nblocks = 0;
     // per-frame constants on the device: rotation (9 doubles) then lights [S][6]
-    char *frame_dev = nullptr;
+    char *frame_dev[2]{};
     char *frame_host[kFrameSlots]{};          // pinned
     hipEvent_t frame_ev[kFrameSlots]{};
     bool frame_used[kFrameSlots]{};
     int slot = 0;
     size_t frame_bytes = 0;
     BatchTuning tuning{};
-    hipGraph_t graph[2]{};
-    hipGraphExec_t exec[2]{};
+    hipGraph_t front[2]{}, back[2]{};
+    hipGraphExec_t front_exec[2]{}, back_exec[2]{};
+    hipStream_t side = nullptr;
+    hipEvent_t ev_gate = nullptr, ev_primary = nullptr, ev_tail = nullptr;
+    bool serialize_next = true;              // the next frame waits for everything before it
     bool have_frame = false;
 };
 
 namespace {
 
-void batch_free(sdfddgi_batch *b) {
+void batch_drop_graphs(sdfddgi_batch *b) {
     for (int k = 0; k < 2; ++k) {
-        if (b->exec[k]) (void)hipGraphExecDestroy(b->exec[k]);
-        if (b->graph[k]) (void)hipGraphDestroy(b->graph[k]);
-        b->exec[k] = nullptr;
-        b->graph[k] = nullptr;
+        if (b->front_exec[k]) (void)hipGraphExecDestroy(b->front_exec[k]);
+        if (b->back_exec[k]) (void)hipGraphExecDestroy(b->back_exec[k]);
+        if (b->front[k]) (void)hipGraphDestroy(b->front[k]);
+        if (b->back[k]) (void)hipGraphDestroy(b->back[k]);
+        b->front_exec[k] = b->back_exec[k] = nullptr;
+        b->front[k] = b->back[k] = nullptr;
     }
+}
+
+void batch_free(sdfddgi_batch *b) {
+    batch_drop_graphs(b);
     for (int s = 0; s < kMaxBatchScenes; ++s) {
         dev_free(b->quad[s]);
         dev_free(b->alb[s]);
     }
     for (BatchSet &r : b->sets) {
-        dev_free(r.base); dev_free(r.w16_i); dev_free(r.w16_d); dev_free(r.norm_i);
-        dev_free(r.norm_d);
+        dev_free(r.base);
+        for (int k = 0; k < 2; ++k) {
+            dev_free(r.w16_i[k]); dev_free(r.w16_d[k]); dev_free(r.norm_i[k]); dev_free(r.norm_d[k]);
+        }
     }
-    dev_free(b->dev_scenes); dev_free(b->probe_pos); dev_free(b->dirs); dev_free(b->probe_order);
+    for (int k = 0; k < 2; ++k) {
+        dev_free(b->dev_scenes[k]); dev_free(b->dirs[k]); dev_free(b->payload[k]);
+        dev_free(b->hitq[k]); dev_free(b->counter[k]); dev_free(b->stamps[k]);
+        dev_free(b->frame_dev[k]);
+    }
+    dev_free(b->probe_pos); dev_free(b->probe_order);
     dev_free(b->texel_i); dev_free(b->texel_d);
     dev_free(b->irr[0]); dev_free(b->irr[1]); dev_free(b->depth[0]); dev_free(b->depth[1]);
-    dev_free(b->reject); dev_free(b->payload); dev_free(b->hitq); dev_free(b->counter);
-    dev_free(b->stamps); dev_free(b->blocks); dev_free(b->frame_dev);
+    dev_free(b->reject); dev_free(b->blocks);
     for (int k = 0; k < kFrameSlots; ++k) {
         if (b->frame_host[k]) (void)hipHostFree(b->frame_host[k]);
         if (b->frame_ev[k]) (void)hipEventDestroy(b->frame_ev[k]);
     }
+    if (b->ev_gate) (void)hipEventDestroy(b->ev_gate);
+    if (b->ev_primary) (void)hipEventDestroy(b->ev_primary);
+    if (b->ev_tail) (void)hipEventDestroy(b->ev_tail);
+    if (b->side) (void)hipStreamDestroy(b->side);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
 }
 
-BatchArgs batch_args(const sdfddgi_batch *b, int cur) {
+// Arguments of a frame reading map pair `cur` with lane `lane`'s buffers.
+BatchArgs batch_args(const sdfddgi_batch *b, int cur, int lane) {
     BatchArgs a{};
     a.nscenes = b->S;
-    a.scenes = b->dev_scenes;
-    a.lights = reinterpret_cast<const float *>(b->frame_dev + 9 * sizeof(double));
+    a.scenes = b->dev_scenes[lane];
+    a.lights = reinterpret_cast<const float *>(b->frame_dev[lane] + 9 * sizeof(double));
     a.total_rays = (int)b->total_rays;
     a.probe_pos = b->probe_pos;
     a.probe_order = b->probe_order;
-    a.dirs = b->dirs;
+    a.dirs = b->dirs[lane];
     a.prev_irr = b->irr[cur];
-    a.payload = b->payload;
-    a.hitq = b->hitq;
-    a.counter = b->counter;
+    a.payload = b->payload[lane];
+    a.hitq = b->hitq[lane];
+    a.counter = b->counter[lane];
     a.refill = b->tuning.refill;
     return a;
 }
 
-// The launches of one frame reading map pair `cur` and writing the other; `ev`
-// (may be null) receives events around the primary and hit kernels.
-hipError_t batch_enqueue(sdfddgi_batch *b, int cur, const BatchTuning &t, hipEvent_t *ev) {
-    hipError_t e = launch_batch_begin(b->counter, b->stamps, b->S, b->stream);
+// The launches of one frame reading map pair `cur` and writing the other, with
+// lane `lane`'s buffers (a frame normally uses lane cur), in two parts: the front
+// (counters, tables, primary trace; reads no map) and the back (hit shading, blend).
+// `ev` (may be null) receives events before the primary trace (front), and after
+// it and after the hit shading (back).
+hipError_t batch_enqueue_front(sdfddgi_batch *b, int lane, const BatchTuning &t, hipStream_t st,
+                               hipEvent_t *ev) {
+    const int cur = lane;
+    hipError_t e = launch_batch_begin(b->counter[lane], b->stamps[lane], b->S, st);
     for (const BatchSet &r : b->sets) {
         if (e != hipSuccess) return e;
         TableArgs ta{};
@@ -1608,63 +1640,85 @@ hipError_t batch_enqueue(sdfddgi_batch *b, int cur, const BatchTuning &t, hipEve
         ta.Td = 256;
         ta.Tpi = 64;
         ta.Tpd = 256;
-        ta.q_dev = reinterpret_cast<const double *>(b->frame_dev);
+        ta.q_dev = reinterpret_cast<const double *>(b->frame_dev[cur]);
         ta.sharp = b->sharp;
         ta.base = r.base;
         ta.texel_i = b->texel_i;
         ta.texel_d = b->texel_d;
-        ta.dirs = b->dirs + 3 * (size_t)r.dir_base;
-        ta.norm_i = r.norm_i;
-        ta.norm_d = r.norm_d;
+        ta.dirs = b->dirs[cur] + 3 * (size_t)r.dir_base;
+        ta.norm_i = r.norm_i[cur];
+        ta.norm_d = r.norm_d[cur];
         ta.Rpad = r.R;
-        ta.w16_i = r.w16_i;
-        ta.w16_d = r.w16_d;
-        e = launch_tables(ta, b->stream);
+        ta.w16_i = r.w16_i[cur];
+        ta.w16_d = r.w16_d[cur];
+        e = launch_tables(ta, st);
     }
     if (e != hipSuccess) return e;
-    BatchArgs a = batch_args(b, cur);
+    BatchArgs a = batch_args(b, cur, lane);
     a.refill = t.refill;
-    if (ev && (e = hipEventRecord(ev[0], b->stream)) != hipSuccess) return e;
-    if ((e = launch_batch_primary(a, t, b->stream)) != hipSuccess) return e;
-    if (ev && (e = hipEventRecord(ev[1], b->stream)) != hipSuccess) return e;
-    if ((e = launch_batch_hits(a, t, b->stream)) != hipSuccess) return e;
-    if (ev && (e = hipEventRecord(ev[2], b->stream)) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
+    return launch_batch_primary(a, t, st);
+}
+
+hipError_t batch_enqueue_back(sdfddgi_batch *b, int cur, int lane, const BatchTuning &t,
+                              hipStream_t st, hipEvent_t *ev) {
+    hipError_t e = hipSuccess;
+    BatchArgs a = batch_args(b, cur, lane);
+    a.refill = t.refill;
+    if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
+    if ((e = launch_batch_hits(a, t, st)) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
     BatchBlendArgs bb{};
     bb.nscenes = b->S;
-    bb.scenes = b->dev_scenes;
+    bb.scenes = b->dev_scenes[lane];
     bb.blocks = b->blocks;
-    bb.payload = b->payload;
+    bb.payload = b->payload[lane];
     bb.prev_irr = b->irr[cur];
     bb.prev_depth = b->depth[cur];
     bb.new_irr = b->irr[1 - cur];
     bb.new_depth = b->depth[1 - cur];
     bb.reject = b->reject;
-    bb.done = b->stamps + 1;
-    return launch_batch_blend(bb, b->nblocks, b->stream);
+    bb.done = b->stamps[lane] + 1;
+    return launch_batch_blend(bb, b->nblocks, st);
 }
 
+// One whole frame on the caller's stream (the autotuner's candidates).
+hipError_t batch_enqueue(sdfddgi_batch *b, int cur, const BatchTuning &t, hipEvent_t *ev) {
+    hipError_t e = batch_enqueue_front(b, cur, t, b->stream, ev);
+    return e != hipSuccess ? e : batch_enqueue_back(b, cur, cur, t, b->stream, ev);
+}
+
+// Graphs of both parts for both lanes: fronts captured on the side stream, backs on
+// the caller's.
 hipError_t batch_capture(sdfddgi_batch *b) {
+    batch_drop_graphs(b);
     for (int k = 0; k < 2; ++k) {
-        if (b->exec[k]) (void)hipGraphExecDestroy(b->exec[k]);
-        if (b->graph[k]) (void)hipGraphDestroy(b->graph[k]);
-        b->exec[k] = nullptr;
-        b->graph[k] = nullptr;
-    }
-    for (int k = 0; k < 2; ++k) {
-        hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+        hipError_t e = hipStreamBeginCapture(b->side, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return e;
-        const hipError_t le = batch_enqueue(b, k, b->tuning, nullptr);
-        e = hipStreamEndCapture(b->stream, &b->graph[k]);
+        hipError_t le = batch_enqueue_front(b, k, b->tuning, b->side, nullptr);
+        e = hipStreamEndCapture(b->side, &b->front[k]);
         if (le != hipSuccess) return le;
         if (e != hipSuccess) return e;
-        if ((e = hipGraphInstantiate(&b->exec[k], b->graph[k], nullptr, nullptr, 0)) != hipSuccess)
+        if ((e = hipGraphInstantiate(&b->front_exec[k], b->front[k], nullptr, nullptr, 0)) !=
+            hipSuccess)
+            return e;
+        if ((e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return e;
+        le = batch_enqueue_back(b, k, k, b->tuning, b->stream, nullptr);
+        e = hipStreamEndCapture(b->stream, &b->back[k]);
+        if (le != hipSuccess) return le;
+        if (e != hipSuccess) return e;
+        if ((e = hipGraphInstantiate(&b->back_exec[k], b->back[k], nullptr, nullptr, 0)) !=
+            hipSuccess)
             return e;
     }
     return hipSuccess;
 }
 
-// Stage the frame's rotation and lights through a pinned slot.
-sdfddgi_status batch_stage_frame(sdfddgi_batch *b, const sdfddgi_light *lights, uint64_t seed) {
+// Stage the frame's rotation and lights through a pinned slot into lane `lane`'s
+// constants, on stream `st`.
+sdfddgi_status batch_stage_frame(sdfddgi_batch *b, const sdfddgi_light *lights, uint64_t seed,
+                                 int lane, hipStream_t st) {
     if (!lights) return lfail(SDFDDGI_EINVAL, "lights is NULL");
     const int k = b->slot;
     hipError_t e = hipSuccess;
@@ -1687,9 +1741,9 @@ sdfddgi_status batch_stage_frame(sdfddgi_batch *b, const sdfddgi_light *lights, 
         lt[6 * s + 2] = (float)(d2 / len);
         for (int c = 0; c < 3; ++c) lt[6 * s + 3 + c] = li.radiance_rgb[c];
     }
-    if ((e = hipMemcpyAsync(b->frame_dev, b->frame_host[k], b->frame_bytes, hipMemcpyHostToDevice,
-                            b->stream)) != hipSuccess ||
-        (e = hipEventRecord(b->frame_ev[k], b->stream)) != hipSuccess)
+    if ((e = hipMemcpyAsync(b->frame_dev[lane], b->frame_host[k], b->frame_bytes,
+                            hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipEventRecord(b->frame_ev[k], st)) != hipSuccess)
         return lhip_fail(e, "staging the frame");
     b->frame_used[k] = true;
     b->slot = (k + 1) % kFrameSlots;
@@ -1704,6 +1758,7 @@ sdfddgi_status sdfddgi_batch_destroy(sdfddgi_batch *b) {
     if (!b) return SDFDDGI_OK;
     (void)hipSetDevice(b->device);
     (void)hipStreamSynchronize(b->stream);
+    if (b->side) (void)hipStreamSynchronize(b->side);
     batch_free(b);
     delete b;
     return SDFDDGI_OK;
@@ -1788,12 +1843,15 @@ sdfddgi_status sdfddgi_batch_create(const sdfddgi_batch_scene *scenes, int32_t c
         B_TRY(dev_alloc(&r.base, h.size()), "allocating ray sets");
         B_TRY(hipMemcpy(r.base, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice),
               "uploading ray sets");
-        B_TRY(dev_alloc(&r.w16_i, (size_t)64 * r.R), "allocating tables");
-        B_TRY(dev_alloc(&r.w16_d, (size_t)256 * r.R), "allocating tables");
-        B_TRY(dev_alloc(&r.norm_i, 64), "allocating tables");
-        B_TRY(dev_alloc(&r.norm_d, 256), "allocating tables");
+        for (int k = 0; k < 2; ++k) {
+            B_TRY(dev_alloc(&r.w16_i[k], (size_t)64 * r.R), "allocating tables");
+            B_TRY(dev_alloc(&r.w16_d[k], (size_t)256 * r.R), "allocating tables");
+            B_TRY(dev_alloc(&r.norm_i[k], 64), "allocating tables");
+            B_TRY(dev_alloc(&r.norm_d[k], 256), "allocating tables");
+        }
     }
-    B_TRY(dev_alloc(&b->dirs, 3 * (size_t)dir_total), "allocating directions");
+    for (int k = 0; k < 2; ++k)
+        B_TRY(dev_alloc(&b->dirs[k], 3 * (size_t)dir_total), "allocating directions");
     {
         std::vector<double> ti(3 * 64), td(3 * 256);
         for (int t = 0; t < 64; ++t) texel_direction(8, t % 8, t / 8, &ti[3 * t]);
@@ -1874,10 +1932,10 @@ sdfddgi_status sdfddgi_batch_create(const sdfddgi_batch_scene *scenes, int32_t c
         d.hysteresis = p.hysteresis;
         d.sky0 = p.sky_rgb[0]; d.sky1 = p.sky_rgb[1]; d.sky2 = p.sky_rgb[2];
         d.alb0 = p.albedo[0]; d.alb1 = p.albedo[1]; d.alb2 = p.albedo[2];
-        d.w16_i = r.w16_i;
-        d.w16_d = r.w16_d;
-        d.norm_i = r.norm_i;
-        d.norm_d = r.norm_d;
+        d.w16_i = r.w16_i[0];  // lane 0; lane 1's descriptors are patched below
+        d.w16_d = r.w16_d[0];
+        d.norm_i = r.norm_i[0];
+        d.norm_d = r.norm_d[0];
         // positions (binary64, rounded once) and the Morton tracing order
         const int nx = pg.n[0], ny = pg.n[1];
         std::vector<std::pair<uint64_t, int32_t>> morton((size_t)P);
@@ -1900,10 +1958,20 @@ sdfddgi_status sdfddgi_batch_create(const sdfddgi_batch_scene *scenes, int32_t c
         rbase += P * p.rays_per_probe;
     }
     b->nblocks = (int)h_blocks.size();
-    B_TRY(dev_alloc(&b->dev_scenes, count), "allocating scene descriptors");
-    B_TRY(hipMemcpy(b->dev_scenes, b->host_scenes.data(), count * sizeof(BatchScene),
-                    hipMemcpyHostToDevice),
-          "uploading scene descriptors");
+    for (int k = 0; k < 2; ++k) {
+        std::vector<BatchScene> lane = b->host_scenes;
+        for (int s = 0; s < count; ++s) {
+            const BatchSet &r = b->sets[set_of[s]];
+            lane[s].w16_i = r.w16_i[k];
+            lane[s].w16_d = r.w16_d[k];
+            lane[s].norm_i = r.norm_i[k];
+            lane[s].norm_d = r.norm_d[k];
+        }
+        B_TRY(dev_alloc(&b->dev_scenes[k], count), "allocating scene descriptors");
+        B_TRY(hipMemcpy(b->dev_scenes[k], lane.data(), count * sizeof(BatchScene),
+                        hipMemcpyHostToDevice),
+              "uploading scene descriptors");
+    }
     B_TRY(dev_alloc(&b->probe_pos, h_pos.size()), "allocating probes");
     B_TRY(dev_alloc(&b->probe_order, h_order.size()), "allocating probes");
     B_TRY(dev_alloc(&b->blocks, h_blocks.size()), "allocating the blend table");
@@ -1924,12 +1992,18 @@ sdfddgi_status sdfddgi_batch_create(const sdfddgi_batch_scene *scenes, int32_t c
     }
     B_TRY(dev_alloc(&b->reject, (size_t)GP), "allocating history flags");
     B_TRY(launch_fill_u8(b->reject, 1, GP, b->stream), "launching fill");
-    B_TRY(dev_alloc(&b->payload, (size_t)rays), "allocating payload");
-    B_TRY(dev_alloc(&b->hitq, (size_t)rays), "allocating the hit queue");
-    B_TRY(dev_alloc(&b->counter, kBatchCounters), "allocating counters");
-    B_TRY(dev_alloc(&b->stamps, 1 + (size_t)count), "allocating stamps");
     b->frame_bytes = 9 * sizeof(double) + 6 * sizeof(float) * (size_t)count;
-    B_TRY(dev_alloc(&b->frame_dev, b->frame_bytes), "allocating frame constants");
+    for (int k = 0; k < 2; ++k) {
+        B_TRY(dev_alloc(&b->payload[k], (size_t)rays), "allocating payload");
+        B_TRY(dev_alloc(&b->hitq[k], (size_t)rays), "allocating the hit queue");
+        B_TRY(dev_alloc(&b->counter[k], kBatchCounters), "allocating counters");
+        B_TRY(dev_alloc(&b->stamps[k], 1 + (size_t)count), "allocating stamps");
+        B_TRY(dev_alloc(&b->frame_dev[k], b->frame_bytes), "allocating frame constants");
+    }
+    B_TRY(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking), "creating a stream");
+    B_TRY(hipEventCreateWithFlags(&b->ev_gate, hipEventDisableTiming), "creating events");
+    B_TRY(hipEventCreateWithFlags(&b->ev_primary, hipEventDisableTiming), "creating events");
+    B_TRY(hipEventCreateWithFlags(&b->ev_tail, hipEventDisableTiming), "creating events");
     for (int k = 0; k < kFrameSlots; ++k) {
         B_TRY(hipHostMalloc((void **)&b->frame_host[k], b->frame_bytes, hipHostMallocDefault),
               "allocating pinned staging");
@@ -1954,12 +2028,32 @@ sdfddgi_status sdfddgi_batch_update_frame(sdfddgi_batch *b, const sdfddgi_light 
     (void)hipGetLastError();
     hipError_t e = hipSetDevice(b->device);
     if (e != hipSuccess) return lhip_fail(e, "hipSetDevice");
-    sdfddgi_status st = batch_stage_frame(b, lights, rotation_seed);
+    const int k = b->cur;
+    const bool serial = b->serialize_next;
+    b->serialize_next = true;  // until this frame has gone in completely
+    // the front of frame f uses lane f mod 2, last used by frame f-2, whose back ran
+    // on the caller's stream before frame f-1's gate
+    if (serial) {
+        if ((e = hipEventRecord(b->ev_tail, b->stream)) != hipSuccess ||
+            (e = hipStreamWaitEvent(b->side, b->ev_tail, 0)) != hipSuccess)
+            return lhip_fail(e, "ordering the frame");
+    } else if ((e = hipStreamWaitEvent(b->side, b->ev_gate, 0)) != hipSuccess) {
+        return lhip_fail(e, "ordering the frame");
+    }
+    sdfddgi_status st = batch_stage_frame(b, lights, rotation_seed, k, b->side);
     if (st != SDFDDGI_OK) return st;
-    if ((e = hipGraphLaunch(b->exec[b->cur], b->stream)) != hipSuccess)
+    if ((e = hipGraphLaunch(b->front_exec[k], b->side)) != hipSuccess)
         return lhip_fail(e, "launching the frame graph");
-    b->cur = 1 - b->cur;
+    if ((e = hipEventRecord(b->ev_primary, b->side)) != hipSuccess ||
+        (e = hipStreamWaitEvent(b->stream, b->ev_primary, 0)) != hipSuccess ||
+        (e = hipEventRecord(b->ev_gate, b->stream)) != hipSuccess)
+        return lhip_fail(e, "ordering the frame");
+    if ((e = hipGraphLaunch(b->back_exec[k], b->stream)) != hipSuccess)
+        return lhip_fail(e, "launching the frame graph");
+    b->last_lane = k;
+    b->cur = 1 - k;
     b->have_frame = true;
+    b->serialize_next = false;
     return SDFDDGI_OK;
 }
 
@@ -1977,6 +2071,9 @@ sdfddgi_status sdfddgi_batch_set_tuning(sdfddgi_batch *b, const sdfddgi_batch_tu
     if (!tuning_valid(b->device, t)) return lfail(SDFDDGI_EINVAL, "tuning out of range");
     hipError_t e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return lhip_fail(e, "waiting for the stream");
+    if ((e = hipStreamSynchronize(b->side)) != hipSuccess)
+        return lhip_fail(e, "waiting for the stream");
+    b->serialize_next = true;
     b->tuning = BatchTuning{t->primary_chunk, t->primary_blocks, t->hits_chunk, t->hits_blocks,
                             t->refill};
     if ((e = batch_capture(b)) != hipSuccess) return lhip_fail(e, "capturing the frame graphs");
@@ -1992,7 +2089,12 @@ sdfddgi_status sdfddgi_batch_autotune(sdfddgi_batch *b, const sdfddgi_light *lig
     (void)hipGetLastError();
     hipError_t e = hipSetDevice(b->device);
     if (e != hipSuccess) return lhip_fail(e, "hipSetDevice");
-    sdfddgi_status st = batch_stage_frame(b, lights, rotation_seed);
+    // candidates run whole frames on the caller's stream, after everything so far
+    b->serialize_next = true;
+    if ((e = hipEventRecord(b->ev_tail, b->side)) != hipSuccess ||
+        (e = hipStreamWaitEvent(b->stream, b->ev_tail, 0)) != hipSuccess)
+        return lhip_fail(e, "ordering the autotuner");
+    sdfddgi_status st = batch_stage_frame(b, lights, rotation_seed, b->cur, b->stream);
     if (st != SDFDDGI_OK) return st;
     // candidate frames read the current maps and write the other pair (the state
     // does not advance); the history flags, which a blend clears, are restored
@@ -2051,6 +2153,47 @@ sdfddgi_status sdfddgi_batch_autotune(sdfddgi_batch *b, const sdfddgi_light *lig
                 best.hits_blocks = t.hits_blocks;
             }
         }
+    // then the grids of both parts as consecutive frames run them, the front of one
+    // beside the back of the previous (the times above are each kernel alone): whole
+    // overlapped frames, lanes alternating, all reading the current maps
+    auto measure_overlapped = [&](const BatchTuning &t, float &ms) -> hipError_t {
+        const int n = 2 * frames + 2;
+        hipError_t x = hipEventRecord(ev[0], b->stream);
+        if (x == hipSuccess) x = hipStreamWaitEvent(b->side, ev[0], 0);
+        for (int f = 0; f < n && x == hipSuccess; ++f) {
+            const int lane = f & 1;
+            if (f > 0) x = hipStreamWaitEvent(b->side, b->ev_gate, 0);
+            if (x == hipSuccess) x = batch_enqueue_front(b, lane, t, b->side, nullptr);
+            if (x == hipSuccess) x = hipEventRecord(b->ev_primary, b->side);
+            if (x == hipSuccess) x = hipStreamWaitEvent(b->stream, b->ev_primary, 0);
+            if (x == hipSuccess) x = hipEventRecord(b->ev_gate, b->stream);
+            if (x == hipSuccess) x = batch_enqueue_back(b, b->cur, lane, t, b->stream, nullptr);
+        }
+        if (x == hipSuccess) x = hipEventRecord(ev[2], b->stream);
+        if (x == hipSuccess) x = hipEventSynchronize(ev[2]);
+        if (x == hipSuccess) x = hipEventElapsedTime(&ms, ev[0], ev[2]);
+        ms /= n;
+        ++count;
+        return x;
+    };
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->frame_dev[1 - b->cur], b->frame_dev[b->cur], b->frame_bytes,
+                           hipMemcpyDeviceToDevice, b->stream);
+    const int opgrids[3] = {pmax, std::max(1, pmax * 3 / 4), std::max(1, pmax / 2)};
+    const int ohgrids[3] = {hmax, std::max(1, hmax / 2), std::max(1, hmax / 4)};
+    const BatchTuning alone = best;
+    float best_o = 1e30f, o = 0;
+    for (int pi = 0; pi < 3 && e == hipSuccess; ++pi)
+        for (int hi = 0; hi < 3 && e == hipSuccess; ++hi) {
+            BatchTuning t = alone;
+            t.primary_blocks = opgrids[pi];
+            t.hits_blocks = ohgrids[hi];
+            if ((e = measure_overlapped(t, o)) == hipSuccess && o < best_o) {
+                best_o = o;
+                best.primary_blocks = t.primary_blocks;
+                best.hits_blocks = t.hits_blocks;
+            }
+        }
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->reject, saved, (size_t)b->GP, hipMemcpyDeviceToDevice, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
@@ -2072,6 +2215,7 @@ sdfddgi_status sdfddgi_batch_get_maps(sdfddgi_batch *b, int32_t scene, float *ir
     if (!b) return lfail(SDFDDGI_EINVAL, "batch is NULL");
     if (scene < 0 || scene >= b->S) return lfail(SDFDDGI_EINVAL, "scene %d out of range", scene);
     (void)hipGetLastError();
+    b->serialize_next = true;
     const BatchScene &d = b->host_scenes[scene];
     const size_t ti = 10 * 10 * 3, td = 18 * 18 * 2;
     hipError_t e = hipSuccess;
@@ -2091,12 +2235,14 @@ sdfddgi_status sdfddgi_batch_scene_latency(sdfddgi_batch *b, float *ms, float *f
     if (!b || !ms) return lfail(SDFDDGI_EINVAL, "null argument");
     if (!b->have_frame) return lfail(SDFDDGI_ESTATE, "no frame yet");
     (void)hipGetLastError();
+    b->serialize_next = true;
     std::vector<unsigned long long> st(1 + (size_t)b->S);
     int rate_khz = 0;
     hipError_t e = hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, b->device);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(st.data(), b->stamps, st.size() * sizeof(unsigned long long),
-                           hipMemcpyDeviceToHost, b->stream);
+        e = hipMemcpyAsync(st.data(), b->stamps[b->last_lane],
+                           st.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                           b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return lhip_fail(e, "reading the stamps");
     if (rate_khz <= 0) return lfail(SDFDDGI_EDEVICE, "no device clock rate");

@@ -77,7 +77,7 @@ def test_autotune_changes_no_result(S):
     before = [to_host(S.sdfddgi_batch_get_maps(t, s)[0]) for s in range(len(specs))]
     tuning, tried = S.sdfddgi_batch_autotune(t, lights_of(specs, 1), seeds[1], 1)
     announce(f"autotune tried {tried}: {tuning}")
-    assert tried == 40
+    assert tried == 32 + 8 + 9   # primary alone, hits alone, both grids overlapped
     assert tuning["primary_chunk"] in (64, 128, 256, 512) and tuning["hits_chunk"] in (16, 32, 64, 128)
     for s in range(len(specs)):   # the tuning frames leave the state as it was
         assert np.array_equal(to_host(S.sdfddgi_batch_get_maps(t, s)[0]), before[s])
