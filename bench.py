@@ -144,6 +144,7 @@ def cpu_baseline(w, probes: int):
     rays1 = len(one) * w.params.rays_per_probe
     full = w.num_probes * w.params.rays_per_probe
     return {"value": rays / dt, "unit": "probe-rays/s", "cores": threads, "kind": "oracle",
+            "host_cpus": os.cpu_count(),
             "sample": f"{len(sample)} of {w.num_probes} probes (every {step}th) x "
                       f"{w.params.rays_per_probe} rays, one frame, binary32 geometry + "
                       f"binary64 radiometry, {threads} threads, {dt:.2f} s wall",
