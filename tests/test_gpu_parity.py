@@ -324,6 +324,31 @@ def test_pipelined_frames_match_frames_run_one_at_a_time(S, probes, half):
         S.sdfddgi_destroy(ctx)
 
 
+def test_pipelined_frames_with_other_calls_in_between(S):
+    """Plain frames overlap only back to back; a call in between (maps in, history
+    reset, probe relocation) must make the next frame wait for it. A context that
+    keeps per-ray records never overlaps: both must end with the same bits after the
+    same sequence of calls."""
+    import torch
+    w = scenegen.config2(1, probes=8192, frames=8)
+    irr0, dep0 = scenegen.random_atlas(w.num_probes, w.params, seed=5)
+    ctxs = [S.context_from_workload(w), S.context_from_workload(w, flags=S.SDFDDGI_FLAG_RECORD_RAYS)]
+    for ctx in ctxs:
+        fr = w.frames
+        gpu_frame(S, ctx, fr[0]); gpu_frame(S, ctx, fr[1])
+        S.sdfddgi_relocate_probes(ctx, 0.6, 0.25, 8, 0.45)
+        gpu_frame(S, ctx, fr[2]); gpu_frame(S, ctx, fr[3])
+        S.sdfddgi_set_maps(ctx, to_dev(irr0), to_dev(dep0))
+        gpu_frame(S, ctx, fr[4]); gpu_frame(S, ctx, fr[5])
+        S.sdfddgi_reset_history(ctx)
+        gpu_frame(S, ctx, fr[6]); gpu_frame(S, ctx, fr[7])
+    (ia, da), (ib, db) = [S.sdfddgi_get_maps(c) for c in ctxs]
+    assert torch.equal(ia, ib) and torch.equal(da, db)
+    assert torch.equal(S.sdfddgi_get_probe_positions(ctxs[0]), S.sdfddgi_get_probe_positions(ctxs[1]))
+    for ctx in ctxs:
+        S.sdfddgi_destroy(ctx)
+
+
 def test_kernel_timing_reports_positive_times(S):
     w = scenegen.config1(0, "1b", frames=2)
     ctx = S.context_from_workload(w, flags=S.SDFDDGI_FLAG_TIMING)
