@@ -377,8 +377,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the probe update "
-                                   "shards by probe slabs, which is not built here",
+        print(json.dumps({"error": "the benchmark runs on one GPU only; the probe update "
+                                   "would shard by probe slabs, which is not implemented",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
