@@ -159,6 +159,11 @@ struct sdfddgi_ctx {
     hipStream_t side = nullptr;
     hipEvent_t ev_gate = nullptr, ev_primary = nullptr, ev_tail = nullptr;
     bool serialize_next = true;
+    // Learned frames overlap the same way among themselves (their low-ray pass's
+    // tables and primary trace beside the previous learned frame's denoiser and
+    // fallback pass); a switch between plain and learned frames waits for
+    // everything before it.
+    bool learned_chain = false;
     float *irr[2]{}, *depth[2]{};
     int cur = 0;
     uint8_t *reject = nullptr;
@@ -829,9 +834,10 @@ sdfddgi_status sdfddgi_update_frame(sdfddgi_ctx *c, const sdfddgi_light *light,
                                     uint64_t rotation_seed) {
     // overlap with the previous frame only when nothing else came in between and no
     // per-ray records are kept (they are one buffer for both frames)
-    const bool serial = !c || c->serialize_next || c->records;
+    const bool serial = !c || c->serialize_next || c->records || c->learned_chain;
     sdfddgi_status st = check_ctx(c);
     if (st != SDFDDGI_OK) return st;
+    c->learned_chain = false;
     float l[3], rad[3];
     if ((st = light_of(c, light, l, rad)) != SDFDDGI_OK) return st;
     RaySet &r = c->spare;  // becomes main once every launch has gone in
@@ -1173,8 +1179,10 @@ static sdfddgi_status check_learned(sdfddgi_ctx *c, const sdfddgi_denoiser *d) {
 
 sdfddgi_status sdfddgi_update_frame_learned(sdfddgi_ctx *c, const sdfddgi_denoiser *d,
                                             const sdfddgi_light *light, uint64_t rotation_seed) {
+    const bool serial = !c || c->serialize_next || c->records || !c->learned_chain;
     sdfddgi_status st = check_ctx(c);
     if (st != SDFDDGI_OK) return st;
+    c->learned_chain = false;
     if ((st = check_learned(c, d)) != SDFDDGI_OK) return st;
     float l[3], rad[3];
     if ((st = light_of(c, light, l, rad)) != SDFDDGI_OK) return st;
@@ -1182,26 +1190,38 @@ sdfddgi_status sdfddgi_update_frame_learned(sdfddgi_ctx *c, const sdfddgi_denois
     const int nxt = 1 - c->cur;
     int *fb_count = c->counter + 6;
     FrameEvents ev = frame_events(c);
-    TRY_HIP(c, ev.mark(0), "event");
-    // tables of both sets; the first one zeroes every counter of the frame
-    TRY_HIP(c, launch_tables(table_args(c, c->low, rotation_seed, kCounters), c->stream),
-            "launching tables_kernel");
-    TRY_HIP(c, launch_tables(table_args(c, c->main, rotation_seed, 0), c->stream),
-            "launching tables_kernel");
-    TRY_HIP(c, ev.mark(1), "event");
-    // low-ray pass over every probe, Eq. 3 without hysteresis
-    const TraceArgs tl = trace_pass(base, c->low, c->counter, c->counter + kPartStride, nullptr,
+    // low-ray pass over every probe, Eq. 3 without hysteresis; its tables and primary
+    // trace on the side stream, after the previous learned frame's low-ray blend (the
+    // last use of the low set: its gate) or, when serial, after everything so far
+    RaySet &lo = c->low;
+    const TraceArgs tl = trace_pass(base, lo, lo.counter, lo.counter + kPartStride, nullptr,
                                     nullptr, nullptr);
-    TRY_HIP(c, launch_primary(tl, c->low.grid, c->stream), "launching primary_kernel");
-    TRY_HIP(c, ev.mark(2), "event");
+    if (serial) {
+        TRY_HIP(c, hipEventRecord(c->ev_tail, c->stream), "event");
+        TRY_HIP(c, hipStreamWaitEvent(c->side, c->ev_tail, 0), "stream wait");
+    } else {
+        TRY_HIP(c, hipStreamWaitEvent(c->side, c->ev_gate, 0), "stream wait");
+    }
+    TRY_HIP(c, ev.mark_on(0, c->side), "event");
+    TRY_HIP(c, launch_tables(table_args(c, lo, rotation_seed, kSetCounters, lo.counter), c->side),
+            "launching tables_kernel");
+    TRY_HIP(c, ev.mark_on(1, c->side), "event");
+    TRY_HIP(c, launch_primary(tl, lo.grid, c->side), "launching primary_kernel");
+    TRY_HIP(c, ev.mark_on(2, c->side), "event");
+    TRY_HIP(c, hipEventRecord(c->ev_primary, c->side), "event");
+    TRY_HIP(c, hipStreamWaitEvent(c->stream, c->ev_primary, 0), "stream wait");
+    // the main set's tables for the fallback pass; they zero the frame's counters
+    TRY_HIP(c, launch_tables(table_args(c, c->main, rotation_seed, kCounters), c->stream),
+            "launching tables_kernel");
     TRY_HIP(c, ev.mark(3), "event");
-    TRY_HIP(c, launch_hits(tl, c->low.grid, c->stream), "launching hits_kernel");
+    TRY_HIP(c, launch_hits(tl, lo.grid, c->stream), "launching hits_kernel");
     TRY_HIP(c, ev.mark(4), "event");
-    TRY_HIP(c, launch_blend(blend_args(c, c->low, c->low.payload, 0.0f, c->irr[c->cur],
+    TRY_HIP(c, launch_blend(blend_args(c, lo, lo.payload, 0.0f, c->irr[c->cur],
                                        c->depth[c->cur], c->u_irr, c->u_depth, nullptr, nullptr,
                                        nullptr),
                             c->stream),
             "launching blend_kernel");
+    TRY_HIP(c, hipEventRecord(c->ev_gate, c->stream), "event");
     TRY_HIP(c, ev.mark(5), "event");
     // network, decision, accepted probes' maps, fallback list
     DenoiseArgs da{};
@@ -1236,6 +1256,8 @@ sdfddgi_status sdfddgi_update_frame_learned(sdfddgi_ctx *c, const sdfddgi_denois
     frame_done(c);
     c->cur = nxt;
     c->have_learned = true;
+    c->learned_chain = true;
+    c->serialize_next = false;
     return SDFDDGI_OK;
 }
 

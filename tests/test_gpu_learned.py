@@ -300,6 +300,32 @@ def test_all_fallback_is_the_plain_frame_bit_for_bit(S):
     assert np.array_equal(res[0]["depth"].astype(np.float32), to_host(pd))
 
 
+@pytest.mark.parametrize("tau", [0.02, 0.0])
+def test_overlapped_learned_frames_match_frames_run_one_at_a_time(S, tau):
+    """Back-to-back learned frames overlap (the low-ray pass's tables and primary trace
+    beside the previous frame's denoiser and fallback pass); with a call in between
+    every learned frame waits for the one before. Both must give the same bits, for
+    a mix of accepted and fallback probes and for fallback everywhere."""
+    announce(f"overlapped learned frames, tau={tau}")
+    import torch
+    w = scenegen.config2(0, probes=8192, frames=6)
+    den = S.sdfddgi_denoiser_create(random_theta(4).astype(np.float32), S_IRR, D_DEPTH)
+    a = make_ctx(S, w, tau)
+    b = make_ctx(S, w, tau)
+    for ctx in (a, b):
+        fr = w.frames[0]
+        S.sdfddgi_update_frame(ctx, fr.dir_to_light, fr.radiance_rgb, fr.rotation_seed)
+    for fr in w.frames[1:]:
+        S.sdfddgi_update_frame_learned(a, den, fr.dir_to_light, fr.radiance_rgb, fr.rotation_seed)
+        S.sdfddgi_update_frame_learned(b, den, fr.dir_to_light, fr.radiance_rgb, fr.rotation_seed)
+        S.sdfddgi_get_fallback(b, want_lists=False)  # a call in between: b never overlaps
+    (ia, da), (ib, db) = S.sdfddgi_get_maps(a), S.sdfddgi_get_maps(b)
+    assert torch.equal(ia, ib) and torch.equal(da, db)
+    assert S.sdfddgi_get_fallback(a, want_lists=False)[0] == S.sdfddgi_get_fallback(b, want_lists=False)[0]
+    for ctx in (a, b):
+        S.sdfddgi_destroy(ctx)
+
+
 def test_reset_history_falls_back_everywhere(S):
     announce("learned frame after reset")
     w = learned_workload()
