@@ -67,6 +67,78 @@ __device__ __forceinline__ void blend_epilogue(const BlendArgs &a, const float *
     }
 }
 
+// Floats of the LDS buffer the standard-layout epilogue needs: 16 probes x 256
+// depth texels x 2 moments (the irradiance map, 16 x 64 x 3, fits in it too).
+constexpr int kEpilogueFloats = kBlendProbes * 256 * 2;
+
+// One map of the standard-layout epilogue (n x n interior, comps components per
+// texel) through LDS: the waves have left the normalised update u of each interior
+// texel in buf as [probe][texel][component]; the workgroup mixes it with the
+// previous interior (hysteresis, or none where the history is rejected; the previous
+// value where all weights vanish), then writes every probe's whole padded tile,
+// interior and border, in order -- coalesced reads and stores instead of one
+// scattered store per texel and border copy.
+template <int kN, int kComps>
+__device__ __forceinline__ void epilogue_map_lds(const float *prev, float *next, const float *norm,
+                                                 const float *s_h, const int *s_pid, int np,
+                                                 float *buf) {
+    constexpr int T = kN * kN, kSide = kN + 2, kTile = kSide * kSide * kComps;
+    const int tid = threadIdx.x;
+    __syncthreads();  // the waves' updates are in buf
+    for (int e = tid; e < np * T * kComps; e += blockDim.x) {
+        const int q = e / (T * kComps), rem = e - q * (T * kComps);
+        const int t = rem / kComps, c = rem - t * kComps;
+        const int i = t % kN, j = t / kN;
+        const float old = prev[(size_t)s_pid[q] * kTile + ((j + 1) * kSide + (i + 1)) * kComps + c];
+        const float nrm = norm[t];
+        const float u = buf[e];
+        buf[e] = nrm < 0.0f ? old : fmaf(s_h[q], old - u, u);
+    }
+    __syncthreads();
+    for (int e = tid; e < np * kTile; e += blockDim.x) {
+        const int q = e / kTile, rem = e - q * kTile;
+        const int pos = rem / kComps, c = rem - pos * kComps;
+        int i, j;
+        padded_source(kN, pos % kSide, pos / kSide, i, j);
+        next[(size_t)s_pid[q] * kTile + rem] = buf[(q * T + j * kN + i) * kComps + c];
+    }
+    __syncthreads();  // buf is free again
+}
+
+// Epilogue of the standard layout (8x8 irradiance in slot 0 of every wave, 16x16
+// depth in slots 1..4) for one workgroup's probes; buf: kEpilogueFloats of LDS that
+// the caller no longer needs.
+__device__ __forceinline__ void blend_epilogue_std(const BlendArgs &a, const float *s_h,
+                                                   const int *s_pid, int np, int wave, int row,
+                                                   int krow, const floatx4 (&acc)[kMSlots][3],
+                                                   float *buf) {
+    __syncthreads();  // every wave is done with what buf held before
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+        const int col = n * 16 + row, q = col / 3, c = col - 3 * q;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int t = wave * 16 + 4 * krow + r;
+            if (q < np) buf[(q * 64 + t) * 3 + c] = acc[0][n][r] * a.norm_i[t];
+        }
+    }
+    epilogue_map_lds<8, 3>(a.prev_irr, a.new_irr, a.norm_i, s_h, s_pid, np, buf);
+#pragma unroll
+    for (int s = 1; s < kMSlots; ++s) {
+        const int tile = (s - 1) * 4 + wave;
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+            const int col = n * 16 + row, q = col >> 1, m = col & 1;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int t = tile * 16 + 4 * krow + r;
+                if (q < np) buf[(q * 256 + t) * 2 + m] = acc[s][n][r] * a.norm_d[t];
+            }
+        }
+    }
+    epilogue_map_lds<16, 2>(a.prev_depth, a.new_depth, a.norm_d, s_h, s_pid, np, buf);
+}
+
 typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 constexpr int kPitch16 = kBlendChunk + 8;  // halves per LDS column (+8 spreads the banks)
@@ -79,8 +151,14 @@ constexpr int kPitch16 = kBlendChunk + 8;  // halves per LDS column (+8 spreads 
 // the body of the batched blend, which passes each scene's arguments.
 template <bool kStd>
 __device__ __forceinline__ void blend16_block(const BlendArgs &a, int pb) {
-    __shared__ __attribute__((aligned(16))) _Float16 si[(kBlendProbes * 3 + 1) * kPitch16];
-    __shared__ __attribute__((aligned(16))) __bf16 sd[(kBlendProbes * 2 + 1) * kPitch16];
+    // payload staging (FP16 radiance, BF16 moments); the standard layout's epilogue
+    // reuses the buffer
+    constexpr int kSi = (kBlendProbes * 3 + 1) * kPitch16, kSd = (kBlendProbes * 2 + 1) * kPitch16;
+    static_assert((kSi + kSd) * 2 <= kEpilogueFloats * 4, "staging fits the epilogue buffer");
+    static_assert(kSi % 8 == 0, "16-byte aligned depth staging");
+    __shared__ __attribute__((aligned(16))) float sbuf[kEpilogueFloats];
+    _Float16 *si = reinterpret_cast<_Float16 *>(sbuf);
+    __bf16 *sd = reinterpret_cast<__bf16 *>(si + kSi);
     __shared__ float s_h[kBlendProbes];
     __shared__ int s_pid[kBlendProbes];
     const int tid = threadIdx.x, lane = tid & 63;
@@ -163,6 +241,10 @@ __device__ __forceinline__ void blend16_block(const BlendArgs &a, int pb) {
                     }
                 }
             }
+        }
+        if (kStd) {
+            blend_epilogue_std(a, s_h, s_pid, np, wave, row, kgrp, acc, sbuf);
+            continue;
         }
 #pragma unroll
         for (int s = 0; s < kMSlots; ++s) {

@@ -423,8 +423,11 @@ __global__ __launch_bounds__(256) void blend16_kernel(BlendArgs a) {
 // compile time; other resolutions take the general instantiation.
 template <bool kStd>
 __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a) {
-    // payload of 16 probes x 4 channels x 64 rays, plus one zero row for absent probes
-    __shared__ float sx[(kBlendProbes * 4 + 1) * kBlendPitch];
+    // payload of 16 probes x 4 channels x 64 rays, plus one zero row for absent
+    // probes; the standard layout's epilogue reuses the buffer
+    constexpr int kStage = (kBlendProbes * 4 + 1) * kBlendPitch;
+    __shared__ float sbuf[kStage > kEpilogueFloats ? kStage : kEpilogueFloats];
+    float *sx = sbuf;
     __shared__ float s_h[kBlendProbes];
     __shared__ int s_pid[kBlendProbes];
     const int tid = threadIdx.x, lane = tid & 63;
@@ -522,6 +525,10 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a) {
             }
         }
         // epilogue: lane holds D[4*krow + r][row] of each tile
+        if (kStd) {
+            blend_epilogue_std(a, s_h, s_pid, np, wave, row, krow, acc, sbuf);
+            continue;
+        }
 #pragma unroll
         for (int s = 0; s < kMSlots; ++s) {
             if (!kStd && mt[s] >= mtiles) continue;

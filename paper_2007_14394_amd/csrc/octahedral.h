@@ -23,4 +23,16 @@ __device__ __forceinline__ void store_with_border(float *__restrict__ tile, int 
     if (i == 0 && j == 0) tile[((n + 1) * side + (n + 1)) * comps + c] = v;
 }
 
+// The interior texel (i, j) whose value padded position (x, y) of an n x n tile
+// holds (0 <= x, y <= n+1): itself inside, else the texel store_with_border copies
+// there.
+__host__ __device__ __forceinline__ void padded_source(int n, int x, int y, int &i, int &j) {
+    const bool in_x = x >= 1 && x <= n, in_y = y >= 1 && y <= n;
+    if (in_x && in_y) { i = x - 1; j = y - 1; return; }
+    if (in_x) { i = n - x; j = y == 0 ? 0 : n - 1; return; }           // top / bottom rows
+    if (in_y) { j = n - y; i = x == 0 ? 0 : n - 1; return; }           // left / right columns
+    i = x == 0 ? n - 1 : 0;                                             // corners
+    j = y == 0 ? n - 1 : 0;
+}
+
 }  // namespace sdfddgi
