@@ -78,7 +78,8 @@ struct TraceArgs {
 
 struct TraceGrid {
     int primary_blocks = 0, hits_blocks = 0;
-    int hits_blocks_overlapped = 0;  // hit shading beside the next frame's primary trace
+    int primary_blocks_overlapped = 0;  // primary trace beside the last frame's hit shading
+    int hits_blocks_overlapped = 0;     // hit shading beside the next frame's primary trace
 };
 
 struct TableArgs {

@@ -673,8 +673,6 @@ hipError_t launch_tables(const TableArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Persistent grid: as many 256-thread blocks as fit on the device at once (fewer
-// when there are fewer rays).
 // Persistent grids: as many 256-thread blocks as fit on the device at once, at most
 // max_per_cu per compute unit (fewer when there are fewer rays). A block is one wave
 // per SIMD.
@@ -695,16 +693,21 @@ static int persistent_blocks(const void *kernel, int device, int64_t rays, int m
 // latency but evict each other's lines. Measured on the open scene at 16384 x 256
 // rays, in both precisions, the primary trace is fastest with 4 waves per SIMD (of
 // the 8 its registers allow) and the hit shading with 2 (of 4) when it runs alone,
-// 1 when it runs beside the next frame's primary trace.
+// 1 when it runs beside the next frame's primary trace. Beside the previous frame's
+// hit shading and blend, the binary32 primary trace does best with 3 waves per SIMD
+// (frame period 0.742 ms vs 0.770 with 4; 2, 5 and 6 give 0.83-0.86), the binary16
+// one still with 4 (0.611 ms vs 0.646 with 3).
 constexpr int kPrimaryBlocksPerCu = 4;
+constexpr int kPrimaryBlocksPerCuOverlapped[2] = {3, 4};  // binary32, binary16 SDF
 constexpr int kHitsBlocksPerCu = 2;
 constexpr int kHitsBlocksPerCuOverlapped = 1;
 
 TraceGrid trace_grid(int device, int64_t rays, bool half) {
     TraceGrid g;
-    g.primary_blocks = persistent_blocks(half ? (const void *)primary_kernel<true>
-                                              : (const void *)primary_kernel<false>,
-                                         device, rays, kPrimaryBlocksPerCu);
+    const void *pk = half ? (const void *)primary_kernel<true> : (const void *)primary_kernel<false>;
+    g.primary_blocks = persistent_blocks(pk, device, rays, kPrimaryBlocksPerCu);
+    g.primary_blocks_overlapped =
+        persistent_blocks(pk, device, rays, kPrimaryBlocksPerCuOverlapped[half ? 1 : 0]);
     const void *hk = half ? (const void *)hits_kernel<true> : (const void *)hits_kernel<false>;
     g.hits_blocks = persistent_blocks(hk, device, rays, kHitsBlocksPerCu);
     g.hits_blocks_overlapped = persistent_blocks(hk, device, rays, kHitsBlocksPerCuOverlapped);

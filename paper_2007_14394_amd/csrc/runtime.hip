@@ -859,7 +859,13 @@ sdfddgi_status sdfddgi_update_frame(sdfddgi_ctx *c, const sdfddgi_light *light,
     TRY_HIP(c, launch_tables(table_args(c, r, rotation_seed, kSetCounters, r.counter), c->side),
             "launching tables_kernel");
     TRY_HIP(c, ev.mark_on(1, c->side), "event");
-    TRY_HIP(c, launch_primary(t, r.grid, c->side), "launching primary_kernel");
+    // overlapped frames share the GPU with the other stream's kernels: their own grids
+    TraceGrid g = r.grid;
+    if (!serial) {
+        g.primary_blocks = r.grid.primary_blocks_overlapped;
+        g.hits_blocks = r.grid.hits_blocks_overlapped;
+    }
+    TRY_HIP(c, launch_primary(t, g, c->side), "launching primary_kernel");
     TRY_HIP(c, ev.mark_on(2, c->side), "event");
     TRY_HIP(c, hipEventRecord(c->ev_primary, c->side), "event");
     // caller's stream: hit shading (reads the previous atlas, so after the previous
@@ -867,9 +873,7 @@ sdfddgi_status sdfddgi_update_frame(sdfddgi_ctx *c, const sdfddgi_light *light,
     TRY_HIP(c, hipStreamWaitEvent(c->stream, c->ev_primary, 0), "stream wait");
     TRY_HIP(c, hipEventRecord(c->ev_gate, c->stream), "event");
     TRY_HIP(c, ev.mark(3), "event");
-    TraceGrid hg = r.grid;
-    if (!serial) hg.hits_blocks = r.grid.hits_blocks_overlapped;
-    TRY_HIP(c, launch_hits(t, hg, c->stream), "launching hits_kernel");
+    TRY_HIP(c, launch_hits(t, g, c->stream), "launching hits_kernel");
     TRY_HIP(c, ev.mark(4), "event");
     TRY_HIP(c, launch_blend(blend_args(c, r, r.payload, c->prm.hysteresis, c->irr[c->cur],
                                        c->depth[c->cur], c->irr[nxt], c->depth[nxt], c->reject,
