@@ -16,7 +16,7 @@ Everything runs in the library's kernels; this script only orchestrates. Writes
 ``<out>/denoiser.f32`` (binary32 parameters, the C ABI's layout) and
 ``<out>/denoiser.json`` (feature scales and the training record).
 
-    python -m paper_2007_14394_amd.train_denoiser --out gpurun_out/denoiser
+    python -m paper_2007_14394_amd.train_denoiser --out denoiser_out
 """
 from __future__ import annotations
 
@@ -119,7 +119,7 @@ def main(argv=None) -> int:
                     help="data rounds; rounds after the first warm up with learned frames")
     ap.add_argument("--tau", type=float, default=0.02, help="fallback threshold of learned frames")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--out", default="gpurun_out/denoiser")
+    ap.add_argument("--out", default="denoiser_out")
     args = ap.parse_args(argv)
 
     import torch
