@@ -692,7 +692,7 @@ static int persistent_blocks(const void *kernel, int device, int64_t rays, int m
 // found in the L2 (each XCD's 4 MB serves its own CUs): more resident waves hide more
 // latency but evict each other's lines. Measured on the open scene at 16384 x 256
 // rays, in both precisions, the primary trace is fastest with 4 waves per SIMD (of
-// the 8 its registers allow) and the hit shading with 2 (of 4) when it runs alone,
+// the 7 that fit) and the hit shading with 2 (of 4) when it runs alone,
 // 1 when it runs beside the next frame's primary trace. Beside the previous frame's
 // hit shading and blend, the binary32 primary trace does best with 3 waves per SIMD
 // (frame period 0.742 ms vs 0.770 with 4; 2, 5 and 6 give 0.83-0.86), the binary16
