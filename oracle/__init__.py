@@ -18,6 +18,8 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 MISS_TMAX, MISS_EXIT, HIT, HIT_EXHAUSTED, INSIDE = 0, 1, 2, 3, 4
 MAX_LEVELS = 4
+GEOMETRY_32, GEOMETRY_64 = 0, 1
+RAY64_FIELDS = 13
 
 # -ffp-contract=off forbids fusing any multiply-add the source does not spell out;
 # fmaf() is the only fused operation, and it is correctly rounded in glibc.
@@ -78,6 +80,9 @@ def _load(path: str):
     L.orc_level32.restype = ctypes.c_int32
     L.orc_blend_probe.restype = ctypes.c_int32
     L.orc_update_probes.restype = ctypes.c_int32
+    L.orc_update_probes_ex.restype = ctypes.c_int32
+    L.orc_sdf64.restype = ctypes.c_double
+    L.orc_level64.restype = ctypes.c_int32
     L.orc_round_bf16.restype = ctypes.c_double
     L.orc_round_bf16.argtypes = [ctypes.c_double]
     L.orc_mlp_loss_grad.restype = ctypes.c_double
@@ -187,6 +192,26 @@ class Checker:
         lib().orc_trace_ray32(self.ref, o, d, l, rec)
         return np.array(list(rec), dtype=np.int32)
 
+    def sdf64(self, level: int, x) -> float:
+        xa = (ctypes.c_double * 3)(*[float(v) for v in x])
+        return float(lib().orc_sdf64(self.ref, ctypes.c_int32(level), xa))
+
+    def level64(self, x) -> Tuple[int, float]:
+        """(finest level holding x or -1, margin of that choice in scene units)."""
+        xa = (ctypes.c_double * 3)(*[float(v) for v in x])
+        m = ctypes.c_double()
+        L = int(lib().orc_level64(self.ref, xa, ctypes.byref(m)))
+        return L, float(m.value)
+
+    def trace_ray64(self, origin, direction, dir_to_light=(0.0, 1.0, 0.0)) -> dict:
+        """Binary64 trace of one ray: fields of the record (see ray64_fields)."""
+        o = (ctypes.c_double * 3)(*[float(v) for v in origin])
+        d = (ctypes.c_double * 3)(*[float(v) for v in direction])
+        l = (ctypes.c_double * 3)(*[float(v) for v in dir_to_light])
+        rec = (ctypes.c_double * RAY64_FIELDS)()
+        lib().orc_trace_ray64(self.ref, o, d, l, rec)
+        return ray64_fields(np.array(list(rec)))
+
     def set_probe_positions(self, pos: Optional[np.ndarray]) -> None:
         """Trace from these binary32 positions [P][3] (relocated probes); None: the grid."""
         if pos is None:
@@ -254,8 +279,15 @@ class Checker:
 
     def update_probes(self, frame, reset: bool, prev_irr: Optional[np.ndarray],
                       prev_depth: Optional[np.ndarray], probes: Optional[Sequence[int]] = None,
-                      threads: int = 0, want_payload: bool = False, want_records: bool = False):
-        """One frame for the listed probes (all by default) from the given previous atlas."""
+                      threads: int = 0, want_payload: bool = False, want_records: bool = False,
+                      geometry: int = GEOMETRY_32, given: Optional[np.ndarray] = None):
+        """One frame for the listed probes (all by default) from the given previous atlas.
+
+        geometry GEOMETRY_32: the binary32 decision copy; records are int32 [count, R, 8].
+        geometry GEOMETRY_64: the binary64 trace; records are float64 [count, R, 10]
+        (see ray64_fields) and ``given`` (bool [count, R]) marks rays that follow the
+        binary32 sequence's decisions instead of their own.
+        """
         if probes is None:
             probes = np.arange(self.num_probes, dtype=np.int32)
         probes = np.ascontiguousarray(probes, dtype=np.int32)
@@ -264,7 +296,15 @@ class Checker:
         irr = np.zeros((cnt, ri, ri, 3))
         dep = np.zeros((cnt, rd, rd, 2))
         pl = np.zeros((cnt, self.rays, 4)) if want_payload else None
-        rec = np.zeros((cnt, self.rays, 8), dtype=np.int32) if want_records else None
+        rec = rec64 = None
+        if want_records and geometry == GEOMETRY_32:
+            rec = np.zeros((cnt, self.rays, 8), dtype=np.int32)
+        if want_records and geometry == GEOMETRY_64:
+            rec64 = np.zeros((cnt, self.rays, RAY64_FIELDS))
+        gv = None
+        if given is not None:
+            gv = np.ascontiguousarray(np.asarray(given, dtype=bool).reshape(cnt, self.rays),
+                                      dtype=np.uint8)
         pi = np.ascontiguousarray(prev_irr, dtype=np.float64) if prev_irr is not None else None
         pd = (np.ascontiguousarray(prev_depth, dtype=np.float64)
               if prev_depth is not None else None)
@@ -275,14 +315,15 @@ class Checker:
         fd.reset_history = int(reset)
         if threads <= 0:
             threads = min(16, os.cpu_count() or 1)
-        rc = lib().orc_update_probes(
+        rc = lib().orc_update_probes_ex(
             self.ref, ctypes.byref(fd), _p(pi) if pi is not None else None,
             _p(pd) if pd is not None else None, _p(probes), ctypes.c_int32(cnt), _p(irr),
             _p(dep), _p(pl) if pl is not None else None, _p(rec) if rec is not None else None,
-            ctypes.c_int32(threads))
+            ctypes.c_int32(geometry), _p(gv) if gv is not None else None,
+            _p(rec64) if rec64 is not None else None, ctypes.c_int32(threads))
         if rc != 0:
-            raise RuntimeError("orc_update_probes failed")
-        return irr, dep, pl, rec
+            raise RuntimeError("orc_update_probes_ex failed")
+        return irr, dep, pl, (rec if geometry == GEOMETRY_32 else rec64)
 
     # -- learned form ---------------------------------------------------
     def probe_sdf(self, p: int) -> float:
@@ -350,7 +391,7 @@ class Checker:
                     features=feats, u_irr=u_irr, u_depth=u_dep)
 
     def run_frames(self, frames, init: Optional[Tuple[np.ndarray, np.ndarray]] = None,
-                   reset_first: bool = True, threads: int = 0):
+                   reset_first: bool = True, threads: int = 0, geometry: int = GEOMETRY_32):
         """Free-run the listed frames from ``init`` (zeros by default); returns every atlas."""
         ri, rd = self.irr_res + 2, self.depth_res + 2
         if init is None:
@@ -362,7 +403,7 @@ class Checker:
         out = []
         for k, fr in enumerate(frames):
             irr, dep, _, _ = self.update_probes(fr, reset_first and k == 0, irr, dep,
-                                                threads=threads)
+                                                threads=threads, geometry=geometry)
             out.append((irr, dep))
         return out
 
@@ -541,3 +582,13 @@ def record_fields(rec: np.ndarray):
     return dict(kind=rec[..., 0] & 0xFF, level=(rec[..., 0] >> 8) & 0xFF, steps=rec[..., 1],
                 visibility=rec[..., 2], shadow_steps=rec[..., 3],
                 t=rec[..., 4].view(np.float32), normal=rec[..., 5:8].view(np.float32))
+
+
+def ray64_fields(rec: np.ndarray):
+    """Split binary64 records [..., 13] into named fields (see oracle.h)."""
+    rec = np.asarray(rec, dtype=np.float64)
+    return dict(kind=rec[..., 0].astype(np.int32), level=rec[..., 1].astype(np.int32),
+                steps=rec[..., 2].astype(np.int32), visibility=rec[..., 3].astype(np.int32),
+                shadow_steps=rec[..., 4].astype(np.int32), t=rec[..., 5],
+                normal=rec[..., 6:9], margin=rec[..., 9], tie=rec[..., 10],
+                t_err=rec[..., 11], n_err=rec[..., 12])

@@ -480,6 +480,404 @@ static double trilinear64(const float *grid, int32_t comps, int32_t comp, const 
     return acc;
 }
 
+/* ======================================================================== */
+/* Geometry in binary64: the trace written plainly from its definition.      */
+/* ======================================================================== */
+
+/* Whether x lies in level L's box (shrunk by one voxel unless L is the
+ * coarsest level), and how far x is from changing that answer: the smallest
+ * slack to a face when inside, the largest excess over a face (the L-inf
+ * distance to the box) when outside. */
+static int in_level_box64(const orc_setup *s, int32_t L, const double x[3], double *margin)
+{
+    const orc_level *lv = &s->level[L];
+    double shrink = L < s->num_levels - 1 ? 1.0 : 0.0;
+    double slack = INFINITY, excess = 0.0;
+    int inside = 1;
+    for (int c = 0; c < 3; ++c) {
+        double lo = lv->origin[c] + lv->spacing * shrink;
+        double hi = lv->origin[c] + lv->spacing * ((double)(lv->n[c] - 1) - shrink);
+        double a = x[c] - lo, b = hi - x[c];
+        if (a < 0.0 || b < 0.0) {
+            inside = 0;
+            double e = a < 0.0 ? -a : -b;
+            if (e > excess) excess = e;
+        } else {
+            double m = a < b ? a : b;
+            if (m < slack) slack = m;
+        }
+    }
+    *margin = inside ? slack : excess;
+    return inside;
+}
+
+/* The finest level holding x (-1 outside the coarsest box); *margin is the
+ * smallest margin of the box tests that chose it. */
+static int32_t level64(const orc_setup *s, const double x[3], double *margin)
+{
+    double m = INFINITY;
+    for (int32_t L = 0; L < s->num_levels; ++L) {
+        double mL;
+        int in = in_level_box64(s, L, x, &mL);
+        if (mL < m) m = mL;
+        if (in) {
+            *margin = m;
+            return L;
+        }
+    }
+    *margin = m;
+    return -1;
+}
+
+/* Trilinear distance of level L at x; grid coordinate (x - origin) / spacing. */
+static double sdf64(const orc_setup *s, int32_t L, const double x[3])
+{
+    const orc_level *lv = &s->level[L];
+    double u[3];
+    for (int c = 0; c < 3; ++c) u[c] = (x[c] - lv->origin[c]) / lv->spacing;
+    return trilinear64(lv->sdf, 1, 0, lv->n, u);
+}
+
+/* ---- forward error bounds of the binary32 evaluation -------------------- */
+/*
+ * To tell a legitimate disagreement from a wrong one, each binary64 ray also
+ * carries a first-order bound on how far a binary32 evaluation of the same
+ * trace (unit roundoff u = 2^-24; one rounding per operation, the sequence of
+ * the decision copy) can drift from it, as long as both take the same
+ * decisions. With e_k = t~_k - t_k and g_k the gradient of the interpolated
+ * distance at sample k (scene units):
+ *   sample point  x~_k - x_k = e_k w + p_k,
+ *                 |p_k| <= o_err + t_k w_err + u (|x_k| + 3 |x_k - origin_L|)
+ *                 (rounded direction and origin, the fma, and the grid
+ *                 coordinate's subtraction, product and rounded 1/spacing)
+ *   distance      |d~_k - d_k| <= |g_k.w| |e_k| + |g_k|_1 |p_k| + 8 u (|d_k| + 2 spacing_L)
+ *                 (the position error, and the seven lerps' roundings of corner
+ *                 values no larger than |d_k| + 2 spacing)
+ *   step          |e_k+1| <= |1 + relax g_k.w| |e_k| + relax (|g_k|_1 |p_k| + 8 u (...))
+ *                            + u t_k+1
+ * (all norms L-inf unless marked). Every decision then has an error bound:
+ * |e_k| for t > t_max, |e_k| + |p_k| for the level boxes, the distance bound
+ * for the inside and hit tests. The ratio margin / bound, minimised over the
+ * ray's decisions, is its tie ratio: below 1 the binary32 evaluation may take
+ * the other branch. The hit normal's bound follows from the same position
+ * error at its six samples. First-order: the gradient is taken at the
+ * binary64 point, so users of the bounds allow a small factor.
+ */
+static const double kU32 = 0x1.0p-24;
+
+static double max_abs3(const double v[3])
+{
+    double m = fabs(v[0]);
+    if (fabs(v[1]) > m) m = fabs(v[1]);
+    if (fabs(v[2]) > m) m = fabs(v[2]);
+    return m;
+}
+
+/* Gradient (scene units) of level L's trilinear interpolant at x, as the
+ * derivative of the same cell's polynomial (zero along an axis whose
+ * fraction is clamped). */
+static void sdf64_gradient(const orc_setup *s, int32_t L, const double x[3], double g[3])
+{
+    const orc_level *lv = &s->level[L];
+    int32_t i[3];
+    double f[3];
+    int clamped[3];
+    for (int c = 0; c < 3; ++c) {
+        double u = (x[c] - lv->origin[c]) / lv->spacing;
+        double fl = floor(u);
+        if (fl < 0.0) fl = 0.0;
+        if (fl > (double)(lv->n[c] - 2)) fl = (double)(lv->n[c] - 2);
+        i[c] = (int32_t)fl;
+        double fr = u - fl;
+        clamped[c] = fr < 0.0 || fr > 1.0;
+        f[c] = fr < 0.0 ? 0.0 : (fr > 1.0 ? 1.0 : fr);
+    }
+    double v[2][2][2];
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx)
+                v[dz][dy][dx] = (double)lv->sdf[((size_t)(i[2] + dz) * lv->n[1] +
+                                                 (size_t)(i[1] + dy)) * lv->n[0] +
+                                                (size_t)(i[0] + dx)];
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            double wa_y = a ? f[1] : 1.0 - f[1], wb_z = b ? f[2] : 1.0 - f[2];
+            double wa_x = a ? f[0] : 1.0 - f[0], wb_y = b ? f[1] : 1.0 - f[1];
+            gx += wa_y * wb_z * (v[b][a][1] - v[b][a][0]);
+            gy += wa_x * wb_z * (v[b][1][a] - v[b][0][a]);
+            gz += wa_x * wb_y * (v[1][b][a] - v[0][b][a]);
+        }
+    g[0] = clamped[0] ? 0.0 : gx / lv->spacing;
+    g[1] = clamped[1] ? 0.0 : gy / lv->spacing;
+    g[2] = clamped[2] ? 0.0 : gz / lv->spacing;
+}
+
+/* Bound on the non-t part p of a binary32 sample point's error at x. */
+static double point_error(const orc_setup *s, int32_t L, const double x[3], double t,
+                          double o_err, double w_err)
+{
+    double rel[3];
+    for (int c = 0; c < 3; ++c) rel[c] = x[c] - s->level[L].origin[c];
+    return o_err + t * w_err + kU32 * (max_abs3(x) + 3.0 * max_abs3(rel));
+}
+
+static double sum_abs3(const double v[3]) { return fabs(v[0]) + fabs(v[1]) + fabs(v[2]); }
+
+typedef struct {
+    int32_t kind, steps, level;
+    double t, x[3];
+    double margin;     /* smallest |decision value - threshold|, scene units */
+    double tie;        /* smallest margin / binary32 error bound of that decision */
+    double t_err;      /* bound on |t32 - t| at the last sample */
+    double x_err;      /* bound on the last sample point's error (L-inf) */
+} trace64_result;
+
+static void min_into(double *m, double v)
+{
+    if (v < *m) *m = v;
+}
+
+static void decision(trace64_result *r, double margin, double err)
+{
+    min_into(&r->margin, margin);
+    min_into(&r->tie, err > 0.0 ? margin / err : INFINITY);
+}
+
+/* Sphere tracing in binary64 with the same stopping rules as the binary32
+ * sequence (t past t_max, outside the coarsest box, inside at the first
+ * sample of a probe ray, distance below the hit epsilon, step budget spent).
+ * o_err, w_err: bounds on the binary32 origin's and direction's rounding. */
+static trace64_result trace64(const orc_setup *s, const double o[3], const double w[3],
+                              int primary, double o_err, double w_err)
+{
+    trace64_result r = {ORC_HIT_EXHAUSTED, s->max_steps, -1, 0.0, {0.0, 0.0, 0.0},
+                        INFINITY, INFINITY, 0.0, 0.0};
+    const double t_max = (double)s->t_max, eps = (double)s->hit_eps, relax = (double)s->relax;
+    double t = 0.0, e = 0.0;
+    for (int32_t k = 0; k < s->max_steps; ++k) {
+        decision(&r, fabs(t - t_max), e + kU32 * t);
+        if (t > t_max) {
+            r.kind = ORC_MISS_TMAX;
+            r.steps = k;
+            return r;
+        }
+        double x[3], mL;
+        for (int c = 0; c < 3; ++c) x[c] = o[c] + t * w[c];
+        int32_t L = level64(s, x, &mL);
+        int32_t Lb = L >= 0 ? L : s->num_levels - 1;
+        double pk = point_error(s, Lb, x, t, o_err, w_err);
+        decision(&r, mL, e * max_abs3(w) + pk);
+        if (L < 0) {
+            r.kind = ORC_MISS_EXIT;
+            r.steps = k;
+            return r;
+        }
+        double d = sdf64(s, L, x), g[3];
+        sdf64_gradient(s, L, x, g);
+        double gw = g[0] * w[0] + g[1] * w[1] + g[2] * w[2];
+        double tri = 8.0 * kU32 * (fabs(d) + 2.0 * s->level[L].spacing);
+        double derr = fabs(gw) * e + sum_abs3(g) * pk + tri;
+        r.t = t;
+        r.level = L;
+        memcpy(r.x, x, sizeof x);
+        r.t_err = e;
+        r.x_err = e * max_abs3(w) + pk;
+        if (primary && k == 0) {
+            decision(&r, fabs(d), derr);
+            if (d < 0.0) {
+                r.kind = ORC_INSIDE;
+                r.steps = 1;
+                return r;
+            }
+        }
+        decision(&r, fabs(d - eps), derr);
+        if (d < eps) {
+            r.kind = ORC_HIT;
+            r.steps = k + 1;
+            return r;
+        }
+        t += relax * d;
+        e = fabs(1.0 + relax * gw) * e + relax * (sum_abs3(g) * pk + tri) + kU32 * t;
+    }
+    return r;
+}
+
+/* Normalised central differences at +-spacing/2 on level L; -w when the
+ * difference vector vanishes (returns 1 then). */
+static int normal64(const orc_setup *s, int32_t L, const double x[3], const double w[3],
+                    double n[3])
+{
+    double h = 0.5 * s->level[L].spacing, g[3];
+    for (int c = 0; c < 3; ++c) {
+        double xp[3] = {x[0], x[1], x[2]}, xm[3] = {x[0], x[1], x[2]};
+        xp[c] += h;
+        xm[c] -= h;
+        g[c] = sdf64(s, L, xp) - sdf64(s, L, xm);
+    }
+    double len2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+    if (!(len2 >= 1e-24)) {
+        for (int c = 0; c < 3; ++c) n[c] = -w[c];
+        return 1;
+    }
+    double len = sqrt(len2);
+    for (int c = 0; c < 3; ++c) n[c] = g[c] / len;
+    return 0;
+}
+
+/* Distance (scene units) from x to the nearest cell face of level L. */
+static double face_distance(const orc_setup *s, int32_t L, const double x[3])
+{
+    const orc_level *lv = &s->level[L];
+    double m = INFINITY;
+    for (int c = 0; c < 3; ++c) {
+        double u = (x[c] - lv->origin[c]) / lv->spacing;
+        double fr = u - floor(u);
+        double d = (fr < 0.5 ? fr : 1.0 - fr) * lv->spacing;
+        if (d < m) m = d;
+    }
+    return m;
+}
+
+/* Bound on a binary32 evaluation's normal error when the hit point is off by
+ * at most x_err (L-inf). The six samples x +- h e_c share the hit point's
+ * error, so a difference G_c = S(x + h e_c) - S(x - h e_c) moves by the
+ * difference of the two gradients times x_err (the sum of their magnitudes
+ * where a sample lies within x_err of a cell face, across which the gradient
+ * jumps), plus each sample's own rounding (offset, grid coordinate, lerps)
+ * and the subtraction's; normalising at most doubles the relative error of
+ * the vector. */
+static double normal64_error(const orc_setup *s, int32_t L, const double x[3], double x_err)
+{
+    double h = 0.5 * s->level[L].spacing, G[3], dG = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        double xp[3] = {x[0], x[1], x[2]}, xm[3] = {x[0], x[1], x[2]};
+        xp[c] += h;
+        xm[c] -= h;
+        double gp[3], gm[3], gd[3];
+        sdf64_gradient(s, L, xp, gp);
+        sdf64_gradient(s, L, xm, gm);
+        for (int k = 0; k < 3; ++k) gd[k] = gp[k] - gm[k];
+        int near_face = face_distance(s, L, xp) <= x_err || face_distance(s, L, xm) <= x_err;
+        double shift = (near_face ? sum_abs3(gp) + sum_abs3(gm) : sum_abs3(gd)) * x_err;
+        double own = sum_abs3(gp) * (kU32 * h + point_error(s, L, xp, 0.0, 0.0, 0.0)) +
+                     sum_abs3(gm) * (kU32 * h + point_error(s, L, xm, 0.0, 0.0, 0.0));
+        double vp = sdf64(s, L, xp), vm = sdf64(s, L, xm);
+        G[c] = vp - vm;
+        double tri = 8.0 * kU32 * (fabs(vp) + fabs(vm) + 4.0 * s->level[L].spacing);
+        double e = shift + own + tri + kU32 * fabs(G[c]);
+        if (e > dG) dG = e;
+    }
+    double len = sqrt(G[0] * G[0] + G[1] * G[1] + G[2] * G[2]);
+    if (!(len > 0.0)) return INFINITY;
+    return 2.0 * sqrt(3.0) * dG / len + 4.0 * kU32;
+}
+
+typedef struct {
+    trace64_result prim;
+    double n[3];
+    int32_t visibility;     /* 1 lit, 0 blocked, -1 not traced */
+    int32_t shadow_steps;
+    double margin, tie;     /* smallest over the primary and shadow decisions */
+    double n_err;           /* bound on the binary32 normal's error (L-inf) */
+} ray64;
+
+/* Primary trace, hit normal and shadow ray in binary64. The decision whether
+ * to trace the shadow ray adds |n.l| to the margins; the shadow ray starts
+ * from a point whose binary32 error includes the hit point's and the bias
+ * times the normal's. */
+static ray64 ray_geometry64(const orc_setup *s, const double o[3], const double w[3],
+                            const double l[3])
+{
+    ray64 g;
+    memset(&g, 0, sizeof g);
+    g.prim = trace64(s, o, w, 1, kU32 * max_abs3(o), kU32);
+    g.margin = g.prim.margin;
+    g.tie = g.prim.tie;
+    g.visibility = -1;
+    if (!is_hit(g.prim.kind)) return g;
+    normal64(s, g.prim.level, g.prim.x, w, g.n);
+    g.n_err = normal64_error(s, g.prim.level, g.prim.x, g.prim.x_err);
+    double ndl = g.n[0] * l[0] + g.n[1] * l[1] + g.n[2] * l[2];
+    min_into(&g.margin, fabs(ndl));
+    min_into(&g.tie, fabs(ndl) / (3.0 * g.n_err + 4.0 * kU32));
+    if (ndl > 0.0) {
+        double xs[3], bias = (double)s->shadow_bias;
+        for (int c = 0; c < 3; ++c) xs[c] = g.prim.x[c] + bias * g.n[c];
+        double xs_err = g.prim.x_err + bias * g.n_err + kU32 * max_abs3(xs);
+        trace64_result sh = trace64(s, xs, l, 0, xs_err, kU32);
+        min_into(&g.margin, sh.margin);
+        min_into(&g.tie, sh.tie);
+        g.visibility = is_hit(sh.kind) ? 0 : 1;
+        g.shadow_steps = sh.steps;
+    }
+    return g;
+}
+
+/* A ray whose geometry is given by the binary32 sequence (`d32`: outcome,
+ * level, steps, hit point and distance, normal, shadow result). */
+static ray64 ray_geometry64_given(const ray32 *d32)
+{
+    ray64 g;
+    memset(&g, 0, sizeof g);
+    g.prim.kind = d32->prim.kind;
+    g.prim.steps = d32->prim.steps;
+    g.prim.level = d32->prim.level;
+    g.prim.t = (double)d32->prim.t;
+    for (int c = 0; c < 3; ++c) g.prim.x[c] = (double)d32->prim.x[c];
+    g.margin = g.tie = -1.0;
+    g.visibility = d32->visibility;
+    g.shadow_steps = d32->shadow_steps;
+    for (int c = 0; c < 3; ++c) g.n[c] = (double)d32->n[c];
+    return g;
+}
+
+/* Per-ray binary64 record (ORC_RAY64_FIELDS doubles): kind, level (0 unless a
+ * hit), steps, visibility, shadow steps, t (t_max for a miss, 0 inside),
+ * normal, margin, tie ratio, bound on the binary32 t error, bound on the
+ * binary32 normal error (the last four -1 for given geometry). */
+static void fill_record64(const orc_setup *s, const ray64 *g, double rec[ORC_RAY64_FIELDS])
+{
+    double t = g->prim.t;
+    if (g->prim.kind == ORC_MISS_TMAX || g->prim.kind == ORC_MISS_EXIT) t = (double)s->t_max;
+    if (g->prim.kind == ORC_INSIDE) t = 0.0;
+    int given = g->margin < 0.0;
+    rec[0] = (double)g->prim.kind;
+    rec[1] = is_hit(g->prim.kind) ? (double)g->prim.level : 0.0;
+    rec[2] = (double)g->prim.steps;
+    rec[3] = (double)g->visibility;
+    rec[4] = (double)g->shadow_steps;
+    rec[5] = t;
+    for (int c = 0; c < 3; ++c) rec[6 + c] = g->n[c];
+    rec[9] = g->margin;
+    rec[10] = g->tie;
+    rec[11] = given ? -1.0 : (is_hit(g->prim.kind) ? g->prim.t_err : 0.0);
+    rec[12] = given ? -1.0 : g->n_err;
+}
+
+void orc_trace_ray64(const orc_setup *s, const double origin[3], const double dir[3],
+                     const double dir_to_light[3], double record[ORC_RAY64_FIELDS])
+{
+    double len = sqrt(dir_to_light[0] * dir_to_light[0] + dir_to_light[1] * dir_to_light[1] +
+                      dir_to_light[2] * dir_to_light[2]);
+    double l[3] = {dir_to_light[0] / len, dir_to_light[1] / len, dir_to_light[2] / len};
+    ray64 g = ray_geometry64(s, origin, dir, l);
+    fill_record64(s, &g, record);
+}
+
+double orc_sdf64(const orc_setup *s, int32_t level, const double x[3])
+{
+    return sdf64(s, level, x);
+}
+
+int32_t orc_level64(const orc_setup *s, const double x[3], double *margin)
+{
+    double m;
+    int32_t L = level64(s, x, &m);
+    if (margin) *margin = m;
+    return L;
+}
+
 /* Irradiance at x for direction n from a probe atlas: trilinear over the 8
  * probes of the cell around x, each read bilinearly from its padded
  * octahedral tile (the probe interpolation of Sec. 3.4, without visibility). */
@@ -530,11 +928,32 @@ void orc_interp_irradiance(const orc_setup *s, const double *atlas, const double
             }
 }
 
+/* What the shading of a ray needs from its geometry. */
+typedef struct {
+    int32_t kind, level, visibility;
+    double t, x[3], n[3];
+} ray_hit;
+
+static ray_hit hit_of32(const ray32 *g)
+{
+    ray_hit h = {g->prim.kind, g->prim.level, g->visibility, (double)g->prim.t,
+                 {(double)g->prim.x[0], (double)g->prim.x[1], (double)g->prim.x[2]},
+                 {(double)g->n[0], (double)g->n[1], (double)g->n[2]}};
+    return h;
+}
+
+static ray_hit hit_of64(const ray64 *g)
+{
+    ray_hit h = {g->prim.kind, g->prim.level, g->visibility, g->prim.t,
+                 {g->prim.x[0], g->prim.x[1], g->prim.x[2]}, {g->n[0], g->n[1], g->n[2]}};
+    return h;
+}
+
 /* Radiance carried back along one probe ray, and its distance (payload). */
 static void shade_ray(const orc_setup *s, const orc_frame *f, const double l64[3],
-                      const double *prev_irr, const ray32 *g, double out[4])
+                      const double *prev_irr, const ray_hit *g, double out[4])
 {
-    int32_t kind = g->prim.kind;
+    int32_t kind = g->kind;
     if (kind == ORC_MISS_TMAX || kind == ORC_MISS_EXIT) {
         for (int c = 0; c < 3; ++c) out[c] = (double)s->sky[c];
         out[3] = (double)s->t_max;
@@ -544,12 +963,8 @@ static void shade_ray(const orc_setup *s, const orc_frame *f, const double l64[3
         out[0] = out[1] = out[2] = out[3] = 0.0;
         return;
     }
-    double x[3], n[3];
-    for (int c = 0; c < 3; ++c) {
-        x[c] = (double)g->prim.x[c];
-        n[c] = (double)g->n[c];
-    }
-    const orc_level *L = &s->level[g->prim.level];
+    const double *x = g->x, *n = g->n;
+    const orc_level *L = &s->level[g->level];
     double albedo[3];
     if (L->albedo) {
         double u[3];
@@ -566,7 +981,7 @@ static void shade_ray(const orc_setup *s, const orc_frame *f, const double l64[3
         double direct = (double)f->radiance[c] * lit;
         out[c] = albedo[c] / kPi * (direct + (double)s->bounce_gain * indirect[c]);
     }
-    out[3] = (double)g->prim.t;
+    out[3] = g->t;
 }
 
 /* Eq. 3 estimated from the probe's ray samples as a ratio of weighted sums,
@@ -659,6 +1074,9 @@ typedef struct {
     int32_t count, stride, first;
     double *irr_tiles, *depth_tiles, *payload;
     int32_t *records;
+    int32_t geometry;
+    const uint8_t *given;
+    double *rays64;
     const double *dirs64;
     const float *dirs32;
     double l64[3];
@@ -680,9 +1098,24 @@ static void *frame_worker(void *arg)
         orc_probe_position(s, p, pos);
         float o[3] = {(float)pos[0], (float)pos[1], (float)pos[2]};
         for (int32_t r = 0; r < R; ++r) {
-            ray32 g = ray_geometry32(s, o, J->dirs32 + 3 * r, J->l32);
-            shade_ray(s, J->f, J->l64, J->prev_irr, &g, pl + 4 * r);
-            if (J->records) fill_record(s, &g, J->records + ((size_t)q * R + r) * 8);
+            size_t ray = (size_t)q * R + r;
+            ray_hit h;
+            if (J->geometry == ORC_GEOMETRY_64) {
+                ray64 g64;
+                if (J->given && J->given[ray]) {
+                    ray32 g = ray_geometry32(s, o, J->dirs32 + 3 * r, J->l32);
+                    g64 = ray_geometry64_given(&g);
+                } else {
+                    g64 = ray_geometry64(s, pos, J->dirs64 + 3 * r, J->l64);
+                }
+                h = hit_of64(&g64);
+                if (J->rays64) fill_record64(s, &g64, J->rays64 + ray * ORC_RAY64_FIELDS);
+            } else {
+                ray32 g = ray_geometry32(s, o, J->dirs32 + 3 * r, J->l32);
+                h = hit_of32(&g);
+                if (J->records) fill_record(s, &g, J->records + ray * 8);
+            }
+            shade_ray(s, J->f, J->l64, J->prev_irr, &h, pl + 4 * r);
         }
         if (J->payload) memcpy(J->payload + (size_t)q * R * 4, pl, sizeof(double) * 4 * R);
         blend_tile(s, J->dirs64, J->f->reset_history, pl,
@@ -694,12 +1127,14 @@ static void *frame_worker(void *arg)
     return NULL;
 }
 
-int32_t orc_update_probes(const orc_setup *s, const orc_frame *f, const double *prev_irr,
-                          const double *prev_depth, const int32_t *probes, int32_t count,
-                          double *irr_tiles, double *depth_tiles, double *payload,
-                          int32_t *records, int32_t threads)
+int32_t orc_update_probes_ex(const orc_setup *s, const orc_frame *f, const double *prev_irr,
+                             const double *prev_depth, const int32_t *probes, int32_t count,
+                             double *irr_tiles, double *depth_tiles, double *payload,
+                             int32_t *records, int32_t geometry, const uint8_t *given,
+                             double *rays64, int32_t threads)
 {
     if (s->rays <= 0 || s->max_steps < 1 || count < 0) return -1;
+    if (geometry != ORC_GEOMETRY_32 && geometry != ORC_GEOMETRY_64) return -1;
     int32_t P = s->probe_n[0] * s->probe_n[1] * s->probe_n[2];
     for (int32_t q = 0; q < count; ++q)
         if (probes[q] < 0 || probes[q] >= P) return -1;
@@ -718,7 +1153,11 @@ int32_t orc_update_probes(const orc_setup *s, const orc_frame *f, const double *
         J->s = s; J->f = f; J->prev_irr = prev_irr; J->prev_depth = prev_depth;
         J->probes = probes; J->count = count; J->stride = threads; J->first = t;
         J->irr_tiles = irr_tiles; J->depth_tiles = depth_tiles; J->payload = payload;
-        J->records = records; J->dirs64 = d64; J->dirs32 = d32;
+        J->records = geometry == ORC_GEOMETRY_32 ? records : NULL;
+        J->geometry = geometry;
+        J->given = geometry == ORC_GEOMETRY_64 ? given : NULL;
+        J->rays64 = geometry == ORC_GEOMETRY_64 ? rays64 : NULL;
+        J->dirs64 = d64; J->dirs32 = d32;
         light_direction(f->dir_to_light, J->l64, J->l32);
     }
     for (int32_t t = 1; t < threads; ++t) pthread_create(&th[t], NULL, frame_worker, &jobs[t]);
@@ -731,4 +1170,14 @@ int32_t orc_update_probes(const orc_setup *s, const orc_frame *f, const double *
     free(d64);
     free(d32);
     return rc;
+}
+
+int32_t orc_update_probes(const orc_setup *s, const orc_frame *f, const double *prev_irr,
+                          const double *prev_depth, const int32_t *probes, int32_t count,
+                          double *irr_tiles, double *depth_tiles, double *payload,
+                          int32_t *records, int32_t threads)
+{
+    return orc_update_probes_ex(s, f, prev_irr, prev_depth, probes, count, irr_tiles,
+                                depth_tiles, payload, records, ORC_GEOMETRY_32, NULL, NULL,
+                                threads);
 }

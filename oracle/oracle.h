@@ -7,17 +7,27 @@
  * CPU-baseline leg to check the GPU library. The library never links, loads or
  * calls it, and it shares no code with the library.
  *
- * Precision policy.
- *   - Every quantity that decides an integer (which cascade level a point
- *     falls in, when a sphere-traced ray stops and why, how many steps it
- *     took, whether a shadow ray is traced and whether it is blocked) is
- *     computed in IEEE binary32 following one fixed operation sequence, the
- *     precision the GPU kernel takes these decisions in. fmaf() marks every
- *     fused multiply-add of that sequence; everything else is a single
- *     correctly rounded binary32 operation. Compile with -ffp-contract=off.
- *   - Everything continuous (albedo, direct light, the multi-bounce lookup,
- *     ray radiance, the Eq. 3 irradiance estimate, depth moments and the
- *     temporal blend) is computed in binary64 from those binary32 results.
+ * Precision policy. The geometry of a ray (which cascade level each sample
+ * falls in, when a sphere-traced ray stops and why, how many steps it took,
+ * the hit point and normal, whether a shadow ray is traced and whether it is
+ * blocked) has two evaluations:
+ *   - ORC_GEOMETRY_64, the reference: the trace written plainly in IEEE
+ *     binary64 from its definition (sample x = o + t w, grid coordinate
+ *     (x - origin) / spacing, trilinear interpolation, t += relax d). Each ray
+ *     also reports its decision margin: the smallest distance, over every
+ *     decision it took, between the decision value and its threshold.
+ *   - ORC_GEOMETRY_32, the decision copy: IEEE binary32 following one fixed
+ *     operation sequence, the precision and order in which the GPU kernels
+ *     take their decisions. fmaf() marks every fused multiply-add of that
+ *     sequence; everything else is a single correctly rounded binary32
+ *     operation (compile with -ffp-contract=off). Its ray geometry can be
+ *     given to the binary64 frame update for chosen rays, so that a ray whose
+ *     binary64 decision sits within rounding of a threshold (or whose trace
+ *     is ill-conditioned) can be compared with binary32 arithmetic that took
+ *     the other branch.
+ * Everything continuous downstream of the geometry (albedo, direct light,
+ * the multi-bounce lookup, ray radiance, the Eq. 3 irradiance estimate,
+ * depth moments and the temporal blend) is computed in binary64.
  *
  * Array layouts (all row-major, x fastest):
  *   SDF level       float [n2][n1][n0], vertex (i,j,k) at origin + spacing*(i,j,k)
@@ -116,6 +126,23 @@ int32_t orc_level32(const orc_setup *s, const float x[3]);
 void orc_trace_ray32(const orc_setup *s, const float origin[3], const float dir[3],
                      const float dir_to_light[3], int32_t record[8]);
 
+/* ---- binary64 geometry -------------------------------------------------- */
+enum { ORC_GEOMETRY_32 = 0, ORC_GEOMETRY_64 = 1 };
+/* record64: [kind, level (0 unless a hit), steps, visibility, shadow steps,
+ *            t (t_max on a miss, 0 inside), nx, ny, nz,
+ *            margin: smallest |decision value - threshold| over the ray's
+ *                    decisions (scene units),
+ *            tie ratio: smallest margin / error bound of a binary32
+ *                    evaluation of that decision (below 1: a near-tie),
+ *            bound on a binary32 evaluation's |t| error (hits; 0 otherwise),
+ *            bound on its normal error (L-inf)]
+ * The last four are -1 for rays whose geometry was given. */
+#define ORC_RAY64_FIELDS 13
+double orc_sdf64(const orc_setup *s, int32_t level, const double x[3]);
+int32_t orc_level64(const orc_setup *s, const double x[3], double *margin);
+void orc_trace_ray64(const orc_setup *s, const double origin[3], const double dir[3],
+                     const double dir_to_light[3], double record[ORC_RAY64_FIELDS]);
+
 /* ---- binary64 radiometry and blending ---------------------------------- */
 void orc_interp_irradiance(const orc_setup *s, const double *irr_atlas, const double x[3],
                            const double n[3], double out[3]);
@@ -130,6 +157,19 @@ int32_t orc_update_probes(const orc_setup *s, const orc_frame *f,
                           double *payload /* [count][rays][4] or NULL */,
                           int32_t *records /* [count][rays][8] or NULL */,
                           int32_t threads);
+/* The frame update with a choice of geometry. ORC_GEOMETRY_32 is
+ * orc_update_probes. ORC_GEOMETRY_64 traces from the binary64 probe position
+ * along the binary64 ray directions and light; given ([count][rays] or NULL)
+ * marks rays whose geometry (outcome, level, steps, hit point and distance,
+ * normal, shadow result) is taken from the binary32 sequence instead, with
+ * everything downstream (shading, Eq. 3, blend) still in binary64; rays64
+ * ([count][rays][ORC_RAY64_FIELDS] or NULL) receives the records; records is
+ * ignored. */
+int32_t orc_update_probes_ex(const orc_setup *s, const orc_frame *f, const double *prev_irr,
+                             const double *prev_depth, const int32_t *probes, int32_t count,
+                             double *irr_tiles, double *depth_tiles, double *payload,
+                             int32_t *records, int32_t geometry, const uint8_t *given,
+                             double *rays64, int32_t threads);
 
 #ifdef __cplusplus
 }

@@ -13,6 +13,7 @@ import oracle
 from tests import test_learned_pins as lp
 from tests import test_cluster_pins as cp
 from tests import test_relocation_pins as rp
+from tests import test_oracle_fp64_pins as p64
 from tests import test_oracle_pins as pins
 from tests.conftest import ROOT
 
@@ -56,6 +57,40 @@ MUTANTS = [
      [rp.test_plane_probes_rise_to_the_threshold]),
     ("inside_ignored", "if (primary && k == 0 && d < 0.0f) {", "if (primary && k == 0 && d < -1e30f) {",
      [pins.test_miss_inside_and_exhaustion_outcomes]),
+    # binary64 trilinear (albedo in both geometries, distance in binary64)
+    ("trilinear64_channel_stride", "acc += w * (double)grid[v * comps + comp];",
+     "acc += w * (double)grid[v + comp];",
+     [lambda: p64.test_affine_albedo_field_is_reproduced(0),
+      lambda: p64.test_affine_albedo_field_is_reproduced(1)]),
+    ("trilinear64_axis", "                double w = (dx ? f[0] : 1.0 - f[0]) * (dy ? f[1] : 1.0 - f[1]) *\n                           (dz ? f[2] : 1.0 - f[2]);",
+     "                double w = (dx ? f[0] : 1.0 - f[0]) * (dy ? f[2] : 1.0 - f[2]) *\n                           (dz ? f[1] : 1.0 - f[1]);",
+     [p64.test_sdf64_exact_at_vertices_and_on_linear_fields,
+      lambda: p64.test_affine_albedo_field_is_reproduced(0)]),
+    # an exhausted shadow ray counts as blocked
+    ("shadow_exhaustion32_lit", "        trace32_result sh = trace32(s, xs, l, 0);\n        g.visibility = is_hit(sh.kind) ? 0 : 1;",
+     "        trace32_result sh = trace32(s, xs, l, 0);\n        g.visibility = sh.kind == ORC_HIT ? 0 : 1;",
+     [lambda: p64.test_exhausted_shadow_ray_counts_as_blocked(0)]),
+    ("shadow_exhaustion64_lit", "        min_into(&g.tie, sh.tie);\n        g.visibility = is_hit(sh.kind) ? 0 : 1;",
+     "        min_into(&g.tie, sh.tie);\n        g.visibility = sh.kind == ORC_HIT ? 0 : 1;",
+     [lambda: p64.test_exhausted_shadow_ray_counts_as_blocked(1)]),
+    # a vanishing gradient's normal faces the ray
+    ("normal32_fallback_sign", "        for (int c = 0; c < 3; ++c) n[c] = -w[c];\n        return;",
+     "        for (int c = 0; c < 3; ++c) n[c] = w[c];\n        return;",
+     [lambda: p64.test_vanishing_gradient_normal_faces_the_ray(0)]),
+    ("normal64_fallback_sign", "        for (int c = 0; c < 3; ++c) n[c] = -w[c];\n        return 1;",
+     "        for (int c = 0; c < 3; ++c) n[c] = w[c];\n        return 1;",
+     [lambda: p64.test_vanishing_gradient_normal_faces_the_ray(1)]),
+    # binary64 trace, level choice and margins
+    ("trace64_step", "        t += relax * d;\n        e = fabs", "        t += relax * d * 0.5;\n        e = fabs",
+     [p64.test_plane_trace64_closed_form_and_margin]),
+    ("level64_not_shrunk", "double shrink = L < s->num_levels - 1 ? 1.0 : 0.0;",
+     "double shrink = L < s->num_levels - 1 ? 0.0 : 0.0;",
+     [p64.test_level64_choice_and_margin]),
+    ("hit_margin_dropped_eps", "decision(&r, fabs(d - eps), derr);", "decision(&r, fabs(d), derr);",
+     [p64.test_plane_trace64_closed_form_and_margin]),
+    # binary32 error bound: drift amplification along the ray dropped
+    ("bound_no_amplification", "e = fabs(1.0 + relax * gw) * e + relax", "e = e + relax",
+     [p64.test_binary32_drift_stays_within_derived_bounds_on_the_open_scene]),
 ]
 
 
