@@ -60,7 +60,12 @@ class Setup(ctypes.Structure):
                 ("bounce_gain", ctypes.c_float), ("depth_sharpness", ctypes.c_float),
                 ("shadow_bias", ctypes.c_float), ("relax", ctypes.c_float),
                 ("sky", ctypes.c_float * 3), ("albedo", ctypes.c_float * 3),
-                ("probe_pos", ctypes.c_void_p)]
+                ("probe_pos", ctypes.c_void_p), ("analytic", ctypes.c_void_p)]
+
+
+class AnalyticSceneDesc(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("kind", ctypes.c_void_p), ("center", ctypes.c_void_p),
+                ("half", ctypes.c_void_p), ("albedo", ctypes.c_void_p)]
 
 
 class FrameDesc(ctypes.Structure):
@@ -129,7 +134,9 @@ def _p(a: np.ndarray):
 class Checker:
     """A reference setup built from a workload (keeps its arrays alive)."""
 
-    def __init__(self, workload, **overrides):
+    def __init__(self, workload, analytic: bool = False, **overrides):
+        """analytic=True: trace the workload's primitives (binary32 centres and half
+        extents, per-primitive albedo) instead of its baked grid levels."""
         w = workload
         prm = w.params
         vals = dict(rays=prm.rays_per_probe, max_steps=prm.max_steps, irr_res=prm.irr_res,
@@ -140,8 +147,19 @@ class Checker:
         vals.update(overrides)
         s = Setup()
         self._keep = []
-        s.num_levels = len(w.levels)
-        for k, lv in enumerate(w.levels):
+        levels = [] if analytic else w.levels
+        s.num_levels = len(levels)
+        if analytic:
+            pr = w.prims
+            kind = np.ascontiguousarray(pr.kind, dtype=np.int32)
+            cen = np.ascontiguousarray(pr.center, dtype=np.float32)
+            hal = np.ascontiguousarray(pr.half, dtype=np.float32)
+            alb = np.ascontiguousarray(pr.albedo, dtype=np.float64)
+            desc = AnalyticSceneDesc(len(kind), kind.ctypes.data, cen.ctypes.data,
+                                     hal.ctypes.data, alb.ctypes.data)
+            self._keep += [kind, cen, hal, alb, desc]
+            s.analytic = ctypes.addressof(desc)
+        for k, lv in enumerate(levels):
             sdf = np.ascontiguousarray(lv.sdf, dtype=np.float32)
             self._keep.append(sdf)
             s.level[k].n[:] = list(lv.n)

@@ -24,6 +24,7 @@
  */
 #define _GNU_SOURCE
 #include "oracle.h"
+#include "cluster.h"
 
 #include <math.h>
 #include <pthread.h>
@@ -377,12 +378,102 @@ void orc_relocate_probe(const orc_setup *s, int32_t p, const float last[3], floa
 
 typedef struct {
     trace32_result prim;
+    int32_t nearest;        /* analytic scenes: the nearest primitive at the hit */
     float n[3];
     int32_t visibility;     /* 1 lit, 0 blocked, -1 not traced */
     int32_t shadow_steps;
 } ray32;
 
 static int is_hit(int32_t kind) { return kind == ORC_HIT || kind == ORC_HIT_EXHAUSTED; }
+
+/* ---- analytic scenes ----------------------------------------------------- */
+
+/* The scene distance at x: the smallest primitive distance; *nearest receives
+ * the primitive that gives it (the lowest index on a tie). */
+static float analytic_distance32(const orc_analytic_scene *a, const float x[3],
+                                 int32_t *nearest)
+{
+    float best = INFINITY;
+    int32_t arg = -1;
+    for (int32_t m = 0; m < a->count; ++m) {
+        float d = orc_prim_distance32(a->kind[m], a->center + 3 * m, a->half + 3 * m, x);
+        if (d < best) {
+            best = d;
+            arg = m;
+        }
+    }
+    *nearest = arg;
+    return best;
+}
+
+/* The same sphere trace as trace32 on the primitives' distance; no grid box, so
+ * a ray misses only past t_max. */
+static trace32_result trace_analytic32(const orc_setup *s, const float o[3], const float w[3],
+                                       int primary, int32_t *nearest)
+{
+    trace32_result r = {ORC_HIT_EXHAUSTED, s->max_steps, 0, 0.0f, {0.0f, 0.0f, 0.0f}};
+    float tt = 0.0f;
+    *nearest = -1;
+    for (int32_t k = 0; k < s->max_steps; ++k) {
+        if (tt > s->t_max) {
+            r.kind = ORC_MISS_TMAX;
+            r.steps = k;
+            return r;
+        }
+        float x[3];
+        for (int c = 0; c < 3; ++c) x[c] = fmaf(tt, w[c], o[c]);
+        float dist = analytic_distance32(s->analytic, x, nearest);
+        r.t = tt;
+        memcpy(r.x, x, sizeof x);
+        if (primary && k == 0 && dist < 0.0f) {
+            r.kind = ORC_INSIDE;
+            r.steps = 1;
+            return r;
+        }
+        if (dist < s->hit_eps) {
+            r.kind = ORC_HIT;
+            r.steps = k + 1;
+            return r;
+        }
+        tt = fmaf(s->relax, dist, tt);
+    }
+    return r;
+}
+
+/* Normal at x from the gradient of primitive m's distance: a sphere's radial
+ * direction x - c; outside a box the offset from its nearest point, inside it the
+ * signed axis of the face nearest to x (the largest q, lowest axis on a tie);
+ * normalised as the grid normal, -w when the gradient vanishes. */
+static void normal_analytic32(const orc_analytic_scene *a, int32_t m, const float x[3],
+                              const float w[3], float n[3])
+{
+    const float *c = a->center + 3 * m, *h = a->half + 3 * m;
+    float d[3] = {x[0] - c[0], x[1] - c[1], x[2] - c[2]};
+    float g[3] = {0.0f, 0.0f, 0.0f};
+    if (a->kind[m] == 0) {
+        for (int k = 0; k < 3; ++k) g[k] = d[k];
+    } else {
+        float q[3];
+        for (int k = 0; k < 3; ++k) q[k] = fabsf(d[k]) - h[k];
+        float qm = fmaxf(q[0], fmaxf(q[1], q[2]));
+        if (qm > 0.0f) {
+            for (int k = 0; k < 3; ++k) {
+                float o = fmaxf(q[k], 0.0f);
+                g[k] = d[k] >= 0.0f ? o : -o;
+            }
+        } else {
+            int ax = q[0] >= q[1] ? (q[0] >= q[2] ? 0 : 2) : (q[1] >= q[2] ? 1 : 2);
+            g[ax] = d[ax] >= 0.0f ? 1.0f : -1.0f;
+        }
+    }
+    float len2 = fmaf(g[2], g[2], fmaf(g[1], g[1], g[0] * g[0]));
+    if (!(len2 >= 1e-24f)) {
+        for (int k = 0; k < 3; ++k) n[k] = -w[k];
+        return;
+    }
+    float inv = 1.0f / sqrtf(len2);
+    for (int k = 0; k < 3; ++k) n[k] = g[k] * inv;
+}
 
 /* Primary trace, hit normal and the SDF shadow ray toward the light. The
  * shadow ray starts at x + bias*n, is traced only where n.l > 0, and counts as
@@ -392,14 +483,28 @@ static ray32 ray_geometry32(const orc_setup *s, const float o[3], const float w[
 {
     ray32 g;
     memset(&g, 0, sizeof g);
-    g.prim = trace32(s, o, w, 1);
+    g.nearest = -1;
+    if (s->analytic)
+        g.prim = trace_analytic32(s, o, w, 1, &g.nearest);
+    else
+        g.prim = trace32(s, o, w, 1);
     g.visibility = -1;
     if (!is_hit(g.prim.kind)) return g;
-    normal32(s, g.prim.level, g.prim.x, w, g.n);
+    if (s->analytic)
+        normal_analytic32(s->analytic, g.nearest, g.prim.x, w, g.n);
+    else
+        normal32(s, g.prim.level, g.prim.x, w, g.n);
     float ndl = fmaf(g.n[2], l[2], fmaf(g.n[1], l[1], g.n[0] * l[0]));
     if (ndl > 0.0f) {
         float xs[3];
         for (int c = 0; c < 3; ++c) xs[c] = fmaf(g.n[c], s->shadow_bias, g.prim.x[c]);
+        if (s->analytic) {
+            int32_t unused;
+            trace32_result sa = trace_analytic32(s, xs, l, 0, &unused);
+            g.visibility = is_hit(sa.kind) ? 0 : 1;
+            g.shadow_steps = sa.steps;
+            return g;
+        }
         trace32_result sh = trace32(s, xs, l, 0);
         g.visibility = is_hit(sh.kind) ? 0 : 1;
         g.shadow_steps = sh.steps;
@@ -932,20 +1037,22 @@ void orc_interp_irradiance(const orc_setup *s, const double *atlas, const double
 typedef struct {
     int32_t kind, level, visibility;
     double t, x[3], n[3];
+    const double *albedo;   /* analytic scenes: the nearest primitive's albedo */
 } ray_hit;
 
-static ray_hit hit_of32(const ray32 *g)
+static ray_hit hit_of32(const orc_setup *s, const ray32 *g)
 {
     ray_hit h = {g->prim.kind, g->prim.level, g->visibility, (double)g->prim.t,
                  {(double)g->prim.x[0], (double)g->prim.x[1], (double)g->prim.x[2]},
-                 {(double)g->n[0], (double)g->n[1], (double)g->n[2]}};
+                 {(double)g->n[0], (double)g->n[1], (double)g->n[2]}, NULL};
+    if (s->analytic && g->nearest >= 0) h.albedo = s->analytic->albedo + 3 * g->nearest;
     return h;
 }
 
 static ray_hit hit_of64(const ray64 *g)
 {
     ray_hit h = {g->prim.kind, g->prim.level, g->visibility, g->prim.t,
-                 {g->prim.x[0], g->prim.x[1], g->prim.x[2]}, {g->n[0], g->n[1], g->n[2]}};
+                 {g->prim.x[0], g->prim.x[1], g->prim.x[2]}, {g->n[0], g->n[1], g->n[2]}, NULL};
     return h;
 }
 
@@ -966,7 +1073,9 @@ static void shade_ray(const orc_setup *s, const orc_frame *f, const double l64[3
     const double *x = g->x, *n = g->n;
     const orc_level *L = &s->level[g->level];
     double albedo[3];
-    if (L->albedo) {
+    if (g->albedo) {
+        for (int c = 0; c < 3; ++c) albedo[c] = g->albedo[c];
+    } else if (L->albedo) {
         double u[3];
         for (int c = 0; c < 3; ++c) u[c] = (x[c] - L->origin[c]) / L->spacing;
         for (int c = 0; c < 3; ++c) albedo[c] = trilinear64(L->albedo, 3, c, L->n, u);
@@ -1112,7 +1221,7 @@ static void *frame_worker(void *arg)
                 if (J->rays64) fill_record64(s, &g64, J->rays64 + ray * ORC_RAY64_FIELDS);
             } else {
                 ray32 g = ray_geometry32(s, o, J->dirs32 + 3 * r, J->l32);
-                h = hit_of32(&g);
+                h = hit_of32(s, &g);
                 if (J->records) fill_record(s, &g, J->records + ray * 8);
             }
             shade_ray(s, J->f, J->l64, J->prev_irr, &h, pl + 4 * r);
@@ -1135,6 +1244,7 @@ int32_t orc_update_probes_ex(const orc_setup *s, const orc_frame *f, const doubl
 {
     if (s->rays <= 0 || s->max_steps < 1 || count < 0) return -1;
     if (geometry != ORC_GEOMETRY_32 && geometry != ORC_GEOMETRY_64) return -1;
+    if (s->analytic && geometry != ORC_GEOMETRY_32) return -1;
     int32_t P = s->probe_n[0] * s->probe_n[1] * s->probe_n[2];
     for (int32_t q = 0; q < count; ++q)
         if (probes[q] < 0 || probes[q] >= P) return -1;

@@ -64,6 +64,17 @@ typedef struct {
     const float *albedo;  /* NULL: the constant albedo of the setup */
 } orc_level;
 
+/* Analytic scene (Sec. 3.1: the scene as a union of primitives; Sec. 3.3 queries
+ * their distance): kind 0 sphere (radius half[.][0]), 1 axis-aligned box (half
+ * extents). Distances in binary32 from the binary32 centre and half extents. */
+typedef struct {
+    int32_t count;
+    const int32_t *kind;          /* [count] */
+    const float *center;          /* [count][3] */
+    const float *half;            /* [count][3] */
+    const double *albedo;         /* [count][3] */
+} orc_analytic_scene;
+
 typedef struct {
     int32_t num_levels;           /* level 0 finest; levels are nested */
     orc_level level[ORC_MAX_LEVELS];
@@ -84,6 +95,13 @@ typedef struct {
     float sky[3];
     float albedo[3];
     const float *probe_pos;       /* [P][3] relocated positions, or NULL: the grid */
+    /* Non-NULL: the geometry comes from these primitives instead of the grid
+     * levels (num_levels is ignored). The trace's sample distance is the
+     * minimum over the primitives; there is no grid box, so a ray only misses
+     * past t_max. At a hit the normal is the normalised gradient of the nearest
+     * primitive (lowest index on a tie) and the albedo is that primitive's.
+     * Only ORC_GEOMETRY_32 is provided for this mode. */
+    const orc_analytic_scene *analytic;
 } orc_setup;
 
 typedef struct {

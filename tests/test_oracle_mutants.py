@@ -11,6 +11,7 @@ import pytest
 
 import oracle
 from tests import test_learned_pins as lp
+from tests import test_analytic_frame_pins as ap
 from tests import test_cluster_pins as cp
 from tests import test_relocation_pins as rp
 from tests import test_oracle_fp64_pins as p64
@@ -91,6 +92,20 @@ MUTANTS = [
     # binary32 error bound: drift amplification along the ray dropped
     ("bound_no_amplification", "e = fabs(1.0 + relax * gw) * e + relax", "e = e + relax",
      [p64.test_binary32_drift_stays_within_derived_bounds_on_the_open_scene]),
+    # analytic-scene mode
+    ("analytic_sphere_normal_sign", "for (int k = 0; k < 3; ++k) g[k] = d[k];",
+     "for (int k = 0; k < 3; ++k) g[k] = -d[k];",
+     [ap.test_sphere_hit_distance_and_radial_normal]),
+    ("analytic_box_normal_side", "g[k] = d[k] >= 0.0f ? o : -o;", "g[k] = o;",
+     [ap.test_box_face_normals_and_hit_distance_closed_form]),
+    ("analytic_albedo_of_first_primitive",
+     "if (s->analytic && g->nearest >= 0) h.albedo = s->analytic->albedo + 3 * g->nearest;",
+     "if (s->analytic && g->nearest >= 0) h.albedo = s->analytic->albedo;",
+     [ap.test_lambert_with_each_primitives_own_albedo]),
+    ("analytic_tie_to_higher_index", "if (d < best) {", "if (d <= best) {",
+     [ap.test_nearest_primitive_gives_the_normal_inside_overlapping_boxes]),
+    ("analytic_shadow_ignored", "            g.visibility = is_hit(sa.kind) ? 0 : 1;",
+     "            g.visibility = 1;", [ap.test_shadow_ray_matches_segment_occluder_test]),
 ]
 
 
