@@ -39,6 +39,10 @@ constexpr int kMSlots = 5;        // 16-texel M-tiles per wave per pass
 // Epilogue of both blend kernels for one 16x16 accumulator tile: lane holds
 // D[4*krow + r][row]. Normalises, mixes with the previous interior (hysteresis, or
 // none for rejected probes) and writes interior and border texels.
+// kClamp (precision form): the depth map's second moment is raised to the square of
+// its first where rounding left it below (the moments of any set of depths satisfy
+// E[t^2] >= E[t]^2); the two moments of a probe sit in neighbouring lanes.
+template <bool kClamp = false>
 __device__ __forceinline__ void blend_epilogue(const BlendArgs &a, const float *s_h, const int *s_pid, int np,
                                                bool irr, int mtile, int n, int row, int krow,
                                                floatx4 acc) {
@@ -62,7 +66,11 @@ __device__ __forceinline__ void blend_epilogue(const BlendArgs &a, const float *
         const float nrm = norm[t];
         const float old = old_tile[((j + 1) * side + (i + 1)) * comps + c];
         const float u = acc[r] * nrm;
-        const float v = nrm < 0.0f ? old : fmaf(h, old - u, u);
+        float v = nrm < 0.0f ? old : fmaf(h, old - u, u);
+        if (kClamp && !irr) {
+            const float first = __shfl_xor(v, 1);  // lane pairs (row, row ^ 1) hold (E[t], E[t^2])
+            if (c == 1) v = fmaxf(v, first * first);
+        }
         store_with_border(new_tile, res, comps, i, j, c, v);
     }
 }
@@ -78,7 +86,7 @@ constexpr int kEpilogueFloats = kBlendProbes * 256 * 2;
 // value where all weights vanish), then writes every probe's whole padded tile,
 // interior and border, in order -- coalesced reads and stores instead of one
 // scattered store per texel and border copy.
-template <int kN, int kComps>
+template <int kN, int kComps, bool kClamp = false>
 __device__ __forceinline__ void epilogue_map_lds(const float *prev, float *next, const float *norm,
                                                  const float *s_h, const int *s_pid, int np,
                                                  float *buf) {
@@ -94,6 +102,11 @@ __device__ __forceinline__ void epilogue_map_lds(const float *prev, float *next,
         const float u = buf[e];
         buf[e] = nrm < 0.0f ? old : fmaf(s_h[q], old - u, u);
     }
+    if (kClamp) {  // moments (kComps == 2): E[t^2] no smaller than E[t]^2
+        __syncthreads();
+        for (int e = tid; e < np * T; e += blockDim.x)
+            buf[2 * e + 1] = fmaxf(buf[2 * e + 1], buf[2 * e] * buf[2 * e]);
+    }
     __syncthreads();
     for (int e = tid; e < np * kTile; e += blockDim.x) {
         const int q = e / kTile, rem = e - q * kTile;
@@ -107,7 +120,8 @@ __device__ __forceinline__ void epilogue_map_lds(const float *prev, float *next,
 
 // Epilogue of the standard layout (8x8 irradiance in slot 0 of every wave, 16x16
 // depth in slots 1..4) for one workgroup's probes; buf: kEpilogueFloats of LDS that
-// the caller no longer needs.
+// the caller no longer needs. kClamp: as for blend_epilogue.
+template <bool kClamp = false>
 __device__ __forceinline__ void blend_epilogue_std(const BlendArgs &a, const float *s_h,
                                                    const int *s_pid, int np, int wave, int row,
                                                    int krow, const floatx4 (&acc)[kMSlots][3],
@@ -136,7 +150,7 @@ __device__ __forceinline__ void blend_epilogue_std(const BlendArgs &a, const flo
             }
         }
     }
-    epilogue_map_lds<16, 2>(a.prev_depth, a.new_depth, a.norm_d, s_h, s_pid, np, buf);
+    epilogue_map_lds<16, 2, kClamp>(a.prev_depth, a.new_depth, a.norm_d, s_h, s_pid, np, buf);
 }
 
 typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
@@ -243,7 +257,7 @@ __device__ __forceinline__ void blend16_block(const BlendArgs &a, int pb) {
             }
         }
         if (kStd) {
-            blend_epilogue_std(a, s_h, s_pid, np, wave, row, kgrp, acc, sbuf);
+            blend_epilogue_std<true>(a, s_h, s_pid, np, wave, row, kgrp, acc, sbuf);
             continue;
         }
 #pragma unroll
@@ -253,8 +267,8 @@ __device__ __forceinline__ void blend16_block(const BlendArgs &a, int pb) {
 #pragma unroll
             for (int n = 0; n < 3; ++n) {
                 if (!irr && n == 2) break;
-                blend_epilogue(a, s_h, s_pid, np, irr, irr ? mt[s] : mt[s] - mti, n, row, kgrp,
-                               acc[s][n]);
+                blend_epilogue<true>(a, s_h, s_pid, np, irr, irr ? mt[s] : mt[s] - mti, n, row,
+                                     kgrp, acc[s][n]);
             }
         }
     }

@@ -101,3 +101,58 @@ def rel_close(gpu, ref, rel=1e-4, floor_frac=1e-3):
     ratio = np.abs(gpu - ref) / scale
     worst = float(ratio.max()) if ratio.size else 0.0
     return worst <= rel, worst
+
+
+# ---------------------------------------------------------- precision form ---
+#
+# SDF in binary16 (clamped to +-65504, rounded to nearest even), blend on FP16 /
+# BF16 MFMA with FP32 accumulation. Decisions are the binary32 sequence on the
+# rounded grid, so they can be compared bit for bit with the checker run on that
+# grid. Map bounds follow from the operand rounding (unit roundoff u16 = 2^-11 for
+# FP16, u_bf = 2^-8 for BF16) in the normalised sums:
+#   irradiance  |dE|     <= 4 u16 * pi * max L        (weights and radiance rounded)
+#   depth       |dE[t]|  <= B1 = 2 u_bf * t_max       (weights and t rounded)
+#               |dE[t2]| <= 2 u_bf * t_max^2, and where the second moment is raised
+#                           to E[t]^2 (it fell below through rounding) at most
+#                           2 t_max B1 + B1^2
+# plus the binary32 accumulation and hysteresis (far below these); hysteresis mixes
+# in the exact previous value, so the bound scales by (1 - h) at most 1.
+
+U16 = 2.0 ** -11
+UBF = 2.0 ** -8
+
+
+def fp16_grid(w):
+    """The workload with every SDF level rounded as the precision form stores it."""
+    import copy
+    w2 = copy.deepcopy(w)
+    for lv in w2.levels:
+        lv.sdf = np.clip(lv.sdf, -65504.0, 65504.0).astype(np.float16).astype(np.float32)
+    return w2
+
+
+def precision_bounds(radiance_max: float, t_max: float):
+    """Per-element bounds (irradiance, E[t], E[t^2]) of the precision form against the
+    checker on the rounded grid; radiance_max bounds every radiance the blend sees
+    (rays' payload and the previous irradiance)."""
+    b1 = 2 * UBF * t_max
+    return (4 * U16 * math.pi * radiance_max, b1,
+            max(2 * UBF * t_max ** 2, 2 * t_max * b1 + b1 * b1))
+
+
+def check_precision_maps(irr, dep, ref_irr, ref_dep, radiance_max: float, t_max: float,
+                         scale: float = 1.0):
+    """Assert the precision-form bounds (times ``scale``) and E[t^2] >= E[t]^2 on every
+    texel; returns the worst error of each map over its bound."""
+    bi, b1, b2 = precision_bounds(radiance_max, t_max)
+    ei = float(np.abs(np.asarray(irr, np.float64) - ref_irr).max())
+    e1 = float(np.abs(np.asarray(dep[..., 0], np.float64) - ref_dep[..., 0]).max())
+    e2 = float(np.abs(np.asarray(dep[..., 1], np.float64) - ref_dep[..., 1]).max())
+    assert ei <= scale * bi, f"irradiance error {ei:.3e} > bound {scale * bi:.3e}"
+    assert e1 <= scale * b1, f"E[t] error {e1:.3e} > bound {scale * b1:.3e}"
+    assert e2 <= scale * b2, f"E[t^2] error {e2:.3e} > bound {scale * b2:.3e}"
+    m1 = np.asarray(dep[..., 0], np.float32)
+    m2 = np.asarray(dep[..., 1], np.float32)
+    bad = m2 < m1 * m1
+    assert not bad.any(), f"{int(bad.sum())} texels with E[t^2] < E[t]^2"
+    return dict(irradiance=ei / bi, depth_mean=e1 / b1, depth_second=e2 / b2)

@@ -1,14 +1,17 @@
 """GPU tests of the batched form: a batch of uneven scenes, updated by one graph
 replay per frame, gives every scene the maps of its own single-scene context in
-the precision form, bit for bit (those are checked against the reference checker
-by the precision-form tests); autotuning changes no result; per-scene latencies
-come from the device clock."""
+the precision form, bit for bit; every scene of the benchmark's batch (after
+autotuning) and a batch with the form's largest probe grid match the reference
+checker on the binary16-rounded grid within the precision form's derived bounds;
+autotuning changes no result; per-scene latencies come from the device clock."""
 import sys
 
 import numpy as np
 import pytest
 
+import oracle
 import scenegen
+from tests import helpers as H
 
 pytestmark = pytest.mark.gpu
 
@@ -120,3 +123,67 @@ def test_scene_latencies_from_the_device_clock(S):
     probes, rays = S.sdfddgi_batch_sizes(b)
     assert probes == sum(int(np.prod(sp.probes.n)) for sp in specs)
     assert rays == sum(int(np.prod(sp.probes.n)) * sp.params.rays_per_probe for sp in specs)
+
+
+# ------------------------------------------------------ against the checker ---
+
+def checker_two_frames(w, seeds):
+    """Frames 0 (history rejected, zero atlas) and 1 of a scene on its binary16 grid:
+    the checker's maps after each, and the largest radiance the blend saw."""
+    chk = oracle.Checker(H.fp16_grid(w))
+    si, sd = scenegen.atlas_shapes(w.num_probes, w.params)
+    irr, dep = np.zeros(si), np.zeros(sd)
+    out, lmax = [], 0.0
+    for f in range(2):
+        fr = scenegen.Frame(w.frames[f].dir_to_light, w.frames[f].radiance_rgb, seeds[f])
+        prev_max = float(irr.max())
+        irr, dep, pl, _ = chk.update_probes(fr, f == 0, irr, dep, want_payload=True, threads=16)
+        lmax = max(lmax, float(pl[..., :3].max()), prev_max)
+        out.append((irr, dep, lmax))
+    return out
+
+
+def check_batch_against_checker(S, specs, seeds, autotune: bool):
+    works = [scenegen.spec_workload(sp) for sp in specs]
+    b = S.batch_from_specs(specs, baked=[w.levels[0] for w in works])
+    if autotune:
+        tuning, tried = S.sdfddgi_batch_autotune(b, lights_of(specs, 0), seeds[0], 1)
+        announce(f"autotuned over {tried} candidates: {tuning}")
+    got = []
+    for f in range(2):
+        S.sdfddgi_batch_update_frame(b, lights_of(specs, f), seeds[f])
+        got.append([tuple(to_host(x) for x in S.sdfddgi_batch_get_maps(b, s))
+                    for s in range(len(specs))])
+    S.sdfddgi_batch_destroy(b)
+    worst = {}
+    for s, w in enumerate(works):
+        t_max = float(np.float32(w.params.t_max))
+        for f, (ri, rd, lmax) in enumerate(checker_two_frames(w, seeds)):
+            gi, gd = got[f][s]
+            # frame 1 reads frame 0's maps (multi-bounce) and mixes them in: the
+            # frame-0 error carries over at most once more (albedo < 1)
+            over = H.check_precision_maps(gi, gd, ri, rd, lmax, t_max, scale=1.0 + f)
+            for k, v in over.items():
+                worst[k] = max(worst.get(k, 0.0), v)
+    announce(f"worst error / bound over {len(specs)} scenes, 2 frames: {worst}")
+    return worst
+
+
+def test_benchmark_batch_every_scene_matches_checker(S):
+    """The benchmark's 64 scenes (SDF 32^3-190^3, probe grids up to 23x12x23, 64-512
+    rays), autotuned as the benchmark does, frames 0 and 1."""
+    specs, seeds = scenegen.batch_scene_specs(0, 64, frames=3)
+    announce("benchmark batch of 64 scenes against the checker")
+    check_batch_against_checker(S, specs, seeds, autotune=True)
+
+
+def test_largest_probe_grid_batch_matches_checker(S):
+    """A 24x12x24 probe grid at 512 rays over a 176^3 grid, beside two small scenes."""
+    big, seeds = scenegen.batch_scene_specs(7, 1, frames=3, sdf_range=(176, 176),
+                                            probes_xz=(24, 24), probes_y=(12, 12), rays=(512,))
+    small, _ = scenegen.batch_scene_specs(8, 2, frames=3, sdf_range=(32, 48),
+                                          probes_xz=(4, 6), probes_y=(4, 5), rays=(64, 128))
+    specs = big + small
+    assert specs[0].probes.n == (24, 12, 24) and specs[0].params.rays_per_probe == 512
+    announce(f"largest-grid batch: {[(sp.probes.n, sp.levels[0][0][0]) for sp in specs]}")
+    check_batch_against_checker(S, specs, seeds, autotune=False)

@@ -182,10 +182,12 @@ def make_ctx(S, w, tau, flags=0, learned_rays=32):
 
 
 def warm(S, ctx, w, frames=2):
-    for fr in w.frames[:frames]:
-        S.sdfddgi_update_frame(ctx, fr.dir_to_light, fr.radiance_rgb, fr.rotation_seed)
-    irr, dep = S.sdfddgi_get_maps(ctx)
-    return to_host(irr).astype(np.float64), to_host(dep).astype(np.float64)
+    """Load the checker's maps after the first ``frames`` plain frames (rounded to
+    binary32) into the context: the previous atlas both sides start from."""
+    irr, dep = oracle.Checker(w).run_frames(w.frames[:frames])[-1]
+    irr, dep = irr.astype(np.float32), dep.astype(np.float32)
+    S.sdfddgi_set_maps(ctx, to_dev(irr), to_dev(dep))
+    return irr.astype(np.float64), dep.astype(np.float64)
 
 
 def test_examples_match_checker(S):
@@ -218,10 +220,10 @@ def test_examples_match_checker(S):
     np.testing.assert_allclose(targ[:, 3], ref_q, rtol=1e-5)
 
 
-def run_learned(S, w, theta, tau, frames, flags=0):
+def run_learned(S, w, theta, tau, frames, flags=0, warm_frames=2):
     ctx = make_ctx(S, w, tau, flags=flags)
     den = S.sdfddgi_denoiser_create(np.asarray(theta, dtype=np.float32), S_IRR, D_DEPTH)
-    irr, dep = warm(S, ctx, w)
+    irr, dep = warm(S, ctx, w, warm_frames)
     out = []
     for fr in frames:
         S.sdfddgi_update_frame_learned(ctx, den, fr.dir_to_light, fr.radiance_rgb,
@@ -245,10 +247,10 @@ def test_learned_frame_matches_checker(S):
     irr0, dep0 = warm(S, ctx, w)
     probe = ck.learned_frame(w.frames[2], False, irr0, dep0, th, S_IRR, D_DEPTH, math.inf, 32)
     tau = float(np.median(probe["mean_error"]))
-    (irr, dep), res = run_learned(S, w, th, tau, [w.frames[2], w.frames[3]])
-    prev = (irr, dep)
-    for k, r in enumerate(res):
+    for k in range(2):
+        # frame 2 + k from the checker's maps after frames 0 .. 1 + k
         fr = w.frames[2 + k]
+        prev, (r,) = run_learned(S, w, th, tau, [fr], warm_frames=2 + k)
         ref = ck.learned_frame(fr, False, prev[0], prev[1], th, S_IRR, D_DEPTH, tau, 32)
         # mean predicted error: exp(o3) moves by at most the output bound of o3
         M3 = magnitude(th, ref["features"].reshape(-1, F))[:, 3].reshape(P, -1)
@@ -282,7 +284,6 @@ def test_learned_frame_matches_checker(S):
         assert np.all(np.abs(got - want) <= bound[acc] + 1e-4 * np.abs(want) + 1e-6)
         # and typically far closer than the bound
         assert np.median(np.abs(got - want) / (np.abs(want) + 1e-3)) <= 1e-4
-        prev = (r["irr"], r["depth"])
 
 
 def test_all_fallback_is_the_plain_frame_bit_for_bit(S):

@@ -362,28 +362,7 @@ def test_kernel_timing_reports_positive_times(S):
 
 # ---------------------------------------------------------- precision form ---
 #
-# SDF in binary16 (clamped to +-65504, rounded to nearest even), blend on FP16 /
-# BF16 MFMA with FP32 accumulation. Decisions are the binary32 sequence on the
-# rounded grid, so they are compared bit for bit with the checker run on that
-# grid. Map bounds follow from the operand rounding (unit roundoff u16 = 2^-11 for
-# FP16, u_bf = 2^-8 for BF16) in the normalised sums:
-#   irradiance  |dE|     <= 4 u16 * pi * max L        (weights and radiance rounded)
-#   depth       |dE[t]|  <= 2 u_bf * t_max            (weights and t rounded)
-#               |dE[t2]| <= 2 u_bf * t_max^2
-# plus the binary32 accumulation and hysteresis (far below these).
-
-U16 = 2.0 ** -11
-UBF = 2.0 ** -8
-
-
-def fp16_grid(w):
-    """The workload with every SDF level rounded as the precision form stores it."""
-    import copy
-    w2 = copy.deepcopy(w)
-    for lv in w2.levels:
-        lv.sdf = np.clip(lv.sdf, -65504.0, 65504.0).astype(np.float16).astype(np.float32)
-    return w2
-
+# Bounds: tests/helpers.py (precision_bounds) states them and their derivation.
 
 def precision_frame_check(S, w, frame, reset, seed_atlas=2, probes=None):
     announce(f"precision form {w.name} P={w.num_probes} R={w.params.rays_per_probe}")
@@ -399,20 +378,17 @@ def precision_frame_check(S, w, frame, reset, seed_atlas=2, probes=None):
     irr, dep = to_host(irr), to_host(dep)
     S.sdfddgi_destroy(ctx)
     probes = np.arange(w.num_probes) if probes is None else np.asarray(probes)
-    chk = oracle.Checker(fp16_grid(w))
+    chk = oracle.Checker(H.fp16_grid(w))
     ri, rd, rp, rr = chk.update_probes(frame, reset, irr0, dep0, probes=probes,
                                        want_payload=True, want_records=True)
     compare_records(rec[probes], rr, w.name + " (fp16 grid)")
     assert_close("payload", pl[probes], rp)
     lmax = float(rp[..., :3].max())
     t_max = float(np.float32(w.params.t_max))
-    ei = np.abs(irr[probes] - ri)
-    ed = np.abs(dep[probes] - rd)
-    # hysteresis mixes in the (exact) previous value: the bound scales by (1 - h) at most 1
-    assert ei.max() <= 4 * U16 * math.pi * max(lmax, float(irr0.max())), ei.max()
-    assert ed[..., 0].max() <= 2 * UBF * t_max, ed[..., 0].max()
-    assert ed[..., 1].max() <= 2 * UBF * t_max ** 2, ed[..., 1].max()
-    return irr, dep
+    over = H.check_precision_maps(irr[probes], dep[probes], ri, rd,
+                                  max(lmax, float(irr0.max())), t_max)
+    announce(f"worst error / bound: {over}")
+    return irr, dep, over
 
 
 @pytest.mark.parametrize("make,reset", [(lambda: scenegen.config1(0, "1b", frames=2), False),
@@ -441,22 +417,22 @@ def test_precision_form_uniform_sky_and_dark_room(S):
     S.sdfddgi_destroy(ctx)
 
 
-def test_precision_form_error_against_fp64_checker_full_size(S):
-    # 16384 probes x 256 rays, one frame from a seeded previous atlas: per-map max and
-    # RMS error of the whole precision form (binary16 SDF included) against the
-    # binary64 checker on the original binary32 grid.
+def test_precision_form_full_size_every_probe(S):
+    """16384 probes x 256 rays, one frame from a seeded previous atlas.
+
+    (1) Every probe: decisions bit-exact with the checker on the binary16-rounded
+    grid, every map element within its derived bound, E[t^2] >= E[t]^2. (2) The
+    whole precision form (binary16 SDF included) against the binary64 checker on
+    the original grid: per-map max and RMS error. Rounding the grid moves surfaces
+    by up to u16 |S|, which flips hits and shadow rays of grazing rays, so only the
+    RMS is gated there; the max is reported."""
     w = scenegen.config2(0, probes=16384, frames=2)
     fr = w.frames[1]
-    announce("precision form vs FP64 checker, 16384 x 256")
-    ctx = S.context_from_workload(w, flags=S.SDFDDGI_FLAG_FP16)
+    irr, dep, over = precision_frame_check(S, w, fr, False, seed_atlas=7)
     irr0, dep0 = scenegen.random_atlas(w.num_probes, w.params, seed=7)
-    S.sdfddgi_set_maps(ctx, to_dev(irr0), to_dev(dep0))
-    gpu_frame(S, ctx, fr)
-    irr, dep = S.sdfddgi_get_maps(ctx)
-    irr, dep = to_host(irr), to_host(dep)
-    S.sdfddgi_destroy(ctx)
-    ri, rd, _, _ = oracle.Checker(w).update_probes(fr, False, irr0, dep0)
-    report = {}
+    ri, rd, _, _ = oracle.Checker(w).update_probes(fr, False, irr0, dep0,
+                                                   geometry=oracle.GEOMETRY_64)
+    report = dict(worst_over_bound_on_rounded_grid=over)
     for name, got, ref in (("irradiance", irr, ri), ("depth_mean", dep[..., 0], rd[..., 0]),
                            ("depth_second", dep[..., 1], rd[..., 1])):
         scale = float(np.abs(ref).max())
@@ -464,6 +440,5 @@ def test_precision_form_error_against_fp64_checker_full_size(S):
         report[name] = dict(max_rel_to_map_max=float(err.max()),
                             rms_rel_to_map_max=float(np.sqrt(np.mean(err ** 2))))
     announce(f"precision form error report: {report}")
-    assert report["irradiance"]["rms_rel_to_map_max"] < 2e-3
-    assert report["depth_mean"]["rms_rel_to_map_max"] < 2e-3
-    assert report["irradiance"]["max_rel_to_map_max"] < 0.1
+    for name in ("irradiance", "depth_mean", "depth_second"):
+        assert report[name]["rms_rel_to_map_max"] < 2e-3, report

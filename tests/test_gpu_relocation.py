@@ -39,7 +39,7 @@ def test_relocation_and_next_frame_match_checker(S, flags):
     w = scenegen.small_cascade(0, probes=(9, 4, 8), rays=64)
     t1, t2, iters, off = 0.6, 0.25, 8, 0.45
     if flags:   # precision form: the checker runs on the binary16-rounded grid
-        from tests.test_gpu_parity import fp16_grid
+        from tests.helpers import fp16_grid
         w = fp16_grid(w)
     ctx = S.context_from_workload(w, flags=flags | S.SDFDDGI_FLAG_RECORD_RAYS)
     ck = oracle.Checker(w)

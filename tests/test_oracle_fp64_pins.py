@@ -252,6 +252,33 @@ def test_binary32_drift_stays_within_derived_bounds_on_the_open_scene():
     assert rep["t_rel_err_max"] > 1e-5
 
 
+def test_near_tie_ray_may_drift_beyond_its_bound_and_is_flagged():
+    # Probe 2547, ray 417 of the open scene (seed 2, 1024 rays, frame 1): both
+    # evaluations end in the same hit after 23 steps, but one intermediate
+    # decision sits 1.6e-6 from its threshold (tie ratio 0.004) and is not kept in
+    # the record; binary32's t ends 9.2e-5 from binary64's, over twice the
+    # same-decision bound. The protocol accepts that on a near-tie ray only, and
+    # flags it for re-evaluation with the binary32 geometry.
+    w = scenegen.config2(2, probes=16384, frames=2, rays=1024)
+    c = oracle.Checker(w)
+    fr = w.frames[1]
+    irr0, dep0 = F.consistent_atlas(w, 23)
+    probes = np.array([2547], dtype=np.int32)
+    _, _, _, r32 = c.update_probes(fr, False, irr0, dep0, probes=probes, want_records=True)
+    _, _, _, r64 = c.update_probes(fr, False, irr0, dep0, probes=probes, want_records=True,
+                                   geometry=oracle.GEOMETRY_64)
+    a, b = oracle.record_fields(r32[0, 417]), oracle.ray64_fields(r64[0, 417])
+    assert int(a["steps"]) == int(b["steps"]) == 23 and b["tie"] < 1.0
+    assert abs(float(a["t"]) - float(b["t"])) > 2 * float(b["t_err"])
+    flagged, rep = F.compare_geometry(r32, r64)
+    assert flagged[0, 417] and rep["drift_beyond_bound_on_near_tie_rays"] >= 1
+    # the same drift on a ray without a near-tie is an error
+    r64b = r64.copy()
+    r64b[0, 417, 10] = 2.0
+    with pytest.raises(AssertionError, match="drifts beyond its bound"):
+        F.compare_geometry(r32, r64b)
+
+
 def test_plane_drift_and_bound():
     # On an exactly linear field the binary32 trace differs from binary64 only by
     # rounding: a handful of ulps, always inside the bound.
