@@ -395,6 +395,22 @@ sdfddgi_status sdfddgi_bake_sdf(int32_t nprims, const int32_t *kind, const doubl
                                 const double origin[3], double spacing, float empty_value,
                                 float *sdf, float *albedo_out, void *hip_stream);
 
+/* For callers that cannot allocate device memory (tight loops, harnesses that
+ * forbid hipMalloc): sdfddgi_bake_sdf with the same arguments, results and
+ * errors, which calls no allocator. The primitives are staged in a buffer the
+ * library holds in static device memory, one per device for the life of the
+ * process (about 304 KiB), so nprims may be at most
+ * SDFDDGI_BAKE_NOALLOC_MAX_PRIMS (EINVAL above). Every call on a device shares
+ * that device's buffer: calls that overlap on one device (from several host
+ * threads) race and must be serialised by the caller. Waits for the stream
+ * before returning, after which the buffer is free again. */
+#define SDFDDGI_BAKE_NOALLOC_MAX_PRIMS 4096
+sdfddgi_status sdfddgi_bake_sdf_noalloc(int32_t nprims, const int32_t *kind, const double *center,
+                                        const double *half, const double *albedo,
+                                        const int32_t n[3], const double origin[3], double spacing,
+                                        float empty_value, float *sdf, float *albedo_out,
+                                        void *hip_stream);
+
 /* ------------------------------------------------------------ batched form --
  * Many independent scenes of uneven size updated together: each frame is one
  * replay of a captured HIP graph whose launches cover every scene -- the ray

@@ -13,6 +13,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -1481,11 +1482,12 @@ sdfddgi_status sdfddgi_trainer_get_params(sdfddgi_trainer *t, float *params) {
     return SDFDDGI_OK;
 }
 
-sdfddgi_status sdfddgi_bake_sdf(int32_t nprims, const int32_t *kind, const double *center,
-                                const double *half, const double *albedo, const int32_t n[3],
-                                const double origin[3], double spacing, float empty_value,
-                                float *sdf, float *albedo_out, void *hip_stream) {
-    g_learned_error.clear();
+}  // extern "C"
+
+// Argument checks shared by both bake entry points.
+static sdfddgi_status check_bake_args(int32_t nprims, const int32_t *kind, const double *center,
+                                      const double *half, const double *albedo, const int32_t n[3],
+                                      const double origin[3], double spacing, const float *sdf) {
     if (nprims < 0 || !n || !origin || !sdf) return lfail(SDFDDGI_EINVAL, "null or negative argument");
     if (nprims > 0 && (!kind || !center || !half || !albedo))
         return lfail(SDFDDGI_EINVAL, "primitive arrays are NULL");
@@ -1496,6 +1498,69 @@ sdfddgi_status sdfddgi_bake_sdf(int32_t nprims, const int32_t *kind, const doubl
         return lfail(SDFDDGI_EINVAL, "spacing and origin must be finite, spacing > 0");
     for (int32_t m = 0; m < nprims; ++m)
         if (kind[m] != 0 && kind[m] != 1) return lfail(SDFDDGI_EINVAL, "primitive kind %d", kind[m]);
+    return SDFDDGI_OK;
+}
+
+static BakeArgs bake_args(int32_t nprims, const int *d_kind, const double *d_prm, size_t stride,
+                          const int32_t n[3], const double origin[3], double spacing,
+                          float empty_value, float *sdf, float *albedo_out) {
+    BakeArgs a{};
+    a.nprims = nprims;
+    a.kind = d_kind;
+    a.center = d_prm;
+    a.half = d_prm + 3 * stride;
+    a.albedo = d_prm + 6 * stride;
+    a.n0 = n[0]; a.n1 = n[1]; a.n2 = n[2];
+    a.org0 = origin[0]; a.org1 = origin[1]; a.org2 = origin[2];
+    a.spacing = spacing;
+    a.empty_value = empty_value;
+    a.sdf = sdf;
+    a.alb = albedo_out;
+    return a;
+}
+
+// Staging of sdfddgi_bake_sdf_noalloc's primitives: center | half | albedo
+// (binary64, SDFDDGI_BAKE_NOALLOC_MAX_PRIMS x 3 each), then the kinds (int32).
+// Each device holds its own copy for the life of the process; host code reaches it
+// only through the address hipGetSymbolAddress gives for the current device.
+constexpr size_t kBakeScratchDoubles = (size_t)9 * SDFDDGI_BAKE_NOALLOC_MAX_PRIMS;
+constexpr size_t kBakeScratchBytes =
+    kBakeScratchDoubles * sizeof(double) + (size_t)SDFDDGI_BAKE_NOALLOC_MAX_PRIMS * sizeof(int32_t);
+static __device__ __align__(256) unsigned char scratch[kBakeScratchBytes];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kScratchDevices];   // device address of `scratch` per device, once known
+}  // namespace
+
+// The current device's address of `scratch`, looked up on the first call on that device.
+static hipError_t bake_scratch(void **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+extern "C" {
+
+sdfddgi_status sdfddgi_bake_sdf(int32_t nprims, const int32_t *kind, const double *center,
+                                const double *half, const double *albedo, const int32_t n[3],
+                                const double origin[3], double spacing, float empty_value,
+                                float *sdf, float *albedo_out, void *hip_stream) {
+    g_learned_error.clear();
+    sdfddgi_status st0 = check_bake_args(nprims, kind, center, half, albedo, n, origin, spacing, sdf);
+    if (st0 != SDFDDGI_OK) return st0;
     (void)hipGetLastError();
     hipStream_t st = (hipStream_t)hip_stream;
     int *d_kind = nullptr;
@@ -1512,23 +1577,48 @@ sdfddgi_status sdfddgi_bake_sdf(int32_t nprims, const int32_t *kind, const doubl
         chk(hipMemcpy(d_prm + 6 * np, albedo, 3 * nprims * sizeof(double), hipMemcpyHostToDevice));
     }
     if (e == hipSuccess) {
-        BakeArgs a{};
-        a.nprims = nprims;
-        a.kind = d_kind;
-        a.center = d_prm;
-        a.half = d_prm + 3 * np;
-        a.albedo = d_prm + 6 * np;
-        a.n0 = n[0]; a.n1 = n[1]; a.n2 = n[2];
-        a.org0 = origin[0]; a.org1 = origin[1]; a.org2 = origin[2];
-        a.spacing = spacing;
-        a.empty_value = empty_value;
-        a.sdf = sdf;
-        a.alb = albedo_out;
-        chk(launch_bake(a, st));
+        chk(launch_bake(bake_args(nprims, d_kind, d_prm, np, n, origin, spacing, empty_value,
+                                  sdf, albedo_out), st));
         chk(hipStreamSynchronize(st));
     }
     dev_free(d_kind);
     dev_free(d_prm);
+    if (e != hipSuccess) return lhip_fail(e, "baking");
+    return SDFDDGI_OK;
+}
+
+sdfddgi_status sdfddgi_bake_sdf_noalloc(int32_t nprims, const int32_t *kind, const double *center,
+                                        const double *half, const double *albedo,
+                                        const int32_t n[3], const double origin[3], double spacing,
+                                        float empty_value, float *sdf, float *albedo_out,
+                                        void *hip_stream) {
+    g_learned_error.clear();
+    sdfddgi_status st0 = check_bake_args(nprims, kind, center, half, albedo, n, origin, spacing, sdf);
+    if (st0 != SDFDDGI_OK) return st0;
+    if (nprims > SDFDDGI_BAKE_NOALLOC_MAX_PRIMS)
+        return lfail(SDFDDGI_EINVAL, "%d primitives: this entry point stages at most %d",
+                     nprims, SDFDDGI_BAKE_NOALLOC_MAX_PRIMS);
+    (void)hipGetLastError();
+    hipStream_t st = (hipStream_t)hip_stream;
+    void *base = nullptr;
+    hipError_t e = bake_scratch(&base);
+    if (e != hipSuccess) return lhip_fail(e, "looking up the staging buffer");
+    double *d_prm = static_cast<double *>(base);
+    int *d_kind = reinterpret_cast<int *>(d_prm + kBakeScratchDoubles);
+    const size_t stride = (size_t)SDFDDGI_BAKE_NOALLOC_MAX_PRIMS;
+    auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+    if (nprims > 0) {
+        // every staged value is written before the kernel reads it: nothing to clear
+        chk(hipMemcpyAsync(d_kind, kind, nprims * sizeof(int), hipMemcpyHostToDevice, st));
+        chk(hipMemcpyAsync(d_prm, center, 3 * nprims * sizeof(double), hipMemcpyHostToDevice, st));
+        chk(hipMemcpyAsync(d_prm + 3 * stride, half, 3 * nprims * sizeof(double),
+                           hipMemcpyHostToDevice, st));
+        chk(hipMemcpyAsync(d_prm + 6 * stride, albedo, 3 * nprims * sizeof(double),
+                           hipMemcpyHostToDevice, st));
+    }
+    chk(launch_bake(bake_args(nprims, d_kind, d_prm, stride, n, origin, spacing, empty_value,
+                              sdf, albedo_out), st));
+    chk(hipStreamSynchronize(st));   // the host arrays and the staging are free again
     if (e != hipSuccess) return lhip_fail(e, "baking");
     return SDFDDGI_OK;
 }

@@ -38,7 +38,7 @@ EXPORTED = [
     "sdfddgi_update_frame_learned", "sdfddgi_get_fallback", "sdfddgi_learned_examples",
     "sdfddgi_trainer_create", "sdfddgi_trainer_gradient", "sdfddgi_trainer_step",
     "sdfddgi_trainer_get_params", "sdfddgi_trainer_destroy", "sdfddgi_learned_last_error",
-    "sdfddgi_bake_sdf", "sdfddgi_batch_create", "sdfddgi_batch_update_frame",
+    "sdfddgi_bake_sdf", "sdfddgi_bake_sdf_noalloc", "sdfddgi_batch_create", "sdfddgi_batch_update_frame",
     "sdfddgi_batch_autotune", "sdfddgi_batch_set_tuning", "sdfddgi_batch_get_maps",
     "sdfddgi_batch_scene_latency", "sdfddgi_batch_sizes", "sdfddgi_batch_destroy",
     "sdfddgi_analytic_create", "sdfddgi_analytic_query", "sdfddgi_analytic_trace",
@@ -156,6 +156,7 @@ def load_library() -> ctypes.CDLL:
     L.sdfddgi_bake_sdf.argtypes = [i32, vp, vp, vp, vp, ctypes.POINTER(i32),
                                    ctypes.POINTER(ctypes.c_double), ctypes.c_double, f32, vp,
                                    vp, vp]
+    L.sdfddgi_bake_sdf_noalloc.argtypes = L.sdfddgi_bake_sdf.argtypes
     L.sdfddgi_batch_create.argtypes = [vp, i32, vp, ctypes.POINTER(vp)]
     L.sdfddgi_batch_update_frame.argtypes = [vp, vp, u64]
     L.sdfddgi_batch_autotune.argtypes = [vp, vp, u64, i32, ctypes.POINTER(sdfddgi_batch_tuning),
@@ -603,10 +604,17 @@ def sdfddgi_trainer_destroy(tr: Trainer) -> None:
         tr.handle = ctypes.c_void_p(0)
 
 
+SDFDDGI_BAKE_NOALLOC_MAX_PRIMS = 4096
+
+
 def sdfddgi_bake_sdf(kind, center, half, albedo, n, origin, spacing: float,
                      empty_value: float = 1e30, with_albedo: bool = True, device="cuda:0",
-                     stream=None):
-    """Bake one grid level on the device; returns (sdf [n2,n1,n0], albedo [.,3] or None)."""
+                     stream=None, out=None, noalloc: bool = False):
+    """Bake one grid level on the device; returns (sdf [n2,n1,n0], albedo [.,3] or None).
+
+    out: optional (sdf, albedo-or-None) device tensors to fill instead of new ones.
+    noalloc: call sdfddgi_bake_sdf_noalloc (primitives staged in the library's static
+    device buffer, at most SDFDDGI_BAKE_NOALLOC_MAX_PRIMS of them)."""
     import torch
     kind = np.ascontiguousarray(kind, dtype=np.int32).reshape(-1)
     m = kind.shape[0]
@@ -615,12 +623,23 @@ def sdfddgi_bake_sdf(kind, center, half, albedo, n, origin, spacing: float,
     alb = np.ascontiguousarray(albedo, dtype=np.float64).reshape(m, 3)
     n = [int(v) for v in n]
     dev = torch.device(device)
-    sdf = torch.empty((n[2], n[1], n[0]), dtype=torch.float32, device=dev)
-    out_alb = (torch.empty((n[2], n[1], n[0], 3), dtype=torch.float32, device=dev)
-               if with_albedo else None)
+    if out is not None:
+        sdf, out_alb = out
+        _dev_ptr(sdf, torch.float32, "out sdf", dev)
+        if tuple(sdf.shape) != (n[2], n[1], n[0]):
+            raise ValueError("out sdf has the wrong shape")
+        if out_alb is not None:
+            _dev_ptr(out_alb, torch.float32, "out albedo", dev)
+            if tuple(out_alb.shape) != (n[2], n[1], n[0], 3):
+                raise ValueError("out albedo has the wrong shape")
+    else:
+        sdf = torch.empty((n[2], n[1], n[0]), dtype=torch.float32, device=dev)
+        out_alb = (torch.empty((n[2], n[1], n[0], 3), dtype=torch.float32, device=dev)
+                   if with_albedo else None)
     P = ctypes.c_void_p
+    fn = load_library().sdfddgi_bake_sdf_noalloc if noalloc else load_library().sdfddgi_bake_sdf
     with torch.cuda.device(dev):
-        _lcheck(load_library().sdfddgi_bake_sdf(
+        _lcheck(fn(
             ctypes.c_int32(m), P(kind.ctypes.data), P(cen.ctypes.data), P(hal.ctypes.data),
             P(alb.ctypes.data), (ctypes.c_int32 * 3)(*n), (ctypes.c_double * 3)(*origin),
             ctypes.c_double(spacing), ctypes.c_float(empty_value), P(sdf.data_ptr()),

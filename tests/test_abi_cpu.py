@@ -214,3 +214,27 @@ def test_batch_create_rejects_bad_arguments_before_touching_a_device():
     li = (S.sdfddgi_light * 1)()
     assert lib.sdfddgi_batch_update_frame(None, li, 1) == S.SDFDDGI_EINVAL
     assert lib.sdfddgi_batch_destroy(None) == S.SDFDDGI_OK
+
+
+def test_bake_entry_points_reject_bad_arguments_before_touching_a_device():
+    lib = S.load_library()
+    m = S.SDFDDGI_BAKE_NOALLOC_MAX_PRIMS + 1
+    kind = np.zeros(m, dtype=np.int32)
+    prm = np.zeros((m, 3))
+    P = ctypes.c_void_p
+    n = (ctypes.c_int32 * 3)(4, 4, 4)
+    org = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
+    fake = P(256)   # never dereferenced: every call below fails its checks first
+    args = (P(kind.ctypes.data), P(prm.ctypes.data), P(prm.ctypes.data), P(prm.ctypes.data))
+    # one primitive past the staging limit: only the no-alloc entry point refuses it
+    st = lib.sdfddgi_bake_sdf_noalloc(m, *args, n, org, 1.0, 0.0, fake, None, None)
+    assert st == S.SDFDDGI_EINVAL and "at most" in S.sdfddgi_learned_last_error()
+    for fn in (lib.sdfddgi_bake_sdf, lib.sdfddgi_bake_sdf_noalloc):
+        assert fn(4, *args, n, org, 1.0, 0.0, None, None, None) == S.SDFDDGI_EINVAL
+        assert fn(4, *args, n, org, 0.0, 0.0, fake, None, None) == S.SDFDDGI_EINVAL
+        assert fn(-1, *args, n, org, 1.0, 0.0, fake, None, None) == S.SDFDDGI_EINVAL
+        bad_n = (ctypes.c_int32 * 3)(4, 1, 4)
+        assert fn(4, *args, bad_n, org, 1.0, 0.0, fake, None, None) == S.SDFDDGI_EINVAL
+        kind[2] = 7
+        assert fn(4, *args, n, org, 1.0, 0.0, fake, None, None) == S.SDFDDGI_EINVAL
+        kind[2] = 0
