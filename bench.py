@@ -122,37 +122,60 @@ def ray_statistics(S, w, frames):
     return {k: v / n for k, v in tot.items()}
 
 
-def cpu_baseline(w, probes: int):
+def cpu_baseline(S, w, probes: int, torch):
+    """The binary64 reference checker timed on the host's cores (one frame of the
+    benchmarked workload from a seeded previous atlas), and, when the sample is the
+    whole frame, the per-map error of the GPU's FP32 and precision forms against it
+    (same frame, same previous atlas; errors relative to each map's maximum)."""
     import numpy as np
     import oracle
+    import scenegen
     threads = min(16, os.cpu_count() or 1)
     chk = oracle.Checker(w)
     step = max(1, w.num_probes // probes)
     sample = np.arange(0, w.num_probes, step, dtype=np.int32)[:probes]
-    import scenegen
     irr0, dep0 = scenegen.random_atlas(w.num_probes, w.params, seed=1)
     fr = w.frames[0]
     t0 = time.perf_counter()
-    chk.update_probes(fr, False, irr0, dep0, probes=sample, threads=threads)
+    ri, rd, _, _ = chk.update_probes(fr, False, irr0, dep0, probes=sample, threads=threads,
+                                     geometry=oracle.GEOMETRY_64)
     dt = time.perf_counter() - t0
     rays = len(sample) * w.params.rays_per_probe
     # one thread on every 16th probe of that sample
     one = sample[::16]
     t1 = time.perf_counter()
-    chk.update_probes(fr, False, irr0, dep0, probes=one, threads=1)
+    chk.update_probes(fr, False, irr0, dep0, probes=one, threads=1, geometry=oracle.GEOMETRY_64)
     d1 = time.perf_counter() - t1
     rays1 = len(one) * w.params.rays_per_probe
     full = w.num_probes * w.params.rays_per_probe
-    return {"value": rays / dt, "unit": "probe-rays/s", "cores": threads, "kind": "oracle",
+    base = {"value": rays / dt, "unit": "probe-rays/s", "cores": threads, "kind": "oracle",
             "host_cpus": os.cpu_count(),
             "sample": f"{len(sample)} of {w.num_probes} probes (every {step}th) x "
-                      f"{w.params.rays_per_probe} rays, one frame, binary32 geometry + "
-                      f"binary64 radiometry, {threads} threads, {dt:.2f} s wall",
+                      f"{w.params.rays_per_probe} rays, one frame, binary64 checker, "
+                      f"{threads} threads, {dt:.2f} s wall",
             "ms_per_frame": full / (rays / dt) * 1e3,
             "single_thread": {"value": rays1 / d1, "unit": "probe-rays/s",
                               "ms_per_frame": full / (rays1 / d1) * 1e3,
                               "sample": f"{len(one)} probes (every {16 * step}th), 1 thread, "
                                         f"{d1:.2f} s wall"}}
+    errors = None
+    if len(sample) == w.num_probes:
+        errors = {}
+        for name, flags in (("f32", 0), ("f16", S.SDFDDGI_FLAG_FP16)):
+            ctx = S.context_from_workload(w, flags=flags)
+            S.sdfddgi_set_maps(ctx, torch.from_numpy(irr0).cuda(), torch.from_numpy(dep0).cuda())
+            S.sdfddgi_update_frame(ctx, fr.dir_to_light, fr.radiance_rgb, fr.rotation_seed)
+            gi, gd = S.sdfddgi_get_maps(ctx)
+            gi, gd = gi.cpu().numpy(), gd.cpu().numpy()
+            S.sdfddgi_destroy(ctx)
+            rep = {}
+            for m, got, ref in (("irradiance", gi, ri), ("depth_mean", gd[..., 0], rd[..., 0]),
+                                ("depth_second", gd[..., 1], rd[..., 1])):
+                err = np.abs(got - ref) / float(np.abs(ref).max())
+                rep[m] = {"max_rel_to_map_max": float(err.max()),
+                          "rms_rel_to_map_max": float(np.sqrt(np.mean(err ** 2)))}
+            errors[name] = rep
+    return base, errors
 
 
 def learned_comparison(S, w, n_frames: int, torch):
@@ -165,8 +188,8 @@ def learned_comparison(S, w, n_frames: int, torch):
     sum E_ref^2) over every interior irradiance texel and channel, against the
     1024-ray plain run at the same frame; the reported error is its mean over frames
     20, 25, ... (after the history has built up). ms/frame is measured afterwards on
-    the same context: 20 back-to-back frames between two events on the stream (plain
-    frames overlap their neighbours there, learned frames run one at a time).
+    the same context: 20 back-to-back frames between two events on the stream
+    (consecutive frames of either form overlap there).
     """
     import numpy as np
     from paper_2007_14394_amd import denoiser_weights
@@ -233,7 +256,7 @@ def learned_comparison(S, w, n_frames: int, torch):
                     kernel_ms=kt, **extra)
 
     forms = {"plain_f32_1024": entry(1024, ref_kt, ref)}
-    for rays in (64, 128, 256):
+    for rays in PLAIN_RAYS:
         sn, kt, _ = run(rays)
         forms[f"plain_f32_{rays}"] = entry(rays, kt, sn)
     sn, kt, _ = run(256, S.SDFDDGI_FLAG_FP16)
@@ -241,25 +264,40 @@ def learned_comparison(S, w, n_frames: int, torch):
     for name, flags in (("learned_f32", 0), ("learned_f16", S.SDFDDGI_FLAG_FP16)):
         sn, kt, fb = run(256, flags, learned=True)
         forms[name] = entry(wts["learned_rays"], kt, sn, fallback_rays=256, fallback_fraction=fb)
-
-    # plain FP32 at equal error: log-log interpolation of error and time in the ray count
-    lr = np.log([64.0, 128.0, 256.0])
-    le = np.log([forms[f"plain_f32_{r}"]["irr_rel_rms_error"] for r in (64, 128, 256)])
-    lm = np.log([forms[f"plain_f32_{r}"]["ms_per_frame"] for r in (64, 128, 256)])
-    out = {}
-    for name in ("learned_f32", "learned_f16"):
-        e = forms[name]["irr_rel_rms_error"]
-        if e <= float(np.exp(le[-1])):
-            # at least as accurate as the plain 256-ray form: compare with that form
-            rays_eq, ms_eq, bound = 256.0, forms["plain_f32_256"]["ms_per_frame"], "lower_error"
-        else:
-            x = float(np.interp(-np.log(e), -le, lr))   # error falls as rays grow
-            rays_eq, ms_eq, bound = float(np.exp(x)), float(np.exp(np.interp(x, lr, lm))), "equal"
-        out[name] = dict(plain_rays_at_equal_error=rays_eq, plain_ms_at_equal_error=ms_eq,
-                         speedup=ms_eq / forms[name]["ms_per_frame"], comparison=bound)
+    plain = [forms[f"plain_f32_{r}"] for r in PLAIN_RAYS]
+    out = {name: equal_error_point(PLAIN_RAYS, [f["irr_rel_rms_error"] for f in plain],
+                                   [f["ms_per_frame"] for f in plain],
+                                   forms[name]["irr_rel_rms_error"], forms[name]["ms_per_frame"])
+           for name in ("learned_f32", "learned_f16")}
     return dict(reference="plain FP32 update with 1024 rays per probe, same frames",
                 frames=n_frames, eval_frames=evals, weights=wts["meta"].get("command"),
                 tau=wts["tau"], forms=forms, at_equal_error=out)
+
+
+PLAIN_RAYS = (32, 48, 64, 128, 256)
+
+
+def equal_error_point(rays, errors, ms, err, ms_form):
+    """The plain form's ray count and ms/frame at the error ``err``: log-log
+    interpolation between the two plain runs that bracket it. Outside the measured
+    range nothing is extrapolated: a form more accurate than the most-rayed plain
+    run is compared with that run (its speed-up is then a lower bound), one less
+    accurate than the fewest-rayed run with that one (an upper bound)."""
+    import numpy as np
+    lr, le, lm = np.log(rays), np.log(errors), np.log(ms)
+    if not np.all(np.diff(le) < 0):
+        return dict(comparison="not_monotonic", plain_errors=list(errors), speedup=None)
+    if err <= errors[-1]:
+        r, m, how = rays[-1], ms[-1], "lower_bound"
+    elif err >= errors[0]:
+        r, m, how = rays[0], ms[0], "upper_bound"
+    else:
+        k = int(np.searchsorted(-le, -np.log(err)))      # errors[k-1] > err >= errors[k]
+        f = (np.log(err) - le[k - 1]) / (le[k] - le[k - 1])
+        x = lr[k - 1] + f * (lr[k] - lr[k - 1])
+        r, m, how = float(np.exp(x)), float(np.exp(lm[k - 1] + f * (lm[k] - lm[k - 1]))), "equal"
+    return dict(plain_rays_at_equal_error=float(r), plain_ms_at_equal_error=float(m),
+                speedup=float(m) / ms_form, comparison=how)
 
 
 def batch_form(S, scenegen, n_frames: int, torch):
@@ -513,7 +551,12 @@ def main():
         out["analytic_sdf"] = analytic_sdf(S, scenegen, torch)
     if args.cpu_probes > 0:
         stage("CPU baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_probes)
+        out["cpu_baseline"], errors = cpu_baseline(S, w, args.cpu_probes, torch)
+        if errors:
+            ref = ("binary64 reference checker, one frame from a seeded previous atlas, "
+                   "every probe; errors relative to each map's maximum")
+            out["error_vs_fp64"] = dict(reference=ref, **errors["f32"])
+            out["precision_form"]["error_vs_fp64"] = dict(reference=ref, **errors["f16"])
     print(json.dumps(out), flush=True)
 
 
