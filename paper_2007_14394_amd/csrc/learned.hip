@@ -202,20 +202,69 @@ __device__ __forceinline__ bf16x8_t to_bf16x8(const float v[8]) {
 // ------------------------------------------------------------------ denoise --
 
 constexpr int kWaves = 4;
-constexpr int kTileBatch = 4;    // texel tiles whose features are gathered together
-constexpr int kMaxDepthF4 = (2 * kMaxLearnedRes + 2) * (2 * kMaxLearnedRes + 2) * 2 / 4;
+constexpr int kDenoiseTiles = 4;   // 16-texel tiles a wave pushes through the network at once
+constexpr int kDenoiseBlocksPerCu = 4;
 
-// One wave per probe (waves stride over probes). Per 16-texel tile: features, the
-// network, U_hat = max(0, E_prev + S o[0..2]) staged in LDS, and exp(o[3]) summed.
-// The probe falls back (appended to the list, nothing written) when its history is
-// rejected or its mean predicted error exceeds tau; otherwise U_hat takes the place
-// of the plain update in the hysteresis mix of its irradiance (interior and borders),
-// and its depth moments take the hysteresis mix with the low-ray update.
-__global__ __launch_bounds__(256) void denoise_kernel(DenoiseArgs a) {
+// ReLU of one m-tile's D (units 16 mt + 4 g + r), rounded to bfloat16 into its slots
+// of the next layer's B operands: k-step mt / 2, slots 4 (mt % 2) + r.
+__device__ __forceinline__ void relu_into(floatx4 d, int mt, bf16x8_t h[2]) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) h[mt >> 1][4 * (mt & 1) + r] = (__bf16)fmaxf(d[r], 0.0f);
+}
+
+// Forward pass of kDenoiseTiles 16-texel tiles with the weight packs in LDS: each
+// A operand is read once and applied to every tile, and each layer is produced one
+// m-tile at a time straight into the next layer's operands (no pre-activations are
+// kept), so that the kernel fits four waves per SIMD. The same products and
+// roundings as mlp_forward. out[q]: lanes g == 0 hold o[0..3] of texel n of tile q.
+__device__ __forceinline__ void mlp_forward_lds(const uint4 *s_w, const float *s_bias, int g,
+                                                int lane, const bf16x8_t xb[kDenoiseTiles],
+                                                floatx4 out[kDenoiseTiles]) {
+    const floatx4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+    bf16x8_t h[kDenoiseTiles][2], hn[kDenoiseTiles][2];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        const bf16x8_t w = as_bf16x8(s_w[mt * 64 + lane]);
+#pragma unroll
+        for (int q = 0; q < kDenoiseTiles; ++q) relu_into(mfma(w, xb[q], zero), mt, h[q]);
+    }
+#pragma unroll
+    for (int layer = 0; layer < 2; ++layer) {
+        const int e0 = layer ? 12 : 4, b0 = layer ? kHidden : 0;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            const bf16x8_t w0 = as_bf16x8(s_w[(e0 + 2 * mt) * 64 + lane]);
+            const bf16x8_t w1 = as_bf16x8(s_w[(e0 + 2 * mt + 1) * 64 + lane]);
+            const floatx4 b = bias4(s_bias, b0 + 16 * mt + 4 * g);
+#pragma unroll
+            for (int q = 0; q < kDenoiseTiles; ++q)
+                relu_into(mfma(w1, h[q][1], mfma(w0, h[q][0], b)), mt, hn[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < kDenoiseTiles; ++q) {
+            h[q][0] = hn[q][0];
+            h[q][1] = hn[q][1];
+        }
+    }
+    const bf16x8_t w0 = as_bf16x8(s_w[20 * 64 + lane]), w1 = as_bf16x8(s_w[21 * 64 + lane]);
+    const floatx4 b = bias4(s_bias, 2 * kHidden + 4 * g);
+#pragma unroll
+    for (int q = 0; q < kDenoiseTiles; ++q) out[q] = mfma(w1, h[q][1], mfma(w0, h[q][0], b));
+}
+
+// One wave per probe (persistent waves stride over probes). Per pair of 16-texel
+// tiles: features, the network, U_hat = max(0, E_prev + S o[0..2]) staged in LDS,
+// and exp(o[3]) summed. The probe falls back (appended to the list, nothing
+// written) when its history is rejected or its mean predicted error exceeds tau;
+// otherwise U_hat takes the place of the plain update in the hysteresis mix of its
+// irradiance (interior and borders), and its depth moments take the hysteresis mix
+// with the low-ray update.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void denoise_kernel(DenoiseArgs a) {
+    __shared__ uint4 s_w[kFwdEntries * 64];
     __shared__ float s_bias[kBiasFloats];
     __shared__ float s_u[kWaves][kMaxLearnedRes * kMaxLearnedRes * 3];
-    bf16x8_t wf[kFwdEntries];
-    load_pack(a.mlp, wf, s_bias);
+    for (int e = threadIdx.x; e < kFwdEntries * 64; e += blockDim.x) s_w[e] = a.mlp.fwd[e];
+    for (int e = threadIdx.x; e < kBiasFloats; e += blockDim.x) s_bias[e] = a.mlp.bias[e];
     __syncthreads();
     const int lane = (int)__lane_id(), n = lane & 15, g = lane >> 4;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -225,30 +274,30 @@ __global__ __launch_bounds__(256) void denoise_kernel(DenoiseArgs a) {
     float *su = s_u[wave];
     for (int p = blockIdx.x * kWaves + wave; p < a.P; p += gridDim.x * kWaves) {
         float esum = 0.0f;
-        for (int tb = 0; tb < tiles; tb += kTileBatch) {
-            // gather the features of kTileBatch tiles first, so their loads overlap
-            bf16x8_t xb[kTileBatch];
+        for (int tb = 0; tb < tiles; tb += kDenoiseTiles) {
+            // keep the weight packs in LDS: without this the compiler hoists their
+            // (loop-invariant) reads out of the probe loop into 88 registers
+            asm volatile("" ::: "memory");
+            bf16x8_t xb[kDenoiseTiles];
 #pragma unroll
-            for (int q = 0; q < kTileBatch; ++q) {
+            for (int q = 0; q < kDenoiseTiles; ++q) {
                 const int t = (tb + q) * 16 + n;
                 float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
                 if (g < 2 && t < Ti) feature_group(a.f, p, t, g, v);
                 xb[q] = to_bf16x8(v);
             }
+            floatx4 o[kDenoiseTiles];
+            mlp_forward_lds(s_w, s_bias, g, lane, xb, o);
 #pragma unroll
-            for (int q = 0; q < kTileBatch; ++q) {
-                if (tb + q >= tiles) break;
+            for (int q = 0; q < kDenoiseTiles; ++q) {
                 const int t = (tb + q) * 16 + n;
-                floatx4 d1[4], d2[4], d3[4];
-                bf16x8_t h1[2], h2[2], h3[2];
-                const floatx4 o = mlp_forward(wf, s_bias, g, xb[q], d1, d2, d3, h1, h2, h3);
                 if (g == 0 && t < Ti) {
                     const float *prev = a.f.prev_irr + (size_t)p * tile_i +
                                         ((size_t)(t / ri + 1) * si + (t % ri + 1)) * 3;
 #pragma unroll
                     for (int c = 0; c < 3; ++c)
-                        su[3 * t + c] = fmaxf(0.0f, fmaf(a.s, o[c], prev[c]));
-                    esum += expf(o[3]);
+                        su[3 * t + c] = fmaxf(0.0f, fmaf(a.s, o[q][c], prev[c]));
+                    esum += expf(o[q][3]);
                 }
             }
         }
@@ -261,30 +310,51 @@ __global__ __launch_bounds__(256) void denoise_kernel(DenoiseArgs a) {
         __builtin_amdgcn_wave_barrier();
         const float h = a.hysteresis;
         float *new_i = a.new_irr + (size_t)p * tile_i;
-        // unrolled so that every lane's loads are in flight together
         const float *old_i = a.f.prev_irr + (size_t)p * tile_i;
+        // kBatch elements per lane at a time, every load issued before the stores (one
+        // batch covers an 8x8 irradiance map and an 18x18 depth tile)
+        constexpr int kBatch = 3;
+        for (int e0 = 0; e0 < Ti * 3; e0 += 64 * kBatch) {
+            float old[kBatch];
 #pragma unroll
-        for (int k = 0; k < kMaxLearnedRes * kMaxLearnedRes * 3 / 64; ++k) {
-            const int e = lane + 64 * k;
-            if (e >= Ti * 3) break;
-            const int t = e / 3, c = e - 3 * (e / 3);
-            const int i = t % ri, j = t / ri;
-            const float u = su[e];
-            const float old = old_i[((j + 1) * si + (i + 1)) * 3 + c];
-            store_with_border(new_i, ri, 3, i, j, c, fmaf(h, old - u, u));
+            for (int k = 0; k < kBatch; ++k) {
+                const int e = e0 + 64 * k + lane;
+                const int t = e / 3, c = e - 3 * t;
+                old[k] = e < Ti * 3 ? old_i[((t / ri + 1) * si + (t % ri + 1)) * 3 + c] : 0.0f;
+            }
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                const int e = e0 + 64 * k + lane;
+                if (e >= Ti * 3) break;
+                const int t = e / 3, c = e - 3 * t;
+                const float u = su[e];
+                store_with_border(new_i, ri, 3, t % ri, t / ri, c, fmaf(h, old[k] - u, u));
+            }
         }
         // depth tiles are whole float4s: (res+2)^2 * 2 floats with res even
         const float4 *old_d = reinterpret_cast<const float4 *>(a.f.prev_depth + (size_t)p * tile_d);
         const float4 *ud = reinterpret_cast<const float4 *>(a.u_depth + (size_t)p * tile_d);
         float4 *new_d = reinterpret_cast<float4 *>(a.new_depth + (size_t)p * tile_d);
         const int nd4 = (int)(tile_d / 4);
+        for (int e0 = 0; e0 < nd4; e0 += 64 * kBatch) {
+            float4 u[kBatch], o[kBatch];
 #pragma unroll
-        for (int k = 0; k < kMaxDepthF4 / 64 + 1; ++k) {
-            const int e = lane + 64 * k;
-            if (e >= nd4) break;
-            const float4 u = ud[e], o = old_d[e];
-            new_d[e] = make_float4(fmaf(h, o.x - u.x, u.x), fmaf(h, o.y - u.y, u.y),
-                                   fmaf(h, o.z - u.z, u.z), fmaf(h, o.w - u.w, u.w));
+            for (int k = 0; k < kBatch; ++k) {
+                const int e = e0 + 64 * k + lane;
+                if (e < nd4) {
+                    u[k] = ud[e];
+                    o[k] = old_d[e];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                const int e = e0 + 64 * k + lane;
+                if (e >= nd4) break;
+                new_d[e] = make_float4(fmaf(h, o[k].x - u[k].x, u[k].x),
+                                       fmaf(h, o[k].y - u[k].y, u[k].y),
+                                       fmaf(h, o[k].z - u[k].z, u[k].z),
+                                       fmaf(h, o[k].w - u[k].w, u[k].w));
+            }
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -585,9 +655,10 @@ hipError_t launch_pack_mlp(const float *theta, uint4 *fwd, uint4 *bwd, float *bi
 }
 
 hipError_t launch_denoise(const DenoiseArgs &a, hipStream_t s) {
-    // more waves than fit at once: the kernel is bound by load latency, and the
-    // workgroups that start later hide the tails of the first ones
-    const int blocks = (int)std::min<int64_t>(grid_for(a.P, kWaves), 8 * device_cus());
+    // persistent: as many workgroups as are resident at once (each loads the weight
+    // packs into its LDS once)
+    const int blocks =
+        (int)std::min<int64_t>(grid_for(a.P, kWaves), kDenoiseBlocksPerCu * device_cus());
     hipLaunchKernelGGL(denoise_kernel, dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
