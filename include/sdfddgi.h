@@ -154,8 +154,9 @@ typedef struct {
     /* Learned form (sdfddgi_update_frame_learned); 0 rays: not available. */
     int32_t learned_rays;      /* low ray count: 0, or a multiple of 16 in 16..R   */
     float fallback_error;      /* tau: mean predicted relative error above which a
-                                  probe takes the plain update, >= 0 (+inf: only
-                                  probes without history do)                       */
+                                  probe takes the plain update in the next learned
+                                  frame, >= 0 (+inf: only probes without history or
+                                  without a prediction do)                         */
 } sdfddgi_params;
 
 /* Directional light: direction toward the light (any non-zero length; it is
@@ -283,12 +284,15 @@ sdfddgi_status sdfddgi_destroy(sdfddgi_ctx *ctx);
  * o = W4 h3 + b4 (16 -> 64 -> 64 -> 64 -> 4) with bfloat16 weights, inputs and
  * activations (round to nearest even) and FP32 accumulation on MFMA. The
  * texel's update is U_hat = max(0, E_prev + S o[0..2]) and its predicted
- * relative error exp(o[3]). A probe whose history is rejected, or whose mean
- * predicted error over its texels exceeds fallback_error, takes the plain
- * update with rays_per_probe rays instead; every other probe mixes U_hat into
- * its irradiance (hysteresis, then borders) and the low-ray depth moments into
- * its depth map. Requires learned_rays > 0, depth_res an even multiple of
- * irr_res and irr_res <= 16.
+ * relative error exp(o[3]). Which probes take the plain update with
+ * rays_per_probe rays instead is decided before the frame's trace: those whose
+ * history is rejected, and those whose mean predicted error over their texels
+ * in the previous learned frame exceeded fallback_error (every probe before the
+ * context's first learned frame; the predictions persist across set_maps). The
+ * network still runs for them, to predict for the next frame. Every other probe
+ * mixes U_hat into its irradiance (hysteresis, then borders) and the low-ray
+ * depth moments into its depth map. Requires learned_rays > 0, depth_res an
+ * even multiple of irr_res and irr_res <= 16.
  *
  * Parameter vector (binary32, SDFDDGI_DENOISER_PARAMS values, row-major):
  *   W1 [64][16] | W2 [64][64] | b2 [64] | W3 [64][64] | b3 [64] | W4 [4][64] | b4 [4] */
@@ -322,7 +326,8 @@ sdfddgi_status sdfddgi_update_frame_learned(sdfddgi_ctx *ctx, const sdfddgi_deno
 /* The last learned frame's fallback: *count (host) = number of probes that took
  * the plain update; probes (device [P], may be NULL) receives their indices in
  * no particular order, mean_error (device [P], may be NULL) every probe's mean
- * predicted relative error. Waits for the stream. ESTATE before a learned frame. */
+ * predicted relative error in that frame (which decides the next learned
+ * frame). Waits for the stream. ESTATE before a learned frame. */
 sdfddgi_status sdfddgi_get_fallback(sdfddgi_ctx *ctx, int32_t *count, int32_t *probes,
                                     float *mean_error);
 

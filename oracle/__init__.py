@@ -364,18 +364,21 @@ class Checker:
 
     def learned_frame(self, frame, reset: bool, prev_irr, prev_depth, theta, S: float, D: float,
                       tau: float, learned_rays: int, fallback=None, threads: int = 0,
-                      mirror: bool = True):
+                      mirror: bool = True, prev_mean_error=None):
         """One frame of the learned form for every probe.
 
         Low-ray Eq. 3 update (no hysteresis), features, network (mirror mode unless
         ``mirror`` is false); an accepted probe mixes the network's
         U_hat = max(0, E_prev + S o) into its irradiance and the low-ray depth
-        moments into its depth map with the hysteresis;
-        per-probe decision: a probe takes the plain update when the history is
-        reset or the mean of exp(o_3) over its texels exceeds tau. ``fallback``
-        (a boolean per probe) overrides the decision, for checking another
-        implementation's choice where the two precisions may legitimately differ.
-        Returns dict(irr, depth, fallback, mean_error, o, features, u_irr, u_depth).
+        moments into its depth map with the hysteresis. Per-probe decision, taken
+        before the frame: a probe takes the plain update when the history is reset,
+        when there is no previous prediction (``prev_mean_error`` None), or when its
+        mean of exp(o_3) over its texels in the previous learned frame
+        (``prev_mean_error``) exceeds tau. ``fallback`` (a boolean per probe)
+        overrides the decision, for checking another implementation's choice where
+        the two precisions may legitimately differ. ``mean_error`` of the result is
+        this frame's prediction, which decides the next frame.
+        Returns dict(irr, depth, fallback, decided, mean_error, o, features, u_irr, u_depth).
         """
         P, T = self.num_probes, self.irr_res ** 2
         low = Checker(self.workload, **{**self._overrides, "rays": learned_rays,
@@ -385,7 +388,10 @@ class Checker:
         feats = self.learned_features(u_irr, prev_irr, prev_depth, S, D)
         o = mlp_forward(theta, feats.reshape(-1, FEATURES), mirror=mirror).reshape(P, T, 4)
         mean_err = np.exp(o[..., 3]).mean(axis=1)
-        decided = np.full(P, True) if reset else mean_err > tau
+        if reset or prev_mean_error is None:
+            decided = np.full(P, True)
+        else:
+            decided = np.asarray(prev_mean_error, dtype=np.float64) > tau
         fb = decided if fallback is None else np.asarray(fallback, dtype=bool)
         h = self.hysteresis
         prev_irr = np.asarray(prev_irr, dtype=np.float64)

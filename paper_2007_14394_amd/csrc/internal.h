@@ -183,12 +183,12 @@ struct DenoiseArgs {
     FeatureArgs f;
     int P;
     float hysteresis, s, tau;
-    const uint8_t *reject;
     const float *u_depth;         // low-ray depth moments atlas (no hysteresis)
     float *new_irr, *new_depth;
     MlpPack mlp;
-    int *fallback_list;           // [P] probes that take the plain update
-    int *fallback_count;          // zeroed before the launch
+    uint8_t *fb_next;             // [P] in: the probe takes the plain update this frame
+                                  //     (written nothing here); out: it will next frame
+                                  //     (mean predicted error above tau)
     float *mean_error;            // [P] mean predicted relative error (may be null)
 };
 
@@ -242,6 +242,11 @@ hipError_t launch_relocate(const TraceArgs &a, const RelocateArgs &r, hipStream_
 hipError_t launch_pack_mlp(const float *theta, uint4 *fwd, uint4 *bwd, float *bias,
                            hipStream_t stream);
 hipError_t launch_denoise(const DenoiseArgs &a, hipStream_t stream);
+// The fallback list of a learned frame: every probe whose history is rejected or
+// whose flag asks for the plain update; the flag is set for both (the denoiser reads
+// it while the fallback blend clears the reject flags). count zeroed before.
+hipError_t launch_select_fallback(const uint8_t *reject, uint8_t *fb_next, int P, int *list,
+                                  int *count, hipStream_t stream);
 hipError_t launch_examples(const ExampleArgs &a, hipStream_t stream);
 hipError_t launch_infer(const InferArgs &a, hipStream_t stream);
 hipError_t launch_train(const TrainArgs &a, hipStream_t stream);

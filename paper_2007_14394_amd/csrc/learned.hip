@@ -252,13 +252,13 @@ __device__ __forceinline__ void mlp_forward_lds(const uint4 *s_w, const float *s
     for (int q = 0; q < kDenoiseTiles; ++q) out[q] = mfma(w1, h[q][1], mfma(w0, h[q][0], b));
 }
 
-// One wave per probe (persistent waves stride over probes). Per pair of 16-texel
+// One wave per probe (persistent waves stride over probes). Per group of 16-texel
 // tiles: features, the network, U_hat = max(0, E_prev + S o[0..2]) staged in LDS,
-// and exp(o[3]) summed. The probe falls back (appended to the list, nothing
-// written) when its history is rejected or its mean predicted error exceeds tau;
-// otherwise U_hat takes the place of the plain update in the hysteresis mix of its
-// irradiance (interior and borders), and its depth moments take the hysteresis mix
-// with the low-ray update.
+// and exp(o[3]) summed. A probe whose flag says it takes the plain update this frame
+// (its fallback pass writes its maps) only records its prediction; every other probe
+// mixes U_hat into its irradiance in place of the plain update (hysteresis, interior
+// and borders), and the low-ray depth moments into its depth map. The flag becomes
+// the next frame's decision: mean predicted error above tau.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void denoise_kernel(DenoiseArgs a) {
     __shared__ uint4 s_w[kFwdEntries * 64];
     __shared__ float s_bias[kBiasFloats];
@@ -302,11 +302,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void d
             }
         }
         const float mean = wave_sum(esum) / (float)Ti;
-        if (a.mean_error && lane == 0) a.mean_error[p] = mean;
-        if (a.reject[p] != 0 || mean > a.tau) {
-            if (lane == 0) a.fallback_list[atomicAdd(a.fallback_count, 1)] = p;
-            continue;
+        const int plain = __builtin_amdgcn_readfirstlane((int)a.fb_next[p]);
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) {
+            if (a.mean_error) a.mean_error[p] = mean;
+            a.fb_next[p] = mean > a.tau ? 1 : 0;
         }
+        if (plain) continue;
         __builtin_amdgcn_wave_barrier();
         const float h = a.hysteresis;
         float *new_i = a.new_irr + (size_t)p * tile_i;
@@ -357,6 +359,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void d
             }
         }
         __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// One thread per probe.
+__global__ __launch_bounds__(256) void select_fallback_kernel(const uint8_t *__restrict__ reject,
+                                                              uint8_t *__restrict__ fb_next,
+                                                              int P, int *__restrict__ list,
+                                                              int *__restrict__ count) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    if (reject[p] || fb_next[p]) {
+        fb_next[p] = 1;
+        list[atomicAdd(count, 1)] = p;
     }
 }
 
@@ -660,6 +675,13 @@ hipError_t launch_denoise(const DenoiseArgs &a, hipStream_t s) {
     const int blocks =
         (int)std::min<int64_t>(grid_for(a.P, kWaves), kDenoiseBlocksPerCu * device_cus());
     hipLaunchKernelGGL(denoise_kernel, dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_fallback(const uint8_t *reject, uint8_t *fb_next, int P, int *list,
+                                  int *count, hipStream_t s) {
+    hipLaunchKernelGGL(select_fallback_kernel, dim3(grid_for(P, 256)), dim3(256), 0, s, reject,
+                       fb_next, P, list, count);
     return hipGetLastError();
 }
 

@@ -27,7 +27,7 @@ thread_local std::string g_create_error;
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kTimingRing = 256;
-constexpr int kEvents = 9;
+constexpr int kEvents = 11;
 
 // ---------------------------------------------------------- frame constants --
 
@@ -151,24 +151,32 @@ struct sdfddgi_ctx {
     double *texel_i = nullptr, *texel_d = nullptr;
     // main: the ray set of the last plain frame; spare: the one the next plain frame
     // traces into while the last one's hit shading and blend may still run
-    RaySet main, spare, low;
+    RaySet main, spare;
+    // the learned form's low ray set, two of them: consecutive learned frames alternate,
+    // so a frame's low-ray trace need not wait for the previous frame's low-ray blend
+    RaySet low[2];
+    int low_next = 0;
     // Plain frames are pipelined: the tables and primary trace of frame f run on the
     // side stream and may overlap frame f-1's hit shading and blend on the caller's
     // stream (the primary trace reads neither the atlas nor anything frame f-1
     // writes). A frame's side work waits for the done event of the ray set it
     // traces into (recorded after the blend of the frame before the previous one)
     // or for ev_gate (recorded on the caller's stream just before the previous
-    // frame's hit shading; learned frames use it the same way); ev_primary joins
-    // the side stream back. Any other call in between makes the next frame wait
-    // for everything before it (serialize_next).
+    // frame's hit shading; learned frames wait for their low set's done event
+    // instead); ev_primary joins the side stream back. Any other call in between
+    // makes the next frame wait for everything before it (serialize_next).
     hipStream_t side = nullptr;
     hipEvent_t ev_gate = nullptr, ev_primary = nullptr, ev_tail = nullptr;
     bool serialize_next = true;
     // Learned frames overlap the same way among themselves (their low-ray pass's
     // tables and primary trace beside the previous learned frame's denoiser and
     // fallback pass); a switch between plain and learned frames waits for
-    // everything before it.
+    // everything before it. Within a learned frame the fallback probes' plain update
+    // runs on side2 beside the low-ray chain: it starts after ev_sel (the fallback
+    // list is built and the previous atlas complete) and ev_fb joins it back.
     bool learned_chain = false;
+    hipStream_t side2 = nullptr;
+    hipEvent_t ev_sel = nullptr, ev_fb = nullptr;
     float *irr[2]{}, *depth[2]{};
     int cur = 0;
     uint8_t *reject = nullptr;
@@ -179,8 +187,10 @@ struct sdfddgi_ctx {
     float *u_irr = nullptr, *u_depth = nullptr;      // low-ray estimates (no hysteresis)
     float *probe_sdf = nullptr;                      // [P]
     float *texel_dir = nullptr;                      // [Ti][3] binary32
-    int *fallback = nullptr;                         // [P]
+    int *fallback = nullptr;                         // [P] this frame's fallback list
     float *mean_error = nullptr;                     // [P]
+    uint8_t *fb_next = nullptr;                      // [P] plain update in the next learned
+                                                     //     frame (set until a prediction)
     // Timing: kEvents events per frame in a ring (see sdfddgi_get_kernel_times);
     // sdfddgi_get_kernel_times averages the frames recorded since its previous call.
     hipEvent_t *ev_ring = nullptr;
@@ -271,18 +281,25 @@ void free_all(sdfddgi_ctx *c) {
     }
     free_set(c->main);
     free_set(c->spare);
-    free_set(c->low);
+    free_set(c->low[0]);
+    free_set(c->low[1]);
+    for (RaySet *r : {&c->low[0], &c->low[1]})
+        if (r->done) (void)hipEventDestroy(r->done);
     if (c->main.done) (void)hipEventDestroy(c->main.done);
     if (c->spare.done) (void)hipEventDestroy(c->spare.done);
     if (c->ev_gate) (void)hipEventDestroy(c->ev_gate);
     if (c->ev_primary) (void)hipEventDestroy(c->ev_primary);
     if (c->ev_tail) (void)hipEventDestroy(c->ev_tail);
     if (c->side) (void)hipStreamDestroy(c->side);
+    if (c->ev_sel) (void)hipEventDestroy(c->ev_sel);
+    if (c->ev_fb) (void)hipEventDestroy(c->ev_fb);
+    if (c->side2) (void)hipStreamDestroy(c->side2);
     dev_free(c->probe_pos); dev_free(c->grid_pos); dev_free(c->probe_order); dev_free(c->texel_i); dev_free(c->texel_d);
     dev_free(c->irr[0]); dev_free(c->irr[1]); dev_free(c->depth[0]); dev_free(c->depth[1]);
     dev_free(c->reject); dev_free(c->counter); dev_free(c->records);
     dev_free(c->u_irr); dev_free(c->u_depth);
     dev_free(c->probe_sdf); dev_free(c->texel_dir); dev_free(c->fallback); dev_free(c->mean_error);
+    dev_free(c->fb_next);
     if (c->ev_ring) {
         for (int k = 0; k < kEvents * kTimingRing; ++k)
             if (c->ev_ring[k]) (void)hipEventDestroy(c->ev_ring[k]);
@@ -795,6 +812,9 @@ sdfddgi_status sdfddgi_create(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_g
     SDF_TRY(hipEventCreateWithFlags(&c->ev_gate, hipEventDisableTiming), "creating events");
     SDF_TRY(hipEventCreateWithFlags(&c->ev_primary, hipEventDisableTiming), "creating events");
     SDF_TRY(hipEventCreateWithFlags(&c->ev_tail, hipEventDisableTiming), "creating events");
+    SDF_TRY(hipStreamCreateWithFlags(&c->side2, hipStreamNonBlocking), "creating a stream");
+    SDF_TRY(hipEventCreateWithFlags(&c->ev_sel, hipEventDisableTiming), "creating events");
+    SDF_TRY(hipEventCreateWithFlags(&c->ev_fb, hipEventDisableTiming), "creating events");
     for (RaySet *r : {&c->main, &c->spare}) {
         SDF_TRY(hipEventCreateWithFlags(&r->done, hipEventDisableTiming), "creating events");
         SDF_TRY(hipEventRecord(r->done, c->stream), "event");
@@ -815,13 +835,18 @@ sdfddgi_status sdfddgi_create(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_g
     if (params->flags & SDFDDGI_FLAG_RECORD_RAYS)
         SDF_TRY(dev_alloc(&c->records, (size_t)P * c->main.R * 8), "allocating ray records");
     if (params->learned_rays > 0) {
-        SDF_TRY(alloc_set(c, c->low, params->learned_rays), "allocating the learned ray set");
+        for (RaySet *r : {&c->low[0], &c->low[1]}) {
+            SDF_TRY(alloc_set(c, *r, params->learned_rays), "allocating the learned ray sets");
+            SDF_TRY(hipEventCreateWithFlags(&r->done, hipEventDisableTiming), "creating events");
+        }
         SDF_TRY(dev_alloc(&c->u_irr, c->irr_floats), "allocating learned buffers");
         SDF_TRY(dev_alloc(&c->u_depth, c->depth_floats), "allocating learned buffers");
         SDF_TRY(dev_alloc(&c->probe_sdf, P), "allocating learned buffers");
         SDF_TRY(dev_alloc(&c->texel_dir, 3 * c->Ti), "allocating learned buffers");
         SDF_TRY(dev_alloc(&c->fallback, P), "allocating learned buffers");
         SDF_TRY(dev_alloc(&c->mean_error, P), "allocating learned buffers");
+        SDF_TRY(dev_alloc(&c->fb_next, P), "allocating learned buffers");
+        SDF_TRY(launch_fill_u8(c->fb_next, 1, P, c->stream), "launching fill");
         SDF_TRY(hipMemcpy(c->texel_dir, h_tif.data(), 3 * c->Ti * sizeof(float),
                           hipMemcpyHostToDevice),
                 "uploading texel directions");
@@ -1034,7 +1059,7 @@ sdfddgi_status sdfddgi_get_kernel_times(sdfddgi_ctx *c, float *ms, int32_t count
             "hipEventSynchronize");
     // tables, primary, hits, blend, frame, denoiser, fallback trace, fallback blend
     constexpr int kTimes = 8;
-    const int pairs[kTimes][2] = {{0, 1}, {1, 2}, {3, 4}, {4, 5}, {0, 8}, {5, 6}, {6, 7}, {7, 8}};
+    const int pairs[kTimes][2] = {{0, 1}, {1, 2}, {3, 4}, {4, 5}, {0, 10}, {5, 6}, {7, 8}, {8, 9}};
     double sum[kTimes] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int f = 0; f < frames; ++f) {
         const hipEvent_t *ev = c->ev_ring + kEvents * ((last - f + kTimingRing) % kTimingRing);
@@ -1105,6 +1130,7 @@ sdfddgi_status sdfddgi_destroy(sdfddgi_ctx *c) {
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     if (c->side) (void)hipStreamSynchronize(c->side);
+    if (c->side2) (void)hipStreamSynchronize(c->side2);
     free_all(c);
     delete c;
     return SDFDDGI_OK;
@@ -1191,7 +1217,7 @@ static FeatureArgs feature_args(const sdfddgi_ctx *c, const sdfddgi_denoiser *d)
 }
 
 static sdfddgi_status check_learned(sdfddgi_ctx *c, const sdfddgi_denoiser *d) {
-    if (!c->low.R) return fail(c, SDFDDGI_ESTATE, "context created with learned_rays == 0");
+    if (!c->low[0].R) return fail(c, SDFDDGI_ESTATE, "context created with learned_rays == 0");
     if (!d) return fail(c, SDFDDGI_EINVAL, "denoiser is NULL");
     if (d->device != c->device) return fail(c, SDFDDGI_EINVAL, "denoiser is on another device");
     return SDFDDGI_OK;
@@ -1211,16 +1237,16 @@ sdfddgi_status sdfddgi_update_frame_learned(sdfddgi_ctx *c, const sdfddgi_denois
     int *fb_count = c->counter + 6;
     FrameEvents ev = frame_events(c);
     // low-ray pass over every probe, Eq. 3 without hysteresis; its tables and primary
-    // trace on the side stream, after the previous learned frame's low-ray blend (the
-    // last use of the low set: its gate) or, when serial, after everything so far
-    RaySet &lo = c->low;
+    // trace on the side stream, after the low-ray blend of the learned frame before the
+    // previous one (the last use of this low set) or, when serial, after everything so far
+    RaySet &lo = c->low[c->low_next];
     const TraceArgs tl = trace_pass(base, lo, lo.counter, lo.counter + kPartStride, nullptr,
                                     nullptr, nullptr);
     if (serial) {
         TRY_HIP(c, hipEventRecord(c->ev_tail, c->stream), "event");
         TRY_HIP(c, hipStreamWaitEvent(c->side, c->ev_tail, 0), "stream wait");
     } else {
-        TRY_HIP(c, hipStreamWaitEvent(c->side, c->ev_gate, 0), "stream wait");
+        TRY_HIP(c, hipStreamWaitEvent(c->side, lo.done, 0), "stream wait");
     }
     TRY_HIP(c, ev.mark_on(0, c->side), "event");
     TRY_HIP(c, launch_tables(table_args(c, lo, rotation_seed, kSetCounters, lo.counter), c->side),
@@ -1229,10 +1255,41 @@ sdfddgi_status sdfddgi_update_frame_learned(sdfddgi_ctx *c, const sdfddgi_denois
     TRY_HIP(c, launch_primary(tl, lo.grid, c->side), "launching primary_kernel");
     TRY_HIP(c, ev.mark_on(2, c->side), "event");
     TRY_HIP(c, hipEventRecord(c->ev_primary, c->side), "event");
-    TRY_HIP(c, hipStreamWaitEvent(c->stream, c->ev_primary, 0), "stream wait");
-    // the main set's tables for the fallback pass; they zero the frame's counters
+    // caller's stream: this frame's fallback list -- probes with a rejected history or
+    // whose mean predicted error in the previous learned frame exceeded tau (every
+    // probe before the first prediction) -- after the main set's tables for the
+    // fallback pass, which zero the frame's counters
     TRY_HIP(c, launch_tables(table_args(c, c->main, rotation_seed, kCounters), c->stream),
             "launching tables_kernel");
+    TRY_HIP(c, launch_select_fallback(c->reject, c->fb_next, (int)c->P, c->fallback, fb_count,
+                                      c->stream),
+            "launching select_fallback_kernel");
+    TRY_HIP(c, hipEventRecord(c->ev_sel, c->stream), "event");
+    // second side stream: the plain update of the fallback probes (trace, hit shading
+    // reading the previous atlas, blend with hysteresis into their tiles of the new
+    // atlas), beside the low-ray chain
+    TRY_HIP(c, hipStreamWaitEvent(c->side2, c->ev_sel, 0), "stream wait");
+    TRY_HIP(c, ev.mark_on(7, c->side2), "event");
+    int *fb_parts = c->counter + kPartStride + kXcds * kPartStride;
+    const TraceArgs tf =
+        trace_pass(base, c->main, c->counter + 3, fb_parts, c->fallback, fb_count, nullptr);
+    // the grids of a trace that shares the GPU with other streams' kernels
+    TraceGrid gf = c->main.grid;
+    gf.primary_blocks = gf.primary_blocks_overlapped;
+    gf.hits_blocks = gf.hits_blocks_overlapped;
+    TRY_HIP(c, launch_primary(tf, gf, c->side2), "launching primary_kernel");
+    TRY_HIP(c, launch_hits(tf, gf, c->side2), "launching hits_kernel");
+    TRY_HIP(c, ev.mark_on(8, c->side2), "event");
+    TRY_HIP(c, launch_blend(blend_args(c, c->main, c->main.payload, c->prm.hysteresis,
+                                       c->irr[c->cur], c->depth[c->cur], c->irr[nxt],
+                                       c->depth[nxt], c->reject, c->fallback, fb_count),
+                            c->side2),
+            "launching blend_kernel");
+    TRY_HIP(c, ev.mark_on(9, c->side2), "event");
+    TRY_HIP(c, hipEventRecord(c->ev_fb, c->side2), "event");
+    // caller's stream: low-ray hit shading and Eq. 3 without hysteresis, then the
+    // network over every probe (maps of the others; every probe's prediction)
+    TRY_HIP(c, hipStreamWaitEvent(c->stream, c->ev_primary, 0), "stream wait");
     TRY_HIP(c, ev.mark(3), "event");
     TRY_HIP(c, launch_hits(tl, lo.grid, c->stream), "launching hits_kernel");
     TRY_HIP(c, ev.mark(4), "event");
@@ -1241,39 +1298,26 @@ sdfddgi_status sdfddgi_update_frame_learned(sdfddgi_ctx *c, const sdfddgi_denois
                                        nullptr),
                             c->stream),
             "launching blend_kernel");
-    TRY_HIP(c, hipEventRecord(c->ev_gate, c->stream), "event");
+    TRY_HIP(c, hipEventRecord(lo.done, c->stream), "event");
     TRY_HIP(c, ev.mark(5), "event");
-    // network, decision, accepted probes' maps, fallback list
     DenoiseArgs da{};
     da.f = feature_args(c, d);
     da.P = (int)c->P;
     da.hysteresis = c->prm.hysteresis;
     da.s = d->S;
     da.tau = c->prm.fallback_error;
-    da.reject = c->reject;
     da.u_depth = c->u_depth;
     da.new_irr = c->irr[nxt];
     da.new_depth = c->depth[nxt];
     da.mlp = MlpPack{d->fwd, d->bwd, d->bias};
-    da.fallback_list = c->fallback;
-    da.fallback_count = fb_count;
+    da.fb_next = c->fb_next;
     da.mean_error = c->mean_error;
     TRY_HIP(c, launch_denoise(da, c->stream), "launching denoise_kernel");
     TRY_HIP(c, ev.mark(6), "event");
-    // plain update of the fallback probes
-    int *fb_parts = c->counter + kPartStride + kXcds * kPartStride;
-    const TraceArgs tf =
-        trace_pass(base, c->main, c->counter + 3, fb_parts, c->fallback, fb_count, nullptr);
-    TRY_HIP(c, launch_primary(tf, c->main.grid, c->stream), "launching primary_kernel");
-    TRY_HIP(c, launch_hits(tf, c->main.grid, c->stream), "launching hits_kernel");
-    TRY_HIP(c, ev.mark(7), "event");
-    TRY_HIP(c, launch_blend(blend_args(c, c->main, c->main.payload, c->prm.hysteresis,
-                                       c->irr[c->cur], c->depth[c->cur], c->irr[nxt],
-                                       c->depth[nxt], c->reject, c->fallback, fb_count),
-                            c->stream),
-            "launching blend_kernel");
-    TRY_HIP(c, ev.mark(8), "event");
+    TRY_HIP(c, hipStreamWaitEvent(c->stream, c->ev_fb, 0), "stream wait");
+    TRY_HIP(c, ev.mark(10), "event");
     frame_done(c);
+    c->low_next ^= 1;
     c->cur = nxt;
     c->have_learned = true;
     c->learned_chain = true;
@@ -1315,13 +1359,14 @@ sdfddgi_status sdfddgi_learned_examples(sdfddgi_ctx *c, const sdfddgi_denoiser *
     float l[3], rad[3];
     if ((st = light_of(c, light, l, rad)) != SDFDDGI_OK) return st;
     const TraceArgs base = trace_base(c, l, rad);
-    TRY_HIP(c, launch_tables(table_args(c, c->low, rotation_seed, kCounters), c->stream),
+    RaySet &lo = c->low[0];
+    TRY_HIP(c, launch_tables(table_args(c, lo, rotation_seed, kCounters), c->stream),
             "launching tables_kernel");
-    const TraceArgs tl = trace_pass(base, c->low, c->counter, c->counter + kPartStride, nullptr,
+    const TraceArgs tl = trace_pass(base, lo, c->counter, c->counter + kPartStride, nullptr,
                                     nullptr, nullptr);
-    TRY_HIP(c, launch_primary(tl, c->low.grid, c->stream), "launching primary_kernel");
-    TRY_HIP(c, launch_hits(tl, c->low.grid, c->stream), "launching hits_kernel");
-    TRY_HIP(c, launch_blend(blend_args(c, c->low, c->low.payload, 0.0f, c->irr[c->cur],
+    TRY_HIP(c, launch_primary(tl, lo.grid, c->stream), "launching primary_kernel");
+    TRY_HIP(c, launch_hits(tl, lo.grid, c->stream), "launching hits_kernel");
+    TRY_HIP(c, launch_blend(blend_args(c, lo, lo.payload, 0.0f, c->irr[c->cur],
                                        c->depth[c->cur], c->u_irr, c->u_depth, nullptr, nullptr,
                                        nullptr),
                             c->stream),

@@ -236,54 +236,74 @@ def run_learned(S, w, theta, tau, frames, flags=0, warm_frames=2):
 
 
 def test_learned_frame_matches_checker(S):
+    """Frame 2 from the checker's maps after frames 0-1: no prediction yet, so every
+    probe takes the plain update, and every probe's prediction is made. Frame 3 from
+    the checker's maps after frames 0-2: each probe's decision is frame 2's
+    prediction against tau. Predictions, decisions and maps against the checker."""
     announce("learned frame small_cascade")
     w = learned_workload()
     th = random_theta(7, scale=0.5)
     th[oracle.OFF_B4 + 3] = -3.0          # predicted errors around exp(-3)
     ck = oracle.Checker(w)
     P = ck.num_probes
-    # tau at the median of the checker's mean predicted errors: both decisions occur
-    ctx = make_ctx(S, w, 0.0)
-    irr0, dep0 = warm(S, ctx, w)
-    probe = ck.learned_frame(w.frames[2], False, irr0, dep0, th, S_IRR, D_DEPTH, math.inf, 32)
-    tau = float(np.median(probe["mean_error"]))
-    for k in range(2):
-        # frame 2 + k from the checker's maps after frames 0 .. 1 + k
-        fr = w.frames[2 + k]
-        prev, (r,) = run_learned(S, w, th, tau, [fr], warm_frames=2 + k)
-        ref = ck.learned_frame(fr, False, prev[0], prev[1], th, S_IRR, D_DEPTH, tau, 32)
-        # mean predicted error: exp(o3) moves by at most the output bound of o3
-        M3 = magnitude(th, ref["features"].reshape(-1, F))[:, 3].reshape(P, -1)
-        slack = np.exp(OUT_BOUND * M3.max(axis=1)) - 1.0
-        rel = np.abs(r["mean_error"] / ref["mean_error"] - 1.0)
-        assert np.all(rel <= slack + 1e-5), float((rel - slack).max())
-        assert np.median(rel) <= 1e-4
-        # decisions agree wherever the checker's mean is clearly on one side of tau
-        gpu_fb = np.zeros(P, bool)
-        gpu_fb[r["fallback"]] = True
-        assert r["count"] == gpu_fb.sum() and len(np.unique(r["fallback"])) == r["count"]
-        clear = np.abs(ref["mean_error"] / tau - 1.0) > 2 * slack + 1e-4
-        assert np.array_equal(gpu_fb[clear], ref["decided"][clear])
-        assert 0 < gpu_fb.sum() < P
-        # maps, given the GPU's decisions
-        ref2 = ck.learned_frame(fr, False, prev[0], prev[1], th, S_IRR, D_DEPTH, tau, 32,
-                                fallback=gpu_fb)
-        ok, worst = H.rel_close(r["depth"], ref2["depth"], rel=1e-4)
-        assert ok, worst
-        ok, worst = H.rel_close(r["irr"][gpu_fb], ref2["irr"][gpu_fb], rel=1e-4)
-        assert ok, worst
-        # accepted texels: U_hat = max(0, E_prev + S o) enters with weight (1 - h)
-        h = ck.hysteresis
-        Mo = magnitude(th, ref2["features"].reshape(-1, F))[:, :3]
-        ri = w.params.irr_res
-        bound = np.zeros_like(ref2["irr"])
-        bound[:, 1:ri + 1, 1:ri + 1, :] = ((1 - h) * S_IRR * OUT_BOUND * Mo).reshape(P, ri, ri, 3)
-        oracle._fill_borders(bound, ri)   # border texels copy interior ones
-        acc = ~gpu_fb
-        got, want = r["irr"][acc], ref2["irr"][acc]
-        assert np.all(np.abs(got - want) <= bound[acc] + 1e-4 * np.abs(want) + 1e-6)
-        # and typically far closer than the bound
-        assert np.median(np.abs(got - want) / (np.abs(want) + 1e-3)) <= 1e-4
+    states = [tuple(m.astype(np.float32).astype(np.float64) for m in st)
+              for st in ck.run_frames(w.frames[:3])]
+    pre = ck.learned_frame(w.frames[2], False, *states[1], th, S_IRR, D_DEPTH, math.inf, 32)
+    # tau at the median of the checker's frame-2 predictions: both decisions occur in frame 3
+    tau = float(np.median(pre["mean_error"]))
+    ctx = make_ctx(S, w, tau)
+    den = S.sdfddgi_denoiser_create(np.asarray(th, dtype=np.float32), S_IRR, D_DEPTH)
+    runs = []
+    for k, fr in ((1, w.frames[2]), (2, w.frames[3])):
+        S.sdfddgi_set_maps(ctx, to_dev(states[k][0]), to_dev(states[k][1]))
+        S.sdfddgi_update_frame_learned(ctx, den, fr.dir_to_light, fr.radiance_rgb,
+                                       fr.rotation_seed)
+        cnt, lst, errs = S.sdfddgi_get_fallback(ctx)
+        ni, nd = S.sdfddgi_get_maps(ctx)
+        runs.append(dict(count=cnt, fallback=np.sort(to_host(lst)[:cnt]),
+                         mean_error=to_host(errs), irr=to_host(ni).astype(np.float64),
+                         depth=to_host(nd).astype(np.float64)))
+    S.sdfddgi_destroy(ctx)
+    # frame 2: the plain update everywhere; predictions within the output bound
+    assert runs[0]["count"] == P
+    M3 = magnitude(th, pre["features"].reshape(-1, F))[:, 3].reshape(P, -1)
+    slack = np.exp(OUT_BOUND * M3.max(axis=1)) - 1.0
+    rel = np.abs(runs[0]["mean_error"] / pre["mean_error"] - 1.0)
+    assert np.all(rel <= slack + 1e-5), float((rel - slack).max())
+    assert np.median(rel) <= 1e-4
+    # frame 3: decisions are frame 2's predictions against tau; they agree with the
+    # checker's wherever its prediction is clearly on one side of tau
+    r = runs[1]
+    gpu_fb = np.zeros(P, bool)
+    gpu_fb[r["fallback"]] = True
+    assert r["count"] == gpu_fb.sum() and len(np.unique(r["fallback"])) == r["count"]
+    np.testing.assert_array_equal(gpu_fb, runs[0]["mean_error"] > np.float32(tau))
+    clear = np.abs(pre["mean_error"] / tau - 1.0) > 2 * slack + 1e-4
+    assert np.array_equal(gpu_fb[clear], (pre["mean_error"] > tau)[clear])
+    assert 0 < gpu_fb.sum() < P
+    fr = w.frames[3]
+    ref = ck.learned_frame(fr, False, *states[2], th, S_IRR, D_DEPTH, tau, 32, fallback=gpu_fb)
+    M3 = magnitude(th, ref["features"].reshape(-1, F))[:, 3].reshape(P, -1)
+    slack = np.exp(OUT_BOUND * M3.max(axis=1)) - 1.0
+    rel = np.abs(r["mean_error"] / ref["mean_error"] - 1.0)
+    assert np.all(rel <= slack + 1e-5), float((rel - slack).max())
+    # maps, given the GPU's decisions
+    ok, worst = H.rel_close(r["depth"], ref["depth"], rel=1e-4)
+    assert ok, worst
+    ok, worst = H.rel_close(r["irr"][gpu_fb], ref["irr"][gpu_fb], rel=1e-4)
+    assert ok, worst
+    # accepted texels: U_hat = max(0, E_prev + S o) enters with weight (1 - h)
+    h = ck.hysteresis
+    Mo = magnitude(th, ref["features"].reshape(-1, F))[:, :3]
+    ri = w.params.irr_res
+    bound = np.zeros_like(ref["irr"])
+    bound[:, 1:ri + 1, 1:ri + 1, :] = ((1 - h) * S_IRR * OUT_BOUND * Mo).reshape(P, ri, ri, 3)
+    oracle._fill_borders(bound, ri)   # border texels copy interior ones
+    acc = ~gpu_fb
+    got, want = r["irr"][acc], ref["irr"][acc]
+    assert np.all(np.abs(got - want) <= bound[acc] + 1e-4 * np.abs(want) + 1e-6)
+    # and typically far closer than the bound
+    assert np.median(np.abs(got - want) / (np.abs(want) + 1e-3)) <= 1e-4
 
 
 def test_all_fallback_is_the_plain_frame_bit_for_bit(S):

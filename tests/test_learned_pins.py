@@ -321,7 +321,9 @@ def test_threshold_zero_falls_back_to_the_plain_update():
     irr, dep = warm_maps(w)
     rng = np.random.default_rng(8)
     th = rng.normal(0, 0.2, oracle.MLP_PARAMS)
-    out = ck.learned_frame(w.frames[2], False, irr, dep, th, 2.0, 1.0, 0.0, learned_rays=32)
+    P = ck.num_probes
+    out = ck.learned_frame(w.frames[2], False, irr, dep, th, 2.0, 1.0, 0.0, learned_rays=32,
+                           prev_mean_error=np.full(P, 0.5))
     plain_i, plain_d, _, _ = ck.update_probes(w.frames[2], False, irr, dep)
     assert out["fallback"].all()
     np.testing.assert_array_equal(out["irr"], plain_i)
@@ -333,7 +335,7 @@ def test_reset_history_falls_back_everywhere():
     ck = oracle.Checker(w)
     irr, dep = warm_maps(w)
     out = ck.learned_frame(w.frames[2], True, irr, dep, passthrough_theta(), 2.0, 1.0, math.inf,
-                           learned_rays=32)
+                           learned_rays=32, prev_mean_error=np.zeros(ck.num_probes))
     plain_i, plain_d, _, _ = ck.update_probes(w.frames[2], True, irr, dep)
     assert out["fallback"].all()
     np.testing.assert_array_equal(out["irr"], plain_i)
@@ -347,7 +349,7 @@ def test_passthrough_network_gives_the_low_ray_plain_update():
     irr, dep = warm_maps(w)
     S = 2.0
     out = ck.learned_frame(w.frames[2], False, irr, dep, passthrough_theta(), S, 1.0, math.inf,
-                           learned_rays=32, mirror=False)
+                           learned_rays=32, mirror=False, prev_mean_error=np.zeros(ck.num_probes))
     li, ld, _, _ = oracle.Checker(w, rays=32).update_probes(w.frames[2], False, irr, dep)
     assert not out["fallback"].any()
     np.testing.assert_allclose(out["irr"], li, rtol=1e-12, atol=1e-12)
@@ -359,8 +361,31 @@ def test_zero_network_keeps_irradiance_history():
     ck = oracle.Checker(w)
     irr, dep = warm_maps(w)
     out = ck.learned_frame(w.frames[2], False, irr, dep, zero_theta(), 2.0, 1.0, math.inf,
-                           learned_rays=32)
+                           learned_rays=32, prev_mean_error=np.zeros(ck.num_probes))
     assert not out["fallback"].any()
     np.testing.assert_allclose(out["irr"], irr, rtol=1e-15, atol=0)
     # exp(0) = 1 is the predicted error of every texel
     np.testing.assert_array_equal(out["mean_error"], 1.0)
+
+
+def test_fallback_follows_the_previous_prediction():
+    # The decision is taken before the frame, from the previous learned frame's mean
+    # predicted errors: above tau -> the plain update, else the network's. Without a
+    # previous prediction every probe takes the plain update. The result's mean_error
+    # is this frame's own prediction (exp(0) = 1 for the zero network).
+    w = learned_workload(rays=64)
+    ck = oracle.Checker(w)
+    P = ck.num_probes
+    irr, dep = warm_maps(w)
+    prev = np.where(np.arange(P) % 3 == 0, 0.05, 0.01)
+    out = ck.learned_frame(w.frames[2], False, irr, dep, zero_theta(), 2.0, 1.0, 0.02,
+                           learned_rays=32, prev_mean_error=prev)
+    np.testing.assert_array_equal(out["fallback"], prev > 0.02)
+    plain_i, plain_d, _, _ = ck.update_probes(w.frames[2], False, irr, dep)
+    fb = out["fallback"]
+    np.testing.assert_array_equal(out["irr"][fb], plain_i[fb])
+    np.testing.assert_allclose(out["irr"][~fb], irr[~fb], rtol=1e-15, atol=0)
+    np.testing.assert_array_equal(out["mean_error"], 1.0)
+    first = ck.learned_frame(w.frames[2], False, irr, dep, zero_theta(), 2.0, 1.0, 0.02,
+                             learned_rays=32)
+    assert first["fallback"].all()
