@@ -369,7 +369,8 @@ def analytic_sdf(S, scenegen, torch):
     primitives: 64 rays from each of the 16384 probes sphere-traced with every
     primitive evaluated (mode 0), with cluster culling (1), and with culling from
     the previous sample's bound (2), for several cluster sizes; all give the same
-    bits (tested), so only time and primitive evaluations differ."""
+    bits (tested), so only time and primitive evaluations differ. Then the whole
+    probe update of an analytic context at 16384 x 256 (full_update)."""
     import numpy as np
     w = scenegen.config2(0, probes=16384, frames=1)
     prims = w.prims
@@ -400,10 +401,32 @@ def analytic_sdf(S, scenegen, torch):
         S.sdfddgi_analytic_destroy(an)
     base = out["mode0_cluster8"]["ms"]
     best = min((k for k in out if k.startswith("mode2")), key=lambda k: out[k]["ms"])
+    # the whole probe update traced on the primitives (an analytic context: primary
+    # trace, hit normals and shadow rays through the culled query), 16384 x 256
+    wf = scenegen.config2(0, probes=16384, frames=5)
+    ctx = S.context_from_workload(wf, flags=S.SDFDDGI_FLAG_TIMING, analytic=True, cluster_size=8)
+    fr = wf.frames[0]
+    S.sdfddgi_update_frame(ctx, fr.dir_to_light, fr.radiance_rgb, fr.rotation_seed)
+    torch.cuda.synchronize()
+    S.sdfddgi_get_kernel_times(ctx)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for fr in wf.frames[1:]:
+        S.sdfddgi_update_frame(ctx, fr.dir_to_light, fr.radiance_rgb, fr.rotation_seed)
+    b.record()
+    torch.cuda.synchronize()
+    ms_full = a.elapsed_time(b) / (len(wf.frames) - 1)
+    kt = S.sdfddgi_get_kernel_times(ctx)
+    S.sdfddgi_destroy(ctx)
+    full = dict(workload="open scene 400 primitives (clusters of 8), 16384 probes x 256 rays, "
+                         "plain FP32 update", ms_per_frame=ms_full,
+                probe_rays_per_s=16384 * 256 / (ms_full * 1e-3),
+                kernel_ms={k: kt[k] for k in ("tables", "primary", "hits", "blend", "frame")})
     return dict(workload=f"open scene 400 primitives, 16384 probes x {R} rays, 64 steps",
                 rays=16384 * R, results=out, best=best,
                 speedup_best_vs_all_primitives=base / out[best]["ms"],
-                speedup_bound_vs_plain_culling=out["mode1_cluster8"]["ms"] / out["mode2_cluster8"]["ms"])
+                speedup_bound_vs_plain_culling=out["mode1_cluster8"]["ms"] / out["mode2_cluster8"]["ms"],
+                full_update=full)
 
 
 def stage(msg: str) -> None:

@@ -180,6 +180,27 @@ sdfddgi_status sdfddgi_create(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_g
                               const sdfddgi_params *params, void *hip_stream,
                               sdfddgi_ctx **out);
 
+/* A context whose probe update traces the scene's primitives instead of a baked
+ * grid (Sec. 3.1: the scene as a union of signed distance primitives; Sec. 3.3:
+ * their distance queried with cluster culling and the 2 lastSDF bound along a
+ * ray). Host arrays, as for sdfddgi_bake_sdf: kind[nprims] (0 sphere of radius
+ * half[.][0], 1 axis-aligned box of half extents half[.][0..2]),
+ * center/half/albedo [nprims][3] (binary64; distances use their binary32
+ * roundings, albedo >= 0), 1 <= nprims <= 1024, primitives packed cluster_size
+ * (1..64) to a cluster in Morton order of their centres, at most 256 clusters.
+ * The update then differs from the grid's only in the scene query: a sample's
+ * distance is the minimum over the primitives (equal bit for bit to the
+ * brute-force minimum), a ray misses only past t_max (there is no grid box), a
+ * hit's normal is the normalised gradient of the nearest primitive's distance
+ * (the lowest index among equals; -w where it vanishes) and its albedo that
+ * primitive's; records report level 0. Everything else is sdfddgi_create's.
+ * Not with SDFDDGI_FLAG_FP16 or learned_rays > 0 (EINVAL); relocation is ESTATE. */
+sdfddgi_status sdfddgi_create_analytic(int32_t nprims, const int32_t *kind, const double *center,
+                                       const double *half, const double *albedo,
+                                       int32_t cluster_size, const sdfddgi_probe_grid *probes,
+                                       const sdfddgi_params *params, void *hip_stream,
+                                       sdfddgi_ctx **out);
+
 /* One frame of the probe update of Sec. 3.3 for every probe (steps 1-5
  * above). Reads the current maps as the previous frame, writes the other
  * buffer pair, then makes it current. Clears every probe's reject flag.

@@ -47,6 +47,19 @@ struct ProbeGridDev {
     float inv0, inv1, inv2;     // (float)(1/spacing)
 };
 
+constexpr int kMaxAnalyticPrims = 1024;
+constexpr int kMaxClusters = 256;
+
+struct AnalyticArgs {
+    int nprims, nclusters;
+    const int *kind;                 // [nprims], primitives ordered by cluster
+    const int *orig;                 // [nprims] each one's index in the caller's order
+                                     //     (null: the cluster order is the caller's)
+    const float *center, *half;      // [nprims][3] binary32
+    const float *lo, *hi;            // [nclusters][3] widened bounding boxes
+    const int *first;                // [nclusters + 1] first primitive of each cluster
+};
+
 struct TraceArgs {
     DevLevel lv[kMaxLevels];
     int nl;
@@ -69,11 +82,15 @@ struct TraceArgs {
     const float *prev_irr;      // previous irradiance atlas
     float4 *payload;            // [P*R]
     int *records;               // [P*R*8] or nullptr
-    int4 *hitq;                 // [P*R] queue of primary hits: (ray, bits of t, outcome|level<<4|steps<<8, 0)
+    int4 *hitq;                 // [P*R] queue of primary hits: (ray, bits of t, outcome|level<<4|steps<<8,
+                                //     nearest primitive slot when analytic, else 0)
     int *counter;               // [3] (unused), queue entries claimed by hits_kernel, queue
                                 //     length (all zeroed by tables_kernel)
     int *parts;                 // [kXcds * kPartStride] primary chunks claimed per XCD, one
                                 //     counter per 128-B line (zeroed likewise)
+    int analytic;               // 1: distances from the primitives in `an`, not the grid
+    AnalyticArgs an;
+    const float *prim_alb;      // [nprims][3] albedo of each primitive, cluster order
 };
 
 struct TraceGrid {
@@ -130,7 +147,7 @@ struct SampleArgs {
 
 // Launchers (kernels.hip). Each enqueues on `stream` and returns the launch status.
 hipError_t launch_tables(const TableArgs &a, hipStream_t stream);
-TraceGrid trace_grid(int device, int64_t rays, bool half);
+TraceGrid trace_grid(int device, int64_t rays, bool half, bool analytic = false);
 hipError_t launch_primary(const TraceArgs &a, const TraceGrid &grid, hipStream_t stream);
 hipError_t launch_hits(const TraceArgs &a, const TraceGrid &grid, hipStream_t stream);
 hipError_t launch_blend(const BlendArgs &a, hipStream_t stream);
@@ -331,16 +348,6 @@ hipError_t launch_batch_blend(const BatchBlendArgs &a, int nblocks, hipStream_t 
 int batch_max_blocks(int device, bool hits);
 
 // -------------------------------------------------- analytic SDF (cluster.hip) --
-constexpr int kMaxAnalyticPrims = 1024;
-constexpr int kMaxClusters = 256;
-
-struct AnalyticArgs {
-    int nprims, nclusters;
-    const int *kind;                 // [nprims], primitives ordered by cluster
-    const float *center, *half;      // [nprims][3] binary32
-    const float *lo, *hi;            // [nclusters][3] widened bounding boxes
-    const int *first;                // [nclusters + 1] first primitive of each cluster
-};
 
 struct AnalyticTrace {
     int n;

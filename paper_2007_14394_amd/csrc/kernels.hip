@@ -20,6 +20,7 @@
 #include "octahedral.h"
 #include "trace_common.h"
 #include "blend_common.h"
+#include "analytic_common.h"
 
 #pragma clang fp contract(off)
 
@@ -60,24 +61,53 @@ __device__ __forceinline__ int select_level(const TraceArgs &a, float x0, float 
     return L;
 }
 
+// Distance backends of the trace kernels: the cascade of grids with binary32 or
+// binary16 values, or the scene's analytic primitives (Sec. 3.1) through the
+// cluster-culled query of Sec. 3.3. The per-workgroup LDS state of each:
+enum : int { kSdfGrid32 = 0, kSdfGrid16 = 1, kSdfAnalytic = 2 };
+template <int kSdf> struct SdfLds { LevelLds lv[kMaxLevels]; };
+template <> struct SdfLds<kSdfAnalytic> { ClusterLds cl; };
+
+template <int kSdf>
+__device__ __forceinline__ void load_sdf(const TraceArgs &a, SdfLds<kSdf> &s) {
+    if constexpr (kSdf == kSdfAnalytic) load_clusters(a.an, s.cl);
+    else load_levels(a, s.lv);
+}
+
 // One sample of the fixed sphere-trace sequence for a ray o + t w at sample k.
 // Returns the outcome code when the ray stops here (steps in *steps), -1 otherwise
 // (t and k are then advanced). x and the level of the sample are returned too.
-template <bool kPrimary, bool kHalf>
-__device__ __forceinline__ int trace_step(const TraceArgs &a, const LevelLds *s_lv, float o0,
+// Analytic backend: no grid box, so a ray misses only past t_max; the distance is
+// the culled minimum over the primitives, starting from `bound` (the previous
+// sample's bound, +inf at a ray's first sample), and a primary ray's sample names
+// its nearest primitive in `slot` (level is 0).
+template <bool kPrimary, int kSdf>
+__device__ __forceinline__ int trace_step(const TraceArgs &a, const SdfLds<kSdf> &s, float o0,
                                           float o1, float o2, float w0, float w1, float w2,
                                           float &t, int &k, float &x0, float &x1, float &x2,
-                                          int &level, int &steps) {
+                                          int &level, int &steps, float &bound, int &slot) {
     if (t > a.t_max) { steps = k; return kMissTmax; }
     x0 = fmaf(t, w0, o0); x1 = fmaf(t, w1, o1); x2 = fmaf(t, w2, o2);
-    level = select_level(a, x0, x1, x2);
-    if (level < 0) { steps = k; return kMissExit; }
-    const LevelLds &d = s_lv[level];
-    const float dist = trilinear<kHalf>(d, (x0 - d.org0) * d.inv, (x1 - d.org1) * d.inv,
-                                        (x2 - d.org2) * d.inv);
+    float dist;
+    if constexpr (kSdf == kSdfAnalytic) {
+        level = 0;
+        if (kPrimary) {
+            dist = nearest_distance(a.an, s.cl, x0, x1, x2, bound, slot);
+        } else {
+            uint32_t evals = 0;
+            dist = scene_distance(a.an, s.cl, 2, x0, x1, x2, bound, evals);
+        }
+    } else {
+        level = select_level(a, x0, x1, x2);
+        if (level < 0) { steps = k; return kMissExit; }
+        const LevelLds &d = s.lv[level];
+        dist = trilinear<kSdf == kSdfGrid16>(d, (x0 - d.org0) * d.inv, (x1 - d.org1) * d.inv,
+                                             (x2 - d.org2) * d.inv);
+    }
     if (kPrimary && k == 0 && dist < 0.0f) { steps = 1; return kInside; }
     if (dist < a.eps) { steps = k + 1; return kHit; }
     t = fmaf(a.relax, dist, t);
+    if constexpr (kSdf == kSdfAnalytic) bound = next_bound(a.relax, dist);
     ++k;
     if (k == a.max_steps) { steps = k; return kHitExhausted; }
     return -1;
@@ -155,11 +185,11 @@ constexpr int kRefillBelow = 32;  // refill / run batched work when fewer lanes 
 // per wave in LDS. Each ray's arithmetic is the fixed sequence of trace_step,
 // whatever lane or wave runs it. Every wave exits once the counter has passed the
 // last ray and its lanes are idle, after flushing its staged hits.
-template <bool kHalf>
+template <int kSdf>
 __global__ __launch_bounds__(256) void primary_kernel(TraceArgs a) {
-    __shared__ LevelLds s_lv[kMaxLevels];
+    __shared__ SdfLds<kSdf> s_sdf;
     __shared__ int4 s_hits[4][64];
-    load_levels(a, s_lv);
+    load_sdf<kSdf>(a, s_sdf);
     const int lane = (int)__lane_id();
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     int staged = 0;  // wave-uniform count of entries in s_hits[wave]
@@ -168,8 +198,8 @@ __global__ __launch_bounds__(256) void primary_kernel(TraceArgs a) {
     BlockFeeder<kChunk, kXcdBlock> feed;
     feed.start();
     bool active = false;
-    int ray = 0, k = 0;
-    float o0 = 0, o1 = 0, o2 = 0, w0 = 0, w1 = 0, w2 = 0, t = 0;
+    int ray = 0, k = 0, slot = -1;
+    float o0 = 0, o1 = 0, o2 = 0, w0 = 0, w1 = 0, w2 = 0, t = 0, bound = INFINITY;
     while (true) {
         uint64_t stepping = __ballot(active);
         if (__popcll(stepping) < kRefillBelow) {
@@ -189,6 +219,7 @@ __global__ __launch_bounds__(256) void primary_kernel(TraceArgs a) {
                     w0 = a.dirs[3 * i]; w1 = a.dirs[3 * i + 1]; w2 = a.dirs[3 * i + 2];
                     t = 0.0f;
                     k = 0;
+                    bound = INFINITY;
                     active = true;
                 }
                 idle = __ballot(!active);
@@ -205,12 +236,13 @@ __global__ __launch_bounds__(256) void primary_kernel(TraceArgs a) {
             const float tt = t;
             float x0, x1, x2;
             int level = 0, steps = 0;
-            const int kind = trace_step<true, kHalf>(a, s_lv, o0, o1, o2, w0, w1, w2, t, k, x0,
-                                                     x1, x2, level, steps);
+            const int kind = trace_step<true, kSdf>(a, s_sdf, o0, o1, o2, w0, w1, w2, t, k, x0,
+                                                    x1, x2, level, steps, bound, slot);
             if (kind >= 0) {
                 if (kind == kHit || kind == kHitExhausted) {
                     hit_now = true;
-                    entry = make_int4(ray, __float_as_int(tt), pack_hit(kind, level, steps), 0);
+                    entry = make_int4(ray, __float_as_int(tt), pack_hit(kind, level, steps),
+                                      kSdf == kSdfAnalytic ? slot : 0);
                 } else {
                     const float4 out = kind == kInside ? make_float4(0.0f, 0.0f, 0.0f, 0.0f)
                                                        : make_float4(a.sky0, a.sky1, a.sky2, a.t_max);
@@ -245,18 +277,18 @@ constexpr int kShadeBatch = 16;   // shade when this many lanes wait (or steppin
 // newly assigned lanes), the SDF shadow ray toward the light (wave-compacted like the
 // primary trace), and shading -- albedo, sun, multi-bounce lookup -- batched when
 // kShadeBatch lanes wait or stepping runs low.
-template <bool kHalf>
+template <int kSdf>
 __global__ __launch_bounds__(256) void hits_kernel(TraceArgs a) {
-    __shared__ LevelLds s_lv[kMaxLevels];
-    load_levels(a, s_lv);
+    __shared__ SdfLds<kSdf> s_sdf;
+    load_sdf<kSdf>(a, s_sdf);
     const int lane = (int)__lane_id();
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const int total = a.counter[2];  // queue length, final once primary_kernel has finished
     Feeder<kHitChunk> feed;
 
-    int mode = kIdle, ray = 0, info = 0, k = 0, vis = -1;
+    int mode = kIdle, ray = 0, info = 0, k = 0, vis = -1, slot = 0;
     float ht = 0, hx0 = 0, hx1 = 0, hx2 = 0, n0 = 0, n1 = 0, n2 = 0;
-    float o0 = 0, o1 = 0, o2 = 0, t = 0;
+    float o0 = 0, o1 = 0, o2 = 0, t = 0, bound = INFINITY;
     while (true) {
         uint64_t stepping = __ballot(mode == kShadow);
         const int waiting = __popcll(__ballot(mode == kPendShade));
@@ -265,10 +297,14 @@ __global__ __launch_bounds__(256) void hits_kernel(TraceArgs a) {
                 if (__ballot(mode == kPendShade)) {
                     if (mode == kPendShade) {
                         // k holds the shadow ray's step count here
-                        const LevelLds &d = s_lv[(info >> 4) & 15];
                         const float ndl = fmaf(n2, a.l2, fmaf(n1, a.l1, n0 * a.l0));
                         const float lit = vis == 1 ? ndl : 0.0f;
-                        const float3 alb = albedo_at(a, d, hx0, hx1, hx2);
+                        float3 alb;
+                        if constexpr (kSdf == kSdfAnalytic)
+                            alb = make_float3(a.prim_alb[3 * slot], a.prim_alb[3 * slot + 1],
+                                              a.prim_alb[3 * slot + 2]);
+                        else
+                            alb = albedo_at(a, s_sdf.lv[(info >> 4) & 15], hx0, hx1, hx2);
                         float3 ind = make_float3(0.0f, 0.0f, 0.0f);
                         if (a.gain != 0.0f)
                             ind = interp_irradiance(a.prev_irr, a.irr_res, a.pg, hx0, hx1, hx2, n0,
@@ -296,6 +332,7 @@ __global__ __launch_bounds__(256) void hits_kernel(TraceArgs a) {
                         ray = e.x;
                         ht = __int_as_float(e.y);
                         info = e.z;
+                        slot = e.w;
                         mode = kNew;
                     }
                     idle = __ballot(mode == kIdle);
@@ -308,8 +345,11 @@ __global__ __launch_bounds__(256) void hits_kernel(TraceArgs a) {
                                     po2 = a.probe_pos[3 * p + 2];
                         const float w0 = a.dirs[3 * i], w1 = a.dirs[3 * i + 1], w2 = a.dirs[3 * i + 2];
                         hx0 = fmaf(ht, w0, po0); hx1 = fmaf(ht, w1, po1); hx2 = fmaf(ht, w2, po2);
-                        hit_normal<kHalf>(s_lv[(info >> 4) & 15], hx0, hx1, hx2, w0, w1, w2, n0, n1,
-                                          n2);
+                        if constexpr (kSdf == kSdfAnalytic)
+                            analytic_normal(s_sdf.cl, slot, hx0, hx1, hx2, w0, w1, w2, n0, n1, n2);
+                        else
+                            hit_normal<kSdf == kSdfGrid16>(s_sdf.lv[(info >> 4) & 15], hx0, hx1,
+                                                           hx2, w0, w1, w2, n0, n1, n2);
                         const float ndl = fmaf(n2, a.l2, fmaf(n1, a.l1, n0 * a.l0));
                         if (ndl > 0.0f) {
                             o0 = fmaf(n0, a.bias, hx0);
@@ -317,6 +357,7 @@ __global__ __launch_bounds__(256) void hits_kernel(TraceArgs a) {
                             o2 = fmaf(n2, a.bias, hx2);
                             t = 0.0f;
                             k = 0;
+                            bound = INFINITY;
                             mode = kShadow;
                         } else {
                             vis = -1;
@@ -332,8 +373,9 @@ __global__ __launch_bounds__(256) void hits_kernel(TraceArgs a) {
         if (mode == kShadow) {
             float x0, x1, x2;
             int level = 0, steps = 0;
-            const int kind = trace_step<false, kHalf>(a, s_lv, o0, o1, o2, a.l0, a.l1, a.l2, t,
-                                                      k, x0, x1, x2, level, steps);
+            int unused = 0;
+            const int kind = trace_step<false, kSdf>(a, s_sdf, o0, o1, o2, a.l0, a.l1, a.l2, t,
+                                                     k, x0, x1, x2, level, steps, bound, unused);
             if (kind >= 0) {
                 vis = (kind == kHit || kind == kHitExhausted) ? 0 : 1;
                 k = steps;
@@ -702,13 +744,17 @@ constexpr int kPrimaryBlocksPerCuOverlapped[2] = {3, 4};  // binary32, binary16 
 constexpr int kHitsBlocksPerCu = 2;
 constexpr int kHitsBlocksPerCuOverlapped = 1;
 
-TraceGrid trace_grid(int device, int64_t rays, bool half) {
+TraceGrid trace_grid(int device, int64_t rays, bool half, bool analytic) {
     TraceGrid g;
-    const void *pk = half ? (const void *)primary_kernel<true> : (const void *)primary_kernel<false>;
+    const void *pk = analytic ? (const void *)primary_kernel<kSdfAnalytic>
+                     : half   ? (const void *)primary_kernel<kSdfGrid16>
+                              : (const void *)primary_kernel<kSdfGrid32>;
     g.primary_blocks = persistent_blocks(pk, device, rays, kPrimaryBlocksPerCu);
     g.primary_blocks_overlapped =
         persistent_blocks(pk, device, rays, kPrimaryBlocksPerCuOverlapped[half ? 1 : 0]);
-    const void *hk = half ? (const void *)hits_kernel<true> : (const void *)hits_kernel<false>;
+    const void *hk = analytic ? (const void *)hits_kernel<kSdfAnalytic>
+                     : half   ? (const void *)hits_kernel<kSdfGrid16>
+                              : (const void *)hits_kernel<kSdfGrid32>;
     g.hits_blocks = persistent_blocks(hk, device, rays, kHitsBlocksPerCu);
     g.hits_blocks_overlapped = persistent_blocks(hk, device, rays, kHitsBlocksPerCuOverlapped);
     return g;
@@ -716,19 +762,24 @@ TraceGrid trace_grid(int device, int64_t rays, bool half) {
 
 hipError_t launch_primary(const TraceArgs &a, const TraceGrid &g, hipStream_t s) {
     if ((int64_t)a.P * a.R == 0) return hipSuccess;
-    if (a.half_sdf)
-        hipLaunchKernelGGL(primary_kernel<true>, dim3(g.primary_blocks), dim3(256), 0, s, a);
+    if (a.analytic)
+        hipLaunchKernelGGL(primary_kernel<kSdfAnalytic>, dim3(g.primary_blocks), dim3(256), 0, s,
+                           a);
+    else if (a.half_sdf)
+        hipLaunchKernelGGL(primary_kernel<kSdfGrid16>, dim3(g.primary_blocks), dim3(256), 0, s, a);
     else
-        hipLaunchKernelGGL(primary_kernel<false>, dim3(g.primary_blocks), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(primary_kernel<kSdfGrid32>, dim3(g.primary_blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_hits(const TraceArgs &a, const TraceGrid &g, hipStream_t s) {
     if ((int64_t)a.P * a.R == 0) return hipSuccess;
-    if (a.half_sdf)
-        hipLaunchKernelGGL(hits_kernel<true>, dim3(g.hits_blocks), dim3(256), 0, s, a);
+    if (a.analytic)
+        hipLaunchKernelGGL(hits_kernel<kSdfAnalytic>, dim3(g.hits_blocks), dim3(256), 0, s, a);
+    else if (a.half_sdf)
+        hipLaunchKernelGGL(hits_kernel<kSdfGrid16>, dim3(g.hits_blocks), dim3(256), 0, s, a);
     else
-        hipLaunchKernelGGL(hits_kernel<false>, dim3(g.hits_blocks), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(hits_kernel<kSdfGrid32>, dim3(g.hits_blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

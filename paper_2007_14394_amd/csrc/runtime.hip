@@ -191,6 +191,12 @@ struct sdfddgi_ctx {
     float *mean_error = nullptr;                     // [P]
     uint8_t *fb_next = nullptr;                      // [P] plain update in the next learned
                                                      //     frame (set until a prediction)
+    // analytic scene (sdfddgi_create_analytic): the primitives in cluster order
+    bool analytic = false;
+    int an_nprims = 0, an_nclusters = 0;
+    int *an_kind = nullptr, *an_orig = nullptr, *an_first = nullptr;
+    float *an_center = nullptr, *an_half = nullptr, *an_lo = nullptr, *an_hi = nullptr;
+    float *an_alb = nullptr;
     // Timing: kEvents events per frame in a ring (see sdfddgi_get_kernel_times);
     // sdfddgi_get_kernel_times averages the frames recorded since its previous call.
     hipEvent_t *ev_ring = nullptr;
@@ -300,6 +306,8 @@ void free_all(sdfddgi_ctx *c) {
     dev_free(c->u_irr); dev_free(c->u_depth);
     dev_free(c->probe_sdf); dev_free(c->texel_dir); dev_free(c->fallback); dev_free(c->mean_error);
     dev_free(c->fb_next);
+    dev_free(c->an_kind); dev_free(c->an_orig); dev_free(c->an_first); dev_free(c->an_center);
+    dev_free(c->an_half); dev_free(c->an_lo); dev_free(c->an_hi); dev_free(c->an_alb);
     if (c->ev_ring) {
         for (int k = 0; k < kEvents * kTimingRing; ++k)
             if (c->ev_ring[k]) (void)hipEventDestroy(c->ev_ring[k]);
@@ -308,6 +316,8 @@ void free_all(sdfddgi_ctx *c) {
 }
 
 bool valid_rays(int R) { return R >= 16 && R <= kMaxRays && R % 16 == 0; }
+
+sdfddgi_status validate_probes_params(const sdfddgi_probe_grid *pg, const sdfddgi_params *p);
 
 sdfddgi_status validate(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_grid *pg,
                         const sdfddgi_params *p) {
@@ -330,6 +340,11 @@ sdfddgi_status validate(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_grid *p
             return fail(nullptr, SDFDDGI_EINVAL, "level %d: spacing must be finite and > 0", L);
         if (!lv.sdf) return fail(nullptr, SDFDDGI_EINVAL, "level %d: sdf is NULL", L);
     }
+    return validate_probes_params(pg, p);
+}
+
+sdfddgi_status validate_probes_params(const sdfddgi_probe_grid *pg, const sdfddgi_params *p) {
+    if (!pg || !p) return fail(nullptr, SDFDDGI_EINVAL, "null argument");
     int64_t P = 1;
     for (int c = 0; c < 3; ++c) {
         if (pg->n[c] < 2) return fail(nullptr, SDFDDGI_EINVAL, "probe grid n[%d] < 2", c);
@@ -377,6 +392,101 @@ sdfddgi_status validate(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_grid *p
                         "irr_res", kMaxLearnedRes);
     }
     return SDFDDGI_OK;
+}
+
+// An analytic scene's primitives packed into clusters for the culled query of
+// Sec. 3.3: primitives in Morton order of their centres, cluster_size at a time;
+// each cluster's bounding box is widened by 1e-4 (1 + the scene's reach) and
+// rounded outward, so its binary32 distance stays below every member's.
+struct HostClusters {
+    int nprims = 0, nclusters = 0;
+    std::vector<int> kind, orig, first;
+    std::vector<float> cen, half, lo, hi, alb;
+};
+
+// Empty on success, else why the primitives are refused. albedo may be null.
+std::string build_clusters(int nprims, const int32_t *kind, const double *center,
+                           const double *half, const double *albedo, int cluster_size,
+                           HostClusters &h) {
+    char msg[160];
+    if (nprims < 1 || nprims > kMaxAnalyticPrims || !kind || !center || !half) {
+        std::snprintf(msg, sizeof msg, "need 1..%d primitives", kMaxAnalyticPrims);
+        return msg;
+    }
+    if (cluster_size < 1 || cluster_size > 64) return "cluster_size must be in 1..64";
+    const int nclusters = (nprims + cluster_size - 1) / cluster_size;
+    if (nclusters > kMaxClusters) {
+        std::snprintf(msg, sizeof msg, "more than %d clusters", kMaxClusters);
+        return msg;
+    }
+    double lo_s[3] = {INFINITY, INFINITY, INFINITY}, hi_s[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double reach = 0.0;
+    for (int m = 0; m < nprims; ++m) {
+        if (kind[m] != 0 && kind[m] != 1) {
+            std::snprintf(msg, sizeof msg, "primitive kind %d", kind[m]);
+            return msg;
+        }
+        for (int c = 0; c < 3; ++c) {
+            const double hc = kind[m] == 0 ? half[3 * m] : half[3 * m + c];
+            if (!std::isfinite(center[3 * m + c]) || !std::isfinite(hc) || hc < 0) {
+                std::snprintf(msg, sizeof msg, "primitive %d: bad centre or size", m);
+                return msg;
+            }
+            if (albedo && !(albedo[3 * m + c] >= 0 && std::isfinite(albedo[3 * m + c]))) {
+                std::snprintf(msg, sizeof msg, "primitive %d: bad albedo", m);
+                return msg;
+            }
+            lo_s[c] = std::min(lo_s[c], center[3 * m + c]);
+            hi_s[c] = std::max(hi_s[c], center[3 * m + c]);
+            reach = std::max(reach, std::fabs(center[3 * m + c]) + hc);
+        }
+    }
+    std::vector<std::pair<uint64_t, int>> order((size_t)nprims);
+    for (int m = 0; m < nprims; ++m) {
+        uint64_t code = 0;
+        for (int c = 0; c < 3; ++c) {
+            const double ext = hi_s[c] - lo_s[c];
+            const double u = ext > 0 ? (center[3 * m + c] - lo_s[c]) / ext : 0.0;
+            const uint64_t q = (uint64_t)std::min(1023.0, std::max(0.0, std::floor(u * 1024.0)));
+            for (int bit = 0; bit < 10; ++bit) code |= ((q >> bit) & 1ull) << (3 * bit + c);
+        }
+        order[(size_t)m] = {code, m};
+    }
+    std::sort(order.begin(), order.end());
+    h.nprims = nprims;
+    h.nclusters = nclusters;
+    h.kind.assign(nprims, 0);
+    h.orig.assign(nprims, 0);
+    h.first.assign(nclusters + 1, 0);
+    h.cen.assign(3 * (size_t)nprims, 0.0f);
+    h.half.assign(3 * (size_t)nprims, 0.0f);
+    h.alb.assign(3 * (size_t)nprims, 0.0f);
+    h.lo.assign(3 * (size_t)nclusters, 0.0f);
+    h.hi.assign(3 * (size_t)nclusters, 0.0f);
+    const double widen = 1e-4 * (1.0 + reach);
+    for (int k = 0; k < nclusters; ++k) {
+        h.first[k] = k * cluster_size;
+        double blo[3] = {INFINITY, INFINITY, INFINITY}, bhi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int j = k * cluster_size; j < std::min(nprims, (k + 1) * cluster_size); ++j) {
+            const int m = order[(size_t)j].second;
+            h.kind[j] = kind[m];
+            h.orig[j] = m;
+            for (int c = 0; c < 3; ++c) {
+                const double hc = kind[m] == 0 ? half[3 * m] : half[3 * m + c];
+                h.cen[3 * j + c] = (float)center[3 * m + c];
+                h.half[3 * j + c] = (float)half[3 * m + c];
+                if (albedo) h.alb[3 * j + c] = (float)albedo[3 * m + c];
+                blo[c] = std::min(blo[c], center[3 * m + c] - hc);
+                bhi[c] = std::max(bhi[c], center[3 * m + c] + hc);
+            }
+        }
+        for (int c = 0; c < 3; ++c) {   // widened, then rounded outward
+            h.lo[3 * k + c] = std::nextafter((float)(blo[c] - widen), -INFINITY);
+            h.hi[3 * k + c] = std::nextafter((float)(bhi[c] + widen), INFINITY);
+        }
+    }
+    h.first[nclusters] = nprims;
+    return std::string();
 }
 
 // Monotone integer key of a binary32 value (orders all finite floats).
@@ -497,7 +607,7 @@ hipError_t alloc_set(sdfddgi_ctx *c, RaySet &r, int R) {
         chk(hipMemsetAsync(r.w16_i, 0, (size_t)c->Tpi * r.Rpad * 2, c->stream));
         chk(hipMemsetAsync(r.w16_d, 0, (size_t)c->Tpd * r.Rpad * 2, c->stream));
     }
-    r.grid = trace_grid(c->device, c->P * R, c->half);
+    r.grid = trace_grid(c->device, c->P * R, c->half, c->analytic);
     return e;
 }
 
@@ -582,6 +692,19 @@ TraceArgs trace_base(const sdfddgi_ctx *c, const float l[3], const float rad[3])
     t.probe_pos = c->probe_pos;
     t.probe_order = c->probe_order;
     t.prev_irr = c->irr[c->cur];
+    if (c->analytic) {
+        t.analytic = 1;
+        t.an.nprims = c->an_nprims;
+        t.an.nclusters = c->an_nclusters;
+        t.an.kind = c->an_kind;
+        t.an.orig = c->an_orig;
+        t.an.center = c->an_center;
+        t.an.half = c->an_half;
+        t.an.lo = c->an_lo;
+        t.an.hi = c->an_hi;
+        t.an.first = c->an_first;
+        t.prim_alb = c->an_alb;
+    }
     return t;
 }
 
@@ -688,14 +811,13 @@ void sdfddgi_default_params(sdfddgi_params *p) {
     p->fallback_error = 0.02f;
 }
 
-sdfddgi_status sdfddgi_create(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_grid *probes,
-                              const sdfddgi_params *params, void *hip_stream, sdfddgi_ctx **out) {
-    g_create_error.clear();
-    if (!out) return fail(nullptr, SDFDDGI_EINVAL, "out is NULL");
-    *out = nullptr;
-    sdfddgi_status st = validate(sdf, probes, params);
-    if (st != SDFDDGI_OK) return st;
+}  // extern "C"
 
+// The body of both create entry points, after their checks: the scene is either the
+// grid levels (sdf) or the clustered primitives (hc).
+static sdfddgi_status create_ctx(const sdfddgi_sdf_grid *sdf, const HostClusters *hc,
+                                 const sdfddgi_probe_grid *probes, const sdfddgi_params *params,
+                                 void *hip_stream, sdfddgi_ctx **out) {
     int count = 0;
     hipError_t e = hipGetDeviceCount(&count);
     if (e != hipSuccess || count < 1) return fail(nullptr, SDFDDGI_EDEVICE, "no HIP device visible");
@@ -714,7 +836,8 @@ sdfddgi_status sdfddgi_create(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_g
     c->stream = (hipStream_t)hip_stream;
     c->prm = *params;
     c->half = (params->flags & SDFDDGI_FLAG_FP16) != 0;
-    c->nl = sdf->num_levels;
+    c->nl = sdf ? sdf->num_levels : 0;
+    c->analytic = hc != nullptr;
     c->pg = *probes;
     c->P = (int64_t)probes->n[0] * probes->n[1] * probes->n[2];
     c->Ti = params->irr_res * params->irr_res;
@@ -754,6 +877,35 @@ sdfddgi_status sdfddgi_create(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_g
             SDF_TRY(hipMemcpyAsync(c->alb[L], lv.albedo_rgb, 3 * cnt * sizeof(float),
                                    hipMemcpyDeviceToDevice, c->stream), "copying albedo level");
         }
+    }
+    if (hc) {
+        c->an_nprims = hc->nprims;
+        c->an_nclusters = hc->nclusters;
+        const size_t n3 = 3 * (size_t)hc->nprims, k3 = 3 * (size_t)hc->nclusters;
+        SDF_TRY(dev_alloc(&c->an_kind, hc->nprims), "allocating primitives");
+        SDF_TRY(dev_alloc(&c->an_orig, hc->nprims), "allocating primitives");
+        SDF_TRY(dev_alloc(&c->an_first, hc->nclusters + 1), "allocating primitives");
+        SDF_TRY(dev_alloc(&c->an_center, n3), "allocating primitives");
+        SDF_TRY(dev_alloc(&c->an_half, n3), "allocating primitives");
+        SDF_TRY(dev_alloc(&c->an_alb, n3), "allocating primitives");
+        SDF_TRY(dev_alloc(&c->an_lo, k3), "allocating primitives");
+        SDF_TRY(dev_alloc(&c->an_hi, k3), "allocating primitives");
+        SDF_TRY(hipMemcpy(c->an_kind, hc->kind.data(), hc->nprims * sizeof(int),
+                          hipMemcpyHostToDevice), "uploading primitives");
+        SDF_TRY(hipMemcpy(c->an_orig, hc->orig.data(), hc->nprims * sizeof(int),
+                          hipMemcpyHostToDevice), "uploading primitives");
+        SDF_TRY(hipMemcpy(c->an_first, hc->first.data(), (hc->nclusters + 1) * sizeof(int),
+                          hipMemcpyHostToDevice), "uploading primitives");
+        SDF_TRY(hipMemcpy(c->an_center, hc->cen.data(), n3 * sizeof(float), hipMemcpyHostToDevice),
+                "uploading primitives");
+        SDF_TRY(hipMemcpy(c->an_half, hc->half.data(), n3 * sizeof(float), hipMemcpyHostToDevice),
+                "uploading primitives");
+        SDF_TRY(hipMemcpy(c->an_alb, hc->alb.data(), n3 * sizeof(float), hipMemcpyHostToDevice),
+                "uploading primitives");
+        SDF_TRY(hipMemcpy(c->an_lo, hc->lo.data(), k3 * sizeof(float), hipMemcpyHostToDevice),
+                "uploading primitives");
+        SDF_TRY(hipMemcpy(c->an_hi, hc->hi.data(), k3 * sizeof(float), hipMemcpyHostToDevice),
+                "uploading primitives");
     }
 
     // Host constants in binary64: probe positions (rounded once), the probes'
@@ -864,6 +1016,39 @@ sdfddgi_status sdfddgi_create(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_g
 #undef SDF_TRY
     *out = c;
     return SDFDDGI_OK;
+}
+
+extern "C" {
+
+sdfddgi_status sdfddgi_create(const sdfddgi_sdf_grid *sdf, const sdfddgi_probe_grid *probes,
+                              const sdfddgi_params *params, void *hip_stream, sdfddgi_ctx **out) {
+    g_create_error.clear();
+    if (!out) return fail(nullptr, SDFDDGI_EINVAL, "out is NULL");
+    *out = nullptr;
+    sdfddgi_status st = validate(sdf, probes, params);
+    if (st != SDFDDGI_OK) return st;
+    return create_ctx(sdf, nullptr, probes, params, hip_stream, out);
+}
+
+sdfddgi_status sdfddgi_create_analytic(int32_t nprims, const int32_t *kind, const double *center,
+                                       const double *half, const double *albedo,
+                                       int32_t cluster_size, const sdfddgi_probe_grid *probes,
+                                       const sdfddgi_params *params, void *hip_stream,
+                                       sdfddgi_ctx **out) {
+    g_create_error.clear();
+    if (!out) return fail(nullptr, SDFDDGI_EINVAL, "out is NULL");
+    *out = nullptr;
+    sdfddgi_status st = validate_probes_params(probes, params);
+    if (st != SDFDDGI_OK) return st;
+    if (params->flags & SDFDDGI_FLAG_FP16)
+        return fail(nullptr, SDFDDGI_EINVAL, "the precision form stores a grid: not analytic");
+    if (params->learned_rays != 0)
+        return fail(nullptr, SDFDDGI_EINVAL, "the learned form needs a grid: learned_rays must be 0");
+    if (!albedo) return fail(nullptr, SDFDDGI_EINVAL, "albedo is NULL");
+    HostClusters hc;
+    const std::string why = build_clusters(nprims, kind, center, half, albedo, cluster_size, hc);
+    if (!why.empty()) return fail(nullptr, SDFDDGI_EINVAL, "%s", why.c_str());
+    return create_ctx(nullptr, &hc, probes, params, hip_stream, out);
 }
 
 sdfddgi_status sdfddgi_update_frame(sdfddgi_ctx *c, const sdfddgi_light *light,
@@ -1079,6 +1264,7 @@ sdfddgi_status sdfddgi_relocate_probes(sdfddgi_ctx *c, float threshold1, float t
                                        int32_t iterations, float max_offset) {
     sdfddgi_status st = check_ctx(c);
     if (st != SDFDDGI_OK) return st;
+    if (c->analytic) return fail(c, SDFDDGI_ESTATE, "relocation walks a grid: analytic context");
     const float v[3] = {threshold1, threshold2, max_offset};
     if (!finite_all(v, 3) || !(threshold2 >= 0) || !(max_offset >= 0) || iterations < 0 ||
         iterations > 1024)
@@ -2469,64 +2655,13 @@ sdfddgi_status sdfddgi_analytic_create(int32_t nprims, const int32_t *kind, cons
     g_learned_error.clear();
     if (!out) return lfail(SDFDDGI_EINVAL, "out is NULL");
     *out = nullptr;
-    if (nprims < 1 || nprims > kMaxAnalyticPrims || !kind || !center || !half)
-        return lfail(SDFDDGI_EINVAL, "need 1..%d primitives", kMaxAnalyticPrims);
-    if (cluster_size < 1 || cluster_size > 64)
-        return lfail(SDFDDGI_EINVAL, "cluster_size must be in 1..64");
-    const int nclusters = (nprims + cluster_size - 1) / cluster_size;
-    if (nclusters > kMaxClusters)
-        return lfail(SDFDDGI_EINVAL, "more than %d clusters", kMaxClusters);
-    double lo_s[3] = {INFINITY, INFINITY, INFINITY}, hi_s[3] = {-INFINITY, -INFINITY, -INFINITY};
-    double reach = 0.0;
-    for (int m = 0; m < nprims; ++m) {
-        if (kind[m] != 0 && kind[m] != 1) return lfail(SDFDDGI_EINVAL, "primitive kind %d", kind[m]);
-        for (int c = 0; c < 3; ++c) {
-            const double h = kind[m] == 0 ? half[3 * m] : half[3 * m + c];
-            if (!std::isfinite(center[3 * m + c]) || !std::isfinite(h) || h < 0)
-                return lfail(SDFDDGI_EINVAL, "primitive %d: bad centre or size", m);
-            lo_s[c] = std::min(lo_s[c], center[3 * m + c]);
-            hi_s[c] = std::max(hi_s[c], center[3 * m + c]);
-            reach = std::max(reach, std::fabs(center[3 * m + c]) + h);
-        }
-    }
+    HostClusters hc;
+    const std::string why = build_clusters(nprims, kind, center, half, nullptr, cluster_size, hc);
+    if (!why.empty()) return lfail(SDFDDGI_EINVAL, "%s", why.c_str());
     (void)hipGetLastError();
-    // clusters: primitives in Morton order of their centres, cluster_size at a time
-    std::vector<std::pair<uint64_t, int>> order((size_t)nprims);
-    for (int m = 0; m < nprims; ++m) {
-        uint64_t code = 0;
-        for (int c = 0; c < 3; ++c) {
-            const double ext = hi_s[c] - lo_s[c];
-            const double u = ext > 0 ? (center[3 * m + c] - lo_s[c]) / ext : 0.0;
-            const uint64_t q = (uint64_t)std::min(1023.0, std::max(0.0, std::floor(u * 1024.0)));
-            for (int bit = 0; bit < 10; ++bit) code |= ((q >> bit) & 1ull) << (3 * bit + c);
-        }
-        order[(size_t)m] = {code, m};
-    }
-    std::sort(order.begin(), order.end());
-    std::vector<int> h_kind(nprims), h_first(nclusters + 1);
-    std::vector<float> h_cen(3 * (size_t)nprims), h_half(3 * (size_t)nprims);
-    std::vector<float> h_lo(3 * (size_t)nclusters), h_hi(3 * (size_t)nclusters);
-    const double widen = 1e-4 * (1.0 + reach);
-    for (int k = 0; k < nclusters; ++k) {
-        h_first[k] = k * cluster_size;
-        double blo[3] = {INFINITY, INFINITY, INFINITY}, bhi[3] = {-INFINITY, -INFINITY, -INFINITY};
-        for (int j = k * cluster_size; j < std::min(nprims, (k + 1) * cluster_size); ++j) {
-            const int m = order[(size_t)j].second;
-            h_kind[j] = kind[m];
-            for (int c = 0; c < 3; ++c) {
-                const double h = kind[m] == 0 ? half[3 * m] : half[3 * m + c];
-                h_cen[3 * j + c] = (float)center[3 * m + c];
-                h_half[3 * j + c] = (float)half[3 * m + c];
-                blo[c] = std::min(blo[c], center[3 * m + c] - h);
-                bhi[c] = std::max(bhi[c], center[3 * m + c] + h);
-            }
-        }
-        for (int c = 0; c < 3; ++c) {   // widened, then rounded outward
-            h_lo[3 * k + c] = std::nextafter((float)(blo[c] - widen), -INFINITY);
-            h_hi[3 * k + c] = std::nextafter((float)(bhi[c] + widen), INFINITY);
-        }
-    }
-    h_first[nclusters] = nprims;
+    const int nclusters = hc.nclusters;
+    const std::vector<int> &h_kind = hc.kind, &h_first = hc.first;
+    const std::vector<float> &h_cen = hc.cen, &h_half = hc.half, &h_lo = hc.lo, &h_hi = hc.hi;
     sdfddgi_analytic *an = new (std::nothrow) sdfddgi_analytic();
     if (!an) return lfail(SDFDDGI_ENOMEM, "host allocation failed");
     hipError_t e = hipGetDevice(&an->device);

@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "SDFDDGI_OK", 1: "SDFDDGI_EINVAL", 2: "SDFDDGI_ENOMEM",
                 3: "SDFDDGI_EDEVICE", 4: "SDFDDGI_ESTATE"}
 
 EXPORTED = [
-    "sdfddgi_default_params", "sdfddgi_create", "sdfddgi_update_frame",
+    "sdfddgi_default_params", "sdfddgi_create", "sdfddgi_create_analytic", "sdfddgi_update_frame",
     "sdfddgi_sample_irradiance", "sdfddgi_blend", "sdfddgi_get_maps", "sdfddgi_set_maps",
     "sdfddgi_reset_history", "sdfddgi_get_payload", "sdfddgi_get_ray_records",
     "sdfddgi_get_ray_directions", "sdfddgi_ray_directions", "sdfddgi_get_kernel_times",
@@ -121,6 +121,9 @@ def load_library() -> ctypes.CDLL:
     L.sdfddgi_create.argtypes = [ctypes.POINTER(sdfddgi_sdf_grid),
                                  ctypes.POINTER(sdfddgi_probe_grid),
                                  ctypes.POINTER(sdfddgi_params), vp, ctypes.POINTER(vp)]
+    L.sdfddgi_create_analytic.argtypes = [i32, vp, vp, vp, vp, i32,
+                                          ctypes.POINTER(sdfddgi_probe_grid),
+                                          ctypes.POINTER(sdfddgi_params), vp, ctypes.POINTER(vp)]
     L.sdfddgi_update_frame.argtypes = [vp, ctypes.POINTER(sdfddgi_light), u64]
     L.sdfddgi_sample_irradiance.argtypes = [vp, vp, vp, i64, vp]
     L.sdfddgi_blend.argtypes = [vp, vp, u64]
@@ -285,6 +288,35 @@ def sdfddgi_create(levels: Sequence[dict], probe_n, probe_origin, probe_spacing,
     P = int(np.prod([int(v) for v in probe_n]))
     return Context(out.value, device, stream, P, int(params.rays_per_probe),
                    int(params.irr_res), int(params.depth_res), int(params.flags))
+
+
+def sdfddgi_create_analytic(kind, center, half, albedo, probe_n, probe_origin, probe_spacing,
+                            params: sdfddgi_params, cluster_size: int = 8, device="cuda:0",
+                            stream=None) -> Context:
+    """A context that traces the primitives (host arrays: kind [M], center, half,
+    albedo [M,3]) instead of a grid."""
+    import torch
+    L = load_library()
+    kind = np.ascontiguousarray(kind, dtype=np.int32).reshape(-1)
+    m = kind.shape[0]
+    cen = np.ascontiguousarray(center, dtype=np.float64).reshape(m, 3)
+    hal = np.ascontiguousarray(half, dtype=np.float64).reshape(m, 3)
+    alb = np.ascontiguousarray(albedo, dtype=np.float64).reshape(m, 3)
+    pg = sdfddgi_probe_grid()
+    pg.n[:] = [int(v) for v in probe_n]
+    pg.origin[:] = [float(v) for v in probe_origin]
+    pg.spacing[:] = [float(v) for v in probe_spacing]
+    dev = torch.device(device)
+    P_ = ctypes.c_void_p
+    with torch.cuda.device(dev):
+        out = ctypes.c_void_p()
+        _check(None, L.sdfddgi_create_analytic(
+            ctypes.c_int32(m), P_(kind.ctypes.data), P_(cen.ctypes.data), P_(hal.ctypes.data),
+            P_(alb.ctypes.data), ctypes.c_int32(cluster_size), ctypes.byref(pg),
+            ctypes.byref(params), P_(_stream_handle(stream)), ctypes.byref(out)))
+    P = int(np.prod([int(v) for v in probe_n]))
+    return Context(out.value, dev, stream, P, int(params.rays_per_probe), int(params.irr_res),
+                   int(params.depth_res), int(params.flags))
 
 
 def sdfddgi_update_frame(ctx: Context, dir_to_light, radiance_rgb, rotation_seed: int) -> None:
@@ -872,11 +904,13 @@ def params_from(p, flags: int = 0) -> sdfddgi_params:
     return out
 
 
-def context_from_workload(w, flags: int = 0, device="cuda:0", stream=None, **param_overrides):
+def context_from_workload(w, flags: int = 0, device="cuda:0", stream=None, analytic: bool = False,
+                          cluster_size: int = 8, **param_overrides):
     """Upload a workload's grids (numpy) and create a context on ``device``.
 
     ``w`` needs ``levels`` (n, origin, spacing, sdf, albedo), ``probes`` (n, origin,
     spacing) and ``params``; the uploaded copies are released once create returns.
+    analytic=True: a context that traces ``w.prims`` instead (the grids are unused).
     """
     import torch
     prm = params_from(w.params, flags)
@@ -885,6 +919,11 @@ def context_from_workload(w, flags: int = 0, device="cuda:0", stream=None, **par
             getattr(prm, k)[:] = [float(x) for x in v]
         else:
             setattr(prm, k, v)
+    if analytic:
+        pr = w.prims
+        return sdfddgi_create_analytic(pr.kind, pr.center, pr.half, pr.albedo, w.probes.n,
+                                       w.probes.origin, w.probes.spacing, prm, cluster_size,
+                                       device, stream)
     dev = torch.device(device)
     levels = []
     for lv in w.levels:

@@ -238,3 +238,36 @@ def test_bake_entry_points_reject_bad_arguments_before_touching_a_device():
         kind[2] = 7
         assert fn(4, *args, n, org, 1.0, 0.0, fake, None, None) == S.SDFDDGI_EINVAL
         kind[2] = 0
+
+
+def test_create_analytic_rejects_bad_arguments_before_touching_a_device():
+    lib = S.load_library()
+    out = ctypes.c_void_p()
+    kind = np.array([0, 1], dtype=np.int32)
+    cen = np.zeros((2, 3))
+    hal = np.full((2, 3), 0.5)
+    alb = np.full((2, 3), 0.5)
+    P = ctypes.c_void_p
+    _, pg = _grid_and_probes()
+
+    def create(k=kind, c=cen, h=hal, a=alb, n=2, cs=8, mutate=None):
+        p = S.sdfddgi_default_params()
+        if mutate:
+            mutate(p)
+        return lib.sdfddgi_create_analytic(
+            n, P(k.ctypes.data), P(c.ctypes.data), P(h.ctypes.data),
+            P(a.ctypes.data) if a is not None else None, cs, ctypes.byref(pg), ctypes.byref(p),
+            None, ctypes.byref(out))
+
+    assert create(n=0) == S.SDFDDGI_EINVAL
+    assert create(n=1025) == S.SDFDDGI_EINVAL
+    assert create(cs=0) == S.SDFDDGI_EINVAL
+    assert create(a=None) == S.SDFDDGI_EINVAL
+    assert create(k=np.array([0, 2], dtype=np.int32)) == S.SDFDDGI_EINVAL
+    assert create(h=np.full((2, 3), -1.0)) == S.SDFDDGI_EINVAL
+    assert create(a=np.full((2, 3), -0.1)) == S.SDFDDGI_EINVAL
+    assert create(mutate=lambda p: setattr(p, "flags", S.SDFDDGI_FLAG_FP16)) == S.SDFDDGI_EINVAL
+    assert "precision form" in S.sdfddgi_last_error(None)
+    assert create(mutate=lambda p: setattr(p, "learned_rays", 16)) == S.SDFDDGI_EINVAL
+    assert create(mutate=lambda p: setattr(p, "rays_per_probe", 100)) == S.SDFDDGI_EINVAL
+    assert out.value is None
