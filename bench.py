@@ -122,6 +122,29 @@ def ray_statistics(S, w, frames):
     return {k: v / n for k, v in tot.items()}
 
 
+def gather_peaks(S, torch):
+    """Throughput of independent random 32-byte gathers (two adjacent 16-byte loads,
+    the trace sampler's access) from device buffers sized for the L2 (4 MiB), the
+    Infinity Cache (128 MiB, about the binary32 cascade's 132 MB of corner quads)
+    and HBM (1 GiB): the trace's second roofline denominator."""
+    out = {}
+    threads, reads = 1 << 20, 64
+    stream = torch.cuda.current_stream()
+    for name, mib in (("l2_4MiB", 4), ("infinity_cache_128MiB", 128), ("hbm_1GiB", 1024)):
+        buf = torch.rand(mib << 18, dtype=torch.float32, device="cuda:0")   # mib MiB
+        S.sdfddgi_measure_gather(buf, threads, reads, seed=7, stream=stream)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for k in range(5):
+            S.sdfddgi_measure_gather(buf, threads, reads, seed=11 + k, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / 5
+        out[name] = {"GB/s": threads * reads * 32 / (ms * 1e-3) / 1e9, "ms": ms}
+        del buf
+    return out
+
+
 def cpu_baseline(S, w, probes: int, torch):
     """The binary64 reference checker timed on the host's cores (one frame of the
     benchmarked workload from a seeded previous atlas), and, when the sample is the
@@ -562,6 +585,18 @@ def main():
         out["kernels"] = kernels
         out["ray_stats"] = {"primary_steps": st["prim"], "shadow_steps": st["shadow"],
                             "hit_fraction": st["hits"]}
+        if dom["unit"] == "GB/s":
+            # second denominator: measured gather peaks. The trace's 132 MB of corner
+            # quads exceed the L2, so its ceiling lies between random gathers beyond
+            # the L2 (no locality) and gathers the L2 serves (full locality).
+            stage("gather peaks")
+            peaks = gather_peaks(S, torch)
+            l2 = peaks["l2_4MiB"]["GB/s"]
+            beyond = peaks["infinity_cache_128MiB"]["GB/s"]
+            out["roofline"]["gather_peak"] = {
+                "unit": "GB/s", "l2_resident": l2, "frac_of_l2_resident": dom["achieved"] / l2,
+                "beyond_l2_random": beyond, "achieved_over_beyond_l2_random": dom["achieved"] / beyond,
+                "records": "random 32-B records (two adjacent 16-B loads)", "levels": peaks}
     if not args.no_learned:
         lw = scenegen.config2(args.seed, probes=args.probes, frames=args.learned_frames)
         stage("learned form")

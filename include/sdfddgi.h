@@ -559,6 +559,20 @@ sdfddgi_status sdfddgi_analytic_destroy(sdfddgi_analytic *an);
 
 /* Message of the last failure of a denoiser, trainer, baking, batch or analytic call
  * on this thread. */
+/* ------------------------------------------------------------ measurement --
+ * The gather throughput of the trace's access pattern, the second roofline
+ * denominator of the sphere trace beside HBM bandwidth (the trace reads each
+ * sample's eight corners as two adjacent 16-byte corner quads, at positions the
+ * rays scatter over the grid). Launches threads (1..2^30) threads on hip_stream,
+ * each reading `reads` (a multiple of 8 in 8..4096) independent 32-byte records
+ * of the device buffer buf (bytes = 32 x a power of two, at most 64 GiB) at
+ * indices from a counter-based hash of (seed, thread, read). sink: a device
+ * float the kernel writes only under a condition that finite data never meets.
+ * Asynchronous; the caller times it on the stream. Errors: EINVAL. */
+sdfddgi_status sdfddgi_measure_gather(const void *buf, int64_t bytes, int64_t threads,
+                                      int32_t reads, uint64_t seed, float *sink,
+                                      void *hip_stream);
+
 const char *sdfddgi_learned_last_error(void);
 
 #ifdef __cplusplus

@@ -10,7 +10,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB_DIR = os.path.join(PKG, "lib")
 LIB_PATH = os.path.join(LIB_DIR, "libsdfddgi.so")
-SOURCES = ["runtime.hip", "kernels.hip", "learned.hip", "scene.hip", "batch.hip", "cluster.hip"]
+SOURCES = ["runtime.hip", "kernels.hip", "learned.hip", "scene.hip", "batch.hip", "cluster.hip",
+           "measure.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

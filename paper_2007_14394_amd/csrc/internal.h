@@ -259,6 +259,10 @@ hipError_t launch_relocate(const TraceArgs &a, const RelocateArgs &r, hipStream_
 hipError_t launch_pack_mlp(const float *theta, uint4 *fwd, uint4 *bwd, float *bias,
                            hipStream_t stream);
 hipError_t launch_denoise(const DenoiseArgs &a, hipStream_t stream);
+// Measurement: `threads` threads each gathering `reads` (a multiple of 8) random
+// 32-byte records of a buffer of `records` (a power of two) records.
+hipError_t launch_gather(const void *buf, int64_t records, int64_t threads, int reads,
+                         uint32_t seed, float *sink, hipStream_t stream);
 // The fallback list of a learned frame: every probe whose history is rejected or
 // whose flag asks for the plain update; the flag is set for both (the denoiser reads
 // it while the fallback blend clears the reject flags). count zeroed before.

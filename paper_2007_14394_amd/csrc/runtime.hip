@@ -1856,6 +1856,25 @@ sdfddgi_status sdfddgi_bake_sdf_noalloc(int32_t nprims, const int32_t *kind, con
 
 const char *sdfddgi_learned_last_error(void) { return g_learned_error.c_str(); }
 
+sdfddgi_status sdfddgi_measure_gather(const void *buf, int64_t bytes, int64_t threads,
+                                      int32_t reads, uint64_t seed, float *sink,
+                                      void *hip_stream) {
+    g_learned_error.clear();
+    if (!buf || !sink) return lfail(SDFDDGI_EINVAL, "null buffer");
+    const int64_t records = bytes / 32;
+    if (bytes % 32 || records < 1 || (records & (records - 1)) || records > ((int64_t)1 << 31))
+        return lfail(SDFDDGI_EINVAL, "bytes must be 32 times a power of two, at most 64 GiB");
+    if (reads < 8 || reads > 4096 || reads % 8)
+        return lfail(SDFDDGI_EINVAL, "reads must be a multiple of 8 in 8..4096");
+    if (threads < 1 || threads > ((int64_t)1 << 30))
+        return lfail(SDFDDGI_EINVAL, "threads must be in 1..2^30");
+    (void)hipGetLastError();
+    const hipError_t e = launch_gather(buf, records, threads, reads, (uint32_t)(seed ^ (seed >> 32)),
+                                       sink, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return lhip_fail(e, "launching gather_kernel");
+    return SDFDDGI_OK;
+}
+
 }  // extern "C"
 
 // ------------------------------------------------------------ batched form --

@@ -42,7 +42,7 @@ EXPORTED = [
     "sdfddgi_batch_autotune", "sdfddgi_batch_set_tuning", "sdfddgi_batch_get_maps",
     "sdfddgi_batch_scene_latency", "sdfddgi_batch_sizes", "sdfddgi_batch_destroy",
     "sdfddgi_analytic_create", "sdfddgi_analytic_query", "sdfddgi_analytic_trace",
-    "sdfddgi_analytic_clusters", "sdfddgi_analytic_destroy",
+    "sdfddgi_analytic_clusters", "sdfddgi_analytic_destroy", "sdfddgi_measure_gather",
 ]
 SDFDDGI_MAX_BATCH_SCENES = 64
 SDFDDGI_DENOISER_PARAMS = 9604
@@ -160,6 +160,7 @@ def load_library() -> ctypes.CDLL:
                                    ctypes.POINTER(ctypes.c_double), ctypes.c_double, f32, vp,
                                    vp, vp]
     L.sdfddgi_bake_sdf_noalloc.argtypes = L.sdfddgi_bake_sdf.argtypes
+    L.sdfddgi_measure_gather.argtypes = [vp, i64, i64, i32, u64, vp, vp]
     L.sdfddgi_batch_create.argtypes = [vp, i32, vp, ctypes.POINTER(vp)]
     L.sdfddgi_batch_update_frame.argtypes = [vp, vp, u64]
     L.sdfddgi_batch_autotune.argtypes = [vp, vp, u64, i32, ctypes.POINTER(sdfddgi_batch_tuning),
@@ -884,6 +885,20 @@ def sdfddgi_analytic_destroy(an: Analytic) -> None:
     if an.handle and an.handle.value:
         _lcheck(load_library().sdfddgi_analytic_destroy(an.handle))
         an.handle = ctypes.c_void_p(0)
+
+
+def sdfddgi_measure_gather(buf, threads: int, reads: int, seed: int = 1, stream=None) -> None:
+    """Launch the gather measurement over the bytes of device tensor ``buf``
+    (32 x a power of two) on ``stream``; time it with events on that stream."""
+    import torch
+    if not buf.is_cuda or not buf.is_contiguous():
+        raise TypeError("buf must be a contiguous device tensor")
+    sink = torch.zeros(1, dtype=torch.float32, device=buf.device)
+    nbytes = buf.numel() * buf.element_size()
+    _lcheck(load_library().sdfddgi_measure_gather(
+        ctypes.c_void_p(buf.data_ptr()), ctypes.c_int64(nbytes), ctypes.c_int64(threads),
+        ctypes.c_int32(reads), ctypes.c_uint64(seed), ctypes.c_void_p(sink.data_ptr()),
+        ctypes.c_void_p(_stream_handle(stream))))
 
 
 def sdfddgi_learned_last_error() -> str:

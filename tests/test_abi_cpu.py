@@ -271,3 +271,14 @@ def test_create_analytic_rejects_bad_arguments_before_touching_a_device():
     assert create(mutate=lambda p: setattr(p, "learned_rays", 16)) == S.SDFDDGI_EINVAL
     assert create(mutate=lambda p: setattr(p, "rays_per_probe", 100)) == S.SDFDDGI_EINVAL
     assert out.value is None
+
+
+def test_measure_gather_rejects_bad_arguments_before_touching_a_device():
+    lib = S.load_library()
+    fake = ctypes.c_void_p(256)   # never dereferenced: every call below fails its checks
+    for bytes_, threads, reads in ((0, 1, 8), (96, 1, 8), (1 << 20, 1, 7), (1 << 20, 1, 0),
+                                   (1 << 20, 1, 8192), (1 << 20, 0, 8), (1 << 20, 1 << 31, 8)):
+        assert lib.sdfddgi_measure_gather(fake, bytes_, threads, reads, 1, fake,
+                                          None) == S.SDFDDGI_EINVAL
+    assert lib.sdfddgi_measure_gather(None, 1 << 20, 1, 8, 1, fake, None) == S.SDFDDGI_EINVAL
+    assert lib.sdfddgi_measure_gather(fake, 1 << 20, 1, 8, 1, None, None) == S.SDFDDGI_EINVAL

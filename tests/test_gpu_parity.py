@@ -442,3 +442,17 @@ def test_precision_form_full_size_every_probe(S):
     announce(f"precision form error report: {report}")
     for name in ("irradiance", "depth_mean", "depth_second"):
         assert report[name]["rms_rel_to_map_max"] < 2e-3, report
+
+
+def test_gather_measurement_runs_and_stores_nothing(S):
+    import torch
+    buf = torch.rand(1 << 18, dtype=torch.float32, device="cuda:0")   # 1 MiB
+    lib = S.load_library()
+    sink = torch.zeros(1, dtype=torch.float32, device="cuda:0")
+    import ctypes
+    assert lib.sdfddgi_measure_gather(ctypes.c_void_p(buf.data_ptr()), 1 << 20, 4096, 16, 3,
+                                      ctypes.c_void_p(sink.data_ptr()), None) == S.SDFDDGI_OK
+    torch.cuda.synchronize()
+    assert float(sink.item()) == 0.0
+    with pytest.raises(S.SdfddgiError):
+        S.sdfddgi_measure_gather(buf[:1000], 64, 8)   # not 32 x a power of two bytes
