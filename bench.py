@@ -109,7 +109,12 @@ def ray_statistics(S, w, frames):
         hit = ((kind == 2) | (kind == 3)).double()
         prim = rec[:, 1].double()
         shadow = rec[:, 3].double()
-        primary = (SAMPLE_BYTES * prim + HITREC_BYTES + PAYLOAD_BYTES * (1.0 - hit)).sum()
+        # a ray's first sample is its probe's, read once per probe: every ray whose first
+        # sample only stepped on starts from it (those that stopped there did not)
+        stopped0 = (rec[:, 1] == 0) | ((rec[:, 1] == 1) & ((kind == 2) | (kind == 4)))
+        per_ray = prim - (~stopped0).double()
+        primary = (SAMPLE_BYTES * per_ray + HITREC_BYTES + PAYLOAD_BYTES * (1.0 - hit)).sum()
+        primary += SAMPLE_BYTES * (rec.shape[0] // w.params.rays_per_probe)
         hits = (HITREC_BYTES + hit * (SAMPLE_BYTES * shadow + HIT_BYTES + PAYLOAD_BYTES)).sum()
         tot["primary_bytes"] += float(primary)
         tot["hits_bytes"] += float(hits)

@@ -88,6 +88,9 @@ struct TraceArgs {
                                 //     length (all zeroed by tables_kernel)
     int *parts;                 // [kXcds * kPartStride] primary chunks claimed per XCD, one
                                 //     counter per 128-B line (zeroed likewise)
+    const int2 *probe_first;    // [P] each probe's first sample, which every one of its rays
+                                //     takes at the probe position: (bits of the distance,
+                                //     level or -1 outside every level); null: sample it
     int analytic;               // 1: distances from the primitives in `an`, not the grid
     AnalyticArgs an;
     const float *prim_alb;      // [nprims][3] albedo of each primitive, cluster order
@@ -244,6 +247,7 @@ struct AdamArgs {
 };
 
 hipError_t launch_probe_sdf(const TraceArgs &a, float *out, hipStream_t stream);
+hipError_t launch_probe_first(const TraceArgs &a, int2 *out, hipStream_t stream);
 
 // Alg. 1 (UpdateProbePos) for every probe: new positions from the grid positions,
 // history rejected where a probe moved more than threshold2 since the last call.

@@ -220,6 +220,18 @@ __global__ __launch_bounds__(256) void primary_kernel(TraceArgs a) {
                     t = 0.0f;
                     k = 0;
                     bound = INFINITY;
+                    if (kSdf != kSdfAnalytic && a.probe_first && a.max_steps > 1) {
+                        // the first sample sits at the probe (fma(0, w, o) = o) for every
+                        // ray of it: where that sample only steps on (a level holds the
+                        // probe, distance >= eps), take the step from the probe's
+                        // precomputed sample; otherwise the first trace_step samples
+                        const int2 f = a.probe_first[p];
+                        const float d0 = __int_as_float(f.x);
+                        if (f.y >= 0 && !(d0 < a.eps)) {
+                            t = fmaf(a.relax, d0, 0.0f);
+                            k = 1;
+                        }
+                    }
                     active = true;
                 }
                 idle = __ballot(!active);
@@ -655,6 +667,20 @@ __global__ __launch_bounds__(256) void probe_sdf_kernel(TraceArgs a, float *out)
     out[p] = L < 0 ? 1e30f : sample_at<kHalf>(s_lv[L], x0, x1, x2);
 }
 
+// Each probe's first sample: the level its position selects and the distance there,
+// by the same sequence as a ray's sample at t = 0.
+template <bool kHalf>
+__global__ __launch_bounds__(256) void probe_first_kernel(TraceArgs a, int2 *out) {
+    __shared__ LevelLds s_lv[kMaxLevels];
+    load_levels(a, s_lv);
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.P) return;
+    const float x0 = a.probe_pos[3 * p], x1 = a.probe_pos[3 * p + 1], x2 = a.probe_pos[3 * p + 2];
+    const int L = select_level(a, x0, x1, x2);
+    const float d = L < 0 ? 0.0f : sample_at<kHalf>(s_lv[L], x0, x1, x2);
+    out[p] = make_int2(__float_as_int(d), L);
+}
+
 __global__ __launch_bounds__(256) void sample_kernel(SampleArgs a) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= a.n) return;
@@ -812,6 +838,16 @@ hipError_t launch_probe_sdf(const TraceArgs &a, float *out, hipStream_t s) {
         hipLaunchKernelGGL(probe_sdf_kernel<true>, dim3(blocks_for(a.P, 256)), dim3(256), 0, s, a, out);
     else
         hipLaunchKernelGGL(probe_sdf_kernel<false>, dim3(blocks_for(a.P, 256)), dim3(256), 0, s, a, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_first(const TraceArgs &a, int2 *out, hipStream_t s) {
+    if (a.half_sdf)
+        hipLaunchKernelGGL(probe_first_kernel<true>, dim3(blocks_for(a.P, 256)), dim3(256), 0, s, a,
+                           out);
+    else
+        hipLaunchKernelGGL(probe_first_kernel<false>, dim3(blocks_for(a.P, 256)), dim3(256), 0, s,
+                           a, out);
     return hipGetLastError();
 }
 

@@ -147,6 +147,7 @@ struct sdfddgi_ctx {
     int64_t irr_floats = 0, depth_floats = 0;
     float *probe_pos = nullptr;
     float *grid_pos = nullptr;   // the grid positions (probe_pos differs after relocation)
+    int2 *probe_first = nullptr; // grid scenes: each probe's first sample (see TraceArgs)
     int *probe_order = nullptr;
     double *texel_i = nullptr, *texel_d = nullptr;
     // main: the ray set of the last plain frame; spare: the one the next plain frame
@@ -300,7 +301,7 @@ void free_all(sdfddgi_ctx *c) {
     if (c->ev_sel) (void)hipEventDestroy(c->ev_sel);
     if (c->ev_fb) (void)hipEventDestroy(c->ev_fb);
     if (c->side2) (void)hipStreamDestroy(c->side2);
-    dev_free(c->probe_pos); dev_free(c->grid_pos); dev_free(c->probe_order); dev_free(c->texel_i); dev_free(c->texel_d);
+    dev_free(c->probe_pos); dev_free(c->grid_pos); dev_free(c->probe_first); dev_free(c->probe_order); dev_free(c->texel_i); dev_free(c->texel_d);
     dev_free(c->irr[0]); dev_free(c->irr[1]); dev_free(c->depth[0]); dev_free(c->depth[1]);
     dev_free(c->reject); dev_free(c->counter); dev_free(c->records);
     dev_free(c->u_irr); dev_free(c->u_depth);
@@ -691,6 +692,7 @@ TraceArgs trace_base(const sdfddgi_ctx *c, const float l[3], const float rad[3])
     t.alb2 = c->prm.albedo[2];
     t.probe_pos = c->probe_pos;
     t.probe_order = c->probe_order;
+    t.probe_first = c->probe_first;
     t.prev_irr = c->irr[c->cur];
     if (c->analytic) {
         t.analytic = 1;
@@ -1006,6 +1008,13 @@ static sdfddgi_status create_ctx(const sdfddgi_sdf_grid *sdf, const HostClusters
         SDF_TRY(launch_probe_sdf(trace_base(c, l, rad), c->probe_sdf, c->stream),
                 "launching probe_sdf_kernel");
     }
+    if (!c->analytic) {
+        // every ray of a probe takes its first sample at the probe
+        const float l[3] = {0.0f, 1.0f, 0.0f}, rad[3] = {0.0f, 0.0f, 0.0f};
+        SDF_TRY(dev_alloc(&c->probe_first, P), "allocating probe samples");
+        SDF_TRY(launch_probe_first(trace_base(c, l, rad), c->probe_first, c->stream),
+                "launching probe_first_kernel");
+    }
     if (params->flags & SDFDDGI_FLAG_TIMING) {
         c->ev_ring = new (std::nothrow) hipEvent_t[kEvents * kTimingRing]();
         if (!c->ev_ring) return bail(fail(nullptr, SDFDDGI_ENOMEM, "host allocation failed"));
@@ -1284,6 +1293,8 @@ sdfddgi_status sdfddgi_relocate_probes(sdfddgi_ctx *c, float threshold1, float t
     TRY_HIP(c, launch_relocate(t, r, c->stream), "launching relocate_kernel");
     if (c->probe_sdf)   // the learned form's feature follows the probe
         TRY_HIP(c, launch_probe_sdf(t, c->probe_sdf, c->stream), "launching probe_sdf_kernel");
+    // and so does the rays' first sample
+    TRY_HIP(c, launch_probe_first(t, c->probe_first, c->stream), "launching probe_first_kernel");
     return SDFDDGI_OK;
 }
 
