@@ -217,16 +217,16 @@ __device__ __forceinline__ void relu_into(floatx4 d, int mt, bf16x8_t h[2]) {
 // m-tile at a time straight into the next layer's operands (no pre-activations are
 // kept), so that the kernel fits four waves per SIMD. The same products and
 // roundings as mlp_forward. out[q]: lanes g == 0 hold o[0..3] of texel n of tile q.
+template <int kT = kDenoiseTiles>
 __device__ __forceinline__ void mlp_forward_lds(const uint4 *s_w, const float *s_bias, int g,
-                                                int lane, const bf16x8_t xb[kDenoiseTiles],
-                                                floatx4 out[kDenoiseTiles]) {
+                                                int lane, const bf16x8_t xb[kT], floatx4 out[kT]) {
     const floatx4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
-    bf16x8_t h[kDenoiseTiles][2], hn[kDenoiseTiles][2];
+    bf16x8_t h[kT][2], hn[kT][2];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
         const bf16x8_t w = as_bf16x8(s_w[mt * 64 + lane]);
 #pragma unroll
-        for (int q = 0; q < kDenoiseTiles; ++q) relu_into(mfma(w, xb[q], zero), mt, h[q]);
+        for (int q = 0; q < kT; ++q) relu_into(mfma(w, xb[q], zero), mt, h[q]);
     }
 #pragma unroll
     for (int layer = 0; layer < 2; ++layer) {
@@ -237,11 +237,11 @@ __device__ __forceinline__ void mlp_forward_lds(const uint4 *s_w, const float *s
             const bf16x8_t w1 = as_bf16x8(s_w[(e0 + 2 * mt + 1) * 64 + lane]);
             const floatx4 b = bias4(s_bias, b0 + 16 * mt + 4 * g);
 #pragma unroll
-            for (int q = 0; q < kDenoiseTiles; ++q)
+            for (int q = 0; q < kT; ++q)
                 relu_into(mfma(w1, h[q][1], mfma(w0, h[q][0], b)), mt, hn[q]);
         }
 #pragma unroll
-        for (int q = 0; q < kDenoiseTiles; ++q) {
+        for (int q = 0; q < kT; ++q) {
             h[q][0] = hn[q][0];
             h[q][1] = hn[q][1];
         }
@@ -249,7 +249,7 @@ __device__ __forceinline__ void mlp_forward_lds(const uint4 *s_w, const float *s
     const bf16x8_t w0 = as_bf16x8(s_w[20 * 64 + lane]), w1 = as_bf16x8(s_w[21 * 64 + lane]);
     const floatx4 b = bias4(s_bias, 2 * kHidden + 4 * g);
 #pragma unroll
-    for (int q = 0; q < kDenoiseTiles; ++q) out[q] = mfma(w1, h[q][1], mfma(w0, h[q][0], b));
+    for (int q = 0; q < kT; ++q) out[q] = mfma(w1, h[q][1], mfma(w0, h[q][0], b));
 }
 
 // One wave per probe (persistent waves stride over probes). Per group of 16-texel
@@ -357,6 +357,155 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void d
                                        fmaf(h, o[k].z - u[k].z, u[k].z),
                                        fmaf(h, o[k].w - u[k].w, u[k].w));
             }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// denoise_kernel for kRi x kRi irradiance and kRd x kRd depth maps small enough to
+// stage a probe's tiles in LDS (8 x 8 and 16 x 16), with one memory round trip per
+// probe instead of three: every load of the probe (its previous and low-ray depth
+// tiles as float4s, the texels' features) is issued at once; the new depth tile is
+// written as soon as they arrive, the previous one is kept in LDS for the depth
+// features, and the new irradiance tile is assembled in LDS and written whole,
+// borders included, with consecutive lanes on consecutive floats. The same values,
+// rounded in the same order, as denoise_kernel.
+template <int kRi, int kRd>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void denoise_tile_kernel(DenoiseArgs a) {
+    constexpr int kTi = kRi * kRi, kSi = kRi + 2, kSd = kRd + 2, kK = kRd / kRi;
+    constexpr int kTileI = kSi * kSi * 3, kD4 = kSd * kSd * 2 / 4, kD4Lane = (kD4 + 63) / 64;
+    static_assert(kTi == 16 * kDenoiseTiles, "one group of 16-texel tiles per probe");
+    static_assert(kRd % kRi == 0 && (kSd * kSd * 2) % 4 == 0, "depth tile of whole float4s");
+    __shared__ uint4 s_w[kFwdEntries * 64];
+    __shared__ float s_bias[kBiasFloats];
+    __shared__ float4 s_dep[kWaves][kD4];
+    __shared__ float s_irr[kWaves][kTi * 3];
+    for (int e = threadIdx.x; e < kFwdEntries * 64; e += blockDim.x) s_w[e] = a.mlp.fwd[e];
+    for (int e = threadIdx.x; e < kBiasFloats; e += blockDim.x) s_bias[e] = a.mlp.bias[e];
+    __syncthreads();
+    const int lane = (int)__lane_id(), n0 = lane & 15, g = lane >> 4;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const float *sdep = reinterpret_cast<const float *>(s_dep[wave]);
+    float *sirr = s_irr[wave];
+    const float h = a.hysteresis, inv_s = a.f.inv_s, inv_d = a.f.inv_d;
+    for (int p = blockIdx.x * kWaves + wave; p < a.P; p += gridDim.x * kWaves) {
+        asm volatile("" ::: "memory");   // the packs stay in LDS (see denoise_kernel)
+        // fresh copies each probe: addresses derived from the lane are recomputed
+        // rather than hoisted out of the loop into registers the network needs
+        int n = n0, ln = lane;
+        asm volatile("" : "+v"(n), "+v"(ln));
+        const int plain = __builtin_amdgcn_readfirstlane((int)a.fb_next[p]);
+        const size_t di = (size_t)p * kD4, ii = (size_t)p * kTileI;
+        const float4 *old_d = reinterpret_cast<const float4 *>(a.f.prev_depth) + di;
+        const float4 *low_d = reinterpret_cast<const float4 *>(a.u_depth) + di;
+        float4 od[kD4Lane], ud[kD4Lane];
+#pragma unroll
+        for (int k = 0; k < kD4Lane; ++k) {
+            const int e = 64 * k + ln;
+            if (e < kD4) {
+                od[k] = old_d[e];
+                if (!plain) ud[k] = low_d[e];
+            }
+        }
+        // g == 0: low-ray and previous irradiance of the texel; g == 1: its direction
+        float fv[kDenoiseTiles][6];
+#pragma unroll
+        for (int q = 0; q < kDenoiseTiles; ++q) {
+            const int t = q * 16 + n;
+            if (g == 0) {
+                const size_t at = ii + ((size_t)(t / kRi + 1) * kSi + (t % kRi + 1)) * 3;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    fv[q][c] = a.f.u_irr[at + c];
+                    fv[q][3 + c] = a.f.prev_irr[at + c];
+                }
+            } else if (g == 1) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) fv[q][c] = a.f.texel_dir[3 * t + c];
+            }
+        }
+        const float sdf = g == 1 ? a.f.probe_sdf[p] : 0.0f;
+        float4 *new_d = reinterpret_cast<float4 *>(a.new_depth) + di;
+#pragma unroll
+        for (int k = 0; k < kD4Lane; ++k) {
+            const int e = 64 * k + ln;
+            if (e < kD4) {
+                if (!plain)
+                    new_d[e] = make_float4(fmaf(h, od[k].x - ud[k].x, ud[k].x),
+                                           fmaf(h, od[k].y - ud[k].y, ud[k].y),
+                                           fmaf(h, od[k].z - ud[k].z, ud[k].z),
+                                           fmaf(h, od[k].w - ud[k].w, ud[k].w));
+                s_dep[wave][e] = od[k];
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        // features (feature_group's slots and order), the previous irradiance to LDS
+        bf16x8_t xb[kDenoiseTiles];
+#pragma unroll
+        for (int q = 0; q < kDenoiseTiles; ++q) {
+            const int t = q * 16 + n, i = t % kRi, j = t / kRi;
+            float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (g == 0) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    v[c] = fv[q][c] * inv_s;
+                    v[3 + c] = fv[q][3 + c] * inv_s;
+                    sirr[3 * t + c] = fv[q][3 + c];
+                }
+                float m1 = 0.0f, m2 = 0.0f;
+#pragma unroll
+                for (int b = 0; b < kK; ++b)
+#pragma unroll
+                    for (int c = 0; c < kK; ++c) {
+                        const float *d = sdep + ((kK * j + b + 1) * kSd + (kK * i + c + 1)) * 2;
+                        m1 += d[0];
+                        m2 += d[1];
+                    }
+                const float inv_kk = 1.0f / (float)(kK * kK);
+                v[6] = m1 * inv_kk * inv_d;
+                v[7] = sqrtf(fmaxf(m2 * inv_kk, 0.0f)) * inv_d;
+            } else if (g == 1) {
+                v[0] = fv[q][0];
+                v[1] = fv[q][1];
+                v[2] = fv[q][2];
+                v[3] = fminf(fmaxf(sdf * inv_d, -4.0f), 4.0f);
+                v[4] = 1.0f;
+            }
+            xb[q] = to_bf16x8(v);
+        }
+        // two tiles at a time: the activations of four do not fit beside the rest
+        floatx4 o[kDenoiseTiles];
+        mlp_forward_lds<2>(s_w, s_bias, g, lane, xb, o);
+        __builtin_amdgcn_sched_barrier(0);
+        mlp_forward_lds<2>(s_w, s_bias, g, lane, xb + 2, o + 2);
+        // U_hat, the hysteresis mix in place of the previous value, the error sum
+        float esum = 0.0f;
+#pragma unroll
+        for (int q = 0; q < kDenoiseTiles; ++q) {
+            const int t = q * 16 + n;
+            if (g == 0) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float prev = sirr[3 * t + c];
+                    const float u = fmaxf(0.0f, fmaf(a.s, o[q][c], prev));
+                    sirr[3 * t + c] = fmaf(h, prev - u, u);
+                }
+                esum += expf(o[q][3]);
+            }
+        }
+        const float mean = wave_sum(esum) / (float)kTi;
+        if (lane == 0) {
+            if (a.mean_error) a.mean_error[p] = mean;
+            a.fb_next[p] = mean > a.tau ? 1 : 0;
+        }
+        if (plain) continue;
+        __builtin_amdgcn_wave_barrier();
+        float *new_i = a.new_irr + ii;
+        for (int e = ln; e < kTileI; e += 64) {
+            const int pos = e / 3, c = e - 3 * pos;
+            int i, j;
+            padded_source(kRi, pos % kSi, pos / kSi, i, j);
+            new_i[e] = sirr[3 * (j * kRi + i) + c];
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -674,7 +823,11 @@ hipError_t launch_denoise(const DenoiseArgs &a, hipStream_t s) {
     // packs into its LDS once)
     const int blocks =
         (int)std::min<int64_t>(grid_for(a.P, kWaves), kDenoiseBlocksPerCu * device_cus());
-    hipLaunchKernelGGL(denoise_kernel, dim3(blocks), dim3(256), 0, s, a);
+    if (a.f.irr_res == 8 && a.f.depth_res == 16)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(denoise_tile_kernel<8, 16>), dim3(blocks), dim3(256), 0,
+                           s, a);
+    else
+        hipLaunchKernelGGL(denoise_kernel, dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -172,8 +172,9 @@ def test_adam_steps_match_checker(S):
 S_IRR, D_DEPTH = 2.0, 1.5
 
 
-def learned_workload():
+def learned_workload(irr_res=8, depth_res=16):
     w = scenegen.small_cascade(0, rays=64, frames=4)
+    w.params.irr_res, w.params.depth_res = irr_res, depth_res
     return w
 
 
@@ -235,13 +236,16 @@ def run_learned(S, w, theta, tau, frames, flags=0, warm_frames=2):
     return (irr, dep), out
 
 
-def test_learned_frame_matches_checker(S):
+@pytest.mark.parametrize("res", [(8, 16), (6, 12)])
+def test_learned_frame_matches_checker(S, res):
     """Frame 2 from the checker's maps after frames 0-1: no prediction yet, so every
     probe takes the plain update, and every probe's prediction is made. Frame 3 from
     the checker's maps after frames 0-2: each probe's decision is frame 2's
-    prediction against tau. Predictions, decisions and maps against the checker."""
-    announce("learned frame small_cascade")
-    w = learned_workload()
+    prediction against tau. Predictions, decisions and maps against the checker.
+    8 x 8 / 16 x 16 maps take the kernel that stages whole tiles in LDS; 6 x 6 /
+    12 x 12 (36 texels: two full 16-texel tiles and a ragged one) the general one."""
+    announce(f"learned frame small_cascade, maps {res}")
+    w = learned_workload(*res)
     th = random_theta(7, scale=0.5)
     th[oracle.OFF_B4 + 3] = -3.0          # predicted errors around exp(-3)
     ck = oracle.Checker(w)
