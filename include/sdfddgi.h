@@ -154,9 +154,9 @@ typedef struct {
     /* Learned form (sdfddgi_update_frame_learned); 0 rays: not available. */
     int32_t learned_rays;      /* low ray count: 0, or a multiple of 16 in 16..R   */
     float fallback_error;      /* tau: mean predicted relative error above which a
-                                  probe takes the plain update in the next learned
-                                  frame, >= 0 (+inf: only probes without history or
-                                  without a prediction do)                         */
+                                  probe takes the plain update in the learned frame
+                                  after next, >= 0 (+inf: only probes without
+                                  history or without a prediction do)              */
 } sdfddgi_params;
 
 /* Directional light: direction toward the light (any non-zero length; it is
@@ -257,8 +257,11 @@ sdfddgi_status sdfddgi_ray_directions(uint64_t rotation_seed, int32_t rays, floa
  * 256), measured with events recorded on the context's stream around each
  * kernel: [0] ray-direction/weight tables, [1] primary sphere trace, [2] hit
  * shading (normal, shadow ray, lookups), [3] blend, [4] whole frame,
- * [5] denoiser, [6] fallback trace (primary + hits), [7] fallback blend. In a
- * learned frame [1]-[3] are the low-ray pass; [5]-[7] are 0 in a plain frame.
+ * [5] denoiser, [6] fallback trace (tables, list, primary, shadow rays),
+ * [7] fallback lookups and blend. In a learned frame [1]-[3] are the low-ray
+ * pass, whose hit shading is split: the atlas-independent half (normal, shadow
+ * ray, albedo) runs beside the previous frame and the lookups after it, and [2]
+ * spans both; [5]-[7] are 0 in a plain frame.
  * Host pointer ms[count], count <= 8. Waits for the last timed frame.
  * ESTATE without SDFDDGI_FLAG_TIMING or when no frame ran since the last call. */
 sdfddgi_status sdfddgi_get_kernel_times(sdfddgi_ctx *ctx, float *ms, int32_t count);
@@ -308,9 +311,10 @@ sdfddgi_status sdfddgi_destroy(sdfddgi_ctx *ctx);
  * relative error exp(o[3]). Which probes take the plain update with
  * rays_per_probe rays instead is decided before the frame's trace: those whose
  * history is rejected, and those whose mean predicted error over their texels
- * in the previous learned frame exceeded fallback_error (every probe before the
- * context's first learned frame; the predictions persist across set_maps). The
- * network still runs for them, to predict for the next frame. Every other probe
+ * in the learned frame before the previous one exceeded fallback_error (every
+ * probe in the context's first two learned frames; the predictions persist
+ * across set_maps and plain frames). The network still runs for them, to
+ * predict for the learned frame after next. Every other probe
  * mixes U_hat into its irradiance (hysteresis, then borders) and the low-ray
  * depth moments into its depth map. Requires learned_rays > 0, depth_res an
  * even multiple of irr_res and irr_res <= 16.
@@ -347,8 +351,8 @@ sdfddgi_status sdfddgi_update_frame_learned(sdfddgi_ctx *ctx, const sdfddgi_deno
 /* The last learned frame's fallback: *count (host) = number of probes that took
  * the plain update; probes (device [P], may be NULL) receives their indices in
  * no particular order, mean_error (device [P], may be NULL) every probe's mean
- * predicted relative error in that frame (which decides the next learned
- * frame). Waits for the stream. ESTATE before a learned frame. */
+ * predicted relative error in that frame (which decides the learned frame after
+ * next). Waits for the stream. ESTATE before a learned frame. */
 sdfddgi_status sdfddgi_get_fallback(sdfddgi_ctx *ctx, int32_t *count, int32_t *probes,
                                     float *mean_error);
 

@@ -372,12 +372,13 @@ class Checker:
         U_hat = max(0, E_prev + S o) into its irradiance and the low-ray depth
         moments into its depth map with the hysteresis. Per-probe decision, taken
         before the frame: a probe takes the plain update when the history is reset,
-        when there is no previous prediction (``prev_mean_error`` None), or when its
-        mean of exp(o_3) over its texels in the previous learned frame
-        (``prev_mean_error``) exceeds tau. ``fallback`` (a boolean per probe)
+        when there is no prediction to decide from (``prev_mean_error`` None), or
+        when its mean of exp(o_3) over its texels in the learned frame the decision
+        is taken from (``prev_mean_error``: the library takes the learned frame
+        before the previous one) exceeds tau. ``fallback`` (a boolean per probe)
         overrides the decision, for checking another implementation's choice where
         the two precisions may legitimately differ. ``mean_error`` of the result is
-        this frame's prediction, which decides the next frame.
+        this frame's prediction, which decides a later frame.
         Returns dict(irr, depth, fallback, decided, mean_error, o, features, u_irr, u_depth).
         """
         P, T = self.num_probes, self.irr_res ** 2

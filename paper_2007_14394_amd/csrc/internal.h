@@ -94,6 +94,11 @@ struct TraceArgs {
     int analytic;               // 1: distances from the primitives in `an`, not the grid
     AnalyticArgs an;
     const float *prim_alb;      // [nprims][3] albedo of each primitive, cluster order
+    float4 *geo;                // null: hits_kernel shades each hit. Else hit shading is split:
+                                //     hits_kernel stores, per hit-queue entry i, what does not
+                                //     depend on the previous atlas -- geo[2i] = (normal, sun
+                                //     term n.l or 0 in shadow), geo[2i+1] = (albedo, 0) -- and
+                                //     shade_kernel adds the multi-bounce lookup later
 };
 
 struct TraceGrid {
@@ -153,6 +158,8 @@ hipError_t launch_tables(const TableArgs &a, hipStream_t stream);
 TraceGrid trace_grid(int device, int64_t rays, bool half, bool analytic = false);
 hipError_t launch_primary(const TraceArgs &a, const TraceGrid &grid, hipStream_t stream);
 hipError_t launch_hits(const TraceArgs &a, const TraceGrid &grid, hipStream_t stream);
+// The atlas-dependent half of split hit shading (TraceArgs::geo): one thread per queue entry.
+hipError_t launch_shade(const TraceArgs &a, hipStream_t stream);
 hipError_t launch_blend(const BlendArgs &a, hipStream_t stream);
 hipError_t launch_sample(const SampleArgs &a, hipStream_t stream);
 hipError_t launch_pack_quads(const float *grid, int n0, int n1, int n2, bool half, void *quad,
@@ -206,9 +213,9 @@ struct DenoiseArgs {
     const float *u_depth;         // low-ray depth moments atlas (no hysteresis)
     float *new_irr, *new_depth;
     MlpPack mlp;
-    uint8_t *fb_next;             // [P] in: the probe takes the plain update this frame
-                                  //     (written nothing here); out: it will next frame
-                                  //     (mean predicted error above tau)
+    uint8_t *fb_flag;             // [P] in: the probe takes the plain update this frame
+                                  //     (written nothing here); out: it will in the learned
+                                  //     frame after next (mean predicted error above tau)
     float *mean_error;            // [P] mean predicted relative error (may be null)
 };
 
@@ -267,10 +274,11 @@ hipError_t launch_denoise(const DenoiseArgs &a, hipStream_t stream);
 // 32-byte records of a buffer of `records` (a power of two) records.
 hipError_t launch_gather(const void *buf, int64_t records, int64_t threads, int reads,
                          uint32_t seed, float *sink, hipStream_t stream);
-// The fallback list of a learned frame: every probe whose history is rejected or
-// whose flag asks for the plain update; the flag is set for both (the denoiser reads
-// it while the fallback blend clears the reject flags). count zeroed before.
-hipError_t launch_select_fallback(const uint8_t *reject, uint8_t *fb_next, int P, int *list,
+// The fallback list of a learned frame: every probe whose flag asks for the plain
+// update or, when reject is given, whose history is rejected; the flag is set for
+// both (the denoiser reads it, not the reject flags the fallback blend clears).
+// count zeroed before.
+hipError_t launch_select_fallback(const uint8_t *reject, uint8_t *fb_flag, int P, int *list,
                                   int *count, hipStream_t stream);
 hipError_t launch_examples(const ExampleArgs &a, hipStream_t stream);
 hipError_t launch_infer(const InferArgs &a, hipStream_t stream);

@@ -141,16 +141,34 @@ __device__ __forceinline__ float3 albedo_at(const TraceArgs &a, const LevelLds &
 
 // ------------------------------------------------------------- kernels ------
 
+__device__ __forceinline__ void write_record(const TraceArgs &a, int ray, float t, int kind,
+                                             int level, int steps, int vis, int shadow_steps,
+                                             float n0, float n1, float n2) {
+    if (a.records) {
+        int4 *rec = reinterpret_cast<int4 *>(a.records) + 2 * (int64_t)ray;
+        rec[0] = make_int4(kind | (level << 8), steps, vis, shadow_steps);
+        rec[1] = make_int4(__float_as_int(t), __float_as_int(n0), __float_as_int(n1),
+                           __float_as_int(n2));
+    }
+}
+
 __device__ __forceinline__ void write_ray(const TraceArgs &a, int ray, float4 out, int kind,
                                           int level, int steps, int vis, int shadow_steps,
                                           float n0, float n1, float n2) {
     a.payload[ray] = out;
-    if (a.records) {
-        int4 *rec = reinterpret_cast<int4 *>(a.records) + 2 * (int64_t)ray;
-        rec[0] = make_int4(kind | (level << 8), steps, vis, shadow_steps);
-        rec[1] = make_int4(__float_as_int(out.w), __float_as_int(n0), __float_as_int(n1),
-                           __float_as_int(n2));
-    }
+    write_record(a, ray, out.w, kind, level, steps, vis, shadow_steps, n0, n1, n2);
+}
+
+// Payload of a hit: (albedo / pi) (sun radiance x n.l-or-0 + gain x multi-bounce), t.
+__device__ __forceinline__ float4 shade_hit(const TraceArgs &a, float3 alb, float lit, float3 ind,
+                                            float t) {
+    const float inv_pi = 0.318309886183790671538f;
+    float4 out;
+    out.x = alb.x * inv_pi * (a.rad0 * lit + a.gain * ind.x);
+    out.y = alb.y * inv_pi * (a.rad1 * lit + a.gain * ind.y);
+    out.z = alb.z * inv_pi * (a.rad2 * lit + a.gain * ind.z);
+    out.w = t;
+    return out;
 }
 
 // Per-wave staging of hit-queue entries (ray, bits of t, packed info, 0) in LDS;
@@ -298,7 +316,7 @@ __global__ __launch_bounds__(256) void hits_kernel(TraceArgs a) {
     const int total = a.counter[2];  // queue length, final once primary_kernel has finished
     Feeder<kHitChunk> feed;
 
-    int mode = kIdle, ray = 0, info = 0, k = 0, vis = -1, slot = 0;
+    int mode = kIdle, ray = 0, info = 0, k = 0, vis = -1, slot = 0, qi = 0;
     float ht = 0, hx0 = 0, hx1 = 0, hx2 = 0, n0 = 0, n1 = 0, n2 = 0;
     float o0 = 0, o1 = 0, o2 = 0, t = 0, bound = INFINITY;
     while (true) {
@@ -317,18 +335,19 @@ __global__ __launch_bounds__(256) void hits_kernel(TraceArgs a) {
                                               a.prim_alb[3 * slot + 2]);
                         else
                             alb = albedo_at(a, s_sdf.lv[(info >> 4) & 15], hx0, hx1, hx2);
-                        float3 ind = make_float3(0.0f, 0.0f, 0.0f);
-                        if (a.gain != 0.0f)
-                            ind = interp_irradiance(a.prev_irr, a.irr_res, a.pg, hx0, hx1, hx2, n0,
-                                                    n1, n2);
-                        const float inv_pi = 0.318309886183790671538f;
-                        float4 out;
-                        out.x = alb.x * inv_pi * (a.rad0 * lit + a.gain * ind.x);
-                        out.y = alb.y * inv_pi * (a.rad1 * lit + a.gain * ind.y);
-                        out.z = alb.z * inv_pi * (a.rad2 * lit + a.gain * ind.z);
-                        out.w = ht;
-                        write_ray(a, ray, out, info & 15, (info >> 4) & 15, info >> 8, vis, k, n0,
-                                  n1, n2);
+                        if (a.geo) {
+                            a.geo[2 * qi] = make_float4(n0, n1, n2, lit);
+                            a.geo[2 * qi + 1] = make_float4(alb.x, alb.y, alb.z, 0.0f);
+                            write_record(a, ray, ht, info & 15, (info >> 4) & 15, info >> 8, vis,
+                                         k, n0, n1, n2);
+                        } else {
+                            float3 ind = make_float3(0.0f, 0.0f, 0.0f);
+                            if (a.gain != 0.0f)
+                                ind = interp_irradiance(a.prev_irr, a.irr_res, a.pg, hx0, hx1,
+                                                        hx2, n0, n1, n2);
+                            write_ray(a, ray, shade_hit(a, alb, lit, ind, ht), info & 15,
+                                      (info >> 4) & 15, info >> 8, vis, k, n0, n1, n2);
+                        }
                         mode = kIdle;
                     }
                 }
@@ -340,7 +359,8 @@ __global__ __launch_bounds__(256) void hits_kernel(TraceArgs a) {
                     const int n = feed.claim(a.counter + 1, total, __popcll(idle), first);
                     const int rank = __popcll(idle & below);
                     if (mode == kIdle && rank < n) {
-                        const int4 e = a.hitq[first + rank];
+                        qi = first + rank;
+                        const int4 e = a.hitq[qi];
                         ray = e.x;
                         ht = __int_as_float(e.y);
                         info = e.z;
@@ -394,6 +414,29 @@ __global__ __launch_bounds__(256) void hits_kernel(TraceArgs a) {
                 mode = kPendShade;
             }
         }
+    }
+}
+
+// Second half of split hit shading: per hit-queue entry, the hit point again (the
+// same operations as hits_kernel), the multi-bounce lookup into the previous atlas
+// and the payload. Grid-stride over the queue, whose length the primary trace left
+// in counter[2].
+__global__ __launch_bounds__(256) void shade_kernel(TraceArgs a) {
+    const int total = a.counter[2];
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < total; q += gridDim.x * blockDim.x) {
+        const int4 e = a.hitq[q];
+        const float4 g0 = a.geo[2 * q], g1 = a.geo[2 * q + 1];
+        const int ray = e.x;
+        const float ht = __int_as_float(e.y);
+        float3 ind = make_float3(0.0f, 0.0f, 0.0f);
+        if (a.gain != 0.0f) {
+            const int p = ray / a.R, i = ray - (ray / a.R) * a.R;
+            const float hx0 = fmaf(ht, a.dirs[3 * i], a.probe_pos[3 * p]);
+            const float hx1 = fmaf(ht, a.dirs[3 * i + 1], a.probe_pos[3 * p + 1]);
+            const float hx2 = fmaf(ht, a.dirs[3 * i + 2], a.probe_pos[3 * p + 2]);
+            ind = interp_irradiance(a.prev_irr, a.irr_res, a.pg, hx0, hx1, hx2, g0.x, g0.y, g0.z);
+        }
+        a.payload[ray] = shade_hit(a, make_float3(g1.x, g1.y, g1.z), g0.w, ind, ht);
     }
 }
 
@@ -806,6 +849,15 @@ hipError_t launch_hits(const TraceArgs &a, const TraceGrid &g, hipStream_t s) {
         hipLaunchKernelGGL(hits_kernel<kSdfGrid16>, dim3(g.hits_blocks), dim3(256), 0, s, a);
     else
         hipLaunchKernelGGL(hits_kernel<kSdfGrid32>, dim3(g.hits_blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_shade(const TraceArgs &a, hipStream_t s) {
+    if ((int64_t)a.P * a.R == 0) return hipSuccess;
+    const int64_t threads = (int64_t)a.P * a.R;
+    // four workgroups per CU of the 256-CU part, striding over the queue
+    const int blocks = (int)std::min<int64_t>((threads + 255) / 256, 1024);
+    hipLaunchKernelGGL(shade_kernel, dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -257,8 +257,9 @@ __device__ __forceinline__ void mlp_forward_lds(const uint4 *s_w, const float *s
 // and exp(o[3]) summed. A probe whose flag says it takes the plain update this frame
 // (its fallback pass writes its maps) only records its prediction; every other probe
 // mixes U_hat into its irradiance in place of the plain update (hysteresis, interior
-// and borders), and the low-ray depth moments into its depth map. The flag becomes
-// the next frame's decision: mean predicted error above tau.
+// and borders), and the low-ray depth moments into its depth map. The flag is then
+// replaced by the probe's decision for the learned frame after next: mean predicted
+// error above tau.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void denoise_kernel(DenoiseArgs a) {
     __shared__ uint4 s_w[kFwdEntries * 64];
     __shared__ float s_bias[kBiasFloats];
@@ -302,11 +303,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void d
             }
         }
         const float mean = wave_sum(esum) / (float)Ti;
-        const int plain = __builtin_amdgcn_readfirstlane((int)a.fb_next[p]);
+        const int plain = __builtin_amdgcn_readfirstlane((int)a.fb_flag[p]);
         __builtin_amdgcn_wave_barrier();
         if (lane == 0) {
             if (a.mean_error) a.mean_error[p] = mean;
-            a.fb_next[p] = mean > a.tau ? 1 : 0;
+            a.fb_flag[p] = mean > a.tau ? 1 : 0;
         }
         if (plain) continue;
         __builtin_amdgcn_wave_barrier();
@@ -394,7 +395,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void d
         // rather than hoisted out of the loop into registers the network needs
         int n = n0, ln = lane;
         asm volatile("" : "+v"(n), "+v"(ln));
-        const int plain = __builtin_amdgcn_readfirstlane((int)a.fb_next[p]);
+        const int plain = __builtin_amdgcn_readfirstlane((int)a.fb_flag[p]);
         const size_t di = (size_t)p * kD4, ii = (size_t)p * kTileI;
         const float4 *old_d = reinterpret_cast<const float4 *>(a.f.prev_depth) + di;
         const float4 *low_d = reinterpret_cast<const float4 *>(a.u_depth) + di;
@@ -496,7 +497,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void d
         const float mean = wave_sum(esum) / (float)kTi;
         if (lane == 0) {
             if (a.mean_error) a.mean_error[p] = mean;
-            a.fb_next[p] = mean > a.tau ? 1 : 0;
+            a.fb_flag[p] = mean > a.tau ? 1 : 0;
         }
         if (plain) continue;
         __builtin_amdgcn_wave_barrier();
@@ -511,15 +512,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void d
     }
 }
 
-// One thread per probe.
+// One thread per probe: the frame's fallback list, from the flags and (when given)
+// the reject flags, which are folded into the flags.
 __global__ __launch_bounds__(256) void select_fallback_kernel(const uint8_t *__restrict__ reject,
-                                                              uint8_t *__restrict__ fb_next,
+                                                              uint8_t *__restrict__ fb_flag,
                                                               int P, int *__restrict__ list,
                                                               int *__restrict__ count) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
-    if (reject[p] || fb_next[p]) {
-        fb_next[p] = 1;
+    if ((reject && reject[p]) || fb_flag[p]) {
+        fb_flag[p] = 1;
         list[atomicAdd(count, 1)] = p;
     }
 }
@@ -831,10 +833,10 @@ hipError_t launch_denoise(const DenoiseArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_select_fallback(const uint8_t *reject, uint8_t *fb_next, int P, int *list,
+hipError_t launch_select_fallback(const uint8_t *reject, uint8_t *fb_flag, int P, int *list,
                                   int *count, hipStream_t s) {
     hipLaunchKernelGGL(select_fallback_kernel, dim3(grid_for(P, 256)), dim3(256), 0, s, reject,
-                       fb_next, P, list, count);
+                       fb_flag, P, list, count);
     return hipGetLastError();
 }
 

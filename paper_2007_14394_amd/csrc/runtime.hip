@@ -27,7 +27,7 @@ thread_local std::string g_create_error;
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kTimingRing = 256;
-constexpr int kEvents = 11;
+constexpr int kEvents = 12;
 
 // ---------------------------------------------------------- frame constants --
 
@@ -115,10 +115,17 @@ struct RaySet {
     __bf16 *w16_d = nullptr;
     float4 *payload = nullptr;       // [P][R]
     int4 *hitq = nullptr;            // [P][R]
-    int *counter = nullptr;          // [3] counters of a plain frame's trace (see TraceArgs)
+    int *counter = nullptr;          // [kSetCounters] counters of the set's trace (see TraceArgs);
+                                     //     [6] the length of `list`
+    float4 *geo = nullptr;           // learned form: [P][R][2] split hit shading (TraceArgs::geo)
+    int *list = nullptr;             // learned form's fallback sets: [P] the frame's fallback list
     TraceGrid grid;
     hipEvent_t done = nullptr;       // main / spare: recorded on the caller's stream once the
-                                     //     last plain frame that traced into this set is blended
+                                     //     last plain frame that traced into this set is blended;
+                                     //     learned sets: once the last frame that used it is done
+                                     //     with it (see the context)
+    hipEvent_t ready = nullptr;      // learned sets: the set's pass is done (see the context)
+    hipEvent_t sel = nullptr;        // fallback sets: the frame's list is built
 };
 
 // Counters of one learned frame: [0..2] the trace pass over all probes (unused,
@@ -153,10 +160,15 @@ struct sdfddgi_ctx {
     // main: the ray set of the last plain frame; spare: the one the next plain frame
     // traces into while the last one's hit shading and blend may still run
     RaySet main, spare;
-    // the learned form's low ray set, two of them: consecutive learned frames alternate,
-    // so a frame's low-ray trace need not wait for the previous frame's low-ray blend
-    RaySet low[2];
-    int low_next = 0;
+    // The learned form's ray sets, used in turn by consecutive learned frames so that
+    // a frame's traces need not wait for the frame before it: for learned frame n of
+    // parity k = n % 2, low[k] holds learned_rays rays over every probe and fbs[k]
+    // rays_per_probe rays over the frame's fallback list. fb_flag[k]: per probe,
+    // the plain update in the frames of parity k; each frame's denoiser replaces it by
+    // its decision for the learned frame after next.
+    RaySet low[2], fbs[2];
+    uint8_t *fb_flag[2]{};
+    int last_learned = 0;        // parity of the last learned frame
     // Plain frames are pipelined: the tables and primary trace of frame f run on the
     // side stream and may overlap frame f-1's hit shading and blend on the caller's
     // stream (the primary trace reads neither the atlas nor anything frame f-1
@@ -169,15 +181,26 @@ struct sdfddgi_ctx {
     hipStream_t side = nullptr;
     hipEvent_t ev_gate = nullptr, ev_primary = nullptr, ev_tail = nullptr;
     bool serialize_next = true;
-    // Learned frames overlap the same way among themselves (their low-ray pass's
-    // tables and primary trace beside the previous learned frame's denoiser and
-    // fallback pass); a switch between plain and learned frames waits for
-    // everything before it. Within a learned frame the fallback probes' plain update
-    // runs on side2 beside the low-ray chain: it starts after ev_sel (the fallback
-    // list is built and the previous atlas complete) and ev_fb joins it back.
+    // Learned frames overlap among themselves; a switch between plain and learned
+    // frames waits for everything before it. Learned frame n (parity k = n % 2, low
+    // set lo = low[k]) has two side chains, dealt in turn to the three side streams
+    // (side, side2, side3), so that the chains of consecutive frames overlap:
+    //   low chain, after lo.done (learned frame n - 2 is done with that set): the low
+    //     set's tables, primary trace and the atlas-independent half of its hit
+    //     shading, then lo.ready;
+    //   fallback chain, after fbs[k].done (learned frame n - 2 is done: its denoiser
+    //     has written the flags of parity k, its fallback blend has read the set's
+    //     list and payload): the fallback set's tables, the list (fbs[k].sel), its primary
+    //     trace and atlas-independent half; after ev_end (the previous frame is done,
+    //     its atlas complete) the lookup half and the blend with hysteresis into the
+    //     fallback probes' tiles of the new atlas, then fbs[k].ready.
+    // The caller's stream, after the previous frame: the low-ray lookup half and Eq. 3
+    // without hysteresis (lo.done), the denoiser after fbs[k].sel, then it joins
+    // fbs[k].ready (fbs[k].done) and records ev_end.
     bool learned_chain = false;
-    hipStream_t side2 = nullptr;
-    hipEvent_t ev_sel = nullptr, ev_fb = nullptr;
+    hipStream_t side2 = nullptr, side3 = nullptr;
+    hipEvent_t ev_end = nullptr;
+    int64_t learned_index = 0;   // learned frames so far: deals the side chains
     float *irr[2]{}, *depth[2]{};
     int cur = 0;
     uint8_t *reject = nullptr;
@@ -188,10 +211,7 @@ struct sdfddgi_ctx {
     float *u_irr = nullptr, *u_depth = nullptr;      // low-ray estimates (no hysteresis)
     float *probe_sdf = nullptr;                      // [P]
     float *texel_dir = nullptr;                      // [Ti][3] binary32
-    int *fallback = nullptr;                         // [P] this frame's fallback list
     float *mean_error = nullptr;                     // [P]
-    uint8_t *fb_next = nullptr;                      // [P] plain update in the next learned
-                                                     //     frame (set until a prediction)
     // analytic scene (sdfddgi_create_analytic): the primitives in cluster order
     bool analytic = false;
     int an_nprims = 0, an_nclusters = 0;
@@ -277,7 +297,7 @@ void dev_free(T *&p) {
 void free_set(RaySet &r) {
     dev_free(r.base); dev_free(r.dirs); dev_free(r.wt_i); dev_free(r.wt_d);
     dev_free(r.norm_i); dev_free(r.norm_d); dev_free(r.w16_i); dev_free(r.w16_d);
-    dev_free(r.payload); dev_free(r.hitq); dev_free(r.counter);
+    dev_free(r.payload); dev_free(r.hitq); dev_free(r.counter); dev_free(r.geo); dev_free(r.list);
     r.R = r.Rpad = 0;
 }
 
@@ -288,25 +308,27 @@ void free_all(sdfddgi_ctx *c) {
     }
     free_set(c->main);
     free_set(c->spare);
-    free_set(c->low[0]);
-    free_set(c->low[1]);
-    for (RaySet *r : {&c->low[0], &c->low[1]})
+    for (RaySet *r : {&c->low[0], &c->low[1], &c->fbs[0], &c->fbs[1]}) {
+        free_set(*r);
         if (r->done) (void)hipEventDestroy(r->done);
+        if (r->ready) (void)hipEventDestroy(r->ready);
+        if (r->sel) (void)hipEventDestroy(r->sel);
+    }
     if (c->main.done) (void)hipEventDestroy(c->main.done);
     if (c->spare.done) (void)hipEventDestroy(c->spare.done);
     if (c->ev_gate) (void)hipEventDestroy(c->ev_gate);
     if (c->ev_primary) (void)hipEventDestroy(c->ev_primary);
     if (c->ev_tail) (void)hipEventDestroy(c->ev_tail);
     if (c->side) (void)hipStreamDestroy(c->side);
-    if (c->ev_sel) (void)hipEventDestroy(c->ev_sel);
-    if (c->ev_fb) (void)hipEventDestroy(c->ev_fb);
     if (c->side2) (void)hipStreamDestroy(c->side2);
+    if (c->side3) (void)hipStreamDestroy(c->side3);
+    if (c->ev_end) (void)hipEventDestroy(c->ev_end);
     dev_free(c->probe_pos); dev_free(c->grid_pos); dev_free(c->probe_first); dev_free(c->probe_order); dev_free(c->texel_i); dev_free(c->texel_d);
     dev_free(c->irr[0]); dev_free(c->irr[1]); dev_free(c->depth[0]); dev_free(c->depth[1]);
     dev_free(c->reject); dev_free(c->counter); dev_free(c->records);
     dev_free(c->u_irr); dev_free(c->u_depth);
-    dev_free(c->probe_sdf); dev_free(c->texel_dir); dev_free(c->fallback); dev_free(c->mean_error);
-    dev_free(c->fb_next);
+    dev_free(c->probe_sdf); dev_free(c->texel_dir); dev_free(c->mean_error);
+    dev_free(c->fb_flag[0]); dev_free(c->fb_flag[1]);
     dev_free(c->an_kind); dev_free(c->an_orig); dev_free(c->an_first); dev_free(c->an_center);
     dev_free(c->an_half); dev_free(c->an_lo); dev_free(c->an_hi); dev_free(c->an_alb);
     if (c->ev_ring) {
@@ -580,7 +602,7 @@ ProbeGridDev dev_probes(const sdfddgi_ctx *c) {
 
 // Allocate a ray set of R rays: the fixed spherical-Fibonacci set (binary64,
 // uploaded), zeroed weight tables and the per-ray buffers.
-hipError_t alloc_set(sdfddgi_ctx *c, RaySet &r, int R) {
+hipError_t alloc_set(sdfddgi_ctx *c, RaySet &r, int R, bool split = false) {
     free_set(r);
     r.R = R;
     std::vector<double> h_base(3 * (size_t)R);
@@ -596,6 +618,10 @@ hipError_t alloc_set(sdfddgi_ctx *c, RaySet &r, int R) {
     chk(dev_alloc(&r.payload, (size_t)c->P * R));
     chk(dev_alloc(&r.hitq, (size_t)c->P * R));
     chk(dev_alloc(&r.counter, kSetCounters));
+    if (split) {
+        chk(dev_alloc(&r.geo, 2 * (size_t)c->P * R));
+        chk(dev_alloc(&r.list, (size_t)c->P));
+    }
     if (e != hipSuccess) return e;
     chk(hipMemcpy(r.base, h_base.data(), 3 * (size_t)R * sizeof(double), hipMemcpyHostToDevice));
     chk(hipMemsetAsync(r.wt_i, 0, (size_t)R * c->Tpi * sizeof(float), c->stream));
@@ -760,7 +786,10 @@ sdfddgi_status light_of(sdfddgi_ctx *c, const sdfddgi_light *light, float l[3], 
 
 // Timing events of one frame, each recorded when its step is done: [0] start,
 // [1] tables, [2] primary trace, [3] hit shading may start, [4] hit shading,
-// [5] blend, [6] denoiser, [7] fallback trace, [8] fallback blend.
+// [5] blend, [6] denoiser, [7] fallback pass starts, [8] fallback trace (tables,
+// list, primary, atlas-independent hit shading), [9] fallback blend, [10] frame,
+// [11] fallback lookup half may start. A learned frame's hit shading runs from
+// [3] on the side stream to [4] on the caller's.
 struct FrameEvents {
     hipEvent_t *ev = nullptr;
     hipStream_t s = nullptr;
@@ -967,8 +996,9 @@ static sdfddgi_status create_ctx(const sdfddgi_sdf_grid *sdf, const HostClusters
     SDF_TRY(hipEventCreateWithFlags(&c->ev_primary, hipEventDisableTiming), "creating events");
     SDF_TRY(hipEventCreateWithFlags(&c->ev_tail, hipEventDisableTiming), "creating events");
     SDF_TRY(hipStreamCreateWithFlags(&c->side2, hipStreamNonBlocking), "creating a stream");
-    SDF_TRY(hipEventCreateWithFlags(&c->ev_sel, hipEventDisableTiming), "creating events");
-    SDF_TRY(hipEventCreateWithFlags(&c->ev_fb, hipEventDisableTiming), "creating events");
+    SDF_TRY(hipStreamCreateWithFlags(&c->side3, hipStreamNonBlocking), "creating a stream");
+    SDF_TRY(hipEventCreateWithFlags(&c->ev_end, hipEventDisableTiming), "creating events");
+    SDF_TRY(hipEventRecord(c->ev_end, c->stream), "event");
     for (RaySet *r : {&c->main, &c->spare}) {
         SDF_TRY(hipEventCreateWithFlags(&r->done, hipEventDisableTiming), "creating events");
         SDF_TRY(hipEventRecord(r->done, c->stream), "event");
@@ -989,18 +1019,27 @@ static sdfddgi_status create_ctx(const sdfddgi_sdf_grid *sdf, const HostClusters
     if (params->flags & SDFDDGI_FLAG_RECORD_RAYS)
         SDF_TRY(dev_alloc(&c->records, (size_t)P * c->main.R * 8), "allocating ray records");
     if (params->learned_rays > 0) {
-        for (RaySet *r : {&c->low[0], &c->low[1]}) {
-            SDF_TRY(alloc_set(c, *r, params->learned_rays), "allocating the learned ray sets");
+        for (int k = 0; k < 2; ++k) {
+            SDF_TRY(alloc_set(c, c->low[k], params->learned_rays, true),
+                    "allocating the learned ray sets");
+            SDF_TRY(alloc_set(c, c->fbs[k], params->rays_per_probe, true),
+                    "allocating the learned ray sets");
+        }
+        for (RaySet *r : {&c->low[0], &c->low[1], &c->fbs[0], &c->fbs[1]}) {
             SDF_TRY(hipEventCreateWithFlags(&r->done, hipEventDisableTiming), "creating events");
+            SDF_TRY(hipEventCreateWithFlags(&r->ready, hipEventDisableTiming), "creating events");
+            SDF_TRY(hipEventCreateWithFlags(&r->sel, hipEventDisableTiming), "creating events");
+            SDF_TRY(hipEventRecord(r->done, c->stream), "event");
+        }
+        for (int k = 0; k < 2; ++k) {
+            SDF_TRY(dev_alloc(&c->fb_flag[k], P), "allocating learned buffers");
+            SDF_TRY(launch_fill_u8(c->fb_flag[k], 1, P, c->stream), "launching fill");
         }
         SDF_TRY(dev_alloc(&c->u_irr, c->irr_floats), "allocating learned buffers");
         SDF_TRY(dev_alloc(&c->u_depth, c->depth_floats), "allocating learned buffers");
         SDF_TRY(dev_alloc(&c->probe_sdf, P), "allocating learned buffers");
         SDF_TRY(dev_alloc(&c->texel_dir, 3 * c->Ti), "allocating learned buffers");
-        SDF_TRY(dev_alloc(&c->fallback, P), "allocating learned buffers");
         SDF_TRY(dev_alloc(&c->mean_error, P), "allocating learned buffers");
-        SDF_TRY(dev_alloc(&c->fb_next, P), "allocating learned buffers");
-        SDF_TRY(launch_fill_u8(c->fb_next, 1, P, c->stream), "launching fill");
         SDF_TRY(hipMemcpy(c->texel_dir, h_tif.data(), 3 * c->Ti * sizeof(float),
                           hipMemcpyHostToDevice),
                 "uploading texel directions");
@@ -1114,7 +1153,8 @@ sdfddgi_status sdfddgi_update_frame(sdfddgi_ctx *c, const sdfddgi_light *light,
                                        nullptr, nullptr),
                             c->stream),
             "launching blend_kernel");
-    for (int k = 5; k < kEvents; ++k) TRY_HIP(c, ev.mark(k), "event");
+    // the learned form's marks, in an order that makes each of its spans zero
+    for (int k : {5, 7, 8, 11, 9, 6, 10}) TRY_HIP(c, ev.mark(k), "event");
     TRY_HIP(c, hipEventRecord(r.done, c->stream), "event");
     frame_done(c);
     std::swap(c->main, c->spare);
@@ -1249,11 +1289,13 @@ sdfddgi_status sdfddgi_get_kernel_times(sdfddgi_ctx *c, float *ms, int32_t count
     if (c->timed_frames == 0) return fail(c, SDFDDGI_ESTATE, "no timed frame since the last call");
     const int frames = (int)(c->timed_frames < kTimingRing ? c->timed_frames : kTimingRing);
     const int last = (c->ring_head + kTimingRing - 1) % kTimingRing;
-    TRY_HIP(c, hipEventSynchronize(c->ev_ring[kEvents * last + kEvents - 1]),
+    // mark 10 ends a frame: every other mark of the frame is complete by then
+    TRY_HIP(c, hipEventSynchronize(c->ev_ring[kEvents * last + 10]),
             "hipEventSynchronize");
     // tables, primary, hits, blend, frame, denoiser, fallback trace, fallback blend
+    // (the marks of FrameEvents; in a plain frame marks 5.. coincide)
     constexpr int kTimes = 8;
-    const int pairs[kTimes][2] = {{0, 1}, {1, 2}, {3, 4}, {4, 5}, {0, 10}, {5, 6}, {7, 8}, {8, 9}};
+    const int pairs[kTimes][2] = {{0, 1}, {1, 2}, {3, 4}, {4, 5}, {0, 10}, {9, 6}, {7, 8}, {11, 9}};
     double sum[kTimes] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int f = 0; f < frames; ++f) {
         const hipEvent_t *ev = c->ev_ring + kEvents * ((last - f + kTimingRing) % kTimingRing);
@@ -1328,6 +1370,7 @@ sdfddgi_status sdfddgi_destroy(sdfddgi_ctx *c) {
     (void)hipStreamSynchronize(c->stream);
     if (c->side) (void)hipStreamSynchronize(c->side);
     if (c->side2) (void)hipStreamSynchronize(c->side2);
+    if (c->side3) (void)hipStreamSynchronize(c->side3);
     free_all(c);
     delete c;
     return SDFDDGI_OK;
@@ -1430,65 +1473,71 @@ sdfddgi_status sdfddgi_update_frame_learned(sdfddgi_ctx *c, const sdfddgi_denois
     float l[3], rad[3];
     if ((st = light_of(c, light, l, rad)) != SDFDDGI_OK) return st;
     const TraceArgs base = trace_base(c, l, rad);
-    const int nxt = 1 - c->cur;
-    int *fb_count = c->counter + 6;
+    const int nxt = 1 - c->cur, k = (int)(c->learned_index % 2);
     FrameEvents ev = frame_events(c);
-    // low-ray pass over every probe, Eq. 3 without hysteresis; its tables and primary
-    // trace on the side stream, after the low-ray blend of the learned frame before the
-    // previous one (the last use of this low set) or, when serial, after everything so far
-    RaySet &lo = c->low[c->low_next];
-    const TraceArgs tl = trace_pass(base, lo, lo.counter, lo.counter + kPartStride, nullptr,
-                                    nullptr, nullptr);
+    RaySet &lo = c->low[k], &fb = c->fbs[k];
+    hipStream_t sides[3] = {c->side, c->side2, c->side3};
+    hipStream_t sl = sides[(2 * c->learned_index) % 3], sf = sides[(2 * c->learned_index + 1) % 3];
     if (serial) {
+        // after everything so far, and then the reject flags join the flags
         TRY_HIP(c, hipEventRecord(c->ev_tail, c->stream), "event");
-        TRY_HIP(c, hipStreamWaitEvent(c->side, c->ev_tail, 0), "stream wait");
+        TRY_HIP(c, hipStreamWaitEvent(sl, c->ev_tail, 0), "stream wait");
+        TRY_HIP(c, hipStreamWaitEvent(sf, c->ev_tail, 0), "stream wait");
     } else {
-        TRY_HIP(c, hipStreamWaitEvent(c->side, lo.done, 0), "stream wait");
+        // back to back, no reject flag is set: the fallback blend of every frame clears
+        // those of its probes, and a frame with a rejected history is serial
+        TRY_HIP(c, hipStreamWaitEvent(sl, lo.done, 0), "stream wait");
+        TRY_HIP(c, hipStreamWaitEvent(sf, fb.done, 0), "stream wait");
     }
-    TRY_HIP(c, ev.mark_on(0, c->side), "event");
-    TRY_HIP(c, launch_tables(table_args(c, lo, rotation_seed, kSetCounters, lo.counter), c->side),
+    // low chain: the low-ray pass over every probe up to the atlas-independent half of
+    // its hit shading
+    TraceArgs tl = trace_pass(base, lo, lo.counter, lo.counter + kPartStride, nullptr, nullptr,
+                              nullptr);
+    tl.geo = lo.geo;
+    TRY_HIP(c, ev.mark_on(0, sl), "event");
+    TRY_HIP(c, launch_tables(table_args(c, lo, rotation_seed, kSetCounters, lo.counter), sl),
             "launching tables_kernel");
-    TRY_HIP(c, ev.mark_on(1, c->side), "event");
-    TRY_HIP(c, launch_primary(tl, lo.grid, c->side), "launching primary_kernel");
-    TRY_HIP(c, ev.mark_on(2, c->side), "event");
-    TRY_HIP(c, hipEventRecord(c->ev_primary, c->side), "event");
-    // caller's stream: this frame's fallback list -- probes with a rejected history or
-    // whose mean predicted error in the previous learned frame exceeded tau (every
-    // probe before the first prediction) -- after the main set's tables for the
-    // fallback pass, which zero the frame's counters
-    TRY_HIP(c, launch_tables(table_args(c, c->main, rotation_seed, kCounters), c->stream),
-            "launching tables_kernel");
-    TRY_HIP(c, launch_select_fallback(c->reject, c->fb_next, (int)c->P, c->fallback, fb_count,
-                                      c->stream),
-            "launching select_fallback_kernel");
-    TRY_HIP(c, hipEventRecord(c->ev_sel, c->stream), "event");
-    // second side stream: the plain update of the fallback probes (trace, hit shading
-    // reading the previous atlas, blend with hysteresis into their tiles of the new
-    // atlas), beside the low-ray chain
-    TRY_HIP(c, hipStreamWaitEvent(c->side2, c->ev_sel, 0), "stream wait");
-    TRY_HIP(c, ev.mark_on(7, c->side2), "event");
-    int *fb_parts = c->counter + kPartStride + kXcds * kPartStride;
-    const TraceArgs tf =
-        trace_pass(base, c->main, c->counter + 3, fb_parts, c->fallback, fb_count, nullptr);
-    // the grids of a trace that shares the GPU with other streams' kernels
-    TraceGrid gf = c->main.grid;
+    TRY_HIP(c, ev.mark_on(1, sl), "event");
+    TRY_HIP(c, launch_primary(tl, lo.grid, sl), "launching primary_kernel");
+    TRY_HIP(c, ev.mark_on(2, sl), "event");
+    TRY_HIP(c, ev.mark_on(3, sl), "event");
+    TRY_HIP(c, launch_hits(tl, lo.grid, sl), "launching hits_kernel");
+    TRY_HIP(c, hipEventRecord(lo.ready, sl), "event");
+    // fallback chain: the list -- probes whose flag of this parity asks for the plain
+    // update (the decision of the learned frame before the previous one; set in every
+    // probe until then) or, when serial, whose history is rejected -- then the
+    // fallback probes' pass, on the grids of a trace that shares the GPU
+    int *fb_count = fb.counter + 6;
+    TraceArgs tf = trace_pass(base, fb, fb.counter, fb.counter + kPartStride, fb.list, fb_count,
+                              nullptr);
+    tf.geo = fb.geo;
+    TraceGrid gf = fb.grid;
     gf.primary_blocks = gf.primary_blocks_overlapped;
     gf.hits_blocks = gf.hits_blocks_overlapped;
-    TRY_HIP(c, launch_primary(tf, gf, c->side2), "launching primary_kernel");
-    TRY_HIP(c, launch_hits(tf, gf, c->side2), "launching hits_kernel");
-    TRY_HIP(c, ev.mark_on(8, c->side2), "event");
-    TRY_HIP(c, launch_blend(blend_args(c, c->main, c->main.payload, c->prm.hysteresis,
-                                       c->irr[c->cur], c->depth[c->cur], c->irr[nxt],
-                                       c->depth[nxt], c->reject, c->fallback, fb_count),
-                            c->side2),
+    TRY_HIP(c, ev.mark_on(7, sf), "event");
+    TRY_HIP(c, launch_tables(table_args(c, fb, rotation_seed, kSetCounters, fb.counter), sf),
+            "launching tables_kernel");
+    TRY_HIP(c, launch_select_fallback(serial ? c->reject : nullptr, c->fb_flag[k], (int)c->P,
+                                      fb.list, fb_count, sf),
+            "launching select_fallback_kernel");
+    TRY_HIP(c, hipEventRecord(fb.sel, sf), "event");
+    TRY_HIP(c, launch_primary(tf, gf, sf), "launching primary_kernel");
+    TRY_HIP(c, launch_hits(tf, gf, sf), "launching hits_kernel");
+    TRY_HIP(c, ev.mark_on(8, sf), "event");
+    TRY_HIP(c, hipStreamWaitEvent(sf, c->ev_end, 0), "stream wait");
+    TRY_HIP(c, ev.mark_on(11, sf), "event");
+    TRY_HIP(c, launch_shade(tf, sf), "launching shade_kernel");
+    TRY_HIP(c, launch_blend(blend_args(c, fb, fb.payload, c->prm.hysteresis, c->irr[c->cur],
+                                       c->depth[c->cur], c->irr[nxt], c->depth[nxt], c->reject,
+                                       fb.list, fb_count),
+                            sf),
             "launching blend_kernel");
-    TRY_HIP(c, ev.mark_on(9, c->side2), "event");
-    TRY_HIP(c, hipEventRecord(c->ev_fb, c->side2), "event");
-    // caller's stream: low-ray hit shading and Eq. 3 without hysteresis, then the
-    // network over every probe (maps of the others; every probe's prediction)
-    TRY_HIP(c, hipStreamWaitEvent(c->stream, c->ev_primary, 0), "stream wait");
-    TRY_HIP(c, ev.mark(3), "event");
-    TRY_HIP(c, launch_hits(tl, lo.grid, c->stream), "launching hits_kernel");
+    TRY_HIP(c, ev.mark_on(9, sf), "event");
+    TRY_HIP(c, hipEventRecord(fb.ready, sf), "event");
+    // caller's stream (the previous atlas is complete here): low-ray lookup half and
+    // Eq. 3 without hysteresis
+    TRY_HIP(c, hipStreamWaitEvent(c->stream, lo.ready, 0), "stream wait");
+    TRY_HIP(c, launch_shade(tl, c->stream), "launching shade_kernel");
     TRY_HIP(c, ev.mark(4), "event");
     TRY_HIP(c, launch_blend(blend_args(c, lo, lo.payload, 0.0f, c->irr[c->cur],
                                        c->depth[c->cur], c->u_irr, c->u_depth, nullptr, nullptr,
@@ -1497,6 +1546,9 @@ sdfddgi_status sdfddgi_update_frame_learned(sdfddgi_ctx *c, const sdfddgi_denois
             "launching blend_kernel");
     TRY_HIP(c, hipEventRecord(lo.done, c->stream), "event");
     TRY_HIP(c, ev.mark(5), "event");
+    // the network over every probe once the flags of this parity name the frame's
+    // fallback probes: maps of the others, every probe's prediction, and the flags
+    // replaced by the decisions
     DenoiseArgs da{};
     da.f = feature_args(c, d);
     da.P = (int)c->P;
@@ -1507,14 +1559,20 @@ sdfddgi_status sdfddgi_update_frame_learned(sdfddgi_ctx *c, const sdfddgi_denois
     da.new_irr = c->irr[nxt];
     da.new_depth = c->depth[nxt];
     da.mlp = MlpPack{d->fwd, d->bwd, d->bias};
-    da.fb_next = c->fb_next;
+    da.fb_flag = c->fb_flag[k];
     da.mean_error = c->mean_error;
+    TRY_HIP(c, hipStreamWaitEvent(c->stream, fb.sel, 0), "stream wait");
     TRY_HIP(c, launch_denoise(da, c->stream), "launching denoise_kernel");
     TRY_HIP(c, ev.mark(6), "event");
-    TRY_HIP(c, hipStreamWaitEvent(c->stream, c->ev_fb, 0), "stream wait");
+    // the fallback set is free again (its lookup half and blend read its list, counters
+    // and payload) and the flags of this parity hold the decisions
+    TRY_HIP(c, hipStreamWaitEvent(c->stream, fb.ready, 0), "stream wait");
+    TRY_HIP(c, hipEventRecord(fb.done, c->stream), "event");
     TRY_HIP(c, ev.mark(10), "event");
+    TRY_HIP(c, hipEventRecord(c->ev_end, c->stream), "event");
+    ++c->learned_index;
     frame_done(c);
-    c->low_next ^= 1;
+    c->last_learned = k;
     c->cur = nxt;
     c->have_learned = true;
     c->learned_chain = true;
@@ -1528,11 +1586,12 @@ sdfddgi_status sdfddgi_get_fallback(sdfddgi_ctx *c, int32_t *count, int32_t *pro
     if (st != SDFDDGI_OK) return st;
     if (!count) return fail(c, SDFDDGI_EINVAL, "count is NULL");
     if (!c->have_learned) return fail(c, SDFDDGI_ESTATE, "no learned frame yet");
-    TRY_HIP(c, hipMemcpyAsync(count, c->counter + 6, sizeof(int32_t), hipMemcpyDeviceToHost,
+    const RaySet &fb = c->fbs[c->last_learned];
+    TRY_HIP(c, hipMemcpyAsync(count, fb.counter + 6, sizeof(int32_t), hipMemcpyDeviceToHost,
                               c->stream),
             "copying the fallback count");
     if (probes)
-        TRY_HIP(c, hipMemcpyAsync(probes, c->fallback, c->P * sizeof(int32_t),
+        TRY_HIP(c, hipMemcpyAsync(probes, fb.list, c->P * sizeof(int32_t),
                                   hipMemcpyDeviceToDevice, c->stream),
                 "copying the fallback list");
     if (mean_error)

@@ -173,7 +173,7 @@ S_IRR, D_DEPTH = 2.0, 1.5
 
 
 def learned_workload(irr_res=8, depth_res=16):
-    w = scenegen.small_cascade(0, rays=64, frames=4)
+    w = scenegen.small_cascade(0, rays=64, frames=5)
     w.params.irr_res, w.params.depth_res = irr_res, depth_res
     return w
 
@@ -238,10 +238,11 @@ def run_learned(S, w, theta, tau, frames, flags=0, warm_frames=2):
 
 @pytest.mark.parametrize("res", [(8, 16), (6, 12)])
 def test_learned_frame_matches_checker(S, res):
-    """Frame 2 from the checker's maps after frames 0-1: no prediction yet, so every
-    probe takes the plain update, and every probe's prediction is made. Frame 3 from
-    the checker's maps after frames 0-2: each probe's decision is frame 2's
-    prediction against tau. Predictions, decisions and maps against the checker.
+    """Learned frames 2, 3 and 4, each from the checker's maps after the frames before
+    it. Frames 2 and 3 have no prediction to decide from, so every probe takes the
+    plain update, and every probe's prediction is made; in frame 4 each probe's
+    decision is its frame-2 prediction against tau (the learned frame before the
+    previous one). Predictions, decisions and maps against the checker.
     8 x 8 / 16 x 16 maps take the kernel that stages whole tiles in LDS; 6 x 6 /
     12 x 12 (36 texels: two full 16-texel tiles and a ragged one) the general one."""
     announce(f"learned frame small_cascade, maps {res}")
@@ -251,14 +252,14 @@ def test_learned_frame_matches_checker(S, res):
     ck = oracle.Checker(w)
     P = ck.num_probes
     states = [tuple(m.astype(np.float32).astype(np.float64) for m in st)
-              for st in ck.run_frames(w.frames[:3])]
+              for st in ck.run_frames(w.frames[:4])]
     pre = ck.learned_frame(w.frames[2], False, *states[1], th, S_IRR, D_DEPTH, math.inf, 32)
-    # tau at the median of the checker's frame-2 predictions: both decisions occur in frame 3
+    # tau at the median of the checker's frame-2 predictions: both decisions occur in frame 4
     tau = float(np.median(pre["mean_error"]))
     ctx = make_ctx(S, w, tau)
     den = S.sdfddgi_denoiser_create(np.asarray(th, dtype=np.float32), S_IRR, D_DEPTH)
     runs = []
-    for k, fr in ((1, w.frames[2]), (2, w.frames[3])):
+    for k, fr in ((1, w.frames[2]), (2, w.frames[3]), (3, w.frames[4])):
         S.sdfddgi_set_maps(ctx, to_dev(states[k][0]), to_dev(states[k][1]))
         S.sdfddgi_update_frame_learned(ctx, den, fr.dir_to_light, fr.radiance_rgb,
                                        fr.rotation_seed)
@@ -268,16 +269,16 @@ def test_learned_frame_matches_checker(S, res):
                          mean_error=to_host(errs), irr=to_host(ni).astype(np.float64),
                          depth=to_host(nd).astype(np.float64)))
     S.sdfddgi_destroy(ctx)
-    # frame 2: the plain update everywhere; predictions within the output bound
-    assert runs[0]["count"] == P
+    # frames 2 and 3: the plain update everywhere; predictions within the output bound
+    assert runs[0]["count"] == P and runs[1]["count"] == P
     M3 = magnitude(th, pre["features"].reshape(-1, F))[:, 3].reshape(P, -1)
     slack = np.exp(OUT_BOUND * M3.max(axis=1)) - 1.0
     rel = np.abs(runs[0]["mean_error"] / pre["mean_error"] - 1.0)
     assert np.all(rel <= slack + 1e-5), float((rel - slack).max())
     assert np.median(rel) <= 1e-4
-    # frame 3: decisions are frame 2's predictions against tau; they agree with the
+    # frame 4: decisions are frame 2's predictions against tau; they agree with the
     # checker's wherever its prediction is clearly on one side of tau
-    r = runs[1]
+    r = runs[2]
     gpu_fb = np.zeros(P, bool)
     gpu_fb[r["fallback"]] = True
     assert r["count"] == gpu_fb.sum() and len(np.unique(r["fallback"])) == r["count"]
@@ -285,8 +286,8 @@ def test_learned_frame_matches_checker(S, res):
     clear = np.abs(pre["mean_error"] / tau - 1.0) > 2 * slack + 1e-4
     assert np.array_equal(gpu_fb[clear], (pre["mean_error"] > tau)[clear])
     assert 0 < gpu_fb.sum() < P
-    fr = w.frames[3]
-    ref = ck.learned_frame(fr, False, *states[2], th, S_IRR, D_DEPTH, tau, 32, fallback=gpu_fb)
+    fr = w.frames[4]
+    ref = ck.learned_frame(fr, False, *states[3], th, S_IRR, D_DEPTH, tau, 32, fallback=gpu_fb)
     M3 = magnitude(th, ref["features"].reshape(-1, F))[:, 3].reshape(P, -1)
     slack = np.exp(OUT_BOUND * M3.max(axis=1)) - 1.0
     rel = np.abs(r["mean_error"] / ref["mean_error"] - 1.0)
@@ -325,23 +326,37 @@ def test_all_fallback_is_the_plain_frame_bit_for_bit(S):
     assert np.array_equal(res[0]["depth"].astype(np.float32), to_host(pd))
 
 
-@pytest.mark.parametrize("tau", [0.02, 0.0])
-def test_overlapped_learned_frames_match_frames_run_one_at_a_time(S, tau):
-    """Back-to-back learned frames overlap (the low-ray pass's tables and primary trace
-    beside the previous frame's denoiser and fallback pass); with a call in between
-    every learned frame waits for the one before. Both must give the same bits, for
-    a mix of accepted and fallback probes and for fallback everywhere."""
-    announce(f"overlapped learned frames, tau={tau}")
+@pytest.mark.parametrize("tau,probes,frames,flags", [
+    (0.02, 8192, 6, 0), (0.0, 8192, 6, 0),
+    ("trained", 16384, 12, 0), ("trained", 16384, 12, "fp16")])
+def test_overlapped_learned_frames_match_frames_run_one_at_a_time(S, tau, probes, frames, flags):
+    """Back-to-back learned frames overlap (each frame's low-ray and fallback traces
+    beside the frames before it, on three side streams); with a call in between every
+    learned frame waits for the one before. Both must give the same bits, for a mix
+    of accepted and fallback probes and for fallback everywhere, and at the open
+    scene's full size with the trained network (a few per cent of fallback probes,
+    whose lookups and blend run beside the next frames' traces)."""
+    announce(f"overlapped learned frames, tau={tau}, {probes} probes, {frames} frames, {flags}")
     import torch
-    w = scenegen.config2(0, probes=8192, frames=6)
-    den = S.sdfddgi_denoiser_create(random_theta(4).astype(np.float32), S_IRR, D_DEPTH)
-    a = make_ctx(S, w, tau)
-    b = make_ctx(S, w, tau)
+    w = scenegen.config2(0, probes=probes, frames=frames)
+    flags = S.SDFDDGI_FLAG_FP16 if flags == "fp16" else 0
+    if tau == "trained":
+        from paper_2007_14394_amd import denoiser_weights
+        wts = denoiser_weights.load()
+        tau = wts["tau"]
+        den = S.sdfddgi_denoiser_create(wts["params"], wts["irr_scale"], wts["depth_scale"])
+    else:
+        den = S.sdfddgi_denoiser_create(random_theta(4).astype(np.float32), S_IRR, D_DEPTH)
+    a = make_ctx(S, w, tau, flags=flags)
+    b = make_ctx(S, w, tau, flags=flags)
     for ctx in (a, b):
         fr = w.frames[0]
         S.sdfddgi_update_frame(ctx, fr.dir_to_light, fr.radiance_rgb, fr.rotation_seed)
+    # a: back to back, nothing in between (the contexts share the caller's stream, so
+    # b's synchronising calls must not come between a's frames)
     for fr in w.frames[1:]:
         S.sdfddgi_update_frame_learned(a, den, fr.dir_to_light, fr.radiance_rgb, fr.rotation_seed)
+    for fr in w.frames[1:]:
         S.sdfddgi_update_frame_learned(b, den, fr.dir_to_light, fr.radiance_rgb, fr.rotation_seed)
         S.sdfddgi_get_fallback(b, want_lists=False)  # a call in between: b never overlaps
     (ia, da), (ib, db) = S.sdfddgi_get_maps(a), S.sdfddgi_get_maps(b)
@@ -352,20 +367,43 @@ def test_overlapped_learned_frames_match_frames_run_one_at_a_time(S, tau):
 
 
 def test_reset_history_falls_back_everywhere(S):
+    """tau = inf: only probes without history or without a prediction take the plain
+    update. The first two learned frames have no prediction to decide from; a reset
+    history sends every probe to the plain update in the next frame only (the
+    update clears the reject flags), in a back-to-back chain and after it."""
     announce("learned frame after reset")
     w = learned_workload()
     ctx = make_ctx(S, w, math.inf)
     den = S.sdfddgi_denoiser_create(random_theta(5).astype(np.float32), S_IRR, D_DEPTH)
     warm(S, ctx, w)
-    S.sdfddgi_reset_history(ctx)
     fr = w.frames[2]
-    S.sdfddgi_update_frame_learned(ctx, den, fr.dir_to_light, fr.radiance_rgb, fr.rotation_seed)
-    cnt, _, _ = S.sdfddgi_get_fallback(ctx)
-    assert cnt == w.num_probes
-    # the flags are cleared by that update: the next learned frame accepts every probe
-    S.sdfddgi_update_frame_learned(ctx, den, fr.dir_to_light, fr.radiance_rgb, fr.rotation_seed)
-    cnt, _, _ = S.sdfddgi_get_fallback(ctx)
-    assert cnt == 0
+
+    def frame():
+        S.sdfddgi_update_frame_learned(ctx, den, fr.dir_to_light, fr.radiance_rgb,
+                                       fr.rotation_seed)
+
+    def count():
+        return S.sdfddgi_get_fallback(ctx)[0]
+
+    S.sdfddgi_reset_history(ctx)
+    counts = []
+    for _ in range(3):
+        frame()
+        counts.append(count())
+    assert counts == [w.num_probes, w.num_probes, 0]
+    # back to back (no call in between), then a reset, then back to back again
+    for _ in range(2):
+        frame()
+    assert count() == 0
+    S.sdfddgi_reset_history(ctx)
+    frame()
+    frame()
+    frame()
+    assert count() == 0
+    S.sdfddgi_reset_history(ctx)
+    frame()
+    assert count() == w.num_probes
+    S.sdfddgi_destroy(ctx)
 
 
 def test_precision_form_all_fallback_is_its_plain_frame(S):

@@ -368,11 +368,11 @@ def test_zero_network_keeps_irradiance_history():
     np.testing.assert_array_equal(out["mean_error"], 1.0)
 
 
-def test_fallback_follows_the_previous_prediction():
-    # The decision is taken before the frame, from the previous learned frame's mean
-    # predicted errors: above tau -> the plain update, else the network's. Without a
-    # previous prediction every probe takes the plain update. The result's mean_error
-    # is this frame's own prediction (exp(0) = 1 for the zero network).
+def test_fallback_follows_the_given_prediction():
+    # The decision is taken before the frame, from the mean predicted errors of an
+    # earlier learned frame: above tau -> the plain update, else the network's.
+    # Without a prediction every probe takes the plain update. The result's
+    # mean_error is this frame's own prediction (exp(0) = 1 for the zero network).
     w = learned_workload(rays=64)
     ck = oracle.Checker(w)
     P = ck.num_probes
