@@ -462,8 +462,9 @@ typedef struct {
                                      depth_res 16; flags and learned fields ignored    */
 } sdfddgi_batch_scene;
 
-/* Launch configuration of the batch's trace kernels, chosen by
- * sdfddgi_batch_autotune (or the defaults at create). */
+/* Launch configuration of the batch's trace and blend kernels, chosen by
+ * sdfddgi_batch_autotune (or the defaults at create: 256, the resident grid, 64,
+ * the resident grid, 40, 16, 64). */
 typedef struct {
     int32_t primary_chunk;        /* rays claimed per atomic: 64, 128, 256 or 512        */
     int32_t primary_blocks;       /* persistent workgroups of the primary trace          */
@@ -471,6 +472,9 @@ typedef struct {
     int32_t hits_blocks;          /* persistent workgroups of the hit shading            */
     int32_t refill;               /* refill idle lanes when fewer than this many of a
                                      wave's 64 lanes are stepping: 1..64                 */
+    int32_t blend_probes;         /* Eq. 3 blend tile: probes per workgroup, 16 or 8     */
+    int32_t blend_chunk;          /* rays staged in LDS at a time: 32, 64 or 128, and a
+                                     divisor of every scene's rays_per_probe             */
 } sdfddgi_batch_tuning;
 
 /* Validate and upload count (1..SDFDDGI_MAX_BATCH_SCENES) scenes, allocate their
@@ -490,10 +494,11 @@ sdfddgi_status sdfddgi_batch_create(const sdfddgi_batch_scene *scenes, int32_t c
 sdfddgi_status sdfddgi_batch_update_frame(sdfddgi_batch *b, const sdfddgi_light *lights,
                                           uint64_t rotation_seed);
 
-/* Try launch configurations of the trace kernels on real frames of the batch
- * (each candidate timed over frames_per_candidate frames with events), keep the
- * fastest primary and hit configurations -- chunks and refill from each kernel
- * alone, then the two grids from overlapped frames -- re-capture the graphs, and
+/* Try launch configurations of the trace and blend kernels on real frames of the
+ * batch (each candidate timed over frames_per_candidate frames with events), keep
+ * the fastest -- chunks and refill from each trace kernel alone, the blend tile
+ * from the blend alone (2 x 3 tiles, those whose chunk divides every scene's ray
+ * count), then the two trace grids from overlapped frames -- re-capture the graphs, and
  * restore the maps and history flags to what they were before (tuning changes no
  * result: every configuration computes the same bits). *chosen (may be NULL)
  * receives the result; *tried the number of candidates timed. */

@@ -323,10 +323,14 @@ __global__ __launch_bounds__(256) void batch_hits_kernel(BatchArgs a) {
     (void)info;
 }
 
-// One workgroup per 16 probes of one scene: that scene's blend arguments, the
-// shared precision-form blend body, then the scene's end stamp.
+// One workgroup per kP probes of one scene (16 / kP workgroups per entry of the
+// 16-probe block table): that scene's blend arguments, the shared precision-form
+// blend body with the tile (kP, kChunk), then the scene's end stamp.
+template <int kP, int kChunk>
 __global__ __launch_bounds__(256) void batch_blend_kernel(BatchBlendArgs b) {
-    const int2 blk = b.blocks[blockIdx.x];
+    constexpr int kSub = kBlendProbes / kP;
+    const int2 blk = b.blocks[blockIdx.x / kSub];
+    const int pb = blk.y + (int)(blockIdx.x % kSub) * kP;
     const BatchScene &s = b.scenes[blk.x];
     const size_t ti = (size_t)s.probe_base * 10 * 10 * 3, td = (size_t)s.probe_base * 18 * 18 * 2;
     BlendArgs a{};
@@ -346,7 +350,7 @@ __global__ __launch_bounds__(256) void batch_blend_kernel(BatchBlendArgs b) {
     a.new_irr = b.new_irr + ti;
     a.new_depth = b.new_depth + td;
     a.reject = b.reject + s.probe_base;
-    blend16_block<true>(a, blk.y);
+    blend16_block<true, kP, kChunk>(a, pb);
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
@@ -409,10 +413,30 @@ hipError_t launch_batch_hits(const BatchArgs &a, const BatchTuning &t, hipStream
     }
 }
 
-hipError_t launch_batch_blend(const BatchBlendArgs &a, int nblocks, hipStream_t s) {
-    if (nblocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(batch_blend_kernel, dim3(nblocks), dim3(256), 0, s, a);
+template <int kP, int kChunk>
+static hipError_t launch_blend_tile(const BatchBlendArgs &a, int nblocks16, hipStream_t s) {
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(batch_blend_kernel<kP, kChunk>),
+                       dim3(nblocks16 * (kBlendProbes / kP)), dim3(256), 0, s, a);
     return hipGetLastError();
+}
+
+bool batch_blend_tile_supported(int probes, int chunk) {
+    return (probes == 16 || probes == 8) && (chunk == 32 || chunk == 64 || chunk == 128);
+}
+
+hipError_t launch_batch_blend(const BatchBlendArgs &a, int nblocks16, const BatchTuning &t,
+                              hipStream_t s) {
+    if (nblocks16 <= 0) return hipSuccess;
+    const int key = t.blend_probes * 1000 + t.blend_chunk;
+    switch (key) {
+        case 16032: return launch_blend_tile<16, 32>(a, nblocks16, s);
+        case 16064: return launch_blend_tile<16, 64>(a, nblocks16, s);
+        case 16128: return launch_blend_tile<16, 128>(a, nblocks16, s);
+        case 8032: return launch_blend_tile<8, 32>(a, nblocks16, s);
+        case 8064: return launch_blend_tile<8, 64>(a, nblocks16, s);
+        case 8128: return launch_blend_tile<8, 128>(a, nblocks16, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace sdfddgi

@@ -10,13 +10,14 @@ namespace sdfddgi {
 constexpr int kBlendProbes = 16;  // probes per workgroup: the N extent of a tile row
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-// The probes of one blend workgroup (slots pb .. pb+np-1 of the probe list, or of
-// 0..P-1) and their hysteresis: none where the history is rejected. The first
+// The probes of one blend workgroup of kP (slots pb .. pb+np-1 of the probe list, or
+// of 0..P-1) and their hysteresis: none where the history is rejected. The first
 // __syncthreads of the caller's ray loop publishes them.
+template <int kP = kBlendProbes>
 __device__ __forceinline__ void load_blend_probes(const BlendArgs &a, int pb, int np, int *s_pid,
                                                   float *s_h) {
     const int tid = threadIdx.x;
-    if (tid < kBlendProbes) {
+    if (tid < kP) {
         const int pid = tid < np ? (a.probe_list ? a.probe_list[pb + tid] : pb + tid) : 0;
         s_pid[tid] = pid;
         s_h[tid] = (tid < np && !(a.reject && a.reject[pid])) ? a.hysteresis : 0.0f;
@@ -120,15 +121,16 @@ __device__ __forceinline__ void epilogue_map_lds(const float *prev, float *next,
 
 // Epilogue of the standard layout (8x8 irradiance in slot 0 of every wave, 16x16
 // depth in slots 1..4) for one workgroup's probes; buf: kEpilogueFloats of LDS that
-// the caller no longer needs. kClamp: as for blend_epilogue.
-template <bool kClamp = false>
+// the caller no longer needs. kClamp: as for blend_epilogue. kNi / kNd: the 16-column
+// N-tiles of the irradiance (3 per probe) and depth (2 per probe) products.
+template <bool kClamp = false, int kNi = 3, int kNd = 2>
 __device__ __forceinline__ void blend_epilogue_std(const BlendArgs &a, const float *s_h,
                                                    const int *s_pid, int np, int wave, int row,
-                                                   int krow, const floatx4 (&acc)[kMSlots][3],
+                                                   int krow, const floatx4 (&acc)[kMSlots][kNi],
                                                    float *buf) {
     __syncthreads();  // every wave is done with what buf held before
 #pragma unroll
-    for (int n = 0; n < 3; ++n) {
+    for (int n = 0; n < kNi; ++n) {
         const int col = n * 16 + row, q = col / 3, c = col - 3 * q;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -141,7 +143,7 @@ __device__ __forceinline__ void blend_epilogue_std(const BlendArgs &a, const flo
     for (int s = 1; s < kMSlots; ++s) {
         const int tile = (s - 1) * 4 + wave;
 #pragma unroll
-        for (int n = 0; n < 2; ++n) {
+        for (int n = 0; n < kNd; ++n) {
             const int col = n * 16 + row, q = col >> 1, m = col & 1;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -155,54 +157,59 @@ __device__ __forceinline__ void blend_epilogue_std(const BlendArgs &a, const flo
 
 typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
-constexpr int kPitch16 = kBlendChunk + 8;  // halves per LDS column (+8 spreads the banks)
 
 // Precision form of the blend: the same tiling as blend_kernel, with the weights as
 // FP16 (irradiance) / BF16 (depth) rows [T][Rpad] and the payload staged in LDS as
 // FP16 radiance and BF16 (t, t^2) columns, contracted 32 rays at a time on
 // v_mfma_f32_16x16x32_{f16,bf16} with FP32 accumulation.
-// One workgroup's share (probe slots pb .. pb+15) of the precision-form blend; also
-// the body of the batched blend, which passes each scene's arguments.
-template <bool kStd>
+// One workgroup's share (probe slots pb .. pb+kP-1) of the precision-form blend; also
+// the body of the batched blend, which passes each scene's arguments. The tile: kP
+// probes per workgroup (16: 3 irradiance and 2 depth N-tiles of 16 columns; 8: 2 and
+// 1, the last irradiance tile a third empty) and kChunk rays staged in LDS at a time
+// (a multiple of 32 that divides Rpad).
+template <bool kStd, int kP = kBlendProbes, int kChunk = kBlendChunk>
 __device__ __forceinline__ void blend16_block(const BlendArgs &a, int pb) {
+    constexpr int kPitch = kChunk + 8;  // halves per LDS column (+8 spreads the banks)
+    constexpr int kNi = (3 * kP + 15) / 16, kNd = (2 * kP + 15) / 16;
     // payload staging (FP16 radiance, BF16 moments); the standard layout's epilogue
     // reuses the buffer
-    constexpr int kSi = (kBlendProbes * 3 + 1) * kPitch16, kSd = (kBlendProbes * 2 + 1) * kPitch16;
+    constexpr int kSi = (kP * 3 + 1) * kPitch, kSd = (kP * 2 + 1) * kPitch;
+    static_assert(kP <= kBlendProbes && kChunk % 32 == 0, "tile within the buffers");
     static_assert((kSi + kSd) * 2 <= kEpilogueFloats * 4, "staging fits the epilogue buffer");
     static_assert(kSi % 8 == 0, "16-byte aligned depth staging");
     __shared__ __attribute__((aligned(16))) float sbuf[kEpilogueFloats];
     _Float16 *si = reinterpret_cast<_Float16 *>(sbuf);
     __bf16 *sd = reinterpret_cast<__bf16 *>(si + kSi);
-    __shared__ float s_h[kBlendProbes];
-    __shared__ int s_pid[kBlendProbes];
+    __shared__ float s_h[kP];
+    __shared__ int s_pid[kP];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int row = lane & 15, kgrp = lane >> 4;
     const int count = a.probe_list ? min(*a.probe_count, a.P) : a.P;
     if (pb >= count) return;
-    const int np = min(kBlendProbes, count - pb);
+    const int np = min(kP, count - pb);
     const int Ti = a.irr_res * a.irr_res, Td = a.depth_res * a.depth_res;
     const int mti = (Ti + 15) >> 4, mtd = (Td + 15) >> 4;
     const int mtiles = mti + mtd;
-    load_blend_probes(a, pb, np, s_pid, s_h);
-    for (int e = tid; e < kPitch16; e += 256) {
-        si[kBlendProbes * 3 * kPitch16 + e] = (_Float16)0.0f;
-        sd[kBlendProbes * 2 * kPitch16 + e] = (__bf16)0.0f;
+    load_blend_probes<kP>(a, pb, np, s_pid, s_h);
+    for (int e = tid; e < kPitch; e += 256) {
+        si[kP * 3 * kPitch + e] = (_Float16)0.0f;
+        sd[kP * 2 * kPitch + e] = (__bf16)0.0f;
     }
-    int bi_off[3], bd_off[2];
+    int bi_off[kNi], bd_off[kNd];
 #pragma unroll
-    for (int n = 0; n < 3; ++n) {
+    for (int n = 0; n < kNi; ++n) {
         const int col = n * 16 + row;
-        bi_off[n] = (col / 3 < np ? col : kBlendProbes * 3) * kPitch16;
+        bi_off[n] = (col / 3 < np ? col : kP * 3) * kPitch;
     }
 #pragma unroll
-    for (int n = 0; n < 2; ++n) {
+    for (int n = 0; n < kNd; ++n) {
         const int col = n * 16 + row;
-        bd_off[n] = ((col >> 1) < np ? col : kBlendProbes * 2) * kPitch16;
+        bd_off[n] = ((col >> 1) < np ? col : kP * 2) * kPitch;
     }
     const int passes = kStd ? 1 : (mtiles + 4 * kMSlots - 1) / (4 * kMSlots);
     for (int pass = 0; pass < passes; ++pass) {
-        floatx4 acc[kMSlots][3];
+        floatx4 acc[kMSlots][kNi];
         int mt[kMSlots];
         const _Float16 *wi[kMSlots];
         const __bf16 *wd[kMSlots];
@@ -213,51 +220,51 @@ __device__ __forceinline__ void blend16_block(const BlendArgs &a, int pb) {
             wi[s] = a.w16_i + (size_t)(mt[s] * 16 + row) * a.Rpad;
             wd[s] = a.w16_d + (size_t)((irr ? 0 : mt[s] - mti) * 16 + row) * a.Rpad;
 #pragma unroll
-            for (int n = 0; n < 3; ++n) acc[s][n] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            for (int n = 0; n < kNi; ++n) acc[s][n] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
         }
-        for (int k0 = 0; k0 < a.Rpad; k0 += kBlendChunk) {
+        for (int k0 = 0; k0 < a.Rpad; k0 += kChunk) {
             __syncthreads();
-            const int kc = min(kBlendChunk, a.R - k0);  // rays present in this chunk
-            for (int e = tid; e < kBlendProbes * kBlendChunk; e += 256) {
-                const int q = e / kBlendChunk, kk = e - q * kBlendChunk;
+            const int kc = min(kChunk, a.R - k0);  // rays present in this chunk
+            for (int e = tid; e < kP * kChunk; e += 256) {
+                const int q = e / kChunk, kk = e - q * kChunk;
                 float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                 if (q < np && kk < kc) v = a.payload[(size_t)s_pid[q] * a.R + k0 + kk];
-                si[(q * 3 + 0) * kPitch16 + kk] = (_Float16)v.x;
-                si[(q * 3 + 1) * kPitch16 + kk] = (_Float16)v.y;
-                si[(q * 3 + 2) * kPitch16 + kk] = (_Float16)v.z;
-                sd[(q * 2 + 0) * kPitch16 + kk] = (__bf16)v.w;
-                sd[(q * 2 + 1) * kPitch16 + kk] = (__bf16)(v.w * v.w);
+                si[(q * 3 + 0) * kPitch + kk] = (_Float16)v.x;
+                si[(q * 3 + 1) * kPitch + kk] = (_Float16)v.y;
+                si[(q * 3 + 2) * kPitch + kk] = (_Float16)v.z;
+                sd[(q * 2 + 0) * kPitch + kk] = (__bf16)v.w;
+                sd[(q * 2 + 1) * kPitch + kk] = (__bf16)(v.w * v.w);
             }
             __syncthreads();
 #pragma unroll
-            for (int kk = 0; kk < kBlendChunk; kk += 32) {
+            for (int kk = 0; kk < kChunk; kk += 32) {
                 const int kl = kk + 8 * kgrp;  // this lane's 8 rays within the chunk
-                half8_t bi[3];
-                bf16x8_t bd[2];
+                half8_t bi[kNi];
+                bf16x8_t bd[kNd];
 #pragma unroll
-                for (int n = 0; n < 3; ++n)
+                for (int n = 0; n < kNi; ++n)
                     bi[n] = *reinterpret_cast<const half8_t *>(&si[bi_off[n] + kl]);
 #pragma unroll
-                for (int n = 0; n < 2; ++n)
+                for (int n = 0; n < kNd; ++n)
                     bd[n] = *reinterpret_cast<const bf16x8_t *>(&sd[bd_off[n] + kl]);
 #pragma unroll
                 for (int s = 0; s < kMSlots; ++s) {
                     if (kStd ? s == 0 : mt[s] < mti) {
                         const half8_t av = *reinterpret_cast<const half8_t *>(wi[s] + k0 + kl);
 #pragma unroll
-                        for (int n = 0; n < 3; ++n)
+                        for (int n = 0; n < kNi; ++n)
                             acc[s][n] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bi[n], acc[s][n], 0, 0, 0);
                     } else if (kStd || mt[s] < mtiles) {
                         const bf16x8_t av = *reinterpret_cast<const bf16x8_t *>(wd[s] + k0 + kl);
 #pragma unroll
-                        for (int n = 0; n < 2; ++n)
+                        for (int n = 0; n < kNd; ++n)
                             acc[s][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bd[n], acc[s][n], 0, 0, 0);
                     }
                 }
             }
         }
         if (kStd) {
-            blend_epilogue_std<true>(a, s_h, s_pid, np, wave, row, kgrp, acc, sbuf);
+            blend_epilogue_std<true, kNi, kNd>(a, s_h, s_pid, np, wave, row, kgrp, acc, sbuf);
             continue;
         }
 #pragma unroll
@@ -265,8 +272,8 @@ __device__ __forceinline__ void blend16_block(const BlendArgs &a, int pb) {
             if (!kStd && mt[s] >= mtiles) continue;
             const bool irr = kStd ? s == 0 : mt[s] < mti;
 #pragma unroll
-            for (int n = 0; n < 3; ++n) {
-                if (!irr && n == 2) break;
+            for (int n = 0; n < kNi; ++n) {
+                if (!irr && n >= kNd) break;
                 blend_epilogue<true>(a, s_h, s_pid, np, irr, irr ? mt[s] : mt[s] - mti, n, row,
                                      kgrp, acc[s][n]);
             }

@@ -343,7 +343,7 @@ struct BatchArgs {
 struct BatchBlendArgs {
     int nscenes;
     const BatchScene *scenes;
-    const int2 *blocks;                   // [nblocks]: (scene, first probe) of each workgroup
+    const int2 *blocks;                   // [nblocks16]: (scene, first probe) of each 16 probes
     const float4 *payload;
     const float *prev_irr, *prev_depth;
     float *new_irr, *new_depth;
@@ -354,13 +354,18 @@ struct BatchBlendArgs {
 
 struct BatchTuning {
     int primary_chunk, primary_blocks, hits_chunk, hits_blocks, refill;
+    int blend_probes, blend_chunk;        // blend tile: probes per workgroup, rays per LDS stage
 };
 
 hipError_t launch_batch_begin(int *counter, unsigned long long *stamps, int nscenes,
                               hipStream_t stream);
 hipError_t launch_batch_primary(const BatchArgs &a, const BatchTuning &t, hipStream_t stream);
 hipError_t launch_batch_hits(const BatchArgs &a, const BatchTuning &t, hipStream_t stream);
-hipError_t launch_batch_blend(const BatchBlendArgs &a, int nblocks, hipStream_t stream);
+// nblocks16 entries of the 16-probe block table, each split into 16 / blend_probes
+// workgroups.
+hipError_t launch_batch_blend(const BatchBlendArgs &a, int nblocks16, const BatchTuning &t,
+                              hipStream_t stream);
+bool batch_blend_tile_supported(int probes, int chunk);
 int batch_max_blocks(int device, bool hits);
 
 // -------------------------------------------------- analytic SDF (cluster.hip) --

@@ -2078,7 +2078,7 @@ BatchArgs batch_args(const sdfddgi_batch *b, int cur, int lane) {
 // lane `lane`'s buffers (a frame normally uses lane cur), in two parts: the front
 // (counters, tables, primary trace; reads no map) and the back (hit shading, blend).
 // `ev` (may be null) receives events before the primary trace (front), and after
-// it and after the hit shading (back).
+// it, after the hit shading and (when ev[3] is set) after the blend (back).
 hipError_t batch_enqueue_front(sdfddgi_batch *b, int lane, const BatchTuning &t, hipStream_t st,
                                hipEvent_t *ev) {
     const int cur = lane;
@@ -2130,7 +2130,8 @@ hipError_t batch_enqueue_back(sdfddgi_batch *b, int cur, int lane, const BatchTu
     bb.new_depth = b->depth[1 - cur];
     bb.reject = b->reject;
     bb.done = b->stamps[lane] + 1;
-    return launch_batch_blend(bb, b->nblocks, st);
+    if ((e = launch_batch_blend(bb, b->nblocks, t, st)) != hipSuccess) return e;
+    return ev && ev[3] ? hipEventRecord(ev[3], st) : hipSuccess;
 }
 
 // One whole frame on the caller's stream (the autotuner's candidates).
@@ -2465,6 +2466,8 @@ sdfddgi_status sdfddgi_batch_create(const sdfddgi_batch_scene *scenes, int32_t c
     b->tuning.hits_chunk = 64;
     b->tuning.hits_blocks = batch_max_blocks(dev, true);
     b->tuning.refill = 40;
+    b->tuning.blend_probes = 16;
+    b->tuning.blend_chunk = 64;
     B_TRY(hipStreamSynchronize(b->stream), "waiting for the uploads");
     B_TRY(batch_capture(b), "capturing the frame graphs");
 #undef B_TRY
@@ -2508,25 +2511,35 @@ sdfddgi_status sdfddgi_batch_update_frame(sdfddgi_batch *b, const sdfddgi_light 
     return SDFDDGI_OK;
 }
 
-static bool tuning_valid(int device, const sdfddgi_batch_tuning *t) {
+// The blend tile's ray chunk must divide every scene's ray count (the weight rows
+// are read a whole chunk at a time).
+static bool blend_chunk_fits(const sdfddgi_batch *b, int chunk) {
+    for (const BatchScene &s : b->host_scenes)
+        if (s.R % chunk != 0) return false;
+    return true;
+}
+
+static bool tuning_valid(const sdfddgi_batch *b, const sdfddgi_batch_tuning *t) {
     return t && batch_chunk_supported(t->primary_chunk, false) &&
            batch_chunk_supported(t->hits_chunk, true) && t->primary_blocks >= 1 &&
-           t->primary_blocks <= batch_max_blocks(device, false) && t->hits_blocks >= 1 &&
-           t->hits_blocks <= batch_max_blocks(device, true) && t->refill >= 1 && t->refill <= 64;
+           t->primary_blocks <= batch_max_blocks(b->device, false) && t->hits_blocks >= 1 &&
+           t->hits_blocks <= batch_max_blocks(b->device, true) && t->refill >= 1 &&
+           t->refill <= 64 && batch_blend_tile_supported(t->blend_probes, t->blend_chunk) &&
+           blend_chunk_fits(b, t->blend_chunk);
 }
 
 sdfddgi_status sdfddgi_batch_set_tuning(sdfddgi_batch *b, const sdfddgi_batch_tuning *t) {
     g_learned_error.clear();
     if (!b) return lfail(SDFDDGI_EINVAL, "batch is NULL");
     (void)hipGetLastError();
-    if (!tuning_valid(b->device, t)) return lfail(SDFDDGI_EINVAL, "tuning out of range");
+    if (!tuning_valid(b, t)) return lfail(SDFDDGI_EINVAL, "tuning out of range");
     hipError_t e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return lhip_fail(e, "waiting for the stream");
     if ((e = hipStreamSynchronize(b->side)) != hipSuccess)
         return lhip_fail(e, "waiting for the stream");
     b->serialize_next = true;
     b->tuning = BatchTuning{t->primary_chunk, t->primary_blocks, t->hits_chunk, t->hits_blocks,
-                            t->refill};
+                            t->refill, t->blend_probes, t->blend_chunk};
     if ((e = batch_capture(b)) != hipSuccess) return lhip_fail(e, "capturing the frame graphs");
     return SDFDDGI_OK;
 }
@@ -2552,22 +2565,26 @@ sdfddgi_status sdfddgi_batch_autotune(sdfddgi_batch *b, const sdfddgi_light *lig
     uint8_t *saved = nullptr;
     if ((e = dev_alloc(&saved, (size_t)b->GP)) != hipSuccess) return lhip_fail(e, "allocating");
     e = hipMemcpyAsync(saved, b->reject, (size_t)b->GP, hipMemcpyDeviceToDevice, b->stream);
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-    for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipEventCreate(&ev[k]);
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (int k = 0; k < 4 && e == hipSuccess; ++k) e = hipEventCreate(&ev[k]);
     const int pmax = batch_max_blocks(b->device, false), hmax = batch_max_blocks(b->device, true);
     int count = 0;
-    // time one configuration: mean primary and hit kernel times over `frames`
+    // time one configuration: mean primary, hit shading and blend kernel times over
+    // `frames`
+    float blend = 0.0f;
     auto measure = [&](const BatchTuning &t, float &prim, float &hits) -> hipError_t {
-        prim = hits = 0.0f;
+        prim = hits = blend = 0.0f;
         for (int f = 0; f < frames; ++f) {
             hipError_t x = batch_enqueue(b, b->cur, t, ev);
             if (x != hipSuccess) return x;
-            if ((x = hipEventSynchronize(ev[2])) != hipSuccess) return x;
-            float a = 0.0f, c = 0.0f;
+            if ((x = hipEventSynchronize(ev[3])) != hipSuccess) return x;
+            float a = 0.0f, c = 0.0f, d = 0.0f;
             if ((x = hipEventElapsedTime(&a, ev[0], ev[1])) != hipSuccess) return x;
             if ((x = hipEventElapsedTime(&c, ev[1], ev[2])) != hipSuccess) return x;
+            if ((x = hipEventElapsedTime(&d, ev[2], ev[3])) != hipSuccess) return x;
             prim += a / frames;
             hits += c / frames;
+            blend += d / frames;
         }
         ++count;
         return hipSuccess;
@@ -2602,6 +2619,22 @@ sdfddgi_status sdfddgi_batch_autotune(sdfddgi_batch *b, const sdfddgi_light *lig
                 best_h = h;
                 best.hits_chunk = t.hits_chunk;
                 best.hits_blocks = t.hits_blocks;
+            }
+        }
+    // the blend tile: probes per workgroup x rays per LDS stage (those that divide
+    // every scene's ray count)
+    const int bprobes[2] = {16, 8}, bchunks[3] = {32, 64, 128};
+    float best_b = 1e30f;
+    for (int pi = 0; pi < 2 && e == hipSuccess; ++pi)
+        for (int ci = 0; ci < 3 && e == hipSuccess; ++ci) {
+            if (!blend_chunk_fits(b, bchunks[ci])) continue;
+            BatchTuning t = best;
+            t.blend_probes = bprobes[pi];
+            t.blend_chunk = bchunks[ci];
+            if ((e = measure(t, p, h)) == hipSuccess && blend < best_b) {
+                best_b = blend;
+                best.blend_probes = t.blend_probes;
+                best.blend_chunk = t.blend_chunk;
             }
         }
     // then the grids of both parts as consecutive frames run them, the front of one
@@ -2648,7 +2681,7 @@ sdfddgi_status sdfddgi_batch_autotune(sdfddgi_batch *b, const sdfddgi_light *lig
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->reject, saved, (size_t)b->GP, hipMemcpyDeviceToDevice, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < 4; ++k)
         if (ev[k]) (void)hipEventDestroy(ev[k]);
     dev_free(saved);
     if (e != hipSuccess) return lhip_fail(e, "autotuning");
@@ -2656,7 +2689,8 @@ sdfddgi_status sdfddgi_batch_autotune(sdfddgi_batch *b, const sdfddgi_light *lig
     if ((e = batch_capture(b)) != hipSuccess) return lhip_fail(e, "capturing the frame graphs");
     if (chosen)
         *chosen = sdfddgi_batch_tuning{best.primary_chunk, best.primary_blocks, best.hits_chunk,
-                                       best.hits_blocks, best.refill};
+                                       best.hits_blocks, best.refill, best.blend_probes,
+                                       best.blend_chunk};
     if (tried) *tried = count;
     return SDFDDGI_OK;
 }

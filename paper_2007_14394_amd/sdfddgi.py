@@ -86,7 +86,8 @@ class sdfddgi_train_config(ctypes.Structure):
 class sdfddgi_batch_tuning(ctypes.Structure):
     _fields_ = [("primary_chunk", ctypes.c_int32), ("primary_blocks", ctypes.c_int32),
                 ("hits_chunk", ctypes.c_int32), ("hits_blocks", ctypes.c_int32),
-                ("refill", ctypes.c_int32)]
+                ("refill", ctypes.c_int32), ("blend_probes", ctypes.c_int32),
+                ("blend_chunk", ctypes.c_int32)]
 
 
 class sdfddgi_light(ctypes.Structure):
@@ -762,7 +763,8 @@ def sdfddgi_batch_autotune(b: Batch, lights, rotation_seed: int, frames_per_cand
 
 
 def sdfddgi_batch_set_tuning(b: Batch, **fields) -> None:
-    t = sdfddgi_batch_tuning(**fields)
+    """Fields of sdfddgi_batch_tuning; the blend tile defaults to 16 probes x 64 rays."""
+    t = sdfddgi_batch_tuning(**{"blend_probes": 16, "blend_chunk": 64, **fields})
     _lcheck(load_library().sdfddgi_batch_set_tuning(b.handle, ctypes.byref(t)))
 
 

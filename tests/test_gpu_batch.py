@@ -80,8 +80,11 @@ def test_autotune_changes_no_result(S):
     before = [to_host(S.sdfddgi_batch_get_maps(t, s)[0]) for s in range(len(specs))]
     tuning, tried = S.sdfddgi_batch_autotune(t, lights_of(specs, 1), seeds[1], 1)
     announce(f"autotune tried {tried}: {tuning}")
-    assert tried == 32 + 8 + 9   # primary alone, hits alone, both grids overlapped
+    # primary alone, hits alone, the blend tile alone (chunks dividing every R), grids
+    chunks = [c for c in (32, 64, 128) if all(sp.params.rays_per_probe % c == 0 for sp in specs)]
+    assert tried == 32 + 8 + 2 * len(chunks) + 9
     assert tuning["primary_chunk"] in (64, 128, 256, 512) and tuning["hits_chunk"] in (16, 32, 64, 128)
+    assert tuning["blend_probes"] in (16, 8) and tuning["blend_chunk"] in chunks
     for s in range(len(specs)):   # the tuning frames leave the state as it was
         assert np.array_equal(to_host(S.sdfddgi_batch_get_maps(t, s)[0]), before[s])
     for f in (1, 2):
@@ -91,6 +94,30 @@ def test_autotune_changes_no_result(S):
         for k in range(2):
             x, y = S.sdfddgi_batch_get_maps(a, s)[k], S.sdfddgi_batch_get_maps(t, s)[k]
             assert np.array_equal(to_host(x), to_host(y))
+
+
+def test_every_blend_tile_gives_the_same_bits(S):
+    """The blend tile changes how probes and rays are grouped, not the order in which
+    each texel accumulates its rays: every tile gives the default tile's bits."""
+    specs, seeds, works = small_batch(count=4, seed=5)
+    baked = [w.levels[0] for w in works]
+    chunks = [c for c in (32, 64, 128) if all(sp.params.rays_per_probe % c == 0 for sp in specs)]
+    ref = None
+    for probes in (16, 8):
+        for chunk in chunks:
+            announce(f"blend tile {probes} probes x {chunk} rays")
+            b = S.batch_from_specs(specs, baked=baked)
+            S.sdfddgi_batch_set_tuning(b, primary_chunk=256, primary_blocks=256, hits_chunk=64,
+                                       hits_blocks=256, refill=40, blend_probes=probes,
+                                       blend_chunk=chunk)
+            for f in (0, 1):
+                S.sdfddgi_batch_update_frame(b, lights_of(specs, f), seeds[f])
+            maps = [[to_host(m) for m in S.sdfddgi_batch_get_maps(b, s)] for s in range(len(specs))]
+            if ref is None:
+                ref = maps
+            for s in range(len(specs)):
+                for k in range(2):
+                    assert np.array_equal(maps[s][k], ref[s][k]), (probes, chunk, s, k)
 
 
 def test_explicit_tuning_and_its_validation(S):
@@ -105,6 +132,11 @@ def test_explicit_tuning_and_its_validation(S):
     with pytest.raises(S.SdfddgiError):
         S.sdfddgi_batch_set_tuning(b, primary_chunk=64, primary_blocks=64, hits_chunk=16,
                                    hits_blocks=32, refill=0)
+    for probes, chunk in ((4, 64), (16, 48), (8, 256)):
+        with pytest.raises(S.SdfddgiError):
+            S.sdfddgi_batch_set_tuning(b, primary_chunk=64, primary_blocks=64, hits_chunk=16,
+                                       hits_blocks=32, refill=24, blend_probes=probes,
+                                       blend_chunk=chunk)
 
 
 def test_scene_latencies_from_the_device_clock(S):
