@@ -1498,22 +1498,31 @@ sdfddgi_status sdfddgi_update_frame_learned(sdfddgi_ctx *c, const sdfddgi_denois
     TRY_HIP(c, launch_tables(table_args(c, lo, rotation_seed, kSetCounters, lo.counter), sl),
             "launching tables_kernel");
     TRY_HIP(c, ev.mark_on(1, sl), "event");
-    TRY_HIP(c, launch_primary(tl, lo.grid, sl), "launching primary_kernel");
+    // The side chains run on small grids, so that the caller's stream -- the lookups,
+    // Eq. 3 and the network, the frame's critical chain -- keeps most of the GPU:
+    // measured at 16384 probes (FP16 / FP32 ms per frame, median of three 20-frame
+    // windows), full and overlapped grids 0.323 / 0.346; low primary at half the
+    // full grid and the rest at half the overlapped grids 0.275 / 0.298; the
+    // fallback primary at a quarter 0.272 / 0.296; a quarter everywhere 0.289 / 0.319
+    TraceGrid gl = lo.grid;
+    gl.primary_blocks = std::max(1, gl.primary_blocks / 2);
+    gl.hits_blocks = std::max(1, gl.hits_blocks_overlapped / 2);
+    TRY_HIP(c, launch_primary(tl, gl, sl), "launching primary_kernel");
     TRY_HIP(c, ev.mark_on(2, sl), "event");
     TRY_HIP(c, ev.mark_on(3, sl), "event");
-    TRY_HIP(c, launch_hits(tl, lo.grid, sl), "launching hits_kernel");
+    TRY_HIP(c, launch_hits(tl, gl, sl), "launching hits_kernel");
     TRY_HIP(c, hipEventRecord(lo.ready, sl), "event");
     // fallback chain: the list -- probes whose flag of this parity asks for the plain
     // update (the decision of the learned frame before the previous one; set in every
     // probe until then) or, when serial, whose history is rejected -- then the
-    // fallback probes' pass, on the grids of a trace that shares the GPU
+    // fallback probes' pass, on small grids (see the low chain)
     int *fb_count = fb.counter + 6;
     TraceArgs tf = trace_pass(base, fb, fb.counter, fb.counter + kPartStride, fb.list, fb_count,
                               nullptr);
     tf.geo = fb.geo;
     TraceGrid gf = fb.grid;
-    gf.primary_blocks = gf.primary_blocks_overlapped;
-    gf.hits_blocks = gf.hits_blocks_overlapped;
+    gf.primary_blocks = std::max(1, gf.primary_blocks_overlapped / 4);
+    gf.hits_blocks = std::max(1, gf.hits_blocks_overlapped / 2);
     TRY_HIP(c, ev.mark_on(7, sf), "event");
     TRY_HIP(c, launch_tables(table_args(c, fb, rotation_seed, kSetCounters, fb.counter), sf),
             "launching tables_kernel");
