@@ -311,6 +311,112 @@ def test_learned_frame_matches_checker(S, res):
     assert np.median(np.abs(got - want) / (np.abs(want) + 1e-3)) <= 1e-4
 
 
+def lipschitz(theta, dx):
+    """First-order bound on how far each output moves when the input moves by dx: the
+    network evaluated with |W| on |dx| and no biases (a ReLU network is piecewise
+    linear, and on each piece its slope is a product of the weights)."""
+    th = np.abs(np.asarray(theta, dtype=np.float64)).copy()
+    for off, n in ((oracle.OFF_B2, 64), (oracle.OFF_B3, 64), (oracle.OFF_B4, 4)):
+        th[off:off + n] = 0.0
+    return oracle.mlp_forward(th, np.abs(np.asarray(dx, dtype=np.float64)), mirror=False)
+
+
+def test_learned_frame_precision_form_matches_checker(S):
+    """The learned form in the precision form (binary16 SDF, FP16/BF16 blends): learned
+    frames 2, 3 and 4 as in test_learned_frame_matches_checker, against the checker on
+    the rounded grid. Besides the network's rounding flips (2^-5 M per output), the
+    low-ray update U_low differs from the checker's by at most the precision form's
+    irradiance bound b_i (hysteresis 0); it enters the network as U_low / S, so each
+    output moves by at most lipschitz(|dx|) more, with dx = b_i / S in the three U_low
+    slots. The prediction band, the decisions and the maps' bounds take both terms;
+    depth and fallback probes' maps are held to the precision form's own bounds."""
+    announce("learned frame small_cascade, precision form")
+    w = learned_workload()
+    w16 = H.fp16_grid(w)
+    th = random_theta(7, scale=0.5)
+    th[oracle.OFF_B4 + 3] = -3.0
+    ck = oracle.Checker(w16)
+    P = ck.num_probes
+    states = [tuple(m.astype(np.float32).astype(np.float64) for m in st)
+              for st in ck.run_frames(w16.frames[:4])]
+    pre = ck.learned_frame(w16.frames[2], False, *states[1], th, S_IRR, D_DEPTH, math.inf, 32)
+    tau = float(np.median(pre["mean_error"]))
+    ctx = make_ctx(S, w, tau, flags=S.SDFDDGI_FLAG_FP16)
+    den = S.sdfddgi_denoiser_create(np.asarray(th, dtype=np.float32), S_IRR, D_DEPTH)
+    runs = []
+    for k in (1, 2, 3):
+        fr = w.frames[k + 1]
+        S.sdfddgi_set_maps(ctx, to_dev(states[k][0]), to_dev(states[k][1]))
+        S.sdfddgi_update_frame_learned(ctx, den, fr.dir_to_light, fr.radiance_rgb,
+                                       fr.rotation_seed)
+        cnt, lst, errs = S.sdfddgi_get_fallback(ctx)
+        ni, nd = S.sdfddgi_get_maps(ctx)
+        runs.append(dict(count=cnt, fallback=np.sort(to_host(lst)[:cnt]),
+                         mean_error=to_host(errs), irr=to_host(ni).astype(np.float64),
+                         depth=to_host(nd).astype(np.float64)))
+    S.sdfddgi_destroy(ctx)
+    t_max = float(np.float32(w.params.t_max))
+
+    def input_bound(k):
+        """|dx| per texel of learned frame k + 1 (from the checker's maps after frame k)."""
+        low = oracle.Checker(w16, rays=32, hysteresis=0.0)
+        _, _, pay, _ = low.update_probes(w16.frames[k + 1], True, *states[k], want_payload=True)
+        lmax = max(float(pay[..., :3].max()), float(states[k][0].max()))
+        bi = H.precision_bounds(lmax, t_max)[0]
+        dx = np.zeros((P * (w.params.irr_res ** 2), F))
+        dx[:, 0:3] = bi / S_IRR
+        return dx, lmax
+
+    # frames 2 and 3: the plain update everywhere; predictions within the band
+    assert runs[0]["count"] == P and runs[1]["count"] == P
+    dx, _ = input_bound(1)
+    o3 = (OUT_BOUND * magnitude(th, pre["features"].reshape(-1, F))[:, 3]
+          + lipschitz(th, dx)[:, 3]).reshape(P, -1)
+    slack = np.exp(o3.max(axis=1)) - 1.0
+    rel = np.abs(runs[0]["mean_error"] / pre["mean_error"] - 1.0)
+    assert np.all(rel <= slack + 1e-5), float((rel - slack).max())
+    # frame 4: decisions are frame 2's predictions against tau, and agree with the
+    # checker's wherever its prediction is clearly on one side of tau
+    r = runs[2]
+    gpu_fb = np.zeros(P, bool)
+    gpu_fb[r["fallback"]] = True
+    assert r["count"] == gpu_fb.sum() and len(np.unique(r["fallback"])) == r["count"]
+    np.testing.assert_array_equal(gpu_fb, runs[0]["mean_error"] > np.float32(tau))
+    clear = np.abs(pre["mean_error"] / tau - 1.0) > 2 * slack + 1e-4
+    assert np.array_equal(gpu_fb[clear], (pre["mean_error"] > tau)[clear])
+    assert 0 < gpu_fb.sum() < P
+    ref = ck.learned_frame(w16.frames[4], False, *states[3], th, S_IRR, D_DEPTH, tau, 32,
+                           fallback=gpu_fb)
+    dx, lmax = input_bound(3)
+    feats = ref["features"].reshape(-1, F)
+    ob = OUT_BOUND * magnitude(th, feats) + lipschitz(th, dx)
+    slack = np.exp(ob[:, 3].reshape(P, -1).max(axis=1)) - 1.0
+    rel = np.abs(r["mean_error"] / ref["mean_error"] - 1.0)
+    assert np.all(rel <= slack + 1e-5), float((rel - slack).max())
+    # depth of every probe and irradiance of the fallback probes: the precision form's
+    # bounds (an accepted probe's depth mixes the low-ray moments with weight 1 - h)
+    bi, b1, b2 = H.precision_bounds(lmax, t_max)
+    for name, got, want, bound in (("E[t]", r["depth"][..., 0], ref["depth"][..., 0], b1),
+                                   ("E[t^2]", r["depth"][..., 1], ref["depth"][..., 1], b2)):
+        err = float(np.abs(got - want).max())
+        assert err <= bound, f"{name} error {err:.3e} > {bound:.3e}"
+    assert not (r["depth"][..., 1].astype(np.float32) <
+                r["depth"][..., 0].astype(np.float32) ** 2).any()
+    err = float(np.abs(r["irr"][gpu_fb] - ref["irr"][gpu_fb]).max())
+    assert err <= bi, f"fallback irradiance error {err:.3e} > {bi:.3e}"
+    # accepted texels: U_hat enters with weight (1 - h)
+    h = ck.hysteresis
+    ri = w.params.irr_res
+    bound = np.zeros_like(ref["irr"])
+    bound[:, 1:ri + 1, 1:ri + 1, :] = ((1 - h) * S_IRR * ob[:, :3]).reshape(P, ri, ri, 3)
+    oracle._fill_borders(bound, ri)
+    acc = ~gpu_fb
+    got, want = r["irr"][acc], ref["irr"][acc]
+    assert np.all(np.abs(got - want) <= bound[acc] + 1e-4 * np.abs(want) + 1e-6)
+    announce(f"fallback {int(gpu_fb.sum())} of {P}; worst accepted error / bound "
+             f"{float((np.abs(got - want) / (bound[acc] + 1e-6)).max()):.3f}")
+
+
 def test_all_fallback_is_the_plain_frame_bit_for_bit(S):
     announce("learned frame tau=0 vs plain")
     w = learned_workload()
