@@ -1154,7 +1154,7 @@ sdfddgi_status sdfddgi_update_frame(sdfddgi_ctx *c, const sdfddgi_light *light,
                             c->stream),
             "launching blend_kernel");
     // the learned form's marks, in an order that makes each of its spans zero
-    for (int k : {5, 7, 8, 11, 9, 6, 10}) TRY_HIP(c, ev.mark(k), "event");
+    for (int k : {5, 6, 7, 8, 11, 9, 10}) TRY_HIP(c, ev.mark(k), "event");
     TRY_HIP(c, hipEventRecord(r.done, c->stream), "event");
     frame_done(c);
     std::swap(c->main, c->spare);
@@ -1295,7 +1295,7 @@ sdfddgi_status sdfddgi_get_kernel_times(sdfddgi_ctx *c, float *ms, int32_t count
     // tables, primary, hits, blend, frame, denoiser, fallback trace, fallback blend
     // (the marks of FrameEvents; in a plain frame marks 5.. coincide)
     constexpr int kTimes = 8;
-    const int pairs[kTimes][2] = {{0, 1}, {1, 2}, {3, 4}, {4, 5}, {0, 10}, {9, 6}, {7, 8}, {11, 9}};
+    const int pairs[kTimes][2] = {{0, 1}, {1, 2}, {3, 4}, {4, 5}, {0, 10}, {5, 6}, {7, 8}, {11, 9}};
     double sum[kTimes] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int f = 0; f < frames; ++f) {
         const hipEvent_t *ev = c->ev_ring + kEvents * ((last - f + kTimingRing) % kTimingRing);
