@@ -221,6 +221,8 @@ struct sdfddgi_ctx {
     // Timing: kEvents events per frame in a ring (see sdfddgi_get_kernel_times);
     // sdfddgi_get_kernel_times averages the frames recorded since its previous call.
     hipEvent_t *ev_ring = nullptr;
+    bool ring_learned[kTimingRing]{};   // the frame in that slot was learned (else only
+                                        // marks 0-5 and 10 were recorded)
     int ring_head = 0;
     int64_t timed_frames = 0;
     std::string err;
@@ -806,8 +808,9 @@ FrameEvents frame_events(sdfddgi_ctx *c) {
     return f;
 }
 
-void frame_done(sdfddgi_ctx *c) {
+void frame_done(sdfddgi_ctx *c, bool learned) {
     if (c->ev_ring) {
+        c->ring_learned[c->ring_head] = learned;
         c->ring_head = (c->ring_head + 1) % kTimingRing;
         ++c->timed_frames;
     }
@@ -1153,10 +1156,11 @@ sdfddgi_status sdfddgi_update_frame(sdfddgi_ctx *c, const sdfddgi_light *light,
                                        nullptr, nullptr),
                             c->stream),
             "launching blend_kernel");
-    // the learned form's marks, in an order that makes each of its spans zero
-    for (int k : {5, 6, 7, 8, 11, 9, 10}) TRY_HIP(c, ev.mark(k), "event");
+    // the learned form's marks are not recorded (their spans read as 0)
+    TRY_HIP(c, ev.mark(5), "event");
+    TRY_HIP(c, ev.mark(10), "event");
     TRY_HIP(c, hipEventRecord(r.done, c->stream), "event");
-    frame_done(c);
+    frame_done(c, false);
     std::swap(c->main, c->spare);
     c->cur = nxt;
     c->have_frame = true;
@@ -1293,13 +1297,15 @@ sdfddgi_status sdfddgi_get_kernel_times(sdfddgi_ctx *c, float *ms, int32_t count
     TRY_HIP(c, hipEventSynchronize(c->ev_ring[kEvents * last + 10]),
             "hipEventSynchronize");
     // tables, primary, hits, blend, frame, denoiser, fallback trace, fallback blend
-    // (the marks of FrameEvents; in a plain frame marks 5.. coincide)
+    // (the marks of FrameEvents; the last three are learned-only)
     constexpr int kTimes = 8;
     const int pairs[kTimes][2] = {{0, 1}, {1, 2}, {3, 4}, {4, 5}, {0, 10}, {5, 6}, {7, 8}, {11, 9}};
     double sum[kTimes] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int f = 0; f < frames; ++f) {
-        const hipEvent_t *ev = c->ev_ring + kEvents * ((last - f + kTimingRing) % kTimingRing);
+        const int slot = (last - f + kTimingRing) % kTimingRing;
+        const hipEvent_t *ev = c->ev_ring + kEvents * slot;
         for (int k = 0; k < kTimes; ++k) {
+            if (k >= 5 && !c->ring_learned[slot]) continue;
             float v = 0.0f;
             TRY_HIP(c, hipEventElapsedTime(&v, ev[pairs[k][0]], ev[pairs[k][1]]),
                     "hipEventElapsedTime");
@@ -1580,7 +1586,7 @@ sdfddgi_status sdfddgi_update_frame_learned(sdfddgi_ctx *c, const sdfddgi_denois
     TRY_HIP(c, ev.mark(10), "event");
     TRY_HIP(c, hipEventRecord(c->ev_end, c->stream), "event");
     ++c->learned_index;
-    frame_done(c);
+    frame_done(c, true);
     c->last_learned = k;
     c->cur = nxt;
     c->have_learned = true;

@@ -355,7 +355,9 @@ def test_kernel_timing_reports_positive_times(S):
     for fr in w.frames:
         gpu_frame(S, ctx, fr)
     t = S.sdfddgi_get_kernel_times(ctx)
-    assert all(v > 0 for v in t.values())
+    plain = ("tables", "primary", "hits", "blend", "frame")
+    assert all(t[k] > 0 for k in plain), t
+    assert all(t[k] == 0 for k in t if k not in plain), t   # learned-only spans
     assert t["frame"] >= t["primary"] + t["hits"]
     S.sdfddgi_destroy(ctx)
 
