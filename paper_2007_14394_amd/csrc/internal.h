@@ -90,7 +90,8 @@ struct TraceArgs {
                                 //     counter per 128-B line (zeroed likewise)
     const int2 *probe_first;    // [P] each probe's first sample, which every one of its rays
                                 //     takes at the probe position: (bits of the distance,
-                                //     level or -1 outside every level); null: sample it
+                                //     level or -1 outside every level; analytic: the nearest
+                                //     primitive's slot); null: sample it
     int analytic;               // 1: distances from the primitives in `an`, not the grid
     AnalyticArgs an;
     const float *prim_alb;      // [nprims][3] albedo of each primitive, cluster order

@@ -229,8 +229,8 @@ __global__ __launch_bounds__(256) void primary_kernel(TraceArgs a) {
                 if (!active && rank < n) {
                     // slot -> (probe in Morton order, ray): neighbouring slots trace
                     // neighbouring probes, so the rays in flight share cache lines
-                    const int slot = first + rank;
-                    const int q = slot / a.R, i = slot - (slot / a.R) * a.R;
+                    const int sid = first + rank;
+                    const int q = sid / a.R, i = sid - (sid / a.R) * a.R;
                     const int p = a.probe_order[q];
                     ray = p * a.R + i;
                     o0 = a.probe_pos[3 * p]; o1 = a.probe_pos[3 * p + 1]; o2 = a.probe_pos[3 * p + 2];
@@ -238,16 +238,21 @@ __global__ __launch_bounds__(256) void primary_kernel(TraceArgs a) {
                     t = 0.0f;
                     k = 0;
                     bound = INFINITY;
-                    if (kSdf != kSdfAnalytic && a.probe_first && a.max_steps > 1) {
+                    if (a.probe_first && a.max_steps > 1) {
                         // the first sample sits at the probe (fma(0, w, o) = o) for every
                         // ray of it: where that sample only steps on (a level holds the
-                        // probe, distance >= eps), take the step from the probe's
-                        // precomputed sample; otherwise the first trace_step samples
+                        // probe, or the primitives are traced; distance >= eps), take
+                        // the step from the probe's precomputed sample; otherwise the
+                        // first trace_step samples
                         const int2 f = a.probe_first[p];
                         const float d0 = __int_as_float(f.x);
-                        if (f.y >= 0 && !(d0 < a.eps)) {
+                        if ((kSdf == kSdfAnalytic || f.y >= 0) && !(d0 < a.eps)) {
                             t = fmaf(a.relax, d0, 0.0f);
                             k = 1;
+                            if constexpr (kSdf == kSdfAnalytic) {
+                                bound = next_bound(a.relax, d0);
+                                slot = f.y;
+                            }
                         }
                     }
                     active = true;
@@ -724,6 +729,19 @@ __global__ __launch_bounds__(256) void probe_first_kernel(TraceArgs a, int2 *out
     out[p] = make_int2(__float_as_int(d), L);
 }
 
+// The same for the analytic backend: the culled query's distance at the probe from an
+// unbounded start, and the nearest primitive's slot.
+__global__ __launch_bounds__(256) void probe_first_analytic_kernel(TraceArgs a, int2 *out) {
+    __shared__ ClusterLds s_cl;
+    load_clusters(a.an, s_cl);
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.P) return;
+    int slot = -1;
+    const float d = nearest_distance(a.an, s_cl, a.probe_pos[3 * p], a.probe_pos[3 * p + 1],
+                                     a.probe_pos[3 * p + 2], INFINITY, slot);
+    out[p] = make_int2(__float_as_int(d), slot);
+}
+
 __global__ __launch_bounds__(256) void sample_kernel(SampleArgs a) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= a.n) return;
@@ -894,7 +912,10 @@ hipError_t launch_probe_sdf(const TraceArgs &a, float *out, hipStream_t s) {
 }
 
 hipError_t launch_probe_first(const TraceArgs &a, int2 *out, hipStream_t s) {
-    if (a.half_sdf)
+    if (a.analytic)
+        hipLaunchKernelGGL(probe_first_analytic_kernel, dim3(blocks_for(a.P, 256)), dim3(256), 0,
+                           s, a, out);
+    else if (a.half_sdf)
         hipLaunchKernelGGL(probe_first_kernel<true>, dim3(blocks_for(a.P, 256)), dim3(256), 0, s, a,
                            out);
     else

@@ -154,7 +154,7 @@ struct sdfddgi_ctx {
     int64_t irr_floats = 0, depth_floats = 0;
     float *probe_pos = nullptr;
     float *grid_pos = nullptr;   // the grid positions (probe_pos differs after relocation)
-    int2 *probe_first = nullptr; // grid scenes: each probe's first sample (see TraceArgs)
+    int2 *probe_first = nullptr; // each probe's first sample (see TraceArgs)
     int *probe_order = nullptr;
     double *texel_i = nullptr, *texel_d = nullptr;
     // main: the ray set of the last plain frame; spare: the one the next plain frame
@@ -1050,7 +1050,7 @@ static sdfddgi_status create_ctx(const sdfddgi_sdf_grid *sdf, const HostClusters
         SDF_TRY(launch_probe_sdf(trace_base(c, l, rad), c->probe_sdf, c->stream),
                 "launching probe_sdf_kernel");
     }
-    if (!c->analytic) {
+    {
         // every ray of a probe takes its first sample at the probe
         const float l[3] = {0.0f, 1.0f, 0.0f}, rad[3] = {0.0f, 0.0f, 0.0f};
         SDF_TRY(dev_alloc(&c->probe_first, P), "allocating probe samples");
