@@ -193,6 +193,7 @@ constexpr int kHitChunk = 64;     // queued hits claimed at a time (spreads them
 // one contiguous part per XCD (blocks of 2048) was 1.6x slower than one counter.
 constexpr int kXcdBlock = 256;
 constexpr int kRefillBelow = 32;  // refill / run batched work when fewer lanes are stepping
+constexpr int kAnalyticBin = 64;  // probes whose rays of one direction the analytic trace groups
 
 // Primary sphere trace, persistent and wave-compacted: each lane owns one ray and
 // takes one sample per iteration; when fewer than kRefillBelow lanes are stepping,
@@ -230,7 +231,21 @@ __global__ __launch_bounds__(256) void primary_kernel(TraceArgs a) {
                     // slot -> (probe in Morton order, ray): neighbouring slots trace
                     // neighbouring probes, so the rays in flight share cache lines
                     const int sid = first + rank;
-                    const int q = sid / a.R, i = sid - (sid / a.R) * a.R;
+                    int q, i;
+                    if constexpr (kSdf == kSdfAnalytic) {
+                        // groups of kAnalyticBin probes of the Morton order, consecutive
+                        // slots taking one direction across the group's probes: a wave's
+                        // lanes march side by side from neighbouring probes, so the
+                        // clusters that any lane's bound admits stay few
+                        const int nq = total / a.R, gsz = kAnalyticBin * a.R;
+                        const int g = sid / gsz, within = sid - g * gsz;
+                        const int gq = min(kAnalyticBin, nq - g * kAnalyticBin);
+                        i = within / gq;
+                        q = g * kAnalyticBin + (within - i * gq);
+                    } else {
+                        q = sid / a.R;
+                        i = sid - q * a.R;
+                    }
                     const int p = a.probe_order[q];
                     ray = p * a.R + i;
                     o0 = a.probe_pos[3 * p]; o1 = a.probe_pos[3 * p + 1]; o2 = a.probe_pos[3 * p + 2];
