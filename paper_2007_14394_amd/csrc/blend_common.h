@@ -86,22 +86,57 @@ constexpr int kEpilogueFloats = kBlendProbes * 256 * 2;
 // previous interior (hysteresis, or none where the history is rejected; the previous
 // value where all weights vanish), then writes every probe's whole padded tile,
 // interior and border, in order -- coalesced reads and stores instead of one
-// scattered store per texel and border copy.
-template <int kN, int kComps, bool kClamp = false>
+// scattered store per texel and border copy. kFast: the previous interior read
+// kBatch elements per thread at a time (every read issued before the first use),
+// and each padded position's source taken from a table built once per workgroup
+// instead of being derived per element; the same values, the same order.
+template <int kN, int kComps, bool kClamp = false, bool kFast = false>
 __device__ __forceinline__ void epilogue_map_lds(const float *prev, float *next, const float *norm,
                                                  const float *s_h, const int *s_pid, int np,
                                                  float *buf) {
     constexpr int T = kN * kN, kSide = kN + 2, kTile = kSide * kSide * kComps;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, total = np * T * kComps;
+    __shared__ short s_src[kFast ? kTile : 1];
+    if (kFast)
+        for (int r = tid; r < kTile; r += 256) {
+            const int pos = r / kComps, c = r - pos * kComps;
+            int i, j;
+            padded_source(kN, pos % kSide, pos / kSide, i, j);
+            s_src[r] = (short)((j * kN + i) * kComps + c);
+        }
     __syncthreads();  // the waves' updates are in buf
-    for (int e = tid; e < np * T * kComps; e += blockDim.x) {
-        const int q = e / (T * kComps), rem = e - q * (T * kComps);
-        const int t = rem / kComps, c = rem - t * kComps;
-        const int i = t % kN, j = t / kN;
-        const float old = prev[(size_t)s_pid[q] * kTile + ((j + 1) * kSide + (i + 1)) * kComps + c];
-        const float nrm = norm[t];
-        const float u = buf[e];
-        buf[e] = nrm < 0.0f ? old : fmaf(s_h[q], old - u, u);
+    if (kFast) {
+        constexpr int kBatch = 8;   // past the end a thread reads the last element, unused
+        for (int e0 = 0; e0 < total; e0 += 256 * kBatch) {
+            float old[kBatch], nrm[kBatch];
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b) {
+                const int e = min(e0 + 256 * b + tid, total - 1);
+                const int q = e / (T * kComps), rem = e - q * (T * kComps);
+                const int t = rem / kComps, c = rem - t * kComps;
+                const int i = t % kN, j = t / kN;
+                old[b] = prev[(size_t)s_pid[q] * kTile + ((j + 1) * kSide + (i + 1)) * kComps + c];
+                nrm[b] = norm[t];
+            }
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b) {
+                const int e = e0 + 256 * b + tid;
+                if (e < total) {
+                    const float u = buf[e];
+                    buf[e] = nrm[b] < 0.0f ? old[b] : fmaf(s_h[e / (T * kComps)], old[b] - u, u);
+                }
+            }
+        }
+    } else {
+        for (int e = tid; e < total; e += blockDim.x) {
+            const int q = e / (T * kComps), rem = e - q * (T * kComps);
+            const int t = rem / kComps, c = rem - t * kComps;
+            const int i = t % kN, j = t / kN;
+            const float old = prev[(size_t)s_pid[q] * kTile + ((j + 1) * kSide + (i + 1)) * kComps + c];
+            const float nrm = norm[t];
+            const float u = buf[e];
+            buf[e] = nrm < 0.0f ? old : fmaf(s_h[q], old - u, u);
+        }
     }
     if (kClamp) {  // moments (kComps == 2): E[t^2] no smaller than E[t]^2
         __syncthreads();
@@ -111,10 +146,14 @@ __device__ __forceinline__ void epilogue_map_lds(const float *prev, float *next,
     __syncthreads();
     for (int e = tid; e < np * kTile; e += blockDim.x) {
         const int q = e / kTile, rem = e - q * kTile;
-        const int pos = rem / kComps, c = rem - pos * kComps;
-        int i, j;
-        padded_source(kN, pos % kSide, pos / kSide, i, j);
-        next[(size_t)s_pid[q] * kTile + rem] = buf[(q * T + j * kN + i) * kComps + c];
+        if (kFast) {
+            next[(size_t)s_pid[q] * kTile + rem] = buf[q * T * kComps + s_src[rem]];
+        } else {
+            const int pos = rem / kComps, c = rem - pos * kComps;
+            int i, j;
+            padded_source(kN, pos % kSide, pos / kSide, i, j);
+            next[(size_t)s_pid[q] * kTile + rem] = buf[(q * T + j * kN + i) * kComps + c];
+        }
     }
     __syncthreads();  // buf is free again
 }
@@ -122,8 +161,9 @@ __device__ __forceinline__ void epilogue_map_lds(const float *prev, float *next,
 // Epilogue of the standard layout (8x8 irradiance in slot 0 of every wave, 16x16
 // depth in slots 1..4) for one workgroup's probes; buf: kEpilogueFloats of LDS that
 // the caller no longer needs. kClamp: as for blend_epilogue. kNi / kNd: the 16-column
-// N-tiles of the irradiance (3 per probe) and depth (2 per probe) products.
-template <bool kClamp = false, int kNi = 3, int kNd = 2>
+// N-tiles of the irradiance (3 per probe) and depth (2 per probe) products. kFast: as
+// for epilogue_map_lds.
+template <bool kClamp = false, int kNi = 3, int kNd = 2, bool kFast = false>
 __device__ __forceinline__ void blend_epilogue_std(const BlendArgs &a, const float *s_h,
                                                    const int *s_pid, int np, int wave, int row,
                                                    int krow, const floatx4 (&acc)[kMSlots][kNi],
@@ -138,7 +178,7 @@ __device__ __forceinline__ void blend_epilogue_std(const BlendArgs &a, const flo
             if (q < np) buf[(q * 64 + t) * 3 + c] = acc[0][n][r] * a.norm_i[t];
         }
     }
-    epilogue_map_lds<8, 3>(a.prev_irr, a.new_irr, a.norm_i, s_h, s_pid, np, buf);
+    epilogue_map_lds<8, 3, false, kFast>(a.prev_irr, a.new_irr, a.norm_i, s_h, s_pid, np, buf);
 #pragma unroll
     for (int s = 1; s < kMSlots; ++s) {
         const int tile = (s - 1) * 4 + wave;
@@ -152,7 +192,8 @@ __device__ __forceinline__ void blend_epilogue_std(const BlendArgs &a, const flo
             }
         }
     }
-    epilogue_map_lds<16, 2, kClamp>(a.prev_depth, a.new_depth, a.norm_d, s_h, s_pid, np, buf);
+    epilogue_map_lds<16, 2, kClamp, kFast>(a.prev_depth, a.new_depth, a.norm_d, s_h, s_pid, np,
+                                           buf);
 }
 
 typedef _Float16 half8_t __attribute__((ext_vector_type(8)));

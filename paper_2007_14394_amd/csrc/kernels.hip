@@ -597,10 +597,19 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a) {
         for (int k0 = 0; k0 < a.R; k0 += kBlendChunk) {
             __syncthreads();
             const int kc = min(kBlendChunk, a.R - k0);
-            for (int e = tid; e < kBlendProbes * kBlendChunk; e += 256) {
-                const int q = e / kBlendChunk, kk = e - q * kBlendChunk;
-                float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                if (q < np && kk < kc) v = a.payload[(size_t)s_pid[q] * a.R + k0 + kk];
+            // every read of the chunk issued at once (absent probes and rays read a
+            // present one and are zeroed)
+            constexpr int kLoads = kBlendProbes * kBlendChunk / 256;
+            float4 pv[kLoads];
+#pragma unroll
+            for (int b = 0; b < kLoads; ++b) {
+                const int e = tid + 256 * b, q = e / kBlendChunk, kk = e - q * kBlendChunk;
+                pv[b] = a.payload[(size_t)s_pid[min(q, np - 1)] * a.R + k0 + min(kk, kc - 1)];
+            }
+#pragma unroll
+            for (int b = 0; b < kLoads; ++b) {
+                const int e = tid + 256 * b, q = e / kBlendChunk, kk = e - q * kBlendChunk;
+                const float4 v = (q < np && kk < kc) ? pv[b] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                 float *d = sx + q * 4 * kBlendPitch + kk;
                 d[0] = v.x; d[kBlendPitch] = v.y; d[2 * kBlendPitch] = v.z; d[3 * kBlendPitch] = v.w;
             }
@@ -643,7 +652,7 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a) {
         }
         // epilogue: lane holds D[4*krow + r][row] of each tile
         if (kStd) {
-            blend_epilogue_std(a, s_h, s_pid, np, wave, row, krow, acc, sbuf);
+            blend_epilogue_std<false, 3, 2, true>(a, s_h, s_pid, np, wave, row, krow, acc, sbuf);
             continue;
         }
 #pragma unroll
