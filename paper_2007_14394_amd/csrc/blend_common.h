@@ -305,7 +305,7 @@ __device__ __forceinline__ void blend16_block(const BlendArgs &a, int pb) {
             }
         }
         if (kStd) {
-            blend_epilogue_std<true, kNi, kNd>(a, s_h, s_pid, np, wave, row, kgrp, acc, sbuf);
+            blend_epilogue_std<true, kNi, kNd, true>(a, s_h, s_pid, np, wave, row, kgrp, acc, sbuf);
             continue;
         }
 #pragma unroll
