@@ -150,6 +150,11 @@ def gather_peaks(S, torch):
     return out
 
 
+def every(step: int) -> str:
+    """How a sample strides over the probes, in words."""
+    return "every probe" if step == 1 else f"every {step}th probe"
+
+
 def cpu_baseline(S, w, probes: int, torch):
     """The binary64 reference checker timed on the host's cores (one frame of the
     benchmarked workload from a seeded previous atlas), and, when the sample is the
@@ -178,13 +183,13 @@ def cpu_baseline(S, w, probes: int, torch):
     full = w.num_probes * w.params.rays_per_probe
     base = {"value": rays / dt, "unit": "probe-rays/s", "cores": threads, "kind": "oracle",
             "host_cpus": os.cpu_count(),
-            "sample": f"{len(sample)} of {w.num_probes} probes (every {step}th) x "
+            "sample": f"{len(sample)} of {w.num_probes} probes ({every(step)}) x "
                       f"{w.params.rays_per_probe} rays, one frame, binary64 checker, "
                       f"{threads} threads, {dt:.2f} s wall",
             "ms_per_frame": full / (rays / dt) * 1e3,
             "single_thread": {"value": rays1 / d1, "unit": "probe-rays/s",
                               "ms_per_frame": full / (rays1 / d1) * 1e3,
-                              "sample": f"{len(one)} probes (every {16 * step}th), 1 thread, "
+                              "sample": f"{len(one)} probes ({every(16 * step)}), 1 thread, "
                                         f"{d1:.2f} s wall"}}
     errors = None
     if len(sample) == w.num_probes:
