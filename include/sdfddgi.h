@@ -74,9 +74,11 @@
  *     asynchronous: results are valid once the caller synchronises that stream.
  *     The one exception is internal: back-to-back sdfddgi_update_frame calls
  *     run each frame's tables and primary trace on a side stream of the context
- *     (default priority), overlapping the previous frame's hit shading and
- *     blend, and join it back into the caller's stream before the frame's hit
- *     shading -- so the rule above still holds for every result.
+ *     and, on grid contexts, the atlas-independent half of its hit shading
+ *     (normal, shadow ray, albedo) on a second one (default priority), both
+ *     overlapping the previous frame's lookups and blend, and join them back
+ *     into the caller's stream before the frame's multi-bounce lookups -- so the
+ *     rule above still holds for every result.
  *   - Status codes only; nothing is thrown across the ABI. A failed call leaves
  *     the context's maps as they were. sdfddgi_last_error gives the message.
  *   - A context is used by one host thread at a time (no internal locking).
@@ -259,8 +261,9 @@ sdfddgi_status sdfddgi_ray_directions(uint64_t rotation_seed, int32_t rays, floa
  * shading (normal, shadow ray, lookups), [3] blend, [4] whole frame,
  * [5] denoiser, [6] fallback trace (tables, list, primary, shadow rays),
  * [7] fallback lookups and blend. In a learned frame [1]-[3] are the low-ray
- * pass, whose hit shading is split: the atlas-independent half (normal, shadow
- * ray, albedo) runs beside the previous frame and the lookups after it, and [2]
+ * pass. Where the hit shading is split (learned frames, and back-to-back plain
+ * frames on grid contexts) the atlas-independent half (normal, shadow ray,
+ * albedo) runs beside the previous frame and the lookups after it, and [2]
  * spans both; [5]-[7] are 0 in a plain frame.
  * Host pointer ms[count], count <= 8. Waits for the last timed frame.
  * ESTATE without SDFDDGI_FLAG_TIMING or when no frame ran since the last call. */

@@ -356,8 +356,9 @@ __global__ __launch_bounds__(256) void hits_kernel(TraceArgs a) {
                         else
                             alb = albedo_at(a, s_sdf.lv[(info >> 4) & 15], hx0, hx1, hx2);
                         if (a.geo) {
-                            a.geo[2 * qi] = make_float4(n0, n1, n2, lit);
-                            a.geo[2 * qi + 1] = make_float4(alb.x, alb.y, alb.z, 0.0f);
+                            // 64-bit: 2 qi passes INT_MAX from 2^30 queued hits
+                            a.geo[2 * (int64_t)qi] = make_float4(n0, n1, n2, lit);
+                            a.geo[2 * (int64_t)qi + 1] = make_float4(alb.x, alb.y, alb.z, 0.0f);
                             write_record(a, ray, ht, info & 15, (info >> 4) & 15, info >> 8, vis,
                                          k, n0, n1, n2);
                         } else {
@@ -445,7 +446,7 @@ __global__ __launch_bounds__(256) void shade_kernel(TraceArgs a) {
     const int total = a.counter[2];
     for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < total; q += gridDim.x * blockDim.x) {
         const int4 e = a.hitq[q];
-        const float4 g0 = a.geo[2 * q], g1 = a.geo[2 * q + 1];
+        const float4 g0 = a.geo[2 * (int64_t)q], g1 = a.geo[2 * (int64_t)q + 1];
         const int ray = e.x;
         const float ht = __int_as_float(e.y);
         float3 ind = make_float3(0.0f, 0.0f, 0.0f);

@@ -170,16 +170,17 @@ struct sdfddgi_ctx {
     uint8_t *fb_flag[2]{};
     int last_learned = 0;        // parity of the last learned frame
     // Plain frames are pipelined: the tables and primary trace of frame f run on the
-    // side stream and may overlap frame f-1's hit shading and blend on the caller's
-    // stream (the primary trace reads neither the atlas nor anything frame f-1
-    // writes). A frame's side work waits for the done event of the ray set it
-    // traces into (recorded after the blend of the frame before the previous one)
-    // or for ev_gate (recorded on the caller's stream just before the previous
-    // frame's hit shading; learned frames wait for their low set's done event
-    // instead); ev_primary joins the side stream back. Any other call in between
-    // makes the next frame wait for everything before it (serialize_next).
+    // side stream, and on grids the atlas-independent half of its hit shading
+    // (normal, shadow ray, albedo) on side2 after them, so both may overlap frame
+    // f-1's lookups and blend on the caller's stream (neither reads the atlas or
+    // anything frame f-1 writes); the caller's stream then takes frame f's lookup
+    // half and blend. A frame's side work waits for the done event of the ray set it
+    // traces into (recorded after the blend of the frame before the previous one);
+    // ev_primary joins the side stream to side2 (or, unsplit, to the caller's
+    // stream) and the set's ready event side2 to the caller's. Any other call in
+    // between makes the next frame wait for everything before it (serialize_next).
     hipStream_t side = nullptr;
-    hipEvent_t ev_gate = nullptr, ev_primary = nullptr, ev_tail = nullptr;
+    hipEvent_t ev_primary = nullptr, ev_tail = nullptr;
     bool serialize_next = true;
     // Learned frames overlap among themselves; a switch between plain and learned
     // frames waits for everything before it. Learned frame n (parity k = n % 2, low
@@ -316,9 +317,10 @@ void free_all(sdfddgi_ctx *c) {
         if (r->ready) (void)hipEventDestroy(r->ready);
         if (r->sel) (void)hipEventDestroy(r->sel);
     }
-    if (c->main.done) (void)hipEventDestroy(c->main.done);
-    if (c->spare.done) (void)hipEventDestroy(c->spare.done);
-    if (c->ev_gate) (void)hipEventDestroy(c->ev_gate);
+    for (RaySet *r : {&c->main, &c->spare}) {
+        if (r->done) (void)hipEventDestroy(r->done);
+        if (r->ready) (void)hipEventDestroy(r->ready);
+    }
     if (c->ev_primary) (void)hipEventDestroy(c->ev_primary);
     if (c->ev_tail) (void)hipEventDestroy(c->ev_tail);
     if (c->side) (void)hipStreamDestroy(c->side);
@@ -790,8 +792,9 @@ sdfddgi_status light_of(sdfddgi_ctx *c, const sdfddgi_light *light, float l[3], 
 // [1] tables, [2] primary trace, [3] hit shading may start, [4] hit shading,
 // [5] blend, [6] denoiser, [7] fallback pass starts, [8] fallback trace (tables,
 // list, primary, atlas-independent hit shading), [9] fallback blend, [10] frame,
-// [11] fallback lookup half may start. A learned frame's hit shading runs from
-// [3] on the side stream to [4] on the caller's.
+// [11] fallback lookup half may start. Split hit shading (learned frames, and
+// pipelined plain frames on grids) runs from [3] on a side stream to [4] on the
+// caller's.
 struct FrameEvents {
     hipEvent_t *ev = nullptr;
     hipStream_t s = nullptr;
@@ -992,10 +995,12 @@ static sdfddgi_status create_ctx(const sdfddgi_sdf_grid *sdf, const HostClusters
     }
     SDF_TRY(ce, "uploading constants");
 
-    SDF_TRY(alloc_set(c, c->main, params->rays_per_probe), "allocating the ray set");
-    SDF_TRY(alloc_set(c, c->spare, params->rays_per_probe), "allocating the ray set");
+    // the grid backends split the pipelined frames' hit shading (geometry records)
+    SDF_TRY(alloc_set(c, c->main, params->rays_per_probe, !c->analytic),
+            "allocating the ray set");
+    SDF_TRY(alloc_set(c, c->spare, params->rays_per_probe, !c->analytic),
+            "allocating the ray set");
     SDF_TRY(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking), "creating a stream");
-    SDF_TRY(hipEventCreateWithFlags(&c->ev_gate, hipEventDisableTiming), "creating events");
     SDF_TRY(hipEventCreateWithFlags(&c->ev_primary, hipEventDisableTiming), "creating events");
     SDF_TRY(hipEventCreateWithFlags(&c->ev_tail, hipEventDisableTiming), "creating events");
     SDF_TRY(hipStreamCreateWithFlags(&c->side2, hipStreamNonBlocking), "creating a stream");
@@ -1004,6 +1009,7 @@ static sdfddgi_status create_ctx(const sdfddgi_sdf_grid *sdf, const HostClusters
     SDF_TRY(hipEventRecord(c->ev_end, c->stream), "event");
     for (RaySet *r : {&c->main, &c->spare}) {
         SDF_TRY(hipEventCreateWithFlags(&r->done, hipEventDisableTiming), "creating events");
+        SDF_TRY(hipEventCreateWithFlags(&r->ready, hipEventDisableTiming), "creating events");
         SDF_TRY(hipEventRecord(r->done, c->stream), "event");
     }
     for (int k = 0; k < 2; ++k) {
@@ -1117,19 +1123,20 @@ sdfddgi_status sdfddgi_update_frame(sdfddgi_ctx *c, const sdfddgi_light *light,
                                    nullptr, nullptr, c->records);
     FrameEvents ev = frame_events(c);
     const int nxt = 1 - c->cur;
+    // Split hit shading when pipelined on a grid: the atlas-independent half on side2
+    // right after the trace, only the lookups behind the previous frame's blend
+    // (16384 x 256, ms per frame, FP32 / FP16: 0.7275 / 0.590 unsplit, 0.719 /
+    // 0.576 split; that half's grid halved 0.736, not overlapped 0.734 in FP32)
+    const bool split = !serial && r.geo != nullptr;
     // side stream: tables and primary trace. This set was last used by the frame
-    // before the previous one, whose hit shading and blend ran on the caller's
-    // stream before that set's done event and before the previous frame's gate; so
-    // wait for one of those, or, when serial, for everything enqueued so far
+    // before the previous one, whose hit shading and blend ran before that set's
+    // done event; so wait for that (the trace then starts as soon as its set is
+    // free), or, when serial, for everything enqueued so far
     if (serial) {
         TRY_HIP(c, hipEventRecord(c->ev_tail, c->stream), "event");
         TRY_HIP(c, hipStreamWaitEvent(c->side, c->ev_tail, 0), "stream wait");
     } else {
-        // binary32 SDF: the trace is the longer of the two chains, so start it as soon
-        // as its set is free (0.730 vs 0.738 ms per frame); binary16: the chains are
-        // even and an earlier start only slows the hit shading and blend it then
-        // overlaps (0.623 vs 0.608 ms), so wait for the previous frame's gate
-        TRY_HIP(c, hipStreamWaitEvent(c->side, c->half ? c->ev_gate : r.done, 0), "stream wait");
+        TRY_HIP(c, hipStreamWaitEvent(c->side, r.done, 0), "stream wait");
     }
     TRY_HIP(c, ev.mark_on(0, c->side), "event");
     TRY_HIP(c, launch_tables(table_args(c, r, rotation_seed, kSetCounters, r.counter), c->side),
@@ -1144,12 +1151,24 @@ sdfddgi_status sdfddgi_update_frame(sdfddgi_ctx *c, const sdfddgi_light *light,
     TRY_HIP(c, launch_primary(t, g, c->side), "launching primary_kernel");
     TRY_HIP(c, ev.mark_on(2, c->side), "event");
     TRY_HIP(c, hipEventRecord(c->ev_primary, c->side), "event");
-    // caller's stream: hit shading (reads the previous atlas, so after the previous
-    // frame's blend) and blend
-    TRY_HIP(c, hipStreamWaitEvent(c->stream, c->ev_primary, 0), "stream wait");
-    TRY_HIP(c, hipEventRecord(c->ev_gate, c->stream), "event");
-    TRY_HIP(c, ev.mark(3), "event");
-    TRY_HIP(c, launch_hits(t, g, c->stream), "launching hits_kernel");
+    if (split) {
+        // side2: the atlas-independent half of the hit shading; then the caller's
+        // stream, after the previous frame's blend: the lookups into its atlas
+        TraceArgs tg = t;
+        tg.geo = r.geo;
+        TRY_HIP(c, hipStreamWaitEvent(c->side2, c->ev_primary, 0), "stream wait");
+        TRY_HIP(c, ev.mark_on(3, c->side2), "event");
+        TRY_HIP(c, launch_hits(tg, g, c->side2), "launching hits_kernel");
+        TRY_HIP(c, hipEventRecord(r.ready, c->side2), "event");
+        TRY_HIP(c, hipStreamWaitEvent(c->stream, r.ready, 0), "stream wait");
+        TRY_HIP(c, launch_shade(tg, c->stream), "launching shade_kernel");
+    } else {
+        // caller's stream: hit shading (reads the previous atlas, so after the
+        // previous frame's blend)
+        TRY_HIP(c, hipStreamWaitEvent(c->stream, c->ev_primary, 0), "stream wait");
+        TRY_HIP(c, ev.mark(3), "event");
+        TRY_HIP(c, launch_hits(t, g, c->stream), "launching hits_kernel");
+    }
     TRY_HIP(c, ev.mark(4), "event");
     TRY_HIP(c, launch_blend(blend_args(c, r, r.payload, c->prm.hysteresis, c->irr[c->cur],
                                        c->depth[c->cur], c->irr[nxt], c->depth[nxt], c->reject,
