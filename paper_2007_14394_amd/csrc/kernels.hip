@@ -847,12 +847,13 @@ static int persistent_blocks(const void *kernel, int device, int64_t rays, int m
 // latency but evict each other's lines. Measured on the open scene at 16384 x 256
 // rays, in both precisions, the primary trace is fastest with 4 waves per SIMD (of
 // the 7 that fit) and the hit shading with 2 (of 4) when it runs alone,
-// 1 when it runs beside the next frame's primary trace. Beside the previous frame's
-// hit shading and blend, the binary32 primary trace does best with 3 waves per SIMD
-// (frame period 0.742 ms vs 0.770 with 4; 2, 5 and 6 give 0.83-0.86), the binary16
-// one still with 4 (0.611 ms vs 0.646 with 3).
+// 1 when it runs beside the next frame's primary trace. Beside the other frames'
+// work the primary trace also does best with 4 waves per SIMD: with the hit shading
+// split (its atlas-independent half beside the trace), frame period 0.692 ms vs
+// 0.704 with 3 and 0.802 with 2 (binary32), 0.574 ms vs 0.618 with 3 (binary16);
+// before that split the binary32 trace had preferred 3 (0.742 vs 0.770 ms).
 constexpr int kPrimaryBlocksPerCu = 4;
-constexpr int kPrimaryBlocksPerCuOverlapped[2] = {3, 4};  // binary32, binary16 SDF
+constexpr int kPrimaryBlocksPerCuOverlapped[2] = {4, 4};  // binary32, binary16 SDF
 constexpr int kHitsBlocksPerCu = 2;
 constexpr int kHitsBlocksPerCuOverlapped = 1;
 
