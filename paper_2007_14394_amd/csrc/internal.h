@@ -128,6 +128,7 @@ struct TableArgs {
     int Rpad;                   // row length of the 16-bit tables: R rounded up to 64
     _Float16 *w16_i;            // precision form: [Tpi][Rpad] FP16 w_ti (else null)
     __bf16 *w16_d;              // precision form: [Tpd][Rpad] BF16 w_ti^s (else null)
+    int row0;                   // row of block 0 (set by the launch functions)
 };
 
 struct BlendArgs {
@@ -156,6 +157,10 @@ struct SampleArgs {
 
 // Launchers (kernels.hip). Each enqueues on `stream` and returns the launch status.
 hipError_t launch_tables(const TableArgs &a, hipStream_t stream);
+// The directions block alone (it also resets the counters), and the weight rows
+// alone; together they do what launch_tables does.
+hipError_t launch_tables_dirs(TableArgs a, hipStream_t stream);
+hipError_t launch_tables_weights(TableArgs a, hipStream_t stream);
 TraceGrid trace_grid(int device, int64_t rays, bool half, bool analytic = false);
 hipError_t launch_primary(const TraceArgs &a, const TraceGrid &grid, hipStream_t stream);
 hipError_t launch_hits(const TraceArgs &a, const TraceGrid &grid, hipStream_t stream);

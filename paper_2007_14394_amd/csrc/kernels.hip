@@ -465,7 +465,7 @@ __global__ __launch_bounds__(256) void shade_kernel(TraceArgs a) {
 // rows), plus one block that writes the binary32 directions.
 __global__ __launch_bounds__(256) void tables_kernel(TableArgs a) {
     __shared__ double red[256];
-    const int row = blockIdx.x;
+    const int row = blockIdx.x + a.row0;
     const int tid = threadIdx.x;
     const bool is_dirs = row == a.Ti + a.Td;
     const bool is_depth = row >= a.Ti && !is_dirs;
@@ -823,7 +823,21 @@ __global__ __launch_bounds__(256) void fill_u8_kernel(uint8_t *dst, uint8_t valu
 static unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 hipError_t launch_tables(const TableArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(tables_kernel, dim3(a.Ti + a.Td + 1), dim3(256), 0, s, a);
+    TableArgs t = a;
+    t.row0 = 0;
+    hipLaunchKernelGGL(tables_kernel, dim3(t.Ti + t.Td + 1), dim3(256), 0, s, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_tables_dirs(TableArgs a, hipStream_t s) {
+    a.row0 = a.Ti + a.Td;
+    hipLaunchKernelGGL(tables_kernel, dim3(1), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_tables_weights(TableArgs a, hipStream_t s) {
+    a.row0 = 0;
+    hipLaunchKernelGGL(tables_kernel, dim3(a.Ti + a.Td), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
