@@ -257,7 +257,9 @@ sdfddgi_status sdfddgi_ray_directions(uint64_t rotation_seed, int32_t rays, floa
 /* Mean per-kernel GPU times in milliseconds over the update_frame calls (plain
  * or learned) made since the previous call of this function (at most the last
  * 256), measured with events recorded on the context's stream around each
- * kernel: [0] ray-direction/weight tables, [1] primary sphere trace, [2] hit
+ * kernel: [0] ray-direction/weight tables (in back-to-back plain frames on
+ * grids their weight rows, which run beside the trace while the directions block
+ * runs ahead of it), [1] primary sphere trace, [2] hit
  * shading (normal, shadow ray, lookups), [3] blend, [4] whole frame,
  * [5] denoiser, [6] fallback trace (tables, list, primary, shadow rays),
  * [7] fallback lookups and blend. In a learned frame [1]-[3] are the low-ray
