@@ -259,7 +259,8 @@ sdfddgi_status sdfddgi_ray_directions(uint64_t rotation_seed, int32_t rays, floa
  * 256), measured with events recorded on the context's stream around each
  * kernel: [0] ray-direction/weight tables (in back-to-back plain frames on
  * grids their weight rows, which run beside the trace while the directions block
- * runs ahead of it), [1] primary sphere trace, [2] hit
+ * runs ahead of it; in a learned frame the low set's directions block, its weight
+ * rows running before the low-ray blend), [1] primary sphere trace, [2] hit
  * shading (normal, shadow ray, lookups), [3] blend, [4] whole frame,
  * [5] denoiser, [6] fallback trace (tables, list, primary, shadow rays),
  * [7] fallback lookups and blend. In a learned frame [1]-[3] are the low-ray

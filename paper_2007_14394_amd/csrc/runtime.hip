@@ -1535,9 +1535,12 @@ sdfddgi_status sdfddgi_update_frame_learned(sdfddgi_ctx *c, const sdfddgi_denois
                               nullptr);
     tl.geo = lo.geo;
     TRY_HIP(c, ev.mark_on(0, sl), "event");
+    // only the directions block (it also resets the counters) ahead of the low
+    // trace; the weight rows, which only the low-ray blend reads, on the caller's
+    // stream before it
+    const TableArgs tal = table_args(c, lo, rotation_seed, kSetCounters, lo.counter);
     TRY_HIP(c, ev.mark_on(12, sl), "event");
-    TRY_HIP(c, launch_tables(table_args(c, lo, rotation_seed, kSetCounters, lo.counter), sl),
-            "launching tables_kernel");
+    TRY_HIP(c, launch_tables_dirs(tal, sl), "launching tables_kernel");
     TRY_HIP(c, ev.mark_on(13, sl), "event");
     TRY_HIP(c, ev.mark_on(1, sl), "event");
     // The side chains run on small grids, so that the caller's stream -- the lookups,
@@ -1566,14 +1569,17 @@ sdfddgi_status sdfddgi_update_frame_learned(sdfddgi_ctx *c, const sdfddgi_denois
     gf.primary_blocks = std::max(1, gf.primary_blocks_overlapped / 4);
     gf.hits_blocks = std::max(1, gf.hits_blocks_overlapped / 2);
     TRY_HIP(c, ev.mark_on(7, sf), "event");
-    TRY_HIP(c, launch_tables(table_args(c, fb, rotation_seed, kSetCounters, fb.counter), sf),
-            "launching tables_kernel");
+    // the fallback set's directions ahead of its trace, its weight rows (read by its
+    // blend only) after it
+    const TableArgs taf = table_args(c, fb, rotation_seed, kSetCounters, fb.counter);
+    TRY_HIP(c, launch_tables_dirs(taf, sf), "launching tables_kernel");
     TRY_HIP(c, launch_select_fallback(serial ? c->reject : nullptr, c->fb_flag[k], (int)c->P,
                                       fb.list, fb_count, sf),
             "launching select_fallback_kernel");
     TRY_HIP(c, hipEventRecord(fb.sel, sf), "event");
     TRY_HIP(c, launch_primary(tf, gf, sf), "launching primary_kernel");
     TRY_HIP(c, launch_hits(tf, gf, sf), "launching hits_kernel");
+    TRY_HIP(c, launch_tables_weights(taf, sf), "launching tables_kernel");
     TRY_HIP(c, ev.mark_on(8, sf), "event");
     TRY_HIP(c, hipStreamWaitEvent(sf, c->ev_end, 0), "stream wait");
     TRY_HIP(c, ev.mark_on(11, sf), "event");
@@ -1588,6 +1594,7 @@ sdfddgi_status sdfddgi_update_frame_learned(sdfddgi_ctx *c, const sdfddgi_denois
     // caller's stream (the previous atlas is complete here): low-ray lookup half and
     // Eq. 3 without hysteresis
     TRY_HIP(c, hipStreamWaitEvent(c->stream, lo.ready, 0), "stream wait");
+    TRY_HIP(c, launch_tables_weights(tal, c->stream), "launching tables_kernel");
     TRY_HIP(c, launch_shade(tl, c->stream), "launching shade_kernel");
     TRY_HIP(c, ev.mark(4), "event");
     TRY_HIP(c, launch_blend(blend_args(c, lo, lo.payload, 0.0f, c->irr[c->cur],
